@@ -1,0 +1,228 @@
+"""CPU oracle for the reverse-mode rules (test infrastructure only).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product library never does: it
+shares no code with the oracle, and neither imports the other.
+
+The arithmetic lives in ``oracle.c`` (plain C, FP64, explicit tape, reverse
+sweep).  This module only converts numpy arrays (every floating-point input is
+upcast to float64, which is exact for float32) and calls it through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+ADD, MUL, MIN, MAX = 0, 1, 2, 3
+OPS = {"add": ADD, "mul": MUL, "min": MIN, "max": MAX}
+FN_SQUARE, FN_EXP, FN_LOG, FN_SIN, FN_TANH = 0, 1, 2, 3, 4
+FNS = {"square": FN_SQUARE, "exp": FN_EXP, "log": FN_LOG, "sin": FN_SIN, "tanh": FN_TANH}
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_L = ctypes.c_int64
+_D = ctypes.c_double
+
+_SIGS = {
+    "orc_linrec_scan": [_L, _P, _P, _P, _P],
+    "orc_linrec_scan_vjp": [_L, _P, _P, _P, _P, _P, _P],
+    "orc_reduce": [_I, _L, _P, _P, _P, _P, _P],
+    "orc_reduce_vjp": [_I, _L, _P, _D, _P],
+    "orc_hist": [_I, _L, _L, _P, _P, _P, _P, _P, _P, _P],
+    "orc_hist_vjp": [_I, _L, _L, _P, _P, _P, _P],
+    "orc_scatter": [_L, _P, _L, _P, _P, _P, _P],
+    "orc_scatter_vjp": [_L, _L, _P, _P, _P, _P],
+    "orc_map": [_I, _L, _P, _P],
+    "orc_map_vjp": [_I, _L, _P, _P, _P],
+    "orc_fig1": [_L, _P, _P, _P, _P],
+    "orc_fig1_vjp": [_L, _P, _P, _P, _P, _P, _P],
+    "orc_gmm_objective": [_L, _I, _I, _P, _P, _P, _P, _P, _P, _P],
+    "orc_gmm_vjp": [_L, _I, _I, _P, _P, _P, _P, _P, _D, _P, _P, _P, _P],
+}
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (plain C, no fast-math)."""
+    from . import build as _b
+
+    return _b.build(force=force)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        for name, argt in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = argt
+            f.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _f64(x):
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+
+
+def _i32(x):
+    return np.ascontiguousarray(np.asarray(x, dtype=np.int32))
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check(rc, name):
+    if rc != 0:
+        raise RuntimeError(f"oracle {name} failed with status {rc}")
+
+
+# ---------------------------------------------------------------- linrec scan
+def linrec_scan(a, b):
+    a, b = _f64(a), _f64(b)
+    n = a.size
+    A, B = np.empty(n), np.empty(n)
+    _check(lib().orc_linrec_scan(n, _p(a), _p(b), _p(A), _p(B)), "linrec_scan")
+    return A, B
+
+
+def linrec_scan_vjp(a, b, yA_bar, yB_bar):
+    a, b, ya, yb = _f64(a), _f64(b), _f64(yA_bar), _f64(yB_bar)
+    n = a.size
+    ab, bb = np.empty(n), np.empty(n)
+    _check(lib().orc_linrec_scan_vjp(n, _p(a), _p(b), _p(ya), _p(yb), _p(ab), _p(bb)),
+           "linrec_scan_vjp")
+    return ab, bb
+
+
+# --------------------------------------------------------------------- reduce
+def reduce(op, x):
+    """Returns (y, arg, p, z): arg is the lowest index of the extreme for
+    min/max (-1 for n == 0); p, z the non-zero product and zero count."""
+    op = OPS.get(op, op)
+    x = _f64(x)
+    y, p = ctypes.c_double(), ctypes.c_double()
+    arg, z = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().orc_reduce(op, x.size, _p(x), ctypes.byref(y), ctypes.byref(arg),
+                            ctypes.byref(p), ctypes.byref(z)), "reduce")
+    return y.value, arg.value, p.value, z.value
+
+
+def reduce_vjp(op, x, y_bar):
+    op = OPS.get(op, op)
+    x = _f64(x)
+    xb = np.empty(x.size)
+    _check(lib().orc_reduce_vjp(op, x.size, _p(x), float(y_bar), _p(xb)), "reduce_vjp")
+    return xb
+
+
+# ------------------------------------------------------------ reduce_by_index
+def hist(op, inds, vs, m):
+    """Returns dict with hs, winner, p, z, count (all length m)."""
+    op = OPS.get(op, op)
+    inds, vs = _i32(inds), _f64(vs)
+    out = {
+        "hs": np.empty(m),
+        "winner": np.empty(m, dtype=np.int64),
+        "p": np.empty(m),
+        "z": np.empty(m, dtype=np.int64),
+        "count": np.empty(m, dtype=np.int64),
+    }
+    _check(lib().orc_hist(op, vs.size, m, _p(inds), _p(vs), _p(out["hs"]), _p(out["winner"]),
+                          _p(out["p"]), _p(out["z"]), _p(out["count"])), "hist")
+    return out
+
+
+def hist_vjp(op, inds, vs, hs_bar):
+    op = OPS.get(op, op)
+    inds, vs, hb = _i32(inds), _f64(vs), _f64(hs_bar)
+    vb = np.empty(vs.size)
+    _check(lib().orc_hist_vjp(op, vs.size, hb.size, _p(inds), _p(vs), _p(hb), _p(vb)),
+           "hist_vjp")
+    return vb
+
+
+# -------------------------------------------------------------------- scatter
+def scatter(xs, is_, vs):
+    xs, is_, vs = _f64(xs), _i32(is_), _f64(vs)
+    ys, saved = np.empty(xs.size), np.empty(is_.size)
+    _check(lib().orc_scatter(xs.size, _p(xs), is_.size, _p(is_), _p(vs), _p(ys), _p(saved)),
+           "scatter")
+    return ys, saved
+
+
+def scatter_vjp(is_, ys_bar):
+    is_, yb = _i32(is_), _f64(ys_bar)
+    xb, vb = np.empty(yb.size), np.empty(is_.size)
+    _check(lib().orc_scatter_vjp(yb.size, is_.size, _p(is_), _p(yb), _p(xb), _p(vb)),
+           "scatter_vjp")
+    return xb, vb
+
+
+# ------------------------------------------------------------------------ map
+def map_(fn, x):
+    fn = FNS.get(fn, fn)
+    x = _f64(x)
+    y = np.empty(x.size)
+    _check(lib().orc_map(fn, x.size, _p(x), _p(y)), "map")
+    return y
+
+
+def map_vjp(fn, x, y_bar):
+    fn = FNS.get(fn, fn)
+    x, yb = _f64(x), _f64(y_bar)
+    xb = np.empty(x.size)
+    _check(lib().orc_map_vjp(fn, x.size, _p(x), _p(yb), _p(xb)), "map_vjp")
+    return xb
+
+
+def fig1(x0, x1):
+    x0, x1 = _f64(x0), _f64(x1)
+    y0, y1 = np.empty(x0.size), np.empty(x0.size)
+    _check(lib().orc_fig1(x0.size, _p(x0), _p(x1), _p(y0), _p(y1)), "fig1")
+    return y0, y1
+
+
+def fig1_vjp(x0, x1, y0_bar, y1_bar):
+    x0, x1, b0, b1 = _f64(x0), _f64(x1), _f64(y0_bar), _f64(y1_bar)
+    r0, r1 = np.empty(x0.size), np.empty(x0.size)
+    _check(lib().orc_fig1_vjp(x0.size, _p(x0), _p(x1), _p(b0), _p(b1), _p(r0), _p(r1)),
+           "fig1_vjp")
+    return r0, r1
+
+
+# ------------------------------------------------------------------------ GMM
+def _gmm_args(X, alpha, mu, q, l):
+    X, alpha, mu, q, l = _f64(X), _f64(alpha), _f64(mu), _f64(q), _f64(l)
+    N, D = X.shape if X.ndim == 2 else (0, mu.shape[-1])
+    K = alpha.size
+    return X, alpha, mu, q, l, N, D, K
+
+
+def gmm_objective(X, alpha, mu, q, l):
+    """Returns (loglik, lse[N])."""
+    X, alpha, mu, q, l, N, D, K = _gmm_args(X, alpha, mu, q, l)
+    ll = ctypes.c_double()
+    lse = np.empty(N)
+    _check(lib().orc_gmm_objective(N, D, K, _p(X), _p(alpha), _p(mu), _p(q), _p(l),
+                                   ctypes.byref(ll), _p(lse)), "gmm_objective")
+    return ll.value, lse
+
+
+def gmm_vjp(X, alpha, mu, q, l, ell_bar=1.0):
+    """Returns (alpha_bar, mu_bar, q_bar, l_bar) shaped like the parameters."""
+    X, alpha, mu, q, l, N, D, K = _gmm_args(X, alpha, mu, q, l)
+    ab, mb, qb, lb = (np.zeros_like(alpha), np.zeros_like(mu), np.zeros_like(q),
+                      np.zeros_like(l))
+    _check(lib().orc_gmm_vjp(N, D, K, _p(X), _p(alpha), _p(mu), _p(q), _p(l), float(ell_bar),
+                             _p(ab), _p(mb), _p(qb), _p(lb)), "gmm_vjp")
+    return ab, mb, qb, lb

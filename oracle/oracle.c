@@ -1,0 +1,735 @@
+/*
+ * CPU oracle: sequential FP64 semantics + explicit tape + reverse sweep.
+ *
+ * TEST INFRASTRUCTURE ONLY (see oracle.h).  Plain C99, libm only, single
+ * thread.  It is meant to be slow and easy to check by eye, not fast.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* 2*pi to double precision. */
+static const double TWO_PI = 6.283185307179586476925286766559;
+
+/* ------------------------------------------------------------------------ */
+/* The tape.                                                                  */
+/*                                                                            */
+/* A variable is a slot holding a value and an adjoint.  Every elementary     */
+/* step v = f(a, b) appends one record {v, a, b, df/da, df/db} with the local */
+/* partial derivatives evaluated at the forward point (Sec. 2.0.2).  The      */
+/* reverse sweep visits the records newest-first and applies                  */
+/* adj[a] += df/da * adj[v], adj[b] += df/db * adj[v]; a variable used many   */
+/* times therefore receives the sum of all its contributions.                 */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t out, in0, in1; /* in1 == -1 for unary steps */
+    double w0, w1;         /* partials of out w.r.t. in0 and in1 */
+} rec_t;
+
+typedef struct {
+    double* val;
+    double* adj;
+    int64_t nv, capv;
+    rec_t* rec;
+    int64_t nr, capr;
+    int oom;
+} tape_t;
+
+static int tape_init(tape_t* t, int64_t capv, int64_t capr) {
+    memset(t, 0, sizeof(*t));
+    if (capv < 16) capv = 16;
+    if (capr < 16) capr = 16;
+    t->val = (double*)malloc((size_t)capv * sizeof(double));
+    t->rec = (rec_t*)malloc((size_t)capr * sizeof(rec_t));
+    t->capv = capv;
+    t->capr = capr;
+    if (!t->val || !t->rec) {
+        free(t->val);
+        free(t->rec);
+        t->val = NULL;
+        t->rec = NULL;
+        return -2;
+    }
+    return 0;
+}
+
+static void tape_free(tape_t* t) {
+    free(t->val);
+    free(t->adj);
+    free(t->rec);
+    memset(t, 0, sizeof(*t));
+}
+
+static void tape_clear(tape_t* t) {
+    t->nv = 0;
+    t->nr = 0;
+}
+
+static int64_t new_slot(tape_t* t, double v) {
+    if (t->nv == t->capv) {
+        int64_t c = t->capv * 2;
+        double* p = (double*)realloc(t->val, (size_t)c * sizeof(double));
+        if (!p) {
+            t->oom = 1;
+            return 0;
+        }
+        t->val = p;
+        t->capv = c;
+    }
+    t->val[t->nv] = v;
+    return t->nv++;
+}
+
+static void push_rec(tape_t* t, int64_t out, int64_t a, double wa, int64_t b, double wb) {
+    if (t->nr == t->capr) {
+        int64_t c = t->capr * 2;
+        rec_t* p = (rec_t*)realloc(t->rec, (size_t)c * sizeof(rec_t));
+        if (!p) {
+            t->oom = 1;
+            return;
+        }
+        t->rec = p;
+        t->capr = c;
+    }
+    rec_t* r = &t->rec[t->nr++];
+    r->out = out;
+    r->in0 = a;
+    r->in1 = b;
+    r->w0 = wa;
+    r->w1 = wb;
+}
+
+#define V(s) (t->val[(s)])
+
+/* An independent variable (or a constant whose adjoint is simply ignored). */
+static int64_t leaf(tape_t* t, double v) { return new_slot(t, v); }
+
+static int64_t emit1(tape_t* t, double v, int64_t a, double wa) {
+    int64_t s = new_slot(t, v);
+    push_rec(t, s, a, wa, -1, 0.0);
+    return s;
+}
+
+static int64_t emit2(tape_t* t, double v, int64_t a, double wa, int64_t b, double wb) {
+    int64_t s = new_slot(t, v);
+    push_rec(t, s, a, wa, b, wb);
+    return s;
+}
+
+/* Elementary steps with their textbook partial derivatives. */
+static int64_t t_add(tape_t* t, int64_t a, int64_t b) { return emit2(t, V(a) + V(b), a, 1.0, b, 1.0); }
+static int64_t t_sub(tape_t* t, int64_t a, int64_t b) { return emit2(t, V(a) - V(b), a, 1.0, b, -1.0); }
+static int64_t t_mul(tape_t* t, int64_t a, int64_t b) {
+    double va = V(a), vb = V(b);
+    return emit2(t, va * vb, a, vb, b, va);
+}
+static int64_t t_scale(tape_t* t, int64_t a, double c) { return emit1(t, c * V(a), a, c); }
+static int64_t t_exp(tape_t* t, int64_t a) {
+    double e = exp(V(a));
+    return emit1(t, e, a, e);
+}
+static int64_t t_log(tape_t* t, int64_t a) {
+    double va = V(a);
+    return emit1(t, log(va), a, 1.0 / va);
+}
+static int64_t t_sin(tape_t* t, int64_t a) {
+    double va = V(a);
+    return emit1(t, sin(va), a, cos(va));
+}
+static int64_t t_tanh(tape_t* t, int64_t a) {
+    double y = tanh(V(a));
+    return emit1(t, y, a, 1.0 - y * y);
+}
+/* A selection: the result is a copy of whichever operand was chosen, so the
+ * whole adjoint flows to that operand (min/max, Sec. 5.1.1). */
+static int64_t t_pick(tape_t* t, int64_t a, int64_t b, int take_b) {
+    return take_b ? emit1(t, V(b), b, 1.0) : emit1(t, V(a), a, 1.0);
+}
+
+static int tape_reverse(tape_t* t) {
+    free(t->adj);
+    t->adj = (double*)calloc((size_t)(t->nv > 0 ? t->nv : 1), sizeof(double));
+    return t->adj ? 0 : -2;
+}
+
+/* Seeds must be placed after tape_reverse() allocated adj and before sweep(). */
+static void sweep(tape_t* t) {
+    for (int64_t r = t->nr - 1; r >= 0; --r) {
+        const rec_t* q = &t->rec[r];
+        double g = t->adj[q->out];
+        if (g == 0.0) continue; /* exact: contributions would be +-0 */
+        t->adj[q->in0] += q->w0 * g;
+        if (q->in1 >= 0) t->adj[q->in1] += q->w1 * g;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Linear-recurrence inclusive scan (Sec. 5.2).                               */
+/* rs[0] = as[0]; rs[i] = rs[i-1] (+) as[i], with                             */
+/* (A, B) (+) (a, b) = (a*A, a*B + b).                                        */
+/* ------------------------------------------------------------------------ */
+
+int orc_linrec_scan(int64_t n, const double* a, const double* b, double* A, double* B) {
+    if (n < 0 || (n > 0 && (!a || !b || !A || !B))) return -1;
+    for (int64_t i = 0; i < n; ++i) {
+        if (i == 0) {
+            A[0] = a[0];
+            B[0] = b[0];
+        } else {
+            A[i] = a[i] * A[i - 1];
+            B[i] = a[i] * B[i - 1] + b[i];
+        }
+    }
+    return 0;
+}
+
+int orc_linrec_scan_vjp(int64_t n, const double* a, const double* b,
+                        const double* yA_bar, const double* yB_bar,
+                        double* a_bar, double* b_bar) {
+    if (n < 0 || (n > 0 && (!a || !b || !yA_bar || !yB_bar || !a_bar || !b_bar))) return -1;
+    if (n == 0) return 0;
+    tape_t T, *t = &T;
+    if (tape_init(t, 5 * n + 16, 3 * n + 16)) return -2;
+    int64_t* sa = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+    int64_t* sb = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+    int64_t* sA = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+    int64_t* sB = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+    int rc = 0;
+    if (!sa || !sb || !sA || !sB) {
+        rc = -2;
+        goto done;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        sa[i] = leaf(t, a[i]);
+        sb[i] = leaf(t, b[i]);
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        if (i == 0) { /* rs[0] = as[0]: the same variables */
+            sA[0] = sa[0];
+            sB[0] = sb[0];
+        } else {
+            sA[i] = t_mul(t, sa[i], sA[i - 1]);
+            sB[i] = t_add(t, t_mul(t, sa[i], sB[i - 1]), sb[i]);
+        }
+    }
+    if (t->oom || tape_reverse(t)) {
+        rc = -2;
+        goto done;
+    }
+    for (int64_t i = 0; i < n; ++i) { /* += : A[0] aliases a[0] */
+        t->adj[sA[i]] += yA_bar[i];
+        t->adj[sB[i]] += yB_bar[i];
+    }
+    sweep(t);
+    for (int64_t i = 0; i < n; ++i) {
+        a_bar[i] = t->adj[sa[i]];
+        b_bar[i] = t->adj[sb[i]];
+    }
+done:
+    free(sa);
+    free(sb);
+    free(sA);
+    free(sB);
+    tape_free(t);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* reduce (Sec. 5.1): y = e; for i: y = y (+) x[i].                           */
+/* For min/max the first element of the array always replaces the neutral    */
+/* element and a later element replaces y only when strictly better, so the   */
+/* adjoint goes to the lowest index attaining the extreme (Sec. 5.1.1).       */
+/* ------------------------------------------------------------------------ */
+
+static double neutral(int op) {
+    switch (op) {
+        case ORC_ADD: return 0.0;
+        case ORC_MUL: return 1.0;
+        case ORC_MIN: return INFINITY;
+        default: return -INFINITY;
+    }
+}
+
+static int better(int op, double v, double cur) { return op == ORC_MAX ? (v > cur) : (v < cur); }
+
+int orc_reduce(int op, int64_t n, const double* x, double* y, int64_t* arg,
+               double* p, int64_t* z) {
+    if (op < ORC_ADD || op > ORC_MAX || n < 0 || (n > 0 && !x) || !y) return -1;
+    double acc = neutral(op);
+    int64_t best = -1;
+    double prod_nz = 1.0;
+    int64_t zeros = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        switch (op) {
+            case ORC_ADD: acc = acc + x[i]; break;
+            case ORC_MUL:
+                acc = acc * x[i];
+                if (x[i] == 0.0)
+                    zeros++;
+                else
+                    prod_nz *= x[i];
+                break;
+            default:
+                if (best < 0 || better(op, x[i], acc)) {
+                    acc = x[i];
+                    best = i;
+                }
+        }
+    }
+    *y = acc;
+    if (arg) *arg = best;
+    if (p) *p = prod_nz;
+    if (z) *z = zeros;
+    return 0;
+}
+
+int orc_reduce_vjp(int op, int64_t n, const double* x, double y_bar, double* x_bar) {
+    if (op < ORC_ADD || op > ORC_MAX || n < 0 || (n > 0 && (!x || !x_bar))) return -1;
+    if (n == 0) return 0;
+    tape_t T, *t = &T;
+    if (tape_init(t, 2 * n + 16, n + 16)) return -2;
+    int64_t* sx = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+    if (!sx) {
+        tape_free(t);
+        return -2;
+    }
+    for (int64_t i = 0; i < n; ++i) sx[i] = leaf(t, x[i]);
+    int64_t y = leaf(t, neutral(op)); /* the neutral element: a constant */
+    int first = 1;
+    for (int64_t i = 0; i < n; ++i) {
+        switch (op) {
+            case ORC_ADD: y = t_add(t, y, sx[i]); break;
+            case ORC_MUL: y = t_mul(t, y, sx[i]); break;
+            default: y = t_pick(t, y, sx[i], first || better(op, x[i], V(y)));
+        }
+        first = 0;
+    }
+    int rc = (t->oom || tape_reverse(t)) ? -2 : 0;
+    if (!rc) {
+        t->adj[y] += y_bar;
+        sweep(t);
+        for (int64_t i = 0; i < n; ++i) x_bar[i] = t->adj[sx[i]];
+    }
+    free(sx);
+    tape_free(t);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* reduce_by_index (Sec. 5.1.2):                                               */
+/* hs = replicate m e; for i in 0..n-1: hs[inds[i]] (+)= vs[i].               */
+/* The first element of a bin replaces the neutral element exactly (e (+) v   */
+/* == v for all four operators), so a bin's variable is that element's.       */
+/* ------------------------------------------------------------------------ */
+
+int orc_hist(int op, int64_t n, int64_t m, const int32_t* inds, const double* vs,
+             double* hs, int64_t* winner, double* p, int64_t* z, int64_t* count) {
+    if (op < ORC_ADD || op > ORC_MAX || n < 0 || m < 0 || (n > 0 && (!inds || !vs))) return -1;
+    for (int64_t k = 0; k < m; ++k) {
+        if (hs) hs[k] = neutral(op);
+        if (winner) winner[k] = -1;
+        if (p) p[k] = 1.0;
+        if (z) z[k] = 0;
+        if (count) count[k] = 0;
+    }
+    int64_t* cnt = (int64_t*)calloc((size_t)(m > 0 ? m : 1), sizeof(int64_t));
+    double* h = (double*)malloc((size_t)(m > 0 ? m : 1) * sizeof(double));
+    if (!cnt || !h) {
+        free(cnt);
+        free(h);
+        return -2;
+    }
+    for (int64_t k = 0; k < m; ++k) h[k] = neutral(op);
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t k = inds[i];
+        if (k < 0 || k >= m) continue;
+        double v = vs[i];
+        switch (op) {
+            case ORC_ADD: h[k] = h[k] + v; break;
+            case ORC_MUL:
+                h[k] = h[k] * v;
+                if (v == 0.0) {
+                    if (z) z[k]++;
+                } else if (p) {
+                    p[k] *= v;
+                }
+                break;
+            default:
+                if (cnt[k] == 0 || better(op, v, h[k])) {
+                    h[k] = v;
+                    if (winner) winner[k] = i;
+                }
+        }
+        cnt[k]++;
+    }
+    for (int64_t k = 0; k < m; ++k) {
+        if (hs) hs[k] = h[k];
+        if (count) count[k] = cnt[k];
+    }
+    free(cnt);
+    free(h);
+    return 0;
+}
+
+int orc_hist_vjp(int op, int64_t n, int64_t m, const int32_t* inds, const double* vs,
+                 const double* hs_bar, double* vs_bar) {
+    if (op < ORC_ADD || op > ORC_MAX || n < 0 || m < 0 ||
+        (n > 0 && (!inds || !vs || !vs_bar)) || (m > 0 && !hs_bar))
+        return -1;
+    if (n == 0) return 0;
+    tape_t T, *t = &T;
+    if (tape_init(t, 2 * n + 16, n + 16)) return -2;
+    int64_t* sv = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+    int64_t* sh = (int64_t*)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+    if (!sv || !sh) {
+        free(sv);
+        free(sh);
+        tape_free(t);
+        return -2;
+    }
+    for (int64_t i = 0; i < n; ++i) sv[i] = leaf(t, vs[i]);
+    for (int64_t k = 0; k < m; ++k) sh[k] = -1; /* empty bin: still the constant e */
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t k = inds[i];
+        if (k < 0 || k >= m) continue;
+        if (sh[k] < 0) {
+            sh[k] = sv[i];
+            continue;
+        }
+        switch (op) {
+            case ORC_ADD: sh[k] = t_add(t, sh[k], sv[i]); break;
+            case ORC_MUL: sh[k] = t_mul(t, sh[k], sv[i]); break;
+            default: sh[k] = t_pick(t, sh[k], sv[i], better(op, vs[i], V(sh[k])));
+        }
+    }
+    int rc = (t->oom || tape_reverse(t)) ? -2 : 0;
+    if (!rc) {
+        for (int64_t k = 0; k < m; ++k)
+            if (sh[k] >= 0) t->adj[sh[k]] += hs_bar[k];
+        sweep(t);
+        for (int64_t i = 0; i < n; ++i) vs_bar[i] = t->adj[sv[i]];
+    }
+    free(sv);
+    free(sh);
+    tape_free(t);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* scatter (Sec. 5.3): ys = xs; for j: ys[is[j]] = vs[j].                     */
+/* An assignment makes ys[k] the very variable vs[j]; the tape needs no       */
+/* records, only the map from output positions to variables.                  */
+/* ------------------------------------------------------------------------ */
+
+int orc_scatter(int64_t n, const double* xs, int64_t m, const int32_t* is,
+                const double* vs, double* ys, double* xs_saved) {
+    if (n < 0 || m < 0 || (n > 0 && (!xs || !ys)) || (m > 0 && (!is || !vs))) return -1;
+    for (int64_t k = 0; k < n; ++k) ys[k] = xs[k];
+    for (int64_t j = 0; j < m; ++j) {
+        int64_t k = is[j];
+        int ok = (k >= 0 && k < n);
+        if (xs_saved) xs_saved[j] = ok ? xs[k] : 0.0;
+        if (ok) ys[k] = vs[j];
+    }
+    return 0;
+}
+
+int orc_scatter_vjp(int64_t n, int64_t m, const int32_t* is, const double* ys_bar,
+                    double* xs_bar, double* vs_bar) {
+    if (n < 0 || m < 0 || (n > 0 && (!ys_bar || !xs_bar)) || (m > 0 && (!is || !vs_bar))) return -1;
+    tape_t T, *t = &T;
+    if (tape_init(t, n + m + 16, 16)) return -2;
+    int64_t* out = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    if (!out) {
+        tape_free(t);
+        return -2;
+    }
+    int64_t x0 = t->nv;
+    for (int64_t k = 0; k < n; ++k) out[k] = leaf(t, 0.0); /* xs variables */
+    int64_t v0 = t->nv;
+    for (int64_t j = 0; j < m; ++j) leaf(t, 0.0); /* vs variables */
+    for (int64_t j = 0; j < m; ++j) {
+        int64_t k = is[j];
+        if (k >= 0 && k < n) out[k] = v0 + j;
+    }
+    int rc = (t->oom || tape_reverse(t)) ? -2 : 0;
+    if (!rc) {
+        for (int64_t k = 0; k < n; ++k) t->adj[out[k]] += ys_bar[k];
+        sweep(t);
+        for (int64_t k = 0; k < n; ++k) xs_bar[k] = t->adj[x0 + k];
+        for (int64_t j = 0; j < m; ++j) vs_bar[j] = t->adj[v0 + j];
+    }
+    free(out);
+    tape_free(t);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* map (Sec. 5.4).  Each element is an independent small program.           */
+/* ------------------------------------------------------------------------ */
+
+static int64_t apply_fn(tape_t* t, int fn, int64_t x) {
+    switch (fn) {
+        case ORC_FN_SQUARE: return t_mul(t, x, x);
+        case ORC_FN_EXP: return t_exp(t, x);
+        case ORC_FN_LOG: return t_log(t, x);
+        case ORC_FN_SIN: return t_sin(t, x);
+        default: return t_tanh(t, x);
+    }
+}
+
+int orc_map(int fn, int64_t n, const double* x, double* y) {
+    if (fn < ORC_FN_SQUARE || fn > ORC_FN_TANH || n < 0 || (n > 0 && (!x || !y))) return -1;
+    tape_t T, *t = &T;
+    if (tape_init(t, 16, 16)) return -2;
+    for (int64_t i = 0; i < n; ++i) {
+        tape_clear(t);
+        y[i] = V(apply_fn(t, fn, leaf(t, x[i])));
+    }
+    tape_free(t);
+    return 0;
+}
+
+int orc_map_vjp(int fn, int64_t n, const double* x, const double* y_bar, double* x_bar) {
+    if (fn < ORC_FN_SQUARE || fn > ORC_FN_TANH || n < 0 || (n > 0 && (!x || !y_bar || !x_bar)))
+        return -1;
+    tape_t T, *t = &T;
+    if (tape_init(t, 16, 16)) return -2;
+    for (int64_t i = 0; i < n; ++i) {
+        tape_clear(t);
+        int64_t xs = leaf(t, x[i]);
+        int64_t ys = apply_fn(t, fn, xs);
+        if (tape_reverse(t)) {
+            tape_free(t);
+            return -2;
+        }
+        t->adj[ys] += y_bar[i];
+        sweep(t);
+        x_bar[i] = t->adj[xs];
+    }
+    tape_free(t);
+    return 0;
+}
+
+/* Fig. 1(a): v0 = sin(x0); v1 = x1 * v0; v2 = x0 * x1; (y0, y1) = (v1, v2). */
+static void fig1_program(tape_t* t, int64_t x0, int64_t x1, int64_t* y0, int64_t* y1) {
+    int64_t v0 = t_sin(t, x0);
+    int64_t v1 = t_mul(t, x1, v0);
+    int64_t v2 = t_mul(t, x0, x1);
+    *y0 = v1;
+    *y1 = v2;
+}
+
+int orc_fig1(int64_t n, const double* x0, const double* x1, double* y0, double* y1) {
+    if (n < 0 || (n > 0 && (!x0 || !x1 || !y0 || !y1))) return -1;
+    tape_t T, *t = &T;
+    if (tape_init(t, 16, 16)) return -2;
+    for (int64_t i = 0; i < n; ++i) {
+        tape_clear(t);
+        int64_t a = leaf(t, x0[i]), b = leaf(t, x1[i]), r0, r1;
+        fig1_program(t, a, b, &r0, &r1);
+        y0[i] = V(r0);
+        y1[i] = V(r1);
+    }
+    tape_free(t);
+    return 0;
+}
+
+int orc_fig1_vjp(int64_t n, const double* x0, const double* x1,
+                 const double* y0_bar, const double* y1_bar,
+                 double* x0_bar, double* x1_bar) {
+    if (n < 0 || (n > 0 && (!x0 || !x1 || !y0_bar || !y1_bar || !x0_bar || !x1_bar))) return -1;
+    tape_t T, *t = &T;
+    if (tape_init(t, 16, 16)) return -2;
+    for (int64_t i = 0; i < n; ++i) {
+        tape_clear(t);
+        int64_t a = leaf(t, x0[i]), b = leaf(t, x1[i]), r0, r1;
+        fig1_program(t, a, b, &r0, &r1);
+        if (tape_reverse(t)) {
+            tape_free(t);
+            return -2;
+        }
+        t->adj[r0] += y0_bar[i];
+        t->adj[r1] += y1_bar[i];
+        sweep(t);
+        x0_bar[i] = t->adj[a];
+        x1_bar[i] = t->adj[b];
+    }
+    tape_free(t);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Gaussian mixture (the objective is stated in oracle.h).                    */
+/* ------------------------------------------------------------------------ */
+
+/* log-sum-exp of the variables s[0..K-1]: mx + log(sum_k exp(s_k - mx)).
+ * The shift mx = max_k s_k enters as a constant: the derivative of LSE does
+ * not depend on the shift. */
+static int64_t t_lse(tape_t* t, const int64_t* s, int K) {
+    double mx = -INFINITY;
+    for (int k = 0; k < K; ++k)
+        if (V(s[k]) > mx) mx = V(s[k]);
+    int64_t c = leaf(t, mx);
+    int64_t acc = -1;
+    for (int k = 0; k < K; ++k) {
+        int64_t e = t_exp(t, t_sub(t, s[k], c));
+        acc = (acc < 0) ? e : t_add(t, acc, e);
+    }
+    return t_add(t, t_log(t, acc), c);
+}
+
+typedef struct {
+    int64_t *alpha, *mu, *q, *l; /* parameter variables */
+} gmm_slots;
+
+/* Records the point term LSE_k(s_ik) of point x (length D); returns its slot. */
+static int64_t gmm_point(tape_t* t, int D, int K, const double* x, const gmm_slots* P,
+                         int64_t* s /* K scratch */) {
+    const int64_t tri = (int64_t)D * (D - 1) / 2;
+    int64_t* y = (int64_t*)malloc((size_t)D * sizeof(int64_t));
+    int64_t* ed = (int64_t*)malloc((size_t)D * sizeof(int64_t));
+    if (!y || !ed) {
+        free(y);
+        free(ed);
+        t->oom = 1;
+        return 0;
+    }
+    for (int k = 0; k < K; ++k) {
+        for (int d = 0; d < D; ++d) {
+            y[d] = t_sub(t, leaf(t, x[d]), P->mu[(int64_t)k * D + d]); /* y = x - mu_k */
+            ed[d] = t_exp(t, P->q[(int64_t)k * D + d]);                /* diag of Q_k */
+        }
+        int64_t sq = -1;
+        for (int r = 0; r < D; ++r) { /* z_r = exp(q_kr) y_r + sum_{c<r} L_rc y_c */
+            int64_t z = t_mul(t, ed[r], y[r]);
+            for (int c = 0; c < r; ++c)
+                z = t_add(t, z, t_mul(t, P->l[(int64_t)k * tri + (int64_t)r * (r - 1) / 2 + c], y[c]));
+            int64_t z2 = t_mul(t, z, z);
+            sq = (sq < 0) ? z2 : t_add(t, sq, z2);
+        }
+        int64_t sumq = P->q[(int64_t)k * D];
+        for (int d = 1; d < D; ++d) sumq = t_add(t, sumq, P->q[(int64_t)k * D + d]);
+        s[k] = t_sub(t, t_add(t, P->alpha[k], sumq), t_scale(t, sq, 0.5));
+    }
+    free(y);
+    free(ed);
+    return t_lse(t, s, K);
+}
+
+static int gmm_make_leaves(tape_t* t, int D, int K, const double* alpha, const double* mu,
+                           const double* q, const double* l, gmm_slots* P) {
+    const int64_t tri = (int64_t)D * (D - 1) / 2;
+    P->alpha = (int64_t*)malloc((size_t)K * sizeof(int64_t));
+    P->mu = (int64_t*)malloc((size_t)K * D * sizeof(int64_t));
+    P->q = (int64_t*)malloc((size_t)K * D * sizeof(int64_t));
+    P->l = (int64_t*)malloc((size_t)(K * tri > 0 ? K * tri : 1) * sizeof(int64_t));
+    if (!P->alpha || !P->mu || !P->q || !P->l) return -2;
+    for (int k = 0; k < K; ++k) P->alpha[k] = leaf(t, alpha[k]);
+    for (int64_t j = 0; j < (int64_t)K * D; ++j) P->mu[j] = leaf(t, mu[j]);
+    for (int64_t j = 0; j < (int64_t)K * D; ++j) P->q[j] = leaf(t, q[j]);
+    for (int64_t j = 0; j < (int64_t)K * tri; ++j) P->l[j] = leaf(t, l[j]);
+    return t->oom ? -2 : 0;
+}
+
+static void gmm_free_leaves(gmm_slots* P) {
+    free(P->alpha);
+    free(P->mu);
+    free(P->q);
+    free(P->l);
+}
+
+static int gmm_args_ok(int64_t N, int D, int K, const double* X, const double* alpha,
+                       const double* mu, const double* q, const double* l) {
+    if (N < 0 || D < 1 || K < 1) return 0;
+    if (!alpha || !mu || !q || (D > 1 && !l) || (N > 0 && !X)) return 0;
+    return 1;
+}
+
+int orc_gmm_objective(int64_t N, int D, int K, const double* X, const double* alpha,
+                      const double* mu, const double* q, const double* l,
+                      double* loglik, double* lse) {
+    if (!gmm_args_ok(N, D, K, X, alpha, mu, q, l) || !loglik) return -1;
+    tape_t T, *t = &T;
+    if (tape_init(t, 1 << 16, 1 << 16)) return -2;
+    int64_t* s = (int64_t*)malloc((size_t)K * sizeof(int64_t));
+    gmm_slots P = {0, 0, 0, 0};
+    int rc = s ? 0 : -2;
+    double total = 0.0;
+    for (int64_t i = 0; i < N && !rc; ++i) {
+        tape_clear(t);
+        if ((rc = gmm_make_leaves(t, D, K, alpha, mu, q, l, &P))) break;
+        int64_t r = gmm_point(t, D, K, X + i * D, &P, s);
+        gmm_free_leaves(&P);
+        if (t->oom) {
+            rc = -2;
+            break;
+        }
+        if (lse) lse[i] = V(r);
+        total += V(r);
+    }
+    if (!rc) {
+        tape_clear(t);
+        if (!(rc = gmm_make_leaves(t, D, K, alpha, mu, q, l, &P))) {
+            double la = V(t_lse(t, P.alpha, K));
+            *loglik = total - (double)N * la - 0.5 * (double)N * D * log(TWO_PI);
+        }
+        gmm_free_leaves(&P);
+    }
+    free(s);
+    tape_free(t);
+    return rc;
+}
+
+int orc_gmm_vjp(int64_t N, int D, int K, const double* X, const double* alpha,
+                const double* mu, const double* q, const double* l, double ell_bar,
+                double* alpha_bar, double* mu_bar, double* q_bar, double* l_bar) {
+    if (!gmm_args_ok(N, D, K, X, alpha, mu, q, l) || !alpha_bar || !mu_bar || !q_bar ||
+        (D > 1 && !l_bar))
+        return -1;
+    const int64_t tri = (int64_t)D * (D - 1) / 2;
+    memset(alpha_bar, 0, (size_t)K * sizeof(double));
+    memset(mu_bar, 0, (size_t)K * D * sizeof(double));
+    memset(q_bar, 0, (size_t)K * D * sizeof(double));
+    if (tri > 0) memset(l_bar, 0, (size_t)(K * tri) * sizeof(double));
+    tape_t T, *t = &T;
+    if (tape_init(t, 1 << 16, 1 << 16)) return -2;
+    int64_t* s = (int64_t*)malloc((size_t)K * sizeof(int64_t));
+    gmm_slots P = {0, 0, 0, 0};
+    int rc = s ? 0 : -2;
+    /* One tape per point term (each point's LSE is its own small program), plus
+     * one for the -N * LSE(alpha) term.  Parameter adjoints are summed. */
+    for (int64_t i = 0; i <= N && !rc; ++i) {
+        tape_clear(t);
+        if ((rc = gmm_make_leaves(t, D, K, alpha, mu, q, l, &P))) break;
+        int64_t r;
+        double seed;
+        if (i < N) {
+            r = gmm_point(t, D, K, X + i * D, &P, s);
+            seed = ell_bar;
+        } else {
+            r = t_lse(t, P.alpha, K);
+            seed = -(double)N * ell_bar;
+        }
+        if (t->oom || tape_reverse(t)) {
+            rc = -2;
+            gmm_free_leaves(&P);
+            break;
+        }
+        t->adj[r] += seed;
+        sweep(t);
+        for (int k = 0; k < K; ++k) alpha_bar[k] += t->adj[P.alpha[k]];
+        for (int64_t j = 0; j < (int64_t)K * D; ++j) {
+            mu_bar[j] += t->adj[P.mu[j]];
+            q_bar[j] += t->adj[P.q[j]];
+        }
+        for (int64_t j = 0; j < (int64_t)K * tri; ++j) l_bar[j] += t->adj[P.l[j]];
+        gmm_free_leaves(&P);
+    }
+    free(s);
+    tape_free(t);
+    return rc;
+}

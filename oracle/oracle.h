@@ -1,0 +1,94 @@
+/*
+ * CPU oracle for the reverse-mode rules of bulk-parallel operators.
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product path may include, link or
+ * call this code; it exists so that the GPU library can be checked against a
+ * plain, slow, obviously correct implementation that shares no code with it.
+ *
+ * Method. Every function evaluates its operator by the sequential semantics
+ * the paper states for it (reduce: Sec. 5.1; reduce_by_index: Sec. 5.1.2;
+ * inclusive scan: Sec. 5.2; scatter: Sec. 5.3; map: Sec. 5.4) in FP64 while
+ * recording each elementary step on an explicit tape (a Wengert list of
+ * records holding the local partial derivatives).  A VJP seeds the output
+ * adjoints and sweeps the tape in reverse, applying the core rewrite rule
+ * a_bar += (df/da) * v_bar of Sec. 2.0.2 (eq. rewrite-adj), summing over all
+ * uses of a variable.  The oracle deliberately does NOT implement the
+ * paper's per-operator rewrite rules (two scans for reduce, the three-case
+ * product rule, the lin_o reversed scan, the gather form of the scatter
+ * adjoint): those are what the GPU kernels implement, so agreement between the
+ * two is independent evidence.
+ *
+ * All arrays are host arrays owned by the caller; all floating-point data is
+ * double (FP32 inputs are upcast exactly by the caller).  Return value: 0 on
+ * success, -1 on bad arguments, -2 on allocation failure.
+ */
+#ifndef PVJP_ORACLE_H
+#define PVJP_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_ADD = 0, ORC_MUL = 1, ORC_MIN = 2, ORC_MAX = 3 };
+enum { ORC_FN_SQUARE = 0, ORC_FN_EXP = 1, ORC_FN_LOG = 2, ORC_FN_SIN = 3, ORC_FN_TANH = 4 };
+
+/* Linear-recurrence inclusive scan (Sec. 5.2 with the operator
+ * (a1,b1) (+) (a2,b2) = (a2*a1, a2*b1 + b2)). */
+int orc_linrec_scan(int64_t n, const double* a, const double* b, double* A, double* B);
+int orc_linrec_scan_vjp(int64_t n, const double* a, const double* b,
+                        const double* yA_bar, const double* yB_bar,
+                        double* a_bar, double* b_bar);
+
+/* reduce (Sec. 5.1, 5.1.1).  Primal outputs: y; for MIN/MAX the lowest index
+ * attaining y (-1 if n == 0); for MUL the product of the non-zero elements p
+ * and the zero count z. */
+int orc_reduce(int op, int64_t n, const double* x, double* y, int64_t* arg,
+               double* p, int64_t* z);
+int orc_reduce_vjp(int op, int64_t n, const double* x, double y_bar, double* x_bar);
+
+/* reduce_by_index (Sec. 5.1.2): hs[k] = (+) over {i : inds[i] == k} of vs[i].
+ * Indices outside [0, m) are ignored.  Outputs (any may be NULL): hs[m];
+ * winner[m] (MIN/MAX: lowest index attaining hs[k], -1 if empty); p[m] and
+ * z[m] (MUL: product of non-zeros, zero count); count[m]. */
+int orc_hist(int op, int64_t n, int64_t m, const int32_t* inds, const double* vs,
+             double* hs, int64_t* winner, double* p, int64_t* z, int64_t* count);
+int orc_hist_vjp(int op, int64_t n, int64_t m, const int32_t* inds, const double* vs,
+                 const double* hs_bar, double* vs_bar);
+
+/* scatter (Sec. 5.3): ys = xs with ys[is[j]] = vs[j]; xs_saved[j] = xs[is[j]].
+ * Indices outside [0, n) are ignored (xs_saved[j] = 0 for them). */
+int orc_scatter(int64_t n, const double* xs, int64_t m, const int32_t* is,
+                const double* vs, double* ys, double* xs_saved);
+int orc_scatter_vjp(int64_t n, int64_t m, const int32_t* is, const double* ys_bar,
+                    double* xs_bar, double* vs_bar);
+
+/* map (Sec. 5.4) of a unary elementwise function. */
+int orc_map(int fn, int64_t n, const double* x, double* y);
+int orc_map_vjp(int fn, int64_t n, const double* x, const double* y_bar, double* x_bar);
+
+/* map of the two-input, two-output program of Fig. 1:
+ * P(x0, x1) = (x1 * sin(x0), x0 * x1), applied elementwise. */
+int orc_fig1(int64_t n, const double* x0, const double* x1, double* y0, double* y1);
+int orc_fig1_vjp(int64_t n, const double* x0, const double* x1,
+                 const double* y0_bar, const double* y1_bar,
+                 double* x0_bar, double* x1_bar);
+
+/* Gaussian-mixture log-likelihood with a precision-Cholesky parametrisation:
+ *   Q_k = diag(exp(q_k)) + L_k,  L_k strictly lower, entry (r,c), r > c, at
+ *         l[k*D(D-1)/2 + r(r-1)/2 + c];
+ *   s_ik = alpha_k + sum_d q_kd - 0.5 * || Q_k (x_i - mu_k) ||^2;
+ *   loglik = sum_i LSE_k(s_ik) - N * LSE(alpha) - (N*D/2) * log(2*pi).
+ * X is row-major N x D, mu and q are K x D.  lse (nullable) receives the
+ * per-point LSE_k(s_ik). */
+int orc_gmm_objective(int64_t N, int D, int K, const double* X, const double* alpha,
+                      const double* mu, const double* q, const double* l,
+                      double* loglik, double* lse);
+int orc_gmm_vjp(int64_t N, int D, int K, const double* X, const double* alpha,
+                const double* mu, const double* q, const double* l, double ell_bar,
+                double* alpha_bar, double* mu_bar, double* q_bar, double* l_bar);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
