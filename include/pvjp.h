@@ -1,0 +1,228 @@
+/*
+ * pvjp.h -- C ABI of libpvjp.so: primal and reverse-mode (VJP) kernels for
+ * bulk-parallel operators on AMD Instinct MI355X (gfx950).
+ *
+ * The rules follow Schenck, Roenning, Henriksen, Oancea, "AD for an Array
+ * Language with Nested Parallelism" (arXiv 2202.10297).  A VJP entry point
+ * computes x_bar = y_bar . J(x) for the operator at the point x (Sec. 2.0.2,
+ * the definition of vjp), recomputing the primal values it needs per tile
+ * instead of reading a tape (Sec. 4.1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers named for arrays are DEVICE pointers, owned by the caller; the
+ *    library never allocates, frees or retains them.  Scalars travel by value
+ *    or, where a kernel produces or consumes them, as device pointers.
+ *  - Arrays are contiguous, element-aligned, structure-of-arrays.  Indices are
+ *    int32; element counts are int64.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Every call is
+ *    asynchronous on that stream; a returned PVJP_OK means the launch was
+ *    accepted, not that the kernels have finished.
+ *  - `accumulate` != 0 selects the paper's adjoint update x_bar += contribution
+ *    (Sec. 2.0.2, eq. rewrite-adj); 0 overwrites x_bar with the contribution.
+ *  - Outputs must not alias inputs, except where an entry point says it works
+ *    in place.
+ *  - Workspaces: entry points that take (ws, ws_bytes) need device scratch of
+ *    at least the size the matching *_ws_bytes() query returns.  A workspace
+ *    must be zero-filled before its first use (pvjp_ws_clear, or any zeroing
+ *    allocation); every call leaves it ready for the next call.  Two calls
+ *    that may run concurrently must not share a workspace.
+ *  - Errors: host-side validation (NULL pointers where data is needed,
+ *    negative sizes, unknown op/dtype, workspace too small, index range
+ *    limits) returns a non-zero status before any launch; launch failures
+ *    return PVJP_EDEVICE.  pvjp_last_error() then describes the failure (text
+ *    is per calling thread).  No C++ exception crosses this interface.
+ *    Out-of-range indices in reduce_by_index and scatter are not errors: the
+ *    element is ignored (its adjoint is zero).
+ *  - FP32 entry points compute in FP32 except where stated (FP64 for sums and
+ *    products of reductions); FP64 entry points compute in FP64.
+ */
+#ifndef PVJP_H
+#define PVJP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int pvjp_status;
+#define PVJP_OK 0
+#define PVJP_EINVAL 1      /* bad argument (see pvjp_last_error) */
+#define PVJP_ENOMEM 2      /* workspace too small */
+#define PVJP_EDEVICE 3     /* HIP launch or runtime error */
+#define PVJP_EUNSUPPORTED 4 /* valid but unsupported combination */
+
+typedef enum { PVJP_F32 = 0, PVJP_F64 = 1 } pvjp_dtype;
+
+/* Reduction operators of Sec. 5.1.1 and their neutral elements:
+ * ADD 0, MUL 1, MIN +inf, MAX -inf. */
+typedef enum { PVJP_ADD = 0, PVJP_MUL = 1, PVJP_MIN = 2, PVJP_MAX = 3 } pvjp_op;
+
+/* Elementwise functions offered by the map entry points (Sec. 5.4). */
+typedef enum {
+    PVJP_FN_SQUARE = 0, /* x*x, the lambda of Sec. 4.1's example */
+    PVJP_FN_EXP = 1,
+    PVJP_FN_LOG = 2,
+    PVJP_FN_SIN = 3,
+    PVJP_FN_TANH = 4
+} pvjp_fn;
+
+/* ------------------------------------------------------------------------ */
+/* Library                                                                    */
+/* ------------------------------------------------------------------------ */
+
+/* Text of the last failure on the calling thread ("" if none). */
+const char* pvjp_last_error(void);
+/* Version string, e.g. "pvjp 0.1.0 gfx950". */
+const char* pvjp_version(void);
+/* Zero-fills ws_bytes of device memory at ws on `stream` (a kernel, not a
+ * memset node, so it may be captured in a HIP graph). */
+pvjp_status pvjp_ws_clear(void* ws, size_t ws_bytes, void* stream);
+
+/* Synchronises `stream`, then reports whether a lookback kernel found the
+ * workspace `ws` in a state the protocol never leaves it in (a ticket outside
+ * its grid, or a predecessor tile that never published: both mean the
+ * workspace was not zero-filled, or was shared by overlapping calls).  Such a
+ * launch finishes without hanging but its results are invalid.  Returns
+ * PVJP_OK if no error is recorded, PVJP_EDEVICE otherwise (pvjp_last_error()
+ * names the condition); clear != 0 resets the recorded error. */
+pvjp_status pvjp_ws_check(void* ws, int clear, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Inclusive scan of the first-order linear recurrence (Sec. 5.2)             */
+/*                                                                            */
+/* Operator (a1,b1) (+) (a2,b2) = (a2*a1, a2*b1 + b2), neutral (1, 0):        */
+/*   A[0] = a[0], B[0] = b[0]; A[i] = a[i]*A[i-1], B[i] = a[i]*B[i-1] + b[i]. */
+/* Single-pass decoupled-lookback scan.                                       */
+/* ------------------------------------------------------------------------ */
+
+/* Elements per checkpoint: ckpt[c] holds the scan state before element
+ * c * PVJP_LINREC_CKPT_INTERVAL, i.e. the exclusive prefix (A, B). */
+#define PVJP_LINREC_CKPT_INTERVAL 1024
+/* Number of checkpoint pairs for n elements: ceil(n / interval). */
+int64_t pvjp_linrec_ckpt_len(int64_t n);
+
+size_t pvjp_linrec_scan_ws_bytes(pvjp_dtype dtype, int64_t n);
+/* a, b: input arrays [n] of dtype.  A, B: outputs [n] of dtype.
+ * ckpt (nullable): output, 2 * pvjp_linrec_ckpt_len(n) elements of dtype laid
+ * out as pairs (A, B).  A and B may be NULL together to compute only ckpt. */
+pvjp_status pvjp_linrec_scan(pvjp_dtype dtype, const void* a, const void* b, int64_t n,
+                             void* A, void* B, void* ckpt, void* ws, size_t ws_bytes,
+                             void* stream);
+
+size_t pvjp_linrec_scan_vjp_ws_bytes(pvjp_dtype dtype, int64_t n);
+/* Reverse sweep of Sec. 5.2: c_i = a_{i+1} (the Jacobian of the operator in
+ * its left argument is a_{i+1} * I), a reversed scan with
+ * lin_o((d1,c1),(d2,c2)) = (d2 + c2*d1, c2*c1) giving
+ * r_bar_i = y_bar_i + a_{i+1} * r_bar_{i+1}, then the map
+ * a_bar_i = A_{i-1}*rA_bar_i + B_{i-1}*rB_bar_i, b_bar_i = rB_bar_i with
+ * (A_{-1}, B_{-1}) = (1, 0).  The primal prefixes (A_{i-1}, B_{i-1}) are
+ * recomputed per tile from `ckpt` (as written by pvjp_linrec_scan for the same
+ * a, b, n); with ckpt == NULL a checkpoint-only primal pass into the
+ * workspace runs first.  yA_bar, yB_bar: output adjoints [n]; a_bar, b_bar:
+ * input adjoints [n]. */
+pvjp_status pvjp_linrec_scan_vjp(pvjp_dtype dtype, const void* a, const void* b,
+                                 const void* yA_bar, const void* yB_bar, int64_t n,
+                                 const void* ckpt, void* a_bar, void* b_bar, int accumulate,
+                                 void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* reduce (Sec. 5.1, special operators Sec. 5.1.1)                            */
+/* ------------------------------------------------------------------------ */
+
+size_t pvjp_reduce_ws_bytes(pvjp_op op, pvjp_dtype dtype, int64_t n);
+/* y (device, 1 element of dtype) = x[0] op ... op x[n-1] (neutral if n == 0).
+ *  MIN/MAX: arg (device int64, required) = lowest index attaining y, -1 if
+ *           n == 0.
+ *  MUL:     p (device, 1 element of dtype, required) = product of the non-zero
+ *           elements, z (device int64, required) = number of zeros (-0.0
+ *           counts); y = p if z == 0 else 0.  The product is formed in FP64.
+ *  ADD:     the sum is formed in FP64.
+ * Deterministic: the same input gives the same bits. */
+pvjp_status pvjp_reduce(pvjp_op op, pvjp_dtype dtype, const void* x, int64_t n, void* y,
+                        int64_t* arg, void* p, int64_t* z, void* ws, size_t ws_bytes,
+                        void* stream);
+/* x_bar (+)= contribution, with y_bar a device scalar of dtype:
+ *  ADD: y_bar everywhere;
+ *  MUL: z == 0: p / x_i * y_bar;  z == 1: p * y_bar at the zero, 0 elsewhere;
+ *       z >= 2: 0  (p, z from pvjp_reduce);
+ *  MIN/MAX: y_bar at arg, 0 elsewhere (with accumulate only x_bar[arg] is
+ *       touched). */
+pvjp_status pvjp_reduce_vjp(pvjp_op op, pvjp_dtype dtype, const void* x, int64_t n,
+                            const int64_t* arg, const void* p, const int64_t* z,
+                            const void* y_bar, void* x_bar, int accumulate, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* reduce_by_index / histogram (Sec. 5.1.2)                                   */
+/* hs = replicate m e; for i: hs[inds[i]] op= vs[i]   (inds outside [0,m)      */
+/* are skipped).                                                              */
+/* ------------------------------------------------------------------------ */
+
+size_t pvjp_hist_ws_bytes(pvjp_op op, pvjp_dtype dtype, int64_t n, int64_t m);
+/* inds [n] int32, vs [n] dtype, 1 <= m <= 2^30, n < 2^31.
+ * hs [m] dtype (required).
+ * winner [m] int32 (MIN/MAX, required): lowest i with inds[i] == k and
+ *        vs[i] == hs[k]; -1 for an empty bin.  hs[k] is vs[winner[k]] bit for
+ *        bit (so a -0.0 extreme keeps its sign).
+ * p [m] dtype and z [m] int32 (MUL, required): product of the non-zero values
+ *        of the bin (formed in FP64) and their zero count; hs = p or 0.
+ * count [m] int32 (nullable, any op): elements per bin.
+ * ADD sums are accumulated in FP64. */
+pvjp_status pvjp_hist(pvjp_op op, pvjp_dtype dtype, const int32_t* inds, const void* vs,
+                      int64_t n, int64_t m, void* hs, int32_t* winner, void* p, int32_t* z,
+                      int32_t* count, void* ws, size_t ws_bytes, void* stream);
+/* vs_bar (+)= contribution of hs_bar [m]:
+ *  ADD: hs_bar[inds[i]] (a gather);
+ *  MIN/MAX: hs_bar[k] at i == winner[k], 0 elsewhere (with accumulate only
+ *       the m winners are touched; without, vs_bar is zero-filled first);
+ *  MUL: per bin, the three cases of reduce(MUL) with y_bar = hs_bar[k];
+ *       needs vs, p and z.
+ *  vs may be NULL for ADD/MIN/MAX; winner is needed for MIN/MAX only. */
+pvjp_status pvjp_hist_vjp(pvjp_op op, pvjp_dtype dtype, const int32_t* inds, const void* vs,
+                          int64_t n, int64_t m, const int32_t* winner, const void* p,
+                          const int32_t* z, const void* hs_bar, void* vs_bar, int accumulate,
+                          void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* scatter (Sec. 5.3)                                                         */
+/* ------------------------------------------------------------------------ */
+
+/* In place on xs [n]: xs_saved[j] = xs[is[j]]; then xs[is[j]] = vs[j], for
+ * j < m.  `is` must hold no duplicates (duplicates race; the result is then
+ * unspecified); entries outside [0,n) are skipped (xs_saved[j] = 0).
+ * xs_saved [m] dtype (nullable if the caller will not restore). */
+pvjp_status pvjp_scatter(pvjp_dtype dtype, void* xs, int64_t n, const int32_t* is,
+                         const void* vs, int64_t m, void* xs_saved, void* stream);
+/* Return sweep, in place on ys_bar [n], fused into one kernel:
+ *  vs_bar[j] (+)= ys_bar[is[j]]    (a gather),
+ *  ys_bar[is[j]] = 0               (ys_bar becomes xs_bar),
+ *  if ys != NULL: ys[is[j]] = xs_saved[j]  (restores xs in place). */
+pvjp_status pvjp_scatter_vjp(pvjp_dtype dtype, void* ys_bar, int64_t n, const int32_t* is,
+                             int64_t m, void* vs_bar, int accumulate, void* ys,
+                             const void* xs_saved, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* map (Sec. 5.4): y_i = f(x_i); the VJP recomputes f's intermediates inside  */
+/* the lambda instead of reading them from memory (Sec. 4.1).                  */
+/* ------------------------------------------------------------------------ */
+
+pvjp_status pvjp_map(pvjp_fn fn, pvjp_dtype dtype, const void* x, int64_t n, void* y,
+                     void* stream);
+/* x_bar (+)= f'(x_i) * y_bar_i. */
+pvjp_status pvjp_map_vjp(pvjp_fn fn, pvjp_dtype dtype, const void* x, const void* y_bar,
+                         int64_t n, void* x_bar, int accumulate, void* stream);
+/* The program of Fig. 1 mapped over n pairs: (y0, y1) = (x1*sin(x0), x0*x1). */
+pvjp_status pvjp_fig1(pvjp_dtype dtype, const void* x0, const void* x1, int64_t n, void* y0,
+                      void* y1, void* stream);
+/* Its adjoint, Fig. 1(c): x0_bar (+)= x1*y1_bar + cos(x0)*x1*y0_bar,
+ * x1_bar (+)= x0*y1_bar + sin(x0)*y0_bar. */
+pvjp_status pvjp_fig1_vjp(pvjp_dtype dtype, const void* x0, const void* x1, const void* y0_bar,
+                          const void* y1_bar, int64_t n, void* x0_bar, void* x1_bar,
+                          int accumulate, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PVJP_H */

@@ -50,7 +50,7 @@ _SIGS = {
 
 def build(force: bool = True) -> str:
     """Compile liboracle.so with gcc (plain C, no fast-math)."""
-    from . import build as _b
+    from . import _build as _b
 
     return _b.build(force=force)
 

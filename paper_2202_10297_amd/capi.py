@@ -1,0 +1,98 @@
+"""ctypes binding of libpvjp.so under the C-ABI names of include/pvjp.h.
+
+Argument marshalling only: every function here forwards plain integers and
+pointers to the library.  Loading fails loudly when the library is missing;
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpvjp.so")
+
+PVJP_OK, PVJP_EINVAL, PVJP_ENOMEM, PVJP_EDEVICE, PVJP_EUNSUPPORTED = 0, 1, 2, 3, 4
+F32, F64 = 0, 1
+ADD, MUL, MIN, MAX = 0, 1, 2, 3
+FN_SQUARE, FN_EXP, FN_LOG, FN_SIN, FN_TANH = 0, 1, 2, 3, 4
+LINREC_CKPT_INTERVAL = 1024
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_L = ctypes.c_int64
+_Z = ctypes.c_size_t
+_S = ctypes.c_char_p
+
+# name -> (restype, argtypes), in header order.
+SIGNATURES = {
+    "pvjp_last_error": (_S, []),
+    "pvjp_version": (_S, []),
+    "pvjp_ws_clear": (_I, [_P, _Z, _P]),
+    "pvjp_ws_check": (_I, [_P, _I, _P]),
+    "pvjp_linrec_ckpt_len": (_L, [_L]),
+    "pvjp_linrec_scan_ws_bytes": (_Z, [_I, _L]),
+    "pvjp_linrec_scan": (_I, [_I, _P, _P, _L, _P, _P, _P, _P, _Z, _P]),
+    "pvjp_linrec_scan_vjp_ws_bytes": (_Z, [_I, _L]),
+    "pvjp_linrec_scan_vjp": (_I, [_I, _P, _P, _P, _P, _L, _P, _P, _P, _I, _P, _Z, _P]),
+    "pvjp_reduce_ws_bytes": (_Z, [_I, _I, _L]),
+    "pvjp_reduce": (_I, [_I, _I, _P, _L, _P, _P, _P, _P, _P, _Z, _P]),
+    "pvjp_reduce_vjp": (_I, [_I, _I, _P, _L, _P, _P, _P, _P, _P, _I, _P]),
+    "pvjp_hist_ws_bytes": (_Z, [_I, _I, _L, _L]),
+    "pvjp_hist": (_I, [_I, _I, _P, _P, _L, _L, _P, _P, _P, _P, _P, _P, _Z, _P]),
+    "pvjp_hist_vjp": (_I, [_I, _I, _P, _P, _L, _L, _P, _P, _P, _P, _P, _I, _P]),
+    "pvjp_scatter": (_I, [_I, _P, _L, _P, _P, _L, _P, _P]),
+    "pvjp_scatter_vjp": (_I, [_I, _P, _L, _P, _L, _P, _I, _P, _P, _P]),
+    "pvjp_map": (_I, [_I, _I, _P, _L, _P, _P]),
+    "pvjp_map_vjp": (_I, [_I, _I, _P, _P, _L, _P, _I, _P]),
+    "pvjp_fig1": (_I, [_I, _P, _P, _L, _P, _P, _P]),
+    "pvjp_fig1_vjp": (_I, [_I, _P, _P, _P, _P, _L, _P, _P, _I, _P]),
+}
+
+_lib = None
+
+
+class PvjpError(RuntimeError):
+    def __init__(self, name, status, msg):
+        super().__init__(f"{name} failed with status {status}: {msg}")
+        self.status = status
+
+
+def lib() -> ctypes.CDLL:
+    """Loads libpvjp.so (built in-tree by paper_2202_10297_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2202_10297_amd.build` "
+                "(there is no fallback implementation)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().pvjp_last_error().decode()
+
+
+def version() -> str:
+    return lib().pvjp_version().decode()
+
+
+def call(name: str, *args):
+    """Calls a status-returning entry point and raises PvjpError on failure."""
+    st = getattr(lib(), name)(*args)
+    if st != PVJP_OK:
+        raise PvjpError(name, st, last_error())
+    return st
+
+
+def __getattr__(name):
+    # capi.pvjp_xxx -> the raw ctypes function of the same name
+    if name in SIGNATURES:
+        return getattr(lib(), name)
+    raise AttributeError(name)

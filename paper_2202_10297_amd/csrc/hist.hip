@@ -1,0 +1,405 @@
+// reduce_by_index (histogram) with the special operators + * min max and
+// their VJPs (Sec. 5.1.2).
+//
+// Forward sweep: the histogram with the extended operators of Sec. 5.1.1:
+//   ADD: sums accumulated in FP64;
+//   MIN/MAX: (value, lowest index) packed into one ordered 64-bit key
+//            (FP32 values: key = order(v) << 32 | ~i, one atomic max per
+//            element); FP64 values take a second pass that picks the lowest
+//            index among the elements equal to the bin's extreme;
+//   MUL: product of the non-zero values (FP64) and a zero count.
+// Each block privatises a sub-histogram in LDS.  When all m bins fit, a bin
+// is its own LDS slot; otherwise the LDS holds a direct-mapped cache of bins
+// (slot = bin mod S) that bins claim on first touch, and an element whose
+// slot belongs to another bin goes straight to a global atomic.  Hot bins
+// (Zipf) are touched early and often, so they end up LDS-resident.  At the
+// end each block merges its slots into the global FP64/u64 accumulators.
+//
+// Return sweep (the update formula of reduce with y_bar := hs_bar[inds[i]]):
+//   ADD: vs_bar[i] += hs_bar[inds[i]]            (a gather);
+//   MIN/MAX: vs_bar[winner[k]] += hs_bar[k]      (m writes; zero-fill first
+//            when not accumulating);
+//   MUL: per bin, the three zero-count cases of reduce(*).
+#include "common.h"
+#include "prims.h"
+
+namespace pvjp {
+
+constexpr int kHistBlock = 256;
+constexpr int kHistLds = 64 * 1024;   // dynamic LDS per block
+constexpr int kCacheSlots = 4096;     // LDS cache slots when the bins do not fit
+constexpr int kHistMaxGrid = 512;     // 2 resident blocks per CU on 256 CUs
+constexpr int32_t kEmptyTag = -1;
+
+__device__ __forceinline__ uint32_t ord32(float v) {
+    const uint32_t b = __float_as_uint(v == 0.0f ? 0.0f : v);  // -0 and +0 tie
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ uint64_t ord64(double v) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v == 0.0 ? 0.0 : v);
+    return (b >> 63) ? ~b : (b | (1ull << 63));
+}
+
+// Key of one element for the accumulator (u64 bits).
+template <int OP>
+__device__ __forceinline__ uint64_t elem_key(float v, int64_t i) {
+    const uint32_t o = (OP == PVJP_MAX) ? ord32(v) : ~ord32(v);
+    return ((uint64_t)o << 32) | (uint64_t)(~(uint32_t)i);
+}
+template <int OP>
+__device__ __forceinline__ uint64_t elem_key(double v, int64_t) {
+    return (OP == PVJP_MAX) ? ord64(v) : ~ord64(v);
+}
+
+template <int OP>
+__device__ __forceinline__ uint64_t acc_identity() {
+    if (OP == PVJP_MUL) return 0x3FF0000000000000ull;  // 1.0
+    return 0ull;                                        // 0.0 for ADD; empty key
+}
+
+__device__ __forceinline__ void mul_f64_atomic(uint64_t* a, double v) {
+    unsigned long long* p = reinterpret_cast<unsigned long long*>(a);
+    unsigned long long old = *p, assumed;
+    do {
+        assumed = old;
+        old = atomicCAS(p, assumed, (unsigned long long)__double_as_longlong(__longlong_as_double(assumed) * v));
+    } while (assumed != old);
+}
+
+// One update of accumulator word `a` (LDS or global) and zero counter `zc`.
+template <class T, int OP>
+__device__ __forceinline__ void acc_update(uint64_t* a, int32_t* zc, T v, int64_t i) {
+    if (OP == PVJP_ADD) {
+        atomicAdd(reinterpret_cast<double*>(a), (double)v);
+    } else if (OP == PVJP_MUL) {
+        if (v == T(0))
+            atomicAdd(zc, 1);
+        else
+            mul_f64_atomic(a, (double)v);
+    } else {
+        atomicMax(reinterpret_cast<unsigned long long*>(a), (unsigned long long)elem_key<OP>(v, i));
+    }
+}
+
+// Merge of a whole slot into the global accumulator.
+template <int OP>
+__device__ __forceinline__ void acc_merge(uint64_t* g, int32_t* gz, uint64_t a, int32_t zc) {
+    if (OP == PVJP_ADD) {
+        atomicAdd(reinterpret_cast<double*>(g), __longlong_as_double((long long)a));
+    } else if (OP == PVJP_MUL) {
+        if (zc) atomicAdd(gz, zc);
+        if (a != acc_identity<OP>()) mul_f64_atomic(g, __longlong_as_double((long long)a));
+    } else {
+        if (a) atomicMax(reinterpret_cast<unsigned long long*>(g), (unsigned long long)a);
+    }
+}
+
+template <class T, int OP, bool CACHE, bool COUNTS>
+__global__ __launch_bounds__(kHistBlock) void hist_acc_kernel(
+    const int32_t* __restrict__ inds, const T* __restrict__ vs, int64_t n, int32_t m, int64_t chunk,
+    int slots, uint64_t* __restrict__ gacc, int32_t* __restrict__ gz, int32_t* __restrict__ gcount) {
+    extern __shared__ uint64_t smem[];
+    uint64_t* sacc = smem;                                       // [slots]
+    int32_t* stag = reinterpret_cast<int32_t*>(sacc + slots);    // [slots] (CACHE)
+    int32_t* scnt = stag + (CACHE ? slots : 0);                  // [slots] (COUNTS)
+    int32_t* szc = scnt + (COUNTS ? slots : 0);                  // [slots] (MUL)
+
+    for (int s = threadIdx.x; s < slots; s += kHistBlock) {
+        sacc[s] = acc_identity<OP>();
+        if (CACHE) stag[s] = kEmptyTag;
+        if (COUNTS) scnt[s] = 0;
+        if (OP == PVJP_MUL) szc[s] = 0;
+    }
+    __syncthreads();
+
+    const int64_t lo = (int64_t)blockIdx.x * chunk;
+    const int64_t hi = (lo + chunk < n) ? lo + chunk : n;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kHistBlock) {
+        const int32_t k = inds[i];
+        if ((uint32_t)k >= (uint32_t)m) continue;
+        const T v = vs[i];
+        int s;
+        bool local;
+        if (!CACHE) {
+            s = k;
+            local = true;
+        } else {
+            s = k & (slots - 1);
+            // A slot's tag goes from empty to a bin once and never changes
+            // again, so a plain read that sees a bin is final.
+            int32_t t = stag[s];
+            if (t == kEmptyTag) {
+                t = atomicCAS(&stag[s], kEmptyTag, k);
+                if (t == kEmptyTag) t = k;
+            }
+            local = (t == k);
+        }
+        if (local) {
+            acc_update<T, OP>(&sacc[s], OP == PVJP_MUL ? &szc[s] : nullptr, v, i);
+            if (COUNTS) atomicAdd(&scnt[s], 1);
+        } else {
+            acc_update<T, OP>(&gacc[k], OP == PVJP_MUL ? &gz[k] : nullptr, v, i);
+            if (COUNTS) atomicAdd(&gcount[k], 1);
+        }
+    }
+    __syncthreads();
+
+    for (int s = threadIdx.x; s < slots; s += kHistBlock) {
+        const int32_t k = CACHE ? stag[s] : s;
+        if (k < 0 || k >= m) continue;
+        acc_merge<OP>(&gacc[k], OP == PVJP_MUL ? &gz[k] : nullptr, sacc[s], OP == PVJP_MUL ? szc[s] : 0);
+        if (COUNTS && scnt[s]) atomicAdd(&gcount[k], scnt[s]);
+    }
+}
+
+// FP64 min/max, second pass: the lowest index whose value equals the bin's
+// extreme (found by the first pass as an ordered key without index).
+template <int OP>
+__global__ __launch_bounds__(256) void hist_f64_winner_kernel(const int32_t* __restrict__ inds,
+                                                              const double* __restrict__ vs, int64_t n,
+                                                              int32_t m, const uint64_t* __restrict__ gacc,
+                                                              int32_t* __restrict__ winner) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t k = inds[i];
+        if ((uint32_t)k >= (uint32_t)m) continue;
+        if (elem_key<OP>(vs[i], i) == gacc[k]) atomicMin(&winner[k], (int32_t)i);
+    }
+}
+
+template <int OP>
+__global__ void hist_init_kernel(uint64_t* __restrict__ gacc, int32_t* __restrict__ gz,
+                                 int32_t* __restrict__ gcount, int32_t* __restrict__ winner, int32_t m) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x) {
+        gacc[k] = acc_identity<OP>();
+        if (gz) gz[k] = 0;
+        if (gcount) gcount[k] = 0;
+        if (winner) winner[k] = 0x7fffffff;
+    }
+}
+
+template <class T, int OP>
+__global__ void hist_final_kernel(const T* __restrict__ vs, const uint64_t* __restrict__ gacc,
+                                  const int32_t* __restrict__ gz, int32_t m, T* __restrict__ hs,
+                                  int32_t* __restrict__ winner, T* __restrict__ p, int32_t* __restrict__ z) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t a = gacc[k];
+        if (OP == PVJP_ADD) {
+            hs[k] = (T)__longlong_as_double((long long)a);
+        } else if (OP == PVJP_MUL) {
+            const double pr = __longlong_as_double((long long)a);
+            const int32_t zz = gz[k];
+            p[k] = (T)pr;
+            z[k] = zz;
+            hs[k] = zz == 0 ? (T)pr : T(0);
+        } else {
+            int32_t w;
+            if (sizeof(T) == 4)
+                w = a ? (int32_t)(~(uint32_t)(a & 0xffffffffull)) : -1;
+            else
+                w = (winner[k] == 0x7fffffff) ? -1 : winner[k];
+            winner[k] = w;
+            hs[k] = (w >= 0) ? vs[w] : (OP == PVJP_MAX ? -(T)__builtin_huge_val() : (T)__builtin_huge_val());
+        }
+    }
+}
+
+// ------------------------------------------------------------ VJP kernels
+template <class T, bool ACC>
+__global__ __launch_bounds__(256) void hist_vjp_add_kernel(const int32_t* __restrict__ inds, int64_t n,
+                                                           int32_t m, const T* __restrict__ hsbar,
+                                                           T* __restrict__ vsbar) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t k = inds[i];
+        const T g = ((uint32_t)k < (uint32_t)m) ? hsbar[k] : T(0);
+        vsbar[i] = ACC ? vsbar[i] + g : g;
+    }
+}
+
+template <class T, bool ACC>
+__global__ __launch_bounds__(256) void hist_vjp_mul_kernel(const int32_t* __restrict__ inds,
+                                                           const T* __restrict__ vs, int64_t n, int32_t m,
+                                                           const T* __restrict__ p, const int32_t* __restrict__ z,
+                                                           const T* __restrict__ hsbar, T* __restrict__ vsbar) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t k = inds[i];
+        T c = T(0);
+        if ((uint32_t)k < (uint32_t)m) {
+            const int32_t zz = z[k];
+            const T v = vs[i];
+            if (zz == 0)
+                c = p[k] / v * hsbar[k];
+            else if (zz == 1 && v == T(0))
+                c = p[k] * hsbar[k];
+        }
+        vsbar[i] = ACC ? vsbar[i] + c : c;
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void fill_zero_kernel(T* __restrict__ x, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = T(0);
+}
+
+template <class T, bool ACC>
+__global__ __launch_bounds__(256) void hist_vjp_winner_kernel(const int32_t* __restrict__ winner, int32_t m,
+                                                              const T* __restrict__ hsbar, T* __restrict__ vsbar) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t w = winner[k];
+        if (w >= 0) vsbar[w] = ACC ? vsbar[w] + hsbar[k] : hsbar[k];
+    }
+}
+
+// ------------------------------------------------------------------ host
+static size_t slot_bytes(int op, bool counts, bool cache) {
+    return 8 + (counts ? 4 : 0) + (op == PVJP_MUL ? 4 : 0) + (cache ? 4 : 0);
+}
+
+static size_t hist_ws(int op, int64_t m) {
+    return align_up((size_t)m * 8, 256) + (op == PVJP_MUL ? align_up((size_t)m * 4, 256) : 0);
+}
+
+template <class T, int OP, bool CACHE, bool COUNTS>
+static void launch_acc(const int32_t* inds, const T* vs, int64_t n, int32_t m, int slots, uint64_t* gacc,
+                       int32_t* gz, int32_t* gcount, hipStream_t st) {
+    int64_t g = ceil_div(n, (int64_t)kHistBlock * 64);
+    if (g < 1) g = 1;
+    if (g > kHistMaxGrid) g = kHistMaxGrid;
+    const int64_t chunk = ceil_div(n, g);
+    const size_t lds = (size_t)slots * slot_bytes(OP, COUNTS, CACHE);
+    hipLaunchKernelGGL((hist_acc_kernel<T, OP, CACHE, COUNTS>), dim3((unsigned)g), dim3(kHistBlock), lds, st,
+                       inds, vs, n, m, chunk, slots, gacc, gz, gcount);
+}
+
+template <class T, int OP>
+static void run_hist(const int32_t* inds, const T* vs, int64_t n, int32_t m, T* hs, int32_t* winner, T* p,
+                     int32_t* z, int32_t* count, void* ws, hipStream_t st) {
+    uint64_t* gacc = reinterpret_cast<uint64_t*>(ws);
+    int32_t* gz = OP == PVJP_MUL ? reinterpret_cast<int32_t*>(reinterpret_cast<char*>(ws) + align_up((size_t)m * 8, 256))
+                                 : nullptr;
+    const bool f64minmax = sizeof(T) == 8 && (OP == PVJP_MIN || OP == PVJP_MAX);
+    const unsigned gm = flat_grid(m, 256, 4);
+    hipLaunchKernelGGL(hist_init_kernel<OP>, dim3(gm), dim3(256), 0, st, gacc, gz, count,
+                       f64minmax ? winner : nullptr, m);
+    const bool counts = count != nullptr;
+    const int full_slots = (int)(kHistLds / slot_bytes(OP, counts, false));
+    if (m <= full_slots) {
+        if (counts)
+            launch_acc<T, OP, false, true>(inds, vs, n, m, m, gacc, gz, count, st);
+        else
+            launch_acc<T, OP, false, false>(inds, vs, n, m, m, gacc, gz, count, st);
+    } else {
+        int slots = kCacheSlots;
+        while ((size_t)slots * slot_bytes(OP, counts, true) > (size_t)kHistLds) slots >>= 1;
+        if (counts)
+            launch_acc<T, OP, true, true>(inds, vs, n, m, slots, gacc, gz, count, st);
+        else
+            launch_acc<T, OP, true, false>(inds, vs, n, m, slots, gacc, gz, count, st);
+    }
+    if (f64minmax)
+        hipLaunchKernelGGL(hist_f64_winner_kernel<OP>, dim3(flat_grid(n, 256, 8)), dim3(256), 0, st, inds,
+                           (const double*)vs, n, m, gacc, winner);
+    hipLaunchKernelGGL((hist_final_kernel<T, OP>), dim3(gm), dim3(256), 0, st, vs, gacc, gz, m, hs, winner, p, z);
+}
+
+template <class T>
+static void dispatch_hist(pvjp_op op, const int32_t* inds, const void* vs, int64_t n, int32_t m, void* hs,
+                          int32_t* winner, void* p, int32_t* z, int32_t* count, void* ws, hipStream_t st) {
+    const T* v = (const T*)vs;
+    switch (op) {
+        case PVJP_ADD: run_hist<T, PVJP_ADD>(inds, v, n, m, (T*)hs, winner, (T*)p, z, count, ws, st); break;
+        case PVJP_MUL: run_hist<T, PVJP_MUL>(inds, v, n, m, (T*)hs, winner, (T*)p, z, count, ws, st); break;
+        case PVJP_MIN: run_hist<T, PVJP_MIN>(inds, v, n, m, (T*)hs, winner, (T*)p, z, count, ws, st); break;
+        default: run_hist<T, PVJP_MAX>(inds, v, n, m, (T*)hs, winner, (T*)p, z, count, ws, st); break;
+    }
+}
+
+template <class T>
+static void dispatch_vjp(pvjp_op op, const int32_t* inds, const void* vs, int64_t n, int32_t m,
+                         const int32_t* winner, const void* p, const int32_t* z, const void* hsbar, void* vsbar,
+                         int acc, hipStream_t st) {
+    const unsigned gn = flat_grid(n, 256, 8), gm = flat_grid(m, 256, 4);
+    const T* hb = (const T*)hsbar;
+    T* vb = (T*)vsbar;
+    if (op == PVJP_ADD) {
+        if (acc)
+            hipLaunchKernelGGL((hist_vjp_add_kernel<T, true>), dim3(gn), dim3(256), 0, st, inds, n, m, hb, vb);
+        else
+            hipLaunchKernelGGL((hist_vjp_add_kernel<T, false>), dim3(gn), dim3(256), 0, st, inds, n, m, hb, vb);
+    } else if (op == PVJP_MUL) {
+        if (acc)
+            hipLaunchKernelGGL((hist_vjp_mul_kernel<T, true>), dim3(gn), dim3(256), 0, st, inds, (const T*)vs, n, m,
+                               (const T*)p, z, hb, vb);
+        else
+            hipLaunchKernelGGL((hist_vjp_mul_kernel<T, false>), dim3(gn), dim3(256), 0, st, inds, (const T*)vs, n, m,
+                               (const T*)p, z, hb, vb);
+    } else {
+        if (acc) {
+            hipLaunchKernelGGL((hist_vjp_winner_kernel<T, true>), dim3(gm), dim3(256), 0, st, winner, m, hb, vb);
+        } else {
+            hipLaunchKernelGGL(fill_zero_kernel<T>, dim3(gn), dim3(256), 0, st, vb, n);
+            hipLaunchKernelGGL((hist_vjp_winner_kernel<T, false>), dim3(gm), dim3(256), 0, st, winner, m, hb, vb);
+        }
+    }
+}
+
+}  // namespace pvjp
+
+using namespace pvjp;
+
+static constexpr int64_t kMaxBins = (int64_t)1 << 30;
+
+extern "C" size_t pvjp_hist_ws_bytes(pvjp_op op, pvjp_dtype dtype, int64_t n, int64_t m) {
+    if (!valid_op(op) || !valid_dtype(dtype) || n < 0 || m < 1 || m > kMaxBins) return 0;
+    return hist_ws(op, m);
+}
+
+extern "C" pvjp_status pvjp_hist(pvjp_op op, pvjp_dtype dtype, const int32_t* inds, const void* vs, int64_t n,
+                                 int64_t m, void* hs, int32_t* winner, void* p, int32_t* z, int32_t* count,
+                                 void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    PVJP_REQUIRE(valid_op(op), "pvjp_hist: unknown op %d", (int)op);
+    PVJP_REQUIRE(valid_dtype(dtype), "pvjp_hist: unknown dtype %d", (int)dtype);
+    PVJP_REQUIRE(n >= 0 && n <= INT32_MAX, "pvjp_hist: n = %lld out of range [0, 2^31)", (long long)n);
+    PVJP_REQUIRE(m >= 1 && m <= kMaxBins, "pvjp_hist: m = %lld out of range [1, 2^30]", (long long)m);
+    PVJP_REQUIRE(hs != nullptr, "pvjp_hist: hs is NULL");
+    PVJP_REQUIRE(n == 0 || (inds != nullptr && vs != nullptr), "pvjp_hist: inds and vs must be non-NULL");
+    PVJP_REQUIRE(!(op == PVJP_MIN || op == PVJP_MAX) || winner != nullptr, "pvjp_hist: MIN/MAX need winner");
+    PVJP_REQUIRE(op != PVJP_MUL || (p != nullptr && z != nullptr), "pvjp_hist: MUL needs p and z");
+    PVJP_REQUIRE(ws != nullptr && aligned(ws, 256), "pvjp_hist: ws must be non-NULL and 256-byte aligned");
+    const size_t need = pvjp_hist_ws_bytes(op, dtype, n, m);
+    if (ws_bytes < need) {
+        set_error("pvjp_hist: workspace has %zu bytes, needs %zu", ws_bytes, need);
+        return PVJP_ENOMEM;
+    }
+    if (dtype == PVJP_F64)
+        dispatch_hist<double>(op, inds, vs, n, (int32_t)m, hs, winner, p, z, count, ws, as_stream(stream));
+    else
+        dispatch_hist<float>(op, inds, vs, n, (int32_t)m, hs, winner, p, z, count, ws, as_stream(stream));
+    PVJP_LAUNCHED("pvjp_hist");
+    return PVJP_OK;
+}
+
+extern "C" pvjp_status pvjp_hist_vjp(pvjp_op op, pvjp_dtype dtype, const int32_t* inds, const void* vs, int64_t n,
+                                     int64_t m, const int32_t* winner, const void* p, const int32_t* z,
+                                     const void* hs_bar, void* vs_bar, int accumulate, void* stream) {
+    clear_error();
+    PVJP_REQUIRE(valid_op(op), "pvjp_hist_vjp: unknown op %d", (int)op);
+    PVJP_REQUIRE(valid_dtype(dtype), "pvjp_hist_vjp: unknown dtype %d", (int)dtype);
+    PVJP_REQUIRE(n >= 0 && n <= INT32_MAX, "pvjp_hist_vjp: n = %lld out of range [0, 2^31)", (long long)n);
+    PVJP_REQUIRE(m >= 1 && m <= kMaxBins, "pvjp_hist_vjp: m = %lld out of range [1, 2^30]", (long long)m);
+    if (n == 0) return PVJP_OK;
+    PVJP_REQUIRE(hs_bar != nullptr && vs_bar != nullptr, "pvjp_hist_vjp: hs_bar and vs_bar must be non-NULL");
+    PVJP_REQUIRE(op == PVJP_MIN || op == PVJP_MAX || inds != nullptr, "pvjp_hist_vjp: inds is NULL");
+    PVJP_REQUIRE(!(op == PVJP_MIN || op == PVJP_MAX) || winner != nullptr, "pvjp_hist_vjp: MIN/MAX need winner");
+    PVJP_REQUIRE(op != PVJP_MUL || (vs != nullptr && p != nullptr && z != nullptr),
+                 "pvjp_hist_vjp: MUL needs vs, p and z");
+    if (dtype == PVJP_F64)
+        dispatch_vjp<double>(op, inds, vs, n, (int32_t)m, winner, p, z, hs_bar, vs_bar, accumulate,
+                             as_stream(stream));
+    else
+        dispatch_vjp<float>(op, inds, vs, n, (int32_t)m, winner, p, z, hs_bar, vs_bar, accumulate,
+                            as_stream(stream));
+    PVJP_LAUNCHED("pvjp_hist_vjp");
+    return PVJP_OK;
+}

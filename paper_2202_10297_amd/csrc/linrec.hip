@@ -1,0 +1,363 @@
+// Inclusive scan of the first-order linear recurrence and its VJP (Sec. 5.2).
+//
+// Primal: single-pass decoupled-lookback scan with the operator
+//   (a1,b1) (+) (a2,b2) = (a2*a1, a2*b1 + b2).
+// It optionally writes a checkpoint (the exclusive prefix) every
+// PVJP_LINREC_CKPT_INTERVAL elements; this is the only primal state the VJP
+// keeps.
+//
+// VJP: the return sweep of Sec. 5.2 in one kernel per tile, tiles taken in
+// reverse virtual order:
+//   1. recompute the primal prefixes (A_{i-1}, B_{i-1}) of the tile from its
+//      checkpoint (redundant execution of the forward sweep, Sec. 4.1);
+//   2. map c_i = a_{i+1} (the left Jacobian of the operator is a_{i+1} * I),
+//      d_i = y_bar_i;
+//   3. reversed scan with lin_o over (c, d) -- tile aggregate, lookback over
+//      the tiles to the right, local apply -- giving
+//      r_bar_i = y_bar_i + a_{i+1} r_bar_{i+1};
+//   4. map a_bar_i = A_{i-1} rA_bar_i + B_{i-1} rB_bar_i, b_bar_i = rB_bar_i
+//      (the transposed right Jacobian [[A_{i-1}, 0], [B_{i-1}, 1]]).
+#include "common.h"
+#include "prims.h"
+
+namespace pvjp {
+
+constexpr int kCk = PVJP_LINREC_CKPT_INTERVAL;
+constexpr int kScanBlock = 256;
+
+template <class T>
+struct ScanCfg;
+template <>
+struct ScanCfg<double> {
+    static constexpr int IPT = 8;  // 2048-element tiles
+};
+template <>
+struct ScanCfg<float> {
+    static constexpr int IPT = 16;  // 4096-element tiles
+};
+
+template <class T>
+constexpr int scan_tile() {
+    return kScanBlock * ScanCfg<T>::IPT;
+}
+
+static_assert(scan_tile<double>() % kCk == 0 && scan_tile<float>() % kCk == 0,
+              "scan tiles must be whole checkpoint intervals");
+
+template <class T>
+__global__ __launch_bounds__(kScanBlock) void linrec_fwd_kernel(
+    const T* __restrict__ a, const T* __restrict__ b, int64_t n, T* __restrict__ A,
+    T* __restrict__ B, T* __restrict__ ckpt, LookbackHdr* hdr,
+    TileState<typename LinRec<T>::S>* states, int64_t ntiles) {
+    using Op = LinRec<T>;
+    using S = typename Op::S;
+    constexpr int IPT = ScanCfg<T>::IPT;
+    constexpr int TS = kScanBlock * IPT;
+    __shared__ T lds[lds_elems<T, TS>()];
+    __shared__ S wtot[kScanBlock / kWave];
+    __shared__ uint32_t s_tag, s_ticket;
+    __shared__ S s_prefix;
+
+    if (threadIdx.x == 0) {
+        lookback_begin(hdr, s_tag, s_ticket);
+        if (s_ticket >= ntiles) lookback_error(hdr, kErrTicket);
+    }
+    __syncthreads();
+    const uint32_t tag = s_tag;
+    if (s_ticket >= ntiles) {  // the workspace was not zero-filled: do nothing
+        lookback_end(hdr, tag);
+        return;
+    }
+    const int64_t tile = s_ticket;
+    const int64_t base = tile * TS;
+    const int cnt = (int)((n - base) < TS ? (n - base) : TS);
+
+    T ra[IPT], rb[IPT];
+    load_blocked<T, kScanBlock, IPT>(a + base, cnt, ra, lds, T(1));
+    __syncthreads();
+    load_blocked<T, kScanBlock, IPT>(b + base, cnt, rb, lds, T(0));
+
+    S agg = S{ra[0], rb[0]};
+#pragma unroll
+    for (int j = 1; j < IPT; ++j) agg = Op::comb(agg, S{ra[j], rb[j]});
+    S total;
+    S excl = block_exclusive_scan<Op, kScanBlock, false>(agg, total, wtot);
+
+    if (threadIdx.x < kWave) {
+        S prefix = Op::id();
+        if (tile == 0) {
+            if (threadIdx.x == 0) publish(&states[tile], total, kInc, tag);
+        } else {
+            if (threadIdx.x == 0) publish(&states[tile], total, kAgg, tag);
+            prefix = lookback<Op, false>(states, tile, ntiles, tag, hdr);
+            if (threadIdx.x == 0) publish(&states[tile], Op::comb(prefix, total), kInc, tag);
+        }
+        if (threadIdx.x == 0) s_prefix = prefix;
+    }
+    __syncthreads();
+
+    S run = Op::comb(s_prefix, excl);
+    const int first = (int)threadIdx.x * IPT;
+    if (ckpt != nullptr && (first % kCk) == 0 && first < cnt) {
+        const int64_t c = (base + first) / kCk;
+        ckpt[2 * c] = run.a;
+        ckpt[2 * c + 1] = run.b;
+    }
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        run = Op::comb(run, S{ra[j], rb[j]});
+        ra[j] = run.a;
+        rb[j] = run.b;
+    }
+    if (A != nullptr) {
+        store_blocked<T, kScanBlock, IPT, false>(A + base, cnt, ra, lds);
+        store_blocked<T, kScanBlock, IPT, false>(B + base, cnt, rb, lds);
+    }
+    lookback_end(hdr, tag);
+}
+
+template <class T, bool ACC>
+__global__ __launch_bounds__(kScanBlock) void linrec_vjp_kernel(
+    const T* __restrict__ a, const T* __restrict__ b, const T* __restrict__ ya,
+    const T* __restrict__ yb, int64_t n, const T* __restrict__ ckpt, T* __restrict__ abar,
+    T* __restrict__ bbar, LookbackHdr* hdr, TileState<typename LinO<T>::S>* states,
+    int64_t ntiles) {
+    using P = LinRec<T>;
+    using L = LinO<T>;
+    using PS = typename P::S;
+    using LS = typename L::S;
+    constexpr int IPT = ScanCfg<T>::IPT;
+    constexpr int TS = kScanBlock * IPT;
+    __shared__ T lds[lds_elems<T, TS>()];
+    __shared__ PS wtot_p[kScanBlock / kWave];
+    __shared__ LS wtot_l[kScanBlock / kWave];
+    __shared__ uint32_t s_tag, s_ticket;
+    __shared__ LS s_suffix;
+
+    if (threadIdx.x == 0) {
+        lookback_begin(hdr, s_tag, s_ticket);
+        if (s_ticket >= ntiles) lookback_error(hdr, kErrTicket);
+    }
+    __syncthreads();
+    const uint32_t tag = s_tag;
+    if (s_ticket >= ntiles) {  // the workspace was not zero-filled: do nothing
+        lookback_end(hdr, tag);
+        return;
+    }
+    const int64_t tile = ntiles - 1 - (int64_t)s_ticket;  // reverse virtual order
+    const int64_t base = tile * TS;
+    const int cnt = (int)((n - base) < TS ? (n - base) : TS);
+    const int first = (int)threadIdx.x * IPT;
+
+    // --- loads (a with its one-element look-ahead for c_i = a_{i+1})
+    T ra[IPT], rc[IPT];
+    load_blocked<T, kScanBlock, IPT>(a + base, cnt, ra, lds, T(1));
+    {
+        T nxt;
+        if ((int)threadIdx.x < kScanBlock - 1)
+            nxt = lds[lds_pad<T>(first + IPT)];
+        else
+            nxt = (base + TS < n) ? a[base + TS] : T(1);
+#pragma unroll
+        for (int j = 0; j < IPT - 1; ++j) rc[j] = ra[j + 1];
+        rc[IPT - 1] = nxt;
+    }
+    T rb[IPT], rya[IPT], ryb[IPT];
+    __syncthreads();
+    load_blocked<T, kScanBlock, IPT>(b + base, cnt, rb, lds, T(0));
+    __syncthreads();
+    load_blocked<T, kScanBlock, IPT>(ya + base, cnt, rya, lds, T(0));
+    __syncthreads();
+    load_blocked<T, kScanBlock, IPT>(yb + base, cnt, ryb, lds, T(0));
+
+    // --- 1. recompute primal prefixes from the tile's checkpoint
+    T pA[IPT], pB[IPT];
+    {
+        PS agg = PS{ra[0], rb[0]};
+#pragma unroll
+        for (int j = 1; j < IPT; ++j) agg = P::comb(agg, PS{ra[j], rb[j]});
+        PS total;
+        PS excl = block_exclusive_scan<P, kScanBlock, false>(agg, total, wtot_p);
+        const int64_t c = base / kCk;
+        PS run = P::comb(PS{ckpt[2 * c], ckpt[2 * c + 1]}, excl);
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            pA[j] = run.a;  // (A_{i-1}, B_{i-1})
+            pB[j] = run.b;
+            run = P::comb(run, PS{ra[j], rb[j]});
+        }
+    }
+
+    // --- 2. map: lin_o elements (c_i, y_bar_i); the last element of the array
+    //        has no successor, and padding elements are the neutral element.
+    LS e[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const int64_t gi = base + first + j;
+        T c = rc[j];
+        if (gi == n - 1) c = T(0);
+        e[j] = LS{c, rya[j], ryb[j]};
+    }
+
+    // --- 3. reversed scan (scan order = decreasing index)
+    LS agg = L::id();
+#pragma unroll
+    for (int j = IPT - 1; j >= 0; --j) agg = L::comb(agg, e[j]);
+    LS total;
+    LS excl = block_exclusive_scan<L, kScanBlock, true>(agg, total, wtot_l);
+    if (threadIdx.x < kWave) {
+        LS suffix = L::id();
+        if (tile == ntiles - 1) {
+            if (threadIdx.x == 0) publish(&states[tile], total, kInc, tag);
+        } else {
+            if (threadIdx.x == 0) publish(&states[tile], total, kAgg, tag);
+            suffix = lookback<L, true>(states, tile, ntiles, tag, hdr);
+            if (threadIdx.x == 0) publish(&states[tile], L::comb(suffix, total), kInc, tag);
+        }
+        if (threadIdx.x == 0) s_suffix = suffix;
+    }
+    __syncthreads();
+
+    // --- 4. map: input adjoints
+    LS run = L::comb(s_suffix, excl);
+#pragma unroll
+    for (int j = IPT - 1; j >= 0; --j) {
+        run = L::comb(run, e[j]);
+        ra[j] = pA[j] * run.dA + pB[j] * run.dB;
+        rb[j] = run.dB;
+    }
+    store_blocked<T, kScanBlock, IPT, ACC>(abar + base, cnt, ra, lds);
+    store_blocked<T, kScanBlock, IPT, ACC>(bbar + base, cnt, rb, lds);
+    lookback_end(hdr, tag);
+}
+
+// ------------------------------------------------------------------ host
+template <class S>
+static size_t lookback_bytes(int64_t ntiles) {
+    return sizeof(LookbackHdr) + (size_t)ntiles * sizeof(TileState<S>);
+}
+
+template <class T>
+static size_t fwd_ws(int64_t n) {
+    return lookback_bytes<typename LinRec<T>::S>(ceil_div(n, scan_tile<T>()));
+}
+
+// Workspace layout of both entry points: [header | tile states | ckpt].  The
+// checkpoint-only pre-pass of the VJP and the VJP itself run one after the
+// other on the same header and tile states (tile states are 64 bytes for both
+// operators and both use the same tile size), so every launch on a workspace
+// takes its tag from the one epoch sequence.
+template <class T>
+static size_t vjp_ws(int64_t n) {
+    const int64_t nt = ceil_div(n, scan_tile<T>());
+    return align_up(lookback_bytes<typename LinO<T>::S>(nt), 256) +
+           align_up((size_t)(2 * ceil_div(n, kCk)) * sizeof(T), 256);
+}
+static_assert(sizeof(TileState<LinRec<double>::S>) == sizeof(TileState<LinO<double>::S>) &&
+                  sizeof(TileState<LinRec<float>::S>) == sizeof(TileState<LinO<float>::S>),
+              "primal and adjoint tile states share one workspace region");
+
+template <class T>
+static pvjp_status launch_fwd(const void* a, const void* b, int64_t n, void* A, void* B,
+                              void* ckpt, void* ws, hipStream_t st) {
+    using S = typename LinRec<T>::S;
+    const int64_t nt = ceil_div(n, scan_tile<T>());
+    auto* hdr = reinterpret_cast<LookbackHdr*>(ws);
+    auto* states = reinterpret_cast<TileState<S>*>(reinterpret_cast<char*>(ws) + sizeof(LookbackHdr));
+    hipLaunchKernelGGL(linrec_fwd_kernel<T>, dim3((unsigned)nt), dim3(kScanBlock), 0, st,
+                       (const T*)a, (const T*)b, n, (T*)A, (T*)B, (T*)ckpt, hdr, states, nt);
+    PVJP_LAUNCHED("pvjp_linrec_scan");
+    return PVJP_OK;
+}
+
+template <class T>
+static pvjp_status launch_vjp(const void* a, const void* b, const void* ya, const void* yb,
+                              int64_t n, const void* ckpt, void* abar, void* bbar, int acc,
+                              void* ws, hipStream_t st) {
+    using LS = typename LinO<T>::S;
+    const int64_t nt = ceil_div(n, scan_tile<T>());
+    char* w = reinterpret_cast<char*>(ws);
+    auto* hdr = reinterpret_cast<LookbackHdr*>(w);
+    auto* states = reinterpret_cast<TileState<LS>*>(w + sizeof(LookbackHdr));
+    if (ckpt == nullptr) {  // checkpoint-only primal pass into the workspace
+        T* ck = reinterpret_cast<T*>(w + align_up(lookback_bytes<LS>(nt), 256));
+        pvjp_status s = launch_fwd<T>(a, b, n, nullptr, nullptr, ck, ws, st);
+        if (s != PVJP_OK) return s;
+        ckpt = ck;
+    }
+    if (acc)
+        hipLaunchKernelGGL((linrec_vjp_kernel<T, true>), dim3((unsigned)nt), dim3(kScanBlock), 0, st,
+                           (const T*)a, (const T*)b, (const T*)ya, (const T*)yb, n, (const T*)ckpt,
+                           (T*)abar, (T*)bbar, hdr, states, nt);
+    else
+        hipLaunchKernelGGL((linrec_vjp_kernel<T, false>), dim3((unsigned)nt), dim3(kScanBlock), 0, st,
+                           (const T*)a, (const T*)b, (const T*)ya, (const T*)yb, n, (const T*)ckpt,
+                           (T*)abar, (T*)bbar, hdr, states, nt);
+    PVJP_LAUNCHED("pvjp_linrec_scan_vjp");
+    return PVJP_OK;
+}
+
+}  // namespace pvjp
+
+using namespace pvjp;
+
+// Tile counts are carried in 32-bit tickets.
+static constexpr int64_t kMaxScanN = (int64_t)1 << 40;
+
+extern "C" int64_t pvjp_linrec_ckpt_len(int64_t n) { return n <= 0 ? 0 : ceil_div(n, kCk); }
+
+extern "C" size_t pvjp_linrec_scan_ws_bytes(pvjp_dtype dtype, int64_t n) {
+    if (n <= 0 || !valid_dtype(dtype)) return 0;
+    return dtype == PVJP_F64 ? fwd_ws<double>(n) : fwd_ws<float>(n);
+}
+
+extern "C" size_t pvjp_linrec_scan_vjp_ws_bytes(pvjp_dtype dtype, int64_t n) {
+    if (n <= 0 || !valid_dtype(dtype)) return 0;
+    return dtype == PVJP_F64 ? vjp_ws<double>(n) : vjp_ws<float>(n);
+}
+
+extern "C" pvjp_status pvjp_linrec_scan(pvjp_dtype dtype, const void* a, const void* b, int64_t n,
+                                        void* A, void* B, void* ckpt, void* ws, size_t ws_bytes,
+                                        void* stream) {
+    clear_error();
+    PVJP_REQUIRE(valid_dtype(dtype), "pvjp_linrec_scan: unknown dtype %d", (int)dtype);
+    PVJP_REQUIRE(n >= 0 && n <= kMaxScanN, "pvjp_linrec_scan: n = %lld out of range", (long long)n);
+    if (n == 0) return PVJP_OK;
+    PVJP_REQUIRE(a && b, "pvjp_linrec_scan: a and b must be non-NULL");
+    PVJP_REQUIRE((A == nullptr) == (B == nullptr), "pvjp_linrec_scan: A and B must both be given or both NULL");
+    PVJP_REQUIRE(A || ckpt, "pvjp_linrec_scan: nothing to compute (A, B and ckpt all NULL)");
+    PVJP_REQUIRE(ws != nullptr, "pvjp_linrec_scan: ws is NULL");
+    const size_t need = pvjp_linrec_scan_ws_bytes(dtype, n);
+    if (ws_bytes < need) {
+        set_error("pvjp_linrec_scan: workspace has %zu bytes, needs %zu", ws_bytes, need);
+        return PVJP_ENOMEM;
+    }
+    PVJP_REQUIRE(aligned(ws, 256), "pvjp_linrec_scan: ws must be 256-byte aligned");
+    return dtype == PVJP_F64 ? launch_fwd<double>(a, b, n, A, B, ckpt, ws, as_stream(stream))
+                             : launch_fwd<float>(a, b, n, A, B, ckpt, ws, as_stream(stream));
+}
+
+extern "C" pvjp_status pvjp_linrec_scan_vjp(pvjp_dtype dtype, const void* a, const void* b,
+                                            const void* yA_bar, const void* yB_bar, int64_t n,
+                                            const void* ckpt, void* a_bar, void* b_bar,
+                                            int accumulate, void* ws, size_t ws_bytes,
+                                            void* stream) {
+    clear_error();
+    PVJP_REQUIRE(valid_dtype(dtype), "pvjp_linrec_scan_vjp: unknown dtype %d", (int)dtype);
+    PVJP_REQUIRE(n >= 0 && n <= kMaxScanN, "pvjp_linrec_scan_vjp: n = %lld out of range", (long long)n);
+    if (n == 0) return PVJP_OK;
+    PVJP_REQUIRE(a && b && yA_bar && yB_bar && a_bar && b_bar,
+                 "pvjp_linrec_scan_vjp: a, b, yA_bar, yB_bar, a_bar, b_bar must be non-NULL");
+    PVJP_REQUIRE(ws != nullptr, "pvjp_linrec_scan_vjp: ws is NULL");
+    const size_t need = pvjp_linrec_scan_vjp_ws_bytes(dtype, n);
+    if (ws_bytes < need) {
+        set_error("pvjp_linrec_scan_vjp: workspace has %zu bytes, needs %zu", ws_bytes, need);
+        return PVJP_ENOMEM;
+    }
+    PVJP_REQUIRE(aligned(ws, 256), "pvjp_linrec_scan_vjp: ws must be 256-byte aligned");
+    return dtype == PVJP_F64
+               ? launch_vjp<double>(a, b, yA_bar, yB_bar, n, ckpt, a_bar, b_bar, accumulate, ws,
+                                    as_stream(stream))
+               : launch_vjp<float>(a, b, yA_bar, yB_bar, n, ckpt, a_bar, b_bar, accumulate, ws,
+                                   as_stream(stream));
+}

@@ -1,0 +1,218 @@
+"""Torch-tensor front end of libpvjp.so.
+
+Torch provides device memory and the current HIP stream; every step of every
+operator runs in the library's kernels (called through ``capi``).  Outputs and
+workspaces are allocated here with torch, then raw pointers are passed on.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import capi
+
+_DT = {torch.float32: capi.F32, torch.float64: capi.F64}
+_OPS = {"add": capi.ADD, "mul": capi.MUL, "min": capi.MIN, "max": capi.MAX}
+_FNS = {"square": capi.FN_SQUARE, "exp": capi.FN_EXP, "log": capi.FN_LOG, "sin": capi.FN_SIN,
+        "tanh": capi.FN_TANH}
+
+
+def _dt(t: torch.Tensor) -> int:
+    try:
+        return _DT[t.dtype]
+    except KeyError:
+        raise TypeError(f"unsupported dtype {t.dtype}; expected float32 or float64") from None
+
+
+def _op(op) -> int:
+    return _OPS[op] if isinstance(op, str) else int(op)
+
+
+def _fn(fn) -> int:
+    return _FNS[fn] if isinstance(fn, str) else int(fn)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("pvjp operates on device tensors only")
+    if not t.is_contiguous():
+        raise ValueError("pvjp expects contiguous tensors")
+    return t.data_ptr() or None
+
+
+def _stream(device=None):
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Workspaces:
+    """Zero-initialised device workspaces, cached per (device, stream, key).
+
+    The library leaves a workspace ready for reuse after every call; calls on
+    one stream are ordered, so one workspace per stream and purpose is safe."""
+
+    def __init__(self):
+        self._bufs = {}
+
+    def get(self, key, nbytes: int, device) -> torch.Tensor:
+        dev = torch.device(device)
+        k = (dev.index, _stream(dev), key)
+        buf = self._bufs.get(k)
+        if buf is None or buf.numel() < nbytes:
+            buf = torch.zeros(max(nbytes, 256) + 256, dtype=torch.uint8, device=dev)
+            off = (-buf.data_ptr()) % 256
+            buf = buf[off:off + max(nbytes, 256)]
+            self._bufs[k] = buf
+        return buf
+
+    def clear(self):
+        self._bufs.clear()
+
+
+WS = Workspaces()
+
+
+# ------------------------------------------------------------ linrec scan
+def linrec_scan(a: torch.Tensor, b: torch.Tensor, ckpt: bool = True):
+    """Inclusive scan of (a, b) under (a1,b1)(+)(a2,b2) = (a2 a1, a2 b1 + b2).
+    Returns (A, B, ckpt or None)."""
+    n = a.numel()
+    dt = _dt(a)
+    A, B = torch.empty_like(a), torch.empty_like(b)
+    ck = torch.empty(2 * capi.lib().pvjp_linrec_ckpt_len(n), dtype=a.dtype, device=a.device) if ckpt else None
+    nb = capi.lib().pvjp_linrec_scan_ws_bytes(dt, n)
+    ws = WS.get("linrec_fwd", nb, a.device)
+    capi.call("pvjp_linrec_scan", dt, _ptr(a), _ptr(b), n, _ptr(A), _ptr(B), _ptr(ck), _ptr(ws), ws.numel(),
+              _stream(a.device))
+    return A, B, ck
+
+
+def linrec_scan_vjp(a, b, yA_bar, yB_bar, ckpt=None, a_bar=None, b_bar=None, accumulate=False):
+    n = a.numel()
+    dt = _dt(a)
+    if a_bar is None:
+        a_bar = torch.zeros_like(a) if accumulate else torch.empty_like(a)
+    if b_bar is None:
+        b_bar = torch.zeros_like(b) if accumulate else torch.empty_like(b)
+    nb = capi.lib().pvjp_linrec_scan_vjp_ws_bytes(dt, n)
+    ws = WS.get("linrec_vjp", nb, a.device)
+    capi.call("pvjp_linrec_scan_vjp", dt, _ptr(a), _ptr(b), _ptr(yA_bar), _ptr(yB_bar), n, _ptr(ckpt),
+              _ptr(a_bar), _ptr(b_bar), int(accumulate), _ptr(ws), ws.numel(), _stream(a.device))
+    return a_bar, b_bar
+
+
+# ----------------------------------------------------------------- reduce
+def reduce(op, x: torch.Tensor):
+    """Returns (y, aux) with aux = {"arg"} for min/max, {"p", "z"} for mul."""
+    o, dt, n = _op(op), _dt(x), x.numel()
+    dev = x.device
+    y = torch.empty(1, dtype=x.dtype, device=dev)
+    aux = {}
+    arg = p = z = None
+    if o in (capi.MIN, capi.MAX):
+        arg = aux["arg"] = torch.empty(1, dtype=torch.int64, device=dev)
+    if o == capi.MUL:
+        p = aux["p"] = torch.empty(1, dtype=x.dtype, device=dev)
+        z = aux["z"] = torch.empty(1, dtype=torch.int64, device=dev)
+    nb = capi.lib().pvjp_reduce_ws_bytes(o, dt, n)
+    ws = WS.get("reduce", nb, dev)
+    capi.call("pvjp_reduce", o, dt, _ptr(x), n, _ptr(y), _ptr(arg), _ptr(p), _ptr(z), _ptr(ws), ws.numel(),
+              _stream(dev))
+    return y, aux
+
+
+def reduce_vjp(op, x, aux, y_bar, x_bar=None, accumulate=False):
+    o, dt, n = _op(op), _dt(x), x.numel()
+    if x_bar is None:
+        x_bar = torch.zeros_like(x) if accumulate else torch.empty_like(x)
+    capi.call("pvjp_reduce_vjp", o, dt, _ptr(x), n, _ptr(aux.get("arg")), _ptr(aux.get("p")), _ptr(aux.get("z")),
+              _ptr(y_bar), _ptr(x_bar), int(accumulate), _stream(x.device))
+    return x_bar
+
+
+# ---------------------------------------------------------- reduce_by_index
+def hist(op, inds: torch.Tensor, vs: torch.Tensor, m: int, counts: bool = False):
+    """Returns (hs, aux): aux has "winner" (min/max), "p" and "z" (mul),
+    "count" (if counts)."""
+    o, dt, n = _op(op), _dt(vs), vs.numel()
+    dev = vs.device
+    if inds.dtype != torch.int32:
+        raise TypeError("inds must be int32")
+    hs = torch.empty(m, dtype=vs.dtype, device=dev)
+    aux = {}
+    winner = p = z = count = None
+    if o in (capi.MIN, capi.MAX):
+        winner = aux["winner"] = torch.empty(m, dtype=torch.int32, device=dev)
+    if o == capi.MUL:
+        p = aux["p"] = torch.empty(m, dtype=vs.dtype, device=dev)
+        z = aux["z"] = torch.empty(m, dtype=torch.int32, device=dev)
+    if counts:
+        count = aux["count"] = torch.empty(m, dtype=torch.int32, device=dev)
+    nb = capi.lib().pvjp_hist_ws_bytes(o, dt, n, m)
+    ws = WS.get("hist", nb, dev)
+    capi.call("pvjp_hist", o, dt, _ptr(inds), _ptr(vs), n, m, _ptr(hs), _ptr(winner), _ptr(p), _ptr(z),
+              _ptr(count), _ptr(ws), ws.numel(), _stream(dev))
+    return hs, aux
+
+
+def hist_vjp(op, inds, vs, m, aux, hs_bar, vs_bar=None, accumulate=False, n=None):
+    o = _op(op)
+    dt = _dt(hs_bar)
+    n = inds.numel() if n is None else n
+    if vs_bar is None:
+        shape = (n,)
+        vs_bar = (torch.zeros if accumulate else torch.empty)(shape, dtype=hs_bar.dtype, device=hs_bar.device)
+    capi.call("pvjp_hist_vjp", o, dt, _ptr(inds), _ptr(vs), n, m, _ptr(aux.get("winner")), _ptr(aux.get("p")),
+              _ptr(aux.get("z")), _ptr(hs_bar), _ptr(vs_bar), int(accumulate), _stream(hs_bar.device))
+    return vs_bar
+
+
+# ----------------------------------------------------------------- scatter
+def scatter_(xs: torch.Tensor, is_: torch.Tensor, vs: torch.Tensor, save: bool = True):
+    """In place on xs; returns xs_saved (or None)."""
+    dt = _dt(xs)
+    saved = torch.empty(is_.numel(), dtype=xs.dtype, device=xs.device) if save else None
+    capi.call("pvjp_scatter", dt, _ptr(xs), xs.numel(), _ptr(is_), _ptr(vs), is_.numel(), _ptr(saved),
+              _stream(xs.device))
+    return saved
+
+
+def scatter_vjp_(ys_bar, is_, vs_bar=None, accumulate=False, ys=None, xs_saved=None):
+    """In place on ys_bar (which becomes xs_bar); optionally restores ys."""
+    dt = _dt(ys_bar)
+    if vs_bar is None:
+        vs_bar = (torch.zeros if accumulate else torch.empty)(is_.numel(), dtype=ys_bar.dtype, device=ys_bar.device)
+    capi.call("pvjp_scatter_vjp", dt, _ptr(ys_bar), ys_bar.numel(), _ptr(is_), is_.numel(), _ptr(vs_bar),
+              int(accumulate), _ptr(ys), _ptr(xs_saved), _stream(ys_bar.device))
+    return vs_bar
+
+
+# --------------------------------------------------------------------- map
+def map_(fn, x):
+    y = torch.empty_like(x)
+    capi.call("pvjp_map", _fn(fn), _dt(x), _ptr(x), x.numel(), _ptr(y), _stream(x.device))
+    return y
+
+
+def map_vjp(fn, x, y_bar, x_bar=None, accumulate=False):
+    if x_bar is None:
+        x_bar = torch.zeros_like(x) if accumulate else torch.empty_like(x)
+    capi.call("pvjp_map_vjp", _fn(fn), _dt(x), _ptr(x), _ptr(y_bar), x.numel(), _ptr(x_bar), int(accumulate),
+              _stream(x.device))
+    return x_bar
+
+
+def fig1(x0, x1):
+    y0, y1 = torch.empty_like(x0), torch.empty_like(x0)
+    capi.call("pvjp_fig1", _dt(x0), _ptr(x0), _ptr(x1), x0.numel(), _ptr(y0), _ptr(y1), _stream(x0.device))
+    return y0, y1
+
+
+def fig1_vjp(x0, x1, y0_bar, y1_bar, accumulate=False, x0_bar=None, x1_bar=None):
+    if x0_bar is None:
+        x0_bar = torch.zeros_like(x0) if accumulate else torch.empty_like(x0)
+    if x1_bar is None:
+        x1_bar = torch.zeros_like(x1) if accumulate else torch.empty_like(x1)
+    capi.call("pvjp_fig1_vjp", _dt(x0), _ptr(x0), _ptr(x1), _ptr(y0_bar), _ptr(y1_bar), x0.numel(), _ptr(x0_bar),
+              _ptr(x1_bar), int(accumulate), _stream(x0.device))
+    return x0_bar, x1_bar

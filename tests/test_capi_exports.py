@@ -1,0 +1,73 @@
+"""The C-ABI library loads and exports every symbol include/pvjp.h declares;
+host-side validation rejects bad arguments before any launch.  No GPU needed:
+nothing here launches a kernel."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pvjp.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pvjp_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def capi():
+    from paper_2202_10297_amd import build, capi as c
+
+    if not os.path.exists(c.LIB_PATH):
+        build.build()
+    return c
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for must in ["pvjp_linrec_scan", "pvjp_linrec_scan_vjp", "pvjp_reduce", "pvjp_reduce_vjp", "pvjp_hist",
+                 "pvjp_hist_vjp", "pvjp_scatter", "pvjp_scatter_vjp", "pvjp_map", "pvjp_map_vjp"]:
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(capi):
+    lib = ctypes.CDLL(capi.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    out = subprocess.run(["nm", "-D", "--defined-only", capi.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\b(pvjp_[a-z0-9_]+)\b", out))
+    assert set(declared_functions()) <= exported
+
+
+def test_binding_covers_header(capi):
+    assert set(capi.SIGNATURES) == set(declared_functions())
+
+
+def test_validation_before_launch(capi):
+    L = capi.lib()
+    assert L.pvjp_linrec_scan(7, None, None, 10, None, None, None, None, 0, None) == capi.PVJP_EINVAL
+    assert "dtype" in capi.last_error()
+    assert L.pvjp_linrec_scan(capi.F64, 8, 8, -1, None, None, None, None, 0, None) == capi.PVJP_EINVAL
+    # workspace too small
+    assert L.pvjp_linrec_scan(capi.F64, 8, 8, 100, 8, 8, None, 256, 1, None) == capi.PVJP_ENOMEM
+    assert L.pvjp_hist(0, 0, None, None, 10, 0, None, None, None, None, None, None, 0, None) == capi.PVJP_EINVAL
+    assert L.pvjp_hist(capi.MAX, 0, 8, 8, 10, 4, 8, None, None, None, None, 256, 1 << 20, None) == capi.PVJP_EINVAL
+    assert "winner" in capi.last_error()
+    assert L.pvjp_reduce(9, 0, None, 1, None, None, None, None, None, 0, None) == capi.PVJP_EINVAL
+    assert L.pvjp_map(42, 0, 8, 1, 8, None) == capi.PVJP_EINVAL
+    # empty inputs are valid and launch nothing
+    assert L.pvjp_linrec_scan(capi.F32, None, None, 0, None, None, None, None, 0, None) == capi.PVJP_OK
+    assert L.pvjp_scatter(capi.F32, None, 0, None, None, 0, None, None) == capi.PVJP_OK
+
+
+def test_workspace_queries(capi):
+    L = capi.lib()
+    assert L.pvjp_linrec_ckpt_len(0) == 0
+    assert L.pvjp_linrec_ckpt_len(1) == 1 and L.pvjp_linrec_ckpt_len(1025) == 2
+    assert L.pvjp_linrec_scan_ws_bytes(capi.F64, 65536) >= 256 + 32 * 64
+    assert L.pvjp_hist_ws_bytes(capi.ADD, capi.F32, 1 << 26, 1 << 20) == 8 << 20
+    assert L.pvjp_reduce_ws_bytes(capi.ADD, capi.F32, 0) > 0
