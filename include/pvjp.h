@@ -222,6 +222,38 @@ pvjp_status pvjp_fig1_vjp(pvjp_dtype dtype, const void* x0, const void* x1, cons
                           const void* y1_bar, int64_t n, void* x0_bar, void* x1_bar,
                           int accumulate, void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* Gaussian-mixture log-likelihood and its gradient (the workload of          */
+/* Sec. 7.6; accumulators turned into contractions as in Sec. 6.1)            */
+/*                                                                            */
+/* The paper measures this objective without stating it; the definition here  */
+/* is the textbook mixture with a precision-Cholesky parametrisation:         */
+/*   Q_k = diag(exp(q_k)) + L_k, L_k strictly lower with entry (r, c), r > c,  */
+/*         at l[k*D(D-1)/2 + r(r-1)/2 + c];                                    */
+/*   s_ik = alpha_k + sum_d q_kd - 0.5 * |Q_k (x_i - mu_k)|^2;                 */
+/*   loglik = sum_i LSE_k(s_ik) - N*LSE(alpha) - (N*D/2)*log(2*pi).            */
+/* X: N x D row-major FP32 (16-byte aligned); alpha [K]; mu, q: K x D; l:      */
+/* K x D(D-1)/2; all FP32.  D must be 32 or 64 (PVJP_EUNSUPPORTED otherwise).  */
+/* The contraction Q_k (x_i - mu_k) runs on FP32 MFMA; |z|^2, the log-sum-exp  */
+/* and all cross-tile sums are FP64.                                           */
+/* ------------------------------------------------------------------------ */
+
+size_t pvjp_gmm_ws_bytes(int64_t N, int D, int K);
+/* loglik: device double (output).  lse: device double[N] (nullable output):
+ * the per-point LSE_k(s_ik), the checkpoint the reverse sweep reads. */
+pvjp_status pvjp_gmm_objective(const float* X, int64_t N, int D, int K, const float* alpha,
+                               const float* mu, const float* q, const float* l, double* loglik,
+                               double* lse, void* ws, size_t ws_bytes, void* stream);
+/* Reverse sweep with output adjoint ell_bar: alpha_bar [K], mu_bar and q_bar
+ * [K x D], l_bar [K x D(D-1)/2] (FP32 outputs, (+)=).  lse: the checkpoint
+ * written by pvjp_gmm_objective for the same inputs (nullable: the forward
+ * sweep then runs first into the workspace).  The per-point, per-component
+ * weights w_ik = ell_bar * exp(s_ik - LSE_i) are recomputed, not stored. */
+pvjp_status pvjp_gmm_vjp(const float* X, int64_t N, int D, int K, const float* alpha,
+                         const float* mu, const float* q, const float* l, double ell_bar,
+                         const double* lse, float* alpha_bar, float* mu_bar, float* q_bar,
+                         float* l_bar, int accumulate, void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

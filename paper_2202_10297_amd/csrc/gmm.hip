@@ -1,0 +1,603 @@
+// Gaussian-mixture log-likelihood and its full reverse-mode gradient (the
+// workload of Sec. 7.6; accumulators turned into reductions and contractions
+// as in Sec. 6.1).
+//
+// Objective (precision-Cholesky parametrisation; the paper leaves the
+// definition to its benchmark suite, this is the textbook mixture):
+//   Q_k = diag(exp q_k) + L_k (L_k strictly lower, row-major packed in l_k),
+//   z_ik = Q_k (x_i - mu_k) = Q_k x_i - c_k with c_k = Q_k mu_k,
+//   s_ik = alpha_k + sum_d q_kd - |z_ik|^2 / 2,
+//   loglik = sum_i LSE_k s_ik - N LSE(alpha) - N D/2 log(2 pi).
+//
+// Forward sweep (gmm_fwd): per 32-point tile a wave forms Z^T = Q_k X^T with
+// FP32 MFMA 32x32x2 (only the lower-triangular 32x32 blocks of Q_k), squares
+// and sums z in FP64, and keeps an online FP64 log-sum-exp over k.  LSE_i is
+// the per-point checkpoint of the reverse sweep.
+//
+// Return sweep: with w_ik = ell_bar * exp(s_ik - LSE_i) (s_ik recomputed,
+// Sec. 4.1), the parameter adjoints are
+//   G_k = sum_i w_ik z_ik y_ik^T   (y = x - mu_k; an MFMA contraction over
+//                                   points of the weighted Z and Y tiles),
+//   v_k = sum_i w_ik z_ik, W_k = sum_i w_ik,
+//   alpha_bar_k = W_k - N ell_bar softmax(alpha)_k,
+//   mu_bar_k = Q_k^T v_k,
+//   q_bar_kd = W_k - exp(q_kd) G_k[d][d],
+//   l_bar_k[r,c] = -G_k[r][c]  (r > c).
+// Per (component, point chunk) blocks write FP32 partials (accumulated in the
+// MFMA registers over at most 4096 points per wave); a per-component kernel
+// sums them in FP64 in a fixed order and applies the parameter maps.
+#include <math.h>
+
+#include "common.h"
+#include "prims.h"
+
+namespace pvjp {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ f32x16 mfma32(float a, float b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+// Result layout of a 32x32 MFMA: lane l, item t holds row drow(t, l) and
+// column l % 32.
+__device__ __forceinline__ int drow(int t, int lane) { return 8 * (t >> 2) + 4 * (lane >> 5) + (t & 3); }
+
+// Operand layout of a 32x32x2 MFMA step: lane l supplies A[l % 32][l / 32] and
+// B[l / 32][l % 32]; the contraction index of step s, half h, is c = 2s + h.
+template <int D>
+struct Gm {
+    static constexpr int RT = D / 32;                    // 32-row tiles of Q_k
+    static constexpr int S = D / 2;                      // steps over a full row
+    static constexpr int NF = 16 * RT * (RT + 1) / 2;    // A fragments in the lower triangle
+    static constexpr int NGT = RT * (RT + 1) / 2;        // lower-triangular 32x32 blocks of G_k
+};
+
+// Fragment index of row tile rt, step s (rt's row needs steps s < 16 (rt+1)).
+__host__ __device__ constexpr int fidx(int rt, int s) { return 8 * rt * (rt + 1) + s; }
+
+// X tile of 32 points in LDS, row-major [p][c] with an XOR swizzle that keeps
+// both the point-major and the column-major fragment reads conflict-free.
+template <int D>
+__device__ __forceinline__ int xs_at(int p, int c) {
+    return p * D + (c ^ (D == 64 ? 2 * p : 2 * (p >> 1)));
+}
+// Weighted-Z tile [r][p] (32 points per row), swizzled the same way.
+__device__ __forceinline__ int zs_at(int r, int p) { return r * 32 + (p ^ (2 * ((r >> 1) & 15))); }
+
+constexpr double kLog2Pi = 1.8378770664093454835606594728112;
+
+// -------------------------------------------------------------------- prep
+template <int D>
+__global__ __launch_bounds__(256) void gmm_prep_kernel(const float* __restrict__ alpha, const float* __restrict__ mu,
+                                                       const float* __restrict__ q, const float* __restrict__ l,
+                                                       int K, float* __restrict__ Qf, float* __restrict__ cvec,
+                                                       double* __restrict__ bias, double* __restrict__ lse_alpha) {
+    using C = Gm<D>;
+    const int k = blockIdx.x;
+    const int64_t tri = (int64_t)D * (D - 1) / 2;
+    __shared__ float Q[D][D + 1];
+    for (int e = threadIdx.x; e < D * D; e += blockDim.x) {
+        const int r = e / D, c = e % D;
+        float v = 0.f;
+        if (r == c)
+            v = (float)exp((double)q[(int64_t)k * D + r]);
+        else if (r > c)
+            v = l[(int64_t)k * tri + r * (r - 1) / 2 + c];
+        Q[r][c] = v;
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < D; r += blockDim.x) {
+        double acc = 0.0;
+        for (int c = 0; c <= r; ++c) acc += (double)Q[r][c] * (double)mu[(int64_t)k * D + c];
+        cvec[(int64_t)k * D + r] = (float)acc;
+    }
+    for (int e = threadIdx.x; e < C::NF * 64; e += blockDim.x) {
+        const int f = e / 64, lane = e % 64;
+        const int rt = (f < 16) ? 0 : 1;
+        const int s = f - fidx(rt, 0);
+        Qf[((int64_t)k * C::NF + f) * 64 + lane] = Q[32 * rt + (lane & 31)][2 * s + (lane >> 5)];
+    }
+    if (threadIdx.x == 0) {
+        double b = (double)alpha[k];
+        for (int d = 0; d < D; ++d) b += (double)q[(int64_t)k * D + d];
+        bias[k] = b;
+        if (k == 0) {
+            double mx = -INFINITY;
+            for (int j = 0; j < K; ++j) mx = fmax(mx, (double)alpha[j]);
+            double s = 0.0;
+            for (int j = 0; j < K; ++j) s += exp((double)alpha[j] - mx);
+            *lse_alpha = mx + log(s);
+        }
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void stage_x(const float* __restrict__ X, int64_t N, int64_t p0, float* xs) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < (32 * D) / 256; ++q) {
+        const int e = 4 * (lane + 64 * q);  // 4 consecutive floats of one point
+        const int pt = e / D, c = e % D;
+        const int64_t p = p0 + pt;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (p < N) v = *reinterpret_cast<const float4*>(X + p * D + c);
+        xs[xs_at<D>(pt, c)] = v.x;
+        xs[xs_at<D>(pt, c + 1)] = v.y;
+        xs[xs_at<D>(pt, c + 2)] = v.z;
+        xs[xs_at<D>(pt, c + 3)] = v.w;
+    }
+}
+
+// z = Q_k x - c_k for the wave's 32 points (column j = lane % 32), as MFMA
+// accumulators; returns sum_r z_r^2 in FP64 for the lane's point.
+template <int D>
+__device__ __forceinline__ double tile_znorm(const float (&qa)[Gm<D>::NF], const float (&bx)[Gm<D>::S],
+                                             const float (&cl)[Gm<D>::RT][16], f32x16 (&acc)[Gm<D>::RT]) {
+    using C = Gm<D>;
+#pragma unroll
+    for (int rt = 0; rt < C::RT; ++rt) {
+        f32x16 a = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 16 * (rt + 1); ++s) a = mfma32(qa[fidx(rt, s)], bx[s], a);
+        acc[rt] = a;
+    }
+    double nrm = 0.0;
+#pragma unroll
+    for (int rt = 0; rt < C::RT; ++rt) {
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const float z = acc[rt][t] - cl[rt][t];
+            acc[rt][t] = z;
+            nrm = fma((double)z, (double)z, nrm);
+        }
+    }
+    return nrm + __shfl_xor(nrm, 32, kWave);
+}
+
+template <int D>
+__device__ __forceinline__ void load_component(const float* __restrict__ Qf, const float* __restrict__ cvec, int k,
+                                               float (&qa)[Gm<D>::NF], float (&cl)[Gm<D>::RT][16]) {
+    using C = Gm<D>;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int f = 0; f < C::NF; ++f) qa[f] = Qf[((int64_t)k * C::NF + f) * 64 + lane];
+#pragma unroll
+    for (int rt = 0; rt < C::RT; ++rt)
+#pragma unroll
+        for (int t = 0; t < 16; ++t) cl[rt][t] = cvec[(int64_t)k * D + 32 * rt + drow(t, lane)];
+}
+
+struct GmmHdr {
+    uint32_t done;
+    uint32_t pad[63];
+};
+
+// ------------------------------------------------------------------ forward
+template <int D>
+__global__ __launch_bounds__(256) void gmm_fwd_kernel(const float* __restrict__ X, int64_t N, int K,
+                                                      const float* __restrict__ Qf, const float* __restrict__ cvec,
+                                                      const double* __restrict__ bias,
+                                                      const double* __restrict__ lse_alpha, double* __restrict__ lse,
+                                                      double* parts, GmmHdr* hdr, double* loglik) {
+    using C = Gm<D>;
+    __shared__ float Xs[4][32 * D];
+    __shared__ double red[4];
+    __shared__ int s_last;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t p0 = ((int64_t)blockIdx.x * 4 + w) * 32;
+    stage_x<D>(X, N, p0, Xs[w]);
+    __syncthreads();
+    float bx[C::S];
+#pragma unroll
+    for (int s = 0; s < C::S; ++s) bx[s] = Xs[w][xs_at<D>(lane & 31, 2 * s + (lane >> 5))];
+    const int64_t p = p0 + (lane & 31);
+
+    double m = -INFINITY, ssum = 0.0;
+    float qa[C::NF], cl[C::RT][16];
+    for (int k = 0; k < K; ++k) {
+        load_component<D>(Qf, cvec, k, qa, cl);
+        f32x16 acc[C::RT];
+        const double nrm = tile_znorm<D>(qa, bx, cl, acc);
+        const double s = bias[k] - 0.5 * nrm;
+        if (s > m) {
+            ssum = ssum * exp(m - s) + 1.0;
+            m = s;
+        } else {
+            ssum += exp(s - m);
+        }
+    }
+    const double l_i = m + log(ssum);
+    const bool valid = (lane < 32) && (p < N);
+    if (valid && lse) lse[p] = l_i;
+
+    double v = valid ? l_i : 0.0;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        st_coherent(&parts[blockIdx.x], (red[0] + red[1]) + (red[2] + red[3]));
+        const uint32_t d = __hip_atomic_fetch_add(&hdr->done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (d == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!s_last) return;
+    // Last block: fixed-order sum of the block partials.
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += 256) acc += ld_coherent(&parts[b]);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, kWave);
+    __syncthreads();
+    if (lane == 0) red[w] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double tot = (red[0] + red[1]) + (red[2] + red[3]);
+        *loglik = tot - (double)N * (*lse_alpha) - 0.5 * (double)N * D * kLog2Pi;
+        __hip_atomic_store(&hdr->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// ----------------------------------------------------------------- backward
+template <int D>
+__global__ __launch_bounds__(256) void gmm_bwd_kernel(const float* __restrict__ X, int64_t N, int K, int64_t chunk,
+                                                      int nch, const float* __restrict__ Qf,
+                                                      const float* __restrict__ cvec, const float* __restrict__ mu,
+                                                      const double* __restrict__ bias, const double* __restrict__ lse,
+                                                      double ell_bar, float* __restrict__ gpart,
+                                                      float* __restrict__ vpart, double* __restrict__ wpart) {
+    using C = Gm<D>;
+    // X tiles and weighted-Z tiles of the four waves; reused at the end as
+    // the scratch of the cross-wave reduction.
+    __shared__ float smem[2 * 4 * 32 * D];
+    float* const Xw = smem + (threadIdx.x >> 6) * 32 * D;
+    float* const Zw = smem + 4 * 32 * D + (threadIdx.x >> 6) * 32 * D;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int k = blockIdx.x % K;
+    const int ch = blockIdx.x / K;
+    const int h = lane >> 5, j = lane & 31;
+
+    float qa[C::NF], cl[C::RT][16];
+    load_component<D>(Qf, cvec, k, qa, cl);
+    float mub[C::RT];
+#pragma unroll
+    for (int ct = 0; ct < C::RT; ++ct) mub[ct] = mu[(int64_t)k * D + 32 * ct + j];
+    const double bk = bias[k];
+
+    f32x16 gacc[C::NGT];
+#pragma unroll
+    for (int g = 0; g < C::NGT; ++g)
+#pragma unroll
+        for (int t = 0; t < 16; ++t) gacc[g][t] = 0.f;
+    float vs[C::RT][16];
+#pragma unroll
+    for (int rt = 0; rt < C::RT; ++rt)
+#pragma unroll
+        for (int t = 0; t < 16; ++t) vs[rt][t] = 0.f;
+    double wsum = 0.0;
+
+    const int64_t cbeg = (int64_t)ch * chunk;
+    const int iters = (int)(chunk / 128);
+    for (int it = 0; it < iters; ++it) {
+        const int64_t p0 = cbeg + (int64_t)(it * 4 + w) * 32;
+        __syncthreads();
+        stage_x<D>(X, N, p0, Xw);
+        __syncthreads();
+        float bx[C::S];
+#pragma unroll
+        for (int s = 0; s < C::S; ++s) bx[s] = Xw[xs_at<D>(j, 2 * s + h)];
+        f32x16 z[C::RT];
+        const double nrm = tile_znorm<D>(qa, bx, cl, z);
+        const int64_t p = p0 + j;
+        double wd = 0.0;
+        if (p < N) wd = ell_bar * exp((bk - 0.5 * nrm) - lse[p]);
+        const float wf = (float)wd;
+        if (h == 0) wsum += wd;
+#pragma unroll
+        for (int rt = 0; rt < C::RT; ++rt)
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const float wz = wf * z[rt][t];
+                vs[rt][t] += wz;
+                Zw[zs_at(32 * rt + drow(t, lane), j)] = wz;
+            }
+        __syncthreads();
+        // G_k += (w Z)^T Y over this tile's 32 points, lower-triangular blocks.
+        int g = 0;
+#pragma unroll
+        for (int rt = 0; rt < C::RT; ++rt) {
+#pragma unroll
+            for (int ct = 0; ct <= rt; ++ct) {
+                f32x16 a = gacc[g];
+#pragma unroll
+                for (int s = 0; s < 16; ++s) {
+                    const int pt = 2 * s + h;
+                    const float za = Zw[zs_at(32 * rt + j, pt)];
+                    const float yb = Xw[xs_at<D>(pt, 32 * ct + j)] - mub[ct];
+                    a = mfma32(za, yb, a);
+                }
+                gacc[g] = a;
+                ++g;
+            }
+        }
+    }
+
+    // Sum v over the 32 points of each half-wave (lanes with the same h).
+#pragma unroll
+    for (int rt = 0; rt < C::RT; ++rt)
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            float v = vs[rt][t];
+#pragma unroll
+            for (int d = 16; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+            vs[rt][t] = v;
+        }
+#pragma unroll
+    for (int d = 16; d >= 1; d >>= 1) wsum += __shfl_xor(wsum, d, kWave);
+
+    // Combine the four waves through LDS (reusing the tiles) in a fixed order.
+    __syncthreads();
+    float* red = smem;
+    constexpr int kRedFloats = 3 * Gm<D>::NGT * 1024 + 3 * D;
+    static_assert(kRedFloats + 8 <= 2 * 4 * 32 * D, "reduction scratch");
+    double* wred = reinterpret_cast<double*>(smem + ((kRedFloats + 1) & ~1));
+    if (w > 0) {
+#pragma unroll
+        for (int g = 0; g < C::NGT; ++g)
+#pragma unroll
+            for (int t = 0; t < 16; ++t) red[((w - 1) * C::NGT * 16 + g * 16 + t) * 64 + lane] = gacc[g][t];
+        if (j == 0) {
+#pragma unroll
+            for (int rt = 0; rt < C::RT; ++rt)
+#pragma unroll
+                for (int t = 0; t < 16; ++t) red[3 * C::NGT * 1024 + (w - 1) * D + 32 * rt + drow(t, lane)] = vs[rt][t];
+        }
+    }
+    if (lane == 0) wred[w] = wsum;
+    __syncthreads();
+    if (w == 0) {
+        const int64_t rec = (int64_t)k * nch + ch;
+#pragma unroll
+        for (int g = 0; g < C::NGT; ++g)
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                float s = gacc[g][t];
+                for (int o = 0; o < 3; ++o) s += red[(o * C::NGT * 16 + g * 16 + t) * 64 + lane];
+                gpart[(rec * C::NGT * 16 + g * 16 + t) * 64 + lane] = s;
+            }
+        if (j == 0) {
+#pragma unroll
+            for (int rt = 0; rt < C::RT; ++rt)
+#pragma unroll
+                for (int t = 0; t < 16; ++t) {
+                    const int r = 32 * rt + drow(t, lane);
+                    float s = vs[rt][t];
+                    for (int o = 0; o < 3; ++o) s += red[3 * C::NGT * 1024 + o * D + r];
+                    vpart[rec * D + r] = s;
+                }
+        }
+        if (lane == 0) wpart[rec] = (wred[0] + wred[1]) + (wred[2] + wred[3]);
+    }
+}
+
+// ------------------------------------------------------ reduce + parameters
+template <int D>
+__global__ __launch_bounds__(256) void gmm_param_kernel(int64_t N, int K, int nch, const float* __restrict__ alpha,
+                                                        const float* __restrict__ q, const float* __restrict__ l,
+                                                        const double* __restrict__ lse_alpha, double ell_bar,
+                                                        const float* __restrict__ gpart,
+                                                        const float* __restrict__ vpart,
+                                                        const double* __restrict__ wpart, float* __restrict__ abar,
+                                                        float* __restrict__ mbar, float* __restrict__ qbar,
+                                                        float* __restrict__ lbar, int accumulate) {
+    using C = Gm<D>;
+    const int k = blockIdx.x;
+    const int64_t tri = (int64_t)D * (D - 1) / 2;
+    __shared__ double G[D][D + 1];
+    __shared__ double v[D];
+    __shared__ double Wk;
+    __shared__ float Q[D][D + 1];
+    // G (lower-triangular 32x32 blocks) summed over chunks in FP64, chunk order.
+    for (int e = threadIdx.x; e < C::NGT * 1024; e += blockDim.x) {
+        const int g = e / 1024, t = (e / 64) % 16, lane = e % 64;
+        int rt = 0, ct = 0;
+        if (g == 1) rt = 1;
+        if (g == 2) rt = 1, ct = 1;
+        double s = 0.0;
+        for (int c = 0; c < nch; ++c) s += (double)gpart[(((int64_t)k * nch + c) * C::NGT * 16 + g * 16 + t) * 64 + lane];
+        G[32 * rt + drow(t, lane)][32 * ct + (lane & 31)] = s;
+    }
+    for (int r = threadIdx.x; r < D; r += blockDim.x) {
+        double s = 0.0;
+        for (int c = 0; c < nch; ++c) s += (double)vpart[((int64_t)k * nch + c) * D + r];
+        v[r] = s;
+    }
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int c = 0; c < nch; ++c) s += wpart[(int64_t)k * nch + c];
+        Wk = s;
+    }
+    for (int e = threadIdx.x; e < D * D; e += blockDim.x) {
+        const int r = e / D, c = e % D;
+        float x = 0.f;
+        if (r == c)
+            x = (float)exp((double)q[(int64_t)k * D + r]);
+        else if (r > c)
+            x = l[(int64_t)k * tri + r * (r - 1) / 2 + c];
+        Q[r][c] = x;
+    }
+    __syncthreads();
+    const double W = Wk;
+    if (threadIdx.x == 0) {
+        const double a = W - (double)N * ell_bar * exp((double)alpha[k] - *lse_alpha);
+        abar[k] = accumulate ? abar[k] + (float)a : (float)a;
+    }
+    for (int c = threadIdx.x; c < D; c += blockDim.x) {
+        double s = 0.0;  // (Q_k^T v_k)_c = sum_{r >= c} Q[r][c] v[r]
+        for (int r = c; r < D; ++r) s += (double)Q[r][c] * v[r];
+        const int64_t o = (int64_t)k * D + c;
+        mbar[o] = accumulate ? mbar[o] + (float)s : (float)s;
+        const double qd = W - (double)Q[c][c] * G[c][c];
+        qbar[o] = accumulate ? qbar[o] + (float)qd : (float)qd;
+    }
+    for (int e = threadIdx.x; e < tri; e += blockDim.x) {
+        // packed strictly-lower index e -> (r, c), r > c, e = r(r-1)/2 + c
+        int r = (int)((1.0 + sqrt(1.0 + 8.0 * (double)e)) / 2.0);
+        while (r * (r - 1) / 2 > e) --r;
+        while ((r + 1) * r / 2 <= e) ++r;
+        const int c = e - r * (r - 1) / 2;
+        const int64_t o = (int64_t)k * tri + e;
+        const float g = (float)(-G[r][c]);
+        lbar[o] = accumulate ? lbar[o] + g : g;
+    }
+}
+
+// ------------------------------------------------------------------ host
+struct GmmLayout {
+    size_t Qf, cvec, bias, scal, fparts, lse, gpart, vpart, wpart, total;
+    int64_t nch, chunk;
+    unsigned fgrid;
+};
+
+static GmmLayout gmm_layout(int64_t N, int D, int K) {
+    GmmLayout L{};
+    const int RT = D / 32;
+    const int NF = 16 * RT * (RT + 1) / 2, NGT = RT * (RT + 1) / 2;
+    int64_t target = 4096 / K;
+    if (target < 1) target = 1;
+    int64_t chunk = ceil_div(ceil_div(N > 0 ? N : 1, target), 128) * 128;
+    if (chunk > 16384) chunk = 16384;
+    if (chunk < 128) chunk = 128;
+    L.chunk = chunk;
+    L.nch = ceil_div(N > 0 ? N : 1, chunk);
+    L.fgrid = (unsigned)ceil_div(N > 0 ? N : 1, 128);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o += align_up(bytes, 256);
+        return at;
+    };
+    L.scal = take(sizeof(GmmHdr) + 256);  // header, lse_alpha, loglik scratch
+    L.Qf = take((size_t)K * NF * 64 * 4);
+    L.cvec = take((size_t)K * D * 4);
+    L.bias = take((size_t)K * 8);
+    L.fparts = take((size_t)L.fgrid * 8);
+    L.lse = take((size_t)(N > 0 ? N : 1) * 8);
+    L.gpart = take((size_t)K * L.nch * NGT * 1024 * 4);
+    L.vpart = take((size_t)K * L.nch * D * 4);
+    L.wpart = take((size_t)K * L.nch * 8);
+    L.total = o;
+    return L;
+}
+
+template <int D>
+static void launch_prep(const float* alpha, const float* mu, const float* q, const float* l, int K, char* ws,
+                        const GmmLayout& L, hipStream_t st) {
+    double* scal = reinterpret_cast<double*>(ws + L.scal + sizeof(GmmHdr));
+    hipLaunchKernelGGL(gmm_prep_kernel<D>, dim3(K), dim3(256), 0, st, alpha, mu, q, l, K, (float*)(ws + L.Qf),
+                       (float*)(ws + L.cvec), (double*)(ws + L.bias), scal);
+}
+
+template <int D>
+static void launch_fwd(const float* X, int64_t N, int K, char* ws, const GmmLayout& L, double* lse, double* loglik,
+                       hipStream_t st) {
+    double* scal = reinterpret_cast<double*>(ws + L.scal + sizeof(GmmHdr));
+    hipLaunchKernelGGL(gmm_fwd_kernel<D>, dim3(L.fgrid), dim3(256), 0, st, X, N, K, (const float*)(ws + L.Qf),
+                       (const float*)(ws + L.cvec), (const double*)(ws + L.bias), (const double*)scal, lse,
+                       (double*)(ws + L.fparts), (GmmHdr*)(ws + L.scal), loglik);
+}
+
+template <int D>
+static void launch_bwd(const float* X, int64_t N, int K, const float* alpha, const float* mu, const float* q,
+                       const float* l, double ell_bar, const double* lse, float* ab, float* mb, float* qb, float* lb,
+                       int acc, char* ws, const GmmLayout& L, hipStream_t st) {
+    double* scal = reinterpret_cast<double*>(ws + L.scal + sizeof(GmmHdr));
+    hipLaunchKernelGGL(gmm_bwd_kernel<D>, dim3((unsigned)(K * L.nch)), dim3(256), 0, st, X, N, K, L.chunk, (int)L.nch,
+                       (const float*)(ws + L.Qf), (const float*)(ws + L.cvec), mu, (const double*)(ws + L.bias), lse,
+                       ell_bar, (float*)(ws + L.gpart), (float*)(ws + L.vpart), (double*)(ws + L.wpart));
+    hipLaunchKernelGGL(gmm_param_kernel<D>, dim3(K), dim3(256), 0, st, N, K, (int)L.nch, alpha, q, l,
+                       (const double*)scal, ell_bar, (const float*)(ws + L.gpart), (const float*)(ws + L.vpart),
+                       (const double*)(ws + L.wpart), ab, mb, qb, lb, acc);
+}
+
+static pvjp_status gmm_args(int64_t N, int D, int K, const void* X, const void* alpha, const void* mu,
+                            const void* q, const void* l, const char* name) {
+    if (D != 32 && D != 64) {
+        set_error("%s: D = %d unsupported (the MFMA path is built for D = 32 and D = 64)", name, D);
+        return PVJP_EUNSUPPORTED;
+    }
+    PVJP_REQUIRE(N >= 0 && N <= ((int64_t)1 << 40), "%s: N = %lld out of range", name, (long long)N);
+    PVJP_REQUIRE(K >= 1 && K <= 65535, "%s: K = %d out of range [1, 65535]", name, K);
+    PVJP_REQUIRE(alpha && mu && q && l && (N == 0 || X), "%s: X, alpha, mu, q and l must be non-NULL", name);
+    PVJP_REQUIRE(aligned(X, 16), "%s: X must be 16-byte aligned", name);
+    return PVJP_OK;
+}
+
+}  // namespace pvjp
+
+using namespace pvjp;
+
+extern "C" size_t pvjp_gmm_ws_bytes(int64_t N, int D, int K) {
+    if (N < 0 || (D != 32 && D != 64) || K < 1) return 0;
+    return gmm_layout(N, D, K).total;
+}
+
+extern "C" pvjp_status pvjp_gmm_objective(const float* X, int64_t N, int D, int K, const float* alpha,
+                                          const float* mu, const float* q, const float* l, double* loglik,
+                                          double* lse, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    if (pvjp_status e = gmm_args(N, D, K, X, alpha, mu, q, l, "pvjp_gmm_objective")) return e;
+    PVJP_REQUIRE(loglik != nullptr, "pvjp_gmm_objective: loglik is NULL");
+    PVJP_REQUIRE(ws != nullptr && aligned(ws, 256), "pvjp_gmm_objective: ws must be non-NULL and 256-byte aligned");
+    const GmmLayout L = gmm_layout(N, D, K);
+    if (ws_bytes < L.total) {
+        set_error("pvjp_gmm_objective: workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+        return PVJP_ENOMEM;
+    }
+    char* w = reinterpret_cast<char*>(ws);
+    hipStream_t st = as_stream(stream);
+    if (D == 64) {
+        launch_prep<64>(alpha, mu, q, l, K, w, L, st);
+        launch_fwd<64>(X, N, K, w, L, lse, loglik, st);
+    } else {
+        launch_prep<32>(alpha, mu, q, l, K, w, L, st);
+        launch_fwd<32>(X, N, K, w, L, lse, loglik, st);
+    }
+    PVJP_LAUNCHED("pvjp_gmm_objective");
+    return PVJP_OK;
+}
+
+extern "C" pvjp_status pvjp_gmm_vjp(const float* X, int64_t N, int D, int K, const float* alpha, const float* mu,
+                                    const float* q, const float* l, double ell_bar, const double* lse,
+                                    float* alpha_bar, float* mu_bar, float* q_bar, float* l_bar, int accumulate,
+                                    void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    if (pvjp_status e = gmm_args(N, D, K, X, alpha, mu, q, l, "pvjp_gmm_vjp")) return e;
+    PVJP_REQUIRE(alpha_bar && mu_bar && q_bar && l_bar, "pvjp_gmm_vjp: the four adjoint outputs must be non-NULL");
+    PVJP_REQUIRE(ws != nullptr && aligned(ws, 256), "pvjp_gmm_vjp: ws must be non-NULL and 256-byte aligned");
+    const GmmLayout L = gmm_layout(N, D, K);
+    if (ws_bytes < L.total) {
+        set_error("pvjp_gmm_vjp: workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+        return PVJP_ENOMEM;
+    }
+    char* w = reinterpret_cast<char*>(ws);
+    hipStream_t st = as_stream(stream);
+    double* ll_scratch = reinterpret_cast<double*>(w + L.scal + sizeof(GmmHdr)) + 1;
+    if (D == 64) {
+        launch_prep<64>(alpha, mu, q, l, K, w, L, st);
+        if (lse == nullptr) {
+            launch_fwd<64>(X, N, K, w, L, (double*)(w + L.lse), ll_scratch, st);
+            lse = (const double*)(w + L.lse);
+        }
+        launch_bwd<64>(X, N, K, alpha, mu, q, l, ell_bar, lse, alpha_bar, mu_bar, q_bar, l_bar, accumulate, w, L, st);
+    } else {
+        launch_prep<32>(alpha, mu, q, l, K, w, L, st);
+        if (lse == nullptr) {
+            launch_fwd<32>(X, N, K, w, L, (double*)(w + L.lse), ll_scratch, st);
+            lse = (const double*)(w + L.lse);
+        }
+        launch_bwd<32>(X, N, K, alpha, mu, q, l, ell_bar, lse, alpha_bar, mu_bar, q_bar, l_bar, accumulate, w, L, st);
+    }
+    PVJP_LAUNCHED("pvjp_gmm_vjp");
+    return PVJP_OK;
+}

@@ -216,3 +216,34 @@ def fig1_vjp(x0, x1, y0_bar, y1_bar, accumulate=False, x0_bar=None, x1_bar=None)
     capi.call("pvjp_fig1_vjp", _dt(x0), _ptr(x0), _ptr(x1), _ptr(y0_bar), _ptr(y1_bar), x0.numel(), _ptr(x0_bar),
               _ptr(x1_bar), int(accumulate), _stream(x0.device))
     return x0_bar, x1_bar
+
+
+# --------------------------------------------------------------------- GMM
+def gmm_objective(X, alpha, mu, q, l, want_lse=True):
+    """Returns (loglik [1] float64 device tensor, lse [N] float64 or None)."""
+    N, D = X.shape
+    K = alpha.numel()
+    dev = X.device
+    ll = torch.empty(1, dtype=torch.float64, device=dev)
+    lse = torch.empty(N, dtype=torch.float64, device=dev) if want_lse else None
+    nb = capi.lib().pvjp_gmm_ws_bytes(N, D, K)
+    ws = WS.get("gmm", nb, dev)
+    capi.call("pvjp_gmm_objective", _ptr(X), N, D, K, _ptr(alpha), _ptr(mu), _ptr(q), _ptr(l), _ptr(ll), _ptr(lse),
+              _ptr(ws), ws.numel(), _stream(dev))
+    return ll, lse
+
+
+def gmm_vjp(X, alpha, mu, q, l, lse=None, ell_bar=1.0, out=None, accumulate=False):
+    """Returns (alpha_bar, mu_bar, q_bar, l_bar) (float32, device)."""
+    N, D = X.shape
+    K = alpha.numel()
+    dev = X.device
+    if out is None:
+        mk = torch.zeros_like if accumulate else torch.empty_like
+        out = (mk(alpha), mk(mu), mk(q), mk(l))
+    ab, mb, qb, lb = out
+    nb = capi.lib().pvjp_gmm_ws_bytes(N, D, K)
+    ws = WS.get("gmm", nb, dev)
+    capi.call("pvjp_gmm_vjp", _ptr(X), N, D, K, _ptr(alpha), _ptr(mu), _ptr(q), _ptr(l), float(ell_bar), _ptr(lse),
+              _ptr(ab), _ptr(mb), _ptr(qb), _ptr(lb), int(accumulate), _ptr(ws), ws.numel(), _stream(dev))
+    return ab, mb, qb, lb

@@ -1,0 +1,99 @@
+"""GPU parity of the Gaussian-mixture objective and gradient against the taped
+FP64 oracle (FP32 inputs, relative L2 per parameter group <= 2e-5)."""
+import numpy as np
+import pytest
+
+from _util import TOL_F32, rel_l2
+from paper_2202_10297_amd import workloads
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def ops():
+    from paper_2202_10297_amd import capi, ops as o
+
+    capi.lib()
+    return o
+
+
+CASES = [(1, 32, 1), (7, 32, 3), (130, 32, 5), (300, 64, 4), (1000, 64, 20), (2049, 32, 50), (200, 64, 200)]
+
+
+@pytest.mark.parametrize("N,D,K", CASES)
+def test_gmm_objective_and_gradient(ops, orc, N, D, K):
+    X, alpha, mu, q, l = workloads.gmm(N, D, K, seed=N + D + K)
+    ll, lse = ops.gmm_objective(dev(X), dev(alpha), dev(mu), dev(q), dev(l))
+    rll, rlse = orc.gmm_objective(X, alpha, mu, q, l)
+    assert abs(host(ll)[0] - rll) <= TOL_F32 * abs(rll)
+    assert rel_l2(host(lse), rlse) <= TOL_F32
+    got = ops.gmm_vjp(dev(X), dev(alpha), dev(mu), dev(q), dev(l), lse=lse, ell_bar=1.0)
+    ref = orc.gmm_vjp(X, alpha, mu, q, l, 1.0)
+    for name, g, r in zip(["alpha", "mu", "q", "l"], got, ref):
+        err = rel_l2(host(g), r)
+        assert err <= TOL_F32, (name, err)
+    assert rel_l2([host(g) for g in got], list(ref)) <= TOL_F32
+
+
+def test_gmm_vjp_without_checkpoint_and_accumulate(ops, orc):
+    N, D, K = 500, 64, 6
+    X, alpha, mu, q, l = workloads.gmm(N, D, K, seed=3)
+    ref = orc.gmm_vjp(X, alpha, mu, q, l, 0.5)
+    got = ops.gmm_vjp(dev(X), dev(alpha), dev(mu), dev(q), dev(l), lse=None, ell_bar=0.5)
+    assert rel_l2([host(g) for g in got], list(ref)) <= TOL_F32
+    base = [workloads.rng(i).standard_normal(a.shape).astype(np.float32) for i, a in enumerate((alpha, mu, q, l))]
+    out = tuple(dev(b) for b in base)
+    ops.gmm_vjp(dev(X), dev(alpha), dev(mu), dev(q), dev(l), ell_bar=0.5, out=out, accumulate=True)
+    for g, b, r in zip(out, base, ref):
+        assert rel_l2(host(g), b + r) <= TOL_F32
+
+
+def test_gmm_empty_and_unsupported(ops):
+    from paper_2202_10297_amd import capi
+
+    X, alpha, mu, q, l = workloads.gmm(0, 32, 3, seed=1)
+    X = np.zeros((0, 32), dtype=np.float32)
+    ll, _ = ops.gmm_objective(dev(X).reshape(0, 32), dev(alpha), dev(mu), dev(q), dev(l))
+    assert host(ll)[0] == 0.0
+    ab, mb, qb, lb = ops.gmm_vjp(dev(X).reshape(0, 32), dev(alpha), dev(mu), dev(q), dev(l))
+    assert np.all(host(ab) == 0) and np.all(host(mb) == 0) and np.all(host(lb) == 0)
+    assert np.all(host(qb) == 0)
+    # D outside the built shapes is refused before any launch
+    L = capi.lib()
+    assert L.pvjp_gmm_objective(8, 10, 48, 3, 8, 8, 8, 8, 8, None, 256, 1 << 20, None) == capi.PVJP_EUNSUPPORTED
+
+
+def test_gmm_full_size_sampled(ops, orc):
+    # N = 10^6, D = 64, K = 200: per-point LSE on sampled points against the
+    # oracle (each LSE_i depends on point i only), and properties of the full
+    # gradient: sum(alpha_bar) = 0, and additivity over two halves of the data.
+    N, D, K = 1_000_000, 64, 200
+    X, alpha, mu, q, l = workloads.gmm(N, D, K, seed=0)
+    Xd = dev(X)
+    P = [dev(a) for a in (alpha, mu, q, l)]
+    ll, lse = ops.gmm_objective(Xd, *P)
+    idx = np.random.default_rng(5).choice(N, 24, replace=False)
+    _, rl = orc.gmm_objective(X[idx], alpha, mu, q, l)
+    assert rel_l2(host(lse)[idx], rl) <= TOL_F32
+    from scipy.special import logsumexp
+
+    expect = host(lse).sum() - N * logsumexp(alpha.astype(np.float64)) - 0.5 * N * D * np.log(2 * np.pi)
+    assert abs(host(ll)[0] - expect) <= 1e-12 * abs(expect)
+    g = [host(t) for t in ops.gmm_vjp(Xd, *P, lse=lse)]
+    assert abs(g[0].sum()) <= 1e-5 * np.abs(g[0]).sum()
+    h = N // 2
+    g1 = [host(t) for t in ops.gmm_vjp(dev(X[:h]), *P)]
+    g2 = [host(t) for t in ops.gmm_vjp(dev(X[h:]), *P)]
+    # alpha_bar's -N softmax(alpha) term splits with N as well
+    for a, b, c in zip(g, g1, g2):
+        assert rel_l2(b + c, a) <= TOL_F32
