@@ -223,6 +223,43 @@ pvjp_status pvjp_fig1_vjp(pvjp_dtype dtype, const void* x0, const void* x1, cons
                           int accumulate, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* Segmented batches: many instances of uneven length stored back to back     */
+/* (segment s = elements [offsets[s], offsets[s+1])), each processed as one   */
+/* segmented operation per launch.  This generalises the rule of Sec. 5.2     */
+/* that turns a vectorised scan into a regular-segmented scan to irregular    */
+/* segments.  Segments must be non-empty.                                     */
+/* ------------------------------------------------------------------------ */
+
+/* Workspace for `total` elements in `nseg` segments with tiles of
+ * tile_elems (1024, 2048 or 4096 elements per tile). */
+size_t pvjp_seg_ws_bytes(int64_t total, int64_t nseg, int tile_elems);
+/* Validates the HOST offsets [nseg+1] (offsets[0] = 0, strictly increasing)
+ * and uploads the segment tables into ws (synchronises `stream`).  Later calls
+ * with this ws must pass the same total (= offsets[nseg]), nseg and
+ * tile_elems.  The lookback header in ws is left as pvjp_ws_clear leaves it
+ * only if ws was zero-filled before. */
+pvjp_status pvjp_seg_prepare(const int64_t* host_offsets, int64_t nseg, int tile_elems, void* ws,
+                             size_t ws_bytes, void* stream);
+/* Every segment's linear-recurrence scan (Sec. 5.2) in one decoupled-lookback
+ * launch with the segmented operator; A, B (nullable together) and ckpt
+ * (nullable; 2 * pvjp_linrec_ckpt_len(total) elements: the state before each
+ * global multiple of the checkpoint interval) as for pvjp_linrec_scan. */
+pvjp_status pvjp_seg_linrec_scan(pvjp_dtype dtype, const void* a, const void* b, int64_t total,
+                                 int64_t nseg, int tile_elems, void* A, void* B, void* ckpt, void* ws,
+                                 size_t ws_bytes, void* stream);
+/* One persistent launch of `grid_blocks` workgroups that pulls work from a
+ * queue: the reverse sweep of every segment's scan (as pvjp_linrec_scan_vjp,
+ * needs the segmented ckpt) and, when sum_ybar is given, the adjoint of a
+ * sum-reduce per segment, sum_xbar[i] (+)= sum_ybar[segment of i]
+ * (Sec. 5.1.1).  Either part may be omitted (a == NULL, or sum_ybar ==
+ * sum_xbar == NULL).  Safe to capture in a HIP graph and replay. */
+pvjp_status pvjp_seg_batch_vjp(pvjp_dtype dtype, const void* a, const void* b, const void* yA_bar,
+                               const void* yB_bar, int64_t total, int64_t nseg, int tile_elems,
+                               const void* ckpt, void* a_bar, void* b_bar, const void* sum_ybar,
+                               void* sum_xbar, int accumulate, int grid_blocks, void* ws,
+                               size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* Gaussian-mixture log-likelihood and its gradient (the workload of          */
 /* Sec. 7.6; accumulators turned into contractions as in Sec. 6.1)            */
 /*                                                                            */

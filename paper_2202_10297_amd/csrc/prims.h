@@ -62,6 +62,42 @@ struct LinO {
     }
 };
 
+// The linear recurrence restarted at segment heads (the standard segmented
+// form of an operator): a state carries a flag "contains a segment start";
+// combining with a later flagged state discards the earlier one.
+template <class T>
+struct SegLinRec {
+    struct S {
+        T a, b;
+        uint32_t f, pad;
+    };
+    __device__ static __forceinline__ S id() { return S{T(1), T(0), 0u, 0u}; }
+    __device__ static __forceinline__ S comb(S x, S y) {
+        return y.f ? y : S{y.a * x.a, y.a * x.b + y.b, x.f, 0u};
+    }
+    __device__ static __forceinline__ S up(S v, int d) {
+        return S{shfl_up1(v.a, d), shfl_up1(v.b, d), (uint32_t)shfl_up1((int)v.f, d), 0u};
+    }
+    __device__ static __forceinline__ S down(S v, int d) {
+        return S{shfl_down1(v.a, d), shfl_down1(v.b, d), (uint32_t)shfl_down1((int)v.f, d), 0u};
+    }
+    __device__ static __forceinline__ S idx(S v, int s) {
+        return S{shfl_idx1(v.a, s), shfl_idx1(v.b, s), (uint32_t)shfl_idx1((int)v.f, s), 0u};
+    }
+};
+
+// Integer sum (counts of segment heads).
+struct IntSum {
+    struct S {
+        int v;
+    };
+    __device__ static __forceinline__ S id() { return S{0}; }
+    __device__ static __forceinline__ S comb(S x, S y) { return S{x.v + y.v}; }
+    __device__ static __forceinline__ S up(S v, int d) { return S{shfl_up1(v.v, d)}; }
+    __device__ static __forceinline__ S down(S v, int d) { return S{shfl_down1(v.v, d)}; }
+    __device__ static __forceinline__ S idx(S v, int s) { return S{shfl_idx1(v.v, s)}; }
+};
+
 // ------------------------------------------------------------- block scan
 // Exclusive scan over the threads of a block in scan order.  With REV the
 // scan order of threads is reversed (thread BLOCK-1 first).  `agg` is the

@@ -1,0 +1,464 @@
+// Segmented batches: many linear-recurrence scans (and their VJPs) and many
+// sum-reduce VJPs of uneven lengths, stored back to back, processed as ONE
+// segmented operation per launch (the segmented-scan idea of Sec. 5.2's
+// vectorised-operator rule, generalised to irregular segments).
+//
+//  - Primal (seg_linrec_fwd): one decoupled-lookback scan over the whole
+//    concatenation with the segmented operator (a flag restarts the
+//    recurrence at each segment head), writing per-segment results and
+//    checkpoints every PVJP_LINREC_CKPT_INTERVAL global elements.
+//  - Return sweep (seg_batch_vjp): one persistent launch.  Blocks take
+//    tickets from a queue holding first every scan tile in reverse order,
+//    then every sum-reduce tile.  For a scan tile the lin_o reversed scan
+//    needs no flag at all: the last element of each segment has no successor
+//    in its segment, so its c_i is 0, which cuts the carry exactly as the
+//    end of the array does.  The primal prefixes are recomputed from the
+//    checkpoint with the segmented operator.  A sum-reduce tile writes
+//    x_bar_i = y_bar[segment of i] (reduce(+)'s adjoint, Sec. 5.1.1).
+//
+// Segment heads of a tile come from an LDS bitmap built from the tile's first
+// segment (a table written once by pvjp_seg_prepare) and the segment offsets.
+#include <vector>
+
+#include "common.h"
+#include "prims.h"
+
+namespace pvjp {
+
+constexpr int kSegBlock = 256;
+constexpr int kSegCk = PVJP_LINREC_CKPT_INTERVAL;
+
+// Workspace: [LookbackHdr | tile states | tile_seg0 int32[ntiles+1] |
+//             offsets int64[nseg+1]]
+struct SegLayout {
+    size_t states, seg0, offs, total;
+    int64_t ntiles;
+};
+
+static SegLayout seg_layout(int64_t total, int64_t nseg, int ts) {
+    SegLayout L{};
+    L.ntiles = ceil_div(total > 0 ? total : 1, ts);
+    L.states = sizeof(LookbackHdr);
+    L.seg0 = L.states + align_up((size_t)L.ntiles * 64, 256);
+    L.offs = L.seg0 + align_up((size_t)(L.ntiles + 1) * 4, 256);
+    L.total = L.offs + align_up((size_t)(nseg + 1) * 8, 256);
+    return L;
+}
+
+static_assert(sizeof(TileState<SegLinRec<double>::S>) == 64 && sizeof(TileState<LinO<double>::S>) == 64 &&
+                  sizeof(TileState<SegLinRec<float>::S>) == 64 && sizeof(TileState<LinO<float>::S>) == 64,
+              "tile states of both sweeps share one 64-byte slot per tile");
+
+// Bitmap of segment heads over tile positions 0..TS (position TS is the first
+// element of the next tile): bit j set iff base + j starts a segment (or is
+// the end of the data).  Segments are non-empty, so a position holds at most
+// one head.
+template <int TS>
+__device__ __forceinline__ void build_heads(uint32_t* bits, const int32_t* __restrict__ seg0,
+                                            const int64_t* __restrict__ offs, int64_t nseg, int64_t tile,
+                                            int64_t base) {
+    constexpr int NW = (TS + 1 + 31) / 32;
+    for (int w = threadIdx.x; w < NW; w += kSegBlock) bits[w] = 0u;
+    __syncthreads();
+    const int64_t s_lo = seg0[tile], s_hi = seg0[tile + 1] + 1;
+    for (int64_t s = s_lo + threadIdx.x; s <= s_hi && s <= nseg; s += kSegBlock) {
+        const int64_t j = offs[s] - base;
+        if (j >= 0 && j <= TS) atomicOr(&bits[j >> 5], 1u << (j & 31));
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ bool bit_at(const uint32_t* bits, int j) { return (bits[j >> 5] >> (j & 31)) & 1u; }
+
+// ------------------------------------------------------------------ primal
+template <class T, int IPT>
+__global__ __launch_bounds__(kSegBlock) void seg_linrec_fwd_kernel(
+    const T* __restrict__ a, const T* __restrict__ b, int64_t total, int64_t nseg, const int64_t* __restrict__ offs,
+    const int32_t* __restrict__ seg0, T* __restrict__ A, T* __restrict__ B, T* __restrict__ ckpt, LookbackHdr* hdr,
+    TileState<typename SegLinRec<T>::S>* states, int64_t ntiles) {
+    using Op = SegLinRec<T>;
+    using S = typename Op::S;
+    constexpr int TS = kSegBlock * IPT;
+    __shared__ T lds[lds_elems<T, TS>()];
+    __shared__ S wtot[kSegBlock / kWave];
+    __shared__ uint32_t bits[(TS + 1 + 31) / 32];
+    __shared__ uint32_t s_tag, s_ticket;
+    __shared__ S s_prefix;
+
+    if (threadIdx.x == 0) {
+        lookback_begin(hdr, s_tag, s_ticket);
+        if (s_ticket >= ntiles) lookback_error(hdr, kErrTicket);
+    }
+    __syncthreads();
+    const uint32_t tag = s_tag;
+    if (s_ticket >= ntiles) {
+        lookback_end(hdr, tag);
+        return;
+    }
+    const int64_t tile = s_ticket;
+    const int64_t base = tile * TS;
+    const int cnt = (int)((total - base) < TS ? (total - base) : TS);
+    const int first = (int)threadIdx.x * IPT;
+
+    build_heads<TS>(bits, seg0, offs, nseg, tile, base);
+    T ra[IPT], rb[IPT];
+    load_blocked<T, kSegBlock, IPT>(a + base, cnt, ra, lds, T(1));
+    __syncthreads();
+    load_blocked<T, kSegBlock, IPT>(b + base, cnt, rb, lds, T(0));
+
+    S e[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) e[j] = S{ra[j], rb[j], (uint32_t)bit_at(bits, first + j), 0u};
+    S agg = e[0];
+#pragma unroll
+    for (int j = 1; j < IPT; ++j) agg = Op::comb(agg, e[j]);
+    S tot;
+    S excl = block_exclusive_scan<Op, kSegBlock, false>(agg, tot, wtot);
+    if (threadIdx.x < kWave) {
+        S prefix = Op::id();
+        if (tile == 0) {
+            if (threadIdx.x == 0) publish(&states[tile], tot, kInc, tag);
+        } else {
+            if (threadIdx.x == 0) publish(&states[tile], tot, kAgg, tag);
+            prefix = lookback<Op, false>(states, tile, ntiles, tag, hdr);
+            if (threadIdx.x == 0) publish(&states[tile], Op::comb(prefix, tot), kInc, tag);
+        }
+        if (threadIdx.x == 0) s_prefix = prefix;
+    }
+    __syncthreads();
+    S run = Op::comb(s_prefix, excl);
+    if (ckpt != nullptr && (first % kSegCk) == 0 && first < cnt) {
+        const int64_t c = (base + first) / kSegCk;
+        ckpt[2 * c] = run.a;
+        ckpt[2 * c + 1] = run.b;
+    }
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        run = Op::comb(run, e[j]);
+        ra[j] = run.a;
+        rb[j] = run.b;
+    }
+    if (A != nullptr) {
+        store_blocked<T, kSegBlock, IPT, false>(A + base, cnt, ra, lds);
+        store_blocked<T, kSegBlock, IPT, false>(B + base, cnt, rb, lds);
+    }
+    lookback_end(hdr, tag);
+}
+
+// ----------------------------------------------------------- return sweep
+template <class T, int IPT, bool ACC>
+__device__ __forceinline__ void seg_scan_vjp_tile(const T* __restrict__ a, const T* __restrict__ b,
+                                                  const T* __restrict__ ya, const T* __restrict__ yb,
+                                                  int64_t total, const T* __restrict__ ckpt, T* __restrict__ abar,
+                                                  T* __restrict__ bbar, LookbackHdr* hdr,
+                                                  TileState<typename LinO<T>::S>* states, int64_t ntiles,
+                                                  int64_t tile, uint32_t tag, T* lds, const uint32_t* bits,
+                                                  typename SegLinRec<T>::S* wtot_p, typename LinO<T>::S* wtot_l,
+                                                  typename LinO<T>::S* s_suffix) {
+    using P = SegLinRec<T>;
+    using L = LinO<T>;
+    using PS = typename P::S;
+    using LS = typename L::S;
+    constexpr int TS = kSegBlock * IPT;
+    const int64_t base = tile * TS;
+    const int cnt = (int)((total - base) < TS ? (total - base) : TS);
+    const int first = (int)threadIdx.x * IPT;
+
+    T ra[IPT], rc[IPT];
+    load_blocked<T, kSegBlock, IPT>(a + base, cnt, ra, lds, T(1));
+    {
+        T nxt;
+        if ((int)threadIdx.x < kSegBlock - 1)
+            nxt = lds[lds_pad<T>(first + IPT)];
+        else
+            nxt = (base + TS < total) ? a[base + TS] : T(1);
+#pragma unroll
+        for (int j = 0; j < IPT - 1; ++j) rc[j] = ra[j + 1];
+        rc[IPT - 1] = nxt;
+    }
+    T rb[IPT], rya[IPT], ryb[IPT];
+    __syncthreads();
+    load_blocked<T, kSegBlock, IPT>(b + base, cnt, rb, lds, T(0));
+    __syncthreads();
+    load_blocked<T, kSegBlock, IPT>(ya + base, cnt, rya, lds, T(0));
+    __syncthreads();
+    load_blocked<T, kSegBlock, IPT>(yb + base, cnt, ryb, lds, T(0));
+
+    // 1. primal prefixes (A_{i-1}, B_{i-1}) within each segment
+    T pA[IPT], pB[IPT];
+    {
+        PS e[IPT];
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) e[j] = PS{ra[j], rb[j], (uint32_t)bit_at(bits, first + j), 0u};
+        PS agg = e[0];
+#pragma unroll
+        for (int j = 1; j < IPT; ++j) agg = P::comb(agg, e[j]);
+        PS tot;
+        PS excl = block_exclusive_scan<P, kSegBlock, false>(agg, tot, wtot_p);
+        const int64_t c = base / kSegCk;
+        PS run = P::comb(PS{ckpt[2 * c], ckpt[2 * c + 1], 0u, 0u}, excl);
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            const bool head = e[j].f != 0u;
+            pA[j] = head ? T(1) : run.a;
+            pB[j] = head ? T(0) : run.b;
+            run = P::comb(run, e[j]);
+        }
+    }
+    // 2. lin_o elements: c_i = a_{i+1}, or 0 when i ends its segment
+    LS e[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const bool last = bit_at(bits, first + j + 1);
+        e[j] = LS{last ? T(0) : rc[j], rya[j], ryb[j]};
+    }
+    // 3. reversed scan with lookback over the tiles to the right
+    LS agg = L::id();
+#pragma unroll
+    for (int j = IPT - 1; j >= 0; --j) agg = L::comb(agg, e[j]);
+    LS tot;
+    LS excl = block_exclusive_scan<L, kSegBlock, true>(agg, tot, wtot_l);
+    if (threadIdx.x < kWave) {
+        LS suffix = L::id();
+        if (tile == ntiles - 1) {
+            if (threadIdx.x == 0) publish(&states[tile], tot, kInc, tag);
+        } else {
+            if (threadIdx.x == 0) publish(&states[tile], tot, kAgg, tag);
+            suffix = lookback<L, true>(states, tile, ntiles, tag, hdr);
+            if (threadIdx.x == 0) publish(&states[tile], L::comb(suffix, tot), kInc, tag);
+        }
+        if (threadIdx.x == 0) *s_suffix = suffix;
+    }
+    __syncthreads();
+    // 4. input adjoints
+    LS run = L::comb(*s_suffix, excl);
+#pragma unroll
+    for (int j = IPT - 1; j >= 0; --j) {
+        run = L::comb(run, e[j]);
+        ra[j] = pA[j] * run.dA + pB[j] * run.dB;
+        rb[j] = run.dB;
+    }
+    store_blocked<T, kSegBlock, IPT, ACC>(abar + base, cnt, ra, lds);
+    store_blocked<T, kSegBlock, IPT, ACC>(bbar + base, cnt, rb, lds);
+}
+
+template <class T, int IPT, bool ACC>
+__device__ __forceinline__ void seg_sum_vjp_tile(int64_t total, const int32_t* __restrict__ seg0,
+                                                 const T* __restrict__ ybar, T* __restrict__ xbar, int64_t tile,
+                                                 const uint32_t* bits, T* lds, IntSum::S* wtot_i) {
+    constexpr int TS = kSegBlock * IPT;
+    const int64_t base = tile * TS;
+    const int cnt = (int)((total - base) < TS ? (total - base) : TS);
+    const int first = (int)threadIdx.x * IPT;
+    // The segment of tile position j is seg0[tile] plus the number of heads at
+    // positions 1..j: a block exclusive scan of per-thread head counts, then a
+    // walk over the thread's own items.
+    int mine = 0;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) mine += (first + j > 0 && bit_at(bits, first + j)) ? 1 : 0;
+    IntSum::S tot;
+    int seg = seg0[tile] + block_exclusive_scan<IntSum, kSegBlock, false>(IntSum::S{mine}, tot, wtot_i).v;
+    T out[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        if (first + j > 0 && bit_at(bits, first + j)) ++seg;
+        out[j] = (first + j < cnt) ? ybar[seg] : T(0);
+    }
+    store_blocked<T, kSegBlock, IPT, ACC>(xbar + base, cnt, out, lds);
+}
+
+template <class T, int IPT, bool ACC>
+__global__ __launch_bounds__(kSegBlock) void seg_batch_vjp_kernel(
+    const T* __restrict__ a, const T* __restrict__ b, const T* __restrict__ ya, const T* __restrict__ yb,
+    int64_t total, int64_t nseg, const int64_t* __restrict__ offs, const int32_t* __restrict__ seg0,
+    const T* __restrict__ ckpt, T* __restrict__ abar, T* __restrict__ bbar, const T* __restrict__ sum_ybar,
+    T* __restrict__ sum_xbar, LookbackHdr* hdr, TileState<typename LinO<T>::S>* states, int64_t ntiles,
+    int64_t nscan, int64_t nsum) {
+    constexpr int TS = kSegBlock * IPT;
+    __shared__ T lds[lds_elems<T, TS>()];
+    __shared__ typename SegLinRec<T>::S wtot_p[kSegBlock / kWave];
+    __shared__ typename LinO<T>::S wtot_l[kSegBlock / kWave];
+    __shared__ IntSum::S wtot_i[kSegBlock / kWave];
+    __shared__ typename LinO<T>::S s_suffix;
+    __shared__ uint32_t bits[(TS + 1 + 31) / 32];
+    __shared__ uint32_t s_tag, s_ticket;
+
+    if (threadIdx.x == 0) lookback_begin(hdr, s_tag, s_ticket);
+    __syncthreads();
+    const uint32_t tag = s_tag;
+    // Queue: items [0, nscan) are the scan tiles in reverse order, items
+    // [nscan, nscan + nsum) the sum tiles.  A block only waits (in the
+    // lookback) on scan items dequeued before its own, which running blocks
+    // hold, so the loop always drains.
+    while (true) {
+        const int64_t item = s_ticket;
+        if (item >= nscan + nsum) break;
+        if (item < nscan) {
+            const int64_t tile = ntiles - 1 - item;  // reverse order inside the scan part
+            build_heads<TS>(bits, seg0, offs, nseg, tile, tile * TS);
+            seg_scan_vjp_tile<T, IPT, ACC>(a, b, ya, yb, total, ckpt, abar, bbar, hdr, states, ntiles, tile, tag, lds,
+                                           bits, wtot_p, wtot_l, &s_suffix);
+        } else {
+            const int64_t tile = item - nscan;
+            build_heads<TS>(bits, seg0, offs, nseg, tile, tile * TS);
+            seg_sum_vjp_tile<T, IPT, ACC>(total, seg0, sum_ybar, sum_xbar, tile, bits, lds, wtot_i);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0)
+            s_ticket = __hip_atomic_fetch_add(&hdr->ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+    }
+    lookback_end(hdr, tag);
+}
+
+// ------------------------------------------------------------------ host
+static bool valid_tile(int ts) { return ts == 1024 || ts == 2048 || ts == 4096; }
+
+template <class T, int IPT>
+static void launch_fwd(const void* a, const void* b, int64_t total, int64_t nseg, void* A, void* B, void* ckpt,
+                       char* ws, const SegLayout& L, hipStream_t st) {
+    hipLaunchKernelGGL((seg_linrec_fwd_kernel<T, IPT>), dim3((unsigned)L.ntiles), dim3(kSegBlock), 0, st,
+                       (const T*)a, (const T*)b, total, nseg, (const int64_t*)(ws + L.offs),
+                       (const int32_t*)(ws + L.seg0), (T*)A, (T*)B, (T*)ckpt, (LookbackHdr*)ws,
+                       (TileState<typename SegLinRec<T>::S>*)(ws + L.states), L.ntiles);
+}
+
+template <class T, int IPT, bool ACC>
+static void launch_batch(const void* a, const void* b, const void* ya, const void* yb, int64_t total, int64_t nseg,
+                         const void* ckpt, void* abar, void* bbar, const void* sy, void* sx, int grid, char* ws,
+                         const SegLayout& L, hipStream_t st) {
+    hipLaunchKernelGGL((seg_batch_vjp_kernel<T, IPT, ACC>), dim3((unsigned)grid), dim3(kSegBlock), 0, st, (const T*)a,
+                       (const T*)b, (const T*)ya, (const T*)yb, total, nseg, (const int64_t*)(ws + L.offs),
+                       (const int32_t*)(ws + L.seg0), (const T*)ckpt, (T*)abar, (T*)bbar, (const T*)sy, (T*)sx,
+                       (LookbackHdr*)ws, (TileState<typename LinO<T>::S>*)(ws + L.states), L.ntiles,
+                       a ? L.ntiles : 0, sy ? L.ntiles : 0);
+}
+
+template <class T, bool ACC>
+static void dispatch_batch(int ts, const void* a, const void* b, const void* ya, const void* yb, int64_t total,
+                           int64_t nseg, const void* ckpt, void* abar, void* bbar, const void* sy, void* sx, int grid,
+                           char* ws, const SegLayout& L, hipStream_t st) {
+    if (ts == 1024)
+        launch_batch<T, 1024 / kSegBlock, ACC>(a, b, ya, yb, total, nseg, ckpt, abar, bbar, sy, sx, grid, ws, L, st);
+    else if (ts == 2048)
+        launch_batch<T, 2048 / kSegBlock, ACC>(a, b, ya, yb, total, nseg, ckpt, abar, bbar, sy, sx, grid, ws, L, st);
+    else
+        launch_batch<T, 4096 / kSegBlock, ACC>(a, b, ya, yb, total, nseg, ckpt, abar, bbar, sy, sx, grid, ws, L, st);
+}
+
+}  // namespace pvjp
+
+using namespace pvjp;
+
+extern "C" size_t pvjp_seg_ws_bytes(int64_t total, int64_t nseg, int tile_elems) {
+    if (total < 1 || nseg < 1 || !valid_tile(tile_elems)) return 0;
+    return seg_layout(total, nseg, tile_elems).total;
+}
+
+extern "C" pvjp_status pvjp_seg_prepare(const int64_t* host_offsets, int64_t nseg, int tile_elems, void* ws,
+                                        size_t ws_bytes, void* stream) {
+    clear_error();
+    PVJP_REQUIRE(host_offsets != nullptr && nseg >= 1, "pvjp_seg_prepare: need host offsets of nseg >= 1 segments");
+    PVJP_REQUIRE(valid_tile(tile_elems), "pvjp_seg_prepare: tile_elems must be 1024, 2048 or 4096");
+    PVJP_REQUIRE(host_offsets[0] == 0, "pvjp_seg_prepare: offsets[0] must be 0");
+    for (int64_t s = 0; s < nseg; ++s)
+        PVJP_REQUIRE(host_offsets[s + 1] > host_offsets[s], "pvjp_seg_prepare: segment %lld is empty or offsets decrease",
+                     (long long)s);
+    const int64_t total = host_offsets[nseg];
+    PVJP_REQUIRE(total <= ((int64_t)1 << 40), "pvjp_seg_prepare: total length out of range");
+    PVJP_REQUIRE(ws != nullptr && aligned(ws, 256), "pvjp_seg_prepare: ws must be non-NULL and 256-byte aligned");
+    const SegLayout L = seg_layout(total, nseg, tile_elems);
+    if (ws_bytes < L.total) {
+        set_error("pvjp_seg_prepare: workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+        return PVJP_ENOMEM;
+    }
+    std::vector<int32_t> seg0((size_t)L.ntiles + 1);
+    int64_t s = 0;
+    for (int64_t t = 0; t < L.ntiles; ++t) {
+        const int64_t base = t * tile_elems;
+        while (host_offsets[s + 1] <= base) ++s;
+        seg0[(size_t)t] = (int32_t)s;
+    }
+    seg0[(size_t)L.ntiles] = (int32_t)nseg;
+    char* w = reinterpret_cast<char*>(ws);
+    hipStream_t st = as_stream(stream);
+    if (hipMemcpyAsync(w + L.seg0, seg0.data(), seg0.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(w + L.offs, host_offsets, (size_t)(nseg + 1) * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        set_error("pvjp_seg_prepare: uploading the segment tables failed");
+        return PVJP_EDEVICE;
+    }
+    return PVJP_OK;
+}
+
+extern "C" pvjp_status pvjp_seg_linrec_scan(pvjp_dtype dtype, const void* a, const void* b, int64_t total, int64_t nseg,
+                                            int tile_elems, void* A, void* B, void* ckpt, void* ws, size_t ws_bytes,
+                                            void* stream) {
+    clear_error();
+    PVJP_REQUIRE(valid_dtype(dtype), "pvjp_seg_linrec_scan: unknown dtype %d", (int)dtype);
+    PVJP_REQUIRE(total >= 1 && nseg >= 1, "pvjp_seg_linrec_scan: total and nseg must be >= 1");
+    PVJP_REQUIRE(valid_tile(tile_elems), "pvjp_seg_linrec_scan: tile_elems must be 1024, 2048 or 4096");
+    PVJP_REQUIRE(a && b, "pvjp_seg_linrec_scan: a and b must be non-NULL");
+    PVJP_REQUIRE((A == nullptr) == (B == nullptr) && (A || ckpt), "pvjp_seg_linrec_scan: need A and B, or ckpt");
+    PVJP_REQUIRE(ws != nullptr && aligned(ws, 256), "pvjp_seg_linrec_scan: ws must be non-NULL and 256-byte aligned");
+    const SegLayout L = seg_layout(total, nseg, tile_elems);
+    if (ws_bytes < L.total) {
+        set_error("pvjp_seg_linrec_scan: workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+        return PVJP_ENOMEM;
+    }
+    char* w = reinterpret_cast<char*>(ws);
+    hipStream_t st = as_stream(stream);
+    if (dtype == PVJP_F64) {
+        if (tile_elems == 1024) launch_fwd<double, 4>(a, b, total, nseg, A, B, ckpt, w, L, st);
+        else if (tile_elems == 2048) launch_fwd<double, 8>(a, b, total, nseg, A, B, ckpt, w, L, st);
+        else launch_fwd<double, 16>(a, b, total, nseg, A, B, ckpt, w, L, st);
+    } else {
+        if (tile_elems == 1024) launch_fwd<float, 4>(a, b, total, nseg, A, B, ckpt, w, L, st);
+        else if (tile_elems == 2048) launch_fwd<float, 8>(a, b, total, nseg, A, B, ckpt, w, L, st);
+        else launch_fwd<float, 16>(a, b, total, nseg, A, B, ckpt, w, L, st);
+    }
+    PVJP_LAUNCHED("pvjp_seg_linrec_scan");
+    return PVJP_OK;
+}
+
+extern "C" pvjp_status pvjp_seg_batch_vjp(pvjp_dtype dtype, const void* a, const void* b, const void* yA_bar,
+                                          const void* yB_bar, int64_t total, int64_t nseg, int tile_elems,
+                                          const void* ckpt, void* a_bar, void* b_bar, const void* sum_ybar,
+                                          void* sum_xbar, int accumulate, int grid_blocks, void* ws, size_t ws_bytes,
+                                          void* stream) {
+    clear_error();
+    PVJP_REQUIRE(valid_dtype(dtype), "pvjp_seg_batch_vjp: unknown dtype %d", (int)dtype);
+    PVJP_REQUIRE(total >= 1 && nseg >= 1, "pvjp_seg_batch_vjp: total and nseg must be >= 1");
+    PVJP_REQUIRE(valid_tile(tile_elems), "pvjp_seg_batch_vjp: tile_elems must be 1024, 2048 or 4096");
+    const bool scan = a != nullptr;
+    PVJP_REQUIRE(!scan || (b && yA_bar && yB_bar && ckpt && a_bar && b_bar),
+                 "pvjp_seg_batch_vjp: the scan part needs b, yA_bar, yB_bar, ckpt, a_bar and b_bar");
+    PVJP_REQUIRE((sum_ybar == nullptr) == (sum_xbar == nullptr), "pvjp_seg_batch_vjp: sum_ybar and sum_xbar go together");
+    PVJP_REQUIRE(scan || sum_ybar, "pvjp_seg_batch_vjp: nothing to compute");
+    PVJP_REQUIRE(grid_blocks >= 1 && grid_blocks <= 65536, "pvjp_seg_batch_vjp: grid_blocks out of range [1, 65536]");
+    PVJP_REQUIRE(ws != nullptr && aligned(ws, 256), "pvjp_seg_batch_vjp: ws must be non-NULL and 256-byte aligned");
+    const SegLayout L = seg_layout(total, nseg, tile_elems);
+    if (ws_bytes < L.total) {
+        set_error("pvjp_seg_batch_vjp: workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+        return PVJP_ENOMEM;
+    }
+    char* w = reinterpret_cast<char*>(ws);
+    hipStream_t st = as_stream(stream);
+    if (dtype == PVJP_F64) {
+        if (accumulate)
+            dispatch_batch<double, true>(tile_elems, a, b, yA_bar, yB_bar, total, nseg, ckpt, a_bar, b_bar, sum_ybar,
+                                         sum_xbar, grid_blocks, w, L, st);
+        else
+            dispatch_batch<double, false>(tile_elems, a, b, yA_bar, yB_bar, total, nseg, ckpt, a_bar, b_bar, sum_ybar,
+                                          sum_xbar, grid_blocks, w, L, st);
+    } else {
+        if (accumulate)
+            dispatch_batch<float, true>(tile_elems, a, b, yA_bar, yB_bar, total, nseg, ckpt, a_bar, b_bar, sum_ybar,
+                                        sum_xbar, grid_blocks, w, L, st);
+        else
+            dispatch_batch<float, false>(tile_elems, a, b, yA_bar, yB_bar, total, nseg, ckpt, a_bar, b_bar, sum_ybar,
+                                         sum_xbar, grid_blocks, w, L, st);
+    }
+    PVJP_LAUNCHED("pvjp_seg_batch_vjp");
+    return PVJP_OK;
+}
