@@ -1,0 +1,149 @@
+"""torch.autograd.Function wrappers: each operator's primal and VJP kernels as
+one differentiable op.
+
+Forward saves only the inputs and the small auxiliary results the return
+sweep needs (scan checkpoints, argmax indices, zero counts and non-zero
+products, histogram winners, scatter's overwritten values, per-point LSE);
+never a tape of intermediates.  Backward calls the library's VJP kernel.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import ops
+
+
+class LinRecScan(torch.autograd.Function):
+    """(A, B) = inclusive scan of (a, b) under (a1,b1)(+)(a2,b2) = (a2 a1, a2 b1 + b2)."""
+
+    @staticmethod
+    def forward(ctx, a, b):
+        a, b = a.contiguous(), b.contiguous()
+        A, B, ck = ops.linrec_scan(a, b)
+        ctx.save_for_backward(a, b, ck)
+        return A, B
+
+    @staticmethod
+    def backward(ctx, gA, gB):
+        a, b, ck = ctx.saved_tensors
+        gA = torch.zeros_like(a) if gA is None else gA.contiguous()
+        gB = torch.zeros_like(b) if gB is None else gB.contiguous()
+        ab, bb = ops.linrec_scan_vjp(a, b, gA, gB, ckpt=ck)
+        return ab, bb
+
+
+class Reduce(torch.autograd.Function):
+    """y = reduce(op) x for op in add, mul, min, max (Sec. 5.1.1 adjoints)."""
+
+    @staticmethod
+    def forward(ctx, x, op):
+        x = x.contiguous()
+        y, aux = ops.reduce(op, x)
+        ctx.op = op
+        ctx.aux_keys = tuple(aux)
+        ctx.save_for_backward(x, *aux.values())
+        return y.reshape(())
+
+    @staticmethod
+    def backward(ctx, gy):
+        x, *vals = ctx.saved_tensors
+        aux = dict(zip(ctx.aux_keys, vals))
+        xb = ops.reduce_vjp(ctx.op, x, aux, gy.reshape(1).contiguous())
+        return xb, None
+
+
+class ReduceByIndex(torch.autograd.Function):
+    """hs = reduce_by_index(op) over bins inds[i] of vs[i], m bins."""
+
+    @staticmethod
+    def forward(ctx, vs, inds, m, op):
+        vs, inds = vs.contiguous(), inds.contiguous()
+        hs, aux = ops.hist(op, inds, vs, m)
+        ctx.op, ctx.m = op, m
+        ctx.aux_keys = tuple(aux)
+        ctx.save_for_backward(vs, inds, *aux.values())
+        return hs
+
+    @staticmethod
+    def backward(ctx, ghs):
+        vs, inds, *vals = ctx.saved_tensors
+        aux = dict(zip(ctx.aux_keys, vals))
+        vb = ops.hist_vjp(ctx.op, inds, vs if ctx.op == "mul" else None, ctx.m, aux, ghs.contiguous(),
+                          n=vs.numel())
+        return vb, None, None, None
+
+
+class Scatter(torch.autograd.Function):
+    """ys = scatter(xs, is, vs) out of place (xs is copied first, so autograd
+    sees a pure function); is must hold no duplicates."""
+
+    @staticmethod
+    def forward(ctx, xs, is_, vs):
+        ys = xs.contiguous().clone()
+        ops.scatter_(ys, is_.contiguous(), vs.contiguous(), save=False)
+        ctx.save_for_backward(is_)
+        return ys
+
+    @staticmethod
+    def backward(ctx, gys):
+        (is_,) = ctx.saved_tensors
+        xb = gys.contiguous().clone()
+        vb = ops.scatter_vjp_(xb, is_)
+        return xb, None, vb
+
+
+class Map(torch.autograd.Function):
+    """y = f(x) elementwise, f in square, exp, log, sin, tanh."""
+
+    @staticmethod
+    def forward(ctx, x, fn):
+        x = x.contiguous()
+        ctx.fn = fn
+        ctx.save_for_backward(x)
+        return ops.map_(fn, x)
+
+    @staticmethod
+    def backward(ctx, gy):
+        (x,) = ctx.saved_tensors
+        return ops.map_vjp(ctx.fn, x, gy.contiguous()), None
+
+
+class GMMLogLik(torch.autograd.Function):
+    """Gaussian-mixture log-likelihood (FP32 parameters, FP64 result)."""
+
+    @staticmethod
+    def forward(ctx, X, alpha, mu, q, l):
+        args = [t.contiguous() for t in (X, alpha, mu, q, l)]
+        ll, lse = ops.gmm_objective(*args)
+        ctx.save_for_backward(*args, lse)
+        return ll.reshape(())
+
+    @staticmethod
+    def backward(ctx, g):
+        X, alpha, mu, q, l, lse = ctx.saved_tensors
+        ab, mb, qb, lb = ops.gmm_vjp(X, alpha, mu, q, l, lse=lse, ell_bar=float(g))
+        return None, ab, mb, qb, lb
+
+
+def linrec_scan(a, b):
+    return LinRecScan.apply(a, b)
+
+
+def reduce(x, op="add"):
+    return Reduce.apply(x, op)
+
+
+def reduce_by_index(vs, inds, m, op="add"):
+    return ReduceByIndex.apply(vs, inds, m, op)
+
+
+def scatter(xs, is_, vs):
+    return Scatter.apply(xs, is_, vs)
+
+
+def map(x, fn):  # noqa: A001 - the operator's name
+    return Map.apply(x, fn)
+
+
+def gmm_loglik(X, alpha, mu, q, l):
+    return GMMLogLik.apply(X, alpha, mu, q, l)
