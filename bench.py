@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 21, help="elements per instance for the CPU oracle")
+    ap.add_argument("--skip", default="", help="comma list of extra workloads to skip: scan,gmm,batch,serve")
+    ap.add_argument("--serve-seconds", type=float, default=4.0, help="measured seconds of the serving trace")
     return ap.parse_args()
 
 
@@ -242,6 +244,22 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.cpu_sample, vs_np, inst, xs_np, is_np, sv_np, yb_np)
 
+    # Free the histogram/scatter inputs before the other workloads.
+    del inst, vs, xs, is_, sv, ysb, calls
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    extra = {}
+    for name, fn in (("scan", bench_scan), ("gmm", bench_gmm), ("batch", bench_batch), ("serve", bench_serve)):
+        if name in args.skip:
+            continue
+        try:
+            log(f"extra: {name}")
+            extra[name] = fn(args)
+        except Exception as e:  # report, keep the main line
+            extra[name] = {"error": f"{type(e).__name__}: {e}"}
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+
     out = {
         "metric": METRIC,
         "value": round(elems_per_step / (ms_per_step * 1e-3), 1),
@@ -267,8 +285,150 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "detail": detail,
+        "other_workloads": extra,
     }
+    if "serve" in extra and "p50_ms" in extra["serve"]:
+        out["served_latency"] = {"p50_ms": extra["serve"]["p50_ms"], "p99_ms": extra["serve"]["p99_ms"]}
     print(json.dumps(out), flush=True)
+
+
+def _events_ms(fn, reps, warm=2):
+    import torch
+
+    for _ in range(warm):
+        fn()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps
+
+
+def bench_scan(args):
+    """Linear-recurrence scan, FP64: the latency-bound n = 65,536 instance and
+    an HBM-bound n = 2^26 instance (primal 32 B/elem, VJP with checkpoint
+    48 B/elem)."""
+    import torch
+
+    from paper_2202_10297_amd import ops, workloads
+
+    res = {}
+    for n in (65536, 1 << 26):
+        a, b, ya, yb = (torch.from_numpy(x).cuda() for x in workloads.linrec(n, "f64", seed=0))
+        _, _, ck = ops.linrec_scan(a, b)
+        A, B = torch.empty_like(a), torch.empty_like(b)
+        ab, bb = torch.empty_like(a), torch.empty_like(b)
+        reps = 200 if n < 1 << 20 else 10
+        tp = _events_ms(lambda: ops.linrec_scan(a, b), reps)
+        tv = _events_ms(lambda: ops.linrec_scan_vjp(a, b, ya, yb, ckpt=ck, a_bar=ab, b_bar=bb), reps)
+        res[f"n{n}"] = {"primal_us": round(tp * 1e3, 2), "vjp_us": round(tv * 1e3, 2),
+                        "grad_over_primal": round((tp + tv) / tp, 3),
+                        "vjp_elems_per_s": round(n / (tv * 1e-3), 1),
+                        "primal_GBps": round(32 * n / (tp * 1e-3) / 1e9, 1),
+                        "vjp_GBps": round(48 * n / (tv * 1e-3) / 1e9, 1)}
+        del a, b, ya, yb, ck, A, B, ab, bb
+    return res
+
+
+def bench_gmm(args):
+    """GMM N = 10^6, D = 64, K = 200 (FP32, FP64 LSE): objective and gradient.
+    Algorithmic flops: forward N K D (D+1) with the triangle of Q_k used,
+    gradient about twice that (recomputation + the contraction of G_k)."""
+    import torch
+
+    from paper_2202_10297_amd import ops, workloads
+
+    N, D, K = 1_000_000, 64, 200
+    P = [torch.from_numpy(x).cuda() for x in workloads.gmm(N, D, K, seed=0)]
+    _, lse = ops.gmm_objective(*P)
+    tf = _events_ms(lambda: ops.gmm_objective(*P), 5)
+    out = tuple(torch.empty_like(t) for t in P[1:])
+    tb = _events_ms(lambda: ops.gmm_vjp(*P, lse=lse, out=out), 5)
+    flop_f = N * K * D * (D + 1)
+    return {"objective_ms": round(tf, 3), "gradient_ms": round(tb, 3), "grad_over_primal": round((tf + tb) / tf, 3),
+            "objective_TFLOPs": round(flop_f / (tf * 1e-3) / 1e12, 1),
+            "gradient_TFLOPs": round(2 * flop_f / (tb * 1e-3) / 1e12, 1),
+            "vjp_points_per_s": round(N / (tb * 1e-3), 1)}
+
+
+def bench_batch(args):
+    """4,096 scan VJPs + 4,096 sum-reduce VJPs, lengths log-uniform in
+    [64, 2^20], FP32: one persistent launch (autotuned tile and grid, replayed
+    from a HIP graph) against one launch per instance."""
+    import torch
+
+    from paper_2202_10297_amd import batch, ops, workloads
+
+    lengths = workloads.segment_lengths(4096, 64, 1 << 20, seed=0)
+    total = int(lengths.sum())
+    g = workloads.rng(0)
+    dev = torch.device("cuda")
+    a = torch.from_numpy(g.uniform(0.5, 1.0, total).astype(np.float32)).to(dev)
+    b = torch.from_numpy(g.standard_normal(total, dtype=np.float32)).to(dev)
+    ya = torch.from_numpy(g.standard_normal(total, dtype=np.float32)).to(dev)
+    yb = torch.from_numpy(g.standard_normal(total, dtype=np.float32)).to(dev)
+    sy = torch.from_numpy(g.standard_normal(4096).astype(np.float32)).to(dev)
+    ab, bb, sx = torch.empty_like(a), torch.empty_like(a), torch.empty_like(a)
+    t0 = time.time()
+    probe = batch.SegPlan(lengths, torch.float32)
+    _, _, ck0 = probe.scan(a, b, outputs=False)
+    tile, grid = __import__("paper_2202_10297_amd.tune", fromlist=["x"]).seg_config(
+        probe, dict(a=a, b=b, yA_bar=ya, yB_bar=yb, a_bar=ab, b_bar=bb, sum_ybar=sy, sum_xbar=sx))
+    tune_s = time.time() - t0
+    plan = batch.SegPlan(lengths, torch.float32, tile=tile, grid=grid)
+    _, _, ck = plan.scan(a, b, outputs=False)
+    kw = dict(a=a, b=b, yA_bar=ya, yB_bar=yb, ckpt=ck, a_bar=ab, b_bar=bb, sum_ybar=sy, sum_xbar=sx)
+    t_eager = _events_ms(lambda: plan.vjp(**kw), 5)
+    plan.capture(**kw)
+    t_graph = _events_ms(plan.replay, 5)
+    # one launch per instance
+    off = plan.offsets
+    cks = []
+    for s in range(4096):
+        lo, hi = int(off[s]), int(off[s + 1])
+        cks.append(ops.linrec_scan(a[lo:hi], b[lo:hi])[2])
+    aux = {}
+
+    def per_instance():
+        for s in range(4096):
+            lo, hi = int(off[s]), int(off[s + 1])
+            ops.linrec_scan_vjp(a[lo:hi], b[lo:hi], ya[lo:hi], yb[lo:hi], ckpt=cks[s], a_bar=ab[lo:hi],
+                                b_bar=bb[lo:hi])
+            ops.reduce_vjp("add", a[lo:hi], aux, sy[s:s + 1], x_bar=sx[lo:hi])
+
+    t_each = _events_ms(per_instance, 2, warm=1)
+    alg = 24 * total + 4 * total
+    return {"segments": 4096, "elements_per_set": total, "tile_elems": tile, "grid_blocks": grid,
+            "tune_s": round(tune_s, 2), "batched_ms": round(t_eager, 3), "graph_replay_ms": round(t_graph, 3),
+            "per_instance_ms": round(t_each, 3), "speedup_vs_per_instance": round(t_each / t_graph, 2),
+            "alg_GBps": round(alg / (t_graph * 1e-3) / 1e9, 1),
+            "vjp_elems_per_s": round(2 * total / (t_graph * 1e-3), 1)}
+
+
+def bench_serve(args):
+    """Poisson arrivals at 2,000 requests/s mixing scan VJPs (n in [1e3, 1e7]),
+    + histogram VJPs (n in [1e4, 1e7], 2^12..2^18 bins, Zipf) and GMM gradients
+    (N in [1e3, 1e5], D = 32, K = 50) under a 64 GB budget; the same trace
+    served serially (one slot) for comparison."""
+    from paper_2202_10297_amd import serve
+
+    pool = serve.Pool(per_kind=24, seed=0)
+    warm = 1.0
+    trace = serve.make_trace(pool, rate=2000.0, duration=warm + args.serve_seconds, seed=0)
+    srv = serve.Server(pool, slots=8, budget_bytes=64 << 30)
+    stats, _ = srv.run(trace, warmup=warm)
+    serial = serve.Server(pool, slots=1, budget_bytes=64 << 30)
+    trace1 = serve.make_trace(pool, rate=2000.0, duration=warm + args.serve_seconds, seed=0)
+    s1, _ = serial.run(trace1, warmup=warm)
+    keep = lambda d: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
+    out = keep(stats)
+    out["serial_one_slot"] = keep({k: s1[k] for k in ("p50_ms", "p99_ms", "throughput_rps", "max_inflight")})
+    out["rate_rps"] = 2000.0
+    out["measured_s"] = args.serve_seconds
+    return out
 
 
 def cpu_baseline(ns, vs_np, inst, xs_np, is_np, sv_np, yb_np):

@@ -28,8 +28,9 @@ namespace pvjp {
 constexpr int kHistBlock = 256;
 constexpr int kHistLds = 64 * 1024;   // dynamic LDS per block
 constexpr int kCacheSlots = 4096;     // LDS cache slots when the bins do not fit
-constexpr int kHistMaxGrid = 512;     // 2 resident blocks per CU on 256 CUs
 constexpr int32_t kEmptyTag = -1;
+
+__device__ __forceinline__ int64_t ceil_div_dev(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 __device__ __forceinline__ uint32_t ord32(float v) {
     const uint32_t b = __float_as_uint(v == 0.0f ? 0.0f : v);  // -0 and +0 tie
@@ -94,10 +95,86 @@ __device__ __forceinline__ void acc_merge(uint64_t* g, int32_t* gz, uint64_t a, 
     }
 }
 
+// One element's update: into its LDS slot when the block owns the bin (always
+// in FULL mode), else straight into the global accumulator.
 template <class T, int OP, bool CACHE, bool COUNTS>
+__device__ __forceinline__ void hist_update(int32_t k, T v, int64_t i, int32_t m, int slots, uint64_t* sacc,
+                                            int32_t* stag, int32_t* scnt, int32_t* szc, uint64_t* gacc, int32_t* gz,
+                                            int32_t* gcount) {
+    if ((uint32_t)k >= (uint32_t)m) return;
+    int s;
+    bool local;
+    if (!CACHE) {
+        s = k;
+        local = true;
+    } else {
+        s = k & (slots - 1);
+        // A slot's tag goes from empty to a bin once and never changes
+        // again, so a plain read that sees a bin is final.
+        int32_t t = stag[s];
+        if (t == kEmptyTag) {
+            t = atomicCAS(&stag[s], kEmptyTag, k);
+            if (t == kEmptyTag) t = k;
+        }
+        local = (t == k);
+    }
+    if (local) {
+        acc_update<T, OP>(&sacc[s], OP == PVJP_MUL ? &szc[s] : nullptr, v, i);
+        if (COUNTS) atomicAdd(&scnt[s], 1);
+    } else {
+        acc_update<T, OP>(&gacc[k], OP == PVJP_MUL ? &gz[k] : nullptr, v, i);
+        if (COUNTS) atomicAdd(&gcount[k], 1);
+    }
+}
+
+// Four consecutive elements (one 16-byte load of indices).
+template <class T>
+struct Quad {
+    int4 k;
+    T v[4];
+};
+
+template <class T, bool VEC>
+__device__ __forceinline__ Quad<T> load_quad(const int32_t* __restrict__ inds, const T* __restrict__ vs, int64_t e,
+                                             int64_t hi) {
+    Quad<T> q;
+    if (VEC && e + 3 < hi) {
+        q.k = *reinterpret_cast<const int4*>(inds + e);
+        if (sizeof(T) == 4) {
+            const float4 f = *reinterpret_cast<const float4*>(vs + e);
+            q.v[0] = (T)f.x, q.v[1] = (T)f.y, q.v[2] = (T)f.z, q.v[3] = (T)f.w;
+        } else {
+            const double2 d0 = *reinterpret_cast<const double2*>(vs + e);
+            const double2 d1 = *reinterpret_cast<const double2*>(vs + e + 2);
+            q.v[0] = (T)d0.x, q.v[1] = (T)d0.y, q.v[2] = (T)d1.x, q.v[3] = (T)d1.y;
+        }
+    } else {
+        int kk[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const bool ok = e + u < hi;
+            kk[u] = ok ? inds[e + u] : -1;  // -1: out of range, skipped
+            q.v[u] = ok ? vs[e + u] : T(0);
+        }
+        q.k = make_int4(kk[0], kk[1], kk[2], kk[3]);
+    }
+    return q;
+}
+
+constexpr int kHistBatch = 4;  // quads per thread per batch: 16 elements in flight
+
+// Each block accumulates a contiguous chunk (a multiple of 4 * 256
+// elements) into its LDS sub-histogram.  Loads are 16-byte vectors, four per
+// thread per batch, and the next batch is loaded before the current batch's
+// atomics are issued: the in-order memory counter then never makes a wave
+// wait for its own atomics before it can use newly loaded data.
+// FULL mode (!CACHE) writes the block's sub-histogram to `part` for a
+// fixed-order merge; CACHE mode flushes its claimed slots with atomics.
+template <class T, int OP, bool CACHE, bool COUNTS, bool VEC>
 __global__ __launch_bounds__(kHistBlock) void hist_acc_kernel(
-    const int32_t* __restrict__ inds, const T* __restrict__ vs, int64_t n, int32_t m, int64_t chunk,
-    int slots, uint64_t* __restrict__ gacc, int32_t* __restrict__ gz, int32_t* __restrict__ gcount) {
+    const int32_t* __restrict__ inds, const T* __restrict__ vs, int64_t n, int32_t m, int64_t chunk, int slots,
+    uint64_t* __restrict__ gacc, int32_t* __restrict__ gz, int32_t* __restrict__ gcount, uint64_t* __restrict__ pacc,
+    int32_t* __restrict__ pz, int32_t* __restrict__ pcnt) {
     extern __shared__ uint64_t smem[];
     uint64_t* sacc = smem;                                       // [slots]
     int32_t* stag = reinterpret_cast<int32_t*>(sacc + slots);    // [slots] (CACHE)
@@ -114,41 +191,100 @@ __global__ __launch_bounds__(kHistBlock) void hist_acc_kernel(
 
     const int64_t lo = (int64_t)blockIdx.x * chunk;
     const int64_t hi = (lo + chunk < n) ? lo + chunk : n;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += kHistBlock) {
-        const int32_t k = inds[i];
-        if ((uint32_t)k >= (uint32_t)m) continue;
-        const T v = vs[i];
-        int s;
-        bool local;
-        if (!CACHE) {
-            s = k;
-            local = true;
-        } else {
-            s = k & (slots - 1);
-            // A slot's tag goes from empty to a bin once and never changes
-            // again, so a plain read that sees a bin is final.
-            int32_t t = stag[s];
-            if (t == kEmptyTag) {
-                t = atomicCAS(&stag[s], kEmptyTag, k);
-                if (t == kEmptyTag) t = k;
-            }
-            local = (t == k);
+    constexpr int64_t kStride = 4 * kHistBlock * kHistBatch;  // elements per block batch
+    Quad<T> cur[kHistBatch], nxt[kHistBatch];
+#pragma unroll
+    for (int u = 0; u < kHistBatch; ++u)
+        cur[u] = load_quad<T, VEC>(inds, vs, lo + 4 * ((int64_t)u * kHistBlock + threadIdx.x), hi);
+    for (int64_t base = lo; base < hi; base += kStride) {
+        const int64_t nb = base + kStride;
+        if (nb < hi) {
+#pragma unroll
+            for (int u = 0; u < kHistBatch; ++u)
+                nxt[u] = load_quad<T, VEC>(inds, vs, nb + 4 * ((int64_t)u * kHistBlock + threadIdx.x), hi);
         }
-        if (local) {
-            acc_update<T, OP>(&sacc[s], OP == PVJP_MUL ? &szc[s] : nullptr, v, i);
-            if (COUNTS) atomicAdd(&scnt[s], 1);
-        } else {
-            acc_update<T, OP>(&gacc[k], OP == PVJP_MUL ? &gz[k] : nullptr, v, i);
-            if (COUNTS) atomicAdd(&gcount[k], 1);
+#pragma unroll
+        for (int u = 0; u < kHistBatch; ++u) {
+            const int64_t e = base + 4 * ((int64_t)u * kHistBlock + threadIdx.x);
+            hist_update<T, OP, CACHE, COUNTS>(cur[u].k.x, cur[u].v[0], e, m, slots, sacc, stag, scnt, szc, gacc, gz, gcount);
+            hist_update<T, OP, CACHE, COUNTS>(cur[u].k.y, cur[u].v[1], e + 1, m, slots, sacc, stag, scnt, szc, gacc, gz, gcount);
+            hist_update<T, OP, CACHE, COUNTS>(cur[u].k.z, cur[u].v[2], e + 2, m, slots, sacc, stag, scnt, szc, gacc, gz, gcount);
+            hist_update<T, OP, CACHE, COUNTS>(cur[u].k.w, cur[u].v[3], e + 3, m, slots, sacc, stag, scnt, szc, gacc, gz, gcount);
         }
+#pragma unroll
+        for (int u = 0; u < kHistBatch; ++u) cur[u] = nxt[u];
     }
     __syncthreads();
 
+    if (!CACHE) {
+        const int64_t row = (int64_t)blockIdx.x * m;
+        for (int s = threadIdx.x; s < m; s += kHistBlock) {
+            pacc[row + s] = sacc[s];
+            if (OP == PVJP_MUL) pz[row + s] = szc[s];
+            if (COUNTS) pcnt[row + s] = scnt[s];
+        }
+        return;
+    }
     for (int s = threadIdx.x; s < slots; s += kHistBlock) {
-        const int32_t k = CACHE ? stag[s] : s;
+        const int32_t k = stag[s];
         if (k < 0 || k >= m) continue;
         acc_merge<OP>(&gacc[k], OP == PVJP_MUL ? &gz[k] : nullptr, sacc[s], OP == PVJP_MUL ? szc[s] : 0);
         if (COUNTS && scnt[s]) atomicAdd(&gcount[k], scnt[s]);
+    }
+}
+
+// Fixed-order merge of the per-block sub-histograms (FULL mode), in two
+// levels so that many waves share the work: level 1 folds slice j of the
+// per-block partials (blocks j*per .. (j+1)*per-1) for 64 bins per wave;
+// level 2 folds the slices in order.  Sums, products and maxima are formed in
+// FP64/u64, in the same order on every run.
+constexpr int kMergeSlices = 32;
+
+template <int OP>
+__device__ __forceinline__ void merge_fold(uint64_t& acc, int32_t& zz, int32_t& cc, uint64_t a, int32_t z, int32_t c) {
+    if (OP == PVJP_ADD) acc = (uint64_t)__double_as_longlong(__longlong_as_double((long long)acc) +
+                                                             __longlong_as_double((long long)a));
+    if (OP == PVJP_MUL) acc = (uint64_t)__double_as_longlong(__longlong_as_double((long long)acc) *
+                                                             __longlong_as_double((long long)a)), zz += z;
+    if (OP == PVJP_MIN || OP == PVJP_MAX) acc = a > acc ? a : acc;
+    cc += c;
+}
+
+template <int OP>
+__global__ __launch_bounds__(256) void hist_merge1_kernel(const uint64_t* __restrict__ pacc,
+                                                          const int32_t* __restrict__ pz,
+                                                          const int32_t* __restrict__ pcnt, int64_t nblocks, int32_t m,
+                                                          uint64_t* __restrict__ sacc, int32_t* __restrict__ sz,
+                                                          int32_t* __restrict__ scnt) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (k >= m) return;
+    const int64_t per = ceil_div_dev(nblocks, kMergeSlices);
+    const int64_t b0 = j * per, b1 = (b0 + per < nblocks) ? b0 + per : nblocks;
+    uint64_t acc = acc_identity<OP>();
+    int32_t zz = 0, cc = 0;
+    for (int64_t b = b0; b < b1; ++b)
+        merge_fold<OP>(acc, zz, cc, pacc[b * m + k], OP == PVJP_MUL ? pz[b * m + k] : 0, pcnt ? pcnt[b * m + k] : 0);
+    sacc[(int64_t)j * m + k] = acc;
+    if (OP == PVJP_MUL) sz[(int64_t)j * m + k] = zz;
+    if (pcnt) scnt[(int64_t)j * m + k] = cc;
+}
+
+template <int OP>
+__global__ __launch_bounds__(256) void hist_merge2_kernel(const uint64_t* __restrict__ sacc,
+                                                          const int32_t* __restrict__ sz,
+                                                          const int32_t* __restrict__ scnt, int32_t m,
+                                                          uint64_t* __restrict__ gacc, int32_t* __restrict__ gz,
+                                                          int32_t* __restrict__ gcount) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t acc = acc_identity<OP>();
+        int32_t zz = 0, cc = 0;
+        for (int j = 0; j < kMergeSlices; ++j)
+            merge_fold<OP>(acc, zz, cc, sacc[(int64_t)j * m + k], OP == PVJP_MUL ? sz[(int64_t)j * m + k] : 0,
+                           scnt ? scnt[(int64_t)j * m + k] : 0);
+        gacc[k] = acc;
+        if (OP == PVJP_MUL) gz[k] = zz;
+        if (gcount) gcount[k] = cc;
     }
 }
 
@@ -215,6 +351,57 @@ __global__ __launch_bounds__(256) void hist_vjp_add_kernel(const int32_t* __rest
     }
 }
 
+// 16-byte vector form of the gather: four indices per load, four adjoints
+// per store (pointers 16-byte aligned; the last n % 4 elements are done by
+// the first threads of block 0).
+template <class T, bool ACC>
+__global__ __launch_bounds__(256) void hist_vjp_add_vec_kernel(const int32_t* __restrict__ inds, int64_t n,
+                                                               int32_t m, const T* __restrict__ hsbar,
+                                                               T* __restrict__ vsbar) {
+    const int64_t nq = n >> 2;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += (int64_t)gridDim.x * blockDim.x) {
+        const int4 k = reinterpret_cast<const int4*>(inds)[q];
+        T g[4];
+        g[0] = ((uint32_t)k.x < (uint32_t)m) ? hsbar[k.x] : T(0);
+        g[1] = ((uint32_t)k.y < (uint32_t)m) ? hsbar[k.y] : T(0);
+        g[2] = ((uint32_t)k.z < (uint32_t)m) ? hsbar[k.z] : T(0);
+        g[3] = ((uint32_t)k.w < (uint32_t)m) ? hsbar[k.w] : T(0);
+        if (sizeof(T) == 4) {
+            float4* dst = reinterpret_cast<float4*>(vsbar) + q;
+            float4 o = make_float4((float)g[0], (float)g[1], (float)g[2], (float)g[3]);
+            if (ACC) {
+                const float4 c = *dst;
+                o.x += c.x, o.y += c.y, o.z += c.z, o.w += c.w;
+            }
+            *dst = o;
+        } else {
+            double2* dst = reinterpret_cast<double2*>(vsbar) + 2 * q;
+            double2 o0 = make_double2((double)g[0], (double)g[1]), o1 = make_double2((double)g[2], (double)g[3]);
+            if (ACC) {
+                const double2 c0 = dst[0], c1 = dst[1];
+                o0.x += c0.x, o0.y += c0.y, o1.x += c1.x, o1.y += c1.y;
+            }
+            dst[0] = o0;
+            dst[1] = o1;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x < (n & 3)) {
+        const int64_t i = (nq << 2) + threadIdx.x;
+        const int32_t k = inds[i];
+        const T g = ((uint32_t)k < (uint32_t)m) ? hsbar[k] : T(0);
+        vsbar[i] = ACC ? vsbar[i] + g : g;
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void fill_zero_vec_kernel(T* __restrict__ x, int64_t n) {
+    const int64_t nq = (int64_t)(n * sizeof(T)) >> 4;  // 16-byte words
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += (int64_t)gridDim.x * blockDim.x)
+        reinterpret_cast<int4*>(x)[q] = make_int4(0, 0, 0, 0);
+    const int64_t done = (nq << 4) / (int64_t)sizeof(T);
+    if (blockIdx.x == 0 && threadIdx.x < n - done) x[done + threadIdx.x] = T(0);
+}
+
 template <class T, bool ACC>
 __global__ __launch_bounds__(256) void hist_vjp_mul_kernel(const int32_t* __restrict__ inds,
                                                            const T* __restrict__ vs, int64_t n, int32_t m,
@@ -255,46 +442,112 @@ static size_t slot_bytes(int op, bool counts, bool cache) {
     return 8 + (counts ? 4 : 0) + (op == PVJP_MUL ? 4 : 0) + (cache ? 4 : 0);
 }
 
-static size_t hist_ws(int op, int64_t m) {
-    return align_up((size_t)m * 8, 256) + (op == PVJP_MUL ? align_up((size_t)m * 4, 256) : 0);
+constexpr int kCuCount = 256;         // MI355X compute units
+constexpr int kLdsPerCu = 160 * 1024;  // LDS bytes per CU on gfx950
+constexpr int64_t kMaxPartEntries = (int64_t)1 << 23;
+
+struct HistPlan {
+    bool cache;
+    int slots;
+    int64_t grid, chunk;
+    size_t lds;
+};
+
+// FULL mode when the m bins fit one block's LDS; then as many resident blocks
+// as LDS allows (up to 8 per CU), capped so the per-block partials stay
+// bounded.  CACHE mode otherwise, 3 blocks per CU.
+static HistPlan hist_plan(int op, int64_t n, int64_t m, bool counts) {
+    HistPlan P{};
+    const int full_slots = (int)(kHistLds / slot_bytes(op, counts, false));
+    P.cache = m > full_slots;
+    if (!P.cache) {
+        P.slots = (int)m;
+        P.lds = (size_t)m * slot_bytes(op, counts, false);
+    } else {
+        int slots = kCacheSlots;
+        while ((size_t)slots * slot_bytes(op, counts, true) > (size_t)kHistLds) slots >>= 1;
+        P.slots = slots;
+        P.lds = (size_t)slots * slot_bytes(op, counts, true);
+    }
+    int64_t per_cu = kLdsPerCu / (int64_t)(P.lds > 0 ? P.lds : 1);
+    if (per_cu > 8) per_cu = 8;
+    if (per_cu < 1) per_cu = 1;
+    int64_t g = kCuCount * per_cu;
+    if (!P.cache && g * m > kMaxPartEntries) g = kMaxPartEntries / m > 0 ? kMaxPartEntries / m : 1;
+    const int64_t quantum = 4 * kHistBlock;  // chunks are whole vector rows
+    int64_t want = ceil_div(n > 0 ? n : 1, (int64_t)4 * kHistBlock * kHistBatch);
+    if (g > want) g = want;
+    if (g < 1) g = 1;
+    P.chunk = ceil_div(ceil_div(n > 0 ? n : 1, g), quantum) * quantum;
+    P.grid = ceil_div(n > 0 ? n : 1, P.chunk);
+    return P;
+}
+
+// Covers both plans (with and without counts): the FULL/CACHE choice and the
+// grid depend on whether counts are requested.
+static size_t hist_ws(int op, int64_t n, int64_t m) {
+    size_t part = 0;
+    for (int counts = 0; counts < 2; ++counts) {
+        const HistPlan P = hist_plan(op, n, m, counts != 0);
+        if (!P.cache) {
+            // per-block partials and the merge slices: acc 8 + zeros 4 + counts 4
+            const size_t b = align_up((size_t)(P.grid + kMergeSlices) * m * 16, 256);
+            if (b > part) part = b;
+        }
+    }
+    return align_up((size_t)m * 8, 256) + (op == PVJP_MUL ? align_up((size_t)m * 4, 256) : 0) + part;
 }
 
 template <class T, int OP, bool CACHE, bool COUNTS>
-static void launch_acc(const int32_t* inds, const T* vs, int64_t n, int32_t m, int slots, uint64_t* gacc,
-                       int32_t* gz, int32_t* gcount, hipStream_t st) {
-    int64_t g = ceil_div(n, (int64_t)kHistBlock * 64);
-    if (g < 1) g = 1;
-    if (g > kHistMaxGrid) g = kHistMaxGrid;
-    const int64_t chunk = ceil_div(n, g);
-    const size_t lds = (size_t)slots * slot_bytes(OP, COUNTS, CACHE);
-    hipLaunchKernelGGL((hist_acc_kernel<T, OP, CACHE, COUNTS>), dim3((unsigned)g), dim3(kHistBlock), lds, st,
-                       inds, vs, n, m, chunk, slots, gacc, gz, gcount);
+static void launch_acc(const int32_t* inds, const T* vs, int64_t n, int32_t m, const HistPlan& P, uint64_t* gacc,
+                       int32_t* gz, int32_t* gcount, uint64_t* pacc, int32_t* pz, int32_t* pcnt, hipStream_t st) {
+    const bool vec = aligned(inds, 16) && aligned(vs, 16);
+    if (vec)
+        hipLaunchKernelGGL((hist_acc_kernel<T, OP, CACHE, COUNTS, true>), dim3((unsigned)P.grid), dim3(kHistBlock),
+                           P.lds, st, inds, vs, n, m, P.chunk, P.slots, gacc, gz, gcount, pacc, pz, pcnt);
+    else
+        hipLaunchKernelGGL((hist_acc_kernel<T, OP, CACHE, COUNTS, false>), dim3((unsigned)P.grid), dim3(kHistBlock),
+                           P.lds, st, inds, vs, n, m, P.chunk, P.slots, gacc, gz, gcount, pacc, pz, pcnt);
 }
 
 template <class T, int OP>
 static void run_hist(const int32_t* inds, const T* vs, int64_t n, int32_t m, T* hs, int32_t* winner, T* p,
                      int32_t* z, int32_t* count, void* ws, hipStream_t st) {
-    uint64_t* gacc = reinterpret_cast<uint64_t*>(ws);
-    int32_t* gz = OP == PVJP_MUL ? reinterpret_cast<int32_t*>(reinterpret_cast<char*>(ws) + align_up((size_t)m * 8, 256))
-                                 : nullptr;
+    char* w = reinterpret_cast<char*>(ws);
+    uint64_t* gacc = reinterpret_cast<uint64_t*>(w);
+    size_t off = align_up((size_t)m * 8, 256);
+    int32_t* gz = nullptr;
+    if (OP == PVJP_MUL) {
+        gz = reinterpret_cast<int32_t*>(w + off);
+        off += align_up((size_t)m * 4, 256);
+    }
+    const bool counts = count != nullptr;
+    const HistPlan P = hist_plan(OP, n, m, counts);
+    uint64_t* pacc = reinterpret_cast<uint64_t*>(w + off);
+    int32_t* pz = reinterpret_cast<int32_t*>(pacc + (size_t)P.grid * m);
+    int32_t* pcnt = pz + (size_t)P.grid * m;
+    uint64_t* macc = reinterpret_cast<uint64_t*>(pcnt + (size_t)P.grid * m);
+    int32_t* mz = reinterpret_cast<int32_t*>(macc + (size_t)kMergeSlices * m);
+    int32_t* mcnt = mz + (size_t)kMergeSlices * m;
     const bool f64minmax = sizeof(T) == 8 && (OP == PVJP_MIN || OP == PVJP_MAX);
     const unsigned gm = flat_grid(m, 256, 4);
-    hipLaunchKernelGGL(hist_init_kernel<OP>, dim3(gm), dim3(256), 0, st, gacc, gz, count,
-                       f64minmax ? winner : nullptr, m);
-    const bool counts = count != nullptr;
-    const int full_slots = (int)(kHistLds / slot_bytes(OP, counts, false));
-    if (m <= full_slots) {
+    if (P.cache || f64minmax)
+        hipLaunchKernelGGL(hist_init_kernel<OP>, dim3(gm), dim3(256), 0, st, gacc, gz, P.cache ? count : nullptr,
+                           f64minmax ? winner : nullptr, m);
+    if (P.cache) {
         if (counts)
-            launch_acc<T, OP, false, true>(inds, vs, n, m, m, gacc, gz, count, st);
+            launch_acc<T, OP, true, true>(inds, vs, n, m, P, gacc, gz, count, nullptr, nullptr, nullptr, st);
         else
-            launch_acc<T, OP, false, false>(inds, vs, n, m, m, gacc, gz, count, st);
+            launch_acc<T, OP, true, false>(inds, vs, n, m, P, gacc, gz, count, nullptr, nullptr, nullptr, st);
     } else {
-        int slots = kCacheSlots;
-        while ((size_t)slots * slot_bytes(OP, counts, true) > (size_t)kHistLds) slots >>= 1;
         if (counts)
-            launch_acc<T, OP, true, true>(inds, vs, n, m, slots, gacc, gz, count, st);
+            launch_acc<T, OP, false, true>(inds, vs, n, m, P, gacc, gz, count, pacc, pz, pcnt, st);
         else
-            launch_acc<T, OP, true, false>(inds, vs, n, m, slots, gacc, gz, count, st);
+            launch_acc<T, OP, false, false>(inds, vs, n, m, P, gacc, gz, count, pacc, pz, pcnt, st);
+        hipLaunchKernelGGL(hist_merge1_kernel<OP>, dim3((unsigned)ceil_div(m, 256), kMergeSlices), dim3(256), 0, st,
+                           pacc, pz, counts ? pcnt : nullptr, P.grid, m, macc, mz, mcnt);
+        hipLaunchKernelGGL(hist_merge2_kernel<OP>, dim3(gm), dim3(256), 0, st, macc, mz, counts ? mcnt : nullptr, m,
+                           gacc, gz, count);
     }
     if (f64minmax)
         hipLaunchKernelGGL(hist_f64_winner_kernel<OP>, dim3(flat_grid(n, 256, 8)), dim3(256), 0, st, inds,
@@ -321,8 +574,14 @@ static void dispatch_vjp(pvjp_op op, const int32_t* inds, const void* vs, int64_
     const unsigned gn = flat_grid(n, 256, 8), gm = flat_grid(m, 256, 4);
     const T* hb = (const T*)hsbar;
     T* vb = (T*)vsbar;
+    const bool vec = aligned(inds, 16) && aligned(vsbar, 16);
+    const unsigned gq = flat_grid(n, 256, 16);
     if (op == PVJP_ADD) {
-        if (acc)
+        if (vec && acc)
+            hipLaunchKernelGGL((hist_vjp_add_vec_kernel<T, true>), dim3(gq), dim3(256), 0, st, inds, n, m, hb, vb);
+        else if (vec)
+            hipLaunchKernelGGL((hist_vjp_add_vec_kernel<T, false>), dim3(gq), dim3(256), 0, st, inds, n, m, hb, vb);
+        else if (acc)
             hipLaunchKernelGGL((hist_vjp_add_kernel<T, true>), dim3(gn), dim3(256), 0, st, inds, n, m, hb, vb);
         else
             hipLaunchKernelGGL((hist_vjp_add_kernel<T, false>), dim3(gn), dim3(256), 0, st, inds, n, m, hb, vb);
@@ -337,7 +596,10 @@ static void dispatch_vjp(pvjp_op op, const int32_t* inds, const void* vs, int64_
         if (acc) {
             hipLaunchKernelGGL((hist_vjp_winner_kernel<T, true>), dim3(gm), dim3(256), 0, st, winner, m, hb, vb);
         } else {
-            hipLaunchKernelGGL(fill_zero_kernel<T>, dim3(gn), dim3(256), 0, st, vb, n);
+            if (aligned(vsbar, 16))
+                hipLaunchKernelGGL(fill_zero_vec_kernel<T>, dim3(gq), dim3(256), 0, st, vb, n);
+            else
+                hipLaunchKernelGGL(fill_zero_kernel<T>, dim3(gn), dim3(256), 0, st, vb, n);
             hipLaunchKernelGGL((hist_vjp_winner_kernel<T, false>), dim3(gm), dim3(256), 0, st, winner, m, hb, vb);
         }
     }
@@ -351,7 +613,7 @@ static constexpr int64_t kMaxBins = (int64_t)1 << 30;
 
 extern "C" size_t pvjp_hist_ws_bytes(pvjp_op op, pvjp_dtype dtype, int64_t n, int64_t m) {
     if (!valid_op(op) || !valid_dtype(dtype) || n < 0 || m < 1 || m > kMaxBins) return 0;
-    return hist_ws(op, m);
+    return hist_ws(op, n, m);
 }
 
 extern "C" pvjp_status pvjp_hist(pvjp_op op, pvjp_dtype dtype, const int32_t* inds, const void* vs, int64_t n,

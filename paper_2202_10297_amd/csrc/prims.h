@@ -212,19 +212,54 @@ constexpr uint32_t kErrSpin = 2u;    // a predecessor never published
 // workspace ends the kernel with an error instead of hanging it.
 constexpr uint32_t kMaxPolls = 1u << 20;
 
+// A tile's published states.  Every 32-bit word of a state travels together
+// with its launch tag and status in one 64-bit relaxed atomic, so a reader
+// accepts a state only when every word carries the current tag: no fence and
+// no ordering between words is needed.  (A release/acquire pair at device
+// scope would write back and invalidate the whole L2 of an XCD at every
+// publish and poll.)
 template <class S>
-struct alignas(64) TileState {
-    uint32_t flag;  // (tag << 2) | status; status 1 = aggregate, 2 = inclusive
-    uint32_t pad;
-    S agg;
-    S inc;
+struct alignas(128) TileState {
+    static constexpr int W = (int)(sizeof(S) / 4);
+    uint64_t agg[W];
+    uint64_t inc[W];
 };
 
 constexpr uint32_t kAgg = 1u, kInc = 2u;
 
 template <class S>
-__device__ __forceinline__ void st_coherent(S* p, const S& v) {
+__device__ __forceinline__ void publish(TileState<S>* st, const S& v, uint32_t status, uint32_t tag) {
     static_assert(sizeof(S) % 4 == 0, "state must be a whole number of words");
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(&v);
+    uint64_t* dst = status == kInc ? st->inc : st->agg;
+    const uint64_t hi = (uint64_t)((tag << 2) | status) << 32;
+#pragma unroll
+    for (int w = 0; w < TileState<S>::W; ++w)
+        __hip_atomic_store(dst + w, hi | (uint64_t)src[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Reads a field whose first word already showed `hi`; spins (bounded) on any
+// word not yet visible.  Returns false if a word never showed up.
+template <class S>
+__device__ __forceinline__ bool read_state(const uint64_t* f, uint64_t hi, S& v) {
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+    for (int w = 0; w < TileState<S>::W; ++w) {
+        uint64_t u;
+        uint32_t polls = 0;
+        while (((u = __hip_atomic_load(f + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) & ~0xffffffffull) != hi) {
+            if (++polls == (1u << 20)) return false;
+            __builtin_amdgcn_s_sleep(1);
+        }
+        dst[w] = (uint32_t)u;
+    }
+    return true;
+}
+
+// Coherent word-wise store/load of small records (reduction partials).
+template <class S>
+__device__ __forceinline__ void st_coherent(S* p, const S& v) {
+    static_assert(sizeof(S) % 4 == 0, "record must be a whole number of words");
     const uint32_t* src = reinterpret_cast<const uint32_t*>(&v);
     uint32_t* dst = reinterpret_cast<uint32_t*>(p);
 #pragma unroll
@@ -241,12 +276,6 @@ __device__ __forceinline__ S ld_coherent(const S* p) {
     for (int w = 0; w < (int)(sizeof(S) / 4); ++w)
         dst[w] = __hip_atomic_load(src + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return v;
-}
-
-template <class S>
-__device__ __forceinline__ void publish(TileState<S>* st, const S& v, uint32_t status, uint32_t tag) {
-    st_coherent(status == kInc ? &st->inc : &st->agg, v);
-    __hip_atomic_store(&st->flag, (tag << 2) | status, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Called by thread 0 at kernel start: fetches the launch tag and a dynamic
@@ -268,11 +297,13 @@ __device__ __forceinline__ void lookback_error(LookbackHdr* h, uint32_t bits) {
 __device__ __forceinline__ void lookback_end(LookbackHdr* h, uint32_t tag) {
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t d = __hip_atomic_fetch_add(&h->done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        // Relaxed: the reset only has to be visible to the next launch, which
+        // the kernel boundary orders.
+        uint32_t d = __hip_atomic_fetch_add(&h->done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (d == gridDim.x - 1) {
             __hip_atomic_store(&h->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&h->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&h->epoch, tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&h->epoch, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
@@ -295,21 +326,30 @@ __device__ typename Op::S lookback(TileState<typename Op::S>* states, int64_t ti
         uint32_t status = kInc;
         S v = Op::id();
         if (!virt) {
-            uint32_t f = 0;
+            const uint64_t hinc = (uint64_t)((tag << 2) | kInc) << 32;
+            const uint64_t hagg = (uint64_t)((tag << 2) | kAgg) << 32;
+            const uint64_t mask = ~0xffffffffull;
             uint32_t polls = 0;
+            status = 0;
             while (true) {
-                f = __hip_atomic_load(&states[p].flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                if ((f >> 2) == tag && (f & 3u) != 0u) break;
-                if (++polls == kMaxPolls) {
-                    __hip_atomic_fetch_or(&hdr->error, kErrSpin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    f = 0;
+                if ((__hip_atomic_load(&states[p].inc[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & mask) == hinc) {
+                    status = kInc;
                     break;
                 }
+                if ((__hip_atomic_load(&states[p].agg[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & mask) == hagg) {
+                    status = kAgg;
+                    break;
+                }
+                if (++polls == kMaxPolls) break;
                 __builtin_amdgcn_s_sleep(1);
             }
-            if (f != 0) {
-                status = f & 3u;
-                v = ld_coherent(status == kInc ? &states[p].inc : &states[p].agg);
+            if (status == 0 || !read_state(status == kInc ? states[p].inc : states[p].agg,
+                                           status == kInc ? hinc : hagg, v)) {
+                // A predecessor never published: record it and end the wait
+                // (results are invalid, but the kernel terminates).
+                __hip_atomic_fetch_or(&hdr->error, kErrSpin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                status = kInc;
+                v = Op::id();
             }
         }
         const uint64_t incl = __ballot(status == kInc);

@@ -28,7 +28,12 @@ namespace pvjp {
 constexpr int kSegBlock = 256;
 constexpr int kSegCk = PVJP_LINREC_CKPT_INTERVAL;
 
-// Workspace: [LookbackHdr | tile states | tile_seg0 int32[ntiles+1] |
+constexpr size_t kSegState = 128;
+static_assert(sizeof(TileState<SegLinRec<double>::S>) == kSegState && sizeof(TileState<LinO<double>::S>) == kSegState &&
+                  sizeof(TileState<SegLinRec<float>::S>) == kSegState && sizeof(TileState<LinO<float>::S>) == kSegState,
+              "tile states of both sweeps share one slot per tile");
+
+// Workspace: [LookbackHdr | tile states (128 B each) | tile_seg0 int32[ntiles+1] |
 //             offsets int64[nseg+1]]
 struct SegLayout {
     size_t states, seg0, offs, total;
@@ -39,15 +44,12 @@ static SegLayout seg_layout(int64_t total, int64_t nseg, int ts) {
     SegLayout L{};
     L.ntiles = ceil_div(total > 0 ? total : 1, ts);
     L.states = sizeof(LookbackHdr);
-    L.seg0 = L.states + align_up((size_t)L.ntiles * 64, 256);
+    L.seg0 = L.states + align_up((size_t)L.ntiles * kSegState, 256);
     L.offs = L.seg0 + align_up((size_t)(L.ntiles + 1) * 4, 256);
     L.total = L.offs + align_up((size_t)(nseg + 1) * 8, 256);
     return L;
 }
 
-static_assert(sizeof(TileState<SegLinRec<double>::S>) == 64 && sizeof(TileState<LinO<double>::S>) == 64 &&
-                  sizeof(TileState<SegLinRec<float>::S>) == 64 && sizeof(TileState<LinO<float>::S>) == 64,
-              "tile states of both sweeps share one 64-byte slot per tile");
 
 // Bitmap of segment heads over tile positions 0..TS (position TS is the first
 // element of the next tile): bit j set iff base + j starts a segment (or is

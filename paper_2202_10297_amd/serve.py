@@ -126,8 +126,10 @@ class Server:
         # Default-priority streams only.
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(self.nslots)]
         L = capi.lib()
-        self.ws_scan_bytes = L.pvjp_linrec_scan_vjp_ws_bytes(capi.F32, pool.max_n("scan"))
-        self.ws_gmm_bytes = L.pvjp_gmm_ws_bytes(pool.max_n("gmm"), GMM_D, GMM_K)
+        # Workspace sizes are not monotone in the problem size: take the
+        # maximum over the resident instances.
+        self.ws_scan_bytes = max(L.pvjp_linrec_scan_vjp_ws_bytes(capi.F32, i.n) for i in pool.inst["scan"])
+        self.ws_gmm_bytes = max(L.pvjp_gmm_ws_bytes(i.n, GMM_D, GMM_K) for i in pool.inst["gmm"])
         self.ws = []
         for _ in range(self.nslots):
             self.ws.append(dict(scan=self._zeros(self.ws_scan_bytes), gmm=self._zeros(self.ws_gmm_bytes)))
