@@ -20,6 +20,8 @@
 //   MIN/MAX: vs_bar[winner[k]] += hs_bar[k]      (m writes; zero-fill first
 //            when not accumulating);
 //   MUL: per bin, the three zero-count cases of reduce(*).
+#include <algorithm>
+
 #include "common.h"
 #include "prims.h"
 
@@ -437,6 +439,198 @@ __global__ __launch_bounds__(256) void hist_vjp_winner_kernel(const int32_t* __r
     }
 }
 
+// ------------------------------------------------- bucket-partitioned path
+// For FP32 values with + / min / max when the m bins do not fit one block's
+// LDS (m up to 2^22): instead of one global atomic per element,
+//   1. count the elements of every 4096-bin bucket per block (LDS counters),
+//   2. one block scans the (bucket, block) counts into write offsets and
+//      splits every bucket into work items of at most kPartSeg records,
+//   3. scatter each element as a packed record into its bucket,
+//   4. one block per work item accumulates its bucket's 4096 bins in LDS and
+//      writes them out as a partial,
+//   5. merge the partials of each bin in work-item order.
+constexpr int kPartShift = 12;
+constexpr int kPartBins = 1 << kPartShift;
+constexpr int kPartMaxBuckets = 1024;
+constexpr int64_t kPartSeg = (int64_t)1 << 17;
+constexpr int kPartScanThreads = 1024;
+constexpr int kPartGrid = 1024;
+
+template <bool VEC>
+__device__ __forceinline__ int4 load_k4(const int32_t* __restrict__ inds, int64_t e, int64_t hi) {
+    if (VEC && e + 3 < hi) return *reinterpret_cast<const int4*>(inds + e);
+    return make_int4(e < hi ? inds[e] : -1, e + 1 < hi ? inds[e + 1] : -1, e + 2 < hi ? inds[e + 2] : -1,
+                     e + 3 < hi ? inds[e + 3] : -1);
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(kHistBlock) void hpart_count_kernel(const int32_t* __restrict__ inds, int64_t n,
+                                                                 int32_t m, int64_t chunk, int nb,
+                                                                 int32_t* __restrict__ bcount) {
+    __shared__ int32_t cnt[kPartMaxBuckets];
+    for (int b = threadIdx.x; b < nb; b += kHistBlock) cnt[b] = 0;
+    __syncthreads();
+    const int64_t lo = (int64_t)blockIdx.x * chunk;
+    const int64_t hi = (lo + chunk < n) ? lo + chunk : n;
+    constexpr int64_t kStride = 4 * kHistBlock * kHistBatch;
+    for (int64_t base = lo; base < hi; base += kStride) {
+        int4 k[kHistBatch];
+#pragma unroll
+        for (int u = 0; u < kHistBatch; ++u) k[u] = load_k4<VEC>(inds, base + 4 * ((int64_t)u * kHistBlock + threadIdx.x), hi);
+#pragma unroll
+        for (int u = 0; u < kHistBatch; ++u) {
+            if ((uint32_t)k[u].x < (uint32_t)m) atomicAdd(&cnt[k[u].x >> kPartShift], 1);
+            if ((uint32_t)k[u].y < (uint32_t)m) atomicAdd(&cnt[k[u].y >> kPartShift], 1);
+            if ((uint32_t)k[u].z < (uint32_t)m) atomicAdd(&cnt[k[u].z >> kPartShift], 1);
+            if ((uint32_t)k[u].w < (uint32_t)m) atomicAdd(&cnt[k[u].w >> kPartShift], 1);
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += kHistBlock) bcount[(int64_t)b * gridDim.x + blockIdx.x] = cnt[b];
+}
+
+// One block: exclusive offsets of the (bucket, block) counts in bucket-major
+// order (in place), bucket starts, and work-item starts.
+__global__ __launch_bounds__(kPartScanThreads) void hpart_scan_kernel(int32_t* __restrict__ bcount, int nb, int G,
+                                                                      int32_t* __restrict__ bstart,
+                                                                      int32_t* __restrict__ istart) {
+    __shared__ IntSum::S wtot[kPartScanThreads / kWave];
+    const int64_t E = (int64_t)nb * G;
+    const int64_t per = (E + kPartScanThreads - 1) / kPartScanThreads;
+    const int64_t lo = (int64_t)threadIdx.x * per;
+    const int64_t hi = (lo + per < E) ? lo + per : E;
+    int s = 0;
+    for (int64_t e = lo; e < hi; ++e) s += bcount[e];
+    IntSum::S tot;
+    int ex = block_exclusive_scan<IntSum, kPartScanThreads, false>(IntSum::S{s}, tot, wtot).v;
+    for (int64_t e = lo; e < hi; ++e) {
+        const int c = bcount[e];
+        bcount[e] = ex;
+        ex += c;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nb) bstart[threadIdx.x] = bcount[(int64_t)threadIdx.x * G];
+    if (threadIdx.x == 0) bstart[nb] = tot.v;
+    __syncthreads();
+    int items = 0;
+    if ((int)threadIdx.x < nb) {
+        const int c = bstart[threadIdx.x + 1] - bstart[threadIdx.x];
+        items = (int)((c + kPartSeg - 1) / kPartSeg);
+    }
+    IntSum::S itot;
+    const int iex = block_exclusive_scan<IntSum, kPartScanThreads, false>(IntSum::S{items}, itot, wtot).v;
+    if ((int)threadIdx.x < nb) istart[threadIdx.x] = iex;
+    if (threadIdx.x == 0) istart[nb] = itot.v;
+}
+
+template <int OP, bool VEC>
+__global__ __launch_bounds__(kHistBlock) void hpart_scatter_kernel(const int32_t* __restrict__ inds,
+                                                                   const float* __restrict__ vs, int64_t n,
+                                                                   int32_t m, int64_t chunk, int nb,
+                                                                   const int32_t* __restrict__ boff,
+                                                                   uint64_t* __restrict__ rec,
+                                                                   uint16_t* __restrict__ rbin) {
+    __shared__ int32_t cur[kPartMaxBuckets];
+    for (int b = threadIdx.x; b < nb; b += kHistBlock) cur[b] = boff[(int64_t)b * gridDim.x + blockIdx.x];
+    __syncthreads();
+    const int64_t lo = (int64_t)blockIdx.x * chunk;
+    const int64_t hi = (lo + chunk < n) ? lo + chunk : n;
+    constexpr int64_t kStride = 4 * kHistBlock * kHistBatch;
+    for (int64_t base = lo; base < hi; base += kStride) {
+        Quad<float> q[kHistBatch];
+#pragma unroll
+        for (int u = 0; u < kHistBatch; ++u) q[u] = load_quad<float, VEC>(inds, vs, base + 4 * ((int64_t)u * kHistBlock + threadIdx.x), hi);
+#pragma unroll
+        for (int u = 0; u < kHistBatch; ++u) {
+            const int64_t e = base + 4 * ((int64_t)u * kHistBlock + threadIdx.x);
+            const int32_t kk[4] = {q[u].k.x, q[u].k.y, q[u].k.z, q[u].k.w};
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if ((uint32_t)kk[t] >= (uint32_t)m) continue;
+                const int pos = atomicAdd(&cur[kk[t] >> kPartShift], 1);
+                const uint32_t j = (uint32_t)kk[t] & (kPartBins - 1);
+                if (OP == PVJP_ADD) {
+                    rec[pos] = ((uint64_t)j << 32) | (uint64_t)__float_as_uint(q[u].v[t]);
+                } else {
+                    rec[pos] = elem_key<OP>(q[u].v[t], e + t);
+                    rbin[pos] = (uint16_t)j;
+                }
+            }
+        }
+    }
+}
+
+template <int OP, bool COUNTS>
+__global__ __launch_bounds__(kHistBlock) void hpart_acc_kernel(const uint64_t* __restrict__ rec,
+                                                               const uint16_t* __restrict__ rbin, int nb,
+                                                               const int32_t* __restrict__ bstart,
+                                                               const int32_t* __restrict__ istart,
+                                                               uint64_t* __restrict__ pacc,
+                                                               int32_t* __restrict__ pcnt) {
+    __shared__ uint64_t acc[kPartBins];
+    __shared__ int32_t cnt[COUNTS ? kPartBins : 1];
+    const int item = blockIdx.x;
+    if (item >= istart[nb]) return;
+    int lo = 0, hi = nb;  // last bucket b with istart[b] <= item
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (istart[mid] <= item) lo = mid; else hi = mid;
+    }
+    const int b = lo;
+    const int64_t r0 = (int64_t)bstart[b] + (int64_t)(item - istart[b]) * kPartSeg;
+    const int64_t r1 = (r0 + kPartSeg < (int64_t)bstart[b + 1]) ? r0 + kPartSeg : (int64_t)bstart[b + 1];
+    for (int j = threadIdx.x; j < kPartBins; j += kHistBlock) {
+        acc[j] = acc_identity<OP>();
+        if (COUNTS) cnt[j] = 0;
+    }
+    __syncthreads();
+    constexpr int U = 8;
+    for (int64_t base = r0; base < r1; base += (int64_t)U * kHistBlock) {
+        uint64_t u[U];
+        uint32_t jb[U];
+#pragma unroll
+        for (int t = 0; t < U; ++t) {
+            const int64_t r = base + (int64_t)t * kHistBlock + threadIdx.x;
+            u[t] = (r < r1) ? rec[r] : 0ull;
+            jb[t] = (OP == PVJP_ADD || r >= r1) ? 0u : (uint32_t)rbin[r];
+        }
+#pragma unroll
+        for (int t = 0; t < U; ++t) {
+            const int64_t r = base + (int64_t)t * kHistBlock + threadIdx.x;
+            if (r >= r1) continue;
+            if (OP == PVJP_ADD) {
+                const uint32_t j = (uint32_t)(u[t] >> 32);
+                atomicAdd(reinterpret_cast<double*>(&acc[j]), (double)__uint_as_float((uint32_t)u[t]));
+                if (COUNTS) atomicAdd(&cnt[j], 1);
+            } else {
+                atomicMax(reinterpret_cast<unsigned long long*>(&acc[jb[t]]), (unsigned long long)u[t]);
+                if (COUNTS) atomicAdd(&cnt[jb[t]], 1);
+            }
+        }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < kPartBins; j += kHistBlock) {
+        pacc[(int64_t)item * kPartBins + j] = acc[j];
+        if (COUNTS) pcnt[(int64_t)item * kPartBins + j] = cnt[j];
+    }
+}
+
+template <int OP>
+__global__ __launch_bounds__(256) void hpart_merge_kernel(const uint64_t* __restrict__ pacc,
+                                                          const int32_t* __restrict__ pcnt,
+                                                          const int32_t* __restrict__ istart, int32_t m,
+                                                          uint64_t* __restrict__ gacc, int32_t* __restrict__ gcount) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x) {
+        const int b = (int)(k >> kPartShift), j = (int)(k & (kPartBins - 1));
+        uint64_t acc = acc_identity<OP>();
+        int32_t zz = 0, cc = 0;
+        for (int it = istart[b]; it < istart[b + 1]; ++it)
+            merge_fold<OP>(acc, zz, cc, pacc[(int64_t)it * kPartBins + j], 0, pcnt ? pcnt[(int64_t)it * kPartBins + j] : 0);
+        gacc[k] = acc;
+        if (gcount) gcount[k] = cc;
+    }
+}
+
 // ------------------------------------------------------------------ host
 static size_t slot_bytes(int op, bool counts, bool cache) {
     return 8 + (counts ? 4 : 0) + (op == PVJP_MUL ? 4 : 0) + (cache ? 4 : 0);
@@ -483,9 +677,55 @@ static HistPlan hist_plan(int op, int64_t n, int64_t m, bool counts) {
     return P;
 }
 
+// The bucket-partitioned path serves FP32 + / min / max when m does not fit
+// one block's LDS and the buckets fit the scan block.
+static bool use_partition(int op, bool f32, int64_t m, bool counts) {
+    const int full_slots = (int)(kHistLds / slot_bytes(op, counts, false));
+    return f32 && op != PVJP_MUL && m > full_slots && ceil_div(m, kPartBins) <= kPartMaxBuckets;
+}
+
+struct PartLayout {
+    int nb;
+    int64_t chunk, items_max;
+    size_t bcount, bstart, istart, rec, rbin, pacc, pcnt, total;
+};
+
+static PartLayout part_layout(int64_t n, int64_t m) {
+    PartLayout L{};
+    L.nb = (int)ceil_div(m, kPartBins);
+    const int64_t quantum = 4 * kHistBlock;
+    L.chunk = ceil_div(ceil_div(n > 0 ? n : 1, kPartGrid), quantum) * quantum;
+    L.items_max = ceil_div(n > 0 ? n : 1, kPartSeg) + L.nb;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += align_up(bytes, 256);
+        return at;
+    };
+    L.bcount = take((size_t)L.nb * kPartGrid * 4);
+    L.bstart = take((size_t)(L.nb + 1) * 4);
+    L.istart = take((size_t)(L.nb + 1) * 4);
+    L.rec = take((size_t)(n > 0 ? n : 1) * 8);
+    L.rbin = take((size_t)(n > 0 ? n : 1) * 2);
+    L.pacc = take((size_t)L.items_max * kPartBins * 8);
+    L.pcnt = take((size_t)L.items_max * kPartBins * 4);
+    L.total = o;
+    return L;
+}
+
 // Covers both plans (with and without counts): the FULL/CACHE choice and the
 // grid depend on whether counts are requested.
-static size_t hist_ws(int op, int64_t n, int64_t m) {
+static size_t hist_ws(int op, int64_t n, int64_t m, bool f32) {
+    if (use_partition(op, f32, m, false) || use_partition(op, f32, m, true)) {
+        // either plan may run: reserve the larger of the two layouts below
+        const size_t part = part_layout(n, m).total;
+        size_t other = 0;
+        for (int counts = 0; counts < 2; ++counts) {
+            const HistPlan P = hist_plan(op, n, m, counts != 0);
+            if (!P.cache) other = std::max(other, align_up((size_t)(P.grid + kMergeSlices) * m * 16, 256));
+        }
+        return align_up((size_t)m * 8, 256) + std::max(part, other);
+    }
     size_t part = 0;
     for (int counts = 0; counts < 2; ++counts) {
         const HistPlan P = hist_plan(op, n, m, counts != 0);
@@ -496,6 +736,41 @@ static size_t hist_ws(int op, int64_t n, int64_t m) {
         }
     }
     return align_up((size_t)m * 8, 256) + (op == PVJP_MUL ? align_up((size_t)m * 4, 256) : 0) + part;
+}
+
+template <int OP>
+static void run_partitioned(const int32_t* inds, const float* vs, int64_t n, int32_t m, int32_t* count, char* w,
+                            size_t off, uint64_t* gacc, hipStream_t st) {
+    const PartLayout L = part_layout(n, m);
+    char* base = w + off;
+    int32_t* bcount = reinterpret_cast<int32_t*>(base + L.bcount);
+    int32_t* bstart = reinterpret_cast<int32_t*>(base + L.bstart);
+    int32_t* istart = reinterpret_cast<int32_t*>(base + L.istart);
+    uint64_t* rec = reinterpret_cast<uint64_t*>(base + L.rec);
+    uint16_t* rbin = reinterpret_cast<uint16_t*>(base + L.rbin);
+    uint64_t* pacc = reinterpret_cast<uint64_t*>(base + L.pacc);
+    int32_t* pcnt = reinterpret_cast<int32_t*>(base + L.pcnt);
+    const int G = kPartGrid;
+    const bool vec = aligned(inds, 16) && aligned(vs, 16);
+    if (vec)
+        hipLaunchKernelGGL(hpart_count_kernel<true>, dim3(G), dim3(kHistBlock), 0, st, inds, n, m, L.chunk, L.nb, bcount);
+    else
+        hipLaunchKernelGGL(hpart_count_kernel<false>, dim3(G), dim3(kHistBlock), 0, st, inds, n, m, L.chunk, L.nb, bcount);
+    hipLaunchKernelGGL(hpart_scan_kernel, dim3(1), dim3(kPartScanThreads), 0, st, bcount, L.nb, G, bstart, istart);
+    if (vec)
+        hipLaunchKernelGGL((hpart_scatter_kernel<OP, true>), dim3(G), dim3(kHistBlock), 0, st, inds, vs, n, m, L.chunk,
+                           L.nb, bcount, rec, rbin);
+    else
+        hipLaunchKernelGGL((hpart_scatter_kernel<OP, false>), dim3(G), dim3(kHistBlock), 0, st, inds, vs, n, m, L.chunk,
+                           L.nb, bcount, rec, rbin);
+    if (count)
+        hipLaunchKernelGGL((hpart_acc_kernel<OP, true>), dim3((unsigned)L.items_max), dim3(kHistBlock), 0, st, rec, rbin,
+                           L.nb, bstart, istart, pacc, pcnt);
+    else
+        hipLaunchKernelGGL((hpart_acc_kernel<OP, false>), dim3((unsigned)L.items_max), dim3(kHistBlock), 0, st, rec,
+                           rbin, L.nb, bstart, istart, pacc, pcnt);
+    hipLaunchKernelGGL(hpart_merge_kernel<OP>, dim3(flat_grid(m, 256, 4)), dim3(256), 0, st, pacc,
+                       count ? pcnt : nullptr, istart, m, gacc, count);
 }
 
 template <class T, int OP, bool CACHE, bool COUNTS>
@@ -522,6 +797,14 @@ static void run_hist(const int32_t* inds, const T* vs, int64_t n, int32_t m, T* 
         off += align_up((size_t)m * 4, 256);
     }
     const bool counts = count != nullptr;
+    if constexpr (sizeof(T) == 4 && OP != PVJP_MUL) {
+        if (use_partition(OP, true, m, counts)) {
+            run_partitioned<OP>(inds, (const float*)vs, n, m, count, w, off, gacc, st);
+            hipLaunchKernelGGL((hist_final_kernel<T, OP>), dim3(flat_grid(m, 256, 4)), dim3(256), 0, st, vs, gacc, gz,
+                               m, hs, winner, p, z);
+            return;
+        }
+    }
     const HistPlan P = hist_plan(OP, n, m, counts);
     uint64_t* pacc = reinterpret_cast<uint64_t*>(w + off);
     int32_t* pz = reinterpret_cast<int32_t*>(pacc + (size_t)P.grid * m);
@@ -613,7 +896,7 @@ static constexpr int64_t kMaxBins = (int64_t)1 << 30;
 
 extern "C" size_t pvjp_hist_ws_bytes(pvjp_op op, pvjp_dtype dtype, int64_t n, int64_t m) {
     if (!valid_op(op) || !valid_dtype(dtype) || n < 0 || m < 1 || m > kMaxBins) return 0;
-    return hist_ws(op, n, m);
+    return hist_ws(op, n, m, dtype == PVJP_F32);
 }
 
 extern "C" pvjp_status pvjp_hist(pvjp_op op, pvjp_dtype dtype, const int32_t* inds, const void* vs, int64_t n,
