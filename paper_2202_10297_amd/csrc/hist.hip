@@ -489,74 +489,132 @@ __global__ __launch_bounds__(kHistBlock) void hpart_count_kernel(const int32_t* 
     for (int b = threadIdx.x; b < nb; b += kHistBlock) bcount[(int64_t)b * gridDim.x + blockIdx.x] = cnt[b];
 }
 
-// One block: exclusive offsets of the (bucket, block) counts in bucket-major
-// order (in place), bucket starts, and work-item starts.
-__global__ __launch_bounds__(kPartScanThreads) void hpart_scan_kernel(int32_t* __restrict__ bcount, int nb, int G,
+// Exclusive offsets of the (bucket, block) counts: one block per bucket scans
+// its kPartGrid block counts in place (coalesced) and writes the bucket total.
+__global__ __launch_bounds__(kPartGrid) void hpart_scan_local_kernel(int32_t* __restrict__ bcount,
+                                                                     int32_t* __restrict__ btotal) {
+    __shared__ IntSum::S wtot[kPartGrid / kWave];
+    const int64_t e = (int64_t)blockIdx.x * kPartGrid + threadIdx.x;
+    const int c = bcount[e];
+    IntSum::S tot;
+    bcount[e] = block_exclusive_scan<IntSum, kPartGrid, false>(IntSum::S{c}, tot, wtot).v;
+    if (threadIdx.x == 0) btotal[blockIdx.x] = tot.v;
+}
+
+// One block: bucket starts from the bucket totals, and work-item starts.
+__global__ __launch_bounds__(kPartScanThreads) void hpart_scan_kernel(const int32_t* __restrict__ btotal, int nb,
                                                                       int32_t* __restrict__ bstart,
                                                                       int32_t* __restrict__ istart) {
     __shared__ IntSum::S wtot[kPartScanThreads / kWave];
-    const int64_t E = (int64_t)nb * G;
-    const int64_t per = (E + kPartScanThreads - 1) / kPartScanThreads;
-    const int64_t lo = (int64_t)threadIdx.x * per;
-    const int64_t hi = (lo + per < E) ? lo + per : E;
-    int s = 0;
-    for (int64_t e = lo; e < hi; ++e) s += bcount[e];
+    const int b = threadIdx.x;
+    const int c = b < nb ? btotal[b] : 0;
     IntSum::S tot;
-    int ex = block_exclusive_scan<IntSum, kPartScanThreads, false>(IntSum::S{s}, tot, wtot).v;
-    for (int64_t e = lo; e < hi; ++e) {
-        const int c = bcount[e];
-        bcount[e] = ex;
-        ex += c;
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < nb) bstart[threadIdx.x] = bcount[(int64_t)threadIdx.x * G];
-    if (threadIdx.x == 0) bstart[nb] = tot.v;
-    __syncthreads();
-    int items = 0;
-    if ((int)threadIdx.x < nb) {
-        const int c = bstart[threadIdx.x + 1] - bstart[threadIdx.x];
-        items = (int)((c + kPartSeg - 1) / kPartSeg);
-    }
+    const int ex = block_exclusive_scan<IntSum, kPartScanThreads, false>(IntSum::S{c}, tot, wtot).v;
+    if (b < nb) bstart[b] = ex;
+    if (b == 0) bstart[nb] = tot.v;
+    const int items = (int)((c + kPartSeg - 1) / kPartSeg);
     IntSum::S itot;
     const int iex = block_exclusive_scan<IntSum, kPartScanThreads, false>(IntSum::S{items}, itot, wtot).v;
-    if ((int)threadIdx.x < nb) istart[threadIdx.x] = iex;
-    if (threadIdx.x == 0) istart[nb] = itot.v;
+    if (b < nb) istart[b] = iex;
+    if (b == 0) istart[nb] = itot.v;
 }
+
+// Scatter of packed records into their buckets.  Each batch of 4096
+// elements is first counting-sorted by bucket in LDS, so that every bucket's
+// run of the batch leaves as one contiguous, coalesced write.
+constexpr int kPartBatch = 4 * kHistBlock * kHistBatch;  // 4096 elements
 
 template <int OP, bool VEC>
 __global__ __launch_bounds__(kHistBlock) void hpart_scatter_kernel(const int32_t* __restrict__ inds,
                                                                    const float* __restrict__ vs, int64_t n,
                                                                    int32_t m, int64_t chunk, int nb,
-                                                                   const int32_t* __restrict__ boff,
+                                                                   const int32_t* __restrict__ local,
+                                                                   const int32_t* __restrict__ bstart,
                                                                    uint64_t* __restrict__ rec,
                                                                    uint16_t* __restrict__ rbin) {
-    __shared__ int32_t cur[kPartMaxBuckets];
-    for (int b = threadIdx.x; b < nb; b += kHistBlock) cur[b] = boff[(int64_t)b * gridDim.x + blockIdx.x];
+    constexpr bool KEYS = OP != PVJP_ADD;
+    __shared__ int32_t cur[kPartMaxBuckets];   // next global position of each bucket
+    __shared__ int32_t bcnt[kPartMaxBuckets];  // batch count, then batch run start
+    __shared__ uint64_t stage[kPartBatch];
+    __shared__ uint16_t sbkt[kPartBatch];
+    __shared__ uint16_t sbin[KEYS ? kPartBatch : 1];
+    __shared__ IntSum::S wtot[kHistBlock / kWave];
+    for (int b = threadIdx.x; b < nb; b += kHistBlock) {
+        cur[b] = bstart[b] + local[(int64_t)b * gridDim.x + blockIdx.x];
+        bcnt[b] = 0;
+    }
     __syncthreads();
     const int64_t lo = (int64_t)blockIdx.x * chunk;
     const int64_t hi = (lo + chunk < n) ? lo + chunk : n;
-    constexpr int64_t kStride = 4 * kHistBlock * kHistBatch;
-    for (int64_t base = lo; base < hi; base += kStride) {
+    for (int64_t base = lo; base < hi; base += kPartBatch) {
         Quad<float> q[kHistBatch];
 #pragma unroll
-        for (int u = 0; u < kHistBatch; ++u) q[u] = load_quad<float, VEC>(inds, vs, base + 4 * ((int64_t)u * kHistBlock + threadIdx.x), hi);
+        for (int u = 0; u < kHistBatch; ++u)
+            q[u] = load_quad<float, VEC>(inds, vs, base + 4 * ((int64_t)u * kHistBlock + threadIdx.x), hi);
+        int rank[4 * kHistBatch];
 #pragma unroll
         for (int u = 0; u < kHistBatch; ++u) {
-            const int64_t e = base + 4 * ((int64_t)u * kHistBlock + threadIdx.x);
             const int32_t kk[4] = {q[u].k.x, q[u].k.y, q[u].k.z, q[u].k.w};
 #pragma unroll
+            for (int t = 0; t < 4; ++t)
+                rank[4 * u + t] = ((uint32_t)kk[t] < (uint32_t)m) ? atomicAdd(&bcnt[kk[t] >> kPartShift], 1) : -1;
+        }
+        __syncthreads();
+        // exclusive scan of the batch counts: each thread owns 4 buckets
+        int c4[4], sum = 0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int b = 4 * (int)threadIdx.x + t;
+            c4[t] = b < nb ? bcnt[b] : 0;
+            sum += c4[t];
+        }
+        IntSum::S tot;
+        int ex = block_exclusive_scan<IntSum, kHistBlock, false>(IntSum::S{sum}, tot, wtot).v;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int b = 4 * (int)threadIdx.x + t;
+            if (b < nb) bcnt[b] = ex;  // run start of bucket b in the staging area
+            ex += c4[t];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kHistBatch; ++u) {
+            const int32_t kk[4] = {q[u].k.x, q[u].k.y, q[u].k.z, q[u].k.w};
+            const int64_t e = base + 4 * ((int64_t)u * kHistBlock + threadIdx.x);
+#pragma unroll
             for (int t = 0; t < 4; ++t) {
-                if ((uint32_t)kk[t] >= (uint32_t)m) continue;
-                const int pos = atomicAdd(&cur[kk[t] >> kPartShift], 1);
+                if (rank[4 * u + t] < 0) continue;
+                const int b = kk[t] >> kPartShift;
+                const int slot = bcnt[b] + rank[4 * u + t];
                 const uint32_t j = (uint32_t)kk[t] & (kPartBins - 1);
-                if (OP == PVJP_ADD) {
-                    rec[pos] = ((uint64_t)j << 32) | (uint64_t)__float_as_uint(q[u].v[t]);
+                if (KEYS) {
+                    stage[slot] = elem_key<OP>(q[u].v[t], e + t);
+                    sbin[slot] = (uint16_t)j;
                 } else {
-                    rec[pos] = elem_key<OP>(q[u].v[t], e + t);
-                    rbin[pos] = (uint16_t)j;
+                    stage[slot] = ((uint64_t)j << 32) | (uint64_t)__float_as_uint(q[u].v[t]);
                 }
+                sbkt[slot] = (uint16_t)b;
             }
         }
+        __syncthreads();
+        for (int sl = threadIdx.x; sl < tot.v; sl += kHistBlock) {
+            const int b = sbkt[sl];
+            const int pos = cur[b] + (sl - bcnt[b]);
+            rec[pos] = stage[sl];
+            if (KEYS) rbin[pos] = sbin[sl];
+        }
+        __syncthreads();
+        // advance the cursors by the batch counts (run lengths) and reset
+        for (int t = 0; t < 4; ++t) {
+            const int b = 4 * (int)threadIdx.x + t;
+            if (b < nb) {
+                const int next = (b + 1 < nb) ? bcnt[b + 1] : tot.v;
+                cur[b] += next - bcnt[b];
+            }
+        }
+        __syncthreads();
+        for (int b = threadIdx.x; b < nb; b += kHistBlock) bcnt[b] = 0;
+        __syncthreads();
     }
 }
 
@@ -687,7 +745,7 @@ static bool use_partition(int op, bool f32, int64_t m, bool counts) {
 struct PartLayout {
     int nb;
     int64_t chunk, items_max;
-    size_t bcount, bstart, istart, rec, rbin, pacc, pcnt, total;
+    size_t bcount, btotal, bstart, istart, rec, rbin, pacc, pcnt, total;
 };
 
 static PartLayout part_layout(int64_t n, int64_t m) {
@@ -703,6 +761,7 @@ static PartLayout part_layout(int64_t n, int64_t m) {
         return at;
     };
     L.bcount = take((size_t)L.nb * kPartGrid * 4);
+    L.btotal = take((size_t)L.nb * 4);
     L.bstart = take((size_t)(L.nb + 1) * 4);
     L.istart = take((size_t)(L.nb + 1) * 4);
     L.rec = take((size_t)(n > 0 ? n : 1) * 8);
@@ -744,6 +803,7 @@ static void run_partitioned(const int32_t* inds, const float* vs, int64_t n, int
     const PartLayout L = part_layout(n, m);
     char* base = w + off;
     int32_t* bcount = reinterpret_cast<int32_t*>(base + L.bcount);
+    int32_t* btotal = reinterpret_cast<int32_t*>(base + L.btotal);
     int32_t* bstart = reinterpret_cast<int32_t*>(base + L.bstart);
     int32_t* istart = reinterpret_cast<int32_t*>(base + L.istart);
     uint64_t* rec = reinterpret_cast<uint64_t*>(base + L.rec);
@@ -756,13 +816,14 @@ static void run_partitioned(const int32_t* inds, const float* vs, int64_t n, int
         hipLaunchKernelGGL(hpart_count_kernel<true>, dim3(G), dim3(kHistBlock), 0, st, inds, n, m, L.chunk, L.nb, bcount);
     else
         hipLaunchKernelGGL(hpart_count_kernel<false>, dim3(G), dim3(kHistBlock), 0, st, inds, n, m, L.chunk, L.nb, bcount);
-    hipLaunchKernelGGL(hpart_scan_kernel, dim3(1), dim3(kPartScanThreads), 0, st, bcount, L.nb, G, bstart, istart);
+    hipLaunchKernelGGL(hpart_scan_local_kernel, dim3(L.nb), dim3(kPartGrid), 0, st, bcount, btotal);
+    hipLaunchKernelGGL(hpart_scan_kernel, dim3(1), dim3(kPartScanThreads), 0, st, btotal, L.nb, bstart, istart);
     if (vec)
         hipLaunchKernelGGL((hpart_scatter_kernel<OP, true>), dim3(G), dim3(kHistBlock), 0, st, inds, vs, n, m, L.chunk,
-                           L.nb, bcount, rec, rbin);
+                           L.nb, bcount, bstart, rec, rbin);
     else
         hipLaunchKernelGGL((hpart_scatter_kernel<OP, false>), dim3(G), dim3(kHistBlock), 0, st, inds, vs, n, m, L.chunk,
-                           L.nb, bcount, rec, rbin);
+                           L.nb, bcount, bstart, rec, rbin);
     if (count)
         hipLaunchKernelGGL((hpart_acc_kernel<OP, true>), dim3((unsigned)L.items_max), dim3(kHistBlock), 0, st, rec, rbin,
                            L.nb, bstart, istart, pacc, pcnt);
