@@ -160,6 +160,12 @@ pvjp_status pvjp_reduce_vjp(pvjp_op op, pvjp_dtype dtype, const void* x, int64_t
 /* are skipped).                                                              */
 /* ------------------------------------------------------------------------ */
 
+/* Workspace bytes for pvjp_hist (device memory, zero-initialised once by the
+ * caller, owned by the caller, reusable across calls on one stream).  Small
+ * m (the bins fit one block's LDS): per-block partial histograms, O(m) with
+ * a few hundred rows.  FP32 + / min / max with m beyond that and at most
+ * 2^22 bins: the bucket-partitioned path, which stores a packed 8-byte record
+ * and a 2-byte bin per element (about 10n bytes plus per-bucket partials). */
 size_t pvjp_hist_ws_bytes(pvjp_op op, pvjp_dtype dtype, int64_t n, int64_t m);
 /* inds [n] int32, vs [n] dtype, 1 <= m <= 2^30, n < 2^31.
  * hs [m] dtype (required).

@@ -69,5 +69,13 @@ def test_workspace_queries(capi):
     assert L.pvjp_linrec_ckpt_len(0) == 0
     assert L.pvjp_linrec_ckpt_len(1) == 1 and L.pvjp_linrec_ckpt_len(1025) == 2
     assert L.pvjp_linrec_scan_ws_bytes(capi.F64, 65536) >= 256 + 32 * 64
-    assert L.pvjp_hist_ws_bytes(capi.ADD, capi.F32, 1 << 26, 1 << 20) == 8 << 20
+    # bins that fit LDS: per-block partials, independent of n beyond the grid
+    small = L.pvjp_hist_ws_bytes(capi.ADD, capi.F32, 1 << 26, 1 << 10)
+    assert 8 << 10 <= small <= 64 << 20
+    # FP32 + beyond LDS: a packed record and a bin per element
+    n = 1 << 26
+    big = L.pvjp_hist_ws_bytes(capi.ADD, capi.F32, n, 1 << 20)
+    assert 10 * n <= big <= 12 * n
+    # FP64 has no partitioned path: the direct-mapped cache needs no partials
+    assert L.pvjp_hist_ws_bytes(capi.ADD, capi.F64, n, 1 << 20) < 64 << 20
     assert L.pvjp_reduce_ws_bytes(capi.ADD, capi.F32, 0) > 0

@@ -298,6 +298,24 @@ def test_scatter_out_of_range_accumulate(ops, orc):
     assert np.array_equal(host(ybar), rxb) and np.array_equal(host(vbar), base + rvb)
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_scatter_unaligned_indices(ops, orc, dtype):
+    # An index view one element into its buffer takes the scalar-load path.
+    n, m = 50000, 4099
+    xs, is_, vs, yb = workloads.scatter(n, m + 1, dtype, seed=11)
+    dis = dev(is_)[1:]
+    is_, vs = is_[1:], vs[1:]
+    x = dev(xs)
+    saved = ops.scatter_(x, dis, dev(vs))
+    rys, rsaved = orc.scatter(xs, is_, vs)
+    assert np.array_equal(host(x), rys) and np.array_equal(host(saved), rsaved)
+    ybar = dev(yb)
+    vbar = ops.scatter_vjp_(ybar, dis, ys=x, xs_saved=saved)
+    rxb, rvb = orc.scatter_vjp(is_, yb)
+    assert np.array_equal(host(ybar), rxb) and np.array_equal(host(vbar), rvb)
+    assert np.array_equal(host(x), xs)
+
+
 # --------------------------------------------------------------------- map
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 @pytest.mark.parametrize("fn", ["square", "exp", "log", "sin", "tanh"])
