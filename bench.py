@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=1 << 21, help="elements per instance for the CPU oracle")
     ap.add_argument("--skip", default="", help="comma list of extra workloads to skip: scan,gmm,batch,serve")
     ap.add_argument("--serve-seconds", type=float, default=4.0, help="measured seconds of the serving trace")
+    ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn the counter_collection.csv files of a FETCH_SIZE and a WRITE_SIZE run into "
+                         "profiles/traffic.json (no GPU needed), then exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain streaming kernel over 2^28 FP32 (1 GiB read, 1 GiB written), whose "
                          "FETCH_SIZE/WRITE_SIZE counters scale the counters of the other kernels")
@@ -80,6 +83,88 @@ def scatter_vjp_bytes(m):
     return 24 * m  # is, ys_bar[is], xs_saved read; vs_bar, ys_bar[is], ys[is] written
 
 
+def call_order():
+    """(instance key, primal|vjp) of the step's library calls, in launch order."""
+    out = []
+    for m in BINS:
+        for dist in DISTS:
+            for op in HIST_OPS:
+                out += [(f"hist_{op}_m{m}_{dist}", "primal"), (f"hist_{op}_m{m}_{dist}", "vjp")]
+    return out + [("scatter_m2^24_n2^26", "primal"), ("scatter_m2^24_n2^26", "vjp")]
+
+
+# First kernel of each kind of library call: a new call starts at each one.
+CALL_START_KERNELS = ("hist_acc_kernel", "hist_init_kernel", "hpart_count_kernel", "hist_vjp_add_vec_kernel",
+                      "hist_vjp_add_lds_kernel", "hist_vjp_add_kernel", "fill_zero_vec_kernel", "scatter_kernel",
+                      "scatter_vjp_kernel")
+CALL_SOURCE = {"hist": "paper_2202_10297_amd/csrc/hist.hip", "scatter": "paper_2202_10297_amd/csrc/scatter.hip"}
+
+
+def _short_kernel(name):
+    base = name.split("(")[0].split("<")[0]
+    return base.rsplit("::", 1)[-1].replace("void ", "").strip()
+
+
+def _sha16(rel):
+    return hashlib.sha256(open(os.path.join(ROOT, rel), "rb").read()).hexdigest()[:16]
+
+
+def ingest_pmc(fetch_csv, write_csv):
+    """HBM bytes per library call from one `--pmc FETCH_SIZE` and one
+    `--pmc WRITE_SIZE` run of `bench.py --steps 1 --warmup 0
+    --copy-calibration`.  Both counters are in KiB per dispatch; each is
+    scaled by (bytes the calibration kernel moves) / (what the counter read
+    for it), then summed over the kernels of each call.  Writes
+    profiles/traffic.json."""
+    import csv
+
+    def per_dispatch(path):
+        rows = sorted(csv.DictReader(open(path)), key=lambda r: int(r["Dispatch_Id"]))
+        return [(r["Kernel_Name"], float(r["Counter_Value"]) * 1024.0) for r in rows]
+
+    out = {}
+    scale = {}
+    groups_by = {}
+    for what, path in (("fetch", fetch_csv), ("write", write_csv)):
+        d = per_dispatch(path)
+        cal = [v for name, v in d if "neg_kernel" in name]
+        if not cal:
+            raise SystemExit(f"{path}: no calibration kernel (run bench.py with --copy-calibration)")
+        scale[what] = (4.0 * COPY_N) / (sum(cal) / len(cal))
+        groups = []
+        for name, v in d:
+            if "pvjp::" not in name:
+                continue
+            short = _short_kernel(name)
+            if short in CALL_START_KERNELS or not groups:
+                groups.append([])
+            groups[-1].append((short, v))
+        groups_by[what] = groups
+    order = call_order()
+    for what in ("fetch", "write"):
+        if len(groups_by[what]) != len(order):
+            raise SystemExit(f"{what}: {len(groups_by[what])} calls found, expected {len(order)}")
+    for i, (key, kind) in enumerate(order):
+        src = CALL_SOURCE["scatter" if key.startswith("scatter") else "hist"]
+        fb = sum(v for _, v in groups_by["fetch"][i]) * scale["fetch"]
+        wb = sum(v for _, v in groups_by["write"][i]) * scale["write"]
+        out[f"{key}:{kind}"] = {
+            "source": src,
+            "source_sha": _sha16(src),
+            "kernels": [k for k, _ in groups_by["fetch"][i]],
+            "fetch_bytes": round(fb),
+            "write_bytes": round(wb),
+            "bytes_per_launch": round(fb + wb),
+        }
+    out["_calibration"] = {"kernel": f"torch neg over 2^{COPY_N.bit_length() - 1} FP32 (1 GiB read, 1 GiB written)",
+                           "fetch_scale": round(scale["fetch"], 4), "write_scale": round(scale["write"], 4)}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1, sort_keys=True)
+    print(f"wrote {path}: {len(order)} calls; scales {scale}")
+
+
 def traffic_for(kernel_key):
     """HBM bytes per launch from committed rocprofv3 counters, if they were
     taken on the current source of the kernel's file."""
@@ -99,6 +184,9 @@ def traffic_for(kernel_key):
 
 def main():
     args = parse()
+    if args.ingest_pmc:
+        ingest_pmc(*args.ingest_pmc)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
               "(multi-GPU sharding is design-only)", file=sys.stderr)
@@ -186,6 +274,7 @@ def main():
 
     calls.append(("scatter_m2^24_n2^26", "primal", sprim, scatter_bytes(M_SCAT), M_SCAT))
     calls.append(("scatter_m2^24_n2^26", "vjp", svjp, scatter_vjp_bytes(M_SCAT), 0))
+    assert [(c[0], c[1]) for c in calls] == call_order()
     elems_per_step = sum(c[4] for c in calls)
 
     def step(evs=None):

@@ -395,6 +395,91 @@ __global__ __launch_bounds__(256) void hist_vjp_add_vec_kernel(const int32_t* __
     }
 }
 
+// Gather with the head of hs_bar staged in LDS.  A random 4-byte gather
+// served by L2 brings a whole cache line into the CU for each lane, so once
+// hs_bar outgrows the vector cache the gather is bound by the L2-to-CU fill
+// rate, not by HBM.  One 1024-thread block per CU copies the first L bins (up
+// to 160 KB) into LDS and serves them from there; bins at or beyond L come
+// from global memory as before.  Each thread keeps kGatherU index quads in
+// flight.
+constexpr int kGatherBlock = 1024;
+constexpr int kGatherLdsBytes = 160 * 1024;
+constexpr int kGatherU = 4;
+constexpr int32_t kGatherMinBins = 8192;  // below this hs_bar lives in the vector cache
+
+template <class T>
+__device__ __forceinline__ T gather_bin(const T* sh, int32_t L, const T* __restrict__ hsbar, int32_t m, int32_t k) {
+    if ((uint32_t)k < (uint32_t)L) return sh[k];
+    return ((uint32_t)k < (uint32_t)m) ? hsbar[k] : T(0);
+}
+
+template <class T, bool ACC>
+__global__ __launch_bounds__(kGatherBlock) void hist_vjp_add_lds_kernel(const int32_t* __restrict__ inds, int64_t n,
+                                                                        int32_t m, int32_t L,
+                                                                        const T* __restrict__ hsbar,
+                                                                        T* __restrict__ vsbar) {
+    extern __shared__ uint64_t gather_smem[];
+    T* sh = reinterpret_cast<T*>(gather_smem);
+    for (int t = threadIdx.x; t < L; t += kGatherBlock) sh[t] = hsbar[t];
+    __syncthreads();
+    const int64_t nq = n >> 2;
+    const int64_t step = (int64_t)gridDim.x * kGatherBlock;
+    for (int64_t q0 = (int64_t)blockIdx.x * kGatherBlock + threadIdx.x; q0 < nq; q0 += step * kGatherU) {
+        int4 k[kGatherU];
+#pragma unroll
+        for (int u = 0; u < kGatherU; ++u) {
+            const int64_t q = q0 + u * step;
+            k[u] = q < nq ? reinterpret_cast<const int4*>(inds)[q] : make_int4(-1, -1, -1, -1);
+        }
+#pragma unroll
+        for (int u = 0; u < kGatherU; ++u) {
+            const int64_t q = q0 + u * step;
+            if (q >= nq) break;
+            T g[4];
+            g[0] = gather_bin<T>(sh, L, hsbar, m, k[u].x);
+            g[1] = gather_bin<T>(sh, L, hsbar, m, k[u].y);
+            g[2] = gather_bin<T>(sh, L, hsbar, m, k[u].z);
+            g[3] = gather_bin<T>(sh, L, hsbar, m, k[u].w);
+            if (sizeof(T) == 4) {
+                float4* dst = reinterpret_cast<float4*>(vsbar) + q;
+                float4 o = make_float4((float)g[0], (float)g[1], (float)g[2], (float)g[3]);
+                if (ACC) {
+                    const float4 c = *dst;
+                    o.x += c.x, o.y += c.y, o.z += c.z, o.w += c.w;
+                }
+                *dst = o;
+            } else {
+                double2* dst = reinterpret_cast<double2*>(vsbar) + 2 * q;
+                double2 o0 = make_double2((double)g[0], (double)g[1]), o1 = make_double2((double)g[2], (double)g[3]);
+                if (ACC) {
+                    const double2 c0 = dst[0], c1 = dst[1];
+                    o0.x += c0.x, o0.y += c0.y, o1.x += c1.x, o1.y += c1.y;
+                }
+                dst[0] = o0;
+                dst[1] = o1;
+            }
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x < (n & 3)) {
+        const int64_t i = (nq << 2) + threadIdx.x;
+        const T g = gather_bin<T>(sh, L, hsbar, m, inds[i]);
+        vsbar[i] = ACC ? vsbar[i] + g : g;
+    }
+}
+
+// Lets the gather kernel take all of a CU's LDS dynamically (set once per
+// instantiation; a failure here surfaces as a launch error).
+template <class T, bool ACC>
+static void allow_gather_lds() {
+    static const bool once = [] {
+        if (hipFuncSetAttribute(reinterpret_cast<const void*>(&hist_vjp_add_lds_kernel<T, ACC>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kGatherLdsBytes) != hipSuccess)
+            (void)hipGetLastError();
+        return true;
+    }();
+    (void)once;
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void fill_zero_vec_kernel(T* __restrict__ x, int64_t n) {
     const int64_t nq = (int64_t)(n * sizeof(T)) >> 4;  // 16-byte words
@@ -473,10 +558,17 @@ __global__ __launch_bounds__(kHistBlock) void hpart_count_kernel(const int32_t* 
     const int64_t lo = (int64_t)blockIdx.x * chunk;
     const int64_t hi = (lo + chunk < n) ? lo + chunk : n;
     constexpr int64_t kStride = 4 * kHistBlock * kHistBatch;
-    for (int64_t base = lo; base < hi; base += kStride) {
-        int4 k[kHistBatch];
+    // the next batch's indices are in flight while this batch is counted
+    int4 k[kHistBatch], kn[kHistBatch];
 #pragma unroll
-        for (int u = 0; u < kHistBatch; ++u) k[u] = load_k4<VEC>(inds, base + 4 * ((int64_t)u * kHistBlock + threadIdx.x), hi);
+    for (int u = 0; u < kHistBatch; ++u) k[u] = load_k4<VEC>(inds, lo + 4 * ((int64_t)u * kHistBlock + threadIdx.x), hi);
+    for (int64_t base = lo; base < hi; base += kStride) {
+        const int64_t nbase = base + kStride;
+        if (nbase < hi) {
+#pragma unroll
+            for (int u = 0; u < kHistBatch; ++u)
+                kn[u] = load_k4<VEC>(inds, nbase + 4 * ((int64_t)u * kHistBlock + threadIdx.x), hi);
+        }
 #pragma unroll
         for (int u = 0; u < kHistBatch; ++u) {
             if ((uint32_t)k[u].x < (uint32_t)m) atomicAdd(&cnt[k[u].x >> kPartShift], 1);
@@ -484,6 +576,8 @@ __global__ __launch_bounds__(kHistBlock) void hpart_count_kernel(const int32_t* 
             if ((uint32_t)k[u].z < (uint32_t)m) atomicAdd(&cnt[k[u].z >> kPartShift], 1);
             if ((uint32_t)k[u].w < (uint32_t)m) atomicAdd(&cnt[k[u].w >> kPartShift], 1);
         }
+#pragma unroll
+        for (int u = 0; u < kHistBatch; ++u) k[u] = kn[u];
     }
     __syncthreads();
     for (int b = threadIdx.x; b < nb; b += kHistBlock) bcount[(int64_t)b * gridDim.x + blockIdx.x] = cnt[b];
@@ -521,7 +615,11 @@ __global__ __launch_bounds__(kPartScanThreads) void hpart_scan_kernel(const int3
 
 // Scatter of packed records into their buckets.  Each batch of 4096
 // elements is first counting-sorted by bucket in LDS, so that every bucket's
-// run of the batch leaves as one contiguous, coalesced write.
+// run of the batch leaves as one contiguous, coalesced write.  The next
+// batch's loads are issued before the current batch is ranked, staged and
+// written, so HBM reads overlap the LDS work.  For + the staged word carries
+// the full bin (its bucket is recomputed from it); for min/max the staged
+// word is the packed key and the bin is staged beside it.
 constexpr int kPartBatch = 4 * kHistBlock * kHistBatch;  // 4096 elements
 
 template <int OP, bool VEC>
@@ -536,8 +634,7 @@ __global__ __launch_bounds__(kHistBlock) void hpart_scatter_kernel(const int32_t
     __shared__ int32_t cur[kPartMaxBuckets];   // next global position of each bucket
     __shared__ int32_t bcnt[kPartMaxBuckets];  // batch count, then batch run start
     __shared__ uint64_t stage[kPartBatch];
-    __shared__ uint16_t sbkt[kPartBatch];
-    __shared__ uint16_t sbin[KEYS ? kPartBatch : 1];
+    __shared__ int32_t sbin[KEYS ? kPartBatch : 1];
     __shared__ IntSum::S wtot[kHistBlock / kWave];
     for (int b = threadIdx.x; b < nb; b += kHistBlock) {
         cur[b] = bstart[b] + local[(int64_t)b * gridDim.x + blockIdx.x];
@@ -546,11 +643,17 @@ __global__ __launch_bounds__(kHistBlock) void hpart_scatter_kernel(const int32_t
     __syncthreads();
     const int64_t lo = (int64_t)blockIdx.x * chunk;
     const int64_t hi = (lo + chunk < n) ? lo + chunk : n;
-    for (int64_t base = lo; base < hi; base += kPartBatch) {
-        Quad<float> q[kHistBatch];
+    Quad<float> q[kHistBatch], qn[kHistBatch];
 #pragma unroll
-        for (int u = 0; u < kHistBatch; ++u)
-            q[u] = load_quad<float, VEC>(inds, vs, base + 4 * ((int64_t)u * kHistBlock + threadIdx.x), hi);
+    for (int u = 0; u < kHistBatch; ++u)
+        q[u] = load_quad<float, VEC>(inds, vs, lo + 4 * ((int64_t)u * kHistBlock + threadIdx.x), hi);
+    for (int64_t base = lo; base < hi; base += kPartBatch) {
+        const int64_t nbase = base + kPartBatch;
+        if (nbase < hi) {
+#pragma unroll
+            for (int u = 0; u < kHistBatch; ++u)
+                qn[u] = load_quad<float, VEC>(inds, vs, nbase + 4 * ((int64_t)u * kHistBlock + threadIdx.x), hi);
+        }
         int rank[4 * kHistBatch];
 #pragma unroll
         for (int u = 0; u < kHistBatch; ++u) {
@@ -584,24 +687,28 @@ __global__ __launch_bounds__(kHistBlock) void hpart_scatter_kernel(const int32_t
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 if (rank[4 * u + t] < 0) continue;
-                const int b = kk[t] >> kPartShift;
-                const int slot = bcnt[b] + rank[4 * u + t];
-                const uint32_t j = (uint32_t)kk[t] & (kPartBins - 1);
+                const int slot = bcnt[kk[t] >> kPartShift] + rank[4 * u + t];
                 if (KEYS) {
                     stage[slot] = elem_key<OP>(q[u].v[t], e + t);
-                    sbin[slot] = (uint16_t)j;
+                    sbin[slot] = kk[t];
                 } else {
-                    stage[slot] = ((uint64_t)j << 32) | (uint64_t)__float_as_uint(q[u].v[t]);
+                    stage[slot] = ((uint64_t)(uint32_t)kk[t] << 32) | (uint64_t)__float_as_uint(q[u].v[t]);
                 }
-                sbkt[slot] = (uint16_t)b;
             }
         }
         __syncthreads();
         for (int sl = threadIdx.x; sl < tot.v; sl += kHistBlock) {
-            const int b = sbkt[sl];
+            const uint64_t w = stage[sl];
+            const int32_t k = KEYS ? sbin[sl] : (int32_t)(w >> 32);
+            const int b = k >> kPartShift;
             const int pos = cur[b] + (sl - bcnt[b]);
-            rec[pos] = stage[sl];
-            if (KEYS) rbin[pos] = sbin[sl];
+            const uint32_t j = (uint32_t)k & (kPartBins - 1);
+            if (KEYS) {
+                rec[pos] = w;
+                rbin[pos] = (uint16_t)j;
+            } else {
+                rec[pos] = ((uint64_t)j << 32) | (w & 0xffffffffull);
+            }
         }
         __syncthreads();
         // advance the cursors by the batch counts (run lengths) and reset
@@ -614,6 +721,8 @@ __global__ __launch_bounds__(kHistBlock) void hpart_scatter_kernel(const int32_t
         }
         __syncthreads();
         for (int b = threadIdx.x; b < nb; b += kHistBlock) bcnt[b] = 0;
+#pragma unroll
+        for (int u = 0; u < kHistBatch; ++u) q[u] = qn[u];
         __syncthreads();
     }
 }
@@ -642,15 +751,30 @@ __global__ __launch_bounds__(kHistBlock) void hpart_acc_kernel(const uint64_t* _
         if (COUNTS) cnt[j] = 0;
     }
     __syncthreads();
+    // Loads are clamped to the item's last record (never out of range) and
+    // the next round's loads are issued before this round's LDS atomics.
     constexpr int U = 8;
-    for (int64_t base = r0; base < r1; base += (int64_t)U * kHistBlock) {
-        uint64_t u[U];
-        uint32_t jb[U];
+    constexpr int64_t kRound = (int64_t)U * kHistBlock;
+    const int64_t last = r1 - 1;
+    uint64_t u[U], un[U];
+    uint32_t jb[U], jn[U];
 #pragma unroll
-        for (int t = 0; t < U; ++t) {
-            const int64_t r = base + (int64_t)t * kHistBlock + threadIdx.x;
-            u[t] = (r < r1) ? rec[r] : 0ull;
-            jb[t] = (OP == PVJP_ADD || r >= r1) ? 0u : (uint32_t)rbin[r];
+    for (int t = 0; t < U; ++t) {
+        const int64_t r = r0 + (int64_t)t * kHistBlock + threadIdx.x;
+        const int64_t rr = r < r1 ? r : last;
+        u[t] = rec[rr];
+        jb[t] = OP == PVJP_ADD ? 0u : (uint32_t)rbin[rr];
+    }
+    for (int64_t base = r0; base < r1; base += kRound) {
+        const int64_t nbase = base + kRound;
+        if (nbase < r1) {
+#pragma unroll
+            for (int t = 0; t < U; ++t) {
+                const int64_t r = nbase + (int64_t)t * kHistBlock + threadIdx.x;
+                const int64_t rr = r < r1 ? r : last;
+                un[t] = rec[rr];
+                jn[t] = OP == PVJP_ADD ? 0u : (uint32_t)rbin[rr];
+            }
         }
 #pragma unroll
         for (int t = 0; t < U; ++t) {
@@ -664,6 +788,11 @@ __global__ __launch_bounds__(kHistBlock) void hpart_acc_kernel(const uint64_t* _
                 atomicMax(reinterpret_cast<unsigned long long*>(&acc[jb[t]]), (unsigned long long)u[t]);
                 if (COUNTS) atomicAdd(&cnt[jb[t]], 1);
             }
+        }
+#pragma unroll
+        for (int t = 0; t < U; ++t) {
+            u[t] = un[t];
+            jb[t] = jn[t];
         }
     }
     __syncthreads();
@@ -921,7 +1050,20 @@ static void dispatch_vjp(pvjp_op op, const int32_t* inds, const void* vs, int64_
     const bool vec = aligned(inds, 16) && aligned(vsbar, 16);
     const unsigned gq = flat_grid(n, 256, 16);
     if (op == PVJP_ADD) {
-        if (vec && acc)
+        if (vec && m >= kGatherMinBins) {
+            const int32_t L = (int32_t)std::min<int64_t>(m, kGatherLdsBytes / (int)sizeof(T));
+            const size_t lds = (size_t)L * sizeof(T);
+            const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(kCuCount, ceil_div(n, 4 * kGatherBlock)));
+            if (acc) {
+                allow_gather_lds<T, true>();
+                hipLaunchKernelGGL((hist_vjp_add_lds_kernel<T, true>), dim3(g), dim3(kGatherBlock), lds, st, inds, n,
+                                   m, L, hb, vb);
+            } else {
+                allow_gather_lds<T, false>();
+                hipLaunchKernelGGL((hist_vjp_add_lds_kernel<T, false>), dim3(g), dim3(kGatherBlock), lds, st, inds, n,
+                                   m, L, hb, vb);
+            }
+        } else if (vec && acc)
             hipLaunchKernelGGL((hist_vjp_add_vec_kernel<T, true>), dim3(gq), dim3(256), 0, st, inds, n, m, hb, vb);
         else if (vec)
             hipLaunchKernelGGL((hist_vjp_add_vec_kernel<T, false>), dim3(gq), dim3(256), 0, st, inds, n, m, hb, vb);

@@ -59,15 +59,12 @@ __global__ __launch_bounds__(kScanBlock) void linrec_fwd_kernel(
     __shared__ S s_prefix;
 
     if (threadIdx.x == 0) {
-        lookback_begin(hdr, s_tag, s_ticket);
+        s_ticket = lookback_draw(hdr, (uint32_t)(ntiles - 1), &s_tag);
         if (s_ticket >= ntiles) lookback_error(hdr, kErrTicket);
     }
     __syncthreads();
     const uint32_t tag = s_tag;
-    if (s_ticket >= ntiles) {  // the workspace was not zero-filled: do nothing
-        lookback_end(hdr, tag);
-        return;
-    }
+    if (s_ticket >= ntiles) return;  // the workspace was not in its rest state: do nothing
     const int64_t tile = s_ticket;
     const int64_t base = tile * TS;
     const int cnt = (int)((n - base) < TS ? (n - base) : TS);
@@ -89,7 +86,7 @@ __global__ __launch_bounds__(kScanBlock) void linrec_fwd_kernel(
             if (threadIdx.x == 0) publish(&states[tile], total, kInc, tag);
         } else {
             if (threadIdx.x == 0) publish(&states[tile], total, kAgg, tag);
-            prefix = lookback<Op, false>(states, tile, ntiles, tag, hdr);
+            prefix = lookback<Op>(states, states + ntiles, tile, total, tag, hdr);
             if (threadIdx.x == 0) publish(&states[tile], Op::comb(prefix, total), kInc, tag);
         }
         if (threadIdx.x == 0) s_prefix = prefix;
@@ -113,7 +110,6 @@ __global__ __launch_bounds__(kScanBlock) void linrec_fwd_kernel(
         store_blocked<T, kScanBlock, IPT, false>(A + base, cnt, ra, lds);
         store_blocked<T, kScanBlock, IPT, false>(B + base, cnt, rb, lds);
     }
-    lookback_end(hdr, tag);
 }
 
 template <class T, bool ACC>
@@ -135,16 +131,14 @@ __global__ __launch_bounds__(kScanBlock) void linrec_vjp_kernel(
     __shared__ LS s_suffix;
 
     if (threadIdx.x == 0) {
-        lookback_begin(hdr, s_tag, s_ticket);
+        s_ticket = lookback_draw(hdr, (uint32_t)(ntiles - 1), &s_tag);
         if (s_ticket >= ntiles) lookback_error(hdr, kErrTicket);
     }
     __syncthreads();
     const uint32_t tag = s_tag;
-    if (s_ticket >= ntiles) {  // the workspace was not zero-filled: do nothing
-        lookback_end(hdr, tag);
-        return;
-    }
-    const int64_t tile = ntiles - 1 - (int64_t)s_ticket;  // reverse virtual order
+    if (s_ticket >= ntiles) return;  // the workspace was not in its rest state: do nothing
+    const int64_t v = s_ticket;            // virtual index: scan order
+    const int64_t tile = ntiles - 1 - v;  // tiles are taken right to left
     const int64_t base = tile * TS;
     const int cnt = (int)((n - base) < TS ? (n - base) : TS);
     const int first = (int)threadIdx.x * IPT;
@@ -207,12 +201,12 @@ __global__ __launch_bounds__(kScanBlock) void linrec_vjp_kernel(
     LS excl = block_exclusive_scan<L, kScanBlock, true>(agg, total, wtot_l);
     if (threadIdx.x < kWave) {
         LS suffix = L::id();
-        if (tile == ntiles - 1) {
-            if (threadIdx.x == 0) publish(&states[tile], total, kInc, tag);
+        if (v == 0) {
+            if (threadIdx.x == 0) publish(&states[v], total, kInc, tag);
         } else {
-            if (threadIdx.x == 0) publish(&states[tile], total, kAgg, tag);
-            suffix = lookback<L, true>(states, tile, ntiles, tag, hdr);
-            if (threadIdx.x == 0) publish(&states[tile], L::comb(suffix, total), kInc, tag);
+            if (threadIdx.x == 0) publish(&states[v], total, kAgg, tag);
+            suffix = lookback<L>(states, states + ntiles, v, total, tag, hdr);
+            if (threadIdx.x == 0) publish(&states[v], L::comb(suffix, total), kInc, tag);
         }
         if (threadIdx.x == 0) s_suffix = suffix;
     }
@@ -228,13 +222,12 @@ __global__ __launch_bounds__(kScanBlock) void linrec_vjp_kernel(
     }
     store_blocked<T, kScanBlock, IPT, ACC>(abar + base, cnt, ra, lds);
     store_blocked<T, kScanBlock, IPT, ACC>(bbar + base, cnt, rb, lds);
-    lookback_end(hdr, tag);
 }
 
 // ------------------------------------------------------------------ host
 template <class S>
 static size_t lookback_bytes(int64_t ntiles) {
-    return sizeof(LookbackHdr) + (size_t)ntiles * sizeof(TileState<S>);
+    return sizeof(LookbackHdr) + lookback_state_bytes<S>(ntiles);
 }
 
 template <class T>
@@ -242,11 +235,11 @@ static size_t fwd_ws(int64_t n) {
     return lookback_bytes<typename LinRec<T>::S>(ceil_div(n, scan_tile<T>()));
 }
 
-// Workspace layout of both entry points: [header | tile states | ckpt].  The
-// checkpoint-only pre-pass of the VJP and the VJP itself run one after the
-// other on the same header and tile states (tile states are 64 bytes for both
-// operators and both use the same tile size), so every launch on a workspace
-// takes its tag from the one epoch sequence.
+// Workspace layout of both entry points: [header | tile states | group
+// states | ckpt].  The checkpoint-only pre-pass of the VJP and the VJP itself
+// run one after the other on the same header and states (states are 128
+// bytes for both operators and both use the same tile size), so every launch
+// on a workspace takes its tag from the one epoch sequence.
 template <class T>
 static size_t vjp_ws(int64_t n) {
     const int64_t nt = ceil_div(n, scan_tile<T>());

@@ -185,32 +185,40 @@ __device__ __forceinline__ void store_blocked(T* __restrict__ dst, int cnt, cons
 }
 
 // ------------------------------------------------------ decoupled lookback
-// Workspace header.  The whole workspace starts zeroed; the last block of
-// every launch resets `ticket` and `done` and advances `epoch`, so the next
-// launch on the same workspace needs no clearing.  A tile's flag carries the
-// launch tag (epoch + 1) in its upper 30 bits, which makes flags left by an
-// earlier launch read as "not yet published".
+// Workspace header.  The whole workspace starts zeroed.  `seq` holds the
+// launch epoch (high 32 bits) and the next tile ticket (low 32 bits), so one
+// relaxed fetch-add gives a block both its launch tag (epoch + 1) and its
+// ticket.  The block that draws the launch's last ticket stores the next
+// epoch with a zero ticket: every other block of the launch has drawn by
+// then, and the next launch on the workspace (stream-ordered after this one)
+// starts from a clean counter.  No per-block completion counter is needed:
+// on this chip every same-address device-scope atomic costs about 11 ns of
+// serialised time, which at 2^15 tiles would exceed the scan itself.
 //
-// Every lookback kernel that uses a workspace shares this one header at
-// offset 0, so launches on a workspace draw their tags from one increasing
-// sequence and a stale flag can never carry the current tag.  `error` is set
-// (and stays set until cleared by the host) when a launch sees a ticket
-// outside its grid or gives up waiting on a predecessor; either means the
-// workspace was not in the state this protocol leaves it in.
+// A tile's flag carries the launch tag in its upper 30 bits, which makes
+// flags left by an earlier launch read as "not yet published".  Every
+// lookback kernel that uses a workspace shares this one header at offset 0,
+// so launches on a workspace draw their tags from one increasing sequence
+// and a stale flag can never carry the current tag.  `error` is set (and
+// stays set until cleared by the host) when a launch sees a ticket beyond
+// its last or gives up waiting on a predecessor; either means the workspace
+// was not in the state this protocol leaves it in.  `done` is the
+// completion counter of the single-launch reductions (reduce, GMM), which
+// reset it themselves.
 struct alignas(256) LookbackHdr {
-    uint32_t ticket;
+    uint64_t seq;
     uint32_t done;
-    uint32_t epoch;
     uint32_t error;
     uint32_t pad[60];
 };
 
 constexpr uint32_t kErrTicket = 1u;  // ticket outside the grid
 constexpr uint32_t kErrSpin = 2u;    // a predecessor never published
-// Bound on polls of one predecessor flag (each poll sleeps ~64 cycles plus a
-// device-scope load): seconds, far beyond any legitimate wait, so a corrupted
-// workspace ends the kernel with an error instead of hanging it.
+// Bound on polls of one predecessor (each poll sleeps ~64 cycles plus a
+// device-scope load): seconds, far beyond any legitimate wait, so a
+// corrupted workspace ends the kernel with an error instead of hanging it.
 constexpr uint32_t kMaxPolls = 1u << 20;
+constexpr uint32_t kTagMod = (1u << 30) - 1u;  // tags are 1 .. 2^30 - 1
 
 // A tile's published states.  Every 32-bit word of a state travels together
 // with its launch tag and status in one 64-bit relaxed atomic, so a reader
@@ -227,6 +235,21 @@ struct alignas(128) TileState {
 
 constexpr uint32_t kAgg = 1u, kInc = 2u;
 
+// Tiles are grouped by 64 consecutive virtual indices.  The last tile of a
+// group publishes the group's aggregate (in the `agg` field of a group
+// state) as soon as it has read its group-mates' aggregates, so a lookback
+// crosses 64 tiles per state read once it leaves its own group.
+constexpr int kGroupShift = 6;
+constexpr int64_t kGroup = (int64_t)1 << kGroupShift;
+
+inline int64_t lookback_groups(int64_t ntiles) { return (ntiles + kGroup - 1) >> kGroupShift; }
+
+// Bytes of tile and group states for `ntiles` tiles.
+template <class S>
+inline size_t lookback_state_bytes(int64_t ntiles) {
+    return (size_t)(ntiles + lookback_groups(ntiles)) * sizeof(TileState<S>);
+}
+
 template <class S>
 __device__ __forceinline__ void publish(TileState<S>* st, const S& v, uint32_t status, uint32_t tag) {
     static_assert(sizeof(S) % 4 == 0, "state must be a whole number of words");
@@ -236,24 +259,6 @@ __device__ __forceinline__ void publish(TileState<S>* st, const S& v, uint32_t s
 #pragma unroll
     for (int w = 0; w < TileState<S>::W; ++w)
         __hip_atomic_store(dst + w, hi | (uint64_t)src[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Reads a field whose first word already showed `hi`; spins (bounded) on any
-// word not yet visible.  Returns false if a word never showed up.
-template <class S>
-__device__ __forceinline__ bool read_state(const uint64_t* f, uint64_t hi, S& v) {
-    uint32_t* dst = reinterpret_cast<uint32_t*>(&v);
-#pragma unroll
-    for (int w = 0; w < TileState<S>::W; ++w) {
-        uint64_t u;
-        uint32_t polls = 0;
-        while (((u = __hip_atomic_load(f + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) & ~0xffffffffull) != hi) {
-            if (++polls == (1u << 20)) return false;
-            __builtin_amdgcn_s_sleep(1);
-        }
-        dst[w] = (uint32_t)u;
-    }
-    return true;
 }
 
 // Coherent word-wise store/load of small records (reduction partials).
@@ -278,13 +283,20 @@ __device__ __forceinline__ S ld_coherent(const S* p) {
     return v;
 }
 
-// Called by thread 0 at kernel start: fetches the launch tag and a dynamic
-// tile ticket (tickets are handed out in the order blocks actually start, so
-// every tile a block waits on is already resident: no deadlock).
-__device__ __forceinline__ void lookback_begin(LookbackHdr* h, uint32_t& tag, uint32_t& ticket) {
-    tag = __hip_atomic_load(&h->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-    if (tag >= (1u << 30)) tag = 1u;  // flags hold 30 tag bits; 0 never matches
-    ticket = __hip_atomic_fetch_add(&h->ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Draws the next ticket of this launch; `last` is the value of the launch's
+// final draw (grid size - 1 for one draw per block; items + grid - 1 for a
+// persistent queue whose blocks each make one last, empty draw).  Called by
+// one thread.  Tickets are handed out in the order blocks ask, so every tile
+// a block waits on is held by a block that is already running: no deadlock.
+__device__ __forceinline__ uint32_t lookback_draw(LookbackHdr* h, uint32_t last, uint32_t* tag) {
+    const uint64_t old = __hip_atomic_fetch_add(&h->seq, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t epoch = (uint32_t)(old >> 32);
+    const uint32_t ticket = (uint32_t)old;
+    if (tag) *tag = (epoch % kTagMod) + 1u;
+    if (ticket == last)
+        __hip_atomic_store(&h->seq, (uint64_t)((epoch + 1u) % kTagMod) << 32, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    return ticket;
 }
 
 // Thread 0 records a workspace error (see LookbackHdr).
@@ -292,81 +304,131 @@ __device__ __forceinline__ void lookback_error(LookbackHdr* h, uint32_t bits) {
     __hip_atomic_fetch_or(&h->error, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Called by every thread at kernel end.  The last block to finish resets the
-// counters for the next launch on this workspace.
-__device__ __forceinline__ void lookback_end(LookbackHdr* h, uint32_t tag) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        // Relaxed: the reset only has to be visible to the next launch, which
-        // the kernel boundary orders.
-        uint32_t d = __hip_atomic_fetch_add(&h->done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (d == gridDim.x - 1) {
-            __hip_atomic_store(&h->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&h->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&h->epoch, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+// Tries to take a state in one round trip: every tagged word of the
+// inclusive field (at `inc`) and of the aggregate field (at `agg`) is loaded
+// before any is examined.  Returns kInc or kAgg when all words of that field
+// carry the current tag, 0 when neither is complete.
+template <class S>
+__device__ __forceinline__ uint32_t try_state(const uint64_t* inc, const uint64_t* agg, uint64_t hinc,
+                                              uint64_t hagg, S& v) {
+    constexpr int W = TileState<S>::W;
+    constexpr uint64_t mask = ~0xffffffffull;
+    uint64_t wi[W], wa[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) wi[w] = __hip_atomic_load(inc + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+    for (int w = 0; w < W; ++w) wa[w] = __hip_atomic_load(agg + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    bool inc_ok = true, agg_ok = true;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        inc_ok = inc_ok && (wi[w] & mask) == hinc;
+        agg_ok = agg_ok && (wa[w] & mask) == hagg;
     }
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&v);
+    if (inc_ok) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) dst[w] = (uint32_t)wi[w];
+        return kInc;
+    }
+    if (agg_ok) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) dst[w] = (uint32_t)wa[w];
+        return kAgg;
+    }
+    return 0u;
 }
 
-// Executed by all 64 lanes of one wave.  Returns the exclusive prefix (in
-// scan order) of tile `tile`, combining the published states of its
-// predecessors in scan order: tiles tile-1, tile-2, ... (forward) or tile+1,
-// tile+2, ... (REV), 64 at a time, stopping at the nearest inclusive state.
-// Positions before the first tile read as an inclusive neutral element.
-template <class Op, bool REV>
-__device__ typename Op::S lookback(TileState<typename Op::S>* states, int64_t tile, int64_t ntiles,
-                                   uint32_t tag, LookbackHdr* hdr) {
+// try_state, polled until it succeeds.  While a state is missing only the
+// first word of each field is polled (two loads), with a growing pause
+// between polls: hundreds of waiting waves polling every word at full rate
+// would take memory bandwidth from the tiles still streaming their data.
+// Bounded: a state that never shows up is recorded in the header and read
+// as an inclusive neutral element, so the kernel still terminates.
+template <class Op>
+__device__ __forceinline__ uint32_t wait_state(const uint64_t* inc, const uint64_t* agg, uint64_t hinc, uint64_t hagg,
+                                               typename Op::S& v, LookbackHdr* hdr) {
+    constexpr uint64_t mask = ~0xffffffffull;
+    uint32_t st = try_state(inc, agg, hinc, hagg, v);
+    uint32_t polls = 0, pause = 1;
+    while (st == 0u) {
+        for (uint32_t i = 0; i < pause; ++i) __builtin_amdgcn_s_sleep(2);
+        if (pause < 16) pause <<= 1;
+        const uint64_t f0 = __hip_atomic_load(inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t f1 = __hip_atomic_load(agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((f0 & mask) == hinc || (f1 & mask) == hagg) st = try_state(inc, agg, hinc, hagg, v);
+        if (st == 0u && ++polls == kMaxPolls) {
+            __hip_atomic_fetch_or(&hdr->error, kErrSpin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            v = Op::id();
+            return kInc;
+        }
+    }
+    return st;
+}
+
+// Ordered combination of one value per lane, lanes 0..k (lane 0 latest in
+// scan order, higher lanes earlier); lanes above k hold the neutral element.
+// Returns the combination, valid in lane 0 and broadcast.
+template <class Op>
+__device__ __forceinline__ typename Op::S lane_fold(typename Op::S mine, int k, int lane) {
+    if (lane > k) mine = Op::id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        typename Op::S o = Op::down(mine, d);
+        if (lane + d < kWave) mine = Op::comb(o, mine);
+    }
+    return Op::idx(mine, 0);
+}
+
+// Executed by all 64 lanes of one wave of the block holding virtual tile
+// v > 0 (virtual order is scan order; tile 0 publishes its inclusive state
+// without a lookback).  `own` is the tile's aggregate, already published.
+// Returns the exclusive prefix of v:
+//   1. the predecessors inside v's group of 64, nearest first, up to the
+//      nearest inclusive state;
+//   2. if none is inclusive, the earlier groups, 64 per round: a group
+//      contributes the inclusive state of its last tile when published, else
+//      the group aggregate.
+// The last tile of a group that reaches step 2 publishes the group aggregate
+// (its predecessors' aggregates and its own) before it looks further back.
+template <class Op>
+__device__ typename Op::S lookback(TileState<typename Op::S>* states, TileState<typename Op::S>* groups, int64_t v,
+                                   const typename Op::S& own, uint32_t tag, LookbackHdr* hdr) {
     using S = typename Op::S;
     const int lane = threadIdx.x & (kWave - 1);
-    S prefix = Op::id();
-    int64_t base = tile;
-    while (true) {
-        const int64_t p = REV ? base + 1 + lane : base - 1 - lane;
-        const bool virt = REV ? (p >= ntiles) : (p < 0);
-        uint32_t status = kInc;
-        S v = Op::id();
-        if (!virt) {
-            const uint64_t hinc = (uint64_t)((tag << 2) | kInc) << 32;
-            const uint64_t hagg = (uint64_t)((tag << 2) | kAgg) << 32;
-            const uint64_t mask = ~0xffffffffull;
-            uint32_t polls = 0;
-            status = 0;
-            while (true) {
-                if ((__hip_atomic_load(&states[p].inc[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & mask) == hinc) {
-                    status = kInc;
-                    break;
-                }
-                if ((__hip_atomic_load(&states[p].agg[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & mask) == hagg) {
-                    status = kAgg;
-                    break;
-                }
-                if (++polls == kMaxPolls) break;
-                __builtin_amdgcn_s_sleep(1);
+    const uint64_t hinc = (uint64_t)((tag << 2) | kInc) << 32;
+    const uint64_t hagg = (uint64_t)((tag << 2) | kAgg) << 32;
+    const int64_t g = v >> kGroupShift;
+    const int64_t g0 = g << kGroupShift;
+
+    // 1. inside the group
+    {
+        const int64_t p = v - 1 - lane;
+        S val = Op::id();
+        uint32_t st = 0u;
+        if (p >= g0) st = wait_state<Op>(states[p].inc, states[p].agg, hinc, hagg, val, hdr);
+        const uint64_t incl = __ballot(st == kInc);
+        const int k = incl ? __ffsll((unsigned long long)incl) - 1 : kWave - 1;
+        S prefix = lane_fold<Op>(val, k, lane);
+        if (incl) return prefix;
+        if ((v & (kGroup - 1)) == kGroup - 1 && lane == 0) publish(&groups[g], Op::comb(prefix, own), kAgg, tag);
+        // 2. earlier groups (g0 > 0 here: tile 0 is inclusive, so group 0
+        //    always ends in step 1)
+        int64_t h0 = g - 1;
+        while (true) {
+            const int64_t h = h0 - lane;
+            S gv = Op::id();
+            uint32_t gs = kInc;  // before the first group: neutral, inclusive
+            if (h >= 0) {
+                const int64_t last = (h << kGroupShift) + kGroup - 1;
+                gs = wait_state<Op>(states[last].inc, groups[h].agg, hinc, hagg, gv, hdr);
             }
-            if (status == 0 || !read_state(status == kInc ? states[p].inc : states[p].agg,
-                                           status == kInc ? hinc : hagg, v)) {
-                // A predecessor never published: record it and end the wait
-                // (results are invalid, but the kernel terminates).
-                __hip_atomic_fetch_or(&hdr->error, kErrSpin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                status = kInc;
-                v = Op::id();
-            }
+            const uint64_t gincl = __ballot(gs == kInc);
+            const int gk = gincl ? __ffsll((unsigned long long)gincl) - 1 : kWave - 1;
+            prefix = Op::comb(lane_fold<Op>(gv, gk, lane), prefix);
+            if (gincl) return prefix;
+            h0 -= kWave;
         }
-        const uint64_t incl = __ballot(status == kInc);
-        const int k = incl ? __ffsll((unsigned long long)incl) - 1 : kWave;
-        S mine = (lane <= k) ? v : Op::id();
-        // Ordered reduction: lane 0 ends with v_k (+) ... (+) v_0, higher lanes
-        // being earlier in scan order.
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            S o = Op::down(mine, d);
-            if (lane + d < kWave) mine = Op::comb(o, mine);
-        }
-        prefix = Op::comb(Op::idx(mine, 0), prefix);
-        if (incl) break;
-        base = REV ? base + kWave : base - kWave;
     }
-    return prefix;
 }
 
 }  // namespace pvjp

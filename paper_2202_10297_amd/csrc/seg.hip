@@ -33,8 +33,8 @@ static_assert(sizeof(TileState<SegLinRec<double>::S>) == kSegState && sizeof(Til
                   sizeof(TileState<SegLinRec<float>::S>) == kSegState && sizeof(TileState<LinO<float>::S>) == kSegState,
               "tile states of both sweeps share one slot per tile");
 
-// Workspace: [LookbackHdr | tile states (128 B each) | tile_seg0 int32[ntiles+1] |
-//             offsets int64[nseg+1]]
+// Workspace: [LookbackHdr | tile and group states (128 B each) |
+//             tile_seg0 int32[ntiles+1] | offsets int64[nseg+1]]
 struct SegLayout {
     size_t states, seg0, offs, total;
     int64_t ntiles;
@@ -44,7 +44,7 @@ static SegLayout seg_layout(int64_t total, int64_t nseg, int ts) {
     SegLayout L{};
     L.ntiles = ceil_div(total > 0 ? total : 1, ts);
     L.states = sizeof(LookbackHdr);
-    L.seg0 = L.states + align_up((size_t)L.ntiles * kSegState, 256);
+    L.seg0 = L.states + align_up((size_t)(L.ntiles + lookback_groups(L.ntiles)) * kSegState, 256);
     L.offs = L.seg0 + align_up((size_t)(L.ntiles + 1) * 4, 256);
     L.total = L.offs + align_up((size_t)(nseg + 1) * 8, 256);
     return L;
@@ -88,15 +88,12 @@ __global__ __launch_bounds__(kSegBlock) void seg_linrec_fwd_kernel(
     __shared__ S s_prefix;
 
     if (threadIdx.x == 0) {
-        lookback_begin(hdr, s_tag, s_ticket);
+        s_ticket = lookback_draw(hdr, (uint32_t)(ntiles - 1), &s_tag);
         if (s_ticket >= ntiles) lookback_error(hdr, kErrTicket);
     }
     __syncthreads();
     const uint32_t tag = s_tag;
-    if (s_ticket >= ntiles) {
-        lookback_end(hdr, tag);
-        return;
-    }
+    if (s_ticket >= ntiles) return;  // the workspace was not in its rest state: do nothing
     const int64_t tile = s_ticket;
     const int64_t base = tile * TS;
     const int cnt = (int)((total - base) < TS ? (total - base) : TS);
@@ -122,7 +119,7 @@ __global__ __launch_bounds__(kSegBlock) void seg_linrec_fwd_kernel(
             if (threadIdx.x == 0) publish(&states[tile], tot, kInc, tag);
         } else {
             if (threadIdx.x == 0) publish(&states[tile], tot, kAgg, tag);
-            prefix = lookback<Op, false>(states, tile, ntiles, tag, hdr);
+            prefix = lookback<Op>(states, states + ntiles, tile, tot, tag, hdr);
             if (threadIdx.x == 0) publish(&states[tile], Op::comb(prefix, tot), kInc, tag);
         }
         if (threadIdx.x == 0) s_prefix = prefix;
@@ -144,7 +141,6 @@ __global__ __launch_bounds__(kSegBlock) void seg_linrec_fwd_kernel(
         store_blocked<T, kSegBlock, IPT, false>(A + base, cnt, ra, lds);
         store_blocked<T, kSegBlock, IPT, false>(B + base, cnt, rb, lds);
     }
-    lookback_end(hdr, tag);
 }
 
 // ----------------------------------------------------------- return sweep
@@ -154,7 +150,7 @@ __device__ __forceinline__ void seg_scan_vjp_tile(const T* __restrict__ a, const
                                                   int64_t total, const T* __restrict__ ckpt, T* __restrict__ abar,
                                                   T* __restrict__ bbar, LookbackHdr* hdr,
                                                   TileState<typename LinO<T>::S>* states, int64_t ntiles,
-                                                  int64_t tile, uint32_t tag, T* lds, const uint32_t* bits,
+                                                  int64_t v, uint32_t tag, T* lds, const uint32_t* bits,
                                                   typename SegLinRec<T>::S* wtot_p, typename LinO<T>::S* wtot_l,
                                                   typename LinO<T>::S* s_suffix) {
     using P = SegLinRec<T>;
@@ -162,6 +158,7 @@ __device__ __forceinline__ void seg_scan_vjp_tile(const T* __restrict__ a, const
     using PS = typename P::S;
     using LS = typename L::S;
     constexpr int TS = kSegBlock * IPT;
+    const int64_t tile = ntiles - 1 - v;  // virtual order runs right to left
     const int64_t base = tile * TS;
     const int cnt = (int)((total - base) < TS ? (total - base) : TS);
     const int first = (int)threadIdx.x * IPT;
@@ -222,12 +219,12 @@ __device__ __forceinline__ void seg_scan_vjp_tile(const T* __restrict__ a, const
     LS excl = block_exclusive_scan<L, kSegBlock, true>(agg, tot, wtot_l);
     if (threadIdx.x < kWave) {
         LS suffix = L::id();
-        if (tile == ntiles - 1) {
-            if (threadIdx.x == 0) publish(&states[tile], tot, kInc, tag);
+        if (v == 0) {
+            if (threadIdx.x == 0) publish(&states[v], tot, kInc, tag);
         } else {
-            if (threadIdx.x == 0) publish(&states[tile], tot, kAgg, tag);
-            suffix = lookback<L, true>(states, tile, ntiles, tag, hdr);
-            if (threadIdx.x == 0) publish(&states[tile], L::comb(suffix, tot), kInc, tag);
+            if (threadIdx.x == 0) publish(&states[v], tot, kAgg, tag);
+            suffix = lookback<L>(states, states + ntiles, v, tot, tag, hdr);
+            if (threadIdx.x == 0) publish(&states[v], L::comb(suffix, tot), kInc, tag);
         }
         if (threadIdx.x == 0) *s_suffix = suffix;
     }
@@ -285,9 +282,15 @@ __global__ __launch_bounds__(kSegBlock) void seg_batch_vjp_kernel(
     __shared__ uint32_t bits[(TS + 1 + 31) / 32];
     __shared__ uint32_t s_tag, s_ticket;
 
-    if (threadIdx.x == 0) lookback_begin(hdr, s_tag, s_ticket);
+    // every block makes one final, empty draw: the launch's last ticket
+    const uint32_t last = (uint32_t)(nscan + nsum + gridDim.x - 1);
+    if (threadIdx.x == 0) {
+        s_ticket = lookback_draw(hdr, last, &s_tag);
+        if (s_ticket > last) lookback_error(hdr, kErrTicket);
+    }
     __syncthreads();
     const uint32_t tag = s_tag;
+    if (s_ticket > last) return;  // the workspace was not in its rest state: do nothing
     // Queue: items [0, nscan) are the scan tiles in reverse order, items
     // [nscan, nscan + nsum) the sum tiles.  A block only waits (in the
     // lookback) on scan items dequeued before its own, which running blocks
@@ -298,7 +301,7 @@ __global__ __launch_bounds__(kSegBlock) void seg_batch_vjp_kernel(
         if (item < nscan) {
             const int64_t tile = ntiles - 1 - item;  // reverse order inside the scan part
             build_heads<TS>(bits, seg0, offs, nseg, tile, tile * TS);
-            seg_scan_vjp_tile<T, IPT, ACC>(a, b, ya, yb, total, ckpt, abar, bbar, hdr, states, ntiles, tile, tag, lds,
+            seg_scan_vjp_tile<T, IPT, ACC>(a, b, ya, yb, total, ckpt, abar, bbar, hdr, states, ntiles, item, tag, lds,
                                            bits, wtot_p, wtot_l, &s_suffix);
         } else {
             const int64_t tile = item - nscan;
@@ -306,11 +309,9 @@ __global__ __launch_bounds__(kSegBlock) void seg_batch_vjp_kernel(
             seg_sum_vjp_tile<T, IPT, ACC>(total, seg0, sum_ybar, sum_xbar, tile, bits, lds, wtot_i);
         }
         __syncthreads();
-        if (threadIdx.x == 0)
-            s_ticket = __hip_atomic_fetch_add(&hdr->ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x == 0) s_ticket = lookback_draw(hdr, last, nullptr);
         __syncthreads();
     }
-    lookback_end(hdr, tag);
 }
 
 // ------------------------------------------------------------------ host

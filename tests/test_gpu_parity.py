@@ -246,6 +246,27 @@ def test_hist_mul(ops, orc, dtype, n, m):
     assert rel_l2(vb, orc.hist_vjp("mul", inds, vs, hb)) <= tol(dtype)
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("m", [8192, 20480, 20481, 40960, 40961, 1 << 17])
+@pytest.mark.parametrize("accumulate", [False, True])
+def test_hist_add_vjp_gather_paths(ops, orc, dtype, m, accumulate):
+    # Bins below and beyond the LDS-staged head, out-of-range indices, and a
+    # length that is not a multiple of 4 (the tail is done separately).
+    n = 262147
+    g = workloads.rng(m + accumulate)
+    inds = g.integers(-5, m + 5, n).astype(np.int32)
+    inds[::3] = g.integers(0, 64, inds[::3].size)  # a hot head
+    vs = g.standard_normal(n).astype(np.float32 if dtype == "f32" else np.float64)
+    hb = g.standard_normal(m).astype(vs.dtype)
+    base = g.standard_normal(n).astype(vs.dtype)
+    aux = {}
+    vb = dev(base) if accumulate else None
+    out = ops.hist_vjp("add", dev(inds), None, m, aux, dev(hb), vs_bar=vb, accumulate=accumulate)
+    got = host(out)
+    ref = orc.hist_vjp("add", inds, vs, hb).astype(vs.dtype)
+    assert np.array_equal(got, base + ref if accumulate else ref)
+
+
 def test_hist_out_of_range_and_accumulate(ops, orc):
     n, m = 100000, 300
     g = workloads.rng(3)
