@@ -44,11 +44,14 @@ constexpr int scan_tile() {
 static_assert(scan_tile<double>() % kCk == 0 && scan_tile<float>() % kCk == 0,
               "scan tiles must be whole checkpoint intervals");
 
-template <class T>
+// GIVEN = false: single pass, the tile's exclusive prefix comes from the
+// decoupled lookback (tiles taken in ticket order).  GIVEN = true: third
+// pass of the reduce-then-scan form, the prefix is read from `pre`.
+template <class T, bool GIVEN>
 __global__ __launch_bounds__(kScanBlock) void linrec_fwd_kernel(
     const T* __restrict__ a, const T* __restrict__ b, int64_t n, T* __restrict__ A,
     T* __restrict__ B, T* __restrict__ ckpt, LookbackHdr* hdr,
-    TileState<typename LinRec<T>::S>* states, int64_t ntiles) {
+    TileState<typename LinRec<T>::S>* states, int64_t ntiles, const typename LinRec<T>::S* __restrict__ pre) {
     using Op = LinRec<T>;
     using S = typename Op::S;
     constexpr int IPT = ScanCfg<T>::IPT;
@@ -58,7 +61,9 @@ __global__ __launch_bounds__(kScanBlock) void linrec_fwd_kernel(
     __shared__ uint32_t s_tag, s_ticket;
     __shared__ S s_prefix;
 
-    if (threadIdx.x == 0) {
+    if (GIVEN) {
+        if (threadIdx.x == 0) s_ticket = blockIdx.x;
+    } else if (threadIdx.x == 0) {
         s_ticket = lookback_draw(hdr, (uint32_t)(ntiles - 1), &s_tag);
         if (s_ticket >= ntiles) lookback_error(hdr, kErrTicket);
     }
@@ -80,7 +85,9 @@ __global__ __launch_bounds__(kScanBlock) void linrec_fwd_kernel(
     S total;
     S excl = block_exclusive_scan<Op, kScanBlock, false>(agg, total, wtot);
 
-    if (threadIdx.x < kWave) {
+    if (GIVEN) {
+        if (threadIdx.x == 0) s_prefix = pre[tile];
+    } else if (threadIdx.x < kWave) {
         S prefix = Op::id();
         if (tile == 0) {
             if (threadIdx.x == 0) publish(&states[tile], total, kInc, tag);
@@ -112,12 +119,14 @@ __global__ __launch_bounds__(kScanBlock) void linrec_fwd_kernel(
     }
 }
 
-template <class T, bool ACC>
+// GIVEN as for the primal: the tile's suffix (in the reversed scan order)
+// comes from the lookback, or from `pre` in the three-pass form.
+template <class T, bool ACC, bool GIVEN>
 __global__ __launch_bounds__(kScanBlock) void linrec_vjp_kernel(
     const T* __restrict__ a, const T* __restrict__ b, const T* __restrict__ ya,
     const T* __restrict__ yb, int64_t n, const T* __restrict__ ckpt, T* __restrict__ abar,
     T* __restrict__ bbar, LookbackHdr* hdr, TileState<typename LinO<T>::S>* states,
-    int64_t ntiles) {
+    int64_t ntiles, const typename LinO<T>::S* __restrict__ pre) {
     using P = LinRec<T>;
     using L = LinO<T>;
     using PS = typename P::S;
@@ -130,7 +139,9 @@ __global__ __launch_bounds__(kScanBlock) void linrec_vjp_kernel(
     __shared__ uint32_t s_tag, s_ticket;
     __shared__ LS s_suffix;
 
-    if (threadIdx.x == 0) {
+    if (GIVEN) {
+        if (threadIdx.x == 0) s_ticket = blockIdx.x;
+    } else if (threadIdx.x == 0) {
         s_ticket = lookback_draw(hdr, (uint32_t)(ntiles - 1), &s_tag);
         if (s_ticket >= ntiles) lookback_error(hdr, kErrTicket);
     }
@@ -199,7 +210,9 @@ __global__ __launch_bounds__(kScanBlock) void linrec_vjp_kernel(
     for (int j = IPT - 1; j >= 0; --j) agg = L::comb(agg, e[j]);
     LS total;
     LS excl = block_exclusive_scan<L, kScanBlock, true>(agg, total, wtot_l);
-    if (threadIdx.x < kWave) {
+    if (GIVEN) {
+        if (threadIdx.x == 0) s_suffix = pre[tile];
+    } else if (threadIdx.x < kWave) {
         LS suffix = L::id();
         if (v == 0) {
             if (threadIdx.x == 0) publish(&states[v], total, kInc, tag);
@@ -224,10 +237,135 @@ __global__ __launch_bounds__(kScanBlock) void linrec_vjp_kernel(
     store_blocked<T, kScanBlock, IPT, ACC>(bbar + base, cnt, rb, lds);
 }
 
+// ------------------------------------------------- reduce-then-scan form
+// For long inputs the single pass is bound by its lookback: with the tens of
+// MB in flight that saturate HBM, every device-scope round trip waits
+// behind them, and each tile pays several such trips on its critical path.
+// The three-pass form has none: (1) every tile writes its aggregate,
+// (2) one block scans the aggregates, (3) every tile re-reads its input and
+// applies its prefix.  It moves 16 (primal, FP64) or 24 (VJP) more bytes
+// per element but streams at full rate.
+
+// (1) primal tile aggregates
+template <class T>
+__global__ __launch_bounds__(kScanBlock) void linrec_tile_agg_kernel(const T* __restrict__ a, const T* __restrict__ b,
+                                                                     int64_t n, typename LinRec<T>::S* __restrict__ agg) {
+    using Op = LinRec<T>;
+    using S = typename Op::S;
+    constexpr int IPT = ScanCfg<T>::IPT;
+    constexpr int TS = kScanBlock * IPT;
+    __shared__ T lds[lds_elems<T, TS>()];
+    __shared__ S wtot[kScanBlock / kWave];
+    const int64_t tile = blockIdx.x;
+    const int64_t base = tile * TS;
+    const int cnt = (int)((n - base) < TS ? (n - base) : TS);
+    T ra[IPT], rb[IPT];
+    load_blocked<T, kScanBlock, IPT>(a + base, cnt, ra, lds, T(1));
+    __syncthreads();
+    load_blocked<T, kScanBlock, IPT>(b + base, cnt, rb, lds, T(0));
+    S v = S{ra[0], rb[0]};
+#pragma unroll
+    for (int j = 1; j < IPT; ++j) v = Op::comb(v, S{ra[j], rb[j]});
+    S total;
+    (void)block_exclusive_scan<Op, kScanBlock, false>(v, total, wtot);
+    if (threadIdx.x == 0) agg[tile] = total;
+}
+
+// (1) adjoint tile aggregates: the lin_o elements (c_i, y_bar_i) of the tile,
+// combined in decreasing index order.
+template <class T>
+__global__ __launch_bounds__(kScanBlock) void linrec_vjp_tile_agg_kernel(const T* __restrict__ a,
+                                                                         const T* __restrict__ ya,
+                                                                         const T* __restrict__ yb, int64_t n,
+                                                                         typename LinO<T>::S* __restrict__ agg) {
+    using L = LinO<T>;
+    using LS = typename L::S;
+    constexpr int IPT = ScanCfg<T>::IPT;
+    constexpr int TS = kScanBlock * IPT;
+    __shared__ T lds[lds_elems<T, TS>()];
+    __shared__ LS wtot[kScanBlock / kWave];
+    const int64_t tile = blockIdx.x;
+    const int64_t base = tile * TS;
+    const int cnt = (int)((n - base) < TS ? (n - base) : TS);
+    const int first = (int)threadIdx.x * IPT;
+    T ra[IPT], rc[IPT];
+    load_blocked<T, kScanBlock, IPT>(a + base, cnt, ra, lds, T(1));
+    {
+        T nxt;
+        if ((int)threadIdx.x < kScanBlock - 1)
+            nxt = lds[lds_pad<T>(first + IPT)];
+        else
+            nxt = (base + TS < n) ? a[base + TS] : T(1);
+#pragma unroll
+        for (int j = 0; j < IPT - 1; ++j) rc[j] = ra[j + 1];
+        rc[IPT - 1] = nxt;
+    }
+    T rya[IPT], ryb[IPT];
+    __syncthreads();
+    load_blocked<T, kScanBlock, IPT>(ya + base, cnt, rya, lds, T(0));
+    __syncthreads();
+    load_blocked<T, kScanBlock, IPT>(yb + base, cnt, ryb, lds, T(0));
+    LS v = L::id();
+#pragma unroll
+    for (int j = IPT - 1; j >= 0; --j) {
+        const int64_t gi = base + first + j;
+        const T c = (gi == n - 1) ? T(0) : rc[j];
+        v = L::comb(v, LS{c, rya[j], ryb[j]});
+    }
+    LS total;
+    (void)block_exclusive_scan<L, kScanBlock, true>(v, total, wtot);
+    if (threadIdx.x == 0) agg[tile] = total;
+}
+
+// (2) exclusive scan of the tile aggregates by one block, in scan order:
+// increasing tile index, or decreasing with REV.  Thread t folds a
+// contiguous run of the scan order, the runs are scanned across the block,
+// then each thread writes its run's prefixes.
+constexpr int kAggBlock = 1024;
+
+template <class Op, bool REV>
+__global__ __launch_bounds__(kAggBlock) void linrec_agg_scan_kernel(const typename Op::S* __restrict__ agg,
+                                                                    int64_t ntiles,
+                                                                    typename Op::S* __restrict__ pre) {
+    using S = typename Op::S;
+    __shared__ S wtot[kAggBlock / kWave];
+    const int64_t per = (ntiles + kAggBlock - 1) / kAggBlock;
+    const int64_t v0 = (int64_t)threadIdx.x * per;
+    const int64_t v1 = (v0 + per < ntiles) ? v0 + per : ntiles;
+    auto at = [&](int64_t v) { return REV ? ntiles - 1 - v : v; };
+    S run = Op::id();
+    for (int64_t v = v0; v < v1; ++v) run = Op::comb(run, agg[at(v)]);
+    S total;
+    S ex = block_exclusive_scan<Op, kAggBlock, false>(run, total, wtot);
+    for (int64_t v = v0; v < v1; ++v) {
+        pre[at(v)] = ex;
+        ex = Op::comb(ex, agg[at(v)]);
+    }
+}
+
 // ------------------------------------------------------------------ host
+// Inputs of more tiles than this take the three-pass form.
+constexpr int64_t kThreePassTiles = 4096;
+constexpr size_t kAggSlot = 32;  // bytes per tile for an aggregate or a prefix (either operator)
+
+// [header | tile states | group states | aggregates | prefixes]: the
+// three-pass form never touches the lookback states or the header.
 template <class S>
 static size_t lookback_bytes(int64_t ntiles) {
-    return sizeof(LookbackHdr) + lookback_state_bytes<S>(ntiles);
+    static_assert(sizeof(S) <= kAggSlot, "aggregate slot too small");
+    return align_up(sizeof(LookbackHdr) + lookback_state_bytes<S>(ntiles), 256) +
+           align_up((size_t)ntiles * kAggSlot * 2, 256);
+}
+
+template <class S>
+static S* agg_array(void* ws, int64_t ntiles) {
+    return reinterpret_cast<S*>(reinterpret_cast<char*>(ws) +
+                                align_up(sizeof(LookbackHdr) + lookback_state_bytes<S>(ntiles), 256));
+}
+
+template <class S>
+static S* pre_array(void* ws, int64_t ntiles) {
+    return reinterpret_cast<S*>(reinterpret_cast<char*>(agg_array<S>(ws, ntiles)) + (size_t)ntiles * kAggSlot);
 }
 
 template <class T>
@@ -236,7 +374,7 @@ static size_t fwd_ws(int64_t n) {
 }
 
 // Workspace layout of both entry points: [header | tile states | group
-// states | ckpt].  The checkpoint-only pre-pass of the VJP and the VJP itself
+// states | aggregates | prefixes | ckpt].  The checkpoint-only pre-pass of the VJP and the VJP itself
 // run one after the other on the same header and states (states are 128
 // bytes for both operators and both use the same tile size), so every launch
 // on a workspace takes its tag from the one epoch sequence.
@@ -257,8 +395,19 @@ static pvjp_status launch_fwd(const void* a, const void* b, int64_t n, void* A, 
     const int64_t nt = ceil_div(n, scan_tile<T>());
     auto* hdr = reinterpret_cast<LookbackHdr*>(ws);
     auto* states = reinterpret_cast<TileState<S>*>(reinterpret_cast<char*>(ws) + sizeof(LookbackHdr));
-    hipLaunchKernelGGL(linrec_fwd_kernel<T>, dim3((unsigned)nt), dim3(kScanBlock), 0, st,
-                       (const T*)a, (const T*)b, n, (T*)A, (T*)B, (T*)ckpt, hdr, states, nt);
+    if (nt > kThreePassTiles) {
+        S* agg = agg_array<S>(ws, nt);
+        S* pre = pre_array<S>(ws, nt);
+        hipLaunchKernelGGL(linrec_tile_agg_kernel<T>, dim3((unsigned)nt), dim3(kScanBlock), 0, st, (const T*)a,
+                           (const T*)b, n, agg);
+        hipLaunchKernelGGL((linrec_agg_scan_kernel<LinRec<T>, false>), dim3(1), dim3(kAggBlock), 0, st,
+                           (const S*)agg, nt, pre);
+        hipLaunchKernelGGL((linrec_fwd_kernel<T, true>), dim3((unsigned)nt), dim3(kScanBlock), 0, st,
+                           (const T*)a, (const T*)b, n, (T*)A, (T*)B, (T*)ckpt, hdr, states, nt, (const S*)pre);
+    } else {
+        hipLaunchKernelGGL((linrec_fwd_kernel<T, false>), dim3((unsigned)nt), dim3(kScanBlock), 0, st,
+                           (const T*)a, (const T*)b, n, (T*)A, (T*)B, (T*)ckpt, hdr, states, nt, (const S*)nullptr);
+    }
     PVJP_LAUNCHED("pvjp_linrec_scan");
     return PVJP_OK;
 }
@@ -278,14 +427,35 @@ static pvjp_status launch_vjp(const void* a, const void* b, const void* ya, cons
         if (s != PVJP_OK) return s;
         ckpt = ck;
     }
-    if (acc)
-        hipLaunchKernelGGL((linrec_vjp_kernel<T, true>), dim3((unsigned)nt), dim3(kScanBlock), 0, st,
-                           (const T*)a, (const T*)b, (const T*)ya, (const T*)yb, n, (const T*)ckpt,
-                           (T*)abar, (T*)bbar, hdr, states, nt);
-    else
-        hipLaunchKernelGGL((linrec_vjp_kernel<T, false>), dim3((unsigned)nt), dim3(kScanBlock), 0, st,
-                           (const T*)a, (const T*)b, (const T*)ya, (const T*)yb, n, (const T*)ckpt,
-                           (T*)abar, (T*)bbar, hdr, states, nt);
+    const LS* pre = nullptr;
+    if (nt > kThreePassTiles) {
+        LS* agg = agg_array<LS>(ws, nt);
+        LS* p = pre_array<LS>(ws, nt);
+        hipLaunchKernelGGL(linrec_vjp_tile_agg_kernel<T>, dim3((unsigned)nt), dim3(kScanBlock), 0, st, (const T*)a,
+                           (const T*)ya, (const T*)yb, n, agg);
+        hipLaunchKernelGGL((linrec_agg_scan_kernel<LinO<T>, true>), dim3(1), dim3(kAggBlock), 0, st, (const LS*)agg,
+                           nt, p);
+        pre = p;
+    }
+    if (pre) {
+        if (acc)
+            hipLaunchKernelGGL((linrec_vjp_kernel<T, true, true>), dim3((unsigned)nt), dim3(kScanBlock), 0, st,
+                               (const T*)a, (const T*)b, (const T*)ya, (const T*)yb, n, (const T*)ckpt,
+                               (T*)abar, (T*)bbar, hdr, states, nt, pre);
+        else
+            hipLaunchKernelGGL((linrec_vjp_kernel<T, false, true>), dim3((unsigned)nt), dim3(kScanBlock), 0, st,
+                               (const T*)a, (const T*)b, (const T*)ya, (const T*)yb, n, (const T*)ckpt,
+                               (T*)abar, (T*)bbar, hdr, states, nt, pre);
+    } else {
+        if (acc)
+            hipLaunchKernelGGL((linrec_vjp_kernel<T, true, false>), dim3((unsigned)nt), dim3(kScanBlock), 0, st,
+                               (const T*)a, (const T*)b, (const T*)ya, (const T*)yb, n, (const T*)ckpt,
+                               (T*)abar, (T*)bbar, hdr, states, nt, pre);
+        else
+            hipLaunchKernelGGL((linrec_vjp_kernel<T, false, false>), dim3((unsigned)nt), dim3(kScanBlock), 0, st,
+                               (const T*)a, (const T*)b, (const T*)ya, (const T*)yb, n, (const T*)ckpt,
+                               (T*)abar, (T*)bbar, hdr, states, nt, pre);
+    }
     PVJP_LAUNCHED("pvjp_linrec_scan_vjp");
     return PVJP_OK;
 }

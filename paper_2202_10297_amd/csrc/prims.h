@@ -338,31 +338,48 @@ __device__ __forceinline__ uint32_t try_state(const uint64_t* inc, const uint64_
     return 0u;
 }
 
-// try_state, polled until it succeeds.  While a state is missing only the
-// first word of each field is polled (two loads), with a growing pause
-// between polls: hundreds of waiting waves polling every word at full rate
-// would take memory bandwidth from the tiles still streaming their data.
-// Bounded: a state that never shows up is recorded in the header and read
-// as an inclusive neutral element, so the kernel still terminates.
+// Every active lane of the wave takes its state (one try_state each); while
+// some are missing, ONE lane -- the lowest missing, i.e. the nearest
+// predecessor still missing -- polls the first word of its two fields with
+// a growing pause, then all missing lanes try again.  Hundreds of waiting
+// waves polling every lane's state at full rate would take memory
+// bandwidth from the tiles still streaming their data.  Bounded: after
+// kMaxPolls polls the missing states are recorded in the header and read as
+// inclusive neutral elements, so the kernel still terminates.
 template <class Op>
-__device__ __forceinline__ uint32_t wait_state(const uint64_t* inc, const uint64_t* agg, uint64_t hinc, uint64_t hagg,
-                                               typename Op::S& v, LookbackHdr* hdr) {
+__device__ __forceinline__ uint32_t wave_wait_states(bool active, const uint64_t* inc, const uint64_t* agg,
+                                                     uint64_t hinc, uint64_t hagg, typename Op::S& v,
+                                                     LookbackHdr* hdr) {
     constexpr uint64_t mask = ~0xffffffffull;
-    uint32_t st = try_state(inc, agg, hinc, hagg, v);
-    uint32_t polls = 0, pause = 1;
-    while (st == 0u) {
-        for (uint32_t i = 0; i < pause; ++i) __builtin_amdgcn_s_sleep(2);
-        if (pause < 16) pause <<= 1;
-        const uint64_t f0 = __hip_atomic_load(inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint64_t f1 = __hip_atomic_load(agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if ((f0 & mask) == hinc || (f1 & mask) == hagg) st = try_state(inc, agg, hinc, hagg, v);
-        if (st == 0u && ++polls == kMaxPolls) {
-            __hip_atomic_fetch_or(&hdr->error, kErrSpin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            v = Op::id();
-            return kInc;
+    const int lane = threadIdx.x & (kWave - 1);
+    uint32_t st = active ? try_state(inc, agg, hinc, hagg, v) : 0u;
+    uint32_t polls = 0;
+    while (true) {
+        const uint64_t pending = __ballot(active && st == 0u);
+        if (!pending) return st;
+        const int j = __ffsll((unsigned long long)pending) - 1;
+        if (lane == j) {
+            uint32_t pause = 1;
+            while (true) {
+                const uint64_t f0 = __hip_atomic_load(inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t f1 = __hip_atomic_load(agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((f0 & mask) == hinc || (f1 & mask) == hagg) break;
+                if (++polls >= kMaxPolls) break;
+                for (uint32_t i = 0; i < pause; ++i) __builtin_amdgcn_s_sleep(2);
+                if (pause < 16) pause <<= 1;
+            }
         }
+        polls = __shfl(polls, j, kWave);
+        if (polls >= kMaxPolls) {
+            if (lane == 0) __hip_atomic_fetch_or(&hdr->error, kErrSpin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (active && st == 0u) {
+                v = Op::id();
+                st = kInc;
+            }
+            return st;
+        }
+        if (active && st == 0u) st = try_state(inc, agg, hinc, hagg, v);
     }
-    return st;
 }
 
 // Ordered combination of one value per lane, lanes 0..k (lane 0 latest in
@@ -403,9 +420,11 @@ __device__ typename Op::S lookback(TileState<typename Op::S>* states, TileState<
     // 1. inside the group
     {
         const int64_t p = v - 1 - lane;
+        const bool act = p >= g0;
+        const int64_t pc = act ? p : v - 1;  // a valid address for inactive lanes (not read)
         S val = Op::id();
-        uint32_t st = 0u;
-        if (p >= g0) st = wait_state<Op>(states[p].inc, states[p].agg, hinc, hagg, val, hdr);
+        uint32_t st = wave_wait_states<Op>(act, states[pc].inc, states[pc].agg, hinc, hagg, val, hdr);
+        if (!act) val = Op::id();
         const uint64_t incl = __ballot(st == kInc);
         const int k = incl ? __ffsll((unsigned long long)incl) - 1 : kWave - 1;
         S prefix = lane_fold<Op>(val, k, lane);
@@ -416,11 +435,14 @@ __device__ typename Op::S lookback(TileState<typename Op::S>* states, TileState<
         int64_t h0 = g - 1;
         while (true) {
             const int64_t h = h0 - lane;
+            const bool act = h >= 0;
+            const int64_t hc = act ? h : 0;
+            const int64_t last = (hc << kGroupShift) + kGroup - 1;
             S gv = Op::id();
-            uint32_t gs = kInc;  // before the first group: neutral, inclusive
-            if (h >= 0) {
-                const int64_t last = (h << kGroupShift) + kGroup - 1;
-                gs = wait_state<Op>(states[last].inc, groups[h].agg, hinc, hagg, gv, hdr);
+            uint32_t gs = wave_wait_states<Op>(act, states[last].inc, groups[hc].agg, hinc, hagg, gv, hdr);
+            if (!act) {  // before the first group: neutral, inclusive
+                gv = Op::id();
+                gs = kInc;
             }
             const uint64_t gincl = __ballot(gs == kInc);
             const int gk = gincl ? __ffsll((unsigned long long)gincl) - 1 : kWave - 1;

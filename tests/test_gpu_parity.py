@@ -57,6 +57,24 @@ def test_linrec_scan_and_vjp(ops, orc, dtype, n):
     assert rel_l2([host(ab2), host(bb2)], [ra, rb]) <= tol(dtype)
 
 
+# Past 4096 tiles the scan takes the reduce-then-scan form (tile aggregates,
+# one-block scan of the aggregates, scan with given prefixes); the ragged
+# last tile and the checkpoint pre-pass are covered too.
+@pytest.mark.parametrize("dtype,n", [("f64", 4097 * 2048 + 123), ("f32", 4097 * 4096 + 5)])
+def test_linrec_three_pass_form(ops, orc, dtype, n):
+    a, b, ya, yb = workloads.linrec(n, dtype, seed=7)
+    A, B, ck = ops.linrec_scan(dev(a), dev(b))
+    RA, RB = orc.linrec_scan(a, b)
+    assert rel_l2([host(A), host(B)], [RA, RB]) <= tol(dtype)
+    RCK = np.stack([np.concatenate([[1.0], RA[1023:-1:1024]]), np.concatenate([[0.0], RB[1023:-1:1024]])], 1)
+    assert rel_l2(host(ck).reshape(-1, 2), RCK) <= tol(dtype)
+    ra, rb = orc.linrec_scan_vjp(a, b, ya, yb)
+    ab, bb = ops.linrec_scan_vjp(dev(a), dev(b), dev(ya), dev(yb), ckpt=ck)
+    assert rel_l2([host(ab), host(bb)], [ra, rb]) <= tol(dtype)
+    ab2, bb2 = ops.linrec_scan_vjp(dev(a), dev(b), dev(ya), dev(yb), ckpt=None)
+    assert rel_l2([host(ab2), host(bb2)], [ra, rb]) <= tol(dtype)
+
+
 def test_linrec_checkpoint_values(ops, orc):
     n = 5000
     a, b, _, _ = workloads.linrec(n, "f64", seed=1)
