@@ -75,9 +75,14 @@ __global__ __launch_bounds__(kScanBlock) void linrec_fwd_kernel(
     const int cnt = (int)((n - base) < TS ? (n - base) : TS);
 
     T ra[IPT], rb[IPT];
-    load_blocked<T, kScanBlock, IPT>(a + base, cnt, ra, lds, T(1));
-    __syncthreads();
-    load_blocked<T, kScanBlock, IPT>(b + base, cnt, rb, lds, T(0));
+    {
+        T sa[IPT], sb[IPT];  // both arrays in flight before the first transpose
+        load_striped<T, kScanBlock, IPT>(a + base, cnt, sa, T(1));
+        load_striped<T, kScanBlock, IPT>(b + base, cnt, sb, T(0));
+        striped_to_blocked<T, kScanBlock, IPT>(sa, ra, lds);
+        __syncthreads();
+        striped_to_blocked<T, kScanBlock, IPT>(sb, rb, lds);
+    }
 
     S agg = S{ra[0], rb[0]};
 #pragma unroll
@@ -154,26 +159,28 @@ __global__ __launch_bounds__(kScanBlock) void linrec_vjp_kernel(
     const int cnt = (int)((n - base) < TS ? (n - base) : TS);
     const int first = (int)threadIdx.x * IPT;
 
-    // --- loads (a with its one-element look-ahead for c_i = a_{i+1})
-    T ra[IPT], rc[IPT];
-    load_blocked<T, kScanBlock, IPT>(a + base, cnt, ra, lds, T(1));
+    // --- loads (a with its one-element look-ahead for c_i = a_{i+1}); all
+    //     four arrays are in flight before the first transpose
+    T ra[IPT], rc[IPT], rb[IPT], rya[IPT], ryb[IPT];
     {
-        T nxt;
-        if ((int)threadIdx.x < kScanBlock - 1)
-            nxt = lds[lds_pad<T>(first + IPT)];
-        else
-            nxt = (base + TS < n) ? a[base + TS] : T(1);
+        T sa[IPT], sb[IPT], sya[IPT], syb[IPT];
+        load_striped<T, kScanBlock, IPT>(a + base, cnt, sa, T(1));
+        load_striped<T, kScanBlock, IPT>(b + base, cnt, sb, T(0));
+        load_striped<T, kScanBlock, IPT>(ya + base, cnt, sya, T(0));
+        load_striped<T, kScanBlock, IPT>(yb + base, cnt, syb, T(0));
+        const T after = ((int)threadIdx.x == kScanBlock - 1 && base + TS < n) ? a[base + TS] : T(1);
+        striped_to_blocked<T, kScanBlock, IPT>(sa, ra, lds);
+        const T nxt = ((int)threadIdx.x < kScanBlock - 1) ? lds[lds_pad<T>(first + IPT)] : after;
 #pragma unroll
         for (int j = 0; j < IPT - 1; ++j) rc[j] = ra[j + 1];
         rc[IPT - 1] = nxt;
+        __syncthreads();
+        striped_to_blocked<T, kScanBlock, IPT>(sb, rb, lds);
+        __syncthreads();
+        striped_to_blocked<T, kScanBlock, IPT>(sya, rya, lds);
+        __syncthreads();
+        striped_to_blocked<T, kScanBlock, IPT>(syb, ryb, lds);
     }
-    T rb[IPT], rya[IPT], ryb[IPT];
-    __syncthreads();
-    load_blocked<T, kScanBlock, IPT>(b + base, cnt, rb, lds, T(0));
-    __syncthreads();
-    load_blocked<T, kScanBlock, IPT>(ya + base, cnt, rya, lds, T(0));
-    __syncthreads();
-    load_blocked<T, kScanBlock, IPT>(yb + base, cnt, ryb, lds, T(0));
 
     // --- 1. recompute primal prefixes from the tile's checkpoint
     T pA[IPT], pB[IPT];
@@ -260,9 +267,14 @@ __global__ __launch_bounds__(kScanBlock) void linrec_tile_agg_kernel(const T* __
     const int64_t base = tile * TS;
     const int cnt = (int)((n - base) < TS ? (n - base) : TS);
     T ra[IPT], rb[IPT];
-    load_blocked<T, kScanBlock, IPT>(a + base, cnt, ra, lds, T(1));
-    __syncthreads();
-    load_blocked<T, kScanBlock, IPT>(b + base, cnt, rb, lds, T(0));
+    {
+        T sa[IPT], sb[IPT];
+        load_striped<T, kScanBlock, IPT>(a + base, cnt, sa, T(1));
+        load_striped<T, kScanBlock, IPT>(b + base, cnt, sb, T(0));
+        striped_to_blocked<T, kScanBlock, IPT>(sa, ra, lds);
+        __syncthreads();
+        striped_to_blocked<T, kScanBlock, IPT>(sb, rb, lds);
+    }
     S v = S{ra[0], rb[0]};
 #pragma unroll
     for (int j = 1; j < IPT; ++j) v = Op::comb(v, S{ra[j], rb[j]});
@@ -288,23 +300,23 @@ __global__ __launch_bounds__(kScanBlock) void linrec_vjp_tile_agg_kernel(const T
     const int64_t base = tile * TS;
     const int cnt = (int)((n - base) < TS ? (n - base) : TS);
     const int first = (int)threadIdx.x * IPT;
-    T ra[IPT], rc[IPT];
-    load_blocked<T, kScanBlock, IPT>(a + base, cnt, ra, lds, T(1));
+    T ra[IPT], rc[IPT], rya[IPT], ryb[IPT];
     {
-        T nxt;
-        if ((int)threadIdx.x < kScanBlock - 1)
-            nxt = lds[lds_pad<T>(first + IPT)];
-        else
-            nxt = (base + TS < n) ? a[base + TS] : T(1);
+        T sa[IPT], sya[IPT], syb[IPT];
+        load_striped<T, kScanBlock, IPT>(a + base, cnt, sa, T(1));
+        load_striped<T, kScanBlock, IPT>(ya + base, cnt, sya, T(0));
+        load_striped<T, kScanBlock, IPT>(yb + base, cnt, syb, T(0));
+        const T after = ((int)threadIdx.x == kScanBlock - 1 && base + TS < n) ? a[base + TS] : T(1);
+        striped_to_blocked<T, kScanBlock, IPT>(sa, ra, lds);
+        const T nxt = ((int)threadIdx.x < kScanBlock - 1) ? lds[lds_pad<T>(first + IPT)] : after;
 #pragma unroll
         for (int j = 0; j < IPT - 1; ++j) rc[j] = ra[j + 1];
         rc[IPT - 1] = nxt;
+        __syncthreads();
+        striped_to_blocked<T, kScanBlock, IPT>(sya, rya, lds);
+        __syncthreads();
+        striped_to_blocked<T, kScanBlock, IPT>(syb, ryb, lds);
     }
-    T rya[IPT], ryb[IPT];
-    __syncthreads();
-    load_blocked<T, kScanBlock, IPT>(ya + base, cnt, rya, lds, T(0));
-    __syncthreads();
-    load_blocked<T, kScanBlock, IPT>(yb + base, cnt, ryb, lds, T(0));
     LS v = L::id();
 #pragma unroll
     for (int j = IPT - 1; j >= 0; --j) {

@@ -165,6 +165,30 @@ __device__ __forceinline__ void load_blocked(const T* __restrict__ src, int cnt,
     for (int j = 0; j < IPT; ++j) items[j] = lds[lds_pad<T>((int)threadIdx.x * IPT + j)];
 }
 
+// The two halves of load_blocked, so that a tile's several input arrays
+// can all be in flight before the first is transposed: a striped coalesced
+// load into registers (element k*BLOCK + t in slot k of thread t; `fill`
+// past `cnt`), then the LDS transpose of those registers into blocked
+// order.  The transpose ends with the LDS buffer holding the tile; the
+// caller puts a barrier before reusing the buffer.
+template <class T, int BLOCK, int IPT>
+__device__ __forceinline__ void load_striped(const T* __restrict__ src, int cnt, T (&st)[IPT], T fill) {
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+        const int i = k * BLOCK + (int)threadIdx.x;
+        st[k] = (i < cnt) ? src[i] : fill;
+    }
+}
+
+template <class T, int BLOCK, int IPT>
+__device__ __forceinline__ void striped_to_blocked(const T (&st)[IPT], T (&items)[IPT], T* lds) {
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) lds[lds_pad<T>(k * BLOCK + (int)threadIdx.x)] = st[k];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) items[j] = lds[lds_pad<T>((int)threadIdx.x * IPT + j)];
+}
+
 // Blocked items written back through LDS as striped coalesced stores.  With
 // ADD the existing destination value is added (x_bar += contribution).
 template <class T, int BLOCK, int IPT, bool ADD>

@@ -99,11 +99,16 @@ __global__ __launch_bounds__(kSegBlock) void seg_linrec_fwd_kernel(
     const int cnt = (int)((total - base) < TS ? (total - base) : TS);
     const int first = (int)threadIdx.x * IPT;
 
-    build_heads<TS>(bits, seg0, offs, nseg, tile, base);
     T ra[IPT], rb[IPT];
-    load_blocked<T, kSegBlock, IPT>(a + base, cnt, ra, lds, T(1));
-    __syncthreads();
-    load_blocked<T, kSegBlock, IPT>(b + base, cnt, rb, lds, T(0));
+    {
+        T sa[IPT], sb[IPT];  // both arrays in flight while the head bitmap is built
+        load_striped<T, kSegBlock, IPT>(a + base, cnt, sa, T(1));
+        load_striped<T, kSegBlock, IPT>(b + base, cnt, sb, T(0));
+        build_heads<TS>(bits, seg0, offs, nseg, tile, base);
+        striped_to_blocked<T, kSegBlock, IPT>(sa, ra, lds);
+        __syncthreads();
+        striped_to_blocked<T, kSegBlock, IPT>(sb, rb, lds);
+    }
 
     S e[IPT];
 #pragma unroll
@@ -163,25 +168,27 @@ __device__ __forceinline__ void seg_scan_vjp_tile(const T* __restrict__ a, const
     const int cnt = (int)((total - base) < TS ? (total - base) : TS);
     const int first = (int)threadIdx.x * IPT;
 
-    T ra[IPT], rc[IPT];
-    load_blocked<T, kSegBlock, IPT>(a + base, cnt, ra, lds, T(1));
+    // all four arrays in flight before the first transpose
+    T ra[IPT], rc[IPT], rb[IPT], rya[IPT], ryb[IPT];
     {
-        T nxt;
-        if ((int)threadIdx.x < kSegBlock - 1)
-            nxt = lds[lds_pad<T>(first + IPT)];
-        else
-            nxt = (base + TS < total) ? a[base + TS] : T(1);
+        T sa[IPT], sb[IPT], sya[IPT], syb[IPT];
+        load_striped<T, kSegBlock, IPT>(a + base, cnt, sa, T(1));
+        load_striped<T, kSegBlock, IPT>(b + base, cnt, sb, T(0));
+        load_striped<T, kSegBlock, IPT>(ya + base, cnt, sya, T(0));
+        load_striped<T, kSegBlock, IPT>(yb + base, cnt, syb, T(0));
+        const T after = ((int)threadIdx.x == kSegBlock - 1 && base + TS < total) ? a[base + TS] : T(1);
+        striped_to_blocked<T, kSegBlock, IPT>(sa, ra, lds);
+        const T nxt = ((int)threadIdx.x < kSegBlock - 1) ? lds[lds_pad<T>(first + IPT)] : after;
 #pragma unroll
         for (int j = 0; j < IPT - 1; ++j) rc[j] = ra[j + 1];
         rc[IPT - 1] = nxt;
+        __syncthreads();
+        striped_to_blocked<T, kSegBlock, IPT>(sb, rb, lds);
+        __syncthreads();
+        striped_to_blocked<T, kSegBlock, IPT>(sya, rya, lds);
+        __syncthreads();
+        striped_to_blocked<T, kSegBlock, IPT>(syb, ryb, lds);
     }
-    T rb[IPT], rya[IPT], ryb[IPT];
-    __syncthreads();
-    load_blocked<T, kSegBlock, IPT>(b + base, cnt, rb, lds, T(0));
-    __syncthreads();
-    load_blocked<T, kSegBlock, IPT>(ya + base, cnt, rya, lds, T(0));
-    __syncthreads();
-    load_blocked<T, kSegBlock, IPT>(yb + base, cnt, ryb, lds, T(0));
 
     // 1. primal prefixes (A_{i-1}, B_{i-1}) within each segment
     T pA[IPT], pB[IPT];
