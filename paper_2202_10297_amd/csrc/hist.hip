@@ -727,14 +727,24 @@ __global__ __launch_bounds__(kHistBlock) void hpart_scatter_kernel(const int32_t
     }
 }
 
+// One block per work item accumulates its bucket's 4096 bins in LDS.  The
+// accumulators are kept in kAccCopies interleaved copies (bin j, copy c at
+// j * kAccCopies + c; lane l updates copy l % kAccCopies), so lanes of a
+// wave that hit one hot bin -- Zipf-distributed indices put a large share
+// of the records on a few bins -- update different words in different
+// banks instead of serialising on one address.  The copies are folded in a
+// fixed order at the end.
+constexpr int kAccBlock = 1024;
+constexpr int kAccCopies = 4;
+
 template <int OP, bool COUNTS>
-__global__ __launch_bounds__(kHistBlock) void hpart_acc_kernel(const uint64_t* __restrict__ rec,
-                                                               const uint16_t* __restrict__ rbin, int nb,
-                                                               const int32_t* __restrict__ bstart,
-                                                               const int32_t* __restrict__ istart,
-                                                               uint64_t* __restrict__ pacc,
-                                                               int32_t* __restrict__ pcnt) {
-    __shared__ uint64_t acc[kPartBins];
+__global__ __launch_bounds__(kAccBlock) void hpart_acc_kernel(const uint64_t* __restrict__ rec,
+                                                              const uint16_t* __restrict__ rbin, int nb,
+                                                              const int32_t* __restrict__ bstart,
+                                                              const int32_t* __restrict__ istart,
+                                                              uint64_t* __restrict__ pacc,
+                                                              int32_t* __restrict__ pcnt) {
+    __shared__ uint64_t acc[kPartBins * kAccCopies];
     __shared__ int32_t cnt[COUNTS ? kPartBins : 1];
     const int item = blockIdx.x;
     if (item >= istart[nb]) return;
@@ -746,21 +756,21 @@ __global__ __launch_bounds__(kHistBlock) void hpart_acc_kernel(const uint64_t* _
     const int b = lo;
     const int64_t r0 = (int64_t)bstart[b] + (int64_t)(item - istart[b]) * kPartSeg;
     const int64_t r1 = (r0 + kPartSeg < (int64_t)bstart[b + 1]) ? r0 + kPartSeg : (int64_t)bstart[b + 1];
-    for (int j = threadIdx.x; j < kPartBins; j += kHistBlock) {
-        acc[j] = acc_identity<OP>();
-        if (COUNTS) cnt[j] = 0;
-    }
+    for (int j = threadIdx.x; j < kPartBins * kAccCopies; j += kAccBlock) acc[j] = acc_identity<OP>();
+    if (COUNTS)
+        for (int j = threadIdx.x; j < kPartBins; j += kAccBlock) cnt[j] = 0;
     __syncthreads();
+    const uint32_t copy = threadIdx.x & (kAccCopies - 1);
     // Loads are clamped to the item's last record (never out of range) and
     // the next round's loads are issued before this round's LDS atomics.
     constexpr int U = 8;
-    constexpr int64_t kRound = (int64_t)U * kHistBlock;
+    constexpr int64_t kRound = (int64_t)U * kAccBlock;
     const int64_t last = r1 - 1;
     uint64_t u[U], un[U];
     uint32_t jb[U], jn[U];
 #pragma unroll
     for (int t = 0; t < U; ++t) {
-        const int64_t r = r0 + (int64_t)t * kHistBlock + threadIdx.x;
+        const int64_t r = r0 + (int64_t)t * kAccBlock + threadIdx.x;
         const int64_t rr = r < r1 ? r : last;
         u[t] = rec[rr];
         jb[t] = OP == PVJP_ADD ? 0u : (uint32_t)rbin[rr];
@@ -770,7 +780,7 @@ __global__ __launch_bounds__(kHistBlock) void hpart_acc_kernel(const uint64_t* _
         if (nbase < r1) {
 #pragma unroll
             for (int t = 0; t < U; ++t) {
-                const int64_t r = nbase + (int64_t)t * kHistBlock + threadIdx.x;
+                const int64_t r = nbase + (int64_t)t * kAccBlock + threadIdx.x;
                 const int64_t rr = r < r1 ? r : last;
                 un[t] = rec[rr];
                 jn[t] = OP == PVJP_ADD ? 0u : (uint32_t)rbin[rr];
@@ -778,14 +788,16 @@ __global__ __launch_bounds__(kHistBlock) void hpart_acc_kernel(const uint64_t* _
         }
 #pragma unroll
         for (int t = 0; t < U; ++t) {
-            const int64_t r = base + (int64_t)t * kHistBlock + threadIdx.x;
+            const int64_t r = base + (int64_t)t * kAccBlock + threadIdx.x;
             if (r >= r1) continue;
             if (OP == PVJP_ADD) {
                 const uint32_t j = (uint32_t)(u[t] >> 32);
-                atomicAdd(reinterpret_cast<double*>(&acc[j]), (double)__uint_as_float((uint32_t)u[t]));
+                atomicAdd(reinterpret_cast<double*>(&acc[j * kAccCopies + copy]),
+                          (double)__uint_as_float((uint32_t)u[t]));
                 if (COUNTS) atomicAdd(&cnt[j], 1);
             } else {
-                atomicMax(reinterpret_cast<unsigned long long*>(&acc[jb[t]]), (unsigned long long)u[t]);
+                atomicMax(reinterpret_cast<unsigned long long*>(&acc[jb[t] * kAccCopies + copy]),
+                          (unsigned long long)u[t]);
                 if (COUNTS) atomicAdd(&cnt[jb[t]], 1);
             }
         }
@@ -796,8 +808,17 @@ __global__ __launch_bounds__(kHistBlock) void hpart_acc_kernel(const uint64_t* _
         }
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < kPartBins; j += kHistBlock) {
-        pacc[(int64_t)item * kPartBins + j] = acc[j];
+    for (int j = threadIdx.x; j < kPartBins; j += kAccBlock) {
+        uint64_t v = acc[j * kAccCopies];
+#pragma unroll
+        for (int c = 1; c < kAccCopies; ++c) {
+            const uint64_t w = acc[j * kAccCopies + c];
+            if (OP == PVJP_ADD)
+                v = (uint64_t)__double_as_longlong(__longlong_as_double((long long)v) + __longlong_as_double((long long)w));
+            else
+                v = w > v ? w : v;
+        }
+        pacc[(int64_t)item * kPartBins + j] = v;
         if (COUNTS) pcnt[(int64_t)item * kPartBins + j] = cnt[j];
     }
 }
@@ -954,10 +975,10 @@ static void run_partitioned(const int32_t* inds, const float* vs, int64_t n, int
         hipLaunchKernelGGL((hpart_scatter_kernel<OP, false>), dim3(G), dim3(kHistBlock), 0, st, inds, vs, n, m, L.chunk,
                            L.nb, bcount, bstart, rec, rbin);
     if (count)
-        hipLaunchKernelGGL((hpart_acc_kernel<OP, true>), dim3((unsigned)L.items_max), dim3(kHistBlock), 0, st, rec, rbin,
+        hipLaunchKernelGGL((hpart_acc_kernel<OP, true>), dim3((unsigned)L.items_max), dim3(kAccBlock), 0, st, rec, rbin,
                            L.nb, bstart, istart, pacc, pcnt);
     else
-        hipLaunchKernelGGL((hpart_acc_kernel<OP, false>), dim3((unsigned)L.items_max), dim3(kHistBlock), 0, st, rec,
+        hipLaunchKernelGGL((hpart_acc_kernel<OP, false>), dim3((unsigned)L.items_max), dim3(kAccBlock), 0, st, rec,
                            rbin, L.nb, bstart, istart, pacc, pcnt);
     hipLaunchKernelGGL(hpart_merge_kernel<OP>, dim3(flat_grid(m, 256, 4)), dim3(256), 0, st, pacc,
                        count ? pcnt : nullptr, istart, m, gacc, count);
