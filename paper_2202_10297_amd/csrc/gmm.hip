@@ -155,6 +155,37 @@ __device__ __forceinline__ double tile_znorm(const float (&qa)[Gm<D>::NF], const
     return nrm + __shfl_xor(nrm, 32, kWave);
 }
 
+// tile_znorm with Q_k's fragments (qs[f * 64 + lane]) and c_k (cs[r]) read
+// from LDS instead of registers; the row tiles' MFMA chains are interleaved.
+// Each accumulator sees the same operands in the same order as in
+// tile_znorm, so z and |z|^2 are bit-identical to the forward sweep's.
+template <int D>
+__device__ __forceinline__ double tile_znorm_lds(const float* qs, const float* cs, const float (&bx)[Gm<D>::S],
+                                                 f32x16 (&acc)[Gm<D>::RT]) {
+    using C = Gm<D>;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int rt = 0; rt < C::RT; ++rt)
+#pragma unroll
+        for (int t = 0; t < 16; ++t) acc[rt][t] = 0.f;
+#pragma unroll 4
+    for (int s = 0; s < C::S; ++s)
+#pragma unroll
+        for (int rt = 0; rt < C::RT; ++rt)
+            if (s < 16 * (rt + 1)) acc[rt] = mfma32(qs[fidx(rt, s) * 64 + lane], bx[s], acc[rt]);
+    double nrm = 0.0;
+#pragma unroll
+    for (int rt = 0; rt < C::RT; ++rt) {
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const float z = acc[rt][t] - cs[32 * rt + drow(t, lane)];
+            acc[rt][t] = z;
+            nrm = fma((double)z, (double)z, nrm);
+        }
+    }
+    return nrm + __shfl_xor(nrm, 32, kWave);
+}
+
 template <int D>
 __device__ __forceinline__ void load_component(const float* __restrict__ Qf, const float* __restrict__ cvec, int k,
                                                float (&qa)[Gm<D>::NF], float (&cl)[Gm<D>::RT][16]) {
@@ -240,7 +271,7 @@ __global__ __launch_bounds__(256) void gmm_fwd_kernel(const float* __restrict__ 
 
 // ----------------------------------------------------------------- backward
 template <int D>
-__global__ __launch_bounds__(256) void gmm_bwd_kernel(const float* __restrict__ X, int64_t N, int K, int64_t chunk,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gmm_bwd_kernel(const float* __restrict__ X, int64_t N, int K, int64_t chunk,
                                                       int nch, const float* __restrict__ Qf,
                                                       const float* __restrict__ cvec, const float* __restrict__ mu,
                                                       const double* __restrict__ bias, const double* __restrict__ lse,
@@ -248,8 +279,12 @@ __global__ __launch_bounds__(256) void gmm_bwd_kernel(const float* __restrict__ 
                                                       float* __restrict__ vpart, double* __restrict__ wpart) {
     using C = Gm<D>;
     // X tiles and weighted-Z tiles of the four waves; reused at the end as
-    // the scratch of the cross-wave reduction.
+    // the scratch of the cross-wave reduction.  Q_k's MFMA fragments live in
+    // LDS too, read at each step: held in registers they would leave room
+    // for only one wave per SIMD.
     __shared__ float smem[2 * 4 * 32 * D];
+    __shared__ float qs[C::NF * 64];
+    __shared__ float cs[D];
     float* const Xw = smem + (threadIdx.x >> 6) * 32 * D;
     float* const Zw = smem + 4 * 32 * D + (threadIdx.x >> 6) * 32 * D;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -257,8 +292,8 @@ __global__ __launch_bounds__(256) void gmm_bwd_kernel(const float* __restrict__ 
     const int ch = blockIdx.x / K;
     const int h = lane >> 5, j = lane & 31;
 
-    float qa[C::NF], cl[C::RT][16];
-    load_component<D>(Qf, cvec, k, qa, cl);
+    for (int e = threadIdx.x; e < C::NF * 64; e += 256) qs[e] = Qf[(int64_t)k * C::NF * 64 + e];
+    if (threadIdx.x < D) cs[threadIdx.x] = cvec[(int64_t)k * D + threadIdx.x];
     float mub[C::RT];
 #pragma unroll
     for (int ct = 0; ct < C::RT; ++ct) mub[ct] = mu[(int64_t)k * D + 32 * ct + j];
@@ -269,11 +304,10 @@ __global__ __launch_bounds__(256) void gmm_bwd_kernel(const float* __restrict__ 
     for (int g = 0; g < C::NGT; ++g)
 #pragma unroll
         for (int t = 0; t < 16; ++t) gacc[g][t] = 0.f;
-    float vs[C::RT][16];
-#pragma unroll
-    for (int rt = 0; rt < C::RT; ++rt)
-#pragma unroll
-        for (int t = 0; t < 16; ++t) vs[rt][t] = 0.f;
+    // v_k = sum_i w z_i: lane r % D sums row r of each staged w z tile (for
+    // D = 32 the two half-waves take 16 points each), one register instead
+    // of one per (row, point-lane) accumulator.
+    float vrow = 0.f;
     double wsum = 0.0;
 
     const int64_t cbeg = (int64_t)ch * chunk;
@@ -287,7 +321,7 @@ __global__ __launch_bounds__(256) void gmm_bwd_kernel(const float* __restrict__ 
 #pragma unroll
         for (int s = 0; s < C::S; ++s) bx[s] = Xw[xs_at<D>(j, 2 * s + h)];
         f32x16 z[C::RT];
-        const double nrm = tile_znorm<D>(qa, bx, cl, z);
+        const double nrm = tile_znorm_lds<D>(qs, cs, bx, z);
         const int64_t p = p0 + j;
         double wd = 0.0;
         if (p < N) wd = ell_bar * exp((bk - 0.5 * nrm) - lse[p]);
@@ -296,42 +330,42 @@ __global__ __launch_bounds__(256) void gmm_bwd_kernel(const float* __restrict__ 
 #pragma unroll
         for (int rt = 0; rt < C::RT; ++rt)
 #pragma unroll
-            for (int t = 0; t < 16; ++t) {
-                const float wz = wf * z[rt][t];
-                vs[rt][t] += wz;
-                Zw[zs_at(32 * rt + drow(t, lane), j)] = wz;
-            }
+            for (int t = 0; t < 16; ++t) Zw[zs_at(32 * rt + drow(t, lane), j)] = wf * z[rt][t];
         __syncthreads();
-        // G_k += (w Z)^T Y over this tile's 32 points, lower-triangular blocks.
-        int g = 0;
+        {
+            const int r = lane % D;
+            const int pb = (D == 32) ? 16 * h : 0;
+            constexpr int np = (D == 32) ? 16 : 32;
+            float sr = 0.f;
 #pragma unroll
-        for (int rt = 0; rt < C::RT; ++rt) {
+            for (int pp = 0; pp < np; ++pp) sr += Zw[zs_at(r, pb + pp)];
+            vrow += sr;
+        }
+        // G_k += (w Z)^T Y over this tile's 32 points, lower-triangular
+        // blocks; each step loads one operand per row and column tile and
+        // feeds the blocks' independent accumulators in turn.
+#pragma unroll 4
+        for (int s = 0; s < 16; ++s) {
+            const int pt = 2 * s + h;
+            float za[C::RT], yb[C::RT];
 #pragma unroll
-            for (int ct = 0; ct <= rt; ++ct) {
-                f32x16 a = gacc[g];
-#pragma unroll
-                for (int s = 0; s < 16; ++s) {
-                    const int pt = 2 * s + h;
-                    const float za = Zw[zs_at(32 * rt + j, pt)];
-                    const float yb = Xw[xs_at<D>(pt, 32 * ct + j)] - mub[ct];
-                    a = mfma32(za, yb, a);
-                }
-                gacc[g] = a;
-                ++g;
+            for (int t = 0; t < C::RT; ++t) {
+                za[t] = Zw[zs_at(32 * t + j, pt)];
+                yb[t] = Xw[xs_at<D>(pt, 32 * t + j)] - mub[t];
             }
+            int g = 0;
+#pragma unroll
+            for (int rt = 0; rt < C::RT; ++rt)
+#pragma unroll
+                for (int ct = 0; ct <= rt; ++ct) {
+                    gacc[g] = mfma32(za[rt], yb[ct], gacc[g]);
+                    ++g;
+                }
         }
     }
 
-    // Sum v over the 32 points of each half-wave (lanes with the same h).
-#pragma unroll
-    for (int rt = 0; rt < C::RT; ++rt)
-#pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            float v = vs[rt][t];
-#pragma unroll
-            for (int d = 16; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
-            vs[rt][t] = v;
-        }
+    // For D = 32 the two half-waves hold halves of each row sum.
+    if (D == 32) vrow += __shfl_xor(vrow, 32, kWave);
 #pragma unroll
     for (int d = 16; d >= 1; d >>= 1) wsum += __shfl_xor(wsum, d, kWave);
 
@@ -346,12 +380,7 @@ __global__ __launch_bounds__(256) void gmm_bwd_kernel(const float* __restrict__ 
         for (int g = 0; g < C::NGT; ++g)
 #pragma unroll
             for (int t = 0; t < 16; ++t) red[((w - 1) * C::NGT * 16 + g * 16 + t) * 64 + lane] = gacc[g][t];
-        if (j == 0) {
-#pragma unroll
-            for (int rt = 0; rt < C::RT; ++rt)
-#pragma unroll
-                for (int t = 0; t < 16; ++t) red[3 * C::NGT * 1024 + (w - 1) * D + 32 * rt + drow(t, lane)] = vs[rt][t];
-        }
+        if (lane < D) red[3 * C::NGT * 1024 + (w - 1) * D + lane] = vrow;
     }
     if (lane == 0) wred[w] = wsum;
     __syncthreads();
@@ -365,16 +394,10 @@ __global__ __launch_bounds__(256) void gmm_bwd_kernel(const float* __restrict__ 
                 for (int o = 0; o < 3; ++o) s += red[(o * C::NGT * 16 + g * 16 + t) * 64 + lane];
                 gpart[(rec * C::NGT * 16 + g * 16 + t) * 64 + lane] = s;
             }
-        if (j == 0) {
-#pragma unroll
-            for (int rt = 0; rt < C::RT; ++rt)
-#pragma unroll
-                for (int t = 0; t < 16; ++t) {
-                    const int r = 32 * rt + drow(t, lane);
-                    float s = vs[rt][t];
-                    for (int o = 0; o < 3; ++o) s += red[3 * C::NGT * 1024 + o * D + r];
-                    vpart[rec * D + r] = s;
-                }
+        if (lane < D) {
+            float s = vrow;
+            for (int o = 0; o < 3; ++o) s += red[3 * C::NGT * 1024 + o * D + lane];
+            vpart[rec * D + lane] = s;
         }
         if (lane == 0) wpart[rec] = (wred[0] + wred[1]) + (wred[2] + wred[3]);
     }
