@@ -199,6 +199,14 @@ __device__ __forceinline__ void load_component(const float* __restrict__ Qf, con
         for (int t = 0; t < 16; ++t) cl[rt][t] = cvec[(int64_t)k * D + 32 * rt + drow(t, lane)];
 }
 
+// LDS written by a wave and read back by other lanes of the same wave: a
+// wave-scope fence around a wave barrier (no other wave takes part).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 struct GmmHdr {
     uint32_t done;
     uint32_t pad[63];
@@ -312,11 +320,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
 
     const int64_t cbeg = (int64_t)ch * chunk;
     const int iters = (int)(chunk / 128);
+    __syncthreads();  // qs and cs
+    // Every tile below is private to its wave (Xw, Zw), so the waves only
+    // synchronise with themselves and drift apart freely: one wave's MFMA
+    // phase overlaps another's loads and FP64 work.
     for (int it = 0; it < iters; ++it) {
         const int64_t p0 = cbeg + (int64_t)(it * 4 + w) * 32;
-        __syncthreads();
+        wave_lds_sync();
         stage_x<D>(X, N, p0, Xw);
-        __syncthreads();
+        wave_lds_sync();
         float bx[C::S];
 #pragma unroll
         for (int s = 0; s < C::S; ++s) bx[s] = Xw[xs_at<D>(j, 2 * s + h)];
@@ -331,7 +343,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
         for (int rt = 0; rt < C::RT; ++rt)
 #pragma unroll
             for (int t = 0; t < 16; ++t) Zw[zs_at(32 * rt + drow(t, lane), j)] = wf * z[rt][t];
-        __syncthreads();
+        wave_lds_sync();
         {
             const int r = lane % D;
             const int pb = (D == 32) ? 16 * h : 0;
