@@ -165,6 +165,17 @@ def ingest_pmc(fetch_csv, write_csv):
     print(f"wrote {path}: {len(order)} calls; scales {scale}")
 
 
+def scatter_line_bytes(kind, n, m, line=64):
+    """Bytes at cache-line granularity: the sequential arrays once, and every
+    line of a randomly indexed array that holds at least one target once per
+    direction (m distinct random targets in n: a line of line/4 elements is
+    untouched with probability (1 - m/n)^(line/4))."""
+    touched = n * 4 * (1.0 - (1.0 - m / n) ** (line // 4))
+    if kind == "vjp":  # is, xs_saved, vs_bar; ys_bar read + written, ys written
+        return 12 * m + 3 * touched
+    return 12 * m + 2 * touched  # is, vs, xs_saved; xs read + written
+
+
 def traffic_for(kernel_key):
     """HBM bytes per launch from committed rocprofv3 counters, if they were
     taken on the current source of the kernel's file."""
@@ -341,6 +352,12 @@ def main():
         "alg_bytes_per_launch": dbytes,
         "avg_launch_ms": round(float(avg[dom]), 4),
     }
+    if dkey.startswith("scatter"):
+        lg = scatter_line_bytes(dkind, N_SCAT, M_SCAT)
+        roof["line_granular_bytes_per_launch"] = round(lg)
+        roof["frac_line_granular"] = round(lg / (avg[dom] * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
+    if roof["traffic"]:
+        roof["traffic_GBps"] = round(roof["traffic"] / (avg[dom] * 1e-3) / 1e9, 1)
 
     cpu = None
     if not args.no_cpu_baseline:
