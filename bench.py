@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 25, help="elements per instance for the CPU oracle")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 23, help="elements per instance for the CPU oracle")
     ap.add_argument("--skip", default="", help="comma list of extra workloads to skip: scan,gmm,batch,serve")
     ap.add_argument("--serve-seconds", type=float, default=4.0, help="measured seconds of the serving trace")
     ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
