@@ -379,6 +379,11 @@ def main():
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
 
+    try:
+        achievable = copy_bandwidth()
+    except Exception as e:  # report, keep the main line
+        achievable = f"{type(e).__name__}: {e}"
+
     out = {
         "metric": METRIC,
         "value": round(elems_per_step / (ms_per_step * 1e-3), 1),
@@ -402,6 +407,7 @@ def main():
         "grad_over_primal_max": max(d["grad_over_primal"] for d in detail.values()),
         "served_latency": None,
         "roofline": roof,
+        "copy_GBps_achievable": achievable,
         "cpu_baseline": cpu,
         "detail": detail,
         "other_workloads": extra,
@@ -449,7 +455,100 @@ def bench_scan(args):
                         "primal_GBps": round(32 * n / (tp * 1e-3) / 1e9, 1),
                         "vjp_GBps": round(48 * n / (tv * 1e-3) / 1e9, 1)}
         del a, b, ya, yb, ck, A, B, ab, bb
+    # C1 as 20 back-to-back calls captured in one HIP graph (outputs and
+    # workspaces preallocated and zeroed before the capture; the calls go
+    # straight to the C ABI on the capturing stream): kernel time without the
+    # host's per-call work.
+    from paper_2202_10297_amd import capi
+
+    L = capi.lib()
+    n = 65536
+    a, b, ya, yb = (torch.from_numpy(x).cuda() for x in workloads.linrec(n, "f64", seed=0))
+    A, B, ab, bb = (torch.empty_like(a) for _ in range(4))
+    ck = torch.empty(2 * L.pvjp_linrec_ckpt_len(n), dtype=a.dtype, device=a.device)
+    wf = torch.zeros(L.pvjp_linrec_scan_ws_bytes(capi.F64, n), dtype=torch.uint8, device="cuda")
+    wv = torch.zeros(L.pvjp_linrec_scan_vjp_ws_bytes(capi.F64, n), dtype=torch.uint8, device="cuda")
+    p_ = lambda t: t.data_ptr()
+
+    def prim():
+        capi.call("pvjp_linrec_scan", capi.F64, p_(a), p_(b), n, p_(A), p_(B), p_(ck), p_(wf), wf.numel(),
+                  torch.cuda.current_stream().cuda_stream)
+
+    def vjp():
+        capi.call("pvjp_linrec_scan_vjp", capi.F64, p_(a), p_(b), p_(ya), p_(yb), n, p_(ck), p_(ab), p_(bb), 0,
+                  p_(wv), wv.numel(), torch.cuda.current_stream().cuda_stream)
+
+    prim()
+    torch.cuda.synchronize()
+    graphs = {}
+    for name, fn in (("primal", prim), ("vjp", vjp)):
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr):
+            for _ in range(20):
+                fn()
+        graphs[name] = _events_ms(gr.replay, 20) / 20
+    res["n65536_graph"] = {"primal_us": round(graphs["primal"] * 1e3, 2), "vjp_us": round(graphs["vjp"] * 1e3, 2),
+                           "grad_over_primal": round((graphs["primal"] + graphs["vjp"]) / graphs["primal"], 3)}
+    del a, b, ya, yb, ck, A, B, ab, bb, wf, wv, graphs
+    torch.cuda.empty_cache()
+    # C1 with the 256 MiB last-level cache flushed before every run (a 1 GiB
+    # write between runs), mean and median of 20 event-timed runs.
+    n = 65536
+    a, b, ya, yb = (torch.from_numpy(x).cuda() for x in workloads.linrec(n, "f64", seed=0))
+    _, _, ck = ops.linrec_scan(a, b)
+    ab, bb = torch.empty_like(a), torch.empty_like(b)
+    junk = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    tps, tvs = [], []
+    for _ in range(20):
+        for fn, acc in ((lambda: ops.linrec_scan(a, b), tps),
+                        (lambda: ops.linrec_scan_vjp(a, b, ya, yb, ckpt=ck, a_bar=ab, b_bar=bb), tvs)):
+            junk.fill_(1.0)
+            s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s0.record()
+            fn()
+            s1.record()
+            torch.cuda.synchronize()
+            acc.append(s0.elapsed_time(s1) * 1e3)
+    res["n65536_flushed"] = {"primal_us_mean": round(float(np.mean(tps)), 2),
+                             "primal_us_median": round(float(np.median(tps)), 2),
+                             "vjp_us_mean": round(float(np.mean(tvs)), 2),
+                             "vjp_us_median": round(float(np.median(tvs)), 2)}
+    del junk, a, b, ya, yb, ck, ab, bb
+    torch.cuda.empty_cache()
+    # n-sweep (FP64, a ~ U[0.5, 1), b and the adjoints ~ N(0, 1) drawn on the
+    # device): where HBM starts to bind.
+    sweep = {}
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    for lg in (16, 18, 20, 22, 24, 26, 28):
+        n = 1 << lg
+        a = torch.rand(n, dtype=torch.float64, device="cuda", generator=g) * 0.5 + 0.5
+        b, ya, yb = (torch.randn(n, dtype=torch.float64, device="cuda", generator=g) for _ in range(3))
+        A, B, ck = ops.linrec_scan(a, b)
+        ab, bb = torch.empty_like(a), torch.empty_like(b)
+        reps = 50 if lg <= 22 else 5
+        tp = _events_ms(lambda: ops.linrec_scan(a, b), reps)
+        tv = _events_ms(lambda: ops.linrec_scan_vjp(a, b, ya, yb, ckpt=ck, a_bar=ab, b_bar=bb), reps)
+        sweep[f"2^{lg}"] = {"primal_us": round(tp * 1e3, 1), "vjp_us": round(tv * 1e3, 1),
+                            "primal_hbm_frac": round(32 * n / (tp * 1e-3) / 1e9 / HBM_PEAK_GBPS, 3),
+                            "vjp_hbm_frac": round(48 * n / (tv * 1e-3) / 1e9 / HBM_PEAK_GBPS, 3)}
+        del a, b, ya, yb, A, B, ck, ab, bb
+        torch.cuda.empty_cache()
+    res["fp64_sweep"] = sweep
     return res
+
+
+def copy_bandwidth():
+    """Device-to-device copy of 1 GiB (read + write counted): the achievable
+    HBM rate beside the 8 TB/s datasheet peak."""
+    import torch
+
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    t = _events_ms(lambda: dst.copy_(src), 10)
+    del src, dst
+    torch.cuda.empty_cache()
+    return round(2 * (1 << 30) / (t * 1e-3) / 1e9, 1)
 
 
 def bench_gmm(args):
@@ -572,10 +671,20 @@ def cpu_baseline(ns, vs_np, inst, xs_np, is_np, sv_np, yb_np):
     oracle.scatter_vjp(sel, yb_np[:ns])
     elems += sel.size
     dt = time.perf_counter() - t0
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {
         "value": round(elems / dt, 1),
         "unit": "elems/s",
         "cores": 1,
+        "host_cores": os.cpu_count(),
+        "cpu_model": model,
         "kind": "oracle",
         "sample": f"first {ns} elements of each of the 12 histogram instances (+ and max, primal and taped VJP) "
                   f"and a scatter of {sel.size} targets into {ns}; {dt:.1f}s",

@@ -333,7 +333,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
 #pragma unroll
         for (int s = 0; s < C::S; ++s) bx[s] = Xw[xs_at<D>(j, 2 * s + h)];
         f32x16 z[C::RT];
+        // The MFMA phases run at raised wave priority, so that the other wave
+        // on the SIMD issues its loads and FP64 work in their gaps.
+        __builtin_amdgcn_s_setprio(1);
         const double nrm = tile_znorm_lds<D>(qs, cs, bx, z);
+        __builtin_amdgcn_s_setprio(0);
         const int64_t p = p0 + j;
         double wd = 0.0;
         if (p < N) wd = ell_bar * exp((bk - 0.5 * nrm) - lse[p]);
@@ -356,6 +360,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
         // G_k += (w Z)^T Y over this tile's 32 points, lower-triangular
         // blocks; each step loads one operand per row and column tile and
         // feeds the blocks' independent accumulators in turn.
+        __builtin_amdgcn_s_setprio(1);
 #pragma unroll 4
         for (int s = 0; s < 16; ++s) {
             const int pt = 2 * s + h;
@@ -374,6 +379,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
                     ++g;
                 }
         }
+        __builtin_amdgcn_s_setprio(0);
     }
 
     // For D = 32 the two half-waves hold halves of each row sum.
