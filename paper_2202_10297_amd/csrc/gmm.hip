@@ -168,7 +168,7 @@ __device__ __forceinline__ double tile_znorm_lds(const float* qs, const float* c
     for (int rt = 0; rt < C::RT; ++rt)
 #pragma unroll
         for (int t = 0; t < 16; ++t) acc[rt][t] = 0.f;
-#pragma unroll 4
+#pragma unroll 8
     for (int s = 0; s < C::S; ++s)
 #pragma unroll
         for (int rt = 0; rt < C::RT; ++rt)
@@ -290,7 +290,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
     // the scratch of the cross-wave reduction.  Q_k's MFMA fragments live in
     // LDS too, read at each step: held in registers they would leave room
     // for only one wave per SIMD.
-    __shared__ float smem[2 * 4 * 32 * D];
+    __shared__ __align__(16) float smem[2 * 4 * 32 * D];
     __shared__ float qs[C::NF * 64];
     __shared__ float cs[D];
     float* const Xw = smem + (threadIdx.x >> 6) * 32 * D;
@@ -349,19 +349,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
             for (int t = 0; t < 16; ++t) Zw[zs_at(32 * rt + drow(t, lane), j)] = wf * z[rt][t];
         wave_lds_sync();
         {
+            // The swizzle moves even-odd pairs of points together, so a row is
+            // read as float2 pairs.
             const int r = lane % D;
             const int pb = (D == 32) ? 16 * h : 0;
             constexpr int np = (D == 32) ? 16 : 32;
             float sr = 0.f;
 #pragma unroll
-            for (int pp = 0; pp < np; ++pp) sr += Zw[zs_at(r, pb + pp)];
+            for (int pp = 0; pp < np; pp += 2) {
+                const float2 v2 = *reinterpret_cast<const float2*>(&Zw[zs_at(r, pb + pp)]);
+                sr += v2.x + v2.y;
+            }
             vrow += sr;
         }
         // G_k += (w Z)^T Y over this tile's 32 points, lower-triangular
         // blocks; each step loads one operand per row and column tile and
         // feeds the blocks' independent accumulators in turn.
         __builtin_amdgcn_s_setprio(1);
-#pragma unroll 4
+#pragma unroll 8
         for (int s = 0; s < 16; ++s) {
             const int pt = 2 * s + h;
             float za[C::RT], yb[C::RT];
