@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 23, help="elements per instance for the CPU oracle")
-    ap.add_argument("--skip", default="", help="comma list of extra workloads to skip: scan,gmm,batch,serve")
+    ap.add_argument("--skip", default="", help="comma list of extra workloads to skip: reduce_map,scan,gmm,batch,serve")
     ap.add_argument("--serve-seconds", type=float, default=4.0, help="measured seconds of the serving trace")
     ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn the counter_collection.csv files of a FETCH_SIZE and a WRITE_SIZE run into "
@@ -97,6 +97,7 @@ def call_order():
 CALL_START_KERNELS = ("hist_acc_kernel", "hist_init_kernel", "hpart_count_kernel", "hist_vjp_add_vec_kernel",
                       "hist_vjp_add_lds_kernel", "hist_vjp_add_kernel", "fill_zero_vec_kernel", "scatter_kernel",
                       "scatter_vjp_kernel")
+MAIN_LINE_PREFIXES = ("hist_", "hpart_", "fill_zero", "scatter_")
 CALL_SOURCE = {"hist": "paper_2202_10297_amd/csrc/hist.hip", "scatter": "paper_2202_10297_amd/csrc/scatter.hip"}
 
 
@@ -136,6 +137,8 @@ def ingest_pmc(fetch_csv, write_csv):
             if "pvjp::" not in name:
                 continue
             short = _short_kernel(name)
+            if not short.startswith(MAIN_LINE_PREFIXES):
+                break  # the other workloads run after the main line
             if short in CALL_START_KERNELS or not groups:
                 groups.append([])
             groups[-1].append((short, v))
@@ -368,7 +371,8 @@ def main():
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     extra = {}
-    for name, fn in (("scan", bench_scan), ("gmm", bench_gmm), ("batch", bench_batch), ("serve", bench_serve)):
+    for name, fn in (("reduce_map", bench_reduce_map), ("scan", bench_scan), ("gmm", bench_gmm),
+                     ("batch", bench_batch), ("serve", bench_serve)):
         if name in args.skip:
             continue
         try:
@@ -535,6 +539,48 @@ def bench_scan(args):
         del a, b, ya, yb, A, B, ck, ab, bb
         torch.cuda.empty_cache()
     res["fp64_sweep"] = sweep
+    return res
+
+
+def bench_reduce_map(args):
+    """reduce (+, *, max) and map (exp, tanh) primal and VJP at n = 2^26 FP32
+    and FP64, inputs resident.  Algorithmic bytes: reduce reads n values
+    (primal) and the VJP writes n (+, max: x_bar = y_bar or one-hot after a
+    zero fill) or reads x and writes x_bar (*: p / x_i); map reads x and
+    writes y (primal) and reads x, y_bar and writes x_bar (VJP)."""
+    import torch
+
+    from paper_2202_10297_amd import ops
+
+    n = 1 << 26
+    res = {}
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    for dt, tname, es in ((torch.float32, "f32", 4), (torch.float64, "f64", 8)):
+        x = torch.rand(n, dtype=dt, device="cuda", generator=g) * 1.5 + 0.5  # in [0.5, 2): products stay finite
+        sign = torch.where(torch.rand(n, device="cuda", generator=g) < 0.5, -1.0, 1.0).to(dt)
+        x = x * sign
+        xb = torch.empty_like(x)
+        for op, vjp_bytes in (("add", es), ("mul", 2 * es), ("max", es)):
+            y, aux = ops.reduce(op, x)
+            yb = torch.ones_like(y)
+            tp = _events_ms(lambda: ops.reduce(op, x), 10)
+            tv = _events_ms(lambda: ops.reduce_vjp(op, x, aux, yb, x_bar=xb), 10)
+            res[f"reduce_{op}_{tname}"] = {
+                "primal_ms": round(tp, 4), "vjp_ms": round(tv, 4), "grad_over_primal": round((tp + tv) / tp, 3),
+                "primal_hbm_frac": round(es * n / (tp * 1e-3) / 1e9 / HBM_PEAK_GBPS, 3),
+                "vjp_hbm_frac": round(vjp_bytes * n / (tv * 1e-3) / 1e9 / HBM_PEAK_GBPS, 3)}
+        ybar = torch.randn(n, dtype=dt, device="cuda", generator=g)
+        xa = x.abs()
+        for fn in ("exp", "tanh"):
+            tp = _events_ms(lambda: ops.map_(fn, xa), 10)
+            tv = _events_ms(lambda: ops.map_vjp(fn, xa, ybar, x_bar=xb), 10)
+            res[f"map_{fn}_{tname}"] = {
+                "primal_ms": round(tp, 4), "vjp_ms": round(tv, 4), "grad_over_primal": round((tp + tv) / tp, 3),
+                "primal_hbm_frac": round(2 * es * n / (tp * 1e-3) / 1e9 / HBM_PEAK_GBPS, 3),
+                "vjp_hbm_frac": round(3 * es * n / (tv * 1e-3) / 1e9 / HBM_PEAK_GBPS, 3)}
+        del x, xb, sign, ybar, xa
+        torch.cuda.empty_cache()
     return res
 
 

@@ -84,7 +84,27 @@ __device__ __forceinline__ RedPart block_reduce(RedPart v, RedPart* sh) {
     return r;
 }
 
-template <class T, int OP>
+// Four consecutive elements from 16-byte loads (FP32: one, FP64: two).
+template <class T>
+__device__ __forceinline__ void load4(const T* __restrict__ x, int64_t e, T (&v)[4]) {
+    if (sizeof(T) == 4) {
+        const float4 f = *reinterpret_cast<const float4*>(x + e);
+        v[0] = (T)f.x, v[1] = (T)f.y, v[2] = (T)f.z, v[3] = (T)f.w;
+    } else {
+        const double2 a = *reinterpret_cast<const double2*>(x + e);
+        const double2 b = *reinterpret_cast<const double2*>(x + e + 2);
+        v[0] = (T)a.x, v[1] = (T)a.y, v[2] = (T)b.x, v[3] = (T)b.y;
+    }
+}
+
+// VEC: the chunk starts 16-byte aligned; each thread keeps four partial
+// results (one per position in a quad) and has kRedU quads in flight, so
+// the loads are not serialised behind one accumulator chain.  The partials
+// are combined in a fixed order; MIN/MAX ties still go to the lowest index
+// whatever the order.
+constexpr int kRedU = 4;
+
+template <class T, int OP, bool VEC>
 __global__ __launch_bounds__(kRedBlock) void reduce_kernel(const T* __restrict__ x, int64_t n,
                                                            int64_t chunk, RedHdr* hdr,
                                                            RedPart* parts, T* y, int64_t* arg,
@@ -94,7 +114,30 @@ __global__ __launch_bounds__(kRedBlock) void reduce_kernel(const T* __restrict__
     const int64_t lo = (int64_t)blockIdx.x * chunk;
     const int64_t hi = (lo + chunk < n) ? lo + chunk : n;
     RedPart acc = red_id<OP>();
-    for (int64_t i = lo + threadIdx.x; i < hi; i += kRedBlock) acc = red_comb<OP>(acc, red_elem<T, OP>(x[i], i));
+    int64_t rest = lo;
+    if (VEC) {
+        RedPart a4[4] = {red_id<OP>(), red_id<OP>(), red_id<OP>(), red_id<OP>()};
+        const int64_t q0 = lo >> 2, q1 = hi >> 2;  // whole quads of the chunk
+        for (int64_t q = q0 + threadIdx.x; q < q1; q += (int64_t)kRedBlock * kRedU) {
+            T v[kRedU][4];
+#pragma unroll
+            for (int u = 0; u < kRedU; ++u) {
+                const int64_t qq = q + (int64_t)u * kRedBlock;
+                if (qq < q1) load4<T>(x, 4 * qq, v[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < kRedU; ++u) {
+                const int64_t qq = q + (int64_t)u * kRedBlock;
+                if (qq < q1) {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) a4[t] = red_comb<OP>(a4[t], red_elem<T, OP>(v[u][t], 4 * qq + t));
+                }
+            }
+        }
+        acc = red_comb<OP>(red_comb<OP>(a4[0], a4[1]), red_comb<OP>(a4[2], a4[3]));
+        rest = q1 << 2;
+    }
+    for (int64_t i = rest + threadIdx.x; i < hi; i += kRedBlock) acc = red_comb<OP>(acc, red_elem<T, OP>(x[i], i));
     acc = block_reduce<OP>(acc, sh);
     if (threadIdx.x == 0) {
         st_coherent(&parts[blockIdx.x], acc);
@@ -177,12 +220,18 @@ template <class T, int OP>
 static void launch_reduce(const void* x, int64_t n, void* y, int64_t* arg, void* p, int64_t* z,
                           void* ws, hipStream_t st) {
     const int64_t g = red_grid(n);
-    int64_t chunk = ceil_div(n, g);
+    // chunks are whole 4-element quads, so every chunk of an aligned input
+    // starts aligned
+    const int64_t chunk = ceil_div(ceil_div(n, g), (int64_t)4) * 4;
     const int64_t g2 = n > 0 ? ceil_div(n, chunk) : 1;
     auto* hdr = reinterpret_cast<RedHdr*>(ws);
     auto* parts = reinterpret_cast<RedPart*>(reinterpret_cast<char*>(ws) + sizeof(RedHdr));
-    hipLaunchKernelGGL((reduce_kernel<T, OP>), dim3((unsigned)g2), dim3(kRedBlock), 0, st, (const T*)x,
-                       n, chunk, hdr, parts, (T*)y, arg, (T*)p, z);
+    if (aligned(x, 16))
+        hipLaunchKernelGGL((reduce_kernel<T, OP, true>), dim3((unsigned)g2), dim3(kRedBlock), 0, st, (const T*)x,
+                           n, chunk, hdr, parts, (T*)y, arg, (T*)p, z);
+    else
+        hipLaunchKernelGGL((reduce_kernel<T, OP, false>), dim3((unsigned)g2), dim3(kRedBlock), 0, st, (const T*)x,
+                           n, chunk, hdr, parts, (T*)y, arg, (T*)p, z);
 }
 
 template <class T, int OP>

@@ -180,6 +180,39 @@ def test_reduce_mul(ops, orc, dtype, n, zeros):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("offset", [0, 1, 3])
+def test_reduce_vector_and_unaligned(ops, orc, dtype, offset):
+    # Many blocks of whole quads plus a ragged tail; offset > 0 passes a view
+    # that is not 16-byte aligned (the scalar path).
+    n = 1000003
+    g = workloads.rng(offset + 7)
+    dt = np.float32 if dtype == "f32" else np.float64
+    base = g.uniform(0.995, 1.005, n + offset).astype(dt) * np.where(g.random(n + offset) < 0.5, -1, 1).astype(dt)
+    base[offset + 12345] = 0
+    base[offset + n - 2] = 0
+    x = base[offset:]
+    xd = dev(base)[offset:]
+    y, aux = ops.reduce("mul", xd)
+    ry, _, rp, rz = orc.reduce("mul", x)
+    assert int(host(aux["z"])[0]) == rz == 2
+    # A product of n factors rounds n times: about sqrt(n) units of the last
+    # place; dropping or repeating one factor moves it by ~2.5e-3.
+    ulp = 2.0 ** -53 if dtype == "f64" else 2.0 ** -24
+    assert abs(host(aux["p"])[0] - rp) <= 3 * np.sqrt(n) * ulp * abs(rp)
+    assert host(y)[0] == 0
+    for op in ("min", "max"):
+        xt = workloads.tie_values(n + offset, dtype, seed=offset)[offset:]
+        xtd = dev(workloads.tie_values(n + offset, dtype, seed=offset))[offset:]
+        y, aux = ops.reduce(op, xtd)
+        ry, rarg, _, _ = orc.reduce(op, xt)
+        assert int(host(aux["arg"])[0]) == rarg and host(y)[0] == ry
+    xs = g.standard_normal(n).astype(dt)
+    xsd = dev(np.concatenate([np.zeros(offset, dt), xs]))[offset:]
+    y, _ = ops.reduce("add", xsd)
+    assert abs(host(y)[0] - orc.reduce("add", xs)[0]) <= (1e-12 if dtype == "f64" else 1e-6) * np.abs(xs).sum()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
 @pytest.mark.parametrize("op", ["min", "max"])
 @pytest.mark.parametrize("n", [0, 1, 300, 65537, 1000003])
 def test_reduce_minmax(ops, orc, dtype, op, n):
