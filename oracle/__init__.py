@@ -22,6 +22,8 @@ ADD, MUL, MIN, MAX = 0, 1, 2, 3
 OPS = {"add": ADD, "mul": MUL, "min": MIN, "max": MAX}
 FN_SQUARE, FN_EXP, FN_LOG, FN_SIN, FN_TANH = 0, 1, 2, 3, 4
 FNS = {"square": FN_SQUARE, "exp": FN_EXP, "log": FN_LOG, "sin": FN_SIN, "tanh": FN_TANH}
+GOP_LOGADDEXP, GOP_LINREC, GOP_MAT2 = 0, 1, 2
+GOPS = {"logaddexp": GOP_LOGADDEXP, "linrec": GOP_LINREC, "mat2": GOP_MAT2}
 
 _lib = None
 
@@ -45,6 +47,10 @@ _SIGS = {
     "orc_fig1_vjp": [_L, _P, _P, _P, _P, _P, _P],
     "orc_gmm_objective": [_L, _I, _I, _P, _P, _P, _P, _P, _P, _P],
     "orc_gmm_vjp": [_L, _I, _I, _P, _P, _P, _P, _P, _D, _P, _P, _P, _P],
+    "orc_gop_components": [_I],
+    "orc_reduce_generic": [_I, _L, _P, _P],
+    "orc_reduce_generic_vjp": [_I, _L, _P, _P, _P],
+    "orc_reduce_generic_vjp_at": [_I, _L, _P, _P, _L, _P, _P],
 }
 
 
@@ -226,3 +232,50 @@ def gmm_vjp(X, alpha, mu, q, l, ell_bar=1.0):
     _check(lib().orc_gmm_vjp(N, D, K, _p(X), _p(alpha), _p(mu), _p(q), _p(l), float(ell_bar),
                              _p(ab), _p(mb), _p(qb), _p(lb)), "gmm_vjp")
     return ab, mb, qb, lb
+
+
+# ------------------------------------------------------ generic-operator reduce
+def _gop(op):
+    return GOPS.get(op, op)
+
+
+def _components(op, xs):
+    K = lib().orc_gop_components(_gop(op))
+    if K == 0 or len(xs) != K:
+        raise ValueError(f"operator {op} takes {K} component arrays, got {len(xs)}")
+    xs = [_f64(x) for x in xs]
+    n = xs[0].size
+    if any(x.size != n for x in xs):
+        raise ValueError("component arrays differ in length")
+    ptrs = (ctypes.c_void_p * K)(*[x.ctypes.data for x in xs])
+    return xs, ptrs, n, K
+
+
+def reduce_generic(op, xs):
+    """y = xs_0 (.) ... (.) xs_{n-1}; xs is a list of K component arrays.
+    Returns K floats."""
+    xs, ptrs, n, K = _components(op, xs)
+    y = np.empty(K)
+    _check(lib().orc_reduce_generic(_gop(op), n, ptrs, _p(y)), "reduce_generic")
+    return y
+
+
+def reduce_generic_vjp(op, xs, y_bar):
+    """Adjoints of every element: a list of K arrays."""
+    xs, ptrs, n, K = _components(op, xs)
+    yb = _f64(y_bar).reshape(K)
+    out = [np.empty(n) for _ in range(K)]
+    optr = (ctypes.c_void_p * K)(*[o.ctypes.data for o in out])
+    _check(lib().orc_reduce_generic_vjp(_gop(op), n, ptrs, _p(yb), optr), "reduce_generic_vjp")
+    return out
+
+
+def reduce_generic_vjp_at(op, xs, y_bar, idx):
+    """Adjoints of the elements idx only: array [len(idx), K]."""
+    xs, ptrs, n, K = _components(op, xs)
+    yb = _f64(y_bar).reshape(K)
+    idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64))
+    out = np.empty((idx.size, K))
+    _check(lib().orc_reduce_generic_vjp_at(_gop(op), n, ptrs, _p(yb), idx.size, _p(idx), _p(out)),
+           "reduce_generic_vjp_at")
+    return out

@@ -733,3 +733,214 @@ int orc_gmm_vjp(int64_t N, int D, int K, const double* X, const double* alpha,
     tape_free(t);
     return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* reduce with a general associative operator (Sec. 5.1.1): the left fold     */
+/* acc = e; acc = acc (.) x_i for i = 0..n-1.  Each operator step is written  */
+/* out of elementary steps; the VJP records them on the tape.                 */
+/* ------------------------------------------------------------------------ */
+
+int orc_gop_components(int op) {
+    switch (op) {
+        case ORC_GOP_LOGADDEXP: return 1;
+        case ORC_GOP_LINREC: return 2;
+        case ORC_GOP_MAT2: return 4;
+        default: return 0;
+    }
+}
+
+static void gop_neutral(int op, double* e) {
+    switch (op) {
+        case ORC_GOP_LOGADDEXP: e[0] = -INFINITY; break;
+        case ORC_GOP_LINREC: e[0] = 1.0, e[1] = 0.0; break;
+        default: e[0] = 1.0, e[1] = 0.0, e[2] = 0.0, e[3] = 1.0;
+    }
+}
+
+/* out = l (.) r on plain values (out may alias l or r). */
+static void gop_comb(int op, const double* l, const double* r, double* out) {
+    double o[4];
+    switch (op) {
+        case ORC_GOP_LOGADDEXP:
+            if (r[0] == -INFINITY) o[0] = l[0];
+            else if (l[0] == -INFINITY) o[0] = r[0];
+            else {
+                double m = l[0] > r[0] ? l[0] : r[0];
+                o[0] = m + log(exp(l[0] - m) + exp(r[0] - m));
+            }
+            break;
+        case ORC_GOP_LINREC:
+            o[0] = r[0] * l[0];
+            o[1] = r[0] * l[1] + r[1];
+            break;
+        default:
+            o[0] = l[0] * r[0] + l[1] * r[2];
+            o[1] = l[0] * r[1] + l[1] * r[3];
+            o[2] = l[2] * r[0] + l[3] * r[2];
+            o[3] = l[2] * r[1] + l[3] * r[3];
+    }
+    for (int c = 0; c < orc_gop_components(op); ++c) out[c] = o[c];
+}
+
+/* Records out = l (.) r on the tape (slot arrays of K entries). */
+static void gop_step(tape_t* t, int op, const int64_t* l, const int64_t* r, int64_t* out) {
+    int64_t o[4];
+    switch (op) {
+        case ORC_GOP_LOGADDEXP:
+            if (V(r[0]) == -INFINITY) o[0] = l[0]; /* r contributes nothing */
+            else if (V(l[0]) == -INFINITY) o[0] = r[0];
+            else {
+                /* the shift m is a constant: d/da log(e^(a-m) + e^(b-m)) + m
+                 * does not depend on it */
+                int64_t m = leaf(t, V(l[0]) > V(r[0]) ? V(l[0]) : V(r[0]));
+                int64_t s = t_add(t, t_exp(t, t_sub(t, l[0], m)), t_exp(t, t_sub(t, r[0], m)));
+                o[0] = t_add(t, t_log(t, s), m);
+            }
+            break;
+        case ORC_GOP_LINREC:
+            o[0] = t_mul(t, r[0], l[0]);
+            o[1] = t_add(t, t_mul(t, r[0], l[1]), r[1]);
+            break;
+        default:
+            o[0] = t_add(t, t_mul(t, l[0], r[0]), t_mul(t, l[1], r[2]));
+            o[1] = t_add(t, t_mul(t, l[0], r[1]), t_mul(t, l[1], r[3]));
+            o[2] = t_add(t, t_mul(t, l[2], r[0]), t_mul(t, l[3], r[2]));
+            o[3] = t_add(t, t_mul(t, l[2], r[1]), t_mul(t, l[3], r[3]));
+    }
+    for (int c = 0; c < orc_gop_components(op); ++c) out[c] = o[c];
+}
+
+static int gop_args_ok(int op, int64_t n, const double* const* x) {
+    int K = orc_gop_components(op);
+    if (K == 0 || n < 0) return 0;
+    if (n > 0) {
+        if (!x) return 0;
+        for (int c = 0; c < K; ++c)
+            if (!x[c]) return 0;
+    }
+    return 1;
+}
+
+int orc_reduce_generic(int op, int64_t n, const double* const* x, double* y) {
+    if (!gop_args_ok(op, n, x) || !y) return -1;
+    int K = orc_gop_components(op);
+    double acc[4], xi[4];
+    gop_neutral(op, acc);
+    for (int64_t i = 0; i < n; ++i) {
+        for (int c = 0; c < K; ++c) xi[c] = x[c][i];
+        gop_comb(op, acc, xi, acc);
+    }
+    for (int c = 0; c < K; ++c) y[c] = acc[c];
+    return 0;
+}
+
+int orc_reduce_generic_vjp(int op, int64_t n, const double* const* x, const double* y_bar,
+                           double* const* x_bar) {
+    if (!gop_args_ok(op, n, x) || !y_bar) return -1;
+    int K = orc_gop_components(op);
+    if (n == 0) return 0;
+    for (int c = 0; c < K; ++c)
+        if (!x_bar || !x_bar[c]) return -1;
+    tape_t T, *t = &T;
+    if (tape_init(t, (int64_t)(K * 4 + 4) * n + 16, (int64_t)(K * 3 + 4) * n + 16)) return -2;
+    int64_t* sx = (int64_t*)malloc((size_t)n * K * sizeof(int64_t));
+    if (!sx) {
+        tape_free(t);
+        return -2;
+    }
+    double e[4];
+    gop_neutral(op, e);
+    int64_t acc[4];
+    for (int c = 0; c < K; ++c) acc[c] = leaf(t, e[c]); /* constants */
+    for (int64_t i = 0; i < n; ++i) {
+        for (int c = 0; c < K; ++c) sx[i * K + c] = leaf(t, x[c][i]);
+        gop_step(t, op, acc, &sx[i * K], acc);
+    }
+    int rc = (t->oom || tape_reverse(t)) ? -2 : 0;
+    if (!rc) {
+        for (int c = 0; c < K; ++c) t->adj[acc[c]] += y_bar[c];
+        sweep(t);
+        for (int64_t i = 0; i < n; ++i)
+            for (int c = 0; c < K; ++c) x_bar[c][i] = t->adj[sx[i * K + c]];
+    }
+    free(sx);
+    tape_free(t);
+    return rc;
+}
+
+static int cmp_i64(const void* a, const void* b) {
+    int64_t x = *(const int64_t*)a, y = *(const int64_t*)b;
+    return (x > y) - (x < y);
+}
+
+int orc_reduce_generic_vjp_at(int op, int64_t n, const double* const* x, const double* y_bar,
+                              int64_t cnt, const int64_t* idx, double* out) {
+    if (!gop_args_ok(op, n, x) || !y_bar || cnt < 0 || (cnt > 0 && (!idx || !out))) return -1;
+    int K = orc_gop_components(op);
+    for (int64_t j = 0; j < cnt; ++j)
+        if (idx[j] < 0 || idx[j] >= n) return -1;
+    if (cnt == 0) return 0;
+    /* samples in index order; L[j], R[j]: folds before and after sample j */
+    int64_t* ord = (int64_t*)malloc((size_t)cnt * sizeof(int64_t));
+    double* L = (double*)malloc((size_t)cnt * K * sizeof(double));
+    double* R = (double*)malloc((size_t)cnt * K * sizeof(double));
+    if (!ord || !L || !R) {
+        free(ord), free(L), free(R);
+        return -2;
+    }
+    for (int64_t j = 0; j < cnt; ++j) ord[j] = idx[j];
+    qsort(ord, (size_t)cnt, sizeof(int64_t), cmp_i64);
+    double acc[4], xi[4];
+    gop_neutral(op, acc);
+    int64_t j = 0;
+    for (int64_t i = 0; i < n && j < cnt; ++i) {
+        while (j < cnt && ord[j] == i) {
+            for (int c = 0; c < K; ++c) L[j * K + c] = acc[c];
+            ++j;
+        }
+        for (int c = 0; c < K; ++c) xi[c] = x[c][i];
+        gop_comb(op, acc, xi, acc);
+    }
+    /* right folds: r = x_{i+1} (.) r, walking down from the end */
+    gop_neutral(op, acc);
+    j = cnt - 1;
+    for (int64_t i = n - 1; i >= 0 && j >= 0; --i) {
+        while (j >= 0 && ord[j] == i) {
+            for (int c = 0; c < K; ++c) R[j * K + c] = acc[c];
+            --j;
+        }
+        for (int c = 0; c < K; ++c) xi[c] = x[c][i];
+        gop_comb(op, xi, acc, acc);
+    }
+    int rc = 0;
+    tape_t T, *t = &T;
+    if (tape_init(t, 64, 64)) rc = -2;
+    for (int64_t s = 0; s < cnt && !rc; ++s) {
+        /* position of idx[s] among the sorted samples */
+        int64_t lo = 0, hi = cnt - 1;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) / 2;
+            if (ord[mid] < idx[s]) lo = mid + 1;
+            else hi = mid;
+        }
+        tape_clear(t);
+        int64_t sl[4], sa[4], sr[4], acc_s[4];
+        for (int c = 0; c < K; ++c) {
+            sl[c] = leaf(t, L[lo * K + c]);
+            sa[c] = leaf(t, x[c][idx[s]]);
+            sr[c] = leaf(t, R[lo * K + c]);
+        }
+        gop_step(t, op, sl, sa, acc_s);
+        gop_step(t, op, acc_s, sr, acc_s);
+        if (t->oom || tape_reverse(t)) {
+            rc = -2;
+            break;
+        }
+        for (int c = 0; c < K; ++c) t->adj[acc_s[c]] += y_bar[c];
+        sweep(t);
+        for (int c = 0; c < K; ++c) out[s * K + c] = t->adj[sa[c]];
+    }
+    tape_free(t);
+    free(ord), free(L), free(R);
+    return rc;
+}

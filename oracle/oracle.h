@@ -88,6 +88,30 @@ int orc_gmm_vjp(int64_t N, int D, int K, const double* X, const double* alpha,
                 const double* mu, const double* q, const double* l, double ell_bar,
                 double* alpha_bar, double* mu_bar, double* q_bar, double* l_bar);
 
+/* reduce with a general associative operator (Sec. 5.1.1, general rule):
+ * y = x_0 (.) x_1 (.) ... (.) x_{n-1}, a left fold from the neutral element.
+ * An element has K components, each a separate array (x[c][i]):
+ *   LOGADDEXP (K=1): a (.) b = log(exp(a) + exp(b)), neutral -inf.  Inputs
+ *       are finite or -inf; a -inf element contributes nothing and receives
+ *       a zero adjoint.
+ *   LINREC (K=2, components a, b): (a1,b1) (.) (a2,b2) = (a2*a1, a2*b1 + b2),
+ *       neutral (1, 0).
+ *   MAT2 (K=4, row-major m00, m01, m10, m11): the 2x2 matrix product
+ *       y = x_0 x_1 ... x_{n-1}, neutral the identity.
+ * y, y_bar: K values.  x_bar: K arrays of n, overwritten.  The VJP records
+ * the fold's elementary steps on the tape and sweeps it in reverse.
+ * orc_reduce_generic_vjp_at gives the adjoints of the elements idx[0..cnt)
+ * only (out[j*K + c]), in O(n) time and O(cnt) memory: the left fold before
+ * and the right fold after each sampled element are plain FP64 folds, and
+ * only the three-operand fold l (.) x_i (.) r is recorded and swept. */
+enum { ORC_GOP_LOGADDEXP = 0, ORC_GOP_LINREC = 1, ORC_GOP_MAT2 = 2 };
+int orc_gop_components(int op);
+int orc_reduce_generic(int op, int64_t n, const double* const* x, double* y);
+int orc_reduce_generic_vjp(int op, int64_t n, const double* const* x, const double* y_bar,
+                           double* const* x_bar);
+int orc_reduce_generic_vjp_at(int op, int64_t n, const double* const* x, const double* y_bar,
+                              int64_t cnt, const int64_t* idx, double* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,7 +16,12 @@ measured on:
 * scatter: 2^24-style unique target indices drawn without replacement;
 * Gaussian mixture: X ~ N(0,1), alpha ~ N(0,1), mu ~ N(0,1), q and l ~
   N(0, 0.1) (standard deviation 0.1);
-* segmented batches: lengths floor(exp(U[ln lo, ln hi])).
+* segmented batches: lengths floor(exp(U[ln lo, ln hi]));
+* reduce with a general operator: log-add-exp values ~ N(0, 1); linear-
+  recurrence pairs as for the scan; 2x2 matrices that are rotations, each
+  composed with the reflection diag(1, -1) with probability 1/2, so that
+  products of any length stay orthogonal (no overflow or underflow) while
+  the factors do not commute.
 """
 from __future__ import annotations
 
@@ -121,3 +126,32 @@ def gmm(N: int, D: int, K: int, seed: int = 0, dtype="f32"):
 def segment_lengths(nseg: int, lo: int, hi: int, seed: int = 0) -> np.ndarray:
     g = rng(seed)
     return np.floor(np.exp(g.uniform(np.log(lo), np.log(hi), nseg))).astype(np.int64)
+
+
+def gop(op: str, n: int, dtype="f64", seed: int = 0, general: bool = False):
+    """(components, y_bar) for a reduce with a general operator.  components
+    is a list of K arrays of length n; y_bar has K entries ~ N(0, 1).  With
+    `general`, mat2 factors are dense N(0, 1/2) matrices instead (short
+    inputs only: their products grow or shrink geometrically)."""
+    g = rng(seed)
+    dt = _dt(dtype)
+    if op == "logaddexp":
+        xs = [g.standard_normal(n).astype(dt)]
+        yb = g.standard_normal(1).astype(dt)
+    elif op == "linrec":
+        xs = [g.uniform(0.5, 1.0, n).astype(dt), g.standard_normal(n).astype(dt)]
+        yb = g.standard_normal(2).astype(dt)
+    elif op == "mat2":
+        if general:
+            m = g.standard_normal((4, n)) * np.sqrt(0.5)
+        else:
+            th = g.uniform(-np.pi, np.pi, n)
+            f = np.where(g.random(n) < 0.5, -1.0, 1.0)
+            c, s_ = np.cos(th), np.sin(th)
+            # [[c, -s], [s, c]] @ diag(1, f)
+            m = np.stack([c, -s_ * f, s_, c * f])
+        xs = [m[k].astype(dt) for k in range(4)]
+        yb = g.standard_normal(4).astype(dt)
+    else:
+        raise ValueError(f"unknown operator {op}")
+    return xs, yb
