@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 23, help="elements per instance for the CPU oracle")
-    ap.add_argument("--skip", default="", help="comma list of extra workloads to skip: reduce_map,scan,gmm,batch,serve")
+    ap.add_argument("--skip", default="", help="comma list of extra workloads to skip: reduce_map,reduce_generic,scan,gmm,batch,serve")
     ap.add_argument("--serve-seconds", type=float, default=4.0, help="measured seconds of the serving trace")
     ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn the counter_collection.csv files of a FETCH_SIZE and a WRITE_SIZE run into "
@@ -371,8 +371,8 @@ def main():
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     extra = {}
-    for name, fn in (("reduce_map", bench_reduce_map), ("scan", bench_scan), ("gmm", bench_gmm),
-                     ("batch", bench_batch), ("serve", bench_serve)):
+    for name, fn in (("reduce_map", bench_reduce_map), ("reduce_generic", bench_reduce_generic),
+                     ("scan", bench_scan), ("gmm", bench_gmm), ("batch", bench_batch), ("serve", bench_serve)):
         if name in args.skip:
             continue
         try:
@@ -581,6 +581,51 @@ def bench_reduce_map(args):
                 "vjp_hbm_frac": round(3 * es * n / (tv * 1e-3) / 1e9 / HBM_PEAK_GBPS, 3)}
         del x, xb, sign, ybar, xa
         torch.cuda.empty_cache()
+    return res
+
+
+def bench_reduce_generic(args):
+    """reduce with a general operator (Sec. 5.1.1, general rule) and its VJP
+    at n = 2^26 elements, inputs resident: log-add-exp (K = 1), the linear
+    recurrence (K = 2) and the 2x2 matrix product (K = 4).  Algorithmic bytes:
+    the primal reads the n K components; the VJP reads them and writes their
+    adjoints (2 n K per element size).  The kernels move 3 n K (x is read
+    twice: tile folds, then prefixes/suffixes and f); the rule as the paper
+    states it, two whole-array scans plus a map, needs at least 5."""
+    import torch
+
+    from paper_2202_10297_amd import ops
+
+    n = 1 << 26
+    res = {}
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    for op, K in (("logaddexp", 1), ("linrec", 2), ("mat2", 4)):
+        for dt, tname, es in ((torch.float32, "f32", 4), (torch.float64, "f64", 8)):
+            if op == "logaddexp":
+                xs = [torch.randn(n, dtype=dt, device="cuda", generator=g)]
+            elif op == "linrec":
+                xs = [torch.rand(n, dtype=dt, device="cuda", generator=g) * 0.5 + 0.5,
+                      torch.randn(n, dtype=dt, device="cuda", generator=g)]
+            else:  # rotations, each composed with diag(1, -1) with probability 1/2
+                th = (torch.rand(n, dtype=dt, device="cuda", generator=g) * 2 - 1) * 3.141592653589793
+                f = torch.where(torch.rand(n, device="cuda", generator=g) < 0.5, -1.0, 1.0).to(dt)
+                c, s_ = torch.cos(th), torch.sin(th)
+                xs = [c, -s_ * f, s_, c * f]
+                del th, f
+            yb = [torch.randn(1, dtype=dt, device="cuda", generator=g) for _ in range(K)]
+            xb = [torch.empty_like(x) for x in xs]
+            tp = _events_ms(lambda: ops.reduce_generic(op, xs), 10)
+            tv = _events_ms(lambda: ops.reduce_generic_vjp(op, xs, yb, x_bar=xb), 10)
+            comp = n * K * es
+            res[f"{op}_{tname}"] = {
+                "primal_ms": round(tp, 4), "vjp_ms": round(tv, 4), "grad_over_primal": round((tp + tv) / tp, 3),
+                "primal_hbm_frac": round(comp / (tp * 1e-3) / 1e9 / HBM_PEAK_GBPS, 3),
+                "vjp_hbm_frac_algorithmic": round(2 * comp / (tv * 1e-3) / 1e9 / HBM_PEAK_GBPS, 3),
+                "vjp_hbm_frac_moved": round(3 * comp / (tv * 1e-3) / 1e9 / HBM_PEAK_GBPS, 3),
+                "vjp_elems_per_s": round(n / (tv * 1e-3), 1)}
+            del xs, xb, yb
+            torch.cuda.empty_cache()
     return res
 
 

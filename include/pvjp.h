@@ -69,6 +69,15 @@ typedef enum {
     PVJP_FN_TANH = 4
 } pvjp_fn;
 
+/* Associative operators for reduce by the general rule of Sec. 5.1.1.  An
+ * element has K components, each stored in its own array:
+ *  LOGADDEXP (K=1): a (.) b = log(exp(a) + exp(b)), neutral -inf;
+ *  LINREC    (K=2, a then b): (a1,b1) (.) (a2,b2) = (a2*a1, a2*b1 + b2),
+ *            neutral (1, 0) (the operator of the scan of Sec. 5.2);
+ *  MAT2      (K=4, row-major m00 m01 m10 m11): 2x2 matrix product in index
+ *            order, y = x_0 x_1 ... x_{n-1}, neutral the identity. */
+typedef enum { PVJP_GOP_LOGADDEXP = 0, PVJP_GOP_LINREC = 1, PVJP_GOP_MAT2 = 2 } pvjp_gop;
+
 /* ------------------------------------------------------------------------ */
 /* Library                                                                    */
 /* ------------------------------------------------------------------------ */
@@ -227,6 +236,39 @@ pvjp_status pvjp_fig1(pvjp_dtype dtype, const void* x0, const void* x1, int64_t 
 pvjp_status pvjp_fig1_vjp(pvjp_dtype dtype, const void* x0, const void* x1, const void* y0_bar,
                           const void* y1_bar, int64_t n, void* x0_bar, void* x1_bar,
                           int accumulate, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* reduce with a general associative operator (Sec. 5.1.1, general rule):     */
+/* y = x_0 (.) ... (.) x_{n-1}.  Its VJP maps                                  */
+/*   x_bar_i (+)= (d(ls_i (.) x_i (.) rs_i)/dx_i)^T y_bar                      */
+/* over the exclusive prefix folds ls and exclusive suffix folds rs, which     */
+/* are recomputed from x (no tape).  Element i is (x[0][i], .., x[K-1][i]).   */
+/* ------------------------------------------------------------------------ */
+
+/* K of an operator (1, 2 or 4); 0 for an unknown operator. */
+int pvjp_gop_components(pvjp_gop op);
+/* Workspace bytes for both entry points (device memory owned by the caller,
+ * 256-byte aligned, no initialisation needed): 96 bytes per tile of 2048
+ * (FP32) or 1024 (FP64) elements, rounded up. */
+size_t pvjp_reduce_generic_ws_bytes(pvjp_gop op, pvjp_dtype dtype, int64_t n);
+/* x: host array of K device pointers to n elements each (unused if n == 0).
+ * y: host array of K device pointers to one element of dtype each; receives
+ * the fold (the neutral element if n == 0).  Deterministic: fixed tiles and
+ * a fixed combination tree.  LOGADDEXP inputs must be finite or -inf.  With
+ * FP32 data the LINREC and MAT2 folds are formed in FP64 (LOGADDEXP in FP32). */
+pvjp_status pvjp_reduce_generic(pvjp_gop op, pvjp_dtype dtype, const void* const* x, int64_t n,
+                                void* const* y, void* ws, size_t ws_bytes, void* stream);
+/* y_bar: host array of K device pointers to one element each; x_bar: host
+ * array of K device pointers to n elements each, overwritten (accumulate = 0)
+ * or added to.  LOGADDEXP: x_bar_i = y_bar * exp(x_i - (ls_i (.) x_i (.)
+ * rs_i)), and 0 where x_i = -inf.  LINREC, with ls_i = (Al, Bl) and
+ * rs_i = (Ar, Br): a_bar_i = Ar*(y_bar_A*Al + y_bar_B*Bl), b_bar_i =
+ * Ar*y_bar_B.  MAT2: A_bar_i = ls_i^T Y_bar rs_i^T.  Three
+ * kernels: tile folds, one block scanning them both ways, then per tile the
+ * in-tile folds and f (x read twice, x_bar written once). */
+pvjp_status pvjp_reduce_generic_vjp(pvjp_gop op, pvjp_dtype dtype, const void* const* x, int64_t n,
+                                    const void* const* y_bar, void* const* x_bar, int accumulate,
+                                    void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Segmented batches: many instances of uneven length stored back to back     */

@@ -52,6 +52,27 @@ class Reduce(torch.autograd.Function):
         return xb, None
 
 
+class ReduceGeneric(torch.autograd.Function):
+    """y = x_0 (.) ... (.) x_{n-1} for a general operator (Sec. 5.1.1); the
+    inputs are the K component tensors, the outputs K scalars.  Nothing but
+    the inputs is saved: the backward recomputes the prefix and suffix folds."""
+
+    @staticmethod
+    def forward(ctx, op, *xs):
+        xs = [x.contiguous() for x in xs]
+        ys = ops.reduce_generic(op, xs)
+        ctx.op = op
+        ctx.save_for_backward(*xs)
+        return tuple(y.reshape(()) for y in ys)
+
+    @staticmethod
+    def backward(ctx, *gys):
+        xs = ctx.saved_tensors
+        yb = [torch.zeros(1, dtype=xs[0].dtype, device=xs[0].device) if g is None else g.reshape(1).contiguous()
+              for g in gys]
+        return (None, *ops.reduce_generic_vjp(ctx.op, xs, yb))
+
+
 class ReduceByIndex(torch.autograd.Function):
     """hs = reduce_by_index(op) over bins inds[i] of vs[i], m bins."""
 
@@ -131,6 +152,10 @@ def linrec_scan(a, b):
 
 def reduce(x, op="add"):
     return Reduce.apply(x, op)
+
+
+def reduce_generic(op, *xs):
+    return ReduceGeneric.apply(op, *xs)
 
 
 def reduce_by_index(vs, inds, m, op="add"):

@@ -16,6 +16,7 @@ PVJP_OK, PVJP_EINVAL, PVJP_ENOMEM, PVJP_EDEVICE, PVJP_EUNSUPPORTED = 0, 1, 2, 3,
 F32, F64 = 0, 1
 ADD, MUL, MIN, MAX = 0, 1, 2, 3
 FN_SQUARE, FN_EXP, FN_LOG, FN_SIN, FN_TANH = 0, 1, 2, 3, 4
+GOP_LOGADDEXP, GOP_LINREC, GOP_MAT2 = 0, 1, 2
 LINREC_CKPT_INTERVAL = 1024
 
 _P = ctypes.c_void_p
@@ -47,6 +48,10 @@ SIGNATURES = {
     "pvjp_map_vjp": (_I, [_I, _I, _P, _P, _L, _P, _I, _P]),
     "pvjp_fig1": (_I, [_I, _P, _P, _L, _P, _P, _P]),
     "pvjp_fig1_vjp": (_I, [_I, _P, _P, _P, _P, _L, _P, _P, _I, _P]),
+    "pvjp_gop_components": (_I, [_I]),
+    "pvjp_reduce_generic_ws_bytes": (_Z, [_I, _I, _L]),
+    "pvjp_reduce_generic": (_I, [_I, _I, _P, _L, _P, _P, _Z, _P]),
+    "pvjp_reduce_generic_vjp": (_I, [_I, _I, _P, _L, _P, _P, _I, _P, _Z, _P]),
     "pvjp_seg_ws_bytes": (_Z, [_L, _L, _I]),
     "pvjp_seg_prepare": (_I, [_P, _L, _I, _P, _Z, _P]),
     "pvjp_seg_linrec_scan": (_I, [_I, _P, _P, _L, _L, _I, _P, _P, _P, _P, _Z, _P]),
@@ -89,6 +94,12 @@ def last_error() -> str:
 
 def version() -> str:
     return lib().pvjp_version().decode()
+
+
+def ptr_array(ptrs):
+    """A host array of device pointers (the K component arrays of an
+    element); None entries become NULL."""
+    return (ctypes.c_void_p * len(ptrs))(*[p or None for p in ptrs])
 
 
 def call(name: str, *args):

@@ -12,6 +12,7 @@ from . import capi
 
 _DT = {torch.float32: capi.F32, torch.float64: capi.F64}
 _OPS = {"add": capi.ADD, "mul": capi.MUL, "min": capi.MIN, "max": capi.MAX}
+_GOPS = {"logaddexp": capi.GOP_LOGADDEXP, "linrec": capi.GOP_LINREC, "mat2": capi.GOP_MAT2}
 _FNS = {"square": capi.FN_SQUARE, "exp": capi.FN_EXP, "log": capi.FN_LOG, "sin": capi.FN_SIN,
         "tanh": capi.FN_TANH}
 
@@ -127,6 +128,53 @@ def reduce_vjp(op, x, aux, y_bar, x_bar=None, accumulate=False):
         x_bar = torch.zeros_like(x) if accumulate else torch.empty_like(x)
     capi.call("pvjp_reduce_vjp", o, dt, _ptr(x), n, _ptr(aux.get("arg")), _ptr(aux.get("p")), _ptr(aux.get("z")),
               _ptr(y_bar), _ptr(x_bar), int(accumulate), _stream(x.device))
+    return x_bar
+
+
+# ------------------------------------------------ reduce, general operator
+def _gop(op) -> int:
+    return _GOPS[op] if isinstance(op, str) else int(op)
+
+
+def _components(op, xs):
+    K = capi.lib().pvjp_gop_components(_gop(op))
+    xs = list(xs)
+    if K == 0 or len(xs) != K:
+        raise ValueError(f"operator {op} takes {K} component tensors, got {len(xs)}")
+    n = xs[0].numel()
+    if any(x.numel() != n or x.dtype != xs[0].dtype or x.device != xs[0].device for x in xs):
+        raise ValueError("component tensors differ in length, dtype or device")
+    return xs, n, K
+
+
+def reduce_generic(op, xs):
+    """y = xs_0 (.) ... (.) xs_{n-1} for an operator of Sec. 5.1.1's general
+    rule; xs is the list of K component tensors.  Returns K one-element
+    tensors."""
+    xs, n, K = _components(op, xs)
+    dt, dev = _dt(xs[0]), xs[0].device
+    ys = [torch.empty(1, dtype=xs[0].dtype, device=dev) for _ in range(K)]
+    nb = capi.lib().pvjp_reduce_generic_ws_bytes(_gop(op), dt, n)
+    ws = WS.get("reduce_generic", nb, dev)
+    capi.call("pvjp_reduce_generic", _gop(op), dt, capi.ptr_array([_ptr(x) for x in xs]), n,
+              capi.ptr_array([_ptr(y) for y in ys]), _ptr(ws), ws.numel(), _stream(dev))
+    return ys
+
+
+def reduce_generic_vjp(op, xs, y_bar, x_bar=None, accumulate=False):
+    """x_bar (+)= the adjoint of every element (list of K tensors); y_bar is
+    a list of K one-element device tensors."""
+    xs, n, K = _components(op, xs)
+    dt, dev = _dt(xs[0]), xs[0].device
+    if x_bar is None:
+        x_bar = [torch.zeros_like(x) if accumulate else torch.empty_like(x) for x in xs]
+    if len(y_bar) != K or len(x_bar) != K:
+        raise ValueError(f"operator {op} takes {K} components")
+    nb = capi.lib().pvjp_reduce_generic_ws_bytes(_gop(op), dt, n)
+    ws = WS.get("reduce_generic", nb, dev)
+    capi.call("pvjp_reduce_generic_vjp", _gop(op), dt, capi.ptr_array([_ptr(x) for x in xs]), n,
+              capi.ptr_array([_ptr(y) for y in y_bar]), capi.ptr_array([_ptr(x) for x in x_bar]),
+              int(accumulate), _ptr(ws), ws.numel(), _stream(dev))
     return x_bar
 
 

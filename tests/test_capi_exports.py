@@ -79,3 +79,28 @@ def test_workspace_queries(capi):
     # FP64 has no partitioned path: the direct-mapped cache needs no partials
     assert L.pvjp_hist_ws_bytes(capi.ADD, capi.F64, n, 1 << 20) < 64 << 20
     assert L.pvjp_reduce_ws_bytes(capi.ADD, capi.F32, 0) > 0
+
+
+def test_generic_reduce_validation(capi):
+    L = capi.lib()
+    assert [L.pvjp_gop_components(k) for k in range(4)] == [1, 2, 4, 0]
+    # 96 bytes per tile (three 32-byte slots), each array rounded to 256 bytes
+    assert L.pvjp_reduce_generic_ws_bytes(capi.GOP_LOGADDEXP, capi.F32, 2048 * 100) == 3 * 3328
+    assert L.pvjp_reduce_generic_ws_bytes(capi.GOP_MAT2, capi.F64, 1024 * 8 + 1) == 3 * 512
+    assert L.pvjp_reduce_generic_ws_bytes(7, capi.F32, 10) == 0
+    one = capi.ptr_array([256])
+    assert L.pvjp_reduce_generic(7, capi.F32, one, 10, one, 256, 1 << 20, None) == capi.PVJP_EINVAL
+    assert "operator" in capi.last_error()
+    assert L.pvjp_reduce_generic(capi.GOP_LOGADDEXP, 5, one, 10, one, 256, 1 << 20, None) == capi.PVJP_EINVAL
+    assert L.pvjp_reduce_generic(capi.GOP_LOGADDEXP, capi.F32, one, 10, one, 256, 16, None) == capi.PVJP_ENOMEM
+    assert L.pvjp_reduce_generic(capi.GOP_LOGADDEXP, capi.F32, one, 10, one, 100, 1 << 20, None) == capi.PVJP_EINVAL
+    assert "aligned" in capi.last_error()
+    two = capi.ptr_array([256, None])
+    assert L.pvjp_reduce_generic(capi.GOP_LINREC, capi.F64, two, 10, two, 256, 1 << 20, None) == capi.PVJP_EINVAL
+    assert "component 1" in capi.last_error()
+    assert L.pvjp_reduce_generic_vjp(capi.GOP_LOGADDEXP, capi.F32, one, 10, None, one, 0, 256, 1 << 20,
+                                     None) == capi.PVJP_EINVAL
+    misaligned = capi.ptr_array([258])
+    assert L.pvjp_reduce_generic_vjp(capi.GOP_LOGADDEXP, capi.F32, one, 10, one, misaligned, 0, 256, 1 << 20,
+                                     None) == capi.PVJP_EINVAL
+    assert "misaligned" in capi.last_error()

@@ -1,0 +1,191 @@
+"""GPU parity of reduce with a general associative operator (Sec. 5.1.1,
+general rule) and its VJP, through the C ABI, against the oracle on the same
+seeded inputs.
+
+Bars: FP64 relative L2 1e-12, FP32 2e-5 against the FP64 oracle on the same
+FP32 inputs; zero adjoints of -inf log-add-exp elements exact.  Sizes span
+one tile, tile boundaries, ragged tails and more tiles than the aggregate
+scan's block has threads; at the size the benchmark times (2^26 elements)
+sampled adjoints are checked one by one against the oracle's sampled form.
+"""
+import numpy as np
+import pytest
+
+from _util import TOL_F32, TOL_F64, rel_l2
+from paper_2202_10297_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+OPS = ["logaddexp", "linrec", "mat2"]
+TILE = {"f32": 2048, "f64": 1024}
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def tol(dtype):
+    return TOL_F64 if dtype == "f64" else TOL_F32
+
+
+@pytest.fixture(scope="module")
+def ops():
+    from paper_2202_10297_amd import capi, ops as o
+
+    capi.lib()
+    return o
+
+
+def inputs(op, n, dtype, seed):
+    xs, yb = workloads.gop(op, n, dtype, seed=seed)
+    if op == "logaddexp" and n > 3:
+        t = TILE[dtype]
+        for i in {0, n // 2, min(t, n - 1), n - 1}:
+            xs[0][i] = -np.inf
+    return xs, yb
+
+
+def run(ops, op, xs, yb, accumulate=False, base=None):
+    dx = [dev(x) for x in xs]
+    ys = ops.reduce_generic(op, dx)
+    dyb = [dev(yb[c:c + 1]) for c in range(len(xs))]
+    xb = None
+    if base is not None:
+        xb = [dev(b) for b in base]
+    xb = ops.reduce_generic_vjp(op, dx, dyb, x_bar=xb, accumulate=accumulate)
+    return np.array([host(y)[0] for y in ys]), [host(g) for g in xb]
+
+
+SIZES = {"f32": [1, 2, 2047, 2048, 2049, 3 * 2048 + 5, 300001],
+         "f64": [1, 2, 1023, 1024, 1025, 3 * 1024 + 5, 150001]}
+
+
+@pytest.mark.parametrize("op", OPS)
+@pytest.mark.parametrize("dtype,n", [(d, n) for d in SIZES for n in SIZES[d]])
+def test_primal_and_vjp(ops, orc, op, dtype, n):
+    xs, yb = inputs(op, n, dtype, seed=n)
+    y, xb = run(ops, op, xs, yb)
+    ry = orc.reduce_generic(op, xs)
+    assert rel_l2(y, ry) <= (1e-13 if dtype == "f64" else 1e-6)
+    ref = orc.reduce_generic_vjp(op, xs, yb)
+    assert rel_l2(xb, ref) <= tol(dtype)
+    if op == "logaddexp":
+        ninf = np.isneginf(xs[0])
+        assert np.all(xb[0][ninf] == 0)
+
+
+@pytest.mark.parametrize("op", OPS)
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_accumulate(ops, orc, op, dtype):
+    n = 3 * TILE[dtype] + 77
+    xs, yb = inputs(op, n, dtype, seed=5)
+    base = [np.full(n, 0.5, dtype=xs[0].dtype) for _ in xs]
+    _, xb = run(ops, op, xs, yb, accumulate=True, base=base)
+    ref = orc.reduce_generic_vjp(op, xs, yb)
+    assert rel_l2([g - 0.5 for g in xb], ref) <= tol(dtype) * 2
+
+
+@pytest.mark.parametrize("op", OPS)
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_unaligned_views(ops, orc, op, dtype):
+    # component arrays that start 1 element past a 16-byte boundary take the
+    # scalar-load path
+    n = 2 * TILE[dtype] + 333
+    xs, yb = inputs(op, n + 1, dtype, seed=9)
+    dx = [dev(x)[1:] for x in xs]
+    ys = ops.reduce_generic(op, dx)
+    dyb = [dev(yb[c:c + 1]) for c in range(len(xs))]
+    out = [torch.empty(n + 1, dtype=dx[0].dtype, device="cuda")[1:] for _ in xs]
+    ops.reduce_generic_vjp(op, dx, dyb, x_bar=out)
+    sub = [x[1:] for x in xs]
+    assert rel_l2([host(y)[0] for y in ys], orc.reduce_generic(op, sub)) <= (1e-13 if dtype == "f64" else 1e-6)
+    assert rel_l2([host(o) for o in out], orc.reduce_generic_vjp(op, sub, yb)) <= tol(dtype)
+
+
+def test_empty_input(ops):
+    from paper_2202_10297_amd import capi
+
+    for op, neutral in (("logaddexp", [-np.inf]), ("linrec", [1.0, 0.0]), ("mat2", [1.0, 0.0, 0.0, 1.0])):
+        K = len(neutral)
+        xs = [torch.empty(0, dtype=torch.float64, device="cuda") for _ in range(K)]
+        ys = ops.reduce_generic(op, xs)
+        assert [host(y)[0] for y in ys] == neutral
+        # the VJP of an empty input touches nothing
+        xb = [torch.full((4,), 7.0, dtype=torch.float64, device="cuda") for _ in range(K)]
+        yb = [torch.ones(1, dtype=torch.float64, device="cuda") for _ in range(K)]
+        ws = torch.zeros(4096, dtype=torch.uint8, device="cuda")
+        capi.call("pvjp_reduce_generic_vjp", ops._gop(op), capi.F64, capi.ptr_array([x.data_ptr() for x in xs]), 0,
+                  capi.ptr_array([y.data_ptr() for y in yb]), capi.ptr_array([x.data_ptr() for x in xb]), 0,
+                  ws.data_ptr(), ws.numel(), torch.cuda.current_stream().cuda_stream)
+        assert all(np.all(host(x) == 7.0) for x in xb)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_mat2_dense_factors(ops, orc, dtype):
+    # dense N(0, 1/2) factors (products shrink geometrically: short inputs)
+    n = 1000 if dtype == "f64" else 150
+    xs, yb = workloads.gop("mat2", n, dtype, seed=13, general=True)
+    y, xb = run(ops, "mat2", xs, yb)
+    assert rel_l2(y, orc.reduce_generic("mat2", xs)) <= (1e-12 if dtype == "f64" else 1e-5)
+    assert rel_l2(xb, orc.reduce_generic_vjp("mat2", xs, yb)) <= tol(dtype)
+
+
+def sample_indices(n, tile, seed):
+    g = np.random.Generator(np.random.PCG64(seed))
+    fixed = [0, 1, tile - 1, tile, tile + 1, n // 2, n - 2, n - 1]
+    return np.unique(np.concatenate([fixed, g.integers(0, n, 40)]))
+
+
+def check_sampled(orc, op, xs, yb, xb, idx, dtype):
+    ref = orc.reduce_generic_vjp_at(op, xs, yb, idx)
+    got = np.stack([g[idx] for g in xb], axis=1).astype(np.float64)
+    # per element: relative to the sample's own scale (f64) or with the FP32
+    # rounding depth of the folds (f32)
+    scale = np.maximum(np.abs(ref), 1e-300)
+    bound = 1e-11 if dtype == "f64" else 2e-4
+    bad = np.abs(got - ref) > bound * scale + bound * np.abs(ref).max()
+    assert not bad.any(), (idx[np.any(bad, axis=1)][:5], got[bad][:5], ref[bad][:5])
+
+
+@pytest.mark.parametrize("op,dtype,n", [("logaddexp", "f32", 2048 * 1100 + 3), ("linrec", "f64", 1024 * 1500 + 7),
+                                        ("mat2", "f32", 2048 * 1030 + 1), ("mat2", "f64", 1024 * 1200 + 9)])
+def test_more_tiles_than_scan_threads(ops, orc, op, dtype, n):
+    xs, yb = inputs(op, n, dtype, seed=17)
+    y, xb = run(ops, op, xs, yb)
+    assert rel_l2(y, orc.reduce_generic(op, xs)) <= (1e-12 if dtype == "f64" else 1e-5)
+    check_sampled(orc, op, xs, yb, xb, sample_indices(n, TILE[dtype], 3), dtype)
+
+
+@pytest.mark.parametrize("op,dtype", [("logaddexp", "f32"), ("linrec", "f64"), ("mat2", "f32")])
+def test_benchmark_size_sampled(ops, orc, op, dtype):
+    n = 1 << 26
+    xs, yb = workloads.gop(op, n, dtype, seed=0)
+    y, xb = run(ops, op, xs, yb)
+    assert rel_l2(y, orc.reduce_generic(op, xs)) <= (1e-12 if dtype == "f64" else 1e-5)
+    check_sampled(orc, op, xs, yb, xb, sample_indices(n, TILE[dtype], 4), dtype)
+
+
+def test_deterministic(ops):
+    xs, yb = workloads.gop("logaddexp", 500001, "f32", seed=2)
+    a = run(ops, "logaddexp", xs, yb)
+    b = run(ops, "logaddexp", xs, yb)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1][0], b[1][0])
+
+
+def test_autograd(orc):
+    from paper_2202_10297_amd import autograd
+
+    n = 5000
+    xs, yb = workloads.gop("linrec", n, "f64", seed=8)
+    a, b = (dev(x).requires_grad_() for x in xs)
+    yA, yB = autograd.reduce_generic("linrec", a, b)
+    (float(yb[0]) * yA + float(yb[1]) * yB).backward()
+    ref = orc.reduce_generic_vjp("linrec", xs, yb)
+    assert rel_l2([host(a.grad), host(b.grad)], ref) <= TOL_F64
