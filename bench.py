@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 23, help="elements per instance for the CPU oracle")
     ap.add_argument("--skip", default="", help="comma list of extra workloads to skip: reduce_map,reduce_generic,scan,gmm,batch,serve")
+    ap.add_argument("--only", default="",
+                    help="run just this one extra workload (for profiling) and print its JSON instead of the "
+                         "benchmark line")
     ap.add_argument("--serve-seconds", type=float, default=4.0, help="measured seconds of the serving trace")
     ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn the counter_collection.csv files of a FETCH_SIZE and a WRITE_SIZE run into "
@@ -215,6 +218,11 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     L = capi.lib()
+    if args.only:
+        fns = {"reduce_map": bench_reduce_map, "reduce_generic": bench_reduce_generic, "scan": bench_scan,
+               "gmm": bench_gmm, "batch": bench_batch, "serve": bench_serve}
+        print(json.dumps({args.only: fns[args.only](args)}))
+        return
 
     if args.copy_calibration:
         src = torch.ones(COPY_N, dtype=torch.float32, device=dev)

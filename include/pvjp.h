@@ -249,7 +249,7 @@ pvjp_status pvjp_fig1_vjp(pvjp_dtype dtype, const void* x0, const void* x1, cons
 int pvjp_gop_components(pvjp_gop op);
 /* Workspace bytes for both entry points (device memory owned by the caller,
  * 256-byte aligned, no initialisation needed): 96 bytes per tile of 2048
- * (FP32) or 1024 (FP64) elements, rounded up. */
+ * (FP32) or 1024 (FP64) elements and per group of 64 tiles. */
 size_t pvjp_reduce_generic_ws_bytes(pvjp_gop op, pvjp_dtype dtype, int64_t n);
 /* x: host array of K device pointers to n elements each (unused if n == 0).
  * y: host array of K device pointers to one element of dtype each; receives

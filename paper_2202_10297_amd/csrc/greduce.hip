@@ -5,17 +5,20 @@
 // ls_i and rs_i held constant: the function f mapped over (ls, xs, rs).
 //
 // The rule as stated costs two whole-array scans plus a map (at least five
-// global accesses per element).  Here the scans are split over fixed tiles:
-//   1. tile aggregates (read x);
-//   2. one block scans the aggregates forward and backward, giving every
-//      tile the fold of all tiles before it and of all tiles after it (and
-//      the primal result y);
+// global accesses per element).  Here the scans are split over fixed tiles
+// in three levels (tiles, groups of 64 tiles, all groups):
+//   1. one block per tile folds it (read x); one wave per group folds the
+//      group's tile folds;
+//   2. one block scans the group folds forward and backward (and gives the
+//      primal result y); one wave per group then gives each tile the fold of
+//      everything before it and of everything after it;
 //   3. per tile, the in-tile exclusive prefixes and suffixes are formed in
 //      registers and LDS and f is applied at once (read x, write x_bar).
 // x is read twice and x_bar written once; ls and rs never reach memory.
 //
 // Operators (an element has K components, each its own array):
-//   log-add-exp   a (.) b = log(e^a + e^b), neutral -inf (K = 1);
+//   log-add-exp   a (.) b = log(e^a + e^b), neutral -inf (K = 1), carried
+//                 as (max, scaled sum) pairs;
 //   linear recurrence (a1,b1) (.) (a2,b2) = (a2 a1, a2 b1 + b2) (K = 2);
 //   2x2 matrix product, row-major components (K = 4).
 #include <type_traits>
@@ -57,29 +60,42 @@ struct GShfl {
     }
 };
 
-// comb(x, y) = x (.) y with x earlier in index order.  vjp(l, a, r, yb, out)
-// is the function f: out = (d(l (.) a (.) r)/da)^T yb.
+// An operator provides: K input components; a state S (its shuffles come
+// from GShfl) with elem() turning an element's components into a state and
+// value() turning a state back into K result components; the neutral id();
+// comb(x, y) = x (.) y with x earlier in index order; and the function f,
+// vjp(l, a, r, la, yb, out): out = (d(l (.) a (.) r)/da)^T yb, where la is
+// l (.) a (already formed by the caller for the next prefix).
+
+// log-add-exp.  The state is (m, s) standing for m + log(s), the neutral
+// element (-inf, 0): combining costs one exp and no log, and exp(a - y)
+// becomes exp(a - m_y) / s_y.  Each element is (x, 1), or the neutral
+// element when x = -inf.
 template <class T>
-struct GLogAddExp : GShfl<T, 1> {
+struct GLogAddExp : GShfl<T, 2> {
     static constexpr int K = 1;
     using Acc = T;
-    using S = GS<T, 1>;
-    __device__ static __forceinline__ S id() { return S{{-(T)INFINITY}}; }
-    __device__ static __forceinline__ S comb(S x, S y) {
-        const T a = x.c[0], b = y.c[0];
-        if (b == -(T)INFINITY) return x;
-        if (a == -(T)INFINITY) return y;
-        const T m = a > b ? a : b;
-        return S{{m + log1p(exp(-fabs(a - b)))}};
+    using S = GS<T, 2>;
+    __device__ static __forceinline__ S id() { return S{{-(T)INFINITY, T(0)}}; }
+    __device__ static __forceinline__ S elem(const T (&c)[1]) {
+        return S{{c[0], c[0] == -(T)INFINITY ? T(0) : T(1)}};
     }
-    __device__ static __forceinline__ void vjp(S l, S a, S r, const T (&yb)[1], T (&out)[1]) {
+    __device__ static __forceinline__ void value(S v, T (&out)[1]) { out[0] = v.c[0] + log(v.c[1]); }
+    __device__ static __forceinline__ S comb(S x, S y) {
+        if (y.c[1] == T(0)) return x;
+        if (x.c[1] == T(0)) return y;
+        const T d = x.c[0] - y.c[0];
+        const T e = exp(-fabs(d));
+        return d >= T(0) ? S{{x.c[0], x.c[1] + y.c[1] * e}} : S{{y.c[0], x.c[1] * e + y.c[1]}};
+    }
+    __device__ static __forceinline__ void vjp(S, S a, S r, S la, const T (&yb)[1], T (&out)[1]) {
         // d/da log(e^l + e^a + e^r) = e^(a - y); a -inf element receives 0
-        if (a.c[0] == -(T)INFINITY) {
+        if (a.c[1] == T(0)) {
             out[0] = T(0);
             return;
         }
-        const S y = comb(comb(l, a), r);
-        out[0] = yb[0] * exp(a.c[0] - y.c[0]);
+        const S y = comb(la, r);
+        out[0] = yb[0] * exp(a.c[0] - y.c[0]) / y.c[1];
     }
 };
 
@@ -89,8 +105,10 @@ struct GLinRec : GShfl<T, 2> {
     using Acc = T;
     using S = GS<T, 2>;
     __device__ static __forceinline__ S id() { return S{{T(1), T(0)}}; }
+    __device__ static __forceinline__ S elem(const T (&c)[2]) { return S{{c[0], c[1]}}; }
+    __device__ static __forceinline__ void value(S v, T (&out)[2]) { out[0] = v.c[0], out[1] = v.c[1]; }
     __device__ static __forceinline__ S comb(S x, S y) { return S{{y.c[0] * x.c[0], y.c[0] * x.c[1] + y.c[1]}}; }
-    __device__ static __forceinline__ void vjp(S l, S, S r, const T (&yb)[2], T (&out)[2]) {
+    __device__ static __forceinline__ void vjp(S l, S, S r, S, const T (&yb)[2], T (&out)[2]) {
         // y = (r.a x.a l.a, r.a (x.a l.b + x.b) + r.b)
         out[0] = r.c[0] * (yb[0] * l.c[0] + yb[1] * l.c[1]);
         out[1] = r.c[0] * yb[1];
@@ -103,11 +121,15 @@ struct GMat2 : GShfl<T, 4> {
     using Acc = T;
     using S = GS<T, 4>;
     __device__ static __forceinline__ S id() { return S{{T(1), T(0), T(0), T(1)}}; }
+    __device__ static __forceinline__ S elem(const T (&c)[4]) { return S{{c[0], c[1], c[2], c[3]}}; }
+    __device__ static __forceinline__ void value(S v, T (&out)[4]) {
+        for (int c = 0; c < 4; ++c) out[c] = v.c[c];
+    }
     __device__ static __forceinline__ S comb(S x, S y) {
         return S{{x.c[0] * y.c[0] + x.c[1] * y.c[2], x.c[0] * y.c[1] + x.c[1] * y.c[3],
                   x.c[2] * y.c[0] + x.c[3] * y.c[2], x.c[2] * y.c[1] + x.c[3] * y.c[3]}};
     }
-    __device__ static __forceinline__ void vjp(S l, S, S r, const T (&yb)[4], T (&out)[4]) {
+    __device__ static __forceinline__ void vjp(S l, S, S r, S, const T (&yb)[4], T (&out)[4]) {
         // y = l a r, so a_bar = l^T y_bar r^T; M = y_bar r^T first
         const T m00 = yb[0] * r.c[0] + yb[1] * r.c[1], m01 = yb[0] * r.c[2] + yb[1] * r.c[3];
         const T m10 = yb[2] * r.c[0] + yb[3] * r.c[1], m11 = yb[2] * r.c[2] + yb[3] * r.c[3];
@@ -180,10 +202,31 @@ __device__ __forceinline__ void gr_store(T* __restrict__ p, int cnt, const T (&v
 // operator's arithmetic type).
 template <class Op, class T, int IPT>
 __device__ __forceinline__ typename Op::S gr_elem(const T (&v)[Op::K][IPT], int k) {
-    typename Op::S s;
+    typename Op::Acc c[Op::K];
 #pragma unroll
-    for (int c = 0; c < Op::K; ++c) s.c[c] = (typename Op::Acc)v[c][k];
-    return s;
+    for (int j = 0; j < Op::K; ++j) c[j] = (typename Op::Acc)v[j][k];
+    return Op::elem(c);
+}
+
+// Exclusive scan over the lanes of a wave in scan order (REV: lane 63
+// first); lanes hold one state each.
+template <class Op, bool REV>
+__device__ __forceinline__ typename Op::S wave_exclusive_scan(typename Op::S v) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const typename Op::S o = REV ? Op::down(v, d) : Op::up(v, d);
+        if (REV ? (lane + d < kWave) : (lane >= d)) v = Op::comb(o, v);
+    }
+    typename Op::S ex = REV ? Op::down(v, 1) : Op::up(v, 1);
+    if (REV ? (lane == kWave - 1) : (lane == 0)) ex = Op::id();
+    return ex;
+}
+
+template <class T>
+__device__ __forceinline__ int gr_cnt(int64_t n, int64_t base) {
+    const int64_t left = n - base;
+    return left <= 0 ? 0 : (left >= gr_ipt<T>() ? gr_ipt<T>() : (int)left);
 }
 
 // Pass 1: agg[t] = fold of tile t in index order.
@@ -194,8 +237,7 @@ __global__ __launch_bounds__(kGrBlock) void gred_tile_agg_kernel(GPtrs<T> x, int
     constexpr int IPT = gr_ipt<T>();
     __shared__ S wtot[kGrBlock / kWave];
     const int64_t base = (int64_t)blockIdx.x * gr_tile<T>() + (int64_t)threadIdx.x * IPT;
-    const int64_t left = n - base;
-    const int cnt = left <= 0 ? 0 : (left >= IPT ? IPT : (int)left);
+    const int cnt = gr_cnt<T>(n, base);
     T v[Op::K][IPT];
 #pragma unroll
     for (int c = 0; c < Op::K; ++c) gr_load<T, IPT, VEC>(x.p[c] + base, cnt, v[c]);
@@ -208,35 +250,47 @@ __global__ __launch_bounds__(kGrBlock) void gred_tile_agg_kernel(GPtrs<T> x, int
     if (threadIdx.x == 0) agg[blockIdx.x] = total;
 }
 
-// Pass 2 (one block): pre[t] = fold of tiles before t, suf[t] = fold of
-// tiles after t (either may be NULL); y (nullable components) = fold of all.
-// Thread j owns a contiguous run of tiles; runs are scanned across the block
-// in both directions.
+// Tiles are taken in groups of kGrGroup; one wave handles a group, lane j
+// its tile j.
+constexpr int kGrGroup = kWave;
+
+// Pass 1b: gagg[g] = fold of the tile folds of group g.
+template <class Op>
+__global__ __launch_bounds__(kGrBlock) void gred_group_fold_kernel(const typename Op::S* __restrict__ agg, int64_t nt,
+                                                                   int64_t ng, typename Op::S* __restrict__ gagg) {
+    using S = typename Op::S;
+    const int64_t g = (int64_t)blockIdx.x * (kGrBlock / kWave) + threadIdx.x / kWave;
+    if (g >= ng) return;  // whole waves leave together
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t t = g * kGrGroup + lane;
+    const S own = t < nt ? agg[t] : Op::id();
+    const S inc = Op::comb(wave_exclusive_scan<Op, false>(own), own);
+    if (lane == kWave - 1) gagg[g] = inc;
+}
+
+// Pass 2 (one block): pre[g] = fold of the group folds before g, suf[g] =
+// fold of those after g (either may be NULL); y (nullable components) =
+// fold of all.  Thread j owns a contiguous run of the folds; runs are scanned
+// across the block in both directions.
 template <class Op, class T>
 __global__ __launch_bounds__(kGrAggBlock) void gred_agg_scan_kernel(const typename Op::S* __restrict__ agg,
-                                                                    int64_t nt, typename Op::S* __restrict__ pre,
+                                                                    int64_t nb, typename Op::S* __restrict__ pre,
                                                                     typename Op::S* __restrict__ suf, GOut<T> y) {
     using S = typename Op::S;
-    constexpr int U = 8;
     __shared__ S wtot[kGrAggBlock / kWave];
-    const int64_t per = (nt + kGrAggBlock - 1) / kGrAggBlock;
-    const int64_t v0 = (int64_t)threadIdx.x * per < nt ? (int64_t)threadIdx.x * per : nt;
-    const int64_t v1 = v0 + per < nt ? v0 + per : nt;
+    const int64_t per = (nb + kGrAggBlock - 1) / kGrAggBlock;
+    const int64_t v0 = (int64_t)threadIdx.x * per < nb ? (int64_t)threadIdx.x * per : nb;
+    const int64_t v1 = v0 + per < nb ? v0 + per : nb;
     S run = Op::id();
-    for (int64_t v = v0; v < v1; v += U) {
-        S a[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) a[u] = (v + u < v1) ? agg[v + u] : Op::id();
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (v + u < v1) run = Op::comb(run, a[u]);
-    }
+    for (int64_t v = v0; v < v1; ++v) run = Op::comb(run, agg[v]);
     S total;
     S ex = block_exclusive_scan<Op, kGrAggBlock, false>(run, total, wtot);
     if (threadIdx.x == 0) {
+        typename Op::Acc yv[Op::K];
+        Op::value(total, yv);
 #pragma unroll
         for (int c = 0; c < Op::K; ++c)
-            if (y.p[c]) *y.p[c] = (T)total.c[c];
+            if (y.p[c]) *y.p[c] = (T)yv[c];
     }
     if (pre) {
         for (int64_t v = v0; v < v1; ++v) {
@@ -254,24 +308,47 @@ __global__ __launch_bounds__(kGrAggBlock) void gred_agg_scan_kernel(const typena
     }
 }
 
-// Pass 3: per tile, ls_i and rs_i from the tile's prefix/suffix, the block
-// scans of the threads' runs and the in-thread folds; x_bar_i (+)= f.
+// Pass 2b: per tile t of group g, pre[t] = gpre[g] (.) the tiles of the
+// group before t, suf[t] = the tiles of the group after t (.) gsuf[g].
+template <class Op>
+__global__ __launch_bounds__(kGrBlock) void gred_tile_prefix_kernel(const typename Op::S* __restrict__ agg,
+                                                                    int64_t nt, int64_t ng,
+                                                                    const typename Op::S* __restrict__ gpre,
+                                                                    const typename Op::S* __restrict__ gsuf,
+                                                                    typename Op::S* __restrict__ pre,
+                                                                    typename Op::S* __restrict__ suf) {
+    using S = typename Op::S;
+    const int64_t g = (int64_t)blockIdx.x * (kGrBlock / kWave) + threadIdx.x / kWave;
+    if (g >= ng) return;  // whole waves leave together
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t t = g * kGrGroup + lane;
+    const S own = t < nt ? agg[t] : Op::id();
+    const S exf = wave_exclusive_scan<Op, false>(own);
+    const S exb = wave_exclusive_scan<Flip<Op>, true>(own);
+    if (t < nt) {
+        pre[t] = Op::comb(gpre[g], exf);
+        suf[t] = Op::comb(exb, gsuf[g]);
+    }
+}
+
+// Pass 3: per tile, ls_i and rs_i from the tile's prefix and suffix, the
+// block scans of the threads' runs and the in-thread folds; then
+// x_bar_i (+)= f(ls_i, x_i, rs_i).
 template <class Op, class T, bool VEC, bool ACC>
 __global__ __launch_bounds__(kGrBlock) void gred_vjp_kernel(GPtrs<T> x, int64_t n,
                                                             const typename Op::S* __restrict__ pre,
                                                             const typename Op::S* __restrict__ suf, GPtrs<T> ybar,
                                                             GOut<T> xbar) {
     using S = typename Op::S;
+    using A = typename Op::Acc;
     constexpr int K = Op::K;
     constexpr int IPT = gr_ipt<T>();
     __shared__ S wtot[kGrBlock / kWave];
     const int64_t base = (int64_t)blockIdx.x * gr_tile<T>() + (int64_t)threadIdx.x * IPT;
-    const int64_t left = n - base;
-    const int cnt = left <= 0 ? 0 : (left >= IPT ? IPT : (int)left);
+    const int cnt = gr_cnt<T>(n, base);
     T v[K][IPT];
 #pragma unroll
     for (int c = 0; c < K; ++c) gr_load<T, IPT, VEC>(x.p[c] + base, cnt, v[c]);
-    using A = typename Op::Acc;
     A yb[K];
 #pragma unroll
     for (int c = 0; c < K; ++c) yb[c] = (A)*ybar.p[c];
@@ -297,11 +374,12 @@ __global__ __launch_bounds__(kGrBlock) void gred_vjp_kernel(GPtrs<T> x, int64_t 
 #pragma unroll
     for (int k = 0; k < IPT; ++k) {
         const S a = gr_elem<Op, T, IPT>(v, k);
+        const S la = Op::comb(l, a);
         A o[K];
-        Op::vjp(l, a, rs[k], yb, o);
+        Op::vjp(l, a, rs[k], la, yb, o);
 #pragma unroll
         for (int c = 0; c < K; ++c) out[c][k] = (T)o[c];
-        l = Op::comb(l, a);
+        l = la;
     }
 #pragma unroll
     for (int c = 0; c < K; ++c) {
@@ -325,33 +403,61 @@ static int gop_components(pvjp_gop op) {
     }
 }
 
+// Workspace: [tile folds | tile prefixes | tile suffixes] (nt each), then
+// [group folds | group prefixes | group suffixes] (ng each), one 32-byte
+// slot per state, every array 256-byte aligned.
+struct GrPlan {
+    int64_t nt, ng;
+    size_t tiles, groups;  // bytes of one per-tile / per-group array
+};
+
+template <class T>
+static GrPlan gr_plan(int64_t n) {
+    GrPlan p;
+    p.nt = ceil_div(n, gr_tile<T>());
+    p.ng = ceil_div(p.nt, kGrGroup);
+    p.tiles = align_up((size_t)(p.nt > 0 ? p.nt : 1) * kGrSlot, 256);
+    p.groups = align_up((size_t)(p.ng > 0 ? p.ng : 1) * kGrSlot, 256);
+    return p;
+}
+
 template <class T>
 static size_t gr_ws(int64_t n) {
-    const int64_t nt = ceil_div(n, gr_tile<T>());
-    return 3 * align_up((size_t)(nt > 0 ? nt : 1) * kGrSlot, 256);
+    const GrPlan p = gr_plan<T>(n);
+    return 3 * p.tiles + 3 * p.groups;
 }
 
 template <class S>
-static S* gr_slot(void* ws, int64_t n_tiles, int which) {
-    return reinterpret_cast<S*>(reinterpret_cast<char*>(ws) +
-                                (size_t)which * align_up((size_t)(n_tiles > 0 ? n_tiles : 1) * kGrSlot, 256));
+static S* gr_array(void* ws, const GrPlan& p, int which) {
+    const size_t off = which < 3 ? which * p.tiles : 3 * p.tiles + (which - 3) * p.groups;
+    return reinterpret_cast<S*>(reinterpret_cast<char*>(ws) + off);
+}
+
+// tile folds (pass 1) and group folds (pass 1b)
+template <class Op, class T>
+static void launch_folds(const GPtrs<T>& x, int64_t n, const GrPlan& p, typename Op::S* agg,
+                         typename Op::S* gagg, bool vec, hipStream_t st) {
+    using S = typename Op::S;
+    if (p.nt == 0) return;
+    if (vec)
+        hipLaunchKernelGGL((gred_tile_agg_kernel<Op, T, true>), dim3((unsigned)p.nt), dim3(kGrBlock), 0, st, x, n,
+                           agg);
+    else
+        hipLaunchKernelGGL((gred_tile_agg_kernel<Op, T, false>), dim3((unsigned)p.nt), dim3(kGrBlock), 0, st, x, n,
+                           agg);
+    const unsigned gblocks = (unsigned)ceil_div(p.ng, kGrBlock / kWave);
+    hipLaunchKernelGGL((gred_group_fold_kernel<Op>), dim3(gblocks), dim3(kGrBlock), 0, st, (const S*)agg, p.nt, p.ng,
+                       gagg);
 }
 
 template <class Op, class T>
 static void launch_primal(const GPtrs<T>& x, int64_t n, const GOut<T>& y, void* ws, bool vec, hipStream_t st) {
     using S = typename Op::S;
     static_assert(sizeof(S) <= kGrSlot, "slot too small");
-    const int64_t nt = ceil_div(n, gr_tile<T>());
-    S* agg = gr_slot<S>(ws, nt, 0);
-    if (nt > 0) {
-        if (vec)
-            hipLaunchKernelGGL((gred_tile_agg_kernel<Op, T, true>), dim3((unsigned)nt), dim3(kGrBlock), 0, st, x, n,
-                               agg);
-        else
-            hipLaunchKernelGGL((gred_tile_agg_kernel<Op, T, false>), dim3((unsigned)nt), dim3(kGrBlock), 0, st, x, n,
-                               agg);
-    }
-    hipLaunchKernelGGL((gred_agg_scan_kernel<Op, T>), dim3(1), dim3(kGrAggBlock), 0, st, (const S*)agg, nt,
+    const GrPlan p = gr_plan<T>(n);
+    S* gagg = gr_array<S>(ws, p, 3);
+    launch_folds<Op, T>(x, n, p, gr_array<S>(ws, p, 0), gagg, vec, st);
+    hipLaunchKernelGGL((gred_agg_scan_kernel<Op, T>), dim3(1), dim3(kGrAggBlock), 0, st, (const S*)gagg, p.ng,
                        (S*)nullptr, (S*)nullptr, y);
 }
 
@@ -359,29 +465,33 @@ template <class Op, class T>
 static void launch_vjp(const GPtrs<T>& x, int64_t n, const GPtrs<T>& yb, const GOut<T>& xb, int acc, void* ws,
                        bool vec, hipStream_t st) {
     using S = typename Op::S;
-    const int64_t nt = ceil_div(n, gr_tile<T>());
-    S* agg = gr_slot<S>(ws, nt, 0);
-    S* pre = gr_slot<S>(ws, nt, 1);
-    S* suf = gr_slot<S>(ws, nt, 2);
+    const GrPlan p = gr_plan<T>(n);
+    S* agg = gr_array<S>(ws, p, 0);
+    S* pre = gr_array<S>(ws, p, 1);
+    S* suf = gr_array<S>(ws, p, 2);
+    S* gagg = gr_array<S>(ws, p, 3);
+    S* gpre = gr_array<S>(ws, p, 4);
+    S* gsuf = gr_array<S>(ws, p, 5);
     const GOut<T> none{{nullptr, nullptr, nullptr, nullptr}};
-    const dim3 g((unsigned)nt), b(kGrBlock);
-    if (vec) {
-        hipLaunchKernelGGL((gred_tile_agg_kernel<Op, T, true>), g, b, 0, st, x, n, agg);
-    } else {
-        hipLaunchKernelGGL((gred_tile_agg_kernel<Op, T, false>), g, b, 0, st, x, n, agg);
-    }
-    hipLaunchKernelGGL((gred_agg_scan_kernel<Op, T>), dim3(1), dim3(kGrAggBlock), 0, st, (const S*)agg, nt, pre,
-                       suf, none);
+    launch_folds<Op, T>(x, n, p, agg, gagg, vec, st);
+    hipLaunchKernelGGL((gred_agg_scan_kernel<Op, T>), dim3(1), dim3(kGrAggBlock), 0, st, (const S*)gagg, p.ng, gpre,
+                       gsuf, none);
+    const unsigned gblocks = (unsigned)ceil_div(p.ng, kGrBlock / kWave);
+    hipLaunchKernelGGL((gred_tile_prefix_kernel<Op>), dim3(gblocks), dim3(kGrBlock), 0, st, (const S*)agg, p.nt, p.ng,
+                       (const S*)gpre, (const S*)gsuf, pre, suf);
+    const dim3 gt((unsigned)p.nt), b(kGrBlock);
+    const S* cp = pre;
+    const S* cs = suf;
     if (vec) {
         if (acc)
-            hipLaunchKernelGGL((gred_vjp_kernel<Op, T, true, true>), g, b, 0, st, x, n, pre, suf, yb, xb);
+            hipLaunchKernelGGL((gred_vjp_kernel<Op, T, true, true>), gt, b, 0, st, x, n, cp, cs, yb, xb);
         else
-            hipLaunchKernelGGL((gred_vjp_kernel<Op, T, true, false>), g, b, 0, st, x, n, pre, suf, yb, xb);
+            hipLaunchKernelGGL((gred_vjp_kernel<Op, T, true, false>), gt, b, 0, st, x, n, cp, cs, yb, xb);
     } else {
         if (acc)
-            hipLaunchKernelGGL((gred_vjp_kernel<Op, T, false, true>), g, b, 0, st, x, n, pre, suf, yb, xb);
+            hipLaunchKernelGGL((gred_vjp_kernel<Op, T, false, true>), gt, b, 0, st, x, n, cp, cs, yb, xb);
         else
-            hipLaunchKernelGGL((gred_vjp_kernel<Op, T, false, false>), g, b, 0, st, x, n, pre, suf, yb, xb);
+            hipLaunchKernelGGL((gred_vjp_kernel<Op, T, false, false>), gt, b, 0, st, x, n, cp, cs, yb, xb);
     }
 }
 

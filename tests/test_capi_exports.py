@@ -84,9 +84,12 @@ def test_workspace_queries(capi):
 def test_generic_reduce_validation(capi):
     L = capi.lib()
     assert [L.pvjp_gop_components(k) for k in range(4)] == [1, 2, 4, 0]
-    # 96 bytes per tile (three 32-byte slots), each array rounded to 256 bytes
-    assert L.pvjp_reduce_generic_ws_bytes(capi.GOP_LOGADDEXP, capi.F32, 2048 * 100) == 3 * 3328
-    assert L.pvjp_reduce_generic_ws_bytes(capi.GOP_MAT2, capi.F64, 1024 * 8 + 1) == 3 * 512
+    # three 32-byte slots per tile and per group of 64 tiles, each array
+    # rounded to 256 bytes
+    assert L.pvjp_reduce_generic_ws_bytes(capi.GOP_LOGADDEXP, capi.F32, 2048 * 100) == 3 * 3328 + 3 * 256
+    assert L.pvjp_reduce_generic_ws_bytes(capi.GOP_MAT2, capi.F64, 1024 * 8 + 1) == 3 * 512 + 3 * 256
+    # 2^26 FP32: 32768 tiles in 512 groups
+    assert L.pvjp_reduce_generic_ws_bytes(capi.GOP_LINREC, capi.F32, 1 << 26) == 3 * 32768 * 32 + 3 * 512 * 32
     assert L.pvjp_reduce_generic_ws_bytes(7, capi.F32, 10) == 0
     one = capi.ptr_array([256])
     assert L.pvjp_reduce_generic(7, capi.F32, one, 10, one, 256, 1 << 20, None) == capi.PVJP_EINVAL
