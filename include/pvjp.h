@@ -251,24 +251,31 @@ int pvjp_gop_components(pvjp_gop op);
  * 256-byte aligned, no initialisation needed): 96 bytes per tile of 2048
  * (FP32) or 1024 (FP64) elements and per group of 64 tiles. */
 size_t pvjp_reduce_generic_ws_bytes(pvjp_gop op, pvjp_dtype dtype, int64_t n);
+/* Bytes of the optional per-tile checkpoint: 32 per tile (the tile folds). */
+size_t pvjp_reduce_generic_ckpt_bytes(pvjp_gop op, pvjp_dtype dtype, int64_t n);
 /* x: host array of K device pointers to n elements each (unused if n == 0).
  * y: host array of K device pointers to one element of dtype each; receives
- * the fold (the neutral element if n == 0).  Deterministic: fixed tiles and
+ * the fold (the neutral element if n == 0).  ckpt (device, nullable, 16-byte
+ * aligned, pvjp_reduce_generic_ckpt_bytes): receives the fold of every tile,
+ * which lets the VJP skip its first pass over x.  Deterministic: fixed tiles and
  * a fixed combination tree.  LOGADDEXP inputs must be finite or -inf.  With
  * FP32 data the LINREC and MAT2 folds are formed in FP64 (LOGADDEXP in FP32). */
 pvjp_status pvjp_reduce_generic(pvjp_gop op, pvjp_dtype dtype, const void* const* x, int64_t n,
-                                void* const* y, void* ws, size_t ws_bytes, void* stream);
-/* y_bar: host array of K device pointers to one element each; x_bar: host
+                                void* const* y, void* ckpt, void* ws, size_t ws_bytes, void* stream);
+/* ckpt: NULL (the tile folds are recomputed from x) or the checkpoint that
+ * pvjp_reduce_generic wrote for this x, op, dtype and n (then x is read once).
+ * y_bar: host array of K device pointers to one element each; x_bar: host
  * array of K device pointers to n elements each, overwritten (accumulate = 0)
  * or added to.  LOGADDEXP: x_bar_i = y_bar * exp(x_i - (ls_i (.) x_i (.)
  * rs_i)), and 0 where x_i = -inf.  LINREC, with ls_i = (Al, Bl) and
  * rs_i = (Ar, Br): a_bar_i = Ar*(y_bar_A*Al + y_bar_B*Bl), b_bar_i =
- * Ar*y_bar_B.  MAT2: A_bar_i = ls_i^T Y_bar rs_i^T.  Three
- * kernels: tile folds, one block scanning them both ways, then per tile the
- * in-tile folds and f (x read twice, x_bar written once). */
+ * Ar*y_bar_B.  MAT2: A_bar_i = ls_i^T Y_bar rs_i^T.  Passes: tile folds
+ * (skipped with a checkpoint), group folds, one block scanning the groups
+ * both ways, per-tile prefixes and suffixes, then per tile the in-tile folds
+ * and f (x read once with a checkpoint, twice without; x_bar written once). */
 pvjp_status pvjp_reduce_generic_vjp(pvjp_gop op, pvjp_dtype dtype, const void* const* x, int64_t n,
-                                    const void* const* y_bar, void* const* x_bar, int accumulate,
-                                    void* ws, size_t ws_bytes, void* stream);
+                                    const void* ckpt, const void* const* y_bar, void* const* x_bar,
+                                    int accumulate, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Segmented batches: many instances of uneven length stored back to back     */

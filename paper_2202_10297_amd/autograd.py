@@ -54,23 +54,24 @@ class Reduce(torch.autograd.Function):
 
 class ReduceGeneric(torch.autograd.Function):
     """y = x_0 (.) ... (.) x_{n-1} for a general operator (Sec. 5.1.1); the
-    inputs are the K component tensors, the outputs K scalars.  Nothing but
-    the inputs is saved: the backward recomputes the prefix and suffix folds."""
+    inputs are the K component tensors, the outputs K scalars.  Saved: the
+    inputs and the per-tile checkpoint (32 bytes per tile of 1024-2048
+    elements); the backward recomputes the prefix and suffix folds from it."""
 
     @staticmethod
     def forward(ctx, op, *xs):
         xs = [x.contiguous() for x in xs]
-        ys = ops.reduce_generic(op, xs)
+        ys, ck = ops.reduce_generic(op, xs, ckpt=True)
         ctx.op = op
-        ctx.save_for_backward(*xs)
+        ctx.save_for_backward(ck, *xs)
         return tuple(y.reshape(()) for y in ys)
 
     @staticmethod
     def backward(ctx, *gys):
-        xs = ctx.saved_tensors
+        ck, *xs = ctx.saved_tensors
         yb = [torch.zeros(1, dtype=xs[0].dtype, device=xs[0].device) if g is None else g.reshape(1).contiguous()
               for g in gys]
-        return (None, *ops.reduce_generic_vjp(ctx.op, xs, yb))
+        return (None, *ops.reduce_generic_vjp(ctx.op, xs, yb, ckpt=ck))
 
 
 class ReduceByIndex(torch.autograd.Function):

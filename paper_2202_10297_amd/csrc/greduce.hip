@@ -71,6 +71,14 @@ struct GShfl {
 // element (-inf, 0): combining costs one exp and no log, and exp(a - y)
 // becomes exp(a - m_y) / s_y.  Each element is (x, 1), or the neutral
 // element when x = -inf.
+// exp and division for log-add-exp: in FP32 the hardware exp2 (about 1 ulp
+// plus |x| * 2^-24 relative, x <= 0 here) and reciprocal; FP64 uses the
+// library functions.
+__device__ __forceinline__ float lae_exp(float x) { return __expf(x); }
+__device__ __forceinline__ double lae_exp(double x) { return exp(x); }
+__device__ __forceinline__ float lae_div(float a, float b) { return __fdividef(a, b); }
+__device__ __forceinline__ double lae_div(double a, double b) { return a / b; }
+
 template <class T>
 struct GLogAddExp : GShfl<T, 2> {
     static constexpr int K = 1;
@@ -85,7 +93,7 @@ struct GLogAddExp : GShfl<T, 2> {
         if (y.c[1] == T(0)) return x;
         if (x.c[1] == T(0)) return y;
         const T d = x.c[0] - y.c[0];
-        const T e = exp(-fabs(d));
+        const T e = lae_exp(-fabs(d));
         return d >= T(0) ? S{{x.c[0], x.c[1] + y.c[1] * e}} : S{{y.c[0], x.c[1] * e + y.c[1]}};
     }
     __device__ static __forceinline__ void vjp(S, S a, S r, S la, const T (&yb)[1], T (&out)[1]) {
@@ -95,7 +103,7 @@ struct GLogAddExp : GShfl<T, 2> {
             return;
         }
         const S y = comb(la, r);
-        out[0] = yb[0] * exp(a.c[0] - y.c[0]) / y.c[1];
+        out[0] = lae_div(yb[0] * lae_exp(a.c[0] - y.c[0]), y.c[1]);
     }
 };
 
@@ -158,14 +166,17 @@ struct GOut {
     T* p[4];
 };
 
-// Items per thread: 32 bytes of every component (two 16-byte loads).
-template <class T>
+// Items per thread: 32 bytes of every component (two 16-byte loads), fewer
+// where the operator state is large (at most 128 bytes of states per thread
+// for the in-thread suffixes), so that occupancy stays up.
+template <class Op, class T>
 constexpr int gr_ipt() {
-    return 32 / (int)sizeof(T);
+    return (32 / (int)sizeof(T)) < (128 / (int)sizeof(typename Op::S)) ? 32 / (int)sizeof(T)
+                                                                        : 128 / (int)sizeof(typename Op::S);
 }
-template <class T>
+template <class Op, class T>
 constexpr int gr_tile() {
-    return kGrBlock * gr_ipt<T>();
+    return kGrBlock * gr_ipt<Op, T>();
 }
 
 // A thread's IPT consecutive elements of one component; `cnt` of them exist.
@@ -223,10 +234,10 @@ __device__ __forceinline__ typename Op::S wave_exclusive_scan(typename Op::S v) 
     return ex;
 }
 
-template <class T>
+template <int IPT>
 __device__ __forceinline__ int gr_cnt(int64_t n, int64_t base) {
     const int64_t left = n - base;
-    return left <= 0 ? 0 : (left >= gr_ipt<T>() ? gr_ipt<T>() : (int)left);
+    return left <= 0 ? 0 : (left >= IPT ? IPT : (int)left);
 }
 
 // Pass 1: agg[t] = fold of tile t in index order.
@@ -234,10 +245,10 @@ template <class Op, class T, bool VEC>
 __global__ __launch_bounds__(kGrBlock) void gred_tile_agg_kernel(GPtrs<T> x, int64_t n,
                                                                  typename Op::S* __restrict__ agg) {
     using S = typename Op::S;
-    constexpr int IPT = gr_ipt<T>();
+    constexpr int IPT = gr_ipt<Op, T>();
     __shared__ S wtot[kGrBlock / kWave];
-    const int64_t base = (int64_t)blockIdx.x * gr_tile<T>() + (int64_t)threadIdx.x * IPT;
-    const int cnt = gr_cnt<T>(n, base);
+    const int64_t base = (int64_t)blockIdx.x * gr_tile<Op, T>() + (int64_t)threadIdx.x * IPT;
+    const int cnt = gr_cnt<IPT>(n, base);
     T v[Op::K][IPT];
 #pragma unroll
     for (int c = 0; c < Op::K; ++c) gr_load<T, IPT, VEC>(x.p[c] + base, cnt, v[c]);
@@ -342,10 +353,10 @@ __global__ __launch_bounds__(kGrBlock) void gred_vjp_kernel(GPtrs<T> x, int64_t 
     using S = typename Op::S;
     using A = typename Op::Acc;
     constexpr int K = Op::K;
-    constexpr int IPT = gr_ipt<T>();
+    constexpr int IPT = gr_ipt<Op, T>();
     __shared__ S wtot[kGrBlock / kWave];
-    const int64_t base = (int64_t)blockIdx.x * gr_tile<T>() + (int64_t)threadIdx.x * IPT;
-    const int cnt = gr_cnt<T>(n, base);
+    const int64_t base = (int64_t)blockIdx.x * gr_tile<Op, T>() + (int64_t)threadIdx.x * IPT;
+    const int cnt = gr_cnt<IPT>(n, base);
     T v[K][IPT];
 #pragma unroll
     for (int c = 0; c < K; ++c) gr_load<T, IPT, VEC>(x.p[c] + base, cnt, v[c]);
@@ -411,19 +422,19 @@ struct GrPlan {
     size_t tiles, groups;  // bytes of one per-tile / per-group array
 };
 
-template <class T>
+template <class Op, class T>
 static GrPlan gr_plan(int64_t n) {
     GrPlan p;
-    p.nt = ceil_div(n, gr_tile<T>());
+    p.nt = ceil_div(n, gr_tile<Op, T>());
     p.ng = ceil_div(p.nt, kGrGroup);
     p.tiles = align_up((size_t)(p.nt > 0 ? p.nt : 1) * kGrSlot, 256);
     p.groups = align_up((size_t)(p.ng > 0 ? p.ng : 1) * kGrSlot, 256);
     return p;
 }
 
-template <class T>
+template <class Op, class T>
 static size_t gr_ws(int64_t n) {
-    const GrPlan p = gr_plan<T>(n);
+    const GrPlan p = gr_plan<Op, T>(n);
     return 3 * p.tiles + 3 * p.groups;
 }
 
@@ -450,34 +461,46 @@ static void launch_folds(const GPtrs<T>& x, int64_t n, const GrPlan& p, typename
                        gagg);
 }
 
+// The tile folds go to the caller's checkpoint when one is given (the VJP
+// then starts from them instead of folding x again), else to the workspace.
 template <class Op, class T>
-static void launch_primal(const GPtrs<T>& x, int64_t n, const GOut<T>& y, void* ws, bool vec, hipStream_t st) {
+static void launch_primal(const GPtrs<T>& x, int64_t n, const GOut<T>& y, void* ckpt, void* ws, bool vec,
+                          hipStream_t st) {
     using S = typename Op::S;
     static_assert(sizeof(S) <= kGrSlot, "slot too small");
-    const GrPlan p = gr_plan<T>(n);
+    const GrPlan p = gr_plan<Op, T>(n);
     S* gagg = gr_array<S>(ws, p, 3);
-    launch_folds<Op, T>(x, n, p, gr_array<S>(ws, p, 0), gagg, vec, st);
+    S* agg = ckpt ? reinterpret_cast<S*>(ckpt) : gr_array<S>(ws, p, 0);
+    launch_folds<Op, T>(x, n, p, agg, gagg, vec, st);
     hipLaunchKernelGGL((gred_agg_scan_kernel<Op, T>), dim3(1), dim3(kGrAggBlock), 0, st, (const S*)gagg, p.ng,
                        (S*)nullptr, (S*)nullptr, y);
 }
 
 template <class Op, class T>
-static void launch_vjp(const GPtrs<T>& x, int64_t n, const GPtrs<T>& yb, const GOut<T>& xb, int acc, void* ws,
-                       bool vec, hipStream_t st) {
+static void launch_vjp(const GPtrs<T>& x, int64_t n, const void* ckpt, const GPtrs<T>& yb, const GOut<T>& xb, int acc,
+                       void* ws, bool vec, hipStream_t st) {
     using S = typename Op::S;
-    const GrPlan p = gr_plan<T>(n);
-    S* agg = gr_array<S>(ws, p, 0);
+    const GrPlan p = gr_plan<Op, T>(n);
     S* pre = gr_array<S>(ws, p, 1);
     S* suf = gr_array<S>(ws, p, 2);
     S* gagg = gr_array<S>(ws, p, 3);
     S* gpre = gr_array<S>(ws, p, 4);
     S* gsuf = gr_array<S>(ws, p, 5);
     const GOut<T> none{{nullptr, nullptr, nullptr, nullptr}};
-    launch_folds<Op, T>(x, n, p, agg, gagg, vec, st);
+    const unsigned gblocks = (unsigned)ceil_div(p.ng, kGrBlock / kWave);
+    const S* agg;
+    if (ckpt) {
+        agg = reinterpret_cast<const S*>(ckpt);
+        hipLaunchKernelGGL((gred_group_fold_kernel<Op>), dim3(gblocks), dim3(kGrBlock), 0, st, agg, p.nt, p.ng,
+                           gagg);
+    } else {
+        S* a = gr_array<S>(ws, p, 0);
+        launch_folds<Op, T>(x, n, p, a, gagg, vec, st);
+        agg = a;
+    }
     hipLaunchKernelGGL((gred_agg_scan_kernel<Op, T>), dim3(1), dim3(kGrAggBlock), 0, st, (const S*)gagg, p.ng, gpre,
                        gsuf, none);
-    const unsigned gblocks = (unsigned)ceil_div(p.ng, kGrBlock / kWave);
-    hipLaunchKernelGGL((gred_tile_prefix_kernel<Op>), dim3(gblocks), dim3(kGrBlock), 0, st, (const S*)agg, p.nt, p.ng,
+    hipLaunchKernelGGL((gred_tile_prefix_kernel<Op>), dim3(gblocks), dim3(kGrBlock), 0, st, agg, p.nt, p.ng,
                        (const S*)gpre, (const S*)gsuf, pre, suf);
     const dim3 gt((unsigned)p.nt), b(kGrBlock);
     const S* cp = pre;
@@ -504,7 +527,8 @@ using GOpFor = OpT<typename std::conditional<std::is_same<T, float>::value &&
                                              double, T>::type>;
 
 template <template <class> class OpT, class T>
-static void dispatch_primal(const void* const* x, int K, int64_t n, void* const* y, void* ws, hipStream_t st) {
+static void dispatch_primal(const void* const* x, int K, int64_t n, void* const* y, void* ckpt, void* ws,
+                            hipStream_t st) {
     GPtrs<T> xp{};
     GOut<T> yp{};
     bool vec = true;
@@ -513,12 +537,12 @@ static void dispatch_primal(const void* const* x, int K, int64_t n, void* const*
         yp.p[c] = (T*)y[c];
         vec = vec && (n == 0 || aligned(x[c], 16));
     }
-    launch_primal<GOpFor<OpT, T>, T>(xp, n, yp, ws, vec, st);
+    launch_primal<GOpFor<OpT, T>, T>(xp, n, yp, ckpt, ws, vec, st);
 }
 
 template <template <class> class OpT, class T>
-static void dispatch_vjp(const void* const* x, int K, int64_t n, const void* const* yb, void* const* xb, int acc,
-                         void* ws, hipStream_t st) {
+static void dispatch_vjp(const void* const* x, int K, int64_t n, const void* ckpt, const void* const* yb,
+                         void* const* xb, int acc, void* ws, hipStream_t st) {
     GPtrs<T> xp{}, yp{};
     GOut<T> xo{};
     bool vec = true;
@@ -528,7 +552,7 @@ static void dispatch_vjp(const void* const* x, int K, int64_t n, const void* con
         xo.p[c] = (T*)xb[c];
         vec = vec && aligned(x[c], 16) && aligned(xb[c], 16);
     }
-    launch_vjp<GOpFor<OpT, T>, T>(xp, n, yp, xo, acc, ws, vec, st);
+    launch_vjp<GOpFor<OpT, T>, T>(xp, n, ckpt, yp, xo, acc, ws, vec, st);
 }
 
 }  // namespace pvjp
@@ -539,7 +563,29 @@ extern "C" int pvjp_gop_components(pvjp_gop op) { return gop_components(op); }
 
 extern "C" size_t pvjp_reduce_generic_ws_bytes(pvjp_gop op, pvjp_dtype dtype, int64_t n) {
     if (gop_components(op) == 0 || !valid_dtype(dtype) || n < 0) return 0;
-    return dtype == PVJP_F64 ? gr_ws<double>(n) : gr_ws<float>(n);
+    if (dtype == PVJP_F64) {
+        if (op == PVJP_GOP_LOGADDEXP) return gr_ws<GOpFor<GLogAddExp, double>, double>(n);
+        if (op == PVJP_GOP_LINREC) return gr_ws<GOpFor<GLinRec, double>, double>(n);
+        return gr_ws<GOpFor<GMat2, double>, double>(n);
+    }
+    if (op == PVJP_GOP_LOGADDEXP) return gr_ws<GOpFor<GLogAddExp, float>, float>(n);
+    if (op == PVJP_GOP_LINREC) return gr_ws<GOpFor<GLinRec, float>, float>(n);
+    return gr_ws<GOpFor<GMat2, float>, float>(n);
+}
+
+extern "C" size_t pvjp_reduce_generic_ckpt_bytes(pvjp_gop op, pvjp_dtype dtype, int64_t n) {
+    if (gop_components(op) == 0 || !valid_dtype(dtype) || n < 0) return 0;
+    int64_t nt;
+    if (dtype == PVJP_F64) {
+        if (op == PVJP_GOP_LOGADDEXP) nt = gr_plan<GOpFor<GLogAddExp, double>, double>(n).nt;
+        else if (op == PVJP_GOP_LINREC) nt = gr_plan<GOpFor<GLinRec, double>, double>(n).nt;
+        else nt = gr_plan<GOpFor<GMat2, double>, double>(n).nt;
+    } else {
+        if (op == PVJP_GOP_LOGADDEXP) nt = gr_plan<GOpFor<GLogAddExp, float>, float>(n).nt;
+        else if (op == PVJP_GOP_LINREC) nt = gr_plan<GOpFor<GLinRec, float>, float>(n).nt;
+        else nt = gr_plan<GOpFor<GMat2, float>, float>(n).nt;
+    }
+    return (size_t)nt * kGrSlot;
 }
 
 static pvjp_status check_common(const char* name, pvjp_gop op, pvjp_dtype dtype, const void* const* x, int64_t n,
@@ -565,10 +611,11 @@ static pvjp_status check_common(const char* name, pvjp_gop op, pvjp_dtype dtype,
 }
 
 extern "C" pvjp_status pvjp_reduce_generic(pvjp_gop op, pvjp_dtype dtype, const void* const* x, int64_t n,
-                                           void* const* y, void* ws, size_t ws_bytes, void* stream) {
+                                           void* const* y, void* ckpt, void* ws, size_t ws_bytes, void* stream) {
     clear_error();
     const pvjp_status s = check_common("pvjp_reduce_generic", op, dtype, x, n, ws, ws_bytes);
     if (s != PVJP_OK) return s;
+    PVJP_REQUIRE(ckpt == nullptr || aligned(ckpt, 16), "pvjp_reduce_generic: ckpt must be 16-byte aligned");
     const int K = gop_components(op);
     PVJP_REQUIRE(y != nullptr, "pvjp_reduce_generic: y is NULL");
     for (int c = 0; c < K; ++c) PVJP_REQUIRE(y[c] != nullptr, "pvjp_reduce_generic: component %d of y is NULL", c);
@@ -576,24 +623,25 @@ extern "C" pvjp_status pvjp_reduce_generic(pvjp_gop op, pvjp_dtype dtype, const 
     const void* none[4] = {nullptr, nullptr, nullptr, nullptr};
     const void* const* xx = n > 0 ? x : none;
     if (dtype == PVJP_F64) {
-        if (op == PVJP_GOP_LOGADDEXP) dispatch_primal<GLogAddExp, double>(xx, K, n, y, ws, st);
-        else if (op == PVJP_GOP_LINREC) dispatch_primal<GLinRec, double>(xx, K, n, y, ws, st);
-        else dispatch_primal<GMat2, double>(xx, K, n, y, ws, st);
+        if (op == PVJP_GOP_LOGADDEXP) dispatch_primal<GLogAddExp, double>(xx, K, n, y, ckpt, ws, st);
+        else if (op == PVJP_GOP_LINREC) dispatch_primal<GLinRec, double>(xx, K, n, y, ckpt, ws, st);
+        else dispatch_primal<GMat2, double>(xx, K, n, y, ckpt, ws, st);
     } else {
-        if (op == PVJP_GOP_LOGADDEXP) dispatch_primal<GLogAddExp, float>(xx, K, n, y, ws, st);
-        else if (op == PVJP_GOP_LINREC) dispatch_primal<GLinRec, float>(xx, K, n, y, ws, st);
-        else dispatch_primal<GMat2, float>(xx, K, n, y, ws, st);
+        if (op == PVJP_GOP_LOGADDEXP) dispatch_primal<GLogAddExp, float>(xx, K, n, y, ckpt, ws, st);
+        else if (op == PVJP_GOP_LINREC) dispatch_primal<GLinRec, float>(xx, K, n, y, ckpt, ws, st);
+        else dispatch_primal<GMat2, float>(xx, K, n, y, ckpt, ws, st);
     }
     PVJP_LAUNCHED("pvjp_reduce_generic");
     return PVJP_OK;
 }
 
 extern "C" pvjp_status pvjp_reduce_generic_vjp(pvjp_gop op, pvjp_dtype dtype, const void* const* x, int64_t n,
-                                               const void* const* y_bar, void* const* x_bar, int accumulate,
-                                               void* ws, size_t ws_bytes, void* stream) {
+                                               const void* ckpt, const void* const* y_bar, void* const* x_bar,
+                                               int accumulate, void* ws, size_t ws_bytes, void* stream) {
     clear_error();
     const pvjp_status s = check_common("pvjp_reduce_generic_vjp", op, dtype, x, n, ws, ws_bytes);
     if (s != PVJP_OK) return s;
+    PVJP_REQUIRE(ckpt == nullptr || aligned(ckpt, 16), "pvjp_reduce_generic_vjp: ckpt must be 16-byte aligned");
     if (n == 0) return PVJP_OK;
     const int K = gop_components(op);
     PVJP_REQUIRE(y_bar != nullptr && x_bar != nullptr, "pvjp_reduce_generic_vjp: y_bar and x_bar must be non-NULL");
@@ -605,13 +653,13 @@ extern "C" pvjp_status pvjp_reduce_generic_vjp(pvjp_gop op, pvjp_dtype dtype, co
     }
     const hipStream_t st = as_stream(stream);
     if (dtype == PVJP_F64) {
-        if (op == PVJP_GOP_LOGADDEXP) dispatch_vjp<GLogAddExp, double>(x, K, n, y_bar, x_bar, accumulate, ws, st);
-        else if (op == PVJP_GOP_LINREC) dispatch_vjp<GLinRec, double>(x, K, n, y_bar, x_bar, accumulate, ws, st);
-        else dispatch_vjp<GMat2, double>(x, K, n, y_bar, x_bar, accumulate, ws, st);
+        if (op == PVJP_GOP_LOGADDEXP) dispatch_vjp<GLogAddExp, double>(x, K, n, ckpt, y_bar, x_bar, accumulate, ws, st);
+        else if (op == PVJP_GOP_LINREC) dispatch_vjp<GLinRec, double>(x, K, n, ckpt, y_bar, x_bar, accumulate, ws, st);
+        else dispatch_vjp<GMat2, double>(x, K, n, ckpt, y_bar, x_bar, accumulate, ws, st);
     } else {
-        if (op == PVJP_GOP_LOGADDEXP) dispatch_vjp<GLogAddExp, float>(x, K, n, y_bar, x_bar, accumulate, ws, st);
-        else if (op == PVJP_GOP_LINREC) dispatch_vjp<GLinRec, float>(x, K, n, y_bar, x_bar, accumulate, ws, st);
-        else dispatch_vjp<GMat2, float>(x, K, n, y_bar, x_bar, accumulate, ws, st);
+        if (op == PVJP_GOP_LOGADDEXP) dispatch_vjp<GLogAddExp, float>(x, K, n, ckpt, y_bar, x_bar, accumulate, ws, st);
+        else if (op == PVJP_GOP_LINREC) dispatch_vjp<GLinRec, float>(x, K, n, ckpt, y_bar, x_bar, accumulate, ws, st);
+        else dispatch_vjp<GMat2, float>(x, K, n, ckpt, y_bar, x_bar, accumulate, ws, st);
     }
     PVJP_LAUNCHED("pvjp_reduce_generic_vjp");
     return PVJP_OK;

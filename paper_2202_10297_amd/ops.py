@@ -147,23 +147,29 @@ def _components(op, xs):
     return xs, n, K
 
 
-def reduce_generic(op, xs):
+def reduce_generic(op, xs, ckpt: bool = False):
     """y = xs_0 (.) ... (.) xs_{n-1} for an operator of Sec. 5.1.1's general
-    rule; xs is the list of K component tensors.  Returns K one-element
-    tensors."""
+    rule; xs is the list of K component tensors.  Returns (ys, ckpt): K
+    one-element tensors and, if asked for, the per-tile checkpoint (the tile
+    folds, a uint8 tensor) that lets the VJP read x once."""
     xs, n, K = _components(op, xs)
     dt, dev = _dt(xs[0]), xs[0].device
     ys = [torch.empty(1, dtype=xs[0].dtype, device=dev) for _ in range(K)]
+    ck = None
+    if ckpt:
+        ck = torch.empty(max(capi.lib().pvjp_reduce_generic_ckpt_bytes(_gop(op), dt, n), 16), dtype=torch.uint8,
+                         device=dev)
     nb = capi.lib().pvjp_reduce_generic_ws_bytes(_gop(op), dt, n)
     ws = WS.get("reduce_generic", nb, dev)
     capi.call("pvjp_reduce_generic", _gop(op), dt, capi.ptr_array([_ptr(x) for x in xs]), n,
-              capi.ptr_array([_ptr(y) for y in ys]), _ptr(ws), ws.numel(), _stream(dev))
-    return ys
+              capi.ptr_array([_ptr(y) for y in ys]), _ptr(ck), _ptr(ws), ws.numel(), _stream(dev))
+    return ys, ck
 
 
-def reduce_generic_vjp(op, xs, y_bar, x_bar=None, accumulate=False):
+def reduce_generic_vjp(op, xs, y_bar, x_bar=None, accumulate=False, ckpt=None):
     """x_bar (+)= the adjoint of every element (list of K tensors); y_bar is
-    a list of K one-element device tensors."""
+    a list of K one-element device tensors; ckpt is the checkpoint from
+    reduce_generic on the same xs (or None: the tile folds are recomputed)."""
     xs, n, K = _components(op, xs)
     dt, dev = _dt(xs[0]), xs[0].device
     if x_bar is None:
@@ -172,7 +178,7 @@ def reduce_generic_vjp(op, xs, y_bar, x_bar=None, accumulate=False):
         raise ValueError(f"operator {op} takes {K} components")
     nb = capi.lib().pvjp_reduce_generic_ws_bytes(_gop(op), dt, n)
     ws = WS.get("reduce_generic", nb, dev)
-    capi.call("pvjp_reduce_generic_vjp", _gop(op), dt, capi.ptr_array([_ptr(x) for x in xs]), n,
+    capi.call("pvjp_reduce_generic_vjp", _gop(op), dt, capi.ptr_array([_ptr(x) for x in xs]), n, _ptr(ckpt),
               capi.ptr_array([_ptr(y) for y in y_bar]), capi.ptr_array([_ptr(x) for x in x_bar]),
               int(accumulate), _ptr(ws), ws.numel(), _stream(dev))
     return x_bar

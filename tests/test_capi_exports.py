@@ -92,18 +92,23 @@ def test_generic_reduce_validation(capi):
     assert L.pvjp_reduce_generic_ws_bytes(capi.GOP_LINREC, capi.F32, 1 << 26) == 3 * 32768 * 32 + 3 * 512 * 32
     assert L.pvjp_reduce_generic_ws_bytes(7, capi.F32, 10) == 0
     one = capi.ptr_array([256])
-    assert L.pvjp_reduce_generic(7, capi.F32, one, 10, one, 256, 1 << 20, None) == capi.PVJP_EINVAL
+    assert L.pvjp_reduce_generic_ckpt_bytes(capi.GOP_LINREC, capi.F32, (1 << 26) + 1) == 32769 * 32
+    assert L.pvjp_reduce_generic(7, capi.F32, one, 10, one, None, 256, 1 << 20, None) == capi.PVJP_EINVAL
     assert "operator" in capi.last_error()
-    assert L.pvjp_reduce_generic(capi.GOP_LOGADDEXP, 5, one, 10, one, 256, 1 << 20, None) == capi.PVJP_EINVAL
-    assert L.pvjp_reduce_generic(capi.GOP_LOGADDEXP, capi.F32, one, 10, one, 256, 16, None) == capi.PVJP_ENOMEM
-    assert L.pvjp_reduce_generic(capi.GOP_LOGADDEXP, capi.F32, one, 10, one, 100, 1 << 20, None) == capi.PVJP_EINVAL
+    assert L.pvjp_reduce_generic(capi.GOP_LOGADDEXP, 5, one, 10, one, None, 256, 1 << 20, None) == capi.PVJP_EINVAL
+    assert L.pvjp_reduce_generic(capi.GOP_LOGADDEXP, capi.F32, one, 10, one, None, 256, 16, None) == capi.PVJP_ENOMEM
+    assert L.pvjp_reduce_generic(capi.GOP_LOGADDEXP, capi.F32, one, 10, one, None, 100, 1 << 20,
+                                 None) == capi.PVJP_EINVAL
     assert "aligned" in capi.last_error()
+    assert L.pvjp_reduce_generic(capi.GOP_LOGADDEXP, capi.F32, one, 10, one, 8, 256, 1 << 20, None) == capi.PVJP_EINVAL
+    assert "ckpt" in capi.last_error()
     two = capi.ptr_array([256, None])
-    assert L.pvjp_reduce_generic(capi.GOP_LINREC, capi.F64, two, 10, two, 256, 1 << 20, None) == capi.PVJP_EINVAL
+    assert L.pvjp_reduce_generic(capi.GOP_LINREC, capi.F64, two, 10, two, None, 256, 1 << 20,
+                                 None) == capi.PVJP_EINVAL
     assert "component 1" in capi.last_error()
-    assert L.pvjp_reduce_generic_vjp(capi.GOP_LOGADDEXP, capi.F32, one, 10, None, one, 0, 256, 1 << 20,
+    assert L.pvjp_reduce_generic_vjp(capi.GOP_LOGADDEXP, capi.F32, one, 10, None, None, one, 0, 256, 1 << 20,
                                      None) == capi.PVJP_EINVAL
     misaligned = capi.ptr_array([258])
-    assert L.pvjp_reduce_generic_vjp(capi.GOP_LOGADDEXP, capi.F32, one, 10, one, misaligned, 0, 256, 1 << 20,
+    assert L.pvjp_reduce_generic_vjp(capi.GOP_LOGADDEXP, capi.F32, one, 10, None, one, misaligned, 0, 256, 1 << 20,
                                      None) == capi.PVJP_EINVAL
     assert "misaligned" in capi.last_error()

@@ -4,9 +4,10 @@ seeded inputs.
 
 Bars: FP64 relative L2 1e-12, FP32 2e-5 against the FP64 oracle on the same
 FP32 inputs; zero adjoints of -inf log-add-exp elements exact.  Sizes span
-one tile, tile boundaries, ragged tails and more tiles than the aggregate
-scan's block has threads; at the size the benchmark times (2^26 elements)
-sampled adjoints are checked one by one against the oracle's sampled form.
+one tile, tile boundaries, ragged tails, many 64-tile groups and more groups
+than the group scan's block has threads; at the size the benchmark times
+(2^26 elements) sampled adjoints are checked one by one against the oracle's
+sampled form.
 """
 import numpy as np
 import pytest
@@ -19,7 +20,12 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 OPS = ["logaddexp", "linrec", "mat2"]
-TILE = {"f32": 2048, "f64": 1024}
+
+
+def tile(op, dtype):
+    # elements per tile: 2048 (FP32) or 1024 (FP64); 1024 for the FP32 2x2
+    # matrix product, whose FP64 state keeps 4 elements per thread
+    return 1024 if (dtype == "f64" or op == "mat2") else 2048
 
 
 def dev(x):
@@ -46,24 +52,24 @@ def ops():
 def inputs(op, n, dtype, seed):
     xs, yb = workloads.gop(op, n, dtype, seed=seed)
     if op == "logaddexp" and n > 3:
-        t = TILE[dtype]
+        t = tile(op, dtype)
         for i in {0, n // 2, min(t, n - 1), n - 1}:
             xs[0][i] = -np.inf
     return xs, yb
 
 
-def run(ops, op, xs, yb, accumulate=False, base=None):
+def run(ops, op, xs, yb, accumulate=False, base=None, ckpt=False):
     dx = [dev(x) for x in xs]
-    ys = ops.reduce_generic(op, dx)
+    ys, ck = ops.reduce_generic(op, dx, ckpt=ckpt)
     dyb = [dev(yb[c:c + 1]) for c in range(len(xs))]
     xb = None
     if base is not None:
         xb = [dev(b) for b in base]
-    xb = ops.reduce_generic_vjp(op, dx, dyb, x_bar=xb, accumulate=accumulate)
+    xb = ops.reduce_generic_vjp(op, dx, dyb, x_bar=xb, accumulate=accumulate, ckpt=ck)
     return np.array([host(y)[0] for y in ys]), [host(g) for g in xb]
 
 
-SIZES = {"f32": [1, 2, 2047, 2048, 2049, 3 * 2048 + 5, 300001],
+SIZES = {"f32": [1, 2, 1023, 1024, 1025, 2047, 2048, 2049, 3 * 2048 + 5, 300001],
          "f64": [1, 2, 1023, 1024, 1025, 3 * 1024 + 5, 150001]}
 
 
@@ -79,17 +85,21 @@ def test_primal_and_vjp(ops, orc, op, dtype, n):
     if op == "logaddexp":
         ninf = np.isneginf(xs[0])
         assert np.all(xb[0][ninf] == 0)
+    # from the primal's per-tile checkpoint: the same tile folds, the same bits
+    y2, xb2 = run(ops, op, xs, yb, ckpt=True)
+    assert np.array_equal(y, y2) and all(np.array_equal(a, b) for a, b in zip(xb, xb2))
 
 
 @pytest.mark.parametrize("op", OPS)
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_accumulate(ops, orc, op, dtype):
-    n = 3 * TILE[dtype] + 77
+    n = 3 * tile(op, dtype) + 77
     xs, yb = inputs(op, n, dtype, seed=5)
     base = [np.full(n, 0.5, dtype=xs[0].dtype) for _ in xs]
-    _, xb = run(ops, op, xs, yb, accumulate=True, base=base)
     ref = orc.reduce_generic_vjp(op, xs, yb)
-    assert rel_l2([g - 0.5 for g in xb], ref) <= tol(dtype) * 2
+    for ck in (False, True):
+        _, xb = run(ops, op, xs, yb, accumulate=True, base=base, ckpt=ck)
+        assert rel_l2([g - 0.5 for g in xb], ref) <= tol(dtype) * 2
 
 
 @pytest.mark.parametrize("op", OPS)
@@ -97,13 +107,13 @@ def test_accumulate(ops, orc, op, dtype):
 def test_unaligned_views(ops, orc, op, dtype):
     # component arrays that start 1 element past a 16-byte boundary take the
     # scalar-load path
-    n = 2 * TILE[dtype] + 333
+    n = 2 * tile(op, dtype) + 333
     xs, yb = inputs(op, n + 1, dtype, seed=9)
     dx = [dev(x)[1:] for x in xs]
-    ys = ops.reduce_generic(op, dx)
+    ys, ck = ops.reduce_generic(op, dx, ckpt=True)
     dyb = [dev(yb[c:c + 1]) for c in range(len(xs))]
     out = [torch.empty(n + 1, dtype=dx[0].dtype, device="cuda")[1:] for _ in xs]
-    ops.reduce_generic_vjp(op, dx, dyb, x_bar=out)
+    ops.reduce_generic_vjp(op, dx, dyb, x_bar=out, ckpt=ck)
     sub = [x[1:] for x in xs]
     assert rel_l2([host(y)[0] for y in ys], orc.reduce_generic(op, sub)) <= (1e-13 if dtype == "f64" else 1e-6)
     assert rel_l2([host(o) for o in out], orc.reduce_generic_vjp(op, sub, yb)) <= tol(dtype)
@@ -115,14 +125,14 @@ def test_empty_input(ops):
     for op, neutral in (("logaddexp", [-np.inf]), ("linrec", [1.0, 0.0]), ("mat2", [1.0, 0.0, 0.0, 1.0])):
         K = len(neutral)
         xs = [torch.empty(0, dtype=torch.float64, device="cuda") for _ in range(K)]
-        ys = ops.reduce_generic(op, xs)
+        ys, _ = ops.reduce_generic(op, xs)
         assert [host(y)[0] for y in ys] == neutral
         # the VJP of an empty input touches nothing
         xb = [torch.full((4,), 7.0, dtype=torch.float64, device="cuda") for _ in range(K)]
         yb = [torch.ones(1, dtype=torch.float64, device="cuda") for _ in range(K)]
         ws = torch.zeros(4096, dtype=torch.uint8, device="cuda")
         capi.call("pvjp_reduce_generic_vjp", ops._gop(op), capi.F64, capi.ptr_array([x.data_ptr() for x in xs]), 0,
-                  capi.ptr_array([y.data_ptr() for y in yb]), capi.ptr_array([x.data_ptr() for x in xb]), 0,
+                  None, capi.ptr_array([y.data_ptr() for y in yb]), capi.ptr_array([x.data_ptr() for x in xb]), 0,
                   ws.data_ptr(), ws.numel(), torch.cuda.current_stream().cuda_stream)
         assert all(np.all(host(x) == 7.0) for x in xb)
 
@@ -156,20 +166,23 @@ def check_sampled(orc, op, xs, yb, xb, idx, dtype):
 
 @pytest.mark.parametrize("op,dtype,n", [("logaddexp", "f32", 2048 * 1100 + 3), ("linrec", "f64", 1024 * 1500 + 7),
                                         ("mat2", "f32", 2048 * 1030 + 1), ("mat2", "f64", 1024 * 1200 + 9)])
-def test_more_tiles_than_scan_threads(ops, orc, op, dtype, n):
+def test_many_groups_sampled(ops, orc, op, dtype, n):
+    # tens of 64-tile groups, the last one ragged
     xs, yb = inputs(op, n, dtype, seed=17)
     y, xb = run(ops, op, xs, yb)
     assert rel_l2(y, orc.reduce_generic(op, xs)) <= (1e-12 if dtype == "f64" else 1e-5)
-    check_sampled(orc, op, xs, yb, xb, sample_indices(n, TILE[dtype], 3), dtype)
+    check_sampled(orc, op, xs, yb, xb, sample_indices(n, tile(op, dtype), 3), dtype)
 
 
-@pytest.mark.parametrize("op,dtype", [("logaddexp", "f32"), ("linrec", "f64"), ("mat2", "f32")])
-def test_benchmark_size_sampled(ops, orc, op, dtype):
-    n = 1 << 26
+@pytest.mark.parametrize("op,dtype,n", [("logaddexp", "f32", 1 << 26), ("linrec", "f64", (1 << 26) + 1),
+                                        ("mat2", "f32", 1 << 26)])
+def test_benchmark_size_sampled(ops, orc, op, dtype, n):
+    # 2^26 elements as timed; the FP64 case has 65537 tiles in 1025 groups,
+    # one more than the group scan's block has threads
     xs, yb = workloads.gop(op, n, dtype, seed=0)
-    y, xb = run(ops, op, xs, yb)
+    y, xb = run(ops, op, xs, yb, ckpt=True)
     assert rel_l2(y, orc.reduce_generic(op, xs)) <= (1e-12 if dtype == "f64" else 1e-5)
-    check_sampled(orc, op, xs, yb, xb, sample_indices(n, TILE[dtype], 4), dtype)
+    check_sampled(orc, op, xs, yb, xb, sample_indices(n, tile(op, dtype), 4), dtype)
 
 
 def test_deterministic(ops):
