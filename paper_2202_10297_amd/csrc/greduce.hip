@@ -219,21 +219,6 @@ __device__ __forceinline__ typename Op::S gr_elem(const T (&v)[Op::K][IPT], int 
     return Op::elem(c);
 }
 
-// Exclusive scan over the lanes of a wave in scan order (REV: lane 63
-// first); lanes hold one state each.
-template <class Op, bool REV>
-__device__ __forceinline__ typename Op::S wave_exclusive_scan(typename Op::S v) {
-    const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const typename Op::S o = REV ? Op::down(v, d) : Op::up(v, d);
-        if (REV ? (lane + d < kWave) : (lane >= d)) v = Op::comb(o, v);
-    }
-    typename Op::S ex = REV ? Op::down(v, 1) : Op::up(v, 1);
-    if (REV ? (lane == kWave - 1) : (lane == 0)) ex = Op::id();
-    return ex;
-}
-
 template <int IPT>
 __device__ __forceinline__ int gr_cnt(int64_t n, int64_t base) {
     const int64_t left = n - base;

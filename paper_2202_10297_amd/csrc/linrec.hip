@@ -329,7 +329,7 @@ __global__ __launch_bounds__(kScanBlock) void linrec_vjp_tile_agg_kernel(const T
     if (threadIdx.x == 0) agg[tile] = total;
 }
 
-// (2) exclusive scan of the tile aggregates by one block, in scan order:
+// (2) exclusive scan of aggregates by one block, in scan order:
 // increasing tile index, or decreasing with REV.  Thread t folds a
 // contiguous run of the scan order, the runs are scanned across the block,
 // then each thread writes its run's prefixes.
@@ -355,18 +355,59 @@ __global__ __launch_bounds__(kAggBlock) void linrec_agg_scan_kernel(const typena
     }
 }
 
+// (2) with many tiles the one-block scan above would walk tens of thousands
+// of aggregates; tiles are therefore taken in groups of 64, one wave per
+// group: (2a) fold each group in scan order, (2b) scan the group folds with
+// linrec_agg_scan_kernel, (2c) give every tile its group's prefix folded with
+// the group's tiles before it in scan order.
+constexpr int kTileGroup = kWave;
+
+template <class Op, bool REV>
+__global__ __launch_bounds__(kScanBlock) void linrec_group_fold_kernel(const typename Op::S* __restrict__ agg,
+                                                                       int64_t nt, int64_t ng,
+                                                                       typename Op::S* __restrict__ gagg) {
+    using S = typename Op::S;
+    const int64_t g = (int64_t)blockIdx.x * (kScanBlock / kWave) + threadIdx.x / kWave;
+    if (g >= ng) return;  // whole waves leave together
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t t = g * kTileGroup + lane;
+    const S own = t < nt ? agg[t] : Op::id();
+    const S inc = Op::comb(wave_exclusive_scan<Op, REV>(own), own);
+    if (lane == (REV ? 0 : kWave - 1)) gagg[g] = inc;  // the last lane in scan order
+}
+
+template <class Op, bool REV>
+__global__ __launch_bounds__(kScanBlock) void linrec_group_prefix_kernel(const typename Op::S* __restrict__ agg,
+                                                                         int64_t nt, int64_t ng,
+                                                                         const typename Op::S* __restrict__ gpre,
+                                                                         typename Op::S* __restrict__ pre) {
+    using S = typename Op::S;
+    const int64_t g = (int64_t)blockIdx.x * (kScanBlock / kWave) + threadIdx.x / kWave;
+    if (g >= ng) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t t = g * kTileGroup + lane;
+    const S own = t < nt ? agg[t] : Op::id();
+    const S ex = wave_exclusive_scan<Op, REV>(own);
+    if (t < nt) pre[t] = Op::comb(gpre[g], ex);
+}
+
 // ------------------------------------------------------------------ host
 // Inputs of more tiles than this take the three-pass form.
 constexpr int64_t kThreePassTiles = 4096;
 constexpr size_t kAggSlot = 32;  // bytes per tile for an aggregate or a prefix (either operator)
 
-// [header | tile states | group states | aggregates | prefixes]: the
-// three-pass form never touches the lookback states or the header.
+// [header | tile states | group states | tile aggregates | tile prefixes |
+// group folds | group prefixes]: the three-pass form never touches the
+// lookback states or the header.
+static size_t group_bytes(int64_t ntiles) {
+    return align_up((size_t)ceil_div(ntiles, kTileGroup) * kAggSlot, 256);
+}
+
 template <class S>
 static size_t lookback_bytes(int64_t ntiles) {
     static_assert(sizeof(S) <= kAggSlot, "aggregate slot too small");
     return align_up(sizeof(LookbackHdr) + lookback_state_bytes<S>(ntiles), 256) +
-           align_up((size_t)ntiles * kAggSlot * 2, 256);
+           align_up((size_t)ntiles * kAggSlot * 2, 256) + 2 * group_bytes(ntiles);
 }
 
 template <class S>
@@ -378,6 +419,27 @@ static S* agg_array(void* ws, int64_t ntiles) {
 template <class S>
 static S* pre_array(void* ws, int64_t ntiles) {
     return reinterpret_cast<S*>(reinterpret_cast<char*>(agg_array<S>(ws, ntiles)) + (size_t)ntiles * kAggSlot);
+}
+
+template <class S>
+static S* group_array(void* ws, int64_t ntiles, int which) {
+    return reinterpret_cast<S*>(reinterpret_cast<char*>(agg_array<S>(ws, ntiles)) +
+                                align_up((size_t)ntiles * kAggSlot * 2, 256) + which * group_bytes(ntiles));
+}
+
+// (2a)-(2c): pre[t] = exclusive fold of the tile aggregates in scan order.
+template <class Op, bool REV>
+static void scan_aggregates(const typename Op::S* agg, int64_t nt, typename Op::S* pre, void* ws,
+                            hipStream_t st) {
+    using S = typename Op::S;
+    const int64_t ng = ceil_div(nt, kTileGroup);
+    S* gagg = group_array<S>(ws, nt, 0);
+    S* gpre = group_array<S>(ws, nt, 1);
+    const unsigned gb = (unsigned)ceil_div(ng, kScanBlock / kWave);
+    hipLaunchKernelGGL((linrec_group_fold_kernel<Op, REV>), dim3(gb), dim3(kScanBlock), 0, st, agg, nt, ng, gagg);
+    hipLaunchKernelGGL((linrec_agg_scan_kernel<Op, REV>), dim3(1), dim3(kAggBlock), 0, st, (const S*)gagg, ng, gpre);
+    hipLaunchKernelGGL((linrec_group_prefix_kernel<Op, REV>), dim3(gb), dim3(kScanBlock), 0, st, agg, nt, ng,
+                       (const S*)gpre, pre);
 }
 
 template <class T>
@@ -412,8 +474,7 @@ static pvjp_status launch_fwd(const void* a, const void* b, int64_t n, void* A, 
         S* pre = pre_array<S>(ws, nt);
         hipLaunchKernelGGL(linrec_tile_agg_kernel<T>, dim3((unsigned)nt), dim3(kScanBlock), 0, st, (const T*)a,
                            (const T*)b, n, agg);
-        hipLaunchKernelGGL((linrec_agg_scan_kernel<LinRec<T>, false>), dim3(1), dim3(kAggBlock), 0, st,
-                           (const S*)agg, nt, pre);
+        scan_aggregates<LinRec<T>, false>(agg, nt, pre, ws, st);
         hipLaunchKernelGGL((linrec_fwd_kernel<T, true>), dim3((unsigned)nt), dim3(kScanBlock), 0, st,
                            (const T*)a, (const T*)b, n, (T*)A, (T*)B, (T*)ckpt, hdr, states, nt, (const S*)pre);
     } else {
@@ -445,8 +506,7 @@ static pvjp_status launch_vjp(const void* a, const void* b, const void* ya, cons
         LS* p = pre_array<LS>(ws, nt);
         hipLaunchKernelGGL(linrec_vjp_tile_agg_kernel<T>, dim3((unsigned)nt), dim3(kScanBlock), 0, st, (const T*)a,
                            (const T*)ya, (const T*)yb, n, agg);
-        hipLaunchKernelGGL((linrec_agg_scan_kernel<LinO<T>, true>), dim3(1), dim3(kAggBlock), 0, st, (const LS*)agg,
-                           nt, p);
+        scan_aggregates<LinO<T>, true>(agg, nt, p, ws, st);
         pre = p;
     }
     if (pre) {

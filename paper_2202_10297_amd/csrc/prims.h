@@ -135,6 +135,21 @@ __device__ __forceinline__ typename Op::S block_exclusive_scan(typename Op::S ag
     return Op::comb(wpre, ex);
 }
 
+// Exclusive scan over the lanes of one wave in scan order (REV: lane 63
+// first); every lane holds one state.
+template <class Op, bool REV>
+__device__ __forceinline__ typename Op::S wave_exclusive_scan(typename Op::S v) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const typename Op::S o = REV ? Op::down(v, d) : Op::up(v, d);
+        if (REV ? (lane + d < kWave) : (lane >= d)) v = Op::comb(o, v);
+    }
+    typename Op::S ex = REV ? Op::down(v, 1) : Op::up(v, 1);
+    if (REV ? (lane == kWave - 1) : (lane == 0)) ex = Op::id();
+    return ex;
+}
+
 // ------------------------------------------------------- LDS transposes
 // Padded LDS index: one element of padding per 256 bytes keeps both the
 // striped writes and the blocked reads free of bank conflicts for the
