@@ -51,6 +51,8 @@ _SIGS = {
     "orc_reduce_generic": [_I, _L, _P, _P],
     "orc_reduce_generic_vjp": [_I, _L, _P, _P, _P],
     "orc_reduce_generic_vjp_at": [_I, _L, _P, _P, _L, _P, _P],
+    "orc_scan_generic": [_I, _L, _P, _P],
+    "orc_scan_generic_vjp": [_I, _L, _P, _P, _P],
 }
 
 
@@ -278,4 +280,30 @@ def reduce_generic_vjp_at(op, xs, y_bar, idx):
     out = np.empty((idx.size, K))
     _check(lib().orc_reduce_generic_vjp_at(_gop(op), n, ptrs, _p(yb), idx.size, _p(idx), _p(out)),
            "reduce_generic_vjp_at")
+    return out
+
+
+def _arrays(K, n):
+    out = [np.empty(n) for _ in range(K)]
+    return out, (ctypes.c_void_p * K)(*[o.ctypes.data for o in out])
+
+
+def scan_generic(op, xs):
+    """Inclusive scan y_i = xs_0 (.) ... (.) xs_i: a list of K arrays."""
+    xs, ptrs, n, K = _components(op, xs)
+    ys, yptr = _arrays(K, n)
+    _check(lib().orc_scan_generic(_gop(op), n, ptrs, yptr), "scan_generic")
+    return ys
+
+
+def scan_generic_vjp(op, xs, y_bar):
+    """Adjoints of every input element given the adjoints of every output
+    (y_bar: list of K arrays)."""
+    xs, ptrs, n, K = _components(op, xs)
+    yb = [_f64(y) for y in y_bar]
+    if len(yb) != K or any(y.size != n for y in yb):
+        raise ValueError("y_bar must be K arrays of n")
+    ybp = (ctypes.c_void_p * K)(*[y.ctypes.data for y in yb])
+    out, optr = _arrays(K, n)
+    _check(lib().orc_scan_generic_vjp(_gop(op), n, ptrs, ybp, optr), "scan_generic_vjp")
     return out

@@ -944,3 +944,66 @@ int orc_reduce_generic_vjp_at(int op, int64_t n, const double* const* x, const d
     free(ord), free(L), free(R);
     return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Inclusive scan with a general operator: y_i = acc after folding x_i.       */
+/* ------------------------------------------------------------------------ */
+
+int orc_scan_generic(int op, int64_t n, const double* const* x, double* const* y) {
+    if (!gop_args_ok(op, n, x)) return -1;
+    int K = orc_gop_components(op);
+    if (n > 0) {
+        if (!y) return -1;
+        for (int c = 0; c < K; ++c)
+            if (!y[c]) return -1;
+    }
+    double acc[4], xi[4];
+    gop_neutral(op, acc);
+    for (int64_t i = 0; i < n; ++i) {
+        for (int c = 0; c < K; ++c) xi[c] = x[c][i];
+        gop_comb(op, acc, xi, acc);
+        for (int c = 0; c < K; ++c) y[c][i] = acc[c];
+    }
+    return 0;
+}
+
+int orc_scan_generic_vjp(int op, int64_t n, const double* const* x, const double* const* y_bar,
+                         double* const* x_bar) {
+    if (!gop_args_ok(op, n, x)) return -1;
+    int K = orc_gop_components(op);
+    if (n == 0) return 0;
+    if (!y_bar || !x_bar) return -1;
+    for (int c = 0; c < K; ++c)
+        if (!y_bar[c] || !x_bar[c]) return -1;
+    tape_t T, *t = &T;
+    if (tape_init(t, (int64_t)(K * 4 + 4) * n + 16, (int64_t)(K * 3 + 4) * n + 16)) return -2;
+    int64_t* sx = (int64_t*)malloc((size_t)n * K * sizeof(int64_t));
+    int64_t* sy = (int64_t*)malloc((size_t)n * K * sizeof(int64_t));
+    if (!sx || !sy) {
+        free(sx), free(sy);
+        tape_free(t);
+        return -2;
+    }
+    double e[4];
+    gop_neutral(op, e);
+    int64_t acc[4];
+    for (int c = 0; c < K; ++c) acc[c] = leaf(t, e[c]); /* constants */
+    for (int64_t i = 0; i < n; ++i) {
+        for (int c = 0; c < K; ++c) sx[i * K + c] = leaf(t, x[c][i]);
+        gop_step(t, op, acc, &sx[i * K], acc);
+        for (int c = 0; c < K; ++c) sy[i * K + c] = acc[c]; /* the slot holding y_i */
+    }
+    int rc = (t->oom || tape_reverse(t)) ? -2 : 0;
+    if (!rc) {
+        /* y_i and y_{i-1} may share a slot (a -inf log-add-exp element leaves
+         * the fold unchanged): their seeds then add up, as they must */
+        for (int64_t i = 0; i < n; ++i)
+            for (int c = 0; c < K; ++c) t->adj[sy[i * K + c]] += y_bar[c][i];
+        sweep(t);
+        for (int64_t i = 0; i < n; ++i)
+            for (int c = 0; c < K; ++c) x_bar[c][i] = t->adj[sx[i * K + c]];
+    }
+    free(sx), free(sy);
+    tape_free(t);
+    return rc;
+}

@@ -112,6 +112,15 @@ int orc_reduce_generic_vjp(int op, int64_t n, const double* const* x, const doub
 int orc_reduce_generic_vjp_at(int op, int64_t n, const double* const* x, const double* y_bar,
                               int64_t cnt, const int64_t* idx, double* out);
 
+/* Inclusive scan with the same general operators (Sec. 5.2 and its Jacobian
+ * generalisation): y_i = x_0 (.) ... (.) x_i, K output components per
+ * element (LOGADDEXP: the running log-sum-exp).  y[c], y_bar[c], x_bar[c]:
+ * K arrays of n.  The VJP records the fold on the tape, seeds every y_i with
+ * y_bar_i and sweeps in reverse. */
+int orc_scan_generic(int op, int64_t n, const double* const* x, double* const* y);
+int orc_scan_generic_vjp(int op, int64_t n, const double* const* x, const double* const* y_bar,
+                         double* const* x_bar);
+
 #ifdef __cplusplus
 }
 #endif

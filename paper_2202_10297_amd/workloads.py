@@ -155,3 +155,13 @@ def gop(op: str, n: int, dtype="f64", seed: int = 0, general: bool = False):
     else:
         raise ValueError(f"unknown operator {op}")
     return xs, yb
+
+
+def gop_scan(op: str, n: int, dtype="f64", seed: int = 0, general: bool = False):
+    """(components, y_bar) for an inclusive scan with a general operator:
+    the components as in gop(); y_bar is a list of K arrays ~ N(0, 1), one
+    output adjoint per element and component."""
+    xs, _ = gop(op, n, dtype, seed, general)
+    g = rng(seed + 7777)
+    dt = _dt(dtype)
+    return xs, [g.standard_normal(n).astype(dt) for _ in xs]

@@ -1,5 +1,6 @@
-"""Pins for the oracle's reduce with a general associative operator
-(Sec. 5.1.1, general rule) and its VJP.
+"""Pins for the oracle's reduce (Sec. 5.1.1, general rule) and inclusive scan
+(Sec. 5.2, Jacobian generalisation) with a general associative operator, and
+their VJPs.
 
 The oracle folds x_0 (.) ... (.) x_{n-1} on a tape; these pins check it
 against things other than itself: library routines (logsumexp, softmax,
@@ -152,3 +153,86 @@ def test_sampled_adjoints_match_the_full_sweep(orc, op):
     got = orc.reduce_generic_vjp_at(op, xs, yb, idx)
     ref = np.stack([f[idx] for f in full], axis=1)
     assert rel_l2(got, ref) <= 1e-13
+
+
+# ------------------------------------------------- inclusive scan, general operator
+def _matscan(xs):
+    out, acc = [], np.eye(2)
+    for m in _mats(xs):
+        acc = acc @ m
+        out.append(acc.reshape(-1))
+    return np.array(out).T  # K x n
+
+
+@pytest.mark.parametrize("n", [1, 9, 500])
+def test_scan_logaddexp_is_logaddexp_accumulate(orc, n):
+    (x,), _ = workloads.gop_scan("logaddexp", n, seed=n)
+    if n > 3:
+        x[2] = -np.inf
+    (y,) = orc.scan_generic("logaddexp", [x])
+    assert rel_l2(y, np.logaddexp.accumulate(x)) <= 1e-14
+
+
+def test_scan_logaddexp_vjp_closed_form(orc):
+    # y_i = log sum_{j<=i} e^{x_j}, so x_bar_j = sum_{i>=j} y_bar_i e^{x_j - y_i}
+    n = 200
+    (x,), (yb,) = workloads.gop_scan("logaddexp", n, seed=3)
+    x[7] = -np.inf
+    y = np.logaddexp.accumulate(x)
+    ref = np.array([np.sum(yb[j:] * np.exp(x[j] - y[j:])) for j in range(n)])
+    (got,) = orc.scan_generic_vjp("logaddexp", [x], [yb])
+    assert rel_l2(got, ref) <= 1e-13
+    assert got[7] == 0.0
+
+
+def test_scan_logaddexp_vjp_finite_differences(orc):
+    (x,), (yb,) = workloads.gop_scan("logaddexp", 6, seed=4)
+    (got,) = orc.scan_generic_vjp("logaddexp", [x], [yb])
+    (ref,) = fd_grad(lambda x_: float(np.dot(yb, np.logaddexp.accumulate(x_))), [x])
+    assert rel_l2(got, ref) <= 1e-8
+
+
+def test_scan_linrec_matches_the_pinned_scan(orc):
+    n = 300
+    (a, b), (ya, yb) = workloads.gop_scan("linrec", n, seed=6)
+    A, B = orc.scan_generic("linrec", [a, b])
+    RA, RB = orc.linrec_scan(a, b)
+    assert rel_l2([A, B], [RA, RB]) <= 1e-15
+    got = orc.scan_generic_vjp("linrec", [a, b], [ya, yb])
+    assert rel_l2(got, list(orc.linrec_scan_vjp(a, b, ya, yb))) <= 1e-14
+
+
+@pytest.mark.parametrize("general", [False, True])
+def test_scan_mat2_is_cumulative_matrix_product(orc, general):
+    xs, _ = workloads.gop_scan("mat2", 30, seed=2, general=general)
+    ys = orc.scan_generic("mat2", xs)
+    assert rel_l2(ys, list(_matscan(xs))) <= 1e-14
+
+
+def test_scan_mat2_vjp_finite_differences(orc):
+    xs, ybs = workloads.gop_scan("mat2", 5, seed=12, general=True)
+    got = orc.scan_generic_vjp("mat2", xs, ybs)
+
+    def L(*comp):
+        return float(np.sum(_matscan(list(comp)) * np.array(ybs)))
+
+    assert rel_l2(got, fd_grad(L, xs)) <= 1e-8
+
+
+@pytest.mark.parametrize("general", [False, True])
+def test_scan_mat2_vjp_multilinear_identity(orc, general):
+    # Y_i is linear in each of X_0..X_i, so sum_j <X_bar_j, X_j> = sum_i (i+1) <Y_bar_i, Y_i>
+    n = 10 if general else 80
+    xs, ybs = workloads.gop_scan("mat2", n, seed=15, general=general)
+    got = orc.scan_generic_vjp("mat2", xs, ybs)
+    lhs = sum(float(np.dot(g, x)) for g, x in zip(got, xs))
+    Y = _matscan(xs)
+    rhs = float(np.sum((np.arange(n) + 1) * np.sum(np.array(ybs) * Y, axis=0)))
+    assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(rhs))
+
+
+def test_scan_single_element(orc):
+    for op in ("logaddexp", "linrec", "mat2"):
+        xs, ybs = workloads.gop_scan(op, 1, seed=1)
+        got = orc.scan_generic_vjp(op, xs, ybs)
+        assert np.allclose([g[0] for g in got], [y[0] for y in ybs], rtol=1e-15, atol=0), op
