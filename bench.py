@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 23, help="elements per instance for the CPU oracle")
-    ap.add_argument("--skip", default="", help="comma list of extra workloads to skip: reduce_map,reduce_generic,scan,gmm,batch,serve")
+    ap.add_argument("--skip", default="", help="comma list of extra workloads to skip: reduce_map,reduce_generic,scan_generic,scan,gmm,batch,serve")
     ap.add_argument("--only", default="",
                     help="run just this one extra workload (for profiling) and print its JSON instead of the "
                          "benchmark line")
@@ -219,7 +219,8 @@ def main():
     dev = torch.device("cuda:0")
     L = capi.lib()
     if args.only:
-        fns = {"reduce_map": bench_reduce_map, "reduce_generic": bench_reduce_generic, "scan": bench_scan,
+        fns = {"reduce_map": bench_reduce_map, "reduce_generic": bench_reduce_generic,
+               "scan_generic": bench_scan_generic, "scan": bench_scan,
                "gmm": bench_gmm, "batch": bench_batch, "serve": bench_serve}
         print(json.dumps({args.only: fns[args.only](args)}))
         return
@@ -380,7 +381,8 @@ def main():
     torch.cuda.empty_cache()
     extra = {}
     for name, fn in (("reduce_map", bench_reduce_map), ("reduce_generic", bench_reduce_generic),
-                     ("scan", bench_scan), ("gmm", bench_gmm), ("batch", bench_batch), ("serve", bench_serve)):
+                     ("scan_generic", bench_scan_generic), ("scan", bench_scan), ("gmm", bench_gmm),
+                     ("batch", bench_batch), ("serve", bench_serve)):
         if name in args.skip:
             continue
         try:
@@ -641,6 +643,57 @@ def bench_reduce_generic(args):
                     "primal_ms": round(tpc, 4), "vjp_ms": round(tvc, 4),
                     "grad_over_primal": round((tpc + tvc) / tpc, 3),
                     "vjp_hbm_frac": round(2 * comp / (tvc * 1e-3) / 1e9 / HBM_PEAK_GBPS, 3)}}
+            del xs, xb, yb, ck
+            torch.cuda.empty_cache()
+    return res
+
+
+def _gop_inputs(op, n, dt, g):
+    import torch
+
+    if op == "logaddexp":
+        return [torch.randn(n, dtype=dt, device="cuda", generator=g)]
+    if op == "linrec":
+        return [torch.rand(n, dtype=dt, device="cuda", generator=g) * 0.5 + 0.5,
+                torch.randn(n, dtype=dt, device="cuda", generator=g)]
+    # rotations, each composed with diag(1, -1) with probability 1/2
+    th = (torch.rand(n, dtype=dt, device="cuda", generator=g) * 2 - 1) * 3.141592653589793
+    f = torch.where(torch.rand(n, device="cuda", generator=g) < 0.5, -1.0, 1.0).to(dt)
+    c, s_ = torch.cos(th), torch.sin(th)
+    return [c, -s_ * f, s_, c * f]
+
+
+def bench_scan_generic(args):
+    """Inclusive scan with a general operator and its VJP by the d x d
+    Jacobian rule (Sec. 5.2) at n = 2^26, with the per-tile checkpoint.
+    Algorithmic bytes: the primal reads x and writes y (2 n K per element
+    size), the VJP reads x and y_bar and writes x_bar (3 n K).  Moved: x is
+    read twice by the primal (tile folds, then the scan) and x and y_bar twice
+    by the VJP (lin_o tile folds, then the adjoints): 3 n K and 5 n K."""
+    import torch
+
+    from paper_2202_10297_amd import ops
+
+    n = 1 << 26
+    res = {}
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    for op, K in (("logaddexp", 1), ("linrec", 2), ("mat2", 4)):
+        for dt, tname, es in ((torch.float32, "f32", 4), (torch.float64, "f64", 8)):
+            xs = _gop_inputs(op, n, dt, g)
+            yb = [torch.randn(n, dtype=dt, device="cuda", generator=g) for _ in range(K)]
+            xb = [torch.empty_like(x) for x in xs]
+            _, ck = ops.scan_generic(op, xs)
+            tp = _events_ms(lambda: ops.scan_generic(op, xs), 5)
+            tv = _events_ms(lambda: ops.scan_generic_vjp(op, xs, yb, x_bar=xb, ckpt=ck), 5)
+            comp = n * K * es
+            res[f"{op}_{tname}"] = {
+                "primal_ms": round(tp, 4), "vjp_ms": round(tv, 4), "grad_over_primal": round((tp + tv) / tp, 3),
+                "primal_hbm_frac": round(2 * comp / (tp * 1e-3) / 1e9 / HBM_PEAK_GBPS, 3),
+                "primal_hbm_frac_moved": round(3 * comp / (tp * 1e-3) / 1e9 / HBM_PEAK_GBPS, 3),
+                "vjp_hbm_frac": round(3 * comp / (tv * 1e-3) / 1e9 / HBM_PEAK_GBPS, 3),
+                "vjp_hbm_frac_moved": round(5 * comp / (tv * 1e-3) / 1e9 / HBM_PEAK_GBPS, 3),
+                "vjp_elems_per_s": round(n / (tv * 1e-3), 1)}
             del xs, xb, yb, ck
             torch.cuda.empty_cache()
     return res

@@ -278,6 +278,41 @@ pvjp_status pvjp_reduce_generic_vjp(pvjp_gop op, pvjp_dtype dtype, const void* c
                                     int accumulate, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* Inclusive scan with a general associative operator (Sec. 5.2 and its      */
+/* Jacobian generalisation): y_i = x_0 (.) ... (.) x_i, same operators and    */
+/* layout as the general reduce.  The VJP is the reversed scan of lin_o over  */
+/* (d-vector, d x d matrix) pairs (y_bar_i, J_left(i)^T), with                */
+/* J_left(i) = d(y_i (.) x_{i+1})/dy_i, followed by x_bar_i (+)=              */
+/* J_right(i)^T r_i with J_right(i) = d(y_{i-1} (.) x_i)/dx_i; d = K and the  */
+/* Jacobians are formed as explicit d x d matrices.  Primal values are        */
+/* recomputed per tile from the checkpoint, never read back.                  */
+/* ------------------------------------------------------------------------ */
+
+/* Workspace bytes (device memory owned by the caller, 256-byte aligned, no
+ * initialisation needed): per tile (2048 FP32 / 1024 FP64 elements for
+ * LOGADDEXP, 1024 for LINREC, 512 for MAT2) two 32-byte states and two
+ * 160-byte lin_o states, and as much again per group of 64 tiles. */
+size_t pvjp_scan_generic_ws_bytes(pvjp_gop op, pvjp_dtype dtype, int64_t n);
+/* Bytes of the per-tile checkpoint: 32 per tile (the fold of everything
+ * before the tile). */
+size_t pvjp_scan_generic_ckpt_bytes(pvjp_gop op, pvjp_dtype dtype, int64_t n);
+/* x, y: host arrays of K device pointers to n elements each.  ckpt (device,
+ * nullable, 16-byte aligned): receives the per-tile checkpoint.  FP32 LINREC
+ * and MAT2 scans are formed in FP64 and rounded once per output. */
+pvjp_status pvjp_scan_generic(pvjp_gop op, pvjp_dtype dtype, const void* const* x, int64_t n,
+                              void* const* y, void* ckpt, void* ws, size_t ws_bytes, void* stream);
+/* y_bar, x_bar: host arrays of K device pointers to n elements each; x_bar
+ * is overwritten (accumulate = 0) or added to.  ckpt: NULL (the tile
+ * prefixes are recomputed from x first) or the checkpoint pvjp_scan_generic
+ * wrote for this x, op, dtype and n.  Passes: lin_o tile folds (x and y_bar
+ * read), group folds, one block scanning the groups backwards, per-tile
+ * suffixes, then per tile the adjoints (x and y_bar read, x_bar written).
+ * LOGADDEXP: elements equal to -inf get adjoint 0. */
+pvjp_status pvjp_scan_generic_vjp(pvjp_gop op, pvjp_dtype dtype, const void* const* x, int64_t n,
+                                  const void* ckpt, const void* const* y_bar, void* const* x_bar,
+                                  int accumulate, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* Segmented batches: many instances of uneven length stored back to back     */
 /* (segment s = elements [offsets[s], offsets[s+1])), each processed as one   */
 /* segmented operation per launch.  This generalises the rule of Sec. 5.2     */

@@ -52,7 +52,9 @@ _SIGS = {
     "orc_reduce_generic_vjp": [_I, _L, _P, _P, _P],
     "orc_reduce_generic_vjp_at": [_I, _L, _P, _P, _L, _P, _P],
     "orc_scan_generic": [_I, _L, _P, _P],
+    "orc_scan_generic_from": [_I, _L, _P, _P, _P],
     "orc_scan_generic_vjp": [_I, _L, _P, _P, _P],
+    "orc_scan_generic_vjp_from": [_I, _L, _P, _P, _P, _P],
 }
 
 
@@ -288,22 +290,26 @@ def _arrays(K, n):
     return out, (ctypes.c_void_p * K)(*[o.ctypes.data for o in out])
 
 
-def scan_generic(op, xs):
-    """Inclusive scan y_i = xs_0 (.) ... (.) xs_i: a list of K arrays."""
+def scan_generic(op, xs, init=None):
+    """Inclusive scan y_i = init (.) xs_0 (.) ... (.) xs_i (init None: the
+    neutral element): a list of K arrays."""
     xs, ptrs, n, K = _components(op, xs)
     ys, yptr = _arrays(K, n)
-    _check(lib().orc_scan_generic(_gop(op), n, ptrs, yptr), "scan_generic")
+    ini = None if init is None else _f64(init).reshape(K)
+    _check(lib().orc_scan_generic_from(_gop(op), n, _p(ini), ptrs, yptr), "scan_generic")
     return ys
 
 
-def scan_generic_vjp(op, xs, y_bar):
+def scan_generic_vjp(op, xs, y_bar, init=None):
     """Adjoints of every input element given the adjoints of every output
-    (y_bar: list of K arrays)."""
+    (y_bar: list of K arrays).  init: the state the fold starts from (K
+    values; None: the neutral element)."""
     xs, ptrs, n, K = _components(op, xs)
     yb = [_f64(y) for y in y_bar]
     if len(yb) != K or any(y.size != n for y in yb):
         raise ValueError("y_bar must be K arrays of n")
     ybp = (ctypes.c_void_p * K)(*[y.ctypes.data for y in yb])
     out, optr = _arrays(K, n)
-    _check(lib().orc_scan_generic_vjp(_gop(op), n, ptrs, ybp, optr), "scan_generic_vjp")
+    ini = None if init is None else _f64(init).reshape(K)
+    _check(lib().orc_scan_generic_vjp_from(_gop(op), n, _p(ini), ptrs, ybp, optr), "scan_generic_vjp")
     return out

@@ -950,6 +950,10 @@ int orc_reduce_generic_vjp_at(int op, int64_t n, const double* const* x, const d
 /* ------------------------------------------------------------------------ */
 
 int orc_scan_generic(int op, int64_t n, const double* const* x, double* const* y) {
+    return orc_scan_generic_from(op, n, NULL, x, y);
+}
+
+int orc_scan_generic_from(int op, int64_t n, const double* init, const double* const* x, double* const* y) {
     if (!gop_args_ok(op, n, x)) return -1;
     int K = orc_gop_components(op);
     if (n > 0) {
@@ -959,6 +963,8 @@ int orc_scan_generic(int op, int64_t n, const double* const* x, double* const* y
     }
     double acc[4], xi[4];
     gop_neutral(op, acc);
+    if (init)
+        for (int c = 0; c < K; ++c) acc[c] = init[c];
     for (int64_t i = 0; i < n; ++i) {
         for (int c = 0; c < K; ++c) xi[c] = x[c][i];
         gop_comb(op, acc, xi, acc);
@@ -969,6 +975,11 @@ int orc_scan_generic(int op, int64_t n, const double* const* x, double* const* y
 
 int orc_scan_generic_vjp(int op, int64_t n, const double* const* x, const double* const* y_bar,
                          double* const* x_bar) {
+    return orc_scan_generic_vjp_from(op, n, NULL, x, y_bar, x_bar);
+}
+
+int orc_scan_generic_vjp_from(int op, int64_t n, const double* init, const double* const* x,
+                              const double* const* y_bar, double* const* x_bar) {
     if (!gop_args_ok(op, n, x)) return -1;
     int K = orc_gop_components(op);
     if (n == 0) return 0;
@@ -986,6 +997,8 @@ int orc_scan_generic_vjp(int op, int64_t n, const double* const* x, const double
     }
     double e[4];
     gop_neutral(op, e);
+    if (init)
+        for (int c = 0; c < K; ++c) e[c] = init[c];
     int64_t acc[4];
     for (int c = 0; c < K; ++c) acc[c] = leaf(t, e[c]); /* constants */
     for (int64_t i = 0; i < n; ++i) {

@@ -118,8 +118,16 @@ int orc_reduce_generic_vjp_at(int op, int64_t n, const double* const* x, const d
  * K arrays of n.  The VJP records the fold on the tape, seeds every y_i with
  * y_bar_i and sweeps in reverse. */
 int orc_scan_generic(int op, int64_t n, const double* const* x, double* const* y);
+/* The same started from the state init (K values; NULL: neutral). */
+int orc_scan_generic_from(int op, int64_t n, const double* init, const double* const* x, double* const* y);
 int orc_scan_generic_vjp(int op, int64_t n, const double* const* x, const double* const* y_bar,
                          double* const* x_bar);
+/* The same with the fold started from the constant state init (K values;
+ * NULL: the neutral element): y_i = init (.) x_0 (.) ... (.) x_i.  With init
+ * the fold of the elements before a window, this gives the exact adjoints of
+ * the window's elements for the window's output adjoints. */
+int orc_scan_generic_vjp_from(int op, int64_t n, const double* init, const double* const* x,
+                              const double* const* y_bar, double* const* x_bar);
 
 #ifdef __cplusplus
 }

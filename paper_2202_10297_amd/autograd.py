@@ -74,6 +74,26 @@ class ReduceGeneric(torch.autograd.Function):
         return (None, *ops.reduce_generic_vjp(ctx.op, xs, yb, ckpt=ck))
 
 
+class ScanGeneric(torch.autograd.Function):
+    """Inclusive scan with a general operator (Sec. 5.2): K component tensors
+    in, K out.  Saved: the inputs and the per-tile prefix checkpoint; the
+    backward recomputes the primal per tile."""
+
+    @staticmethod
+    def forward(ctx, op, *xs):
+        xs = [x.contiguous() for x in xs]
+        ys, ck = ops.scan_generic(op, xs, ckpt=True)
+        ctx.op = op
+        ctx.save_for_backward(ck, *xs)
+        return tuple(ys)
+
+    @staticmethod
+    def backward(ctx, *gys):
+        ck, *xs = ctx.saved_tensors
+        yb = [torch.zeros_like(x) if g is None else g.contiguous() for g, x in zip(gys, xs)]
+        return (None, *ops.scan_generic_vjp(ctx.op, xs, yb, ckpt=ck))
+
+
 class ReduceByIndex(torch.autograd.Function):
     """hs = reduce_by_index(op) over bins inds[i] of vs[i], m bins."""
 
@@ -157,6 +177,10 @@ def reduce(x, op="add"):
 
 def reduce_generic(op, *xs):
     return ReduceGeneric.apply(op, *xs)
+
+
+def scan_generic(op, *xs):
+    return ScanGeneric.apply(op, *xs)
 
 
 def reduce_by_index(vs, inds, m, op="add"):

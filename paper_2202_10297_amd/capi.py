@@ -53,6 +53,10 @@ SIGNATURES = {
     "pvjp_reduce_generic_ckpt_bytes": (_Z, [_I, _I, _L]),
     "pvjp_reduce_generic": (_I, [_I, _I, _P, _L, _P, _P, _P, _Z, _P]),
     "pvjp_reduce_generic_vjp": (_I, [_I, _I, _P, _L, _P, _P, _P, _I, _P, _Z, _P]),
+    "pvjp_scan_generic_ws_bytes": (_Z, [_I, _I, _L]),
+    "pvjp_scan_generic_ckpt_bytes": (_Z, [_I, _I, _L]),
+    "pvjp_scan_generic": (_I, [_I, _I, _P, _L, _P, _P, _P, _Z, _P]),
+    "pvjp_scan_generic_vjp": (_I, [_I, _I, _P, _L, _P, _P, _P, _I, _P, _Z, _P]),
     "pvjp_seg_ws_bytes": (_Z, [_L, _L, _I]),
     "pvjp_seg_prepare": (_I, [_P, _L, _I, _P, _Z, _P]),
     "pvjp_seg_linrec_scan": (_I, [_I, _P, _P, _L, _L, _I, _P, _P, _P, _P, _Z, _P]),

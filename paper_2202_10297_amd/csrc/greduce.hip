@@ -105,6 +105,15 @@ struct GLogAddExp : GShfl<T, 2> {
         const S y = comb(la, r);
         out[0] = lae_div(yb[0] * lae_exp(a.c[0] - y.c[0]), y.c[1]);
     }
+    // Scan Jacobians (value y = m + log s).  cT = d(y (.) xn)/dy = e^y / (e^y +
+    // e^xn) = s / (s + e^(xn - m)), 0 where y = -inf.
+    __device__ static __forceinline__ void jlT(const S& y, const T (&xn)[1], T (&cT)[1][1]) {
+        cT[0][0] = y.c[1] == T(0) ? T(0) : lae_div(y.c[1], y.c[1] + lae_exp(xn[0] - y.c[0]));
+    }
+    // out = (d(yp (.) x)/dx)^T r = r e^(x - y) with y = yp (.) x; 0 where x = -inf.
+    __device__ static __forceinline__ void jrT(const S&, const T (&x)[1], const S& y, const T (&r)[1], T (&out)[1]) {
+        out[0] = x[0] == -(T)INFINITY ? T(0) : r[0] * lae_div(lae_exp(x[0] - y.c[0]), y.c[1]);
+    }
 };
 
 template <class T>
@@ -120,6 +129,14 @@ struct GLinRec : GShfl<T, 2> {
         // y = (r.a x.a l.a, r.a (x.a l.b + x.b) + r.b)
         out[0] = r.c[0] * (yb[0] * l.c[0] + yb[1] * l.c[1]);
         out[1] = r.c[0] * yb[1];
+    }
+    // Scan Jacobians: d(y (.) xn)/dy = a' I; d(yp (.) x)/dx = [[A, 0], [B, 1]].
+    __device__ static __forceinline__ void jlT(const S&, const T (&xn)[2], T (&cT)[2][2]) {
+        cT[0][0] = xn[0], cT[0][1] = T(0), cT[1][0] = T(0), cT[1][1] = xn[0];
+    }
+    __device__ static __forceinline__ void jrT(const S& yp, const T (&)[2], const S&, const T (&r)[2], T (&out)[2]) {
+        out[0] = yp.c[0] * r[0] + yp.c[1] * r[1];
+        out[1] = r[1];
     }
 };
 
@@ -146,6 +163,21 @@ struct GMat2 : GShfl<T, 4> {
         out[2] = l.c[1] * m00 + l.c[3] * m10;
         out[3] = l.c[1] * m01 + l.c[3] * m11;
     }
+    // Scan Jacobians on row-major 4-vectors.  Y' = Y X: dY'[r][c]/dY[r][k] =
+    // X[k][c], so cT[2r+k][2r+c] = X[k][c] (zero across rows); and
+    // (dY'/dX)^T R = Yp^T R.
+    __device__ static __forceinline__ void jlT(const S&, const T (&xn)[4], T (&cT)[4][4]) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) cT[p][q] = (p >> 1) == (q >> 1) ? xn[2 * (p & 1) + (q & 1)] : T(0);
+    }
+    __device__ static __forceinline__ void jrT(const S& yp, const T (&)[4], const S&, const T (&r)[4], T (&out)[4]) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) out[2 * k + c] = yp.c[k] * r[c] + yp.c[2 + k] * r[2 + c];
+    }
 };
 
 // The same operator with its operands exchanged: a scan in reversed index
@@ -155,6 +187,66 @@ template <class Op>
 struct Flip : Op {
     using S = typename Op::S;
     __device__ static __forceinline__ S comb(S x, S y) { return Op::comb(y, x); }
+};
+
+// lin_o of Sec. 5.2 with a d-vector and a general d x d matrix: the affine
+// map r -> v + c r; (v1,c1) then (v2,c2) gives (v2 + c2 v1, c2 c1), neutral
+// (0, I).  The reversed scan of the VJP folds the elements (y_bar_i,
+// J_left(i)^T) from the last index down.
+template <class A, int D>
+struct LinG {
+    struct S {
+        A v[D];
+        A c[D][D];
+    };
+    __device__ static __forceinline__ S id() {
+        S r;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            r.v[i] = A(0);
+#pragma unroll
+            for (int j = 0; j < D; ++j) r.c[i][j] = i == j ? A(1) : A(0);
+        }
+        return r;
+    }
+    __device__ static __forceinline__ S comb(const S& x, const S& y) {
+        S r;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            A v = y.v[i];
+#pragma unroll
+            for (int j = 0; j < D; ++j) v += y.c[i][j] * x.v[j];
+            r.v[i] = v;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                A c = A(0);
+#pragma unroll
+                for (int j = 0; j < D; ++j) c += y.c[i][j] * x.c[j][k];
+                r.c[i][k] = c;
+            }
+        }
+        return r;
+    }
+    template <class F>
+    __device__ static __forceinline__ S map(const S& v, F f) {
+        S r;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            r.v[i] = f(v.v[i]);
+#pragma unroll
+            for (int j = 0; j < D; ++j) r.c[i][j] = f(v.c[i][j]);
+        }
+        return r;
+    }
+    __device__ static __forceinline__ S up(S v, int d) {
+        return map(v, [d](A a) { return shfl_up1(a, d); });
+    }
+    __device__ static __forceinline__ S down(S v, int d) {
+        return map(v, [d](A a) { return shfl_down1(a, d); });
+    }
+    __device__ static __forceinline__ S idx(S v, int s) {
+        return map(v, [s](A a) { return shfl_idx1(a, s); });
+    }
 };
 
 template <class T>
@@ -182,12 +274,13 @@ constexpr int gr_tile() {
 // A thread's IPT consecutive elements of one component; `cnt` of them exist.
 template <class T, int IPT, bool VEC>
 __device__ __forceinline__ void gr_load(const T* __restrict__ p, int cnt, T (&v)[IPT]) {
-    if (VEC && cnt == IPT) {
-        constexpr int NV = IPT * (int)sizeof(T) / 16;
+    constexpr bool WHOLE = (IPT * sizeof(T)) % 16 == 0;  // the run is whole 16-byte pieces
+    if (VEC && WHOLE && cnt == IPT) {
+        constexpr int NV = WHOLE ? IPT * (int)sizeof(T) / 16 : 1;
         uint4 w[NV];
 #pragma unroll
         for (int j = 0; j < NV; ++j) w[j] = reinterpret_cast<const uint4*>(p)[j];
-        __builtin_memcpy(v, w, sizeof(w));
+        __builtin_memcpy(v, w, sizeof(v));
     } else {
 #pragma unroll
         for (int k = 0; k < IPT; ++k) v[k] = (k < cnt) ? p[k] : T(0);
@@ -196,10 +289,11 @@ __device__ __forceinline__ void gr_load(const T* __restrict__ p, int cnt, T (&v)
 
 template <class T, int IPT, bool VEC>
 __device__ __forceinline__ void gr_store(T* __restrict__ p, int cnt, const T (&v)[IPT]) {
-    if (VEC && cnt == IPT) {
-        constexpr int NV = IPT * (int)sizeof(T) / 16;
+    constexpr bool WHOLE = (IPT * sizeof(T)) % 16 == 0;
+    if (VEC && WHOLE && cnt == IPT) {
+        constexpr int NV = WHOLE ? IPT * (int)sizeof(T) / 16 : 1;
         uint4 w[NV];
-        __builtin_memcpy(w, v, sizeof(w));
+        __builtin_memcpy(w, v, sizeof(v));
 #pragma unroll
         for (int j = 0; j < NV; ++j) reinterpret_cast<uint4*>(p)[j] = w[j];
     } else {
@@ -225,14 +319,13 @@ __device__ __forceinline__ int gr_cnt(int64_t n, int64_t base) {
     return left <= 0 ? 0 : (left >= IPT ? IPT : (int)left);
 }
 
-// Pass 1: agg[t] = fold of tile t in index order.
-template <class Op, class T, bool VEC>
+// Pass 1: agg[t] = fold of tile t (kGrBlock * IPT elements) in index order.
+template <class Op, class T, bool VEC, int IPT = gr_ipt<Op, T>()>
 __global__ __launch_bounds__(kGrBlock) void gred_tile_agg_kernel(GPtrs<T> x, int64_t n,
                                                                  typename Op::S* __restrict__ agg) {
     using S = typename Op::S;
-    constexpr int IPT = gr_ipt<Op, T>();
     __shared__ S wtot[kGrBlock / kWave];
-    const int64_t base = (int64_t)blockIdx.x * gr_tile<Op, T>() + (int64_t)threadIdx.x * IPT;
+    const int64_t base = (int64_t)blockIdx.x * (kGrBlock * IPT) + (int64_t)threadIdx.x * IPT;
     const int cnt = gr_cnt<IPT>(n, base);
     T v[Op::K][IPT];
 #pragma unroll
@@ -376,6 +469,229 @@ __global__ __launch_bounds__(kGrBlock) void gred_vjp_kernel(GPtrs<T> x, int64_t 
 #pragma unroll
         for (int c = 0; c < K; ++c) out[c][k] = (T)o[c];
         l = la;
+    }
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        if (ACC) {
+            T old[IPT];
+            gr_load<T, IPT, VEC>(xbar.p[c] + base, cnt, old);
+#pragma unroll
+            for (int k = 0; k < IPT; ++k) out[c][k] += old[k];
+        }
+        gr_store<T, IPT, VEC>(xbar.p[c] + base, cnt, out[c]);
+    }
+}
+
+// ====================================================================
+// Inclusive scan with a general operator and its VJP (Sec. 5.2 with the
+// Jacobian generalisation): y_i = x_0 (.) ... (.) x_i.  With
+// J_left(i) = d(y_i (.) x_{i+1})/dy_i and J_right(i) = d(y_{i-1} (.) x_i)/dx_i
+// the return sweep is the reversed scan r_i = y_bar_i + J_left(i)^T r_{i+1}
+// (lin_o over (d-vector, d x d matrix)), then x_bar_i = J_right(i)^T r_i.
+// Primal values are not read back: every VJP pass recomputes them per tile
+// from the per-tile prefix checkpoint.
+//
+// Items per thread: at most 32 bytes of each input component and 64 bytes
+// of inputs in the arithmetic type (the per-element states and Jacobians
+// live in registers).
+template <class Op, class T>
+constexpr int gs_ipt() {
+    return (32 / (int)sizeof(T)) < (64 / (Op::K * (int)sizeof(typename Op::Acc)))
+               ? 32 / (int)sizeof(T)
+               : 64 / (Op::K * (int)sizeof(typename Op::Acc));
+}
+template <class Op, class T>
+constexpr int gs_tile() {
+    return kGrBlock * gs_ipt<Op, T>();
+}
+
+// A thread's run of IPT elements starting at `base` (cnt of them exist):
+// the elements in the arithmetic type, the element right after the run (xn,
+// if it exists), the state before the run (sp: the tile prefix folded with
+// the block scan of the runs) and the inclusive states ys[k].
+template <class Op, class T, int IPT, bool VEC>
+__device__ __forceinline__ void gs_run_states(const GPtrs<T>& x, int64_t n, int64_t base, int cnt,
+                                              const typename Op::S& tpre, typename Op::S* wtot,
+                                              typename Op::Acc (&xa)[Op::K][IPT], typename Op::Acc (&xn)[Op::K],
+                                              typename Op::S (&ys)[IPT], typename Op::S& sp) {
+    using S = typename Op::S;
+    using A = typename Op::Acc;
+    constexpr int K = Op::K;
+    T v[K][IPT];
+#pragma unroll
+    for (int c = 0; c < K; ++c) gr_load<T, IPT, VEC>(x.p[c] + base, cnt, v[c]);
+    const bool edge = base + IPT < n;
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        xn[c] = edge ? (A)x.p[c][base + IPT] : A(0);
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) xa[c][k] = (A)v[c][k];
+    }
+    S run = Op::id();
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+        A e[K];
+#pragma unroll
+        for (int c = 0; c < K; ++c) e[c] = xa[c][k];
+        if (k < cnt) run = Op::comb(run, Op::elem(e));
+    }
+    S tot;
+    const S tp = block_exclusive_scan<Op, kGrBlock, false>(run, tot, wtot);
+    sp = Op::comb(tpre, tp);
+    S st = sp;
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+        A e[K];
+#pragma unroll
+        for (int c = 0; c < K; ++c) e[c] = xa[c][k];
+        if (k < cnt) st = Op::comb(st, Op::elem(e));
+        ys[k] = st;
+    }
+}
+
+// The lin_o element of position k of a run: (y_bar_k, J_left(k)^T), with a
+// zero matrix at the last index of the array (nothing follows it).
+template <class Op, int IPT>
+__device__ __forceinline__ void gs_jl(const typename Op::S (&ys)[IPT], const typename Op::Acc (&xa)[Op::K][IPT],
+                                      const typename Op::Acc (&xn)[Op::K], int k, bool has_next,
+                                      typename Op::Acc (&cT)[Op::K][Op::K]) {
+    using A = typename Op::Acc;
+    constexpr int K = Op::K;
+    if (!has_next) {
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+#pragma unroll
+            for (int j = 0; j < K; ++j) cT[i][j] = A(0);
+        return;
+    }
+    A nx[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) nx[c] = k + 1 < IPT ? xa[c][k + 1 < IPT ? k + 1 : 0] : xn[c];
+    Op::jlT(ys[k], nx, cT);
+}
+
+// Fold of a run's lin_o elements in reversed index order.
+template <class Op, class T, int IPT>
+__device__ __forceinline__ typename LinG<typename Op::Acc, Op::K>::S gs_run_lin(
+    const typename Op::S (&ys)[IPT], const typename Op::Acc (&xa)[Op::K][IPT], const typename Op::Acc (&xn)[Op::K],
+    const T (&yb)[Op::K][IPT], int64_t n, int64_t base, int cnt) {
+    using A = typename Op::Acc;
+    using LG = LinG<A, Op::K>;
+    typename LG::S run = LG::id();
+#pragma unroll
+    for (int k = IPT - 1; k >= 0; --k) {
+        if (k < cnt) {
+            typename LG::S e;
+            gs_jl<Op, IPT>(ys, xa, xn, k, base + k + 1 < n, e.c);
+#pragma unroll
+            for (int c = 0; c < Op::K; ++c) e.v[c] = (A)yb[c][k];
+            run = LG::comb(run, e);
+        }
+    }
+    return run;
+}
+
+// Primal: y_i for every element of tile t from its prefix pre[t].
+template <class Op, class T, int IPT, bool VEC>
+__global__ __launch_bounds__(kGrBlock) void gscan_fwd_kernel(GPtrs<T> x, int64_t n,
+                                                             const typename Op::S* __restrict__ pre, GOut<T> y) {
+    using S = typename Op::S;
+    using A = typename Op::Acc;
+    constexpr int K = Op::K;
+    __shared__ S wtot[kGrBlock / kWave];
+    const int64_t base = (int64_t)blockIdx.x * (kGrBlock * IPT) + (int64_t)threadIdx.x * IPT;
+    const int cnt = gr_cnt<IPT>(n, base);
+    A xa[K][IPT], xn[K];
+    S ys[IPT], sp;
+    gs_run_states<Op, T, IPT, VEC>(x, n, base, cnt, pre[blockIdx.x], wtot, xa, xn, ys, sp);
+    T out[K][IPT];
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+        A val[K];
+        Op::value(ys[k], val);
+#pragma unroll
+        for (int c = 0; c < K; ++c) out[c][k] = (T)val[c];
+    }
+#pragma unroll
+    for (int c = 0; c < K; ++c) gr_store<T, IPT, VEC>(y.p[c] + base, cnt, out[c]);
+}
+
+// VJP pass 1: the lin_o fold of every tile, in reversed index order.
+template <class Op, class T, int IPT, bool VEC>
+__global__ __launch_bounds__(kGrBlock) void gscan_vjp_agg_kernel(
+    GPtrs<T> x, int64_t n, const typename Op::S* __restrict__ pre, GPtrs<T> ybar,
+    typename LinG<typename Op::Acc, Op::K>::S* __restrict__ lagg) {
+    using S = typename Op::S;
+    using A = typename Op::Acc;
+    using LG = LinG<A, Op::K>;
+    constexpr int K = Op::K;
+    __shared__ S wtot[kGrBlock / kWave];
+    __shared__ typename LG::S ltot[kGrBlock / kWave];
+    const int64_t base = (int64_t)blockIdx.x * (kGrBlock * IPT) + (int64_t)threadIdx.x * IPT;
+    const int cnt = gr_cnt<IPT>(n, base);
+    T yb[K][IPT];
+#pragma unroll
+    for (int c = 0; c < K; ++c) gr_load<T, IPT, VEC>(ybar.p[c] + base, cnt, yb[c]);
+    A xa[K][IPT], xn[K];
+    S ys[IPT], sp;
+    gs_run_states<Op, T, IPT, VEC>(x, n, base, cnt, pre[blockIdx.x], wtot, xa, xn, ys, sp);
+    const typename LG::S run = gs_run_lin<Op, T, IPT>(ys, xa, xn, yb, n, base, cnt);
+    typename LG::S tot;
+    block_exclusive_scan<LG, kGrBlock, true>(run, tot, ltot);
+    if (threadIdx.x == 0) lagg[blockIdx.x] = tot;
+}
+
+// VJP pass 3: lsuf[t] is the lin_o fold of every tile after t; with the
+// reversed block scan of the runs it gives the adjoint r after each run,
+// then r_k = y_bar_k + J_left(k)^T r_{k+1} walks the run down and
+// x_bar_k (+)= J_right(k)^T r_k.
+template <class Op, class T, int IPT, bool VEC, bool ACC>
+__global__ __launch_bounds__(kGrBlock) void gscan_vjp_kernel(
+    GPtrs<T> x, int64_t n, const typename Op::S* __restrict__ pre, GPtrs<T> ybar,
+    const typename LinG<typename Op::Acc, Op::K>::S* __restrict__ lsuf, GOut<T> xbar) {
+    using S = typename Op::S;
+    using A = typename Op::Acc;
+    using LG = LinG<A, Op::K>;
+    constexpr int K = Op::K;
+    __shared__ S wtot[kGrBlock / kWave];
+    __shared__ typename LG::S ltot[kGrBlock / kWave];
+    const int64_t base = (int64_t)blockIdx.x * (kGrBlock * IPT) + (int64_t)threadIdx.x * IPT;
+    const int cnt = gr_cnt<IPT>(n, base);
+    T yb[K][IPT];
+#pragma unroll
+    for (int c = 0; c < K; ++c) gr_load<T, IPT, VEC>(ybar.p[c] + base, cnt, yb[c]);
+    A xa[K][IPT], xn[K];
+    S ys[IPT], sp;
+    gs_run_states<Op, T, IPT, VEC>(x, n, base, cnt, pre[blockIdx.x], wtot, xa, xn, ys, sp);
+    const typename LG::S run = gs_run_lin<Op, T, IPT>(ys, xa, xn, yb, n, base, cnt);
+    typename LG::S tot;
+    const typename LG::S ex = block_exclusive_scan<LG, kGrBlock, true>(run, tot, ltot);
+    const typename LG::S after = LG::comb(lsuf[blockIdx.x], ex);
+    A r[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) r[c] = after.v[c];
+    T out[K][IPT];
+#pragma unroll
+    for (int k = IPT - 1; k >= 0; --k) {
+        A cT[K][K];
+        gs_jl<Op, IPT>(ys, xa, xn, k, base + k + 1 < n, cT);
+        A rn[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            A v = (A)yb[i][k];
+#pragma unroll
+            for (int j = 0; j < K; ++j) v += cT[i][j] * r[j];
+            rn[i] = v;
+        }
+        A xk[K], o[K];
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            r[c] = k < cnt ? rn[c] : r[c];
+            xk[c] = xa[c][k];
+        }
+        Op::jrT(k == 0 ? sp : ys[k > 0 ? k - 1 : 0], xk, ys[k], r, o);
+#pragma unroll
+        for (int c = 0; c < K; ++c) out[c][k] = (T)o[c];
     }
 #pragma unroll
     for (int c = 0; c < K; ++c) {
@@ -540,6 +856,187 @@ static void dispatch_vjp(const void* const* x, int K, int64_t n, const void* ckp
     launch_vjp<GOpFor<OpT, T>, T>(xp, n, ckpt, yp, xo, acc, ws, vec, st);
 }
 
+// ------------------------------------------------------------- scan host
+constexpr size_t kLinSlot = 160;  // bytes per lin_o state (d = 4 in FP64: 4 + 16 values)
+
+// Workspace: [tile folds | tile prefixes | group folds | group prefixes]
+// of the operator's states (32-byte slots), then [tile lin_o folds | tile
+// lin_o suffixes | group lin_o folds | group lin_o prefixes] (160-byte
+// slots), every array 256-byte aligned.  The tile prefixes are the
+// checkpoint when the caller keeps one.
+struct GsPlan {
+    int64_t nt, ng;
+    size_t t32, g32, tl, gl;
+};
+
+template <class Op, class T>
+static GsPlan gs_plan(int64_t n) {
+    GsPlan p;
+    p.nt = ceil_div(n, gs_tile<Op, T>());
+    p.ng = ceil_div(p.nt, kAggGroup);
+    const size_t nt = (size_t)(p.nt > 0 ? p.nt : 1), ng = (size_t)(p.ng > 0 ? p.ng : 1);
+    p.t32 = align_up(nt * kGrSlot, 256);
+    p.g32 = align_up(ng * kGrSlot, 256);
+    p.tl = align_up(nt * kLinSlot, 256);
+    p.gl = align_up(ng * kLinSlot, 256);
+    return p;
+}
+
+template <class Op, class T>
+static size_t gs_ws(int64_t n) {
+    const GsPlan p = gs_plan<Op, T>(n);
+    return 2 * p.t32 + 2 * p.g32 + 2 * p.tl + 2 * p.gl;
+}
+
+static char* gs_at(void* ws, const GsPlan& p, int which) {
+    const size_t offs[8] = {0,
+                            p.t32,
+                            2 * p.t32,
+                            2 * p.t32 + p.g32,
+                            2 * p.t32 + 2 * p.g32,
+                            2 * p.t32 + 2 * p.g32 + p.tl,
+                            2 * p.t32 + 2 * p.g32 + 2 * p.tl,
+                            2 * p.t32 + 2 * p.g32 + 2 * p.tl + p.gl};
+    return reinterpret_cast<char*>(ws) + offs[which];
+}
+
+// pre[t] = fold of every element before tile t (the forward reduce-then-scan
+// up to the tile prefixes).
+template <class Op, class T>
+static void gs_prefixes(const GPtrs<T>& x, int64_t n, const GsPlan& p, typename Op::S* pre, void* ws, bool vec,
+                        hipStream_t st) {
+    using S = typename Op::S;
+    constexpr int IPT = gs_ipt<Op, T>();
+    if (p.nt == 0) return;
+    S* agg = reinterpret_cast<S*>(gs_at(ws, p, 0));
+    S* gagg = reinterpret_cast<S*>(gs_at(ws, p, 2));
+    S* gpre = reinterpret_cast<S*>(gs_at(ws, p, 3));
+    if (vec)
+        hipLaunchKernelGGL((gred_tile_agg_kernel<Op, T, true, IPT>), dim3((unsigned)p.nt), dim3(kGrBlock), 0, st, x,
+                           n, agg);
+    else
+        hipLaunchKernelGGL((gred_tile_agg_kernel<Op, T, false, IPT>), dim3((unsigned)p.nt), dim3(kGrBlock), 0, st, x,
+                           n, agg);
+    const unsigned gb = (unsigned)ceil_div(p.ng, kGroupBlock / kWave);
+    hipLaunchKernelGGL((group_fold_kernel<Op, false>), dim3(gb), dim3(kGroupBlock), 0, st, (const S*)agg, p.nt, p.ng,
+                       gagg);
+    hipLaunchKernelGGL((agg_scan_kernel<Op, false>), dim3(1), dim3(kAggBlock), 0, st, (const S*)gagg, p.ng, gpre);
+    hipLaunchKernelGGL((group_prefix_kernel<Op, false>), dim3(gb), dim3(kGroupBlock), 0, st, (const S*)agg, p.nt,
+                       p.ng, (const S*)gpre, pre);
+}
+
+template <class Op, class T>
+static void launch_scan(const GPtrs<T>& x, int64_t n, const GOut<T>& y, void* ckpt, void* ws, bool vec,
+                        hipStream_t st) {
+    using S = typename Op::S;
+    constexpr int IPT = gs_ipt<Op, T>();
+    const GsPlan p = gs_plan<Op, T>(n);
+    if (p.nt == 0) return;
+    S* pre = ckpt ? reinterpret_cast<S*>(ckpt) : reinterpret_cast<S*>(gs_at(ws, p, 1));
+    gs_prefixes<Op, T>(x, n, p, pre, ws, vec, st);
+    if (vec)
+        hipLaunchKernelGGL((gscan_fwd_kernel<Op, T, IPT, true>), dim3((unsigned)p.nt), dim3(kGrBlock), 0, st, x, n,
+                           (const S*)pre, y);
+    else
+        hipLaunchKernelGGL((gscan_fwd_kernel<Op, T, IPT, false>), dim3((unsigned)p.nt), dim3(kGrBlock), 0, st, x, n,
+                           (const S*)pre, y);
+}
+
+template <class Op, class T>
+static void launch_scan_vjp(const GPtrs<T>& x, int64_t n, const void* ckpt, const GPtrs<T>& yb, const GOut<T>& xb,
+                            int acc, void* ws, bool vec, hipStream_t st) {
+    using S = typename Op::S;
+    using LG = LinG<typename Op::Acc, Op::K>;
+    using LS = typename LG::S;
+    static_assert(sizeof(LS) <= kLinSlot, "lin_o slot too small");
+    constexpr int IPT = gs_ipt<Op, T>();
+    const GsPlan p = gs_plan<Op, T>(n);
+    if (p.nt == 0) return;
+    const S* pre = reinterpret_cast<const S*>(ckpt);
+    if (!pre) {
+        S* w = reinterpret_cast<S*>(gs_at(ws, p, 1));
+        gs_prefixes<Op, T>(x, n, p, w, ws, vec, st);
+        pre = w;
+    }
+    LS* lagg = reinterpret_cast<LS*>(gs_at(ws, p, 4));
+    LS* lsuf = reinterpret_cast<LS*>(gs_at(ws, p, 5));
+    LS* lgagg = reinterpret_cast<LS*>(gs_at(ws, p, 6));
+    LS* lgpre = reinterpret_cast<LS*>(gs_at(ws, p, 7));
+    const dim3 gt((unsigned)p.nt), b(kGrBlock);
+    if (vec)
+        hipLaunchKernelGGL((gscan_vjp_agg_kernel<Op, T, IPT, true>), gt, b, 0, st, x, n, pre, yb, lagg);
+    else
+        hipLaunchKernelGGL((gscan_vjp_agg_kernel<Op, T, IPT, false>), gt, b, 0, st, x, n, pre, yb, lagg);
+    const unsigned gb = (unsigned)ceil_div(p.ng, kGroupBlock / kWave);
+    hipLaunchKernelGGL((group_fold_kernel<LG, true>), dim3(gb), dim3(kGroupBlock), 0, st, (const LS*)lagg, p.nt, p.ng,
+                       lgagg);
+    hipLaunchKernelGGL((agg_scan_kernel<LG, true>), dim3(1), dim3(kAggBlock), 0, st, (const LS*)lgagg, p.ng, lgpre);
+    hipLaunchKernelGGL((group_prefix_kernel<LG, true>), dim3(gb), dim3(kGroupBlock), 0, st, (const LS*)lagg, p.nt,
+                       p.ng, (const LS*)lgpre, lsuf);
+    const LS* cs = lsuf;
+    if (vec) {
+        if (acc)
+            hipLaunchKernelGGL((gscan_vjp_kernel<Op, T, IPT, true, true>), gt, b, 0, st, x, n, pre, yb, cs, xb);
+        else
+            hipLaunchKernelGGL((gscan_vjp_kernel<Op, T, IPT, true, false>), gt, b, 0, st, x, n, pre, yb, cs, xb);
+    } else {
+        if (acc)
+            hipLaunchKernelGGL((gscan_vjp_kernel<Op, T, IPT, false, true>), gt, b, 0, st, x, n, pre, yb, cs, xb);
+        else
+            hipLaunchKernelGGL((gscan_vjp_kernel<Op, T, IPT, false, false>), gt, b, 0, st, x, n, pre, yb, cs, xb);
+    }
+}
+
+template <template <class> class OpT, class T>
+static void dispatch_scan(const void* const* x, int K, int64_t n, void* const* y, void* ckpt, void* ws,
+                          hipStream_t st) {
+    GPtrs<T> xp{};
+    GOut<T> yp{};
+    bool vec = true;
+    for (int c = 0; c < K; ++c) {
+        xp.p[c] = (const T*)x[c];
+        yp.p[c] = (T*)y[c];
+        vec = vec && aligned(x[c], 16) && aligned(y[c], 16);
+    }
+    launch_scan<GOpFor<OpT, T>, T>(xp, n, yp, ckpt, ws, vec, st);
+}
+
+template <template <class> class OpT, class T>
+static void dispatch_scan_vjp(const void* const* x, int K, int64_t n, const void* ckpt, const void* const* yb,
+                              void* const* xb, int acc, void* ws, hipStream_t st) {
+    GPtrs<T> xp{}, yp{};
+    GOut<T> xo{};
+    bool vec = true;
+    for (int c = 0; c < K; ++c) {
+        xp.p[c] = (const T*)x[c];
+        yp.p[c] = (const T*)yb[c];
+        xo.p[c] = (T*)xb[c];
+        vec = vec && aligned(x[c], 16) && aligned(yb[c], 16) && aligned(xb[c], 16);
+    }
+    launch_scan_vjp<GOpFor<OpT, T>, T>(xp, n, ckpt, yp, xo, acc, ws, vec, st);
+}
+
+// Size queries by operator and dtype.
+template <template <template <class> class, class> class Q>
+static size_t gop_query(pvjp_gop op, pvjp_dtype dtype, int64_t n) {
+    if (dtype == PVJP_F64) {
+        if (op == PVJP_GOP_LOGADDEXP) return Q<GLogAddExp, double>::get(n);
+        if (op == PVJP_GOP_LINREC) return Q<GLinRec, double>::get(n);
+        return Q<GMat2, double>::get(n);
+    }
+    if (op == PVJP_GOP_LOGADDEXP) return Q<GLogAddExp, float>::get(n);
+    if (op == PVJP_GOP_LINREC) return Q<GLinRec, float>::get(n);
+    return Q<GMat2, float>::get(n);
+}
+template <template <class> class OpT, class T>
+struct GsWsQ {
+    static size_t get(int64_t n) { return gs_ws<GOpFor<OpT, T>, T>(n); }
+};
+template <template <class> class OpT, class T>
+struct GsCkQ {
+    static size_t get(int64_t n) { return (size_t)gs_plan<GOpFor<OpT, T>, T>(n).nt * kGrSlot; }
+};
+
 }  // namespace pvjp
 
 using namespace pvjp;
@@ -647,5 +1144,100 @@ extern "C" pvjp_status pvjp_reduce_generic_vjp(pvjp_gop op, pvjp_dtype dtype, co
         else dispatch_vjp<GMat2, float>(x, K, n, ckpt, y_bar, x_bar, accumulate, ws, st);
     }
     PVJP_LAUNCHED("pvjp_reduce_generic_vjp");
+    return PVJP_OK;
+}
+
+// ------------------------------------------------------------ scan entry points
+extern "C" size_t pvjp_scan_generic_ws_bytes(pvjp_gop op, pvjp_dtype dtype, int64_t n) {
+    if (gop_components(op) == 0 || !valid_dtype(dtype) || n < 0) return 0;
+    return gop_query<GsWsQ>(op, dtype, n);
+}
+
+extern "C" size_t pvjp_scan_generic_ckpt_bytes(pvjp_gop op, pvjp_dtype dtype, int64_t n) {
+    if (gop_components(op) == 0 || !valid_dtype(dtype) || n < 0) return 0;
+    return gop_query<GsCkQ>(op, dtype, n);
+}
+
+static pvjp_status check_scan(const char* name, pvjp_gop op, pvjp_dtype dtype, const void* const* x, int64_t n,
+                              const void* ckpt, void* ws, size_t ws_bytes) {
+    const int K = gop_components(op);
+    PVJP_REQUIRE(K > 0, "%s: unknown operator %d", name, (int)op);
+    PVJP_REQUIRE(valid_dtype(dtype), "%s: unknown dtype %d", name, (int)dtype);
+    PVJP_REQUIRE(n >= 0, "%s: negative n", name);
+    PVJP_REQUIRE(n < ((int64_t)1 << 40), "%s: n too large", name);
+    PVJP_REQUIRE(ws != nullptr && aligned(ws, 256), "%s: workspace must be non-NULL and 256-byte aligned", name);
+    PVJP_REQUIRE(ckpt == nullptr || aligned(ckpt, 16), "%s: ckpt must be 16-byte aligned", name);
+    if (ws_bytes < pvjp_scan_generic_ws_bytes(op, dtype, n)) {
+        set_error("%s: workspace of %zu bytes, need %zu", name, ws_bytes, pvjp_scan_generic_ws_bytes(op, dtype, n));
+        return PVJP_ENOMEM;
+    }
+    if (n > 0) {
+        PVJP_REQUIRE(x != nullptr, "%s: x is NULL", name);
+        for (int c = 0; c < K; ++c) {
+            PVJP_REQUIRE(x[c] != nullptr, "%s: component %d of x is NULL", name, c);
+            PVJP_REQUIRE(aligned(x[c], dsize(dtype)), "%s: component %d of x is misaligned", name, c);
+        }
+    }
+    return PVJP_OK;
+}
+
+extern "C" pvjp_status pvjp_scan_generic(pvjp_gop op, pvjp_dtype dtype, const void* const* x, int64_t n,
+                                         void* const* y, void* ckpt, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    const pvjp_status s = check_scan("pvjp_scan_generic", op, dtype, x, n, ckpt, ws, ws_bytes);
+    if (s != PVJP_OK) return s;
+    if (n == 0) return PVJP_OK;
+    const int K = gop_components(op);
+    PVJP_REQUIRE(y != nullptr, "pvjp_scan_generic: y is NULL");
+    for (int c = 0; c < K; ++c) {
+        PVJP_REQUIRE(y[c] != nullptr, "pvjp_scan_generic: component %d of y is NULL", c);
+        PVJP_REQUIRE(aligned(y[c], dsize(dtype)), "pvjp_scan_generic: component %d of y is misaligned", c);
+    }
+    const hipStream_t st = as_stream(stream);
+    if (dtype == PVJP_F64) {
+        if (op == PVJP_GOP_LOGADDEXP) dispatch_scan<GLogAddExp, double>(x, K, n, y, ckpt, ws, st);
+        else if (op == PVJP_GOP_LINREC) dispatch_scan<GLinRec, double>(x, K, n, y, ckpt, ws, st);
+        else dispatch_scan<GMat2, double>(x, K, n, y, ckpt, ws, st);
+    } else {
+        if (op == PVJP_GOP_LOGADDEXP) dispatch_scan<GLogAddExp, float>(x, K, n, y, ckpt, ws, st);
+        else if (op == PVJP_GOP_LINREC) dispatch_scan<GLinRec, float>(x, K, n, y, ckpt, ws, st);
+        else dispatch_scan<GMat2, float>(x, K, n, y, ckpt, ws, st);
+    }
+    PVJP_LAUNCHED("pvjp_scan_generic");
+    return PVJP_OK;
+}
+
+extern "C" pvjp_status pvjp_scan_generic_vjp(pvjp_gop op, pvjp_dtype dtype, const void* const* x, int64_t n,
+                                             const void* ckpt, const void* const* y_bar, void* const* x_bar,
+                                             int accumulate, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    const pvjp_status s = check_scan("pvjp_scan_generic_vjp", op, dtype, x, n, ckpt, ws, ws_bytes);
+    if (s != PVJP_OK) return s;
+    if (n == 0) return PVJP_OK;
+    const int K = gop_components(op);
+    PVJP_REQUIRE(y_bar != nullptr && x_bar != nullptr, "pvjp_scan_generic_vjp: y_bar and x_bar must be non-NULL");
+    for (int c = 0; c < K; ++c) {
+        PVJP_REQUIRE(y_bar[c] != nullptr, "pvjp_scan_generic_vjp: component %d of y_bar is NULL", c);
+        PVJP_REQUIRE(x_bar[c] != nullptr, "pvjp_scan_generic_vjp: component %d of x_bar is NULL", c);
+        PVJP_REQUIRE(aligned(y_bar[c], dsize(dtype)) && aligned(x_bar[c], dsize(dtype)),
+                     "pvjp_scan_generic_vjp: component %d of y_bar or x_bar is misaligned", c);
+    }
+    const hipStream_t st = as_stream(stream);
+    if (dtype == PVJP_F64) {
+        if (op == PVJP_GOP_LOGADDEXP)
+            dispatch_scan_vjp<GLogAddExp, double>(x, K, n, ckpt, y_bar, x_bar, accumulate, ws, st);
+        else if (op == PVJP_GOP_LINREC)
+            dispatch_scan_vjp<GLinRec, double>(x, K, n, ckpt, y_bar, x_bar, accumulate, ws, st);
+        else
+            dispatch_scan_vjp<GMat2, double>(x, K, n, ckpt, y_bar, x_bar, accumulate, ws, st);
+    } else {
+        if (op == PVJP_GOP_LOGADDEXP)
+            dispatch_scan_vjp<GLogAddExp, float>(x, K, n, ckpt, y_bar, x_bar, accumulate, ws, st);
+        else if (op == PVJP_GOP_LINREC)
+            dispatch_scan_vjp<GLinRec, float>(x, K, n, ckpt, y_bar, x_bar, accumulate, ws, st);
+        else
+            dispatch_scan_vjp<GMat2, float>(x, K, n, ckpt, y_bar, x_bar, accumulate, ws, st);
+    }
+    PVJP_LAUNCHED("pvjp_scan_generic_vjp");
     return PVJP_OK;
 }

@@ -329,67 +329,9 @@ __global__ __launch_bounds__(kScanBlock) void linrec_vjp_tile_agg_kernel(const T
     if (threadIdx.x == 0) agg[tile] = total;
 }
 
-// (2) exclusive scan of aggregates by one block, in scan order:
-// increasing tile index, or decreasing with REV.  Thread t folds a
-// contiguous run of the scan order, the runs are scanned across the block,
-// then each thread writes its run's prefixes.
-constexpr int kAggBlock = 1024;
-
-template <class Op, bool REV>
-__global__ __launch_bounds__(kAggBlock) void linrec_agg_scan_kernel(const typename Op::S* __restrict__ agg,
-                                                                    int64_t ntiles,
-                                                                    typename Op::S* __restrict__ pre) {
-    using S = typename Op::S;
-    __shared__ S wtot[kAggBlock / kWave];
-    const int64_t per = (ntiles + kAggBlock - 1) / kAggBlock;
-    const int64_t v0 = (int64_t)threadIdx.x * per;
-    const int64_t v1 = (v0 + per < ntiles) ? v0 + per : ntiles;
-    auto at = [&](int64_t v) { return REV ? ntiles - 1 - v : v; };
-    S run = Op::id();
-    for (int64_t v = v0; v < v1; ++v) run = Op::comb(run, agg[at(v)]);
-    S total;
-    S ex = block_exclusive_scan<Op, kAggBlock, false>(run, total, wtot);
-    for (int64_t v = v0; v < v1; ++v) {
-        pre[at(v)] = ex;
-        ex = Op::comb(ex, agg[at(v)]);
-    }
-}
-
-// (2) with many tiles the one-block scan above would walk tens of thousands
-// of aggregates; tiles are therefore taken in groups of 64, one wave per
-// group: (2a) fold each group in scan order, (2b) scan the group folds with
-// linrec_agg_scan_kernel, (2c) give every tile its group's prefix folded with
-// the group's tiles before it in scan order.
-constexpr int kTileGroup = kWave;
-
-template <class Op, bool REV>
-__global__ __launch_bounds__(kScanBlock) void linrec_group_fold_kernel(const typename Op::S* __restrict__ agg,
-                                                                       int64_t nt, int64_t ng,
-                                                                       typename Op::S* __restrict__ gagg) {
-    using S = typename Op::S;
-    const int64_t g = (int64_t)blockIdx.x * (kScanBlock / kWave) + threadIdx.x / kWave;
-    if (g >= ng) return;  // whole waves leave together
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t t = g * kTileGroup + lane;
-    const S own = t < nt ? agg[t] : Op::id();
-    const S inc = Op::comb(wave_exclusive_scan<Op, REV>(own), own);
-    if (lane == (REV ? 0 : kWave - 1)) gagg[g] = inc;  // the last lane in scan order
-}
-
-template <class Op, bool REV>
-__global__ __launch_bounds__(kScanBlock) void linrec_group_prefix_kernel(const typename Op::S* __restrict__ agg,
-                                                                         int64_t nt, int64_t ng,
-                                                                         const typename Op::S* __restrict__ gpre,
-                                                                         typename Op::S* __restrict__ pre) {
-    using S = typename Op::S;
-    const int64_t g = (int64_t)blockIdx.x * (kScanBlock / kWave) + threadIdx.x / kWave;
-    if (g >= ng) return;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t t = g * kTileGroup + lane;
-    const S own = t < nt ? agg[t] : Op::id();
-    const S ex = wave_exclusive_scan<Op, REV>(own);
-    if (t < nt) pre[t] = Op::comb(gpre[g], ex);
-}
+// (2) the aggregates are scanned in scan order (increasing tile index, or
+// decreasing for the VJP) by agg_scan_kernel / group_fold_kernel /
+// group_prefix_kernel of prims.h.
 
 // ------------------------------------------------------------------ host
 // Inputs of more tiles than this take the three-pass form.
@@ -400,7 +342,7 @@ constexpr size_t kAggSlot = 32;  // bytes per tile for an aggregate or a prefix 
 // group folds | group prefixes]: the three-pass form never touches the
 // lookback states or the header.
 static size_t group_bytes(int64_t ntiles) {
-    return align_up((size_t)ceil_div(ntiles, kTileGroup) * kAggSlot, 256);
+    return align_up((size_t)ceil_div(ntiles, kAggGroup) * kAggSlot, 256);
 }
 
 template <class S>
@@ -432,13 +374,13 @@ template <class Op, bool REV>
 static void scan_aggregates(const typename Op::S* agg, int64_t nt, typename Op::S* pre, void* ws,
                             hipStream_t st) {
     using S = typename Op::S;
-    const int64_t ng = ceil_div(nt, kTileGroup);
+    const int64_t ng = ceil_div(nt, kAggGroup);
     S* gagg = group_array<S>(ws, nt, 0);
     S* gpre = group_array<S>(ws, nt, 1);
-    const unsigned gb = (unsigned)ceil_div(ng, kScanBlock / kWave);
-    hipLaunchKernelGGL((linrec_group_fold_kernel<Op, REV>), dim3(gb), dim3(kScanBlock), 0, st, agg, nt, ng, gagg);
-    hipLaunchKernelGGL((linrec_agg_scan_kernel<Op, REV>), dim3(1), dim3(kAggBlock), 0, st, (const S*)gagg, ng, gpre);
-    hipLaunchKernelGGL((linrec_group_prefix_kernel<Op, REV>), dim3(gb), dim3(kScanBlock), 0, st, agg, nt, ng,
+    const unsigned gb = (unsigned)ceil_div(ng, kGroupBlock / kWave);
+    hipLaunchKernelGGL((group_fold_kernel<Op, REV>), dim3(gb), dim3(kGroupBlock), 0, st, agg, nt, ng, gagg);
+    hipLaunchKernelGGL((agg_scan_kernel<Op, REV>), dim3(1), dim3(kAggBlock), 0, st, (const S*)gagg, ng, gpre);
+    hipLaunchKernelGGL((group_prefix_kernel<Op, REV>), dim3(gb), dim3(kGroupBlock), 0, st, agg, nt, ng,
                        (const S*)gpre, pre);
 }
 

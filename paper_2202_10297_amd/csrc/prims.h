@@ -150,6 +150,66 @@ __device__ __forceinline__ typename Op::S wave_exclusive_scan(typename Op::S v) 
     return ex;
 }
 
+// --------------------------------------------- scans of tile aggregates
+// A reduce-then-scan over many tiles scans the tiles' aggregates in scan
+// order (increasing tile index, or decreasing with REV).  One block walking
+// tens of thousands of aggregates is slow (100-200 us at 32K), so tiles are
+// taken in groups of 64, one wave per group: group_fold_kernel folds each
+// group, agg_scan_kernel scans the group folds, group_prefix_kernel gives
+// every tile its group's prefix folded with the group's tiles before it.
+constexpr int kAggBlock = 1024;
+constexpr int kAggGroup = kWave;
+constexpr int kGroupBlock = 256;
+
+// pre[i] = exclusive fold of agg in scan order.  Thread t folds a contiguous
+// run of the scan order, the runs are scanned across the block, then each
+// thread writes its run's prefixes.
+template <class Op, bool REV>
+__global__ __launch_bounds__(kAggBlock) void agg_scan_kernel(const typename Op::S* __restrict__ agg, int64_t cnt,
+                                                             typename Op::S* __restrict__ pre) {
+    using S = typename Op::S;
+    __shared__ S wtot[kAggBlock / kWave];
+    const int64_t per = (cnt + kAggBlock - 1) / kAggBlock;
+    const int64_t v0 = (int64_t)threadIdx.x * per;
+    const int64_t v1 = (v0 + per < cnt) ? v0 + per : cnt;
+    auto at = [&](int64_t v) { return REV ? cnt - 1 - v : v; };
+    S run = Op::id();
+    for (int64_t v = v0; v < v1; ++v) run = Op::comb(run, agg[at(v)]);
+    S total;
+    S ex = block_exclusive_scan<Op, kAggBlock, false>(run, total, wtot);
+    for (int64_t v = v0; v < v1; ++v) {
+        pre[at(v)] = ex;
+        ex = Op::comb(ex, agg[at(v)]);
+    }
+}
+
+template <class Op, bool REV>
+__global__ __launch_bounds__(kGroupBlock) void group_fold_kernel(const typename Op::S* __restrict__ agg, int64_t nt,
+                                                                 int64_t ng, typename Op::S* __restrict__ gagg) {
+    using S = typename Op::S;
+    const int64_t g = (int64_t)blockIdx.x * (kGroupBlock / kWave) + threadIdx.x / kWave;
+    if (g >= ng) return;  // whole waves leave together
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t t = g * kAggGroup + lane;
+    const S own = t < nt ? agg[t] : Op::id();
+    const S inc = Op::comb(wave_exclusive_scan<Op, REV>(own), own);
+    if (lane == (REV ? 0 : kWave - 1)) gagg[g] = inc;  // the last lane in scan order
+}
+
+template <class Op, bool REV>
+__global__ __launch_bounds__(kGroupBlock) void group_prefix_kernel(const typename Op::S* __restrict__ agg, int64_t nt,
+                                                                   int64_t ng, const typename Op::S* __restrict__ gpre,
+                                                                   typename Op::S* __restrict__ pre) {
+    using S = typename Op::S;
+    const int64_t g = (int64_t)blockIdx.x * (kGroupBlock / kWave) + threadIdx.x / kWave;
+    if (g >= ng) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t t = g * kAggGroup + lane;
+    const S own = t < nt ? agg[t] : Op::id();
+    const S ex = wave_exclusive_scan<Op, REV>(own);
+    if (t < nt) pre[t] = Op::comb(gpre[g], ex);
+}
+
 // ------------------------------------------------------- LDS transposes
 // Padded LDS index: one element of padding per 256 bytes keeps both the
 // striped writes and the blocked reads free of bank conflicts for the

@@ -184,6 +184,42 @@ def reduce_generic_vjp(op, xs, y_bar, x_bar=None, accumulate=False, ckpt=None):
     return x_bar
 
 
+def scan_generic(op, xs, ckpt: bool = True):
+    """Inclusive scan y_i = xs_0 (.) ... (.) xs_i with a general operator
+    (Sec. 5.2); xs is the list of K component tensors.  Returns (ys, ckpt):
+    K tensors and the per-tile checkpoint (uint8 tensor) if asked for."""
+    xs, n, K = _components(op, xs)
+    dt, dev = _dt(xs[0]), xs[0].device
+    ys = [torch.empty_like(x) for x in xs]
+    ck = None
+    if ckpt:
+        ck = torch.empty(max(capi.lib().pvjp_scan_generic_ckpt_bytes(_gop(op), dt, n), 16), dtype=torch.uint8,
+                         device=dev)
+    nb = capi.lib().pvjp_scan_generic_ws_bytes(_gop(op), dt, n)
+    ws = WS.get("scan_generic", nb, dev)
+    capi.call("pvjp_scan_generic", _gop(op), dt, capi.ptr_array([_ptr(x) for x in xs]), n,
+              capi.ptr_array([_ptr(y) for y in ys]), _ptr(ck), _ptr(ws), ws.numel(), _stream(dev))
+    return ys, ck
+
+
+def scan_generic_vjp(op, xs, y_bar, x_bar=None, accumulate=False, ckpt=None):
+    """x_bar (+)= the adjoints of the inputs given the adjoints y_bar of every
+    output (lists of K tensors); ckpt from scan_generic on the same xs, or
+    None (the tile prefixes are recomputed)."""
+    xs, n, K = _components(op, xs)
+    dt, dev = _dt(xs[0]), xs[0].device
+    if x_bar is None:
+        x_bar = [torch.zeros_like(x) if accumulate else torch.empty_like(x) for x in xs]
+    if len(y_bar) != K or len(x_bar) != K:
+        raise ValueError(f"operator {op} takes {K} components")
+    nb = capi.lib().pvjp_scan_generic_ws_bytes(_gop(op), dt, n)
+    ws = WS.get("scan_generic", nb, dev)
+    capi.call("pvjp_scan_generic_vjp", _gop(op), dt, capi.ptr_array([_ptr(x) for x in xs]), n, _ptr(ckpt),
+              capi.ptr_array([_ptr(y) for y in y_bar]), capi.ptr_array([_ptr(x) for x in x_bar]),
+              int(accumulate), _ptr(ws), ws.numel(), _stream(dev))
+    return x_bar
+
+
 # ---------------------------------------------------------- reduce_by_index
 def hist(op, inds: torch.Tensor, vs: torch.Tensor, m: int, counts: bool = False):
     """Returns (hs, aux): aux has "winner" (min/max), "p" and "z" (mul),

@@ -1,0 +1,194 @@
+"""GPU parity of the inclusive scan with a general associative operator and
+its VJP (Sec. 5.2 with the Jacobian generalisation: the reversed lin_o scan
+over (d-vector, d x d matrix) pairs), through the C ABI, against the oracle on
+the same seeded inputs.
+
+Bars: FP64 relative L2 1e-12, FP32 2e-5 against the FP64 oracle on the same
+FP32 inputs; -inf log-add-exp elements get exactly 0.  Sizes span one tile,
+tile boundaries, ragged tails and many 64-tile groups.  At 2^26 elements
+(the size the benchmark times) the last 4096 adjoints are checked against
+the oracle started from the fold of everything before them, and every
+adjoint through an identity that holds at any size.
+"""
+import numpy as np
+import pytest
+
+from _util import TOL_F32, TOL_F64, rel_l2
+from paper_2202_10297_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+OPS = ["logaddexp", "linrec", "mat2"]
+
+
+def tile(op, dtype):
+    if op == "logaddexp":
+        return 2048 if dtype == "f32" else 1024
+    return 1024 if op == "linrec" else 512
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def tol(dtype):
+    return TOL_F64 if dtype == "f64" else TOL_F32
+
+
+@pytest.fixture(scope="module")
+def ops():
+    from paper_2202_10297_amd import capi, ops as o
+
+    capi.lib()
+    return o
+
+
+def inputs(op, n, dtype, seed):
+    xs, ybs = workloads.gop_scan(op, n, dtype, seed=seed)
+    if op == "logaddexp" and n > 3:
+        for i in {0, n // 2, min(tile(op, dtype), n - 1), n - 1}:
+            xs[0][i] = -np.inf
+    return xs, ybs
+
+
+def run(ops, op, xs, ybs, ckpt=True, accumulate=False, base=None):
+    dx = [dev(x) for x in xs]
+    ys, ck = ops.scan_generic(op, dx, ckpt=ckpt)
+    xb = [dev(b) for b in base] if base is not None else None
+    xb = ops.scan_generic_vjp(op, dx, [dev(y) for y in ybs], x_bar=xb, accumulate=accumulate, ckpt=ck)
+    return [host(y) for y in ys], [host(g) for g in xb]
+
+
+def close_outputs(got, ref, bound):
+    """Scan outputs: -inf (a log-add-exp prefix of -inf elements) must match
+    exactly; the rest within a relative L2 bound."""
+    got, ref = [np.asarray(g, dtype=np.float64) for g in got], [np.asarray(r) for r in ref]
+    for g, r in zip(got, ref):
+        m = np.isneginf(r)
+        assert np.array_equal(np.isneginf(g), m)
+    fin = lambda arrs: [np.where(np.isneginf(r), 0.0, a) for a, r in zip(arrs, ref)]
+    return rel_l2(fin(got), fin(ref)) <= bound
+
+
+def sizes(op, dtype):
+    t = tile(op, dtype)
+    return [1, 2, t - 1, t, t + 1, 3 * t + 5, 64 * t + 7, 130 * t + 1]
+
+
+CASES = [(op, d, n) for op in OPS for d in ("f32", "f64") for n in sizes(op, d)]
+
+
+@pytest.mark.parametrize("op,dtype,n", CASES)
+def test_scan_and_vjp(ops, orc, op, dtype, n):
+    xs, ybs = inputs(op, n, dtype, seed=n)
+    ys, xb = run(ops, op, xs, ybs)
+    assert close_outputs(ys, orc.scan_generic(op, xs), 1e-13 if dtype == "f64" else 1e-6)
+    ref = orc.scan_generic_vjp(op, xs, ybs)
+    assert rel_l2(xb, ref) <= tol(dtype)
+    if op == "logaddexp":
+        assert np.all(xb[0][np.isneginf(xs[0])] == 0)
+    # without the checkpoint the prefixes are recomputed: the same bits
+    ys2, xb2 = run(ops, op, xs, ybs, ckpt=False)
+    assert all(np.array_equal(a, b) for a, b in zip(ys + xb, ys2 + xb2))
+
+
+@pytest.mark.parametrize("op", OPS)
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_accumulate(ops, orc, op, dtype):
+    n = 5 * tile(op, dtype) + 33
+    xs, ybs = inputs(op, n, dtype, seed=3)
+    base = [np.full(n, -0.25, dtype=xs[0].dtype) for _ in xs]
+    _, xb = run(ops, op, xs, ybs, accumulate=True, base=base)
+    assert rel_l2([g + 0.25 for g in xb], orc.scan_generic_vjp(op, xs, ybs)) <= 2 * tol(dtype)
+
+
+@pytest.mark.parametrize("op", OPS)
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_unaligned_views(ops, orc, op, dtype):
+    n = 2 * tile(op, dtype) + 77
+    xs, ybs = inputs(op, n + 1, dtype, seed=5)
+    dx = [dev(x)[1:] for x in xs]
+    ys, ck = ops.scan_generic(op, dx)
+    out = [torch.empty(n + 1, dtype=dx[0].dtype, device="cuda")[1:] for _ in xs]
+    ops.scan_generic_vjp(op, dx, [dev(y)[1:] for y in ybs], x_bar=out, ckpt=ck)
+    sub, ybsub = [x[1:] for x in xs], [y[1:] for y in ybs]
+    assert close_outputs([host(y) for y in ys], orc.scan_generic(op, sub), 1e-13 if dtype == "f64" else 1e-6)
+    assert rel_l2([host(o) for o in out], orc.scan_generic_vjp(op, sub, ybsub)) <= tol(dtype)
+
+
+def test_mat2_dense_factors(ops, orc):
+    xs, ybs = workloads.gop_scan("mat2", 700, "f64", seed=13, general=True)
+    ys, xb = run(ops, "mat2", xs, ybs)
+    assert rel_l2(ys, orc.scan_generic("mat2", xs)) <= 1e-12
+    assert rel_l2(xb, orc.scan_generic_vjp("mat2", xs, ybs)) <= TOL_F64
+
+
+def test_linrec_matches_the_specialised_scan(ops, orc):
+    # the same operator through the general d x d rule and through the
+    # scalar-Jacobian kernel of the linear-recurrence scan
+    n = 1024 * 70 + 3
+    (a, b), (ya, yb) = workloads.gop_scan("linrec", n, "f64", seed=2)
+    ys, xb = run(ops, "linrec", [a, b], [ya, yb])
+    A, B, ck = ops.linrec_scan(dev(a), dev(b))
+    ab, bb = ops.linrec_scan_vjp(dev(a), dev(b), dev(ya), dev(yb), ckpt=ck)
+    assert rel_l2(ys, [host(A), host(B)]) <= 1e-14
+    assert rel_l2(xb, [host(ab), host(bb)]) <= 1e-13
+
+
+@pytest.mark.parametrize("op,dtype", [("logaddexp", "f32"), ("linrec", "f64"), ("mat2", "f32")])
+def test_benchmark_size(ops, orc, op, dtype):
+    n, w = 1 << 26, 4096
+    xs, ybs = workloads.gop_scan(op, n, dtype, seed=0)
+    ys, xb = run(ops, op, xs, ybs)
+    # the last w outputs: the oracle's fold started from the state before them
+    init = orc.reduce_generic(op, [x[:n - w] for x in xs])
+    win = [x[n - w:] for x in xs]
+    assert rel_l2([y[n - w:] for y in ys], orc.scan_generic(op, win, init=init)) <= (1e-12 if dtype == "f64" else 1e-5)
+    # the window's adjoints for the window's output adjoints alone
+    ybw = [np.concatenate([np.zeros(n - w, dtype=y.dtype), y[n - w:]]) for y in ybs]
+    _, xbw = run(ops, op, xs, ybw)
+    ref = orc.scan_generic_vjp(op, win, [y[n - w:] for y in ybs], init=init)
+    assert rel_l2([g[n - w:] for g in xbw], ref) <= tol(dtype)
+    # identities over every element
+    if op == "logaddexp":
+        # each output is a log-sum-exp of its prefix: its gradient sums to 1
+        lhs, rhs = np.sum(xb[0], dtype=np.float64), np.sum(ybs[0], dtype=np.float64)
+        assert abs(lhs - rhs) <= 1e-4 * np.sum(np.abs(ybs[0]), dtype=np.float64)
+    elif op == "linrec":
+        # B_i is linear in b: sum_j b_bar_j b_j = sum_i yB_bar_i B_i
+        lhs, rhs = np.dot(xb[1], xs[1]), np.dot(ybs[1], ys[1])
+        assert abs(lhs - rhs) <= 1e-9 * np.abs(ybs[1] * ys[1]).sum()
+    else:
+        # Y_i is linear in each of X_0..X_i: sum_j <X_bar_j, X_j> = sum_i (i+1) <Y_bar_i, Y_i>
+        prods = sum(g.astype(np.float64) * x.astype(np.float64) for g, x in zip(xb, xs))
+        terms = sum(ybs[c].astype(np.float64) * ys[c].astype(np.float64) for c in range(4))
+        ramp = np.arange(1, n + 1, dtype=np.float64)
+        # FP32 rounding of the outputs and adjoints moves either side by far
+        # less than 1e-5 of the adjoint side's magnitude; a wrong Jacobian
+        # moves it by the order of the sums themselves
+        assert abs(prods.sum() - np.dot(ramp, terms)) <= 1e-5 * np.abs(prods).sum()
+
+
+def test_deterministic(ops):
+    xs, ybs = workloads.gop_scan("mat2", 300001, "f32", seed=2)
+    a = run(ops, "mat2", xs, ybs)
+    b = run(ops, "mat2", xs, ybs)
+    assert all(np.array_equal(u, v) for u, v in zip(a[0] + a[1], b[0] + b[1]))
+
+
+def test_autograd(orc):
+    from paper_2202_10297_amd import autograd
+
+    n = 4000
+    xs, ybs = workloads.gop_scan("mat2", n, "f64", seed=8)
+    t = [dev(x).requires_grad_() for x in xs]
+    ys = autograd.scan_generic("mat2", *t)
+    sum((y * dev(g)).sum() for y, g in zip(ys, ybs)).backward()
+    assert rel_l2([host(x.grad) for x in t], orc.scan_generic_vjp("mat2", xs, ybs)) <= TOL_F64

@@ -236,3 +236,17 @@ def test_scan_single_element(orc):
         xs, ybs = workloads.gop_scan(op, 1, seed=1)
         got = orc.scan_generic_vjp(op, xs, ybs)
         assert np.allclose([g[0] for g in got], [y[0] for y in ybs], rtol=1e-15, atol=0), op
+
+
+@pytest.mark.parametrize("op", ["logaddexp", "linrec", "mat2"])
+def test_scan_window_from_a_prefix_state(orc, op):
+    # The adjoints of the last w elements for the last w output adjoints do
+    # not depend on the earlier adjoints: a fold started from the state of
+    # the first n - w elements reproduces them.
+    n, w = 400, 150
+    xs, ybs = workloads.gop_scan(op, n, seed=31)
+    ybw = [np.concatenate([np.zeros(n - w), y[n - w:]]) for y in ybs]
+    full = orc.scan_generic_vjp(op, xs, ybw)
+    init = orc.reduce_generic(op, [x[:n - w] for x in xs])
+    tail = orc.scan_generic_vjp(op, [x[n - w:] for x in xs], [y[n - w:] for y in ybs], init=init)
+    assert rel_l2(tail, [f[n - w:] for f in full]) <= 1e-13
