@@ -715,7 +715,8 @@ def copy_bandwidth():
 def bench_gmm(args):
     """GMM N = 10^6, D = 64, K = 200 (FP32, FP64 LSE): objective and gradient.
     Algorithmic flops: forward N K D (D+1) with the triangle of Q_k used,
-    gradient about twice that (recomputation + the contraction of G_k)."""
+    gradient about twice that (recomputation + the contraction of G_k); with
+    the s_ik checkpoint the gradient is one contraction, N K D (D+1)."""
     import torch
 
     from paper_2202_10297_amd import ops, workloads
@@ -726,11 +727,21 @@ def bench_gmm(args):
     tf = _events_ms(lambda: ops.gmm_objective(*P), 5)
     out = tuple(torch.empty_like(t) for t in P[1:])
     tb = _events_ms(lambda: ops.gmm_vjp(*P, lse=lse, out=out), 5)
+    # with the s_ik checkpoint (8 N K bytes): one contraction in the gradient
+    sck = torch.empty((K, N), dtype=torch.float64, device="cuda")
+    _, lse2 = ops.gmm_objective(*P, s_out=sck)
+    tfs = _events_ms(lambda: ops.gmm_objective(*P, s_out=sck), 5)
+    tbs = _events_ms(lambda: ops.gmm_vjp(*P, lse=lse2, s=sck, out=out), 5)
+    del sck
     flop_f = N * K * D * (D + 1)
     return {"objective_ms": round(tf, 3), "gradient_ms": round(tb, 3), "grad_over_primal": round((tf + tb) / tf, 3),
             "objective_TFLOPs": round(flop_f / (tf * 1e-3) / 1e12, 1),
             "gradient_TFLOPs": round(2 * flop_f / (tb * 1e-3) / 1e12, 1),
-            "vjp_points_per_s": round(N / (tb * 1e-3), 1)}
+            "vjp_points_per_s": round(N / (tb * 1e-3), 1),
+            "with_s_ckpt": {"objective_ms": round(tfs, 3), "gradient_ms": round(tbs, 3),
+                            "grad_over_primal": round((tfs + tbs) / tfs, 3),
+                            "gradient_TFLOPs": round(flop_f / (tbs * 1e-3) / 1e12, 1),
+                            "ckpt_bytes": 8 * N * K}}
 
 
 def bench_batch(args):

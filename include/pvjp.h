@@ -367,19 +367,26 @@ pvjp_status pvjp_seg_batch_vjp(pvjp_dtype dtype, const void* a, const void* b, c
 
 size_t pvjp_gmm_ws_bytes(int64_t N, int D, int K);
 /* loglik: device double (output).  lse: device double[N] (nullable output):
- * the per-point LSE_k(s_ik), the checkpoint the reverse sweep reads. */
+ * the per-point LSE_k(s_ik), the checkpoint the reverse sweep reads.
+ * s: device double[K x N] (nullable output, component-major: s[k*N + i]):
+ * every s_ik, an optional second checkpoint (8 N K bytes) that halves the
+ * reverse sweep's contraction work. */
 pvjp_status pvjp_gmm_objective(const float* X, int64_t N, int D, int K, const float* alpha,
                                const float* mu, const float* q, const float* l, double* loglik,
-                               double* lse, void* ws, size_t ws_bytes, void* stream);
+                               double* lse, double* s, void* ws, size_t ws_bytes, void* stream);
 /* Reverse sweep with output adjoint ell_bar: alpha_bar [K], mu_bar and q_bar
  * [K x D], l_bar [K x D(D-1)/2] (FP32 outputs, (+)=).  lse: the checkpoint
  * written by pvjp_gmm_objective for the same inputs (nullable: the forward
- * sweep then runs first into the workspace).  The per-point, per-component
- * weights w_ik = ell_bar * exp(s_ik - LSE_i) are recomputed, not stored. */
+ * sweep then runs first into the workspace).  s (nullable; needs lse): the
+ * s_ik checkpoint of the same call.  Without s the weights w_ik = ell_bar *
+ * exp(s_ik - LSE_i) are recomputed with z_ik = Q_k (x_i - mu_k) and the
+ * sweep contracts G_k = sum_i w_ik z_ik (x_i - mu_k)^T; with s it contracts
+ * S_k = sum_i w_ik (x_i - mu_k)(x_i - mu_k)^T and forms G_k = Q_k S_k. */
 pvjp_status pvjp_gmm_vjp(const float* X, int64_t N, int D, int K, const float* alpha,
                          const float* mu, const float* q, const float* l, double ell_bar,
-                         const double* lse, float* alpha_bar, float* mu_bar, float* q_bar,
-                         float* l_bar, int accumulate, void* ws, size_t ws_bytes, void* stream);
+                         const double* lse, const double* s, float* alpha_bar, float* mu_bar,
+                         float* q_bar, float* l_bar, int accumulate, void* ws, size_t ws_bytes,
+                         void* stream);
 
 #ifdef __cplusplus
 }

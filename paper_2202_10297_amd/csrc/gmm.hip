@@ -218,7 +218,8 @@ __global__ __launch_bounds__(256) void gmm_fwd_kernel(const float* __restrict__ 
                                                       const float* __restrict__ Qf, const float* __restrict__ cvec,
                                                       const double* __restrict__ bias,
                                                       const double* __restrict__ lse_alpha, double* __restrict__ lse,
-                                                      double* parts, GmmHdr* hdr, double* loglik) {
+                                                      double* __restrict__ sck, double* parts, GmmHdr* hdr,
+                                                      double* loglik) {
     using C = Gm<D>;
     __shared__ float Xs[4][32 * D];
     __shared__ double red[4];
@@ -234,11 +235,13 @@ __global__ __launch_bounds__(256) void gmm_fwd_kernel(const float* __restrict__ 
 
     double m = -INFINITY, ssum = 0.0;
     float qa[C::NF], cl[C::RT][16];
+    const bool own = (lane < 32) && (p < N);
     for (int k = 0; k < K; ++k) {
         load_component<D>(Qf, cvec, k, qa, cl);
         f32x16 acc[C::RT];
         const double nrm = tile_znorm<D>(qa, bx, cl, acc);
         const double s = bias[k] - 0.5 * nrm;
+        if (sck && own) sck[(int64_t)k * N + p] = s;  // component-major: 32 points per wave in a row
         if (s > m) {
             ssum = ssum * exp(m - s) + 1.0;
             m = s;
@@ -278,11 +281,17 @@ __global__ __launch_bounds__(256) void gmm_fwd_kernel(const float* __restrict__ 
 }
 
 // ----------------------------------------------------------------- backward
-template <int D>
+// FROM_S: the forward's s_ik checkpoint (sck, K x N) gives w_ik directly, so
+// z is not recomputed: the tile of w (x - mu_k) is formed from X, and the
+// same contraction accumulates S_k = sum_i w_ik y_ik y_ik^T (and u_k =
+// sum_i w_ik y_ik) instead of G_k and v_k; gmm_param_kernel then forms
+// G_k = Q_k S_k and v_k = Q_k u_k.  Half the MFMA work of the recomputing form.
+template <int D, bool FROM_S>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gmm_bwd_kernel(const float* __restrict__ X, int64_t N, int K, int64_t chunk,
                                                       int nch, const float* __restrict__ Qf,
                                                       const float* __restrict__ cvec, const float* __restrict__ mu,
                                                       const double* __restrict__ bias, const double* __restrict__ lse,
+                                                      const double* __restrict__ sck,
                                                       double ell_bar, float* __restrict__ gpart,
                                                       float* __restrict__ vpart, double* __restrict__ wpart) {
     using C = Gm<D>;
@@ -300,8 +309,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
     const int ch = blockIdx.x / K;
     const int h = lane >> 5, j = lane & 31;
 
-    for (int e = threadIdx.x; e < C::NF * 64; e += 256) qs[e] = Qf[(int64_t)k * C::NF * 64 + e];
-    if (threadIdx.x < D) cs[threadIdx.x] = cvec[(int64_t)k * D + threadIdx.x];
+    if (!FROM_S)
+        for (int e = threadIdx.x; e < C::NF * 64; e += 256) qs[e] = Qf[(int64_t)k * C::NF * 64 + e];
+    // cs: c_k for the recomputing form, mu_k for the checkpointed one
+    if (threadIdx.x < D) cs[threadIdx.x] = FROM_S ? mu[(int64_t)k * D + threadIdx.x] : cvec[(int64_t)k * D + threadIdx.x];
     float mub[C::RT];
 #pragma unroll
     for (int ct = 0; ct < C::RT; ++ct) mub[ct] = mu[(int64_t)k * D + 32 * ct + j];
@@ -329,24 +340,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
         wave_lds_sync();
         stage_x<D>(X, N, p0, Xw);
         wave_lds_sync();
-        float bx[C::S];
-#pragma unroll
-        for (int s = 0; s < C::S; ++s) bx[s] = Xw[xs_at<D>(j, 2 * s + h)];
-        f32x16 z[C::RT];
-        // The MFMA phases run at raised wave priority, so that the other wave
-        // on the SIMD issues its loads and FP64 work in their gaps.
-        __builtin_amdgcn_s_setprio(1);
-        const double nrm = tile_znorm_lds<D>(qs, cs, bx, z);
-        __builtin_amdgcn_s_setprio(0);
         const int64_t p = p0 + j;
-        double wd = 0.0;
-        if (p < N) wd = ell_bar * exp((bk - 0.5 * nrm) - lse[p]);
-        const float wf = (float)wd;
-        if (h == 0) wsum += wd;
+        if (FROM_S) {
+            double wd = 0.0;
+            if (p < N) wd = ell_bar * exp(sck[(int64_t)k * N + p] - lse[p]);
+            const float wf = (float)wd;
+            if (h == 0) wsum += wd;
+            // w (x - mu_k): lane (j, h) fills rows [h D/2, (h+1) D/2) of point j
+#pragma unroll 8
+            for (int r = h * (D / 2); r < (h + 1) * (D / 2); ++r)
+                Zw[zs_at(r, j)] = wf * (Xw[xs_at<D>(j, r)] - cs[r]);
+        } else {
+            float bx[C::S];
 #pragma unroll
-        for (int rt = 0; rt < C::RT; ++rt)
+            for (int s = 0; s < C::S; ++s) bx[s] = Xw[xs_at<D>(j, 2 * s + h)];
+            f32x16 z[C::RT];
+            // The MFMA phases run at raised wave priority, so that the other
+            // wave on the SIMD issues its loads and FP64 work in their gaps.
+            __builtin_amdgcn_s_setprio(1);
+            const double nrm = tile_znorm_lds<D>(qs, cs, bx, z);
+            __builtin_amdgcn_s_setprio(0);
+            double wd = 0.0;
+            if (p < N) wd = ell_bar * exp((bk - 0.5 * nrm) - lse[p]);
+            const float wf = (float)wd;
+            if (h == 0) wsum += wd;
 #pragma unroll
-            for (int t = 0; t < 16; ++t) Zw[zs_at(32 * rt + drow(t, lane), j)] = wf * z[rt][t];
+            for (int rt = 0; rt < C::RT; ++rt)
+#pragma unroll
+                for (int t = 0; t < 16; ++t) Zw[zs_at(32 * rt + drow(t, lane), j)] = wf * z[rt][t];
+        }
         wave_lds_sync();
         {
             // The swizzle moves even-odd pairs of points together, so a row is
@@ -427,7 +449,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
 }
 
 // ------------------------------------------------------ reduce + parameters
-template <int D>
+template <int D, bool FROM_S>
 __global__ __launch_bounds__(256) void gmm_param_kernel(int64_t N, int K, int nch, const float* __restrict__ alpha,
                                                         const float* __restrict__ q, const float* __restrict__ l,
                                                         const double* __restrict__ lse_alpha, double ell_bar,
@@ -473,6 +495,29 @@ __global__ __launch_bounds__(256) void gmm_param_kernel(int64_t N, int K, int nc
         Q[r][c] = x;
     }
     __syncthreads();
+    if (FROM_S) {
+        // The partials hold S_k (lower 32x32 blocks, symmetric) and u_k:
+        // mirror S, then G_k = Q_k S_k row by row from the bottom (row r of G
+        // needs rows <= r of S, which are still unchanged) and v_k = Q_k u_k.
+        for (int e = threadIdx.x; e < D * D; e += blockDim.x) {
+            const int r = e / D, c = e % D;
+            if (c > r) G[r][c] = G[c][r];
+        }
+        __syncthreads();
+        for (int r = D - 1; r >= 0; --r) {
+            double gr = 0.0;
+            const int c = threadIdx.x;
+            if (c < D)
+                for (int j2 = 0; j2 <= r; ++j2) gr += (double)Q[r][j2] * G[j2][c];
+            double vr = 0.0;
+            if (threadIdx.x == 0)
+                for (int j2 = 0; j2 <= r; ++j2) vr += (double)Q[r][j2] * v[j2];
+            __syncthreads();
+            if (c < D) G[r][c] = gr;
+            if (threadIdx.x == 0) v[r] = vr;
+            __syncthreads();
+        }
+    }
     const double W = Wk;
     if (threadIdx.x == 0) {
         const double a = W - (double)N * ell_bar * exp((double)alpha[k] - *lse_alpha);
@@ -545,25 +590,36 @@ static void launch_prep(const float* alpha, const float* mu, const float* q, con
 }
 
 template <int D>
-static void launch_fwd(const float* X, int64_t N, int K, char* ws, const GmmLayout& L, double* lse, double* loglik,
-                       hipStream_t st) {
+static void launch_fwd(const float* X, int64_t N, int K, char* ws, const GmmLayout& L, double* lse, double* sck,
+                       double* loglik, hipStream_t st) {
     double* scal = reinterpret_cast<double*>(ws + L.scal + sizeof(GmmHdr));
     hipLaunchKernelGGL(gmm_fwd_kernel<D>, dim3(L.fgrid), dim3(256), 0, st, X, N, K, (const float*)(ws + L.Qf),
-                       (const float*)(ws + L.cvec), (const double*)(ws + L.bias), (const double*)scal, lse,
+                       (const float*)(ws + L.cvec), (const double*)(ws + L.bias), (const double*)scal, lse, sck,
                        (double*)(ws + L.fparts), (GmmHdr*)(ws + L.scal), loglik);
+}
+
+template <int D, bool FROM_S>
+static void launch_bwd_t(const float* X, int64_t N, int K, const float* alpha, const float* mu, const float* q,
+                         const float* l, double ell_bar, const double* lse, const double* sck, float* ab, float* mb,
+                         float* qb, float* lb, int acc, char* ws, const GmmLayout& L, hipStream_t st) {
+    double* scal = reinterpret_cast<double*>(ws + L.scal + sizeof(GmmHdr));
+    hipLaunchKernelGGL((gmm_bwd_kernel<D, FROM_S>), dim3((unsigned)(K * L.nch)), dim3(256), 0, st, X, N, K, L.chunk,
+                       (int)L.nch, (const float*)(ws + L.Qf), (const float*)(ws + L.cvec), mu,
+                       (const double*)(ws + L.bias), lse, sck, ell_bar, (float*)(ws + L.gpart),
+                       (float*)(ws + L.vpart), (double*)(ws + L.wpart));
+    hipLaunchKernelGGL((gmm_param_kernel<D, FROM_S>), dim3(K), dim3(256), 0, st, N, K, (int)L.nch, alpha, q, l,
+                       (const double*)scal, ell_bar, (const float*)(ws + L.gpart), (const float*)(ws + L.vpart),
+                       (const double*)(ws + L.wpart), ab, mb, qb, lb, acc);
 }
 
 template <int D>
 static void launch_bwd(const float* X, int64_t N, int K, const float* alpha, const float* mu, const float* q,
-                       const float* l, double ell_bar, const double* lse, float* ab, float* mb, float* qb, float* lb,
-                       int acc, char* ws, const GmmLayout& L, hipStream_t st) {
-    double* scal = reinterpret_cast<double*>(ws + L.scal + sizeof(GmmHdr));
-    hipLaunchKernelGGL(gmm_bwd_kernel<D>, dim3((unsigned)(K * L.nch)), dim3(256), 0, st, X, N, K, L.chunk, (int)L.nch,
-                       (const float*)(ws + L.Qf), (const float*)(ws + L.cvec), mu, (const double*)(ws + L.bias), lse,
-                       ell_bar, (float*)(ws + L.gpart), (float*)(ws + L.vpart), (double*)(ws + L.wpart));
-    hipLaunchKernelGGL(gmm_param_kernel<D>, dim3(K), dim3(256), 0, st, N, K, (int)L.nch, alpha, q, l,
-                       (const double*)scal, ell_bar, (const float*)(ws + L.gpart), (const float*)(ws + L.vpart),
-                       (const double*)(ws + L.wpart), ab, mb, qb, lb, acc);
+                       const float* l, double ell_bar, const double* lse, const double* sck, float* ab, float* mb,
+                       float* qb, float* lb, int acc, char* ws, const GmmLayout& L, hipStream_t st) {
+    if (sck)
+        launch_bwd_t<D, true>(X, N, K, alpha, mu, q, l, ell_bar, lse, sck, ab, mb, qb, lb, acc, ws, L, st);
+    else
+        launch_bwd_t<D, false>(X, N, K, alpha, mu, q, l, ell_bar, lse, sck, ab, mb, qb, lb, acc, ws, L, st);
 }
 
 static pvjp_status gmm_args(int64_t N, int D, int K, const void* X, const void* alpha, const void* mu,
@@ -590,7 +646,7 @@ extern "C" size_t pvjp_gmm_ws_bytes(int64_t N, int D, int K) {
 
 extern "C" pvjp_status pvjp_gmm_objective(const float* X, int64_t N, int D, int K, const float* alpha,
                                           const float* mu, const float* q, const float* l, double* loglik,
-                                          double* lse, void* ws, size_t ws_bytes, void* stream) {
+                                          double* lse, double* s, void* ws, size_t ws_bytes, void* stream) {
     clear_error();
     if (pvjp_status e = gmm_args(N, D, K, X, alpha, mu, q, l, "pvjp_gmm_objective")) return e;
     PVJP_REQUIRE(loglik != nullptr, "pvjp_gmm_objective: loglik is NULL");
@@ -604,10 +660,10 @@ extern "C" pvjp_status pvjp_gmm_objective(const float* X, int64_t N, int D, int 
     hipStream_t st = as_stream(stream);
     if (D == 64) {
         launch_prep<64>(alpha, mu, q, l, K, w, L, st);
-        launch_fwd<64>(X, N, K, w, L, lse, loglik, st);
+        launch_fwd<64>(X, N, K, w, L, lse, s, loglik, st);
     } else {
         launch_prep<32>(alpha, mu, q, l, K, w, L, st);
-        launch_fwd<32>(X, N, K, w, L, lse, loglik, st);
+        launch_fwd<32>(X, N, K, w, L, lse, s, loglik, st);
     }
     PVJP_LAUNCHED("pvjp_gmm_objective");
     return PVJP_OK;
@@ -615,10 +671,11 @@ extern "C" pvjp_status pvjp_gmm_objective(const float* X, int64_t N, int D, int 
 
 extern "C" pvjp_status pvjp_gmm_vjp(const float* X, int64_t N, int D, int K, const float* alpha, const float* mu,
                                     const float* q, const float* l, double ell_bar, const double* lse,
-                                    float* alpha_bar, float* mu_bar, float* q_bar, float* l_bar, int accumulate,
-                                    void* ws, size_t ws_bytes, void* stream) {
+                                    const double* s, float* alpha_bar, float* mu_bar, float* q_bar, float* l_bar,
+                                    int accumulate, void* ws, size_t ws_bytes, void* stream) {
     clear_error();
     if (pvjp_status e = gmm_args(N, D, K, X, alpha, mu, q, l, "pvjp_gmm_vjp")) return e;
+    PVJP_REQUIRE(s == nullptr || lse != nullptr, "pvjp_gmm_vjp: the s checkpoint needs lse as well");
     PVJP_REQUIRE(alpha_bar && mu_bar && q_bar && l_bar, "pvjp_gmm_vjp: the four adjoint outputs must be non-NULL");
     PVJP_REQUIRE(ws != nullptr && aligned(ws, 256), "pvjp_gmm_vjp: ws must be non-NULL and 256-byte aligned");
     const GmmLayout L = gmm_layout(N, D, K);
@@ -632,17 +689,19 @@ extern "C" pvjp_status pvjp_gmm_vjp(const float* X, int64_t N, int D, int K, con
     if (D == 64) {
         launch_prep<64>(alpha, mu, q, l, K, w, L, st);
         if (lse == nullptr) {
-            launch_fwd<64>(X, N, K, w, L, (double*)(w + L.lse), ll_scratch, st);
+            launch_fwd<64>(X, N, K, w, L, (double*)(w + L.lse), nullptr, ll_scratch, st);
             lse = (const double*)(w + L.lse);
         }
-        launch_bwd<64>(X, N, K, alpha, mu, q, l, ell_bar, lse, alpha_bar, mu_bar, q_bar, l_bar, accumulate, w, L, st);
+        launch_bwd<64>(X, N, K, alpha, mu, q, l, ell_bar, lse, s, alpha_bar, mu_bar, q_bar, l_bar, accumulate, w, L,
+                       st);
     } else {
         launch_prep<32>(alpha, mu, q, l, K, w, L, st);
         if (lse == nullptr) {
-            launch_fwd<32>(X, N, K, w, L, (double*)(w + L.lse), ll_scratch, st);
+            launch_fwd<32>(X, N, K, w, L, (double*)(w + L.lse), nullptr, ll_scratch, st);
             lse = (const double*)(w + L.lse);
         }
-        launch_bwd<32>(X, N, K, alpha, mu, q, l, ell_bar, lse, alpha_bar, mu_bar, q_bar, l_bar, accumulate, w, L, st);
+        launch_bwd<32>(X, N, K, alpha, mu, q, l, ell_bar, lse, s, alpha_bar, mu_bar, q_bar, l_bar, accumulate, w, L,
+                       st);
     }
     PVJP_LAUNCHED("pvjp_gmm_vjp");
     return PVJP_OK;

@@ -309,8 +309,9 @@ def fig1_vjp(x0, x1, y0_bar, y1_bar, accumulate=False, x0_bar=None, x1_bar=None)
 
 
 # --------------------------------------------------------------------- GMM
-def gmm_objective(X, alpha, mu, q, l, want_lse=True):
-    """Returns (loglik [1] float64 device tensor, lse [N] float64 or None)."""
+def gmm_objective(X, alpha, mu, q, l, want_lse=True, s_out=None):
+    """Returns (loglik [1] float64 device tensor, lse [N] float64 or None).
+    s_out (float64 [K, N], optional) receives every s_ik."""
     N, D = X.shape
     K = alpha.numel()
     dev = X.device
@@ -319,12 +320,22 @@ def gmm_objective(X, alpha, mu, q, l, want_lse=True):
     nb = capi.lib().pvjp_gmm_ws_bytes(N, D, K)
     ws = WS.get("gmm", nb, dev)
     capi.call("pvjp_gmm_objective", _ptr(X), N, D, K, _ptr(alpha), _ptr(mu), _ptr(q), _ptr(l), _ptr(ll), _ptr(lse),
-              _ptr(ws), ws.numel(), _stream(dev))
+              _ptr(s_out), _ptr(ws), ws.numel(), _stream(dev))
     return ll, lse
 
 
-def gmm_vjp(X, alpha, mu, q, l, lse=None, ell_bar=1.0, out=None, accumulate=False):
-    """Returns (alpha_bar, mu_bar, q_bar, l_bar) (float32, device)."""
+def gmm_objective_ckpt(X, alpha, mu, q, l):
+    """The objective with both checkpoints: (loglik, lse [N], s [K, N])."""
+    N = X.shape[0]
+    s = torch.empty((alpha.numel(), N), dtype=torch.float64, device=X.device)
+    ll, lse = gmm_objective(X, alpha, mu, q, l, want_lse=True, s_out=s)
+    return ll, lse, s
+
+
+def gmm_vjp(X, alpha, mu, q, l, lse=None, ell_bar=1.0, out=None, accumulate=False, s=None):
+    """Returns (alpha_bar, mu_bar, q_bar, l_bar) (float32, device).  With the
+    s checkpoint of gmm_objective_ckpt (and its lse) the contraction is
+    S_k = sum w y y^T instead of recomputing z."""
     N, D = X.shape
     K = alpha.numel()
     dev = X.device
@@ -335,5 +346,5 @@ def gmm_vjp(X, alpha, mu, q, l, lse=None, ell_bar=1.0, out=None, accumulate=Fals
     nb = capi.lib().pvjp_gmm_ws_bytes(N, D, K)
     ws = WS.get("gmm", nb, dev)
     capi.call("pvjp_gmm_vjp", _ptr(X), N, D, K, _ptr(alpha), _ptr(mu), _ptr(q), _ptr(l), float(ell_bar), _ptr(lse),
-              _ptr(ab), _ptr(mb), _ptr(qb), _ptr(lb), int(accumulate), _ptr(ws), ws.numel(), _stream(dev))
+              _ptr(s), _ptr(ab), _ptr(mb), _ptr(qb), _ptr(lb), int(accumulate), _ptr(ws), ws.numel(), _stream(dev))
     return ab, mb, qb, lb

@@ -172,7 +172,7 @@ class Server:
                 outs = tuple(torch.empty_like(T[k]) for k in ("alpha", "mu", "q", "l"))
                 ws = self.ws[slot]["gmm"]
                 capi.call("pvjp_gmm_vjp", _ptr(T["X"]), it.n, GMM_D, GMM_K, _ptr(T["alpha"]), _ptr(T["mu"]),
-                          _ptr(T["q"]), _ptr(T["l"]), float(T["ybar"][r.ybar]), _ptr(T["lse"]),
+                          _ptr(T["q"]), _ptr(T["l"]), float(T["ybar"][r.ybar]), _ptr(T["lse"]), None,
                           *[_ptr(o) for o in outs], 0, _ptr(ws), ws.numel(), sp)
                 r.outputs = outs
             ev = torch.cuda.Event()

@@ -45,6 +45,31 @@ def test_gmm_objective_and_gradient(ops, orc, N, D, K):
     assert rel_l2([host(g) for g in got], list(ref)) <= TOL_F32
 
 
+@pytest.mark.parametrize("N,D,K", CASES)
+def test_gmm_gradient_from_s_checkpoint(ops, orc, N, D, K):
+    # the forward also keeps every s_ik; the reverse sweep then contracts
+    # S_k = sum w y y^T and forms G_k = Q_k S_k instead of recomputing z
+    X, alpha, mu, q, l = workloads.gmm(N, D, K, seed=N + D + K)
+    ll, lse, sck = ops.gmm_objective_ckpt(dev(X), dev(alpha), dev(mu), dev(q), dev(l))
+    rll, rlse = orc.gmm_objective(X, alpha, mu, q, l)
+    assert rel_l2(host(lse), rlse) <= TOL_F32
+    # the kept s_ik are the forward's: LSE over k of each point's s is lse
+    sv = host(sck)
+    mx = sv.max(axis=0)
+    assert np.allclose(mx + np.log(np.exp(sv - mx).sum(axis=0)), host(lse), rtol=1e-13, atol=1e-12)
+    got = ops.gmm_vjp(dev(X), dev(alpha), dev(mu), dev(q), dev(l), lse=lse, s=sck, ell_bar=1.0)
+    ref = orc.gmm_vjp(X, alpha, mu, q, l, 1.0)
+    for name, g, r in zip(["alpha", "mu", "q", "l"], got, ref):
+        err = rel_l2(host(g), r)
+        assert err <= TOL_F32, (name, err)
+    # accumulate on top of a base
+    base = [workloads.rng(i + 9).standard_normal(a.shape).astype(np.float32) for i, a in enumerate((alpha, mu, q, l))]
+    out = tuple(dev(b) for b in base)
+    ops.gmm_vjp(dev(X), dev(alpha), dev(mu), dev(q), dev(l), lse=lse, s=sck, ell_bar=1.0, out=out, accumulate=True)
+    for g, b, r in zip(out, base, ref):
+        assert rel_l2(host(g) - b, r) <= 2 * TOL_F32
+
+
 def test_gmm_vjp_without_checkpoint_and_accumulate(ops, orc):
     N, D, K = 500, 64, 6
     X, alpha, mu, q, l = workloads.gmm(N, D, K, seed=3)
@@ -70,7 +95,7 @@ def test_gmm_empty_and_unsupported(ops):
     assert np.all(host(qb) == 0)
     # D outside the built shapes is refused before any launch
     L = capi.lib()
-    assert L.pvjp_gmm_objective(8, 10, 48, 3, 8, 8, 8, 8, 8, None, 256, 1 << 20, None) == capi.PVJP_EUNSUPPORTED
+    assert L.pvjp_gmm_objective(8, 10, 48, 3, 8, 8, 8, 8, 8, None, None, 256, 1 << 20, None) == capi.PVJP_EUNSUPPORTED
 
 
 def test_gmm_full_size_sampled(ops, orc):
@@ -97,3 +122,10 @@ def test_gmm_full_size_sampled(ops, orc):
     # alpha_bar's -N softmax(alpha) term splits with N as well
     for a, b, c in zip(g, g1, g2):
         assert rel_l2(b + c, a) <= TOL_F32
+    # the s_ik checkpoint form at full size: same gradient as the recomputing
+    # form within the FP32 bar (both are checked against the oracle at small N)
+    _, lse2, sck = ops.gmm_objective_ckpt(Xd, *P)
+    assert np.array_equal(host(lse2), host(lse))
+    gs = [host(t) for t in ops.gmm_vjp(Xd, *P, lse=lse2, s=sck)]
+    for name, a, b in zip(["alpha", "mu", "q", "l"], g, gs):
+        assert rel_l2(b, a) <= TOL_F32, name
