@@ -55,6 +55,12 @@ _SIGS = {
     "orc_scan_generic_from": [_I, _L, _P, _P, _P],
     "orc_scan_generic_vjp": [_I, _L, _P, _P, _P],
     "orc_scan_generic_vjp_from": [_I, _L, _P, _P, _P, _P],
+    "orc_reduce_jvp": [_I, _L, _P, _P, _P],
+    "orc_hist_jvp": [_I, _L, _L, _P, _P, _P, _P],
+    "orc_scatter_jvp": [_L, _P, _L, _P, _P, _P],
+    "orc_map_jvp": [_I, _L, _P, _P, _P],
+    "orc_reduce_generic_jvp": [_I, _L, _P, _P, _P],
+    "orc_scan_generic_jvp": [_I, _L, _P, _P, _P],
 }
 
 
@@ -312,4 +318,52 @@ def scan_generic_vjp(op, xs, y_bar, init=None):
     out, optr = _arrays(K, n)
     ini = None if init is None else _f64(init).reshape(K)
     _check(lib().orc_scan_generic_vjp_from(_gop(op), n, _p(ini), ptrs, ybp, optr), "scan_generic_vjp")
+    return out
+
+
+# ------------------------------------------------------------ forward mode
+def reduce_jvp(op, x, x_dot):
+    op = OPS.get(op, op)
+    x, xd = _f64(x), _f64(x_dot)
+    yd = ctypes.c_double()
+    _check(lib().orc_reduce_jvp(op, x.size, _p(x), _p(xd), ctypes.byref(yd)), "reduce_jvp")
+    return yd.value
+
+
+def hist_jvp(op, inds, vs, vs_dot, m):
+    op = OPS.get(op, op)
+    inds, vs, vd = _i32(inds), _f64(vs), _f64(vs_dot)
+    out = np.empty(m)
+    _check(lib().orc_hist_jvp(op, vs.size, m, _p(inds), _p(vs), _p(vd), _p(out)), "hist_jvp")
+    return out
+
+
+def scatter_jvp(xs_dot, is_, vs_dot):
+    xd, is_, vd = _f64(xs_dot), _i32(is_), _f64(vs_dot)
+    out = np.empty(xd.size)
+    _check(lib().orc_scatter_jvp(xd.size, _p(xd), is_.size, _p(is_), _p(vd), _p(out)), "scatter_jvp")
+    return out
+
+
+def map_jvp(fn, x, x_dot):
+    fn = FNS.get(fn, fn)
+    x, xd = _f64(x), _f64(x_dot)
+    out = np.empty(x.size)
+    _check(lib().orc_map_jvp(fn, x.size, _p(x), _p(xd), _p(out)), "map_jvp")
+    return out
+
+
+def reduce_generic_jvp(op, xs, xs_dot):
+    xs, ptrs, n, K = _components(op, xs)
+    xd, dptrs, n2, _ = _components(op, xs_dot)
+    out = np.empty(K)
+    _check(lib().orc_reduce_generic_jvp(_gop(op), n, ptrs, dptrs, _p(out)), "reduce_generic_jvp")
+    return out
+
+
+def scan_generic_jvp(op, xs, xs_dot):
+    xs, ptrs, n, K = _components(op, xs)
+    xd, dptrs, n2, _ = _components(op, xs_dot)
+    out, optr = _arrays(K, n)
+    _check(lib().orc_scan_generic_jvp(_gop(op), n, ptrs, dptrs, optr), "scan_generic_jvp")
     return out

@@ -1020,3 +1020,201 @@ int orc_scan_generic_vjp_from(int op, int64_t n, const double* init, const doubl
     tape_free(t);
     return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Forward mode (Sec. 3, the tangent rewrite rule): the primal is recorded on */
+/* the tape exactly as for the VJP, then one sweep in record order applies    */
+/* tan[out] = d out/d in0 * tan[in0] + d out/d in1 * tan[in1], starting from   */
+/* the seeded leaves.                                                          */
+/* ------------------------------------------------------------------------ */
+
+static double* tan_alloc(tape_t* t) { return (double*)calloc((size_t)(t->nv > 0 ? t->nv : 1), sizeof(double)); }
+
+static void tan_sweep(const tape_t* t, double* tan) {
+    for (int64_t r = 0; r < t->nr; ++r) {
+        const rec_t* q = &t->rec[r];
+        double v = q->w0 * tan[q->in0];
+        if (q->in1 >= 0) v += q->w1 * tan[q->in1];
+        tan[q->out] = v;
+    }
+}
+
+int orc_reduce_jvp(int op, int64_t n, const double* x, const double* x_dot, double* y_dot) {
+    if (op < ORC_ADD || op > ORC_MAX || n < 0 || (n > 0 && (!x || !x_dot)) || !y_dot) return -1;
+    tape_t T, *t = &T;
+    if (tape_init(t, 2 * n + 16, n + 16)) return -2;
+    int64_t* sx = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    if (!sx) {
+        tape_free(t);
+        return -2;
+    }
+    for (int64_t i = 0; i < n; ++i) sx[i] = leaf(t, x[i]);
+    int64_t y = leaf(t, neutral(op));
+    int first = 1;
+    for (int64_t i = 0; i < n; ++i) {
+        switch (op) {
+            case ORC_ADD: y = t_add(t, y, sx[i]); break;
+            case ORC_MUL: y = t_mul(t, y, sx[i]); break;
+            default: y = t_pick(t, y, sx[i], first || better(op, x[i], V(y)));
+        }
+        first = 0;
+    }
+    double* tan = t->oom ? NULL : tan_alloc(t);
+    int rc = tan ? 0 : -2;
+    if (!rc) {
+        for (int64_t i = 0; i < n; ++i) tan[sx[i]] = x_dot[i];
+        tan_sweep(t, tan);
+        *y_dot = tan[y];
+    }
+    free(tan);
+    free(sx);
+    tape_free(t);
+    return rc;
+}
+
+int orc_hist_jvp(int op, int64_t n, int64_t m, const int32_t* inds, const double* vs,
+                 const double* vs_dot, double* hs_dot) {
+    if (op < ORC_ADD || op > ORC_MAX || n < 0 || m < 0 || (n > 0 && (!inds || !vs || !vs_dot)) ||
+        (m > 0 && !hs_dot))
+        return -1;
+    tape_t T, *t = &T;
+    if (tape_init(t, 2 * n + 16, n + 16)) return -2;
+    int64_t* sv = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    int64_t* sh = (int64_t*)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+    if (!sv || !sh) {
+        free(sv), free(sh);
+        tape_free(t);
+        return -2;
+    }
+    for (int64_t i = 0; i < n; ++i) sv[i] = leaf(t, vs[i]);
+    for (int64_t k = 0; k < m; ++k) sh[k] = -1;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t k = inds[i];
+        if (k < 0 || k >= m) continue;
+        if (sh[k] < 0) {
+            sh[k] = sv[i];
+            continue;
+        }
+        switch (op) {
+            case ORC_ADD: sh[k] = t_add(t, sh[k], sv[i]); break;
+            case ORC_MUL: sh[k] = t_mul(t, sh[k], sv[i]); break;
+            default: sh[k] = t_pick(t, sh[k], sv[i], better(op, vs[i], V(sh[k])));
+        }
+    }
+    double* tan = t->oom ? NULL : tan_alloc(t);
+    int rc = tan ? 0 : -2;
+    if (!rc) {
+        for (int64_t i = 0; i < n; ++i) tan[sv[i]] = vs_dot[i];
+        tan_sweep(t, tan);
+        for (int64_t k = 0; k < m; ++k) hs_dot[k] = sh[k] >= 0 ? tan[sh[k]] : 0.0; /* empty: the constant e */
+    }
+    free(tan);
+    free(sv), free(sh);
+    tape_free(t);
+    return rc;
+}
+
+int orc_scatter_jvp(int64_t n, const double* xs_dot, int64_t m, const int32_t* is, const double* vs_dot,
+                    double* ys_dot) {
+    if (n < 0 || m < 0 || (n > 0 && (!xs_dot || !ys_dot)) || (m > 0 && (!is || !vs_dot))) return -1;
+    /* ys[k] is a copy of xs[k] or of the last vs[j] with is[j] == k: its
+     * tangent is that variable's tangent */
+    for (int64_t k = 0; k < n; ++k) ys_dot[k] = xs_dot[k];
+    for (int64_t j = 0; j < m; ++j) {
+        int64_t k = is[j];
+        if (k >= 0 && k < n) ys_dot[k] = vs_dot[j];
+    }
+    return 0;
+}
+
+int orc_map_jvp(int fn, int64_t n, const double* x, const double* x_dot, double* y_dot) {
+    if (fn < ORC_FN_SQUARE || fn > ORC_FN_TANH || n < 0 || (n > 0 && (!x || !x_dot || !y_dot))) return -1;
+    tape_t T, *t = &T;
+    if (tape_init(t, 16, 16)) return -2;
+    double tan[16];
+    for (int64_t i = 0; i < n; ++i) {
+        tape_clear(t);
+        int64_t xs = leaf(t, x[i]);
+        int64_t ys = apply_fn(t, fn, xs);
+        for (int64_t s = 0; s < t->nv && s < 16; ++s) tan[s] = 0.0;
+        tan[xs] = x_dot[i];
+        tan_sweep(t, tan);
+        y_dot[i] = tan[ys];
+    }
+    tape_free(t);
+    return 0;
+}
+
+int orc_reduce_generic_jvp(int op, int64_t n, const double* const* x, const double* const* x_dot,
+                           double* y_dot) {
+    if (!gop_args_ok(op, n, x) || !gop_args_ok(op, n, x_dot) || !y_dot) return -1;
+    int K = orc_gop_components(op);
+    tape_t T, *t = &T;
+    if (tape_init(t, (int64_t)(K * 4 + 4) * n + 16, (int64_t)(K * 3 + 4) * n + 16)) return -2;
+    int64_t* sx = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * K * sizeof(int64_t));
+    if (!sx) {
+        tape_free(t);
+        return -2;
+    }
+    double e[4];
+    gop_neutral(op, e);
+    int64_t acc[4];
+    for (int c = 0; c < K; ++c) acc[c] = leaf(t, e[c]);
+    for (int64_t i = 0; i < n; ++i) {
+        for (int c = 0; c < K; ++c) sx[i * K + c] = leaf(t, x[c][i]);
+        gop_step(t, op, acc, &sx[i * K], acc);
+    }
+    double* tan = t->oom ? NULL : tan_alloc(t);
+    int rc = tan ? 0 : -2;
+    if (!rc) {
+        for (int64_t i = 0; i < n; ++i)
+            for (int c = 0; c < K; ++c) tan[sx[i * K + c]] = x_dot[c][i];
+        tan_sweep(t, tan);
+        for (int c = 0; c < K; ++c) y_dot[c] = tan[acc[c]];
+    }
+    free(tan);
+    free(sx);
+    tape_free(t);
+    return rc;
+}
+
+int orc_scan_generic_jvp(int op, int64_t n, const double* const* x, const double* const* x_dot,
+                         double* const* y_dot) {
+    if (!gop_args_ok(op, n, x) || !gop_args_ok(op, n, x_dot)) return -1;
+    int K = orc_gop_components(op);
+    if (n == 0) return 0;
+    if (!y_dot) return -1;
+    for (int c = 0; c < K; ++c)
+        if (!y_dot[c]) return -1;
+    tape_t T, *t = &T;
+    if (tape_init(t, (int64_t)(K * 4 + 4) * n + 16, (int64_t)(K * 3 + 4) * n + 16)) return -2;
+    int64_t* sx = (int64_t*)malloc((size_t)n * K * sizeof(int64_t));
+    int64_t* sy = (int64_t*)malloc((size_t)n * K * sizeof(int64_t));
+    if (!sx || !sy) {
+        free(sx), free(sy);
+        tape_free(t);
+        return -2;
+    }
+    double e[4];
+    gop_neutral(op, e);
+    int64_t acc[4];
+    for (int c = 0; c < K; ++c) acc[c] = leaf(t, e[c]);
+    for (int64_t i = 0; i < n; ++i) {
+        for (int c = 0; c < K; ++c) sx[i * K + c] = leaf(t, x[c][i]);
+        gop_step(t, op, acc, &sx[i * K], acc);
+        for (int c = 0; c < K; ++c) sy[i * K + c] = acc[c];
+    }
+    double* tan = t->oom ? NULL : tan_alloc(t);
+    int rc = tan ? 0 : -2;
+    if (!rc) {
+        for (int64_t i = 0; i < n; ++i)
+            for (int c = 0; c < K; ++c) tan[sx[i * K + c]] = x_dot[c][i];
+        tan_sweep(t, tan);
+        for (int64_t i = 0; i < n; ++i)
+            for (int c = 0; c < K; ++c) y_dot[c][i] = tan[sy[i * K + c]];
+    }
+    free(tan);
+    free(sx), free(sy);
+    tape_free(t);
+    return rc;
+}

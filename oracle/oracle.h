@@ -129,6 +129,21 @@ int orc_scan_generic_vjp(int op, int64_t n, const double* const* x, const double
 int orc_scan_generic_vjp_from(int op, int64_t n, const double* init, const double* const* x,
                               const double* const* y_bar, double* const* x_bar);
 
+/* Forward mode (Sec. 3): Jacobian-vector products by a forward sweep over
+ * the same tape records (tan[out] = sum of partial * tan[in] in record
+ * order).  Outputs: the tangents of the primal outputs (for hist: hs_dot[m],
+ * 0 for an empty bin; for the general operators: K values or K arrays). */
+int orc_reduce_jvp(int op, int64_t n, const double* x, const double* x_dot, double* y_dot);
+int orc_hist_jvp(int op, int64_t n, int64_t m, const int32_t* inds, const double* vs,
+                 const double* vs_dot, double* hs_dot);
+int orc_scatter_jvp(int64_t n, const double* xs_dot, int64_t m, const int32_t* is, const double* vs_dot,
+                    double* ys_dot);
+int orc_map_jvp(int fn, int64_t n, const double* x, const double* x_dot, double* y_dot);
+int orc_reduce_generic_jvp(int op, int64_t n, const double* const* x, const double* const* x_dot,
+                           double* y_dot);
+int orc_scan_generic_jvp(int op, int64_t n, const double* const* x, const double* const* x_dot,
+                         double* const* y_dot);
+
 #ifdef __cplusplus
 }
 #endif
