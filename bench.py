@@ -48,7 +48,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 23, help="elements per instance for the CPU oracle")
-    ap.add_argument("--skip", default="", help="comma list of extra workloads to skip: reduce_map,reduce_generic,scan_generic,scan,gmm,batch,serve")
+    ap.add_argument("--skip", default="", help="comma list of extra workloads to skip: reduce_map,reduce_generic,scan_generic,jvp,scan,gmm,batch,"
+                         "serve")
     ap.add_argument("--only", default="",
                     help="run just this one extra workload (for profiling) and print its JSON instead of the "
                          "benchmark line")
@@ -220,7 +221,7 @@ def main():
     L = capi.lib()
     if args.only:
         fns = {"reduce_map": bench_reduce_map, "reduce_generic": bench_reduce_generic,
-               "scan_generic": bench_scan_generic, "scan": bench_scan,
+               "scan_generic": bench_scan_generic, "jvp": bench_jvp, "scan": bench_scan,
                "gmm": bench_gmm, "batch": bench_batch, "serve": bench_serve}
         print(json.dumps({args.only: fns[args.only](args)}))
         return
@@ -381,7 +382,8 @@ def main():
     torch.cuda.empty_cache()
     extra = {}
     for name, fn in (("reduce_map", bench_reduce_map), ("reduce_generic", bench_reduce_generic),
-                     ("scan_generic", bench_scan_generic), ("scan", bench_scan), ("gmm", bench_gmm),
+                     ("scan_generic", bench_scan_generic), ("jvp", bench_jvp), ("scan", bench_scan),
+                     ("gmm", bench_gmm),
                      ("batch", bench_batch), ("serve", bench_serve)):
         if name in args.skip:
             continue
@@ -695,6 +697,58 @@ def bench_scan_generic(args):
                 "vjp_hbm_frac_moved": round(5 * comp / (tv * 1e-3) / 1e9 / HBM_PEAK_GBPS, 3),
                 "vjp_elems_per_s": round(n / (tv * 1e-3), 1)}
             del xs, xb, yb, ck
+            torch.cuda.empty_cache()
+    return res
+
+
+def bench_jvp(args):
+    """Forward mode at n = 2^26 (tangents resident): map (exp), reduce(+),
+    reduce_by_index (+ at m = 2^16 Zipf, max at m = 2^20), scatter (2^24
+    targets into 2^26) and the general-operator reduce and scan on (x, x_dot)
+    pairs.  Algorithmic bytes: map 3 s n (x, x_dot read, y_dot written);
+    reduce 4 n; histogram + 8 n, max 12 m; scatter 12 m; general reduce
+    2 K s n; general scan 4 K s n (x, x_dot read, y, y_dot written)."""
+    import torch
+
+    from paper_2202_10297_amd import ops, workloads
+
+    n = 1 << 26
+    res = {}
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    rate = lambda b, t: round(b / (t * 1e-3) / 1e9 / HBM_PEAK_GBPS, 3)
+    x = torch.rand(n, device="cuda", generator=g) + 0.5
+    xd = torch.randn(n, device="cuda", generator=g)
+    t = _events_ms(lambda: ops.map_jvp("exp", x, xd), 10)
+    res["map_exp_f32"] = {"ms": round(t, 4), "hbm_frac": rate(12 * n, t)}
+    _, aux = ops.reduce("add", x)
+    t = _events_ms(lambda: ops.reduce_jvp("add", x, aux, xd), 10)
+    res["reduce_add_f32"] = {"ms": round(t, 4), "hbm_frac": rate(4 * n, t)}
+    for op, m, dist in (("add", 1 << 16, "zipf"), ("max", 1 << 20, "uniform")):
+        inds, vs, _ = workloads.hist(n, m, dist, "f32", seed=0)
+        di, dv = torch.from_numpy(inds).cuda(), torch.from_numpy(vs).cuda()
+        _, aux = ops.hist(op, di, dv, m)
+        t = _events_ms(lambda: ops.hist_jvp(op, di, xd, m, aux), 10)
+        res[f"hist_{op}_m{m}_f32"] = {"ms": round(t, 4),
+                                     "hbm_frac": rate(8 * n if op == "add" else 12 * m, t)}
+        del di, dv
+    m = 1 << 24
+    is_ = torch.randperm(n, device="cuda", generator=g)[:m].to(torch.int32)
+    vd = torch.randn(m, device="cuda", generator=g)
+    yd = xd.clone()
+    t = _events_ms(lambda: ops.scatter_jvp_(yd, is_, vd), 10)
+    res["scatter_f32"] = {"ms": round(t, 4), "hbm_frac": rate(12 * m, t)}
+    del x, xd, is_, vd, yd
+    torch.cuda.empty_cache()
+    for op, K in (("logaddexp", 1), ("linrec", 2)):
+        for dt, tname, es in ((torch.float32, "f32", 4), (torch.float64, "f64", 8)):
+            xs = _gop_inputs(op, n, dt, g)
+            xds = [torch.randn(n, dtype=dt, device="cuda", generator=g) for _ in range(K)]
+            tr = _events_ms(lambda: ops.reduce_generic_jvp(op, xs, xds), 5)
+            ts = _events_ms(lambda: ops.scan_generic_jvp(op, xs, xds), 5)
+            res[f"{op}_{tname}"] = {"reduce_ms": round(tr, 4), "reduce_hbm_frac": rate(2 * K * es * n, tr),
+                                    "scan_ms": round(ts, 4), "scan_hbm_frac": rate(4 * K * es * n, ts)}
+            del xs, xds
             torch.cuda.empty_cache()
     return res
 

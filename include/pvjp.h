@@ -313,6 +313,53 @@ pvjp_status pvjp_scan_generic_vjp(pvjp_gop op, pvjp_dtype dtype, const void* con
                                   int accumulate, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* Forward mode (Sec. 3): Jacobian-vector products.  Each primal is bundled   */
+/* with its tangent and the operator runs on the pairs (the dual-number form  */
+/* of the tangent rewrite rule).  Tangents (x_dot, ...) have the primal's     */
+/* layout and dtype; outputs are overwritten.                                 */
+/* ------------------------------------------------------------------------ */
+
+/* y_dot_i = f'(x_i) x_dot_i (the elementwise Jacobian is diagonal: this is
+ * the VJP kernel with x_dot in place of y_bar). */
+pvjp_status pvjp_map_jvp(pvjp_fn fn, pvjp_dtype dtype, const void* x, const void* x_dot, int64_t n,
+                         void* y_dot, void* stream);
+/* y_dot (device, 1 element) of y = reduce(op) x, with the auxiliary outputs
+ * of pvjp_reduce on the same x:
+ *  ADD: sum of x_dot (FP64 accumulation, ws as for pvjp_reduce);
+ *  MUL: p * sum x_dot_i / x_i (z == 0), p * x_dot at the zero (z == 1), 0
+ *       (z >= 2); needs x, p, z and ws as for pvjp_reduce;
+ *  MIN/MAX: x_dot[arg] (0 if n == 0); ws unused. */
+pvjp_status pvjp_reduce_jvp(pvjp_op op, pvjp_dtype dtype, const void* x, const void* x_dot, int64_t n,
+                            const int64_t* arg, const void* p, const int64_t* z, void* y_dot, void* ws,
+                            size_t ws_bytes, void* stream);
+/* Workspace bytes of pvjp_hist_jvp (ADD only: that of pvjp_hist(ADD)). */
+size_t pvjp_hist_jvp_ws_bytes(pvjp_op op, pvjp_dtype dtype, int64_t n, int64_t m);
+/* hs_dot [m] of hs = reduce_by_index(op):
+ *  ADD: reduce_by_index(+) of vs_dot over the same inds (ws as pvjp_hist);
+ *  MIN/MAX: vs_dot[winner[k]], 0 for an empty bin (winner from pvjp_hist);
+ *  MUL: PVJP_EUNSUPPORTED. */
+pvjp_status pvjp_hist_jvp(pvjp_op op, pvjp_dtype dtype, const int32_t* inds, const void* vs_dot,
+                          int64_t n, int64_t m, const int32_t* winner, void* hs_dot, void* ws,
+                          size_t ws_bytes, void* stream);
+/* In place on ys_dot [n] (x_dot on entry): ys_dot[is[j]] = vs_dot[j] (the
+ * primal scatter of the tangents; same index rules as pvjp_scatter). */
+pvjp_status pvjp_scatter_jvp(pvjp_dtype dtype, void* ys_dot, int64_t n, const int32_t* is,
+                             const void* vs_dot, int64_t m, void* stream);
+/* Reduce / inclusive scan with a general operator on (x, x_dot) pairs: the
+ * primal y and its tangent y_dot in one pass (K components each; for the scan
+ * K arrays of n).  log-add-exp carries (max, scaled sum, scaled tangent sum);
+ * the linear recurrence (A, B, A_dot, B_dot); the 2x2 product (X, X_dot) with
+ * X_dot Y + X Y_dot.  Workspaces: the queries below (no initialisation). */
+size_t pvjp_reduce_generic_jvp_ws_bytes(pvjp_gop op, pvjp_dtype dtype, int64_t n);
+size_t pvjp_scan_generic_jvp_ws_bytes(pvjp_gop op, pvjp_dtype dtype, int64_t n);
+pvjp_status pvjp_reduce_generic_jvp(pvjp_gop op, pvjp_dtype dtype, const void* const* x,
+                                    const void* const* x_dot, int64_t n, void* const* y,
+                                    void* const* y_dot, void* ws, size_t ws_bytes, void* stream);
+pvjp_status pvjp_scan_generic_jvp(pvjp_gop op, pvjp_dtype dtype, const void* const* x,
+                                  const void* const* x_dot, int64_t n, void* const* y,
+                                  void* const* y_dot, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* Segmented batches: many instances of uneven length stored back to back     */
 /* (segment s = elements [offsets[s], offsets[s+1])), each processed as one   */
 /* segmented operation per launch.  This generalises the rule of Sec. 5.2     */

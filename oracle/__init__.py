@@ -61,6 +61,7 @@ _SIGS = {
     "orc_map_jvp": [_I, _L, _P, _P, _P],
     "orc_reduce_generic_jvp": [_I, _L, _P, _P, _P],
     "orc_scan_generic_jvp": [_I, _L, _P, _P, _P],
+    "orc_scan_generic_jvp_from": [_I, _L, _P, _P, _P, _P],
 }
 
 
@@ -361,9 +362,12 @@ def reduce_generic_jvp(op, xs, xs_dot):
     return out
 
 
-def scan_generic_jvp(op, xs, xs_dot):
+def scan_generic_jvp(op, xs, xs_dot, init=None):
+    """Tangents of every output; init: the (constant) state the fold starts
+    from, None for the neutral element."""
     xs, ptrs, n, K = _components(op, xs)
     xd, dptrs, n2, _ = _components(op, xs_dot)
     out, optr = _arrays(K, n)
-    _check(lib().orc_scan_generic_jvp(_gop(op), n, ptrs, dptrs, optr), "scan_generic_jvp")
+    ini = None if init is None else _f64(init).reshape(K)
+    _check(lib().orc_scan_generic_jvp_from(_gop(op), n, _p(ini), ptrs, dptrs, optr), "scan_generic_jvp")
     return out

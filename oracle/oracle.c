@@ -1180,6 +1180,11 @@ int orc_reduce_generic_jvp(int op, int64_t n, const double* const* x, const doub
 
 int orc_scan_generic_jvp(int op, int64_t n, const double* const* x, const double* const* x_dot,
                          double* const* y_dot) {
+    return orc_scan_generic_jvp_from(op, n, NULL, x, x_dot, y_dot);
+}
+
+int orc_scan_generic_jvp_from(int op, int64_t n, const double* init, const double* const* x,
+                              const double* const* x_dot, double* const* y_dot) {
     if (!gop_args_ok(op, n, x) || !gop_args_ok(op, n, x_dot)) return -1;
     int K = orc_gop_components(op);
     if (n == 0) return 0;
@@ -1197,6 +1202,8 @@ int orc_scan_generic_jvp(int op, int64_t n, const double* const* x, const double
     }
     double e[4];
     gop_neutral(op, e);
+    if (init)
+        for (int c = 0; c < K; ++c) e[c] = init[c];
     int64_t acc[4];
     for (int c = 0; c < K; ++c) acc[c] = leaf(t, e[c]);
     for (int64_t i = 0; i < n; ++i) {

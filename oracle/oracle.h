@@ -143,6 +143,9 @@ int orc_reduce_generic_jvp(int op, int64_t n, const double* const* x, const doub
                            double* y_dot);
 int orc_scan_generic_jvp(int op, int64_t n, const double* const* x, const double* const* x_dot,
                          double* const* y_dot);
+/* The same with the fold started from the constant state init (tangent 0). */
+int orc_scan_generic_jvp_from(int op, int64_t n, const double* init, const double* const* x,
+                              const double* const* x_dot, double* const* y_dot);
 
 #ifdef __cplusplus
 }

@@ -57,6 +57,15 @@ SIGNATURES = {
     "pvjp_scan_generic_ckpt_bytes": (_Z, [_I, _I, _L]),
     "pvjp_scan_generic": (_I, [_I, _I, _P, _L, _P, _P, _P, _Z, _P]),
     "pvjp_scan_generic_vjp": (_I, [_I, _I, _P, _L, _P, _P, _P, _I, _P, _Z, _P]),
+    "pvjp_map_jvp": (_I, [_I, _I, _P, _P, _L, _P, _P]),
+    "pvjp_reduce_jvp": (_I, [_I, _I, _P, _P, _L, _P, _P, _P, _P, _P, _Z, _P]),
+    "pvjp_hist_jvp_ws_bytes": (_Z, [_I, _I, _L, _L]),
+    "pvjp_hist_jvp": (_I, [_I, _I, _P, _P, _L, _L, _P, _P, _P, _Z, _P]),
+    "pvjp_scatter_jvp": (_I, [_I, _P, _L, _P, _P, _L, _P]),
+    "pvjp_reduce_generic_jvp_ws_bytes": (_Z, [_I, _I, _L]),
+    "pvjp_scan_generic_jvp_ws_bytes": (_Z, [_I, _I, _L]),
+    "pvjp_reduce_generic_jvp": (_I, [_I, _I, _P, _P, _L, _P, _P, _P, _Z, _P]),
+    "pvjp_scan_generic_jvp": (_I, [_I, _I, _P, _P, _L, _P, _P, _P, _Z, _P]),
     "pvjp_seg_ws_bytes": (_Z, [_L, _L, _I]),
     "pvjp_seg_prepare": (_I, [_P, _L, _I, _P, _Z, _P]),
     "pvjp_seg_linrec_scan": (_I, [_I, _P, _P, _L, _L, _I, _P, _P, _P, _P, _Z, _P]),

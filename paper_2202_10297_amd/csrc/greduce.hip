@@ -31,6 +31,11 @@ namespace pvjp {
 constexpr int kGrBlock = 256;
 constexpr int kGrAggBlock = 1024;
 constexpr size_t kGrSlot = 32;  // bytes per tile for an aggregate, prefix or suffix
+// Slot of a state: 32 bytes, 64 for the dual 2x2 matrix state in FP64.
+template <class S>
+constexpr size_t slot_of() {
+    return sizeof(S) <= 32 ? 32 : 64;
+}
 
 template <class T, int K>
 struct GS {
@@ -180,6 +185,87 @@ struct GMat2 : GShfl<T, 4> {
     }
 };
 
+// ------------------------------------------------------------ forward mode
+// Dual numbers over an operator (forward mode, Sec. 3: each primal bundled
+// with its tangent): an element is (x, x_dot), 2K components (the K primal
+// ones, then the K tangents), and (x, xd) (.) (y, yd) = (x (.) y,
+// d1(x, y) xd + d2(x, y) yd).  A reduce or scan with the dual operator
+// gives the primal result and its tangent in one pass.
+
+// log-add-exp: state (m, s, t) with value m + log s and tangent t / s (t is
+// the tangent sum weighted like s: t = sum e^(x_j - m) x_dot_j).
+template <class T>
+struct GLaeDual : GShfl<T, 3> {
+    static constexpr int K = 2;
+    using Acc = T;
+    using S = GS<T, 3>;
+    __device__ static __forceinline__ S id() { return S{{-(T)INFINITY, T(0), T(0)}}; }
+    __device__ static __forceinline__ S elem(const T (&c)[2]) {
+        const bool ninf = c[0] == -(T)INFINITY;
+        return S{{c[0], ninf ? T(0) : T(1), ninf ? T(0) : c[1]}};
+    }
+    __device__ static __forceinline__ void value(S v, T (&out)[2]) {
+        out[0] = v.c[0] + log(v.c[1]);
+        out[1] = v.c[1] == T(0) ? T(0) : v.c[2] / v.c[1];
+    }
+    __device__ static __forceinline__ S comb(S x, S y) {
+        if (y.c[1] == T(0)) return x;
+        if (x.c[1] == T(0)) return y;
+        const T d = x.c[0] - y.c[0];
+        const T e = lae_exp(-fabs(d));
+        return d >= T(0) ? S{{x.c[0], x.c[1] + y.c[1] * e, x.c[2] + y.c[2] * e}}
+                         : S{{y.c[0], x.c[1] * e + y.c[1], x.c[2] * e + y.c[2]}};
+    }
+};
+
+// linear recurrence: (A, B, A_dot, B_dot); (later) o (earlier) by the
+// product rule.
+template <class T>
+struct GLinRecDual : GShfl<T, 4> {
+    static constexpr int K = 4;
+    using Acc = T;
+    using S = GS<T, 4>;
+    __device__ static __forceinline__ S id() { return S{{T(1), T(0), T(0), T(0)}}; }
+    __device__ static __forceinline__ S elem(const T (&c)[4]) { return S{{c[0], c[1], c[2], c[3]}}; }
+    __device__ static __forceinline__ void value(S v, T (&out)[4]) {
+        for (int c = 0; c < 4; ++c) out[c] = v.c[c];
+    }
+    __device__ static __forceinline__ S comb(S x, S y) {
+        return S{{y.c[0] * x.c[0], y.c[0] * x.c[1] + y.c[1], y.c[2] * x.c[0] + y.c[0] * x.c[2],
+                  y.c[2] * x.c[1] + y.c[0] * x.c[3] + y.c[3]}};
+    }
+};
+
+// 2x2 matrix product: (X, X_dot) (.) (Y, Y_dot) = (X Y, X_dot Y + X Y_dot).
+template <class T>
+struct GMat2Dual : GShfl<T, 8> {
+    static constexpr int K = 8;
+    using Acc = T;
+    using S = GS<T, 8>;
+    __device__ static __forceinline__ S id() { return S{{T(1), T(0), T(0), T(1), T(0), T(0), T(0), T(0)}}; }
+    __device__ static __forceinline__ S elem(const T (&c)[8]) {
+        S s;
+        for (int j = 0; j < 8; ++j) s.c[j] = c[j];
+        return s;
+    }
+    __device__ static __forceinline__ void value(S v, T (&out)[8]) {
+        for (int c = 0; c < 8; ++c) out[c] = v.c[c];
+    }
+    __device__ static __forceinline__ void mm(const T* a, const T* b, T* o, bool add) {
+        const T r0 = a[0] * b[0] + a[1] * b[2], r1 = a[0] * b[1] + a[1] * b[3];
+        const T r2 = a[2] * b[0] + a[3] * b[2], r3 = a[2] * b[1] + a[3] * b[3];
+        if (add) o[0] += r0, o[1] += r1, o[2] += r2, o[3] += r3;
+        else o[0] = r0, o[1] = r1, o[2] = r2, o[3] = r3;
+    }
+    __device__ static __forceinline__ S comb(S x, S y) {
+        S r;
+        mm(x.c, y.c, r.c, false);
+        mm(x.c + 4, y.c, r.c + 4, false);
+        mm(x.c, y.c + 4, r.c + 4, true);
+        return r;
+    }
+};
+
 // The same operator with its operands exchanged: a scan in reversed index
 // order with it folds x_{i+1} (.) x_{i+2} (.) ... (the reversed scan of the
 // rule, whose operator is \x y -> y (.) x).
@@ -251,11 +337,11 @@ struct LinG {
 
 template <class T>
 struct GPtrs {
-    const T* p[4];
+    const T* p[8];
 };
 template <class T>
 struct GOut {
-    T* p[4];
+    T* p[8];
 };
 
 // Items per thread: 32 bytes of every component (two 16-byte loads), fewer
@@ -728,8 +814,9 @@ static GrPlan gr_plan(int64_t n) {
     GrPlan p;
     p.nt = ceil_div(n, gr_tile<Op, T>());
     p.ng = ceil_div(p.nt, kGrGroup);
-    p.tiles = align_up((size_t)(p.nt > 0 ? p.nt : 1) * kGrSlot, 256);
-    p.groups = align_up((size_t)(p.ng > 0 ? p.ng : 1) * kGrSlot, 256);
+    constexpr size_t slot = slot_of<typename Op::S>();
+    p.tiles = align_up((size_t)(p.nt > 0 ? p.nt : 1) * slot, 256);
+    p.groups = align_up((size_t)(p.ng > 0 ? p.ng : 1) * slot, 256);
     return p;
 }
 
@@ -768,7 +855,7 @@ template <class Op, class T>
 static void launch_primal(const GPtrs<T>& x, int64_t n, const GOut<T>& y, void* ckpt, void* ws, bool vec,
                           hipStream_t st) {
     using S = typename Op::S;
-    static_assert(sizeof(S) <= kGrSlot, "slot too small");
+    static_assert(sizeof(S) <= slot_of<S>(), "slot too small");
     const GrPlan p = gr_plan<Op, T>(n);
     S* gagg = gr_array<S>(ws, p, 3);
     S* agg = ckpt ? reinterpret_cast<S*>(ckpt) : gr_array<S>(ws, p, 0);
@@ -787,7 +874,7 @@ static void launch_vjp(const GPtrs<T>& x, int64_t n, const void* ckpt, const GPt
     S* gagg = gr_array<S>(ws, p, 3);
     S* gpre = gr_array<S>(ws, p, 4);
     S* gsuf = gr_array<S>(ws, p, 5);
-    const GOut<T> none{{nullptr, nullptr, nullptr, nullptr}};
+    const GOut<T> none{};
     const unsigned gblocks = (unsigned)ceil_div(p.ng, kGrBlock / kWave);
     const S* agg;
     if (ckpt) {
@@ -875,8 +962,9 @@ static GsPlan gs_plan(int64_t n) {
     p.nt = ceil_div(n, gs_tile<Op, T>());
     p.ng = ceil_div(p.nt, kAggGroup);
     const size_t nt = (size_t)(p.nt > 0 ? p.nt : 1), ng = (size_t)(p.ng > 0 ? p.ng : 1);
-    p.t32 = align_up(nt * kGrSlot, 256);
-    p.g32 = align_up(ng * kGrSlot, 256);
+    constexpr size_t slot = slot_of<typename Op::S>();
+    p.t32 = align_up(nt * slot, 256);
+    p.g32 = align_up(ng * slot, 256);
     p.tl = align_up(nt * kLinSlot, 256);
     p.gl = align_up(ng * kLinSlot, 256);
     return p;
@@ -1037,6 +1125,73 @@ struct GsCkQ {
     static size_t get(int64_t n) { return (size_t)gs_plan<GOpFor<OpT, T>, T>(n).nt * kGrSlot; }
 };
 
+// Forward mode: the dual operator of each operator and storage type (FP32
+// linear-recurrence and matrix duals in FP64, as for the primal).
+template <template <class> class DualT, class T>
+using GDualFor = DualT<typename std::conditional<std::is_same<T, float>::value &&
+                                                     !std::is_same<DualT<float>, GLaeDual<float>>::value,
+                                                 double, T>::type>;
+
+// [x components | x_dot components] -> [y | y_dot]
+template <class T>
+static void dual_ptrs(const void* const* x, const void* const* xd, int K, GPtrs<T>& xp, bool& vec) {
+    for (int c = 0; c < K; ++c) {
+        xp.p[c] = (const T*)x[c];
+        xp.p[K + c] = (const T*)xd[c];
+        vec = vec && aligned(x[c], 16) && aligned(xd[c], 16);
+    }
+}
+
+template <template <class> class DualT, class T>
+static void dispatch_reduce_jvp(const void* const* x, const void* const* xd, int K, int64_t n, void* const* y,
+                                void* const* yd, void* ws, hipStream_t st) {
+    GPtrs<T> xp{};
+    GOut<T> yp{};
+    bool vec = true;
+    if (n > 0) dual_ptrs<T>(x, xd, K, xp, vec);
+    for (int c = 0; c < K; ++c) {
+        yp.p[c] = (T*)y[c];
+        yp.p[K + c] = (T*)yd[c];
+    }
+    launch_primal<GDualFor<DualT, T>, T>(xp, n, yp, nullptr, ws, vec, st);
+}
+
+template <template <class> class DualT, class T>
+static void dispatch_scan_jvp(const void* const* x, const void* const* xd, int K, int64_t n, void* const* y,
+                              void* const* yd, void* ws, hipStream_t st) {
+    GPtrs<T> xp{};
+    GOut<T> yp{};
+    bool vec = true;
+    dual_ptrs<T>(x, xd, K, xp, vec);
+    for (int c = 0; c < K; ++c) {
+        yp.p[c] = (T*)y[c];
+        yp.p[K + c] = (T*)yd[c];
+        vec = vec && aligned(y[c], 16) && aligned(yd[c], 16);
+    }
+    launch_scan<GDualFor<DualT, T>, T>(xp, n, yp, nullptr, ws, vec, st);
+}
+
+template <template <class> class DualT, class T>
+struct GrJvpWsQ {
+    static size_t get(int64_t n) { return gr_ws<GDualFor<DualT, T>, T>(n); }
+};
+template <template <class> class DualT, class T>
+struct GsJvpWsQ {
+    static size_t get(int64_t n) { return gs_ws<GDualFor<DualT, T>, T>(n); }
+};
+
+template <template <template <class> class, class> class Q>
+static size_t dual_query(pvjp_gop op, pvjp_dtype dtype, int64_t n) {
+    if (dtype == PVJP_F64) {
+        if (op == PVJP_GOP_LOGADDEXP) return Q<GLaeDual, double>::get(n);
+        if (op == PVJP_GOP_LINREC) return Q<GLinRecDual, double>::get(n);
+        return Q<GMat2Dual, double>::get(n);
+    }
+    if (op == PVJP_GOP_LOGADDEXP) return Q<GLaeDual, float>::get(n);
+    if (op == PVJP_GOP_LINREC) return Q<GLinRecDual, float>::get(n);
+    return Q<GMat2Dual, float>::get(n);
+}
+
 }  // namespace pvjp
 
 using namespace pvjp;
@@ -1102,7 +1257,7 @@ extern "C" pvjp_status pvjp_reduce_generic(pvjp_gop op, pvjp_dtype dtype, const 
     PVJP_REQUIRE(y != nullptr, "pvjp_reduce_generic: y is NULL");
     for (int c = 0; c < K; ++c) PVJP_REQUIRE(y[c] != nullptr, "pvjp_reduce_generic: component %d of y is NULL", c);
     const hipStream_t st = as_stream(stream);
-    const void* none[4] = {nullptr, nullptr, nullptr, nullptr};
+    const void* none[8] = {};
     const void* const* xx = n > 0 ? x : none;
     if (dtype == PVJP_F64) {
         if (op == PVJP_GOP_LOGADDEXP) dispatch_primal<GLogAddExp, double>(xx, K, n, y, ckpt, ws, st);
@@ -1239,5 +1394,89 @@ extern "C" pvjp_status pvjp_scan_generic_vjp(pvjp_gop op, pvjp_dtype dtype, cons
             dispatch_scan_vjp<GMat2, float>(x, K, n, ckpt, y_bar, x_bar, accumulate, ws, st);
     }
     PVJP_LAUNCHED("pvjp_scan_generic_vjp");
+    return PVJP_OK;
+}
+
+// ------------------------------------------------------- forward mode entries
+extern "C" size_t pvjp_reduce_generic_jvp_ws_bytes(pvjp_gop op, pvjp_dtype dtype, int64_t n) {
+    if (gop_components(op) == 0 || !valid_dtype(dtype) || n < 0) return 0;
+    return dual_query<GrJvpWsQ>(op, dtype, n);
+}
+
+extern "C" size_t pvjp_scan_generic_jvp_ws_bytes(pvjp_gop op, pvjp_dtype dtype, int64_t n) {
+    if (gop_components(op) == 0 || !valid_dtype(dtype) || n < 0) return 0;
+    return dual_query<GsJvpWsQ>(op, dtype, n);
+}
+
+static pvjp_status check_jvp(const char* name, pvjp_gop op, pvjp_dtype dtype, const void* const* x,
+                             const void* const* xd, int64_t n, void* const* y, void* const* yd, void* ws,
+                             size_t ws_bytes, size_t need) {
+    const int K = gop_components(op);
+    PVJP_REQUIRE(K > 0, "%s: unknown operator %d", name, (int)op);
+    PVJP_REQUIRE(valid_dtype(dtype), "%s: unknown dtype %d", name, (int)dtype);
+    PVJP_REQUIRE(n >= 0 && n < ((int64_t)1 << 40), "%s: n out of range", name);
+    PVJP_REQUIRE(ws != nullptr && aligned(ws, 256), "%s: workspace must be non-NULL and 256-byte aligned", name);
+    if (ws_bytes < need) {
+        set_error("%s: workspace of %zu bytes, need %zu", name, ws_bytes, need);
+        return PVJP_ENOMEM;
+    }
+    PVJP_REQUIRE(y != nullptr && yd != nullptr, "%s: y and y_dot must be non-NULL", name);
+    for (int c = 0; c < K; ++c) PVJP_REQUIRE(y[c] && yd[c], "%s: component %d of y or y_dot is NULL", name, c);
+    if (n > 0) {
+        PVJP_REQUIRE(x != nullptr && xd != nullptr, "%s: x and x_dot must be non-NULL", name);
+        for (int c = 0; c < K; ++c) {
+            PVJP_REQUIRE(x[c] && xd[c], "%s: component %d of x or x_dot is NULL", name, c);
+            PVJP_REQUIRE(aligned(x[c], dsize(dtype)) && aligned(xd[c], dsize(dtype)),
+                         "%s: component %d of x or x_dot is misaligned", name, c);
+        }
+    }
+    return PVJP_OK;
+}
+
+extern "C" pvjp_status pvjp_reduce_generic_jvp(pvjp_gop op, pvjp_dtype dtype, const void* const* x,
+                                               const void* const* x_dot, int64_t n, void* const* y,
+                                               void* const* y_dot, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    const pvjp_status s = check_jvp("pvjp_reduce_generic_jvp", op, dtype, x, x_dot, n, y, y_dot, ws, ws_bytes,
+                                    pvjp_reduce_generic_jvp_ws_bytes(op, dtype, n));
+    if (s != PVJP_OK) return s;
+    const int K = gop_components(op);
+    const hipStream_t st = as_stream(stream);
+    if (dtype == PVJP_F64) {
+        if (op == PVJP_GOP_LOGADDEXP) dispatch_reduce_jvp<GLaeDual, double>(x, x_dot, K, n, y, y_dot, ws, st);
+        else if (op == PVJP_GOP_LINREC) dispatch_reduce_jvp<GLinRecDual, double>(x, x_dot, K, n, y, y_dot, ws, st);
+        else dispatch_reduce_jvp<GMat2Dual, double>(x, x_dot, K, n, y, y_dot, ws, st);
+    } else {
+        if (op == PVJP_GOP_LOGADDEXP) dispatch_reduce_jvp<GLaeDual, float>(x, x_dot, K, n, y, y_dot, ws, st);
+        else if (op == PVJP_GOP_LINREC) dispatch_reduce_jvp<GLinRecDual, float>(x, x_dot, K, n, y, y_dot, ws, st);
+        else dispatch_reduce_jvp<GMat2Dual, float>(x, x_dot, K, n, y, y_dot, ws, st);
+    }
+    PVJP_LAUNCHED("pvjp_reduce_generic_jvp");
+    return PVJP_OK;
+}
+
+extern "C" pvjp_status pvjp_scan_generic_jvp(pvjp_gop op, pvjp_dtype dtype, const void* const* x,
+                                             const void* const* x_dot, int64_t n, void* const* y, void* const* y_dot,
+                                             void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    const pvjp_status s = check_jvp("pvjp_scan_generic_jvp", op, dtype, x, x_dot, n, y, y_dot, ws, ws_bytes,
+                                    pvjp_scan_generic_jvp_ws_bytes(op, dtype, n));
+    if (s != PVJP_OK) return s;
+    if (n == 0) return PVJP_OK;
+    const int K = gop_components(op);
+    for (int c = 0; c < K; ++c)
+        PVJP_REQUIRE(aligned(y[c], dsize(dtype)) && aligned(y_dot[c], dsize(dtype)),
+                     "pvjp_scan_generic_jvp: component %d of y or y_dot is misaligned", c);
+    const hipStream_t st = as_stream(stream);
+    if (dtype == PVJP_F64) {
+        if (op == PVJP_GOP_LOGADDEXP) dispatch_scan_jvp<GLaeDual, double>(x, x_dot, K, n, y, y_dot, ws, st);
+        else if (op == PVJP_GOP_LINREC) dispatch_scan_jvp<GLinRecDual, double>(x, x_dot, K, n, y, y_dot, ws, st);
+        else dispatch_scan_jvp<GMat2Dual, double>(x, x_dot, K, n, y, y_dot, ws, st);
+    } else {
+        if (op == PVJP_GOP_LOGADDEXP) dispatch_scan_jvp<GLaeDual, float>(x, x_dot, K, n, y, y_dot, ws, st);
+        else if (op == PVJP_GOP_LINREC) dispatch_scan_jvp<GLinRecDual, float>(x, x_dot, K, n, y, y_dot, ws, st);
+        else dispatch_scan_jvp<GMat2Dual, float>(x, x_dot, K, n, y, y_dot, ws, st);
+    }
+    PVJP_LAUNCHED("pvjp_scan_generic_jvp");
     return PVJP_OK;
 }

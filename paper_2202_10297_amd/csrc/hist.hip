@@ -1112,6 +1112,18 @@ static void dispatch_vjp(pvjp_op op, const int32_t* inds, const void* vs, int64_
     }
 }
 
+// Forward mode of MIN/MAX: hs[k] is a copy of vs[winner[k]], so its
+// tangent is vs_dot[winner[k]] (0 for an empty bin, whose value is the
+// constant neutral element).
+template <class T>
+__global__ __launch_bounds__(256) void hist_jvp_winner_kernel(const int32_t* __restrict__ winner, int64_t m,
+                                                              const T* __restrict__ vd, T* __restrict__ hd) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t w = winner[k];
+        hd[k] = w >= 0 ? vd[w] : T(0);
+    }
+}
+
 }  // namespace pvjp
 
 using namespace pvjp;
@@ -1170,5 +1182,45 @@ extern "C" pvjp_status pvjp_hist_vjp(pvjp_op op, pvjp_dtype dtype, const int32_t
         dispatch_vjp<float>(op, inds, vs, n, (int32_t)m, winner, p, z, hs_bar, vs_bar, accumulate,
                             as_stream(stream));
     PVJP_LAUNCHED("pvjp_hist_vjp");
+    return PVJP_OK;
+}
+
+// Forward mode (Sec. 3): ADD is linear, so hs_dot = reduce_by_index(+) of
+// vs_dot over the same bins; MIN/MAX take the winner's tangent.  MUL is not
+// offered in forward mode.
+extern "C" size_t pvjp_hist_jvp_ws_bytes(pvjp_op op, pvjp_dtype dtype, int64_t n, int64_t m) {
+    if (op != PVJP_ADD) return 0;
+    return pvjp_hist_ws_bytes(op, dtype, n, m);
+}
+
+extern "C" pvjp_status pvjp_hist_jvp(pvjp_op op, pvjp_dtype dtype, const int32_t* inds, const void* vs_dot,
+                                     int64_t n, int64_t m, const int32_t* winner, void* hs_dot, void* ws,
+                                     size_t ws_bytes, void* stream) {
+    clear_error();
+    PVJP_REQUIRE(valid_op(op), "pvjp_hist_jvp: unknown op %d", (int)op);
+    if (op == PVJP_MUL) {
+        set_error("pvjp_hist_jvp: reduce_by_index(*) has no forward mode here");
+        return PVJP_EUNSUPPORTED;
+    }
+    PVJP_REQUIRE(valid_dtype(dtype), "pvjp_hist_jvp: unknown dtype %d", (int)dtype);
+    PVJP_REQUIRE(m >= 1 && m <= kMaxBins, "pvjp_hist_jvp: m = %lld out of range [1, 2^30]", (long long)m);
+    PVJP_REQUIRE(n >= 0 && n <= INT32_MAX, "pvjp_hist_jvp: n = %lld out of range [0, 2^31)", (long long)n);
+    PVJP_REQUIRE(hs_dot != nullptr, "pvjp_hist_jvp: hs_dot is NULL");
+    if (op == PVJP_ADD) {
+        const pvjp_status s = pvjp_hist(op, dtype, inds, vs_dot, n, m, hs_dot, nullptr, nullptr, nullptr, nullptr, ws,
+                                        ws_bytes, stream);
+        if (s != PVJP_OK) set_error("pvjp_hist_jvp: %s", pvjp_last_error());
+        return s;
+    }
+    PVJP_REQUIRE(winner != nullptr, "pvjp_hist_jvp: MIN/MAX need the winners of pvjp_hist");
+    PVJP_REQUIRE(n == 0 || vs_dot != nullptr, "pvjp_hist_jvp: vs_dot is NULL");
+    const unsigned g = flat_grid(m, 256, 4);
+    if (dtype == PVJP_F64)
+        hipLaunchKernelGGL(hist_jvp_winner_kernel<double>, dim3(g), dim3(256), 0, as_stream(stream), winner, m,
+                           (const double*)vs_dot, (double*)hs_dot);
+    else
+        hipLaunchKernelGGL(hist_jvp_winner_kernel<float>, dim3(g), dim3(256), 0, as_stream(stream), winner, m,
+                           (const float*)vs_dot, (float*)hs_dot);
+    PVJP_LAUNCHED("pvjp_hist_jvp");
     return PVJP_OK;
 }

@@ -208,3 +208,22 @@ extern "C" pvjp_status pvjp_fig1_vjp(pvjp_dtype dtype, const void* x0, const voi
     PVJP_LAUNCHED("pvjp_fig1_vjp");
     return PVJP_OK;
 }
+
+// Forward mode: y_dot_i = f'(x_i) x_dot_i.  The Jacobian of an elementwise
+// unary map is diagonal, so this is the VJP kernel with x_dot in place of
+// y_bar (and assignment, not accumulation).
+extern "C" pvjp_status pvjp_map_jvp(pvjp_fn fn, pvjp_dtype dtype, const void* x, const void* x_dot, int64_t n,
+                                    void* y_dot, void* stream) {
+    clear_error();
+    PVJP_REQUIRE(valid_fn(fn), "pvjp_map_jvp: unknown fn %d", (int)fn);
+    PVJP_REQUIRE(valid_dtype(dtype), "pvjp_map_jvp: unknown dtype %d", (int)dtype);
+    PVJP_REQUIRE(n >= 0, "pvjp_map_jvp: negative n");
+    if (n == 0) return PVJP_OK;
+    PVJP_REQUIRE(x != nullptr && x_dot != nullptr && y_dot != nullptr, "pvjp_map_jvp: NULL argument");
+    if (dtype == PVJP_F64)
+        dispatch_map_vjp<double>(fn, x, x_dot, n, y_dot, 0, as_stream(stream));
+    else
+        dispatch_map_vjp<float>(fn, x, x_dot, n, y_dot, 0, as_stream(stream));
+    PVJP_LAUNCHED("pvjp_map_jvp");
+    return PVJP_OK;
+}

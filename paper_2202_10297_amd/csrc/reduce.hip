@@ -250,6 +250,86 @@ static void launch_vjp(const void* x, int64_t n, const int64_t* arg, const void*
                            (const T*)p, z, (const T*)ybar, (T*)xbar);
 }
 
+// ------------------------------------------------------------ forward mode
+// MIN/MAX: y_dot = x_dot[arg] (0 for an empty input).
+template <class T>
+__global__ void reduce_jvp_pick_kernel(const int64_t* arg, const T* __restrict__ xd, T* __restrict__ yd) {
+    const int64_t a = *arg;
+    *yd = a >= 0 ? xd[a] : T(0);
+}
+
+// MUL: with p the product of the non-zero elements and z the zero count,
+// y = p if z == 0 else 0, so y_dot = p sum_i x_dot_i / x_i (z == 0),
+// p x_dot_{i0} at the one zero i0 (z == 1), 0 (z >= 2).  One pass forms both
+// sums in FP64 (s1 over non-zeros, s0 over zeros); the last block combines
+// the block sums in a fixed order.
+struct MulJvpPart {
+    double s0, s1;
+};
+
+template <class T>
+__global__ __launch_bounds__(kRedBlock) void reduce_mul_jvp_kernel(const T* __restrict__ x, const T* __restrict__ xd,
+                                                                   int64_t n, int64_t chunk, RedHdr* hdr,
+                                                                   MulJvpPart* parts, const T* p, const int64_t* z,
+                                                                   T* yd) {
+    __shared__ double sh0[kRedBlock], sh1[kRedBlock];
+    __shared__ int s_last;
+    const int64_t lo = (int64_t)blockIdx.x * chunk;
+    const int64_t hi = (lo + chunk < n) ? lo + chunk : n;
+    double a0 = 0.0, a1 = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kRedBlock) {
+        const double v = (double)x[i], t = (double)xd[i];
+        if (v == 0.0) a0 += t;
+        else a1 += t / v;
+    }
+    sh0[threadIdx.x] = a0, sh1[threadIdx.x] = a1;
+    __syncthreads();
+    for (int d = kRedBlock / 2; d >= 1; d >>= 1) {
+        if ((int)threadIdx.x < d) {
+            sh0[threadIdx.x] += sh0[threadIdx.x + d];
+            sh1[threadIdx.x] += sh1[threadIdx.x + d];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(&parts[blockIdx.x].s0, sh0[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&parts[blockIdx.x].s1, sh1[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t d = __hip_atomic_fetch_add(&hdr->done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (d == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!s_last || threadIdx.x != 0) return;
+    double s0 = 0.0, s1 = 0.0;
+    for (unsigned b = 0; b < gridDim.x; ++b) {
+        s0 += __hip_atomic_load(&parts[b].s0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s1 += __hip_atomic_load(&parts[b].s1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const int64_t zc = *z;
+    const double pv = (double)*p;
+    *yd = (T)(zc == 0 ? pv * s1 : (zc == 1 ? pv * s0 : 0.0));
+    __hip_atomic_store(&hdr->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+static_assert(sizeof(MulJvpPart) <= sizeof(RedPart), "the MUL forward mode reuses the reduce partial slots");
+
+template <class T>
+static void launch_reduce_jvp(pvjp_op op, const void* x, const void* xd, int64_t n, const int64_t* arg,
+                              const void* p, const int64_t* z, void* yd, void* ws, hipStream_t st) {
+    if (op == PVJP_ADD) {
+        launch_reduce<T, PVJP_ADD>(xd, n, yd, nullptr, nullptr, nullptr, ws, st);
+    } else if (op == PVJP_MUL) {
+        const int64_t g = red_grid(n);
+        const int64_t chunk = n > 0 ? ceil_div(n, g) : 1;
+        const int64_t g2 = n > 0 ? ceil_div(n, chunk) : 1;
+        auto* hdr = reinterpret_cast<RedHdr*>(ws);
+        auto* parts = reinterpret_cast<MulJvpPart*>(reinterpret_cast<char*>(ws) + sizeof(RedHdr));
+        hipLaunchKernelGGL(reduce_mul_jvp_kernel<T>, dim3((unsigned)g2), dim3(kRedBlock), 0, st, (const T*)x,
+                           (const T*)xd, n, chunk, hdr, parts, (const T*)p, z, (T*)yd);
+    } else {
+        hipLaunchKernelGGL(reduce_jvp_pick_kernel<T>, dim3(1), dim3(1), 0, st, arg, (const T*)xd, (T*)yd);
+    }
+}
+
 template <class T>
 static void dispatch_reduce(pvjp_op op, const void* x, int64_t n, void* y, int64_t* arg, void* p,
                             int64_t* z, void* ws, hipStream_t st) {
@@ -323,5 +403,32 @@ extern "C" pvjp_status pvjp_reduce_vjp(pvjp_op op, pvjp_dtype dtype, const void*
     else
         dispatch_vjp<float>(op, x, n, arg, p, z, y_bar, x_bar, accumulate, as_stream(stream));
     PVJP_LAUNCHED("pvjp_reduce_vjp");
+    return PVJP_OK;
+}
+
+extern "C" pvjp_status pvjp_reduce_jvp(pvjp_op op, pvjp_dtype dtype, const void* x, const void* x_dot, int64_t n,
+                                       const int64_t* arg, const void* p, const int64_t* z, void* y_dot, void* ws,
+                                       size_t ws_bytes, void* stream) {
+    clear_error();
+    PVJP_REQUIRE(valid_op(op), "pvjp_reduce_jvp: unknown op %d", (int)op);
+    PVJP_REQUIRE(valid_dtype(dtype), "pvjp_reduce_jvp: unknown dtype %d", (int)dtype);
+    PVJP_REQUIRE(n >= 0, "pvjp_reduce_jvp: n = %lld is negative", (long long)n);
+    PVJP_REQUIRE(y_dot != nullptr && (n == 0 || x_dot != nullptr), "pvjp_reduce_jvp: x_dot and y_dot must be non-NULL");
+    PVJP_REQUIRE(op != PVJP_MUL || ((n == 0 || x != nullptr) && p != nullptr && z != nullptr),
+                 "pvjp_reduce_jvp: MUL needs x, p and z");
+    PVJP_REQUIRE(!(op == PVJP_MIN || op == PVJP_MAX) || arg != nullptr, "pvjp_reduce_jvp: MIN/MAX need arg");
+    if (op == PVJP_ADD || op == PVJP_MUL) {
+        PVJP_REQUIRE(ws != nullptr && aligned(ws, 256), "pvjp_reduce_jvp: ws must be non-NULL and 256-byte aligned");
+        const size_t need = pvjp_reduce_ws_bytes(op, dtype, n);
+        if (ws_bytes < need) {
+            set_error("pvjp_reduce_jvp: workspace has %zu bytes, needs %zu", ws_bytes, need);
+            return PVJP_ENOMEM;
+        }
+    }
+    if (dtype == PVJP_F64)
+        launch_reduce_jvp<double>(op, x, x_dot, n, arg, p, z, y_dot, ws, as_stream(stream));
+    else
+        launch_reduce_jvp<float>(op, x, x_dot, n, arg, p, z, y_dot, ws, as_stream(stream));
+    PVJP_LAUNCHED("pvjp_reduce_jvp");
     return PVJP_OK;
 }

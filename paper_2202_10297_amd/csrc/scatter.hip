@@ -101,3 +101,14 @@ extern "C" pvjp_status pvjp_scatter_vjp(pvjp_dtype dtype, void* ys_bar, int64_t 
     PVJP_LAUNCHED("pvjp_scatter_vjp");
     return PVJP_OK;
 }
+
+// Forward mode: ys is a copy of xs with ys[is[j]] = vs[j], so its tangent is
+// x_dot with the same assignment of v_dot: the primal scatter applied to the
+// tangents, in place on ys_dot (which holds x_dot on entry).
+extern "C" pvjp_status pvjp_scatter_jvp(pvjp_dtype dtype, void* ys_dot, int64_t n, const int32_t* is,
+                                        const void* vs_dot, int64_t m, void* stream) {
+    clear_error();
+    const pvjp_status s = pvjp_scatter(dtype, ys_dot, n, is, vs_dot, m, nullptr, stream);
+    if (s != PVJP_OK) set_error("pvjp_scatter_jvp: %s", pvjp_last_error());
+    return s;
+}

@@ -348,3 +348,70 @@ def gmm_vjp(X, alpha, mu, q, l, lse=None, ell_bar=1.0, out=None, accumulate=Fals
     capi.call("pvjp_gmm_vjp", _ptr(X), N, D, K, _ptr(alpha), _ptr(mu), _ptr(q), _ptr(l), float(ell_bar), _ptr(lse),
               _ptr(s), _ptr(ab), _ptr(mb), _ptr(qb), _ptr(lb), int(accumulate), _ptr(ws), ws.numel(), _stream(dev))
     return ab, mb, qb, lb
+
+
+# ------------------------------------------------------------ forward mode
+def map_jvp(fn, x, x_dot):
+    """y_dot = f'(x) x_dot."""
+    y_dot = torch.empty_like(x)
+    capi.call("pvjp_map_jvp", _fn(fn), _dt(x), _ptr(x), _ptr(x_dot), x.numel(), _ptr(y_dot), _stream(x.device))
+    return y_dot
+
+
+def reduce_jvp(op, x, aux, x_dot):
+    """Tangent of reduce(op) x (aux from reduce() on the same x)."""
+    o, dt, n = _op(op), _dt(x), x.numel()
+    yd = torch.empty(1, dtype=x.dtype, device=x.device)
+    nb = capi.lib().pvjp_reduce_ws_bytes(o, dt, n)
+    ws = WS.get("reduce", nb, x.device)
+    capi.call("pvjp_reduce_jvp", o, dt, _ptr(x), _ptr(x_dot), n, _ptr(aux.get("arg")), _ptr(aux.get("p")),
+              _ptr(aux.get("z")), _ptr(yd), _ptr(ws), ws.numel(), _stream(x.device))
+    return yd
+
+
+def hist_jvp(op, inds, vs_dot, m, aux=None):
+    """Tangent of reduce_by_index(op) (aux with "winner" for min/max)."""
+    o, dt, n = _op(op), _dt(vs_dot), vs_dot.numel()
+    hd = torch.empty(m, dtype=vs_dot.dtype, device=vs_dot.device)
+    nb = capi.lib().pvjp_hist_jvp_ws_bytes(o, dt, n, m)
+    ws = WS.get("hist", nb, vs_dot.device) if nb else None
+    capi.call("pvjp_hist_jvp", o, dt, _ptr(inds), _ptr(vs_dot), n, m, _ptr((aux or {}).get("winner")), _ptr(hd),
+              _ptr(ws), ws.numel() if ws is not None else 0, _stream(vs_dot.device))
+    return hd
+
+
+def scatter_jvp_(ys_dot, is_, vs_dot):
+    """In place on ys_dot (x_dot on entry)."""
+    capi.call("pvjp_scatter_jvp", _dt(ys_dot), _ptr(ys_dot), ys_dot.numel(), _ptr(is_), _ptr(vs_dot), is_.numel(),
+              _stream(ys_dot.device))
+    return ys_dot
+
+
+def reduce_generic_jvp(op, xs, xs_dot):
+    """(ys, ys_dot): K one-element tensors each."""
+    xs, n, K = _components(op, xs)
+    xd, _, _ = _components(op, xs_dot)
+    dt, dev = _dt(xs[0]), xs[0].device
+    ys = [torch.empty(1, dtype=xs[0].dtype, device=dev) for _ in range(K)]
+    yds = [torch.empty(1, dtype=xs[0].dtype, device=dev) for _ in range(K)]
+    nb = capi.lib().pvjp_reduce_generic_jvp_ws_bytes(_gop(op), dt, n)
+    ws = WS.get("reduce_generic_jvp", nb, dev)
+    capi.call("pvjp_reduce_generic_jvp", _gop(op), dt, capi.ptr_array([_ptr(x) for x in xs]),
+              capi.ptr_array([_ptr(x) for x in xd]), n, capi.ptr_array([_ptr(y) for y in ys]),
+              capi.ptr_array([_ptr(y) for y in yds]), _ptr(ws), ws.numel(), _stream(dev))
+    return ys, yds
+
+
+def scan_generic_jvp(op, xs, xs_dot):
+    """(ys, ys_dot): K tensors of n each."""
+    xs, n, K = _components(op, xs)
+    xd, _, _ = _components(op, xs_dot)
+    dt, dev = _dt(xs[0]), xs[0].device
+    ys = [torch.empty_like(x) for x in xs]
+    yds = [torch.empty_like(x) for x in xs]
+    nb = capi.lib().pvjp_scan_generic_jvp_ws_bytes(_gop(op), dt, n)
+    ws = WS.get("scan_generic_jvp", nb, dev)
+    capi.call("pvjp_scan_generic_jvp", _gop(op), dt, capi.ptr_array([_ptr(x) for x in xs]),
+              capi.ptr_array([_ptr(x) for x in xd]), n, capi.ptr_array([_ptr(y) for y in ys]),
+              capi.ptr_array([_ptr(y) for y in yds]), _ptr(ws), ws.numel(), _stream(dev))
+    return ys, yds

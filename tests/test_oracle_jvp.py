@@ -117,3 +117,17 @@ def test_generic_jvp_finite_differences(orc):
     assert rel_l2(orc.scan_generic_jvp("logaddexp", [x], [xd]), [fds]) <= 1e-8
     # the tangent of a log-sum-exp prefix with all tangents 1 is 1
     assert np.allclose(orc.scan_generic_jvp("logaddexp", [x], [np.ones(30)])[0], 1.0, rtol=1e-14)
+
+
+@pytest.mark.parametrize("op", ["logaddexp", "linrec", "mat2"])
+def test_scan_jvp_window_from_a_prefix_state(orc, op):
+    # with tangents zero before a window, the window's output tangents come
+    # from the fold started at the state of everything before it
+    n, w = 300, 100
+    xs, _ = workloads.gop_scan(op, n, seed=41)
+    g = _g(42)
+    xd = [np.concatenate([np.zeros(n - w), g.standard_normal(w)]) for _ in xs]
+    full = orc.scan_generic_jvp(op, xs, xd)
+    init = orc.reduce_generic(op, [x[:n - w] for x in xs])
+    win = orc.scan_generic_jvp(op, [x[n - w:] for x in xs], [t[n - w:] for t in xd], init=init)
+    assert rel_l2(win, [f[n - w:] for f in full]) <= 1e-13
