@@ -1,5 +1,6 @@
 """torch.autograd.Function wrappers: each operator's primal and VJP kernels as
-one differentiable op.
+one differentiable op (and, for map, reduce and the general-operator reduce
+and scan, the JVP kernels for torch's forward-mode AD).
 
 Forward saves only the inputs and the small auxiliary results the return
 sweep needs (scan checkpoints, argmax indices, zero counts and non-zero
@@ -42,6 +43,7 @@ class Reduce(torch.autograd.Function):
         ctx.op = op
         ctx.aux_keys = tuple(aux)
         ctx.save_for_backward(x, *aux.values())
+        ctx.save_for_forward(x, *aux.values())
         return y.reshape(())
 
     @staticmethod
@@ -50,6 +52,12 @@ class Reduce(torch.autograd.Function):
         aux = dict(zip(ctx.aux_keys, vals))
         xb = ops.reduce_vjp(ctx.op, x, aux, gy.reshape(1).contiguous())
         return xb, None
+
+    @staticmethod
+    def jvp(ctx, xd, _op):
+        x, *vals = ctx.saved_tensors
+        aux = dict(zip(ctx.aux_keys, vals))
+        return ops.reduce_jvp(ctx.op, x, aux, xd.contiguous()).reshape(())
 
 
 class ReduceGeneric(torch.autograd.Function):
@@ -64,7 +72,15 @@ class ReduceGeneric(torch.autograd.Function):
         ys, ck = ops.reduce_generic(op, xs, ckpt=True)
         ctx.op = op
         ctx.save_for_backward(ck, *xs)
+        ctx.save_for_forward(ck, *xs)  # the same list, whichever sweep reads it
         return tuple(y.reshape(()) for y in ys)
+
+    @staticmethod
+    def jvp(ctx, _op, *xds):
+        xs = ctx.saved_tensors[1:]
+        xds = [torch.zeros_like(x) if t is None else t.contiguous() for t, x in zip(xds, xs)]
+        _, yds = ops.reduce_generic_jvp(ctx.op, xs, xds)
+        return tuple(y.reshape(()) for y in yds)
 
     @staticmethod
     def backward(ctx, *gys):
@@ -85,7 +101,15 @@ class ScanGeneric(torch.autograd.Function):
         ys, ck = ops.scan_generic(op, xs, ckpt=True)
         ctx.op = op
         ctx.save_for_backward(ck, *xs)
+        ctx.save_for_forward(ck, *xs)  # the same list, whichever sweep reads it
         return tuple(ys)
+
+    @staticmethod
+    def jvp(ctx, _op, *xds):
+        xs = ctx.saved_tensors[1:]
+        xds = [torch.zeros_like(x) if t is None else t.contiguous() for t, x in zip(xds, xs)]
+        _, yds = ops.scan_generic_jvp(ctx.op, xs, xds)
+        return tuple(yds)
 
     @staticmethod
     def backward(ctx, *gys):
@@ -142,12 +166,18 @@ class Map(torch.autograd.Function):
         x = x.contiguous()
         ctx.fn = fn
         ctx.save_for_backward(x)
+        ctx.save_for_forward(x)
         return ops.map_(fn, x)
 
     @staticmethod
     def backward(ctx, gy):
         (x,) = ctx.saved_tensors
         return ops.map_vjp(ctx.fn, x, gy.contiguous()), None
+
+    @staticmethod
+    def jvp(ctx, xd, _fn):
+        (x,) = ctx.saved_tensors
+        return ops.map_jvp(ctx.fn, x, xd.contiguous())
 
 
 class GMMLogLik(torch.autograd.Function):

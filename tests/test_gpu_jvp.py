@@ -187,3 +187,25 @@ def test_generic_jvp_vjp_dot_product(ops, op):
     lhs = sum(float(np.dot(a, host(b))) for a, b in zip(ybs, yds))
     rhs = sum(float(np.dot(host(a), b)) for a, b in zip(xb, xd))
     assert abs(lhs - rhs) <= 1e-10 * max(1.0, abs(lhs))
+
+
+def test_torch_forward_mode(orc):
+    # torch.autograd.forward_ad reaches the JVP kernels through the
+    # autograd Functions
+    import torch.autograd.forward_ad as fwAD
+
+    from paper_2202_10297_amd import autograd
+
+    g = workloads.rng(21)
+    x = g.uniform(0.5, 2.0, 5001)
+    xd = g.standard_normal(5001)
+    with fwAD.dual_level():
+        y = autograd.map(fwAD.make_dual(dev(x), dev(xd)), "exp")
+        assert rel_l2(host(fwAD.unpack_dual(y).tangent), orc.map_jvp("exp", x, xd)) <= TOL_F64
+        r = autograd.reduce(fwAD.make_dual(dev(x), dev(xd)), "max")
+        assert host(fwAD.unpack_dual(r).tangent) == orc.reduce_jvp("max", x, xd)
+        xs, _ = workloads.gop("mat2", 3000, "f64", seed=22)
+        ts = [g.standard_normal(3000) for _ in xs]
+        outs = autograd.scan_generic("mat2", *[fwAD.make_dual(dev(a), dev(t)) for a, t in zip(xs, ts)])
+        got = [host(fwAD.unpack_dual(o).tangent) for o in outs]
+        assert rel_l2(got, orc.scan_generic_jvp("mat2", xs, ts)) <= TOL_F64
