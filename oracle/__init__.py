@@ -62,6 +62,9 @@ _SIGS = {
     "orc_reduce_generic_jvp": [_I, _L, _P, _P, _P],
     "orc_scan_generic_jvp": [_I, _L, _P, _P, _P],
     "orc_scan_generic_jvp_from": [_I, _L, _P, _P, _P, _P],
+    "orc_kmeans_objective": [_L, _I, _I, _P, _P, _P, _P],
+    "orc_kmeans_vjp": [_L, _I, _I, _P, _P, _D, _P],
+    "orc_kmeans_hvp": [_L, _I, _I, _P, _P, _D, _P, _P],
 }
 
 
@@ -370,4 +373,32 @@ def scan_generic_jvp(op, xs, xs_dot, init=None):
     out, optr = _arrays(K, n)
     ini = None if init is None else _f64(init).reshape(K)
     _check(lib().orc_scan_generic_jvp_from(_gop(op), n, _p(ini), ptrs, dptrs, optr), "scan_generic_jvp")
+    return out
+
+
+# ------------------------------------------------------------------ k-means
+def kmeans_objective(X, C):
+    """(f, assign [N] int32)."""
+    X, C = _f64(X), _f64(C)
+    N, D = X.shape
+    K = C.shape[0]
+    a = np.empty(N, dtype=np.int32)
+    f = ctypes.c_double()
+    _check(lib().orc_kmeans_objective(N, D, K, _p(X), _p(C), _p(a), ctypes.byref(f)), "kmeans_objective")
+    return f.value, a
+
+
+def kmeans_vjp(X, C, f_bar=1.0):
+    X, C = _f64(X), _f64(C)
+    N, D = X.shape
+    out = np.empty_like(C)
+    _check(lib().orc_kmeans_vjp(N, D, C.shape[0], _p(X), _p(C), float(f_bar), _p(out)), "kmeans_vjp")
+    return out
+
+
+def kmeans_hvp(X, C, C_dot, f_bar=1.0):
+    X, C, Cd = _f64(X), _f64(C), _f64(C_dot)
+    N, D = X.shape
+    out = np.empty_like(C)
+    _check(lib().orc_kmeans_hvp(N, D, C.shape[0], _p(X), _p(C), float(f_bar), _p(Cd), _p(out)), "kmeans_hvp")
     return out

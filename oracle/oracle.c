@@ -1225,3 +1225,128 @@ int orc_scan_generic_jvp_from(int op, int64_t n, const double* init, const doubl
     tape_free(t);
     return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Dense k-means (Sec. 7.4): f(C) = sum_i min_k |x_i - c_k|^2 (squared        */
+/* distance: the reading under which the Hessian is diagonal).  X is N x D,   */
+/* C is K x D, row-major.  The distance is the fused chain                    */
+/* acc = fma(x_d - c_d, x_d - c_d, acc) over d = 0..D-1 in FP64, so that the  */
+/* assignment (lowest k among equal distances) is decided on exactly the     */
+/* values any implementation of the same chain computes.                     */
+/* ------------------------------------------------------------------------ */
+
+static double km_dist(int D, const double* x, const double* c) {
+    double acc = 0.0;
+    for (int d = 0; d < D; ++d) {
+        double t = x[d] - c[d];
+        acc = fma(t, t, acc);
+    }
+    return acc;
+}
+
+static void km_assign(int64_t N, int D, int K, const double* X, const double* C, int32_t* a, double* dmin) {
+    for (int64_t i = 0; i < N; ++i) {
+        int best = 0;
+        double bd = km_dist(D, X + i * D, C);
+        for (int k = 1; k < K; ++k) {
+            double dk = km_dist(D, X + i * D, C + (int64_t)k * D);
+            if (dk < bd) bd = dk, best = k;
+        }
+        a[i] = best;
+        if (dmin) dmin[i] = bd;
+    }
+}
+
+int orc_kmeans_objective(int64_t N, int D, int K, const double* X, const double* C, int32_t* assign,
+                         double* f) {
+    if (N < 0 || D < 1 || K < 1 || (N > 0 && !X) || !C || !f) return -1;
+    int32_t* a = assign ? assign : (int32_t*)malloc((size_t)(N > 0 ? N : 1) * sizeof(int32_t));
+    double* dm = (double*)malloc((size_t)(N > 0 ? N : 1) * sizeof(double));
+    if (!a || !dm) {
+        if (!assign) free(a);
+        free(dm);
+        return -2;
+    }
+    km_assign(N, D, K, X, C, a, dm);
+    double s = 0.0;
+    for (int64_t i = 0; i < N; ++i) s += dm[i];
+    *f = s;
+    if (!assign) free(a);
+    free(dm);
+    return 0;
+}
+
+/* Gradient for fixed assignments a: f is a sum of independent per-point
+ * terms |x_i - c_{a_i}|^2, so each term is recorded on a small tape of its
+ * own, swept, and its adjoint added to the centre's (the adjoint of a sum
+ * reaches every term unchanged). */
+static int km_grad_fixed(int64_t N, int D, int K, const double* X, const double* C, const int32_t* a,
+                         double f_bar, double* C_bar) {
+    for (int64_t e = 0; e < (int64_t)K * D; ++e) C_bar[e] = 0.0;
+    tape_t T, *t = &T;
+    if (tape_init(t, 4 * D + 16, 4 * D + 16)) return -2;
+    int64_t* sc = (int64_t*)malloc((size_t)D * sizeof(int64_t));
+    if (!sc) {
+        tape_free(t);
+        return -2;
+    }
+    for (int64_t i = 0; i < N; ++i) {
+        const double* c = C + (int64_t)a[i] * D;
+        tape_clear(t);
+        int64_t acc = -1;
+        for (int d = 0; d < D; ++d) {
+            sc[d] = leaf(t, c[d]);
+            int64_t xd = leaf(t, X[i * D + d]); /* a constant */
+            int64_t df = t_sub(t, xd, sc[d]);
+            int64_t sq = t_mul(t, df, df);
+            acc = (acc < 0) ? sq : t_add(t, acc, sq);
+        }
+        if (t->oom || tape_reverse(t)) {
+            free(sc);
+            tape_free(t);
+            return -2;
+        }
+        t->adj[acc] += f_bar;
+        sweep(t);
+        for (int d = 0; d < D; ++d) C_bar[(int64_t)a[i] * D + d] += t->adj[sc[d]];
+    }
+    free(sc);
+    tape_free(t);
+    return 0;
+}
+
+int orc_kmeans_vjp(int64_t N, int D, int K, const double* X, const double* C, double f_bar, double* C_bar) {
+    if (N < 0 || D < 1 || K < 1 || (N > 0 && !X) || !C || !C_bar) return -1;
+    int32_t* a = (int32_t*)malloc((size_t)(N > 0 ? N : 1) * sizeof(int32_t));
+    if (!a) return -2;
+    km_assign(N, D, K, X, C, a, NULL);
+    int rc = km_grad_fixed(N, D, K, X, C, a, f_bar, C_bar);
+    free(a);
+    return rc;
+}
+
+/* jvp of the vjp in direction C_dot (Sec. 7.4): the assignments are locally
+ * constant, so the gradient is an affine function of C and its directional
+ * derivative is its central difference with a unit step, exact up to
+ * rounding: (g(C + C_dot) - g(C - C_dot)) / 2 with the assignment of C. */
+int orc_kmeans_hvp(int64_t N, int D, int K, const double* X, const double* C, double f_bar,
+                   const double* C_dot, double* out) {
+    if (N < 0 || D < 1 || K < 1 || (N > 0 && !X) || !C || !C_dot || !out) return -1;
+    const int64_t KD = (int64_t)K * D;
+    int32_t* a = (int32_t*)malloc((size_t)(N > 0 ? N : 1) * sizeof(int32_t));
+    double* cp = (double*)malloc((size_t)KD * sizeof(double));
+    double* cm = (double*)malloc((size_t)KD * sizeof(double));
+    double* gp = (double*)malloc((size_t)KD * sizeof(double));
+    double* gm = (double*)malloc((size_t)KD * sizeof(double));
+    int rc = (a && cp && cm && gp && gm) ? 0 : -2;
+    if (!rc) {
+        km_assign(N, D, K, X, C, a, NULL);
+        for (int64_t e = 0; e < KD; ++e) cp[e] = C[e] + C_dot[e], cm[e] = C[e] - C_dot[e];
+        rc = km_grad_fixed(N, D, K, X, cp, a, f_bar, gp);
+        if (!rc) rc = km_grad_fixed(N, D, K, X, cm, a, f_bar, gm);
+        if (!rc)
+            for (int64_t e = 0; e < KD; ++e) out[e] = 0.5 * (gp[e] - gm[e]);
+    }
+    free(a), free(cp), free(cm), free(gp), free(gm);
+    return rc;
+}

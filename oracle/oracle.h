@@ -147,6 +147,19 @@ int orc_scan_generic_jvp(int op, int64_t n, const double* const* x, const double
 int orc_scan_generic_jvp_from(int op, int64_t n, const double* init, const double* const* x,
                               const double* const* x_dot, double* const* y_dot);
 
+/* Dense k-means (Sec. 7.4) with the squared distance: f(C) = sum_i
+ * min_k |x_i - c_k|^2; X [N x D], C [K x D] row-major.  Distances are the
+ * FP64 chain acc = fma(x_d - c_d, x_d - c_d, acc), d = 0..D-1; ties go to the
+ * lowest k.  assign (nullable) [N].  The VJP tapes each point's term
+ * separately (f is a sum of per-point terms); the jvp of the VJP in
+ * direction C_dot (the Hessian-vector product) is the unit-step central
+ * difference of the gradient at fixed assignments, exact for a quadratic. */
+int orc_kmeans_objective(int64_t N, int D, int K, const double* X, const double* C, int32_t* assign,
+                         double* f);
+int orc_kmeans_vjp(int64_t N, int D, int K, const double* X, const double* C, double f_bar, double* C_bar);
+int orc_kmeans_hvp(int64_t N, int D, int K, const double* X, const double* C, double f_bar,
+                   const double* C_dot, double* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,6 +17,8 @@ measured on:
 * Gaussian mixture: X ~ N(0,1), alpha ~ N(0,1), mu ~ N(0,1), q and l ~
   N(0, 0.1) (standard deviation 0.1);
 * segmented batches: lengths floor(exp(U[ln lo, ln hi]));
+* k-means: K well-separated blobs (centres ~ N(0, 9), points = centre +
+  N(0, 1)), initial centres = K distinct points drawn without replacement;
 * reduce with a general operator: log-add-exp values ~ N(0, 1); linear-
   recurrence pairs as for the scan; 2x2 matrices that are rotations, each
   composed with the reflection diag(1, -1) with probability 1/2, so that
@@ -165,3 +167,16 @@ def gop_scan(op: str, n: int, dtype="f64", seed: int = 0, general: bool = False)
     g = rng(seed + 7777)
     dt = _dt(dtype)
     return xs, [g.standard_normal(n).astype(dt) for _ in xs]
+
+
+def kmeans(N: int, D: int, K: int, dtype="f32", seed: int = 0):
+    """(X [N, D], C [K, D]) for k-means: points around K random blob centres,
+    initial centres = K distinct points."""
+    g = rng(seed)
+    dt = _dt(dtype)
+    centres = g.standard_normal((K, D)) * 3.0
+    lab = g.integers(0, K, N)
+    X = (centres[lab] + g.standard_normal((N, D))).astype(dt)
+    pick = g.choice(N, size=K, replace=False) if N >= K else np.arange(N)
+    C = X[pick].copy()
+    return X, C
