@@ -48,8 +48,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 23, help="elements per instance for the CPU oracle")
-    ap.add_argument("--skip", default="", help="comma list of extra workloads to skip: reduce_map,reduce_generic,scan_generic,jvp,scan,gmm,batch,"
-                         "serve")
+    ap.add_argument("--skip", default="", help="comma list of extra workloads to skip: reduce_map,reduce_generic,scan_generic,jvp,kmeans,scan,"
+                         "gmm,batch,serve")
     ap.add_argument("--only", default="",
                     help="run just this one extra workload (for profiling) and print its JSON instead of the "
                          "benchmark line")
@@ -221,7 +221,7 @@ def main():
     L = capi.lib()
     if args.only:
         fns = {"reduce_map": bench_reduce_map, "reduce_generic": bench_reduce_generic,
-               "scan_generic": bench_scan_generic, "jvp": bench_jvp, "scan": bench_scan,
+               "scan_generic": bench_scan_generic, "jvp": bench_jvp, "kmeans": bench_kmeans, "scan": bench_scan,
                "gmm": bench_gmm, "batch": bench_batch, "serve": bench_serve}
         print(json.dumps({args.only: fns[args.only](args)}))
         return
@@ -382,8 +382,8 @@ def main():
     torch.cuda.empty_cache()
     extra = {}
     for name, fn in (("reduce_map", bench_reduce_map), ("reduce_generic", bench_reduce_generic),
-                     ("scan_generic", bench_scan_generic), ("jvp", bench_jvp), ("scan", bench_scan),
-                     ("gmm", bench_gmm),
+                     ("scan_generic", bench_scan_generic), ("jvp", bench_jvp), ("kmeans", bench_kmeans),
+                     ("scan", bench_scan), ("gmm", bench_gmm),
                      ("batch", bench_batch), ("serve", bench_serve)):
         if name in args.skip:
             continue
@@ -750,6 +750,33 @@ def bench_jvp(args):
                                     "scan_ms": round(ts, 4), "scan_hbm_frac": rate(4 * K * es * n, ts)}
             del xs, xds
             torch.cuda.empty_cache()
+    return res
+
+
+def bench_kmeans(args):
+    """Dense k-means at the paper's shapes (k, n, d) = (5, 494019, 35) and
+    (1024, 10000, 256): the objective (nearest-centre search, FP64 distance
+    chains), the gradient from the kept assignments, and the gradient with the
+    jvp of the VJP (Hessian diagonal) in the same pass.  The search does
+    n k d FP64 FMAs."""
+    import torch
+
+    from paper_2202_10297_amd import ops, workloads
+
+    res = {}
+    for K, N, D in ((5, 494019, 35), (1024, 10000, 256)):
+        X, C = workloads.kmeans(N, D, K, "f32", seed=0)
+        Xd, Cd = torch.from_numpy(X).cuda(), torch.from_numpy(C).cuda()
+        _, a = ops.kmeans_objective(Xd, Cd)
+        ones = torch.ones_like(Cd)
+        out = (torch.empty_like(Cd), torch.empty_like(Cd))
+        tf = _events_ms(lambda: ops.kmeans_objective(Xd, Cd), 10)
+        tg = _events_ms(lambda: ops.kmeans_vjp(Xd, Cd, a, out=(out[0], None)), 10)
+        th = _events_ms(lambda: ops.kmeans_vjp(Xd, Cd, a, C_dot=ones, out=out), 10)
+        res[f"k{K}_n{N}_d{D}"] = {
+            "objective_ms": round(tf, 4), "gradient_ms": round(tg, 4), "gradient_and_hessian_diag_ms": round(th, 4),
+            "search_fp64_TFLOPs": round(2 * N * K * D / (tf * 1e-3) / 1e12, 2),
+            "newton_step_ms": round(tf + th, 4)}
     return res
 
 

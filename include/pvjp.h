@@ -435,6 +435,32 @@ pvjp_status pvjp_gmm_vjp(const float* X, int64_t N, int D, int K, const float* a
                          float* q_bar, float* l_bar, int accumulate, void* ws, size_t ws_bytes,
                          void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* Dense k-means (Sec. 7.4): f(C) = sum_i min_k |x_i - c_k|^2 (squared        */
+/* distance), X [N x D] and C [K x D] row-major FP32, 1 <= D <= 1024.         */
+/* Distances are the FP64 chain acc = fma(x_d - c_d, x_d - c_d, acc) over     */
+/* d = 0..D-1; the nearest centre is the lowest k among equal distances.      */
+/* ------------------------------------------------------------------------ */
+
+/* Workspace bytes for both entry points (device, caller-owned, 256-byte
+ * aligned, no initialisation needed). */
+size_t pvjp_kmeans_ws_bytes(int64_t N, int D, int K);
+/* assign [N] int32 (output, the primal's auxiliary result: each point's
+ * nearest centre); f: device double (output), summed in a fixed order. */
+pvjp_status pvjp_kmeans_objective(const float* X, int64_t N, int D, const float* C, int K,
+                                  int32_t* assign, double* f, void* ws, size_t ws_bytes, void* stream);
+/* Reverse sweep with output adjoint f_bar and the assignments of
+ * pvjp_kmeans_objective (the search is not repeated):
+ *   C_bar_k (+)= 2 f_bar (n_k c_k - S_k),  S_k = sum_{a_i = k} x_i, n_k the
+ *   number of points of centre k (accumulated in FP64, fixed order).
+ * Forward over reverse (nullable pair): with C_dot [K x D], hvp (+)= the jvp
+ * of this VJP in direction C_dot, 2 f_bar n_k C_dot_k (the Hessian is
+ * diagonal: C_dot = 1 gives its diagonal, and C - C_bar / diagonal is the
+ * Newton step). */
+pvjp_status pvjp_kmeans_vjp(const float* X, int64_t N, int D, const float* C, int K,
+                            const int32_t* assign, double f_bar, float* C_bar, const float* C_dot,
+                            float* hvp, int accumulate, void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

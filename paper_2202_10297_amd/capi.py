@@ -70,6 +70,9 @@ SIGNATURES = {
     "pvjp_seg_prepare": (_I, [_P, _L, _I, _P, _Z, _P]),
     "pvjp_seg_linrec_scan": (_I, [_I, _P, _P, _L, _L, _I, _P, _P, _P, _P, _Z, _P]),
     "pvjp_seg_batch_vjp": (_I, [_I, _P, _P, _P, _P, _L, _L, _I, _P, _P, _P, _P, _P, _I, _I, _P, _Z, _P]),
+    "pvjp_kmeans_ws_bytes": (_Z, [_L, _I, _I]),
+    "pvjp_kmeans_objective": (_I, [_P, _L, _I, _P, _I, _P, _P, _P, _Z, _P]),
+    "pvjp_kmeans_vjp": (_I, [_P, _L, _I, _P, _I, _P, ctypes.c_double, _P, _P, _P, _I, _P, _Z, _P]),
     "pvjp_gmm_ws_bytes": (_Z, [_L, _I, _I]),
     "pvjp_gmm_objective": (_I, [_P, _L, _I, _I, _P, _P, _P, _P, _P, _P, _P, _P, _Z, _P]),
     "pvjp_gmm_vjp": (_I, [_P, _L, _I, _I, _P, _P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _P, _P, _I, _P, _Z,

@@ -415,3 +415,33 @@ def scan_generic_jvp(op, xs, xs_dot):
               capi.ptr_array([_ptr(x) for x in xd]), n, capi.ptr_array([_ptr(y) for y in ys]),
               capi.ptr_array([_ptr(y) for y in yds]), _ptr(ws), ws.numel(), _stream(dev))
     return ys, yds
+
+
+# ------------------------------------------------------------------ k-means
+def kmeans_objective(X, C):
+    """(f [1] float64, assign [N] int32) for f = sum_i min_k |x_i - c_k|^2."""
+    N, D = X.shape
+    K = C.shape[0]
+    dev = X.device
+    f = torch.empty(1, dtype=torch.float64, device=dev)
+    a = torch.empty(N, dtype=torch.int32, device=dev)
+    nb = capi.lib().pvjp_kmeans_ws_bytes(N, D, K)
+    ws = WS.get("kmeans", nb, dev)
+    capi.call("pvjp_kmeans_objective", _ptr(X), N, D, _ptr(C), K, _ptr(a), _ptr(f), _ptr(ws), ws.numel(),
+              _stream(dev))
+    return f, a
+
+
+def kmeans_vjp(X, C, assign, f_bar=1.0, C_dot=None, out=None, accumulate=False):
+    """C_bar, and with C_dot also the jvp of the VJP (Hessian-vector
+    product): returns (C_bar, hvp or None)."""
+    N, D = X.shape
+    K = C.shape[0]
+    dev = X.device
+    mk = torch.zeros_like if accumulate else torch.empty_like
+    cb, hv = out if out is not None else (mk(C), mk(C) if C_dot is not None else None)
+    nb = capi.lib().pvjp_kmeans_ws_bytes(N, D, K)
+    ws = WS.get("kmeans", nb, dev)
+    capi.call("pvjp_kmeans_vjp", _ptr(X), N, D, _ptr(C), K, _ptr(assign), float(f_bar), _ptr(cb), _ptr(C_dot),
+              _ptr(hv), int(accumulate), _ptr(ws), ws.numel(), _stream(dev))
+    return cb, hv

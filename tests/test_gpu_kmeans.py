@@ -1,0 +1,85 @@
+"""GPU parity of dense k-means (Sec. 7.4) through the C ABI against the
+oracle: the objective, the nearest-centre assignments (bit-exact: both sides
+decide on the same FP64 distance chain), the gradient and the jvp of the
+VJP (Hessian-vector product), at the paper's two workload shapes (k, n, d) =
+(5, 494019, 35) and (1024, 10000, 256) and at small and ragged sizes.
+"""
+import numpy as np
+import pytest
+
+from _util import TOL_F32, rel_l2
+from paper_2202_10297_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def ops():
+    from paper_2202_10297_amd import capi, ops as o
+
+    capi.lib()
+    return o
+
+
+CASES = [(1, 1, 1), (5, 3, 2), (100, 35, 5), (1000, 17, 33), (777, 64, 70), (3000, 256, 40),
+         (494019, 35, 5), (10000, 256, 1024)]
+
+
+@pytest.mark.parametrize("N,D,K", CASES)
+def test_kmeans_objective_gradient_hvp(ops, orc, N, D, K):
+    X, C = workloads.kmeans(N, D, K, "f32", seed=N + D + K)
+    Xd, Cd = dev(X), dev(C)
+    f, a = ops.kmeans_objective(Xd, Cd)
+    rf, ra = orc.kmeans_objective(X, C)
+    assert np.array_equal(host(a), ra)
+    assert abs(host(f)[0] - rf) <= 1e-12 * max(1.0, rf)
+    Cdot = workloads.rng(5).standard_normal(C.shape).astype(np.float32)
+    cb, hv = ops.kmeans_vjp(Xd, Cd, a, f_bar=0.5, C_dot=dev(Cdot))
+    assert rel_l2(host(cb), orc.kmeans_vjp(X, C, 0.5)) <= TOL_F32
+    assert rel_l2(host(hv), orc.kmeans_hvp(X, C, Cdot, 0.5)) <= TOL_F32
+
+
+def test_kmeans_accumulate_and_newton_step(ops, orc):
+    N, D, K = 20000, 35, 5
+    X, C = workloads.kmeans(N, D, K, "f32", seed=1)
+    Xd, Cd = dev(X), dev(C)
+    _, a = ops.kmeans_objective(Xd, Cd)
+    base = [workloads.rng(i).standard_normal(C.shape).astype(np.float32) for i in (2, 3)]
+    out = (dev(base[0]), dev(base[1]))
+    ops.kmeans_vjp(Xd, Cd, a, f_bar=1.0, C_dot=torch.ones_like(Cd), out=out, accumulate=True)
+    g = orc.kmeans_vjp(X, C, 1.0)
+    h = orc.kmeans_hvp(X, C, np.ones_like(C), 1.0)
+    assert rel_l2(host(out[0]) - base[0], g) <= 2 * TOL_F32
+    assert rel_l2(host(out[1]) - base[1], h) <= 2 * TOL_F32
+    # the Newton step with the Hessian diagonal is the mean of each cluster
+    cb, hv = ops.kmeans_vjp(Xd, Cd, a, f_bar=1.0, C_dot=torch.ones_like(Cd))
+    cbn, hvn = host(cb).astype(np.float64), host(hv).astype(np.float64)
+    an = host(a)
+    n = np.bincount(an, minlength=K)
+    S = np.zeros((K, D))
+    np.add.at(S, an, X.astype(np.float64))
+    nz = n > 0
+    newton = C - cbn / np.where(hvn == 0, 1, hvn)
+    assert rel_l2(newton[nz], (S / np.maximum(n, 1)[:, None])[nz]) <= 1e-5
+
+
+def test_kmeans_empty_input_and_ties(ops, orc):
+    X = np.array([[0.0, 0.0], [1.0, 0.0]], dtype=np.float32)
+    C = np.array([[1.0, 1.0], [1.0, -1.0], [-1.0, 1.0]], dtype=np.float32)
+    f, a = ops.kmeans_objective(dev(X), dev(C))
+    assert list(host(a)) == [0, 0] and host(f)[0] == 3.0
+    f, a = ops.kmeans_objective(dev(np.zeros((0, 2), dtype=np.float32)), dev(C))
+    assert host(f)[0] == 0.0
+    cb, _ = ops.kmeans_vjp(dev(np.zeros((0, 2), dtype=np.float32)), dev(C), a)
+    assert np.all(host(cb) == 0)
