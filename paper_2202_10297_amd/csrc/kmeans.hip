@@ -77,9 +77,26 @@ __global__ __launch_bounds__(256) void km_dist_kernel(const float* __restrict__ 
         const int dn = (D - d0) < kKmChunkD ? (D - d0) : kKmChunkD;
         if (d0 > 0) __syncthreads();  // the previous chunk has been read
         const float* xb = X + p0 * D + d0;
-        for (int e = t; e < np * dn; e += kKmPts) {
-            const int pt = e / dn, j = e - pt * dn;
-            xs[pt * kStride + j] = xb[(int64_t)pt * D + j];
+        if (dn == kKmChunkD && np == kKmPts) {
+            // thread t copies column t % 32 of rows t / 32 + 8 u, u < 32, kU
+            // loads in flight (fewer where the chains need the registers);
+            // each 32-lane group reads one contiguous 128-byte row piece
+            constexpr int kU = CPS >= 16 ? 8 : kKmChunkD;
+            const int j = t & (kKmChunkD - 1), r0 = t / kKmChunkD;
+            const uint32_t lo = (uint32_t)(r0 * D + j);  // the lane's offset from a uniform row base
+#pragma unroll
+            for (int u0 = 0; u0 < kKmChunkD; u0 += kU) {
+                float v[kU];
+#pragma unroll
+                for (int u = 0; u < kU; ++u) v[u] = (xb + (int64_t)(8 * (u0 + u)) * D)[lo];
+#pragma unroll
+                for (int u = 0; u < kU; ++u) xs[(r0 + 8 * (u0 + u)) * kStride + j] = v[u];
+            }
+        } else {
+            for (int e = t; e < np * dn; e += kKmPts) {
+                const int pt = e / dn, j = e - pt * dn;
+                xs[pt * kStride + j] = xb[(int64_t)pt * D + j];
+            }
         }
         __syncthreads();
         const double* cb = Cw + ((int64_t)s * D + d0) * CPS;
@@ -166,7 +183,26 @@ __global__ __launch_bounds__(256) void km_acc_small_kernel(const float* __restri
 #pragma unroll
     for (int k = 0; k < KM; ++k) acc[k] = 0.0, cnt[k] = 0;
     if (act) {
-        for (int64_t j = i0 + g; j < i1; j += G) {
+        constexpr int U = 8;  // points whose loads are in flight together
+        int64_t j = i0 + g;
+        for (; j + (U - 1) * (int64_t)G < i1; j += U * (int64_t)G) {
+            int32_t a[U];
+            float x[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                a[u] = assign[j + u * (int64_t)G];
+                x[u] = X[(j + u * (int64_t)G) * D + d];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+#pragma unroll
+                for (int k = 0; k < KM; ++k) {
+                    acc[k] += (a[u] == k) ? (double)x[u] : 0.0;
+                    cnt[k] += (a[u] == k) ? 1 : 0;
+                }
+            }
+        }
+        for (; j < i1; j += G) {
             const int32_t a = assign[j];
             const double x = (double)X[j * D + d];
 #pragma unroll
