@@ -32,7 +32,11 @@ def ops():
     return o
 
 
+# small and ragged sizes; K = 16 / 17 on either side of the register-accumulator
+# gradient; D > 256 (the listed-point gradient at small K) and D = 1024 (the
+# largest, 8 centres per slice); the paper's two shapes
 CASES = [(1, 1, 1), (5, 3, 2), (100, 35, 5), (1000, 17, 33), (777, 64, 70), (3000, 256, 40),
+         (3001, 40, 16), (3001, 40, 17), (2000, 300, 3), (600, 1024, 20),
          (494019, 35, 5), (10000, 256, 1024)]
 
 
