@@ -65,6 +65,8 @@ _SIGS = {
     "orc_kmeans_objective": [_L, _I, _I, _P, _P, _P, _P],
     "orc_kmeans_vjp": [_L, _I, _I, _P, _P, _D, _P],
     "orc_kmeans_hvp": [_L, _I, _I, _P, _P, _D, _P, _P],
+    "orc_gather_map": [_I, _L, _P, _L, _P, _P, _P],
+    "orc_gather_map_vjp": [_I, _L, _P, _L, _P, _P, _P, _P, _P],
 }
 
 
@@ -402,3 +404,28 @@ def kmeans_hvp(X, C, C_dot, f_bar=1.0):
     out = np.empty_like(C)
     _check(lib().orc_kmeans_hvp(N, D, C.shape[0], _p(X), _p(C), float(f_bar), _p(Cd), _p(out)), "kmeans_hvp")
     return out
+
+
+# ------------------------------------------------------------- gather map
+GMAP = {"gather": 0, "mul": 1, "sqdiff": 2}
+
+
+def gather_map(op, as_, is_, vs=None):
+    """ys[i] = f(as[is[i]], vs[i]) (Sec. 5.4: a map reading a free array)."""
+    o = GMAP[op]
+    as_, is_ = _f64(as_), _i32(is_)
+    vs = _f64(vs) if vs is not None else np.zeros(is_.size)
+    ys = np.empty(is_.size)
+    _check(lib().orc_gather_map(o, as_.size, _p(as_), is_.size, _p(is_), _p(vs), _p(ys)), "gather_map")
+    return ys
+
+
+def gather_map_vjp(op, as_, is_, vs, ys_bar):
+    """(as_bar, vs_bar or None): the read's adjoints accumulated into as_bar."""
+    o = GMAP[op]
+    as_, is_, yb = _f64(as_), _i32(is_), _f64(ys_bar)
+    vs = _f64(vs) if vs is not None else np.zeros(is_.size)
+    ab, vb = np.empty(as_.size), np.empty(is_.size)
+    _check(lib().orc_gather_map_vjp(o, as_.size, _p(as_), is_.size, _p(is_), _p(vs), _p(yb), _p(ab), _p(vb)),
+           "gather_map_vjp")
+    return ab, (vb if o else None)

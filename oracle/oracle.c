@@ -1350,3 +1350,75 @@ int orc_kmeans_hvp(int64_t N, int D, int K, const double* X, const double* C, do
     free(a), free(cp), free(cm), free(gp), free(gm);
     return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* A map whose body reads a free array at computed indices (Sec. 5.4):       */
+/*   ys[i] = f(as[is[i]], vs[i]),  f = a (gather), a v, or (a - v)^2.        */
+/* On the tape each as[k] is one leaf variable and every read of it is an    */
+/* edge from that leaf, so the reverse sweep adds each read's partial into   */
+/* the leaf's adjoint: the accumulator's list of (index, value) updates,     */
+/* applied in reverse record order.  An index outside [0, n) reads the       */
+/* constant 0 (a leaf of its own that the result ignores).                   */
+static int64_t gm_body(tape_t* t, int op, int64_t a, int64_t v) {
+    if (op == 0) return emit1(t, V(a), a, 1.0);
+    if (op == 1) return t_mul(t, a, v);
+    int64_t d = t_sub(t, a, v);
+    return t_mul(t, d, d);
+}
+
+static int gm_check(int op, int64_t n, const double* as, int64_t m, const int32_t* is, const double* vs) {
+    if (op < 0 || op > 2 || n < 0 || m < 0) return -1;
+    if ((n > 0 && !as) || (m > 0 && !is) || (m > 0 && op != 0 && !vs)) return -1;
+    return 0;
+}
+
+int orc_gather_map(int op, int64_t n, const double* as, int64_t m, const int32_t* is, const double* vs,
+                   double* ys) {
+    if (gm_check(op, n, as, m, is, vs) || (m > 0 && !ys)) return -1;
+    tape_t T, *t = &T;
+    if (tape_init(t, n + 4 * m + 16, 3 * m + 16)) return -2;
+    int64_t a0 = t->nv;
+    for (int64_t k = 0; k < n; ++k) leaf(t, as[k]);
+    for (int64_t i = 0; i < m; ++i) {
+        const int64_t k = is[i];
+        const int64_t a = (k >= 0 && k < n) ? a0 + k : leaf(t, 0.0);
+        const int64_t v = leaf(t, op ? vs[i] : 0.0);
+        ys[i] = V(gm_body(t, op, a, v));
+    }
+    int rc = t->oom ? -2 : 0;
+    tape_free(t);
+    return rc;
+}
+
+int orc_gather_map_vjp(int op, int64_t n, const double* as, int64_t m, const int32_t* is, const double* vs,
+                       const double* ys_bar, double* as_bar, double* vs_bar) {
+    if (gm_check(op, n, as, m, is, vs) || (n > 0 && !as_bar) || (m > 0 && (!ys_bar || (op && !vs_bar))))
+        return -1;
+    tape_t T, *t = &T;
+    if (tape_init(t, n + 4 * m + 16, 3 * m + 16)) return -2;
+    int64_t* y = (int64_t*)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+    int64_t* vv = (int64_t*)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+    if (!y || !vv) {
+        free(y), free(vv), tape_free(t);
+        return -2;
+    }
+    int64_t a0 = t->nv;
+    for (int64_t k = 0; k < n; ++k) leaf(t, as[k]);
+    for (int64_t i = 0; i < m; ++i) {
+        const int64_t k = is[i];
+        const int64_t a = (k >= 0 && k < n) ? a0 + k : leaf(t, 0.0);
+        vv[i] = leaf(t, op ? vs[i] : 0.0);
+        y[i] = gm_body(t, op, a, vv[i]);
+    }
+    int rc = (t->oom || tape_reverse(t)) ? -2 : 0;
+    if (!rc) {
+        for (int64_t i = 0; i < m; ++i) t->adj[y[i]] += ys_bar[i];
+        sweep(t);
+        for (int64_t k = 0; k < n; ++k) as_bar[k] = t->adj[a0 + k];
+        if (op)
+            for (int64_t i = 0; i < m; ++i) vs_bar[i] = t->adj[vv[i]];
+    }
+    free(y), free(vv);
+    tape_free(t);
+    return rc;
+}

@@ -160,6 +160,16 @@ int orc_kmeans_vjp(int64_t N, int D, int K, const double* X, const double* C, do
 int orc_kmeans_hvp(int64_t N, int D, int K, const double* X, const double* C, double f_bar,
                    const double* C_dot, double* out);
 
+/* A map whose body reads a free array at computed indices (Sec. 5.4):
+ * ys[i] = f(as[is[i]], vs[i]) with op 0: f = a (vs unused, may be NULL),
+ * 1: a v, 2: (a - v)^2.  An index outside [0, n) reads 0.  The VJP returns
+ * as_bar (every read's partial accumulated into its element) and vs_bar (not
+ * written for op 0). */
+int orc_gather_map(int op, int64_t n, const double* as, int64_t m, const int32_t* is, const double* vs,
+                   double* ys);
+int orc_gather_map_vjp(int op, int64_t n, const double* as, int64_t m, const int32_t* is, const double* vs,
+                       const double* ys_bar, double* as_bar, double* vs_bar);
+
 #ifdef __cplusplus
 }
 #endif

@@ -81,6 +81,17 @@ def hist(n: int, m: int, dist: str = "uniform", dtype="f32", seed: int = 0, s: f
     return inds, vs, hs_bar
 
 
+def gather_map(m: int, n: int, dist: str = "uniform", dtype="f32", seed: int = 0):
+    """(as_, is_, vs, ys_bar) for a map reading the free array as_ [n] at
+    indices is_ [m] (uniform, or Zipf(1.1) over n as for the histograms)."""
+    is_, vs, _ = hist(m, n, dist, dtype, seed)
+    g = rng(seed + 1)
+    dt = _dt(dtype)
+    as_ = g.standard_normal(n).astype(dt)
+    ys_bar = g.standard_normal(m).astype(dt)
+    return as_, is_, vs, ys_bar
+
+
 def tie_values(n: int, dtype="f32", seed: int = 0):
     """Values quantised to multiples of 2^-4 in [-4, 4]: many exact ties."""
     g = rng(seed)
