@@ -48,8 +48,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 23, help="elements per instance for the CPU oracle")
-    ap.add_argument("--skip", default="", help="comma list of extra workloads to skip: reduce_map,reduce_generic,scan_generic,jvp,kmeans,scan,"
-                         "gmm,batch,serve")
+    ap.add_argument("--skip", default="", help="comma list of extra workloads to skip: reduce_map,reduce_generic,scan_generic,jvp,kmeans,"
+                         "gather_map,scan,gmm,batch,serve")
     ap.add_argument("--only", default="",
                     help="run just this one extra workload (for profiling) and print its JSON instead of the "
                          "benchmark line")
@@ -221,7 +221,8 @@ def main():
     L = capi.lib()
     if args.only:
         fns = {"reduce_map": bench_reduce_map, "reduce_generic": bench_reduce_generic,
-               "scan_generic": bench_scan_generic, "jvp": bench_jvp, "kmeans": bench_kmeans, "scan": bench_scan,
+               "scan_generic": bench_scan_generic, "jvp": bench_jvp, "kmeans": bench_kmeans, "gather_map": bench_gather_map,
+               "scan": bench_scan,
                "gmm": bench_gmm, "batch": bench_batch, "serve": bench_serve}
         print(json.dumps({args.only: fns[args.only](args)}))
         return
@@ -383,7 +384,7 @@ def main():
     extra = {}
     for name, fn in (("reduce_map", bench_reduce_map), ("reduce_generic", bench_reduce_generic),
                      ("scan_generic", bench_scan_generic), ("jvp", bench_jvp), ("kmeans", bench_kmeans),
-                     ("scan", bench_scan), ("gmm", bench_gmm),
+                     ("gather_map", bench_gather_map), ("scan", bench_scan), ("gmm", bench_gmm),
                      ("batch", bench_batch), ("serve", bench_serve)):
         if name in args.skip:
             continue
@@ -777,6 +778,34 @@ def bench_kmeans(args):
             "objective_ms": round(tf, 4), "gradient_ms": round(tg, 4), "gradient_and_hessian_diag_ms": round(th, 4),
             "search_fp64_TFLOPs": round(2 * N * K * D / (tf * 1e-3) / 1e12, 2),
             "newton_step_ms": round(tf + th, 4)}
+    return res
+
+
+def bench_gather_map(args):
+    """A map reading a free array at 2^26 computed indices (FP32, a v): the
+    primal and the return sweep with the reads accumulated into as_bar, for
+    n = 2^12 (LDS bins) and 2^20 (global atomics), Zipf(1.1) and uniform
+    indices.  Algorithmic bytes: primal 12 B per element (is, vs read, ys
+    written); VJP 16 B (is, vs, ys_bar read, vs_bar written) + 8 n (as
+    read, as_bar written)."""
+    import torch
+
+    from paper_2202_10297_amd import ops, workloads
+
+    m = 1 << 26
+    res = {}
+    for n, dist in ((1 << 12, "zipf"), (1 << 12, "uniform"), (1 << 20, "zipf"), (1 << 20, "uniform")):
+        as_, is_, vs, yb = (torch.from_numpy(a).cuda() for a in workloads.gather_map(m, n, dist, "f32", seed=0))
+        ys = torch.empty(m, dtype=torch.float32, device="cuda")
+        ab = torch.empty(n, dtype=torch.float32, device="cuda")
+        vb = torch.empty(m, dtype=torch.float32, device="cuda")
+        tp = _events_ms(lambda: ops.gather_map("mul", as_, is_, vs, out=ys), 10)
+        tv = _events_ms(lambda: ops.gather_map_vjp("mul", as_, is_, vs, yb, as_bar=ab, vs_bar=vb), 10)
+        res[f"n2^{n.bit_length() - 1}_{dist}"] = {
+            "primal_ms": round(tp, 4), "vjp_ms": round(tv, 4), "grad_over_primal": round((tp + tv) / tp, 3),
+            "primal_hbm_frac": round(12 * m / (tp * 1e-3) / 8e12, 3),
+            "vjp_hbm_frac": round((16 * m + 8 * n) / (tv * 1e-3) / 8e12, 3)}
+        del as_, is_, vs, yb, ys, ab, vb
     return res
 
 

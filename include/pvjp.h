@@ -461,6 +461,39 @@ pvjp_status pvjp_kmeans_vjp(const float* X, int64_t N, int D, const float* C, in
                             const int32_t* assign, double f_bar, float* C_bar, const float* C_dot,
                             float* hvp, int accumulate, void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* map over a free array (Sec. 5.4; accumulators lowered as in Sec. 6)        */
+/* ------------------------------------------------------------------------ */
+
+typedef enum { PVJP_GMAP_GATHER = 0, PVJP_GMAP_MUL = 1, PVJP_GMAP_SQDIFF = 2 } pvjp_gmap_op;
+
+/* ys[i] = f(as[is[i]], vs[i]) for i < m, the body of a map that reads the
+ * free array as [n] at computed indices: GATHER f = a (vs unused, may be
+ * NULL), MUL f = a v, SQDIFF f = (a - v)^2.  An index outside [0, n) reads 0.
+ * as, vs, ys: dtype; is: int32 [m].  No workspace. */
+pvjp_status pvjp_gather_map(int op, pvjp_dtype dtype, const void* as, int64_t n, const int32_t* is,
+                            const void* vs, int64_t m, void* ys, void* stream);
+/* Bytes of workspace for pvjp_gather_map_vjp (device memory, zero-initialised
+ * once by the caller, owned by the caller, reusable across calls on one
+ * stream). */
+size_t pvjp_gather_map_ws_bytes(pvjp_dtype dtype, int64_t n, int64_t m);
+/* Return sweep.  The reads of the free array become an accumulator (Sec.
+ * 5.4): as_bar[is[i]] (+)= sum over i of (df/da)(as[is[i]], vs[i]) ys_bar[i];
+ * per element vs_bar[i] (+)= (df/dv) ys_bar[i] (not written for GATHER,
+ * where vs_bar may be NULL).  accumulate != 0 adds into as_bar and vs_bar,
+ * else overwrites them (as_bar is written for every k < n, 0 where nothing
+ * was read).  Indices outside [0, n) update nothing.  The partials are
+ * summed in FP64: in LDS bins per block when n <= 16384, the blocks' bins
+ * then added in a fixed order; otherwise each element's partial (rounded to
+ * dtype) goes through the reduce_by_index(+) path (pvjp_hist), whose bin
+ * caches and bucket partitioning keep hot indices off contended atomics.
+ * Atomic order varies, so as_bar may differ between calls in the last bits.
+ * ws: 256-byte aligned, ws_bytes >= pvjp_gather_map_ws_bytes(dtype, n, m),
+ * else PVJP_ENOMEM. */
+pvjp_status pvjp_gather_map_vjp(int op, pvjp_dtype dtype, const void* as, int64_t n, const int32_t* is,
+                                const void* vs, int64_t m, const void* ys_bar, void* as_bar, void* vs_bar,
+                                int accumulate, void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,6 +17,7 @@ F32, F64 = 0, 1
 ADD, MUL, MIN, MAX = 0, 1, 2, 3
 FN_SQUARE, FN_EXP, FN_LOG, FN_SIN, FN_TANH = 0, 1, 2, 3, 4
 GOP_LOGADDEXP, GOP_LINREC, GOP_MAT2 = 0, 1, 2
+GMAP = {"gather": 0, "mul": 1, "sqdiff": 2}
 LINREC_CKPT_INTERVAL = 1024
 
 _P = ctypes.c_void_p
@@ -73,6 +74,9 @@ SIGNATURES = {
     "pvjp_kmeans_ws_bytes": (_Z, [_L, _I, _I]),
     "pvjp_kmeans_objective": (_I, [_P, _L, _I, _P, _I, _P, _P, _P, _Z, _P]),
     "pvjp_kmeans_vjp": (_I, [_P, _L, _I, _P, _I, _P, ctypes.c_double, _P, _P, _P, _I, _P, _Z, _P]),
+    "pvjp_gather_map": (_I, [_I, _I, _P, _L, _P, _P, _L, _P, _P]),
+    "pvjp_gather_map_ws_bytes": (_Z, [_I, _L, _L]),
+    "pvjp_gather_map_vjp": (_I, [_I, _I, _P, _L, _P, _P, _L, _P, _P, _P, _I, _P, _Z, _P]),
     "pvjp_gmm_ws_bytes": (_Z, [_L, _I, _I]),
     "pvjp_gmm_objective": (_I, [_P, _L, _I, _I, _P, _P, _P, _P, _P, _P, _P, _P, _Z, _P]),
     "pvjp_gmm_vjp": (_I, [_P, _L, _I, _I, _P, _P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _P, _P, _I, _P, _Z,

@@ -445,3 +445,31 @@ def kmeans_vjp(X, C, assign, f_bar=1.0, C_dot=None, out=None, accumulate=False):
     capi.call("pvjp_kmeans_vjp", _ptr(X), N, D, _ptr(C), K, _ptr(assign), float(f_bar), _ptr(cb), _ptr(C_dot),
               _ptr(hv), int(accumulate), _ptr(ws), ws.numel(), _stream(dev))
     return cb, hv
+
+
+def gather_map(op, as_, is_, vs=None, out=None):
+    """ys[i] = f(as_[is_[i]], vs[i]) (a map reading the free array as_):
+    op "gather" (f = a), "mul" (a v) or "sqdiff" ((a - v)^2)."""
+    o = capi.GMAP[op]
+    if is_.dtype != torch.int32:
+        raise TypeError("is_ must be int32")
+    m = is_.numel()
+    ys = out if out is not None else torch.empty(m, dtype=as_.dtype, device=as_.device)
+    capi.call("pvjp_gather_map", o, _dt(as_), _ptr(as_), as_.numel(), _ptr(is_), _ptr(vs), m, _ptr(ys),
+              _stream(as_.device))
+    return ys
+
+
+def gather_map_vjp(op, as_, is_, vs, ys_bar, as_bar=None, vs_bar=None, accumulate=False):
+    """(as_bar, vs_bar or None): each read's partial accumulated into as_bar."""
+    o = capi.GMAP[op]
+    n, m = as_.numel(), is_.numel()
+    dev = as_.device
+    mk = torch.zeros if accumulate else torch.empty
+    ab = as_bar if as_bar is not None else mk(n, dtype=as_.dtype, device=dev)
+    vb = vs_bar if (vs_bar is not None or o == 0) else mk(m, dtype=as_.dtype, device=dev)
+    nb = capi.lib().pvjp_gather_map_ws_bytes(_dt(as_), n, m)
+    ws = WS.get("gather_map", nb, dev)
+    capi.call("pvjp_gather_map_vjp", o, _dt(as_), _ptr(as_), n, _ptr(is_), _ptr(vs), m, _ptr(ys_bar), _ptr(ab),
+              _ptr(vb), int(accumulate), _ptr(ws), ws.numel(), _stream(dev))
+    return ab, vb
