@@ -41,15 +41,31 @@ __device__ inline void gm_partials(double a, double v, double yb, double& pa, do
     }
 }
 
+constexpr int kGmU = 4;  // elements per thread per step, their loads in flight together
+
+// Each step of a thread takes elements base + u 256 + t, u < kGmU (coalesced
+// for every u): all index and value loads, then all gathers, then the stores.
 template <int OP, class T>
 __global__ __launch_bounds__(256) void gm_fwd_kernel(const T* __restrict__ as, int64_t n,
                                                      const int32_t* __restrict__ is, const T* __restrict__ vs,
                                                      int64_t m, T* __restrict__ ys) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t k = is[i];
-        const T a = (k >= 0 && k < n) ? as[k] : T(0);
-        const T v = OP ? vs[i] : T(0);
-        ys[i] = gm_f<OP, T>(a, v);
+    const int64_t step = (int64_t)gridDim.x * blockDim.x * kGmU;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x * kGmU + threadIdx.x; base < m; base += step) {
+        int64_t k[kGmU];
+        T v[kGmU], a[kGmU];
+#pragma unroll
+        for (int u = 0; u < kGmU; ++u) {
+            const int64_t i = base + (int64_t)u * blockDim.x;
+            k[u] = i < m ? is[i] : -1;
+            v[u] = (OP && i < m) ? vs[i] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kGmU; ++u) a[u] = (k[u] >= 0 && k[u] < n) ? as[k[u]] : T(0);
+#pragma unroll
+        for (int u = 0; u < kGmU; ++u) {
+            const int64_t i = base + (int64_t)u * blockDim.x;
+            if (i < m) ys[i] = gm_f<OP, T>(a[u], v[u]);
+        }
     }
 }
 
@@ -81,10 +97,29 @@ __global__ __launch_bounds__(kGmLdsBlock) void gm_vjp_lds_kernel(const T* __rest
     __syncthreads();
     const int64_t i0 = (int64_t)blockIdx.x * chunk;
     const int64_t i1 = (i0 + chunk < m) ? i0 + chunk : m;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-        int64_t k;
-        double pa;
-        if (gm_elem<OP, T>(as, n, is, vs, yb, i, vbar, accumulate, k, pa)) atomicAdd(&bins[k], pa);
+    for (int64_t base = i0 + threadIdx.x; base < i1; base += (int64_t)blockDim.x * kGmU) {
+        int32_t k[kGmU];
+        T v[kGmU], y[kGmU], a[kGmU];
+#pragma unroll
+        for (int u = 0; u < kGmU; ++u) {
+            const int64_t i = base + (int64_t)u * blockDim.x;
+            const bool in = i < i1;
+            k[u] = in ? is[i] : -1;
+            v[u] = (OP && in) ? vs[i] : T(0);
+            y[u] = in ? yb[i] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kGmU; ++u) a[u] = (k[u] >= 0 && k[u] < n) ? as[k[u]] : T(0);
+#pragma unroll
+        for (int u = 0; u < kGmU; ++u) {
+            const int64_t i = base + (int64_t)u * blockDim.x;
+            if (i < i1) {
+                double pa, pv;
+                gm_partials<OP>((double)a[u], (double)v[u], (double)y[u], pa, pv);
+                if (OP) vbar[i] = accumulate ? vbar[i] + (T)pv : (T)pv;
+                if (k[u] >= 0 && k[u] < n) atomicAdd(&bins[k[u]], pa);
+            }
+        }
     }
     __syncthreads();
     for (int k = threadIdx.x; k < n; k += blockDim.x) part[(int64_t)blockIdx.x * n + k] = bins[k];
