@@ -429,3 +429,27 @@ def gather_map_vjp(op, as_, is_, vs, ys_bar):
     _check(lib().orc_gather_map_vjp(o, as_.size, _p(as_), is_.size, _p(is_), _p(vs), _p(yb), _p(ab), _p(vb)),
            "gather_map_vjp")
     return ab, (vb if o else None)
+
+
+def scan_generic_rows(op, xs):
+    """Each row of the [B, L] component arrays scanned on its own (a regular
+    segmented scan): the single-scan oracle applied row by row."""
+    xs = [np.atleast_2d(_f64(x)) for x in xs]
+    out = [np.empty_like(x) for x in xs]
+    for b in range(xs[0].shape[0]):
+        ys = scan_generic(op, [x[b] for x in xs])
+        for o, y in zip(out, ys):
+            o[b] = y
+    return out
+
+
+def scan_generic_rows_vjp(op, xs, ys_bar):
+    """The VJP of scan_generic_rows, row by row."""
+    xs = [np.atleast_2d(_f64(x)) for x in xs]
+    yb = [np.atleast_2d(_f64(y)) for y in ys_bar]
+    out = [np.empty_like(x) for x in xs]
+    for b in range(xs[0].shape[0]):
+        g = scan_generic_vjp(op, [x[b] for x in xs], [y[b] for y in yb])
+        for o, v in zip(out, g):
+            o[b] = v
+    return out
