@@ -312,6 +312,28 @@ pvjp_status pvjp_scan_generic_vjp(pvjp_gop op, pvjp_dtype dtype, const void* con
                                   const void* ckpt, const void* const* y_bar, void* const* x_bar,
                                   int accumulate, void* ws, size_t ws_bytes, void* stream);
 
+/* Regular segmented scan (Sec. 5.2, the vectorised-operator rule): B
+ * independent inclusive scans of L elements each with the same operator,
+ * segment b at offset b L of every component array (so x[c] and y[c] are [B x
+ * L] row-major, one scan per row).  A scan whose operator is applied
+ * componentwise to vectors of w elements, over n such vectors stored [n x w],
+ * is this call on the transposed [w x n] arrays (B = w, L = n), which is the
+ * paper's rewrite of such a scan into transpose, a map of scans, transpose.
+ * The primal and the VJP are those of pvjp_scan_generic(_vjp) per row, in one
+ * launch sequence for all rows (rows ride on the grid's second dimension);
+ * the VJP's reversed lin_o scan starts afresh at each row's last element.
+ * 1 <= B <= 65535; the checkpoint holds B times the single-scan tile
+ * prefixes.  The 16-byte vector path is taken when every row starts 16-byte
+ * aligned (L * element size a multiple of 16 and 16-byte aligned arrays). */
+size_t pvjp_scan_generic_batched_ws_bytes(pvjp_gop op, pvjp_dtype dtype, int64_t B, int64_t L);
+size_t pvjp_scan_generic_batched_ckpt_bytes(pvjp_gop op, pvjp_dtype dtype, int64_t B, int64_t L);
+pvjp_status pvjp_scan_generic_batched(pvjp_gop op, pvjp_dtype dtype, const void* const* x, int64_t B, int64_t L,
+                                      void* const* y, void* ckpt, void* ws, size_t ws_bytes, void* stream);
+pvjp_status pvjp_scan_generic_batched_vjp(pvjp_gop op, pvjp_dtype dtype, const void* const* x, int64_t B,
+                                          int64_t L, const void* ckpt, const void* const* y_bar,
+                                          void* const* x_bar, int accumulate, void* ws, size_t ws_bytes,
+                                          void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Forward mode (Sec. 3): Jacobian-vector products.  Each primal is bundled   */
 /* with its tangent and the operator runs on the pairs (the dual-number form  */

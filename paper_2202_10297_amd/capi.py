@@ -58,6 +58,10 @@ SIGNATURES = {
     "pvjp_scan_generic_ckpt_bytes": (_Z, [_I, _I, _L]),
     "pvjp_scan_generic": (_I, [_I, _I, _P, _L, _P, _P, _P, _Z, _P]),
     "pvjp_scan_generic_vjp": (_I, [_I, _I, _P, _L, _P, _P, _P, _I, _P, _Z, _P]),
+    "pvjp_scan_generic_batched_ws_bytes": (_Z, [_I, _I, _L, _L]),
+    "pvjp_scan_generic_batched_ckpt_bytes": (_Z, [_I, _I, _L, _L]),
+    "pvjp_scan_generic_batched": (_I, [_I, _I, _P, _L, _L, _P, _P, _P, _Z, _P]),
+    "pvjp_scan_generic_batched_vjp": (_I, [_I, _I, _P, _L, _L, _P, _P, _P, _I, _P, _Z, _P]),
     "pvjp_map_jvp": (_I, [_I, _I, _P, _P, _L, _P, _P]),
     "pvjp_reduce_jvp": (_I, [_I, _I, _P, _P, _L, _P, _P, _P, _P, _P, _Z, _P]),
     "pvjp_hist_jvp_ws_bytes": (_Z, [_I, _I, _L, _L]),

@@ -83,22 +83,28 @@ __device__ __forceinline__ float lae_exp(float x) { return __expf(x); }
 __device__ __forceinline__ double lae_exp(double x) { return exp(x); }
 __device__ __forceinline__ float lae_div(float a, float b) { return __fdividef(a, b); }
 __device__ __forceinline__ double lae_div(double a, double b) { return a / b; }
+__device__ __forceinline__ float lae_log(float x) { return logf(x); }
+__device__ __forceinline__ double lae_log(double x) { return log(x); }
 
-template <class T>
-struct GLogAddExp : GShfl<T, 2> {
+// Log-add-exp with the state (m, s) in T and the exponentials evaluated in E
+// (E = T, or FP32 with an FP64 state: see the scans' widening below).
+template <class T, class E = T>
+struct GLogAddExpE : GShfl<T, 2> {
     static constexpr int K = 1;
     using Acc = T;
     using S = GS<T, 2>;
+    __device__ static __forceinline__ T ex(T a) { return (T)lae_exp((E)a); }
+    // The output's logarithm in E: nothing downstream accumulates it.
     __device__ static __forceinline__ S id() { return S{{-(T)INFINITY, T(0)}}; }
     __device__ static __forceinline__ S elem(const T (&c)[1]) {
         return S{{c[0], c[0] == -(T)INFINITY ? T(0) : T(1)}};
     }
-    __device__ static __forceinline__ void value(S v, T (&out)[1]) { out[0] = v.c[0] + log(v.c[1]); }
+    __device__ static __forceinline__ void value(S v, T (&out)[1]) { out[0] = v.c[0] + (T)lae_log((E)v.c[1]); }
     __device__ static __forceinline__ S comb(S x, S y) {
         if (y.c[1] == T(0)) return x;
         if (x.c[1] == T(0)) return y;
         const T d = x.c[0] - y.c[0];
-        const T e = lae_exp(-fabs(d));
+        const T e = ex(-fabs(d));
         return d >= T(0) ? S{{x.c[0], x.c[1] + y.c[1] * e}} : S{{y.c[0], x.c[1] * e + y.c[1]}};
     }
     __device__ static __forceinline__ void vjp(S, S a, S r, S la, const T (&yb)[1], T (&out)[1]) {
@@ -108,18 +114,20 @@ struct GLogAddExp : GShfl<T, 2> {
             return;
         }
         const S y = comb(la, r);
-        out[0] = lae_div(yb[0] * lae_exp(a.c[0] - y.c[0]), y.c[1]);
+        out[0] = lae_div(yb[0] * ex(a.c[0] - y.c[0]), y.c[1]);
     }
     // Scan Jacobians (value y = m + log s).  cT = d(y (.) xn)/dy = e^y / (e^y +
     // e^xn) = s / (s + e^(xn - m)), 0 where y = -inf.
     __device__ static __forceinline__ void jlT(const S& y, const T (&xn)[1], T (&cT)[1][1]) {
-        cT[0][0] = y.c[1] == T(0) ? T(0) : lae_div(y.c[1], y.c[1] + lae_exp(xn[0] - y.c[0]));
+        cT[0][0] = y.c[1] == T(0) ? T(0) : lae_div(y.c[1], y.c[1] + ex(xn[0] - y.c[0]));
     }
     // out = (d(yp (.) x)/dx)^T r = r e^(x - y) with y = yp (.) x; 0 where x = -inf.
     __device__ static __forceinline__ void jrT(const S&, const T (&x)[1], const S& y, const T (&r)[1], T (&out)[1]) {
-        out[0] = x[0] == -(T)INFINITY ? T(0) : r[0] * lae_div(lae_exp(x[0] - y.c[0]), y.c[1]);
+        out[0] = x[0] == -(T)INFINITY ? T(0) : r[0] * lae_div(ex(x[0] - y.c[0]), y.c[1]);
     }
 };
+template <class T>
+using GLogAddExp = GLogAddExpE<T, T>;
 
 template <class T>
 struct GLinRec : GShfl<T, 2> {
@@ -405,12 +413,28 @@ __device__ __forceinline__ int gr_cnt(int64_t n, int64_t base) {
     return left <= 0 ? 0 : (left >= IPT ? IPT : (int)left);
 }
 
+// blockIdx.y selects one of several independent arrays of n elements laid
+// out back to back (a regular segmented scan); its tiles' states sit at
+// blockIdx.y * gridDim.x.  A 1-D grid is segment 0.
+template <class T, int K>
+__device__ __forceinline__ void seg_shift(GPtrs<T>& x, int64_t n) {
+#pragma unroll
+    for (int c = 0; c < K; ++c) x.p[c] += (int64_t)blockIdx.y * n;
+}
+template <class T, int K>
+__device__ __forceinline__ void seg_shift(GOut<T>& x, int64_t n) {
+#pragma unroll
+    for (int c = 0; c < K; ++c) x.p[c] += (int64_t)blockIdx.y * n;
+}
+__device__ __forceinline__ int64_t seg_tile() { return (int64_t)blockIdx.y * gridDim.x + blockIdx.x; }
+
 // Pass 1: agg[t] = fold of tile t (kGrBlock * IPT elements) in index order.
 template <class Op, class T, bool VEC, int IPT = gr_ipt<Op, T>()>
 __global__ __launch_bounds__(kGrBlock) void gred_tile_agg_kernel(GPtrs<T> x, int64_t n,
                                                                  typename Op::S* __restrict__ agg) {
     using S = typename Op::S;
     __shared__ S wtot[kGrBlock / kWave];
+    seg_shift<T, Op::K>(x, n);
     const int64_t base = (int64_t)blockIdx.x * (kGrBlock * IPT) + (int64_t)threadIdx.x * IPT;
     const int cnt = gr_cnt<IPT>(n, base);
     T v[Op::K][IPT];
@@ -422,7 +446,7 @@ __global__ __launch_bounds__(kGrBlock) void gred_tile_agg_kernel(GPtrs<T> x, int
         if (k < cnt) run = Op::comb(run, gr_elem<Op, T, IPT>(v, k));
     S total;
     block_exclusive_scan<Op, kGrBlock, false>(run, total, wtot);
-    if (threadIdx.x == 0) agg[blockIdx.x] = total;
+    if (threadIdx.x == 0) agg[seg_tile()] = total;
 }
 
 // Tiles are taken in groups of kGrGroup; one wave handles a group, lane j
@@ -685,11 +709,13 @@ __global__ __launch_bounds__(kGrBlock) void gscan_fwd_kernel(GPtrs<T> x, int64_t
     using A = typename Op::Acc;
     constexpr int K = Op::K;
     __shared__ S wtot[kGrBlock / kWave];
+    seg_shift<T, K>(x, n);
+    seg_shift<T, K>(y, n);
     const int64_t base = (int64_t)blockIdx.x * (kGrBlock * IPT) + (int64_t)threadIdx.x * IPT;
     const int cnt = gr_cnt<IPT>(n, base);
     A xa[K][IPT], xn[K];
     S ys[IPT], sp;
-    gs_run_states<Op, T, IPT, VEC>(x, n, base, cnt, pre[blockIdx.x], wtot, xa, xn, ys, sp);
+    gs_run_states<Op, T, IPT, VEC>(x, n, base, cnt, pre[seg_tile()], wtot, xa, xn, ys, sp);
     T out[K][IPT];
 #pragma unroll
     for (int k = 0; k < IPT; ++k) {
@@ -713,6 +739,8 @@ __global__ __launch_bounds__(kGrBlock) void gscan_vjp_agg_kernel(
     constexpr int K = Op::K;
     __shared__ S wtot[kGrBlock / kWave];
     __shared__ typename LG::S ltot[kGrBlock / kWave];
+    seg_shift<T, K>(x, n);
+    seg_shift<T, K>(ybar, n);
     const int64_t base = (int64_t)blockIdx.x * (kGrBlock * IPT) + (int64_t)threadIdx.x * IPT;
     const int cnt = gr_cnt<IPT>(n, base);
     T yb[K][IPT];
@@ -720,11 +748,11 @@ __global__ __launch_bounds__(kGrBlock) void gscan_vjp_agg_kernel(
     for (int c = 0; c < K; ++c) gr_load<T, IPT, VEC>(ybar.p[c] + base, cnt, yb[c]);
     A xa[K][IPT], xn[K];
     S ys[IPT], sp;
-    gs_run_states<Op, T, IPT, VEC>(x, n, base, cnt, pre[blockIdx.x], wtot, xa, xn, ys, sp);
+    gs_run_states<Op, T, IPT, VEC>(x, n, base, cnt, pre[seg_tile()], wtot, xa, xn, ys, sp);
     const typename LG::S run = gs_run_lin<Op, T, IPT>(ys, xa, xn, yb, n, base, cnt);
     typename LG::S tot;
     block_exclusive_scan<LG, kGrBlock, true>(run, tot, ltot);
-    if (threadIdx.x == 0) lagg[blockIdx.x] = tot;
+    if (threadIdx.x == 0) lagg[seg_tile()] = tot;
 }
 
 // VJP pass 3: lsuf[t] is the lin_o fold of every tile after t; with the
@@ -741,6 +769,9 @@ __global__ __launch_bounds__(kGrBlock) void gscan_vjp_kernel(
     constexpr int K = Op::K;
     __shared__ S wtot[kGrBlock / kWave];
     __shared__ typename LG::S ltot[kGrBlock / kWave];
+    seg_shift<T, K>(x, n);
+    seg_shift<T, K>(ybar, n);
+    seg_shift<T, K>(xbar, n);
     const int64_t base = (int64_t)blockIdx.x * (kGrBlock * IPT) + (int64_t)threadIdx.x * IPT;
     const int cnt = gr_cnt<IPT>(n, base);
     T yb[K][IPT];
@@ -748,11 +779,11 @@ __global__ __launch_bounds__(kGrBlock) void gscan_vjp_kernel(
     for (int c = 0; c < K; ++c) gr_load<T, IPT, VEC>(ybar.p[c] + base, cnt, yb[c]);
     A xa[K][IPT], xn[K];
     S ys[IPT], sp;
-    gs_run_states<Op, T, IPT, VEC>(x, n, base, cnt, pre[blockIdx.x], wtot, xa, xn, ys, sp);
+    gs_run_states<Op, T, IPT, VEC>(x, n, base, cnt, pre[seg_tile()], wtot, xa, xn, ys, sp);
     const typename LG::S run = gs_run_lin<Op, T, IPT>(ys, xa, xn, yb, n, base, cnt);
     typename LG::S tot;
     const typename LG::S ex = block_exclusive_scan<LG, kGrBlock, true>(run, tot, ltot);
-    const typename LG::S after = LG::comb(lsuf[blockIdx.x], ex);
+    const typename LG::S after = LG::comb(lsuf[seg_tile()], ex);
     A r[K];
 #pragma unroll
     for (int c = 0; c < K; ++c) r[c] = after.v[c];
@@ -914,6 +945,24 @@ using GOpFor = OpT<typename std::conditional<std::is_same<T, float>::value &&
                                                  !std::is_same<OpT<float>, GLogAddExp<float>>::value,
                                              double, T>::type>;
 
+// The scans widen FP32 log-add-exp too: the reversed lin_o scan multiplies
+// the coefficients c_k = s_k / (s_k + e^(x_(k+1) - m_k)) along whole suffixes,
+// and an FP32 state rounds every c_k (about 1 late in the scan) by about
+// 2^-24, errors that add up along the suffix (about n 2^-24 after n steps).
+// With the state in FP64 and only the exponential in FP32, a coefficient's
+// error is relative to the new element's share 1 - c_k, and the suffix
+// products stay accurate.  The exponentials keep their FP32 cost.
+template <class Op>
+struct ScanWiden {
+    using type = Op;
+};
+template <>
+struct ScanWiden<GLogAddExpE<float, float>> {
+    using type = GLogAddExpE<double, float>;
+};
+template <template <class> class OpT, class T>
+using GScanOpFor = typename ScanWiden<GOpFor<OpT, T>>::type;
+
 template <template <class> class OpT, class T>
 static void dispatch_primal(const void* const* x, int K, int64_t n, void* const* y, void* ckpt, void* ws,
                             hipStream_t st) {
@@ -952,16 +1001,19 @@ constexpr size_t kLinSlot = 160;  // bytes per lin_o state (d = 4 in FP64: 4 + 1
 // slots), every array 256-byte aligned.  The tile prefixes are the
 // checkpoint when the caller keeps one.
 struct GsPlan {
-    int64_t nt, ng;
+    int64_t nt, ng;  // tiles and groups of one segment
+    int64_t B;       // segments (independent scans of n elements, back to back)
     size_t t32, g32, tl, gl;
 };
 
 template <class Op, class T>
-static GsPlan gs_plan(int64_t n) {
+static GsPlan gs_plan(int64_t n, int64_t B = 1) {
     GsPlan p;
     p.nt = ceil_div(n, gs_tile<Op, T>());
     p.ng = ceil_div(p.nt, kAggGroup);
-    const size_t nt = (size_t)(p.nt > 0 ? p.nt : 1), ng = (size_t)(p.ng > 0 ? p.ng : 1);
+    p.B = B;
+    const size_t b = (size_t)(B > 0 ? B : 1);
+    const size_t nt = b * (size_t)(p.nt > 0 ? p.nt : 1), ng = b * (size_t)(p.ng > 0 ? p.ng : 1);
     constexpr size_t slot = slot_of<typename Op::S>();
     p.t32 = align_up(nt * slot, 256);
     p.g32 = align_up(ng * slot, 256);
@@ -971,8 +1023,8 @@ static GsPlan gs_plan(int64_t n) {
 }
 
 template <class Op, class T>
-static size_t gs_ws(int64_t n) {
-    const GsPlan p = gs_plan<Op, T>(n);
+static size_t gs_ws(int64_t n, int64_t B = 1) {
+    const GsPlan p = gs_plan<Op, T>(n, B);
     return 2 * p.t32 + 2 * p.g32 + 2 * p.tl + 2 * p.gl;
 }
 
@@ -999,47 +1051,47 @@ static void gs_prefixes(const GPtrs<T>& x, int64_t n, const GsPlan& p, typename 
     S* agg = reinterpret_cast<S*>(gs_at(ws, p, 0));
     S* gagg = reinterpret_cast<S*>(gs_at(ws, p, 2));
     S* gpre = reinterpret_cast<S*>(gs_at(ws, p, 3));
+    const unsigned B = (unsigned)p.B;
     if (vec)
-        hipLaunchKernelGGL((gred_tile_agg_kernel<Op, T, true, IPT>), dim3((unsigned)p.nt), dim3(kGrBlock), 0, st, x,
-                           n, agg);
+        hipLaunchKernelGGL((gred_tile_agg_kernel<Op, T, true, IPT>), dim3((unsigned)p.nt, B), dim3(kGrBlock), 0, st,
+                           x, n, agg);
     else
-        hipLaunchKernelGGL((gred_tile_agg_kernel<Op, T, false, IPT>), dim3((unsigned)p.nt), dim3(kGrBlock), 0, st, x,
-                           n, agg);
+        hipLaunchKernelGGL((gred_tile_agg_kernel<Op, T, false, IPT>), dim3((unsigned)p.nt, B), dim3(kGrBlock), 0, st,
+                           x, n, agg);
     const unsigned gb = (unsigned)ceil_div(p.ng, kGroupBlock / kWave);
-    hipLaunchKernelGGL((group_fold_kernel<Op, false>), dim3(gb), dim3(kGroupBlock), 0, st, (const S*)agg, p.nt, p.ng,
-                       gagg);
-    hipLaunchKernelGGL((agg_scan_kernel<Op, false>), dim3(1), dim3(kAggBlock), 0, st, (const S*)gagg, p.ng, gpre);
-    hipLaunchKernelGGL((group_prefix_kernel<Op, false>), dim3(gb), dim3(kGroupBlock), 0, st, (const S*)agg, p.nt,
+    hipLaunchKernelGGL((group_fold_kernel<Op, false>), dim3(gb, B), dim3(kGroupBlock), 0, st, (const S*)agg, p.nt,
+                       p.ng, gagg);
+    hipLaunchKernelGGL((agg_scan_kernel<Op, false>), dim3(1, B), dim3(kAggBlock), 0, st, (const S*)gagg, p.ng, gpre);
+    hipLaunchKernelGGL((group_prefix_kernel<Op, false>), dim3(gb, B), dim3(kGroupBlock), 0, st, (const S*)agg, p.nt,
                        p.ng, (const S*)gpre, pre);
 }
 
 template <class Op, class T>
 static void launch_scan(const GPtrs<T>& x, int64_t n, const GOut<T>& y, void* ckpt, void* ws, bool vec,
-                        hipStream_t st) {
+                        hipStream_t st, int64_t B = 1) {
     using S = typename Op::S;
     constexpr int IPT = gs_ipt<Op, T>();
-    const GsPlan p = gs_plan<Op, T>(n);
-    if (p.nt == 0) return;
+    const GsPlan p = gs_plan<Op, T>(n, B);
+    if (p.nt == 0 || B == 0) return;
     S* pre = ckpt ? reinterpret_cast<S*>(ckpt) : reinterpret_cast<S*>(gs_at(ws, p, 1));
     gs_prefixes<Op, T>(x, n, p, pre, ws, vec, st);
+    const dim3 gt((unsigned)p.nt, (unsigned)B);
     if (vec)
-        hipLaunchKernelGGL((gscan_fwd_kernel<Op, T, IPT, true>), dim3((unsigned)p.nt), dim3(kGrBlock), 0, st, x, n,
-                           (const S*)pre, y);
+        hipLaunchKernelGGL((gscan_fwd_kernel<Op, T, IPT, true>), gt, dim3(kGrBlock), 0, st, x, n, (const S*)pre, y);
     else
-        hipLaunchKernelGGL((gscan_fwd_kernel<Op, T, IPT, false>), dim3((unsigned)p.nt), dim3(kGrBlock), 0, st, x, n,
-                           (const S*)pre, y);
+        hipLaunchKernelGGL((gscan_fwd_kernel<Op, T, IPT, false>), gt, dim3(kGrBlock), 0, st, x, n, (const S*)pre, y);
 }
 
 template <class Op, class T>
 static void launch_scan_vjp(const GPtrs<T>& x, int64_t n, const void* ckpt, const GPtrs<T>& yb, const GOut<T>& xb,
-                            int acc, void* ws, bool vec, hipStream_t st) {
+                            int acc, void* ws, bool vec, hipStream_t st, int64_t B = 1) {
     using S = typename Op::S;
     using LG = LinG<typename Op::Acc, Op::K>;
     using LS = typename LG::S;
     static_assert(sizeof(LS) <= kLinSlot, "lin_o slot too small");
     constexpr int IPT = gs_ipt<Op, T>();
-    const GsPlan p = gs_plan<Op, T>(n);
-    if (p.nt == 0) return;
+    const GsPlan p = gs_plan<Op, T>(n, B);
+    if (p.nt == 0 || B == 0) return;
     const S* pre = reinterpret_cast<const S*>(ckpt);
     if (!pre) {
         S* w = reinterpret_cast<S*>(gs_at(ws, p, 1));
@@ -1050,17 +1102,18 @@ static void launch_scan_vjp(const GPtrs<T>& x, int64_t n, const void* ckpt, cons
     LS* lsuf = reinterpret_cast<LS*>(gs_at(ws, p, 5));
     LS* lgagg = reinterpret_cast<LS*>(gs_at(ws, p, 6));
     LS* lgpre = reinterpret_cast<LS*>(gs_at(ws, p, 7));
-    const dim3 gt((unsigned)p.nt), b(kGrBlock);
+    const dim3 gt((unsigned)p.nt, (unsigned)B), b(kGrBlock);
     if (vec)
         hipLaunchKernelGGL((gscan_vjp_agg_kernel<Op, T, IPT, true>), gt, b, 0, st, x, n, pre, yb, lagg);
     else
         hipLaunchKernelGGL((gscan_vjp_agg_kernel<Op, T, IPT, false>), gt, b, 0, st, x, n, pre, yb, lagg);
     const unsigned gb = (unsigned)ceil_div(p.ng, kGroupBlock / kWave);
-    hipLaunchKernelGGL((group_fold_kernel<LG, true>), dim3(gb), dim3(kGroupBlock), 0, st, (const LS*)lagg, p.nt, p.ng,
-                       lgagg);
-    hipLaunchKernelGGL((agg_scan_kernel<LG, true>), dim3(1), dim3(kAggBlock), 0, st, (const LS*)lgagg, p.ng, lgpre);
-    hipLaunchKernelGGL((group_prefix_kernel<LG, true>), dim3(gb), dim3(kGroupBlock), 0, st, (const LS*)lagg, p.nt,
-                       p.ng, (const LS*)lgpre, lsuf);
+    hipLaunchKernelGGL((group_fold_kernel<LG, true>), dim3(gb, (unsigned)B), dim3(kGroupBlock), 0, st,
+                       (const LS*)lagg, p.nt, p.ng, lgagg);
+    hipLaunchKernelGGL((agg_scan_kernel<LG, true>), dim3(1, (unsigned)B), dim3(kAggBlock), 0, st, (const LS*)lgagg,
+                       p.ng, lgpre);
+    hipLaunchKernelGGL((group_prefix_kernel<LG, true>), dim3(gb, (unsigned)B), dim3(kGroupBlock), 0, st,
+                       (const LS*)lagg, p.nt, p.ng, (const LS*)lgpre, lsuf);
     const LS* cs = lsuf;
     if (vec) {
         if (acc)
@@ -1075,33 +1128,35 @@ static void launch_scan_vjp(const GPtrs<T>& x, int64_t n, const void* ckpt, cons
     }
 }
 
+// B > 1: B independent scans of n elements each, segment b at offset b n of
+// every array; the 16-byte vector path needs every segment 16-byte aligned.
 template <template <class> class OpT, class T>
 static void dispatch_scan(const void* const* x, int K, int64_t n, void* const* y, void* ckpt, void* ws,
-                          hipStream_t st) {
+                          hipStream_t st, int64_t B = 1) {
     GPtrs<T> xp{};
     GOut<T> yp{};
-    bool vec = true;
+    bool vec = B == 1 || ((size_t)n * sizeof(T)) % 16 == 0;
     for (int c = 0; c < K; ++c) {
         xp.p[c] = (const T*)x[c];
         yp.p[c] = (T*)y[c];
         vec = vec && aligned(x[c], 16) && aligned(y[c], 16);
     }
-    launch_scan<GOpFor<OpT, T>, T>(xp, n, yp, ckpt, ws, vec, st);
+    launch_scan<GScanOpFor<OpT, T>, T>(xp, n, yp, ckpt, ws, vec, st, B);
 }
 
 template <template <class> class OpT, class T>
 static void dispatch_scan_vjp(const void* const* x, int K, int64_t n, const void* ckpt, const void* const* yb,
-                              void* const* xb, int acc, void* ws, hipStream_t st) {
+                              void* const* xb, int acc, void* ws, hipStream_t st, int64_t B = 1) {
     GPtrs<T> xp{}, yp{};
     GOut<T> xo{};
-    bool vec = true;
+    bool vec = B == 1 || ((size_t)n * sizeof(T)) % 16 == 0;
     for (int c = 0; c < K; ++c) {
         xp.p[c] = (const T*)x[c];
         yp.p[c] = (const T*)yb[c];
         xo.p[c] = (T*)xb[c];
         vec = vec && aligned(x[c], 16) && aligned(yb[c], 16) && aligned(xb[c], 16);
     }
-    launch_scan_vjp<GOpFor<OpT, T>, T>(xp, n, ckpt, yp, xo, acc, ws, vec, st);
+    launch_scan_vjp<GScanOpFor<OpT, T>, T>(xp, n, ckpt, yp, xo, acc, ws, vec, st, B);
 }
 
 // Size queries by operator and dtype.
@@ -1116,13 +1171,27 @@ static size_t gop_query(pvjp_gop op, pvjp_dtype dtype, int64_t n) {
     if (op == PVJP_GOP_LINREC) return Q<GLinRec, float>::get(n);
     return Q<GMat2, float>::get(n);
 }
+// The same for B segments of n elements.
+template <template <template <class> class, class> class Q>
+static size_t gop_query_b(pvjp_gop op, pvjp_dtype dtype, int64_t n, int64_t B) {
+    if (dtype == PVJP_F64) {
+        if (op == PVJP_GOP_LOGADDEXP) return Q<GLogAddExp, double>::get(n, B);
+        if (op == PVJP_GOP_LINREC) return Q<GLinRec, double>::get(n, B);
+        return Q<GMat2, double>::get(n, B);
+    }
+    if (op == PVJP_GOP_LOGADDEXP) return Q<GLogAddExp, float>::get(n, B);
+    if (op == PVJP_GOP_LINREC) return Q<GLinRec, float>::get(n, B);
+    return Q<GMat2, float>::get(n, B);
+}
 template <template <class> class OpT, class T>
 struct GsWsQ {
-    static size_t get(int64_t n) { return gs_ws<GOpFor<OpT, T>, T>(n); }
+    static size_t get(int64_t n, int64_t B) { return gs_ws<GScanOpFor<OpT, T>, T>(n, B); }
 };
 template <template <class> class OpT, class T>
 struct GsCkQ {
-    static size_t get(int64_t n) { return (size_t)gs_plan<GOpFor<OpT, T>, T>(n).nt * kGrSlot; }
+    static size_t get(int64_t n, int64_t B) {
+        return (size_t)B * (size_t)gs_plan<GScanOpFor<OpT, T>, T>(n).nt * kGrSlot;
+    }
 };
 
 // Forward mode: the dual operator of each operator and storage type (FP32
@@ -1303,27 +1372,45 @@ extern "C" pvjp_status pvjp_reduce_generic_vjp(pvjp_gop op, pvjp_dtype dtype, co
 }
 
 // ------------------------------------------------------------ scan entry points
+constexpr int64_t kMaxSegments = 65535;  // segments ride on blockIdx.y
+
+static size_t scan_ws_bytes(pvjp_gop op, pvjp_dtype dtype, int64_t B, int64_t n) {
+    if (gop_components(op) == 0 || !valid_dtype(dtype) || n < 0 || B < 1 || B > kMaxSegments) return 0;
+    return gop_query_b<GsWsQ>(op, dtype, n, B);
+}
+
+static size_t scan_ckpt_bytes(pvjp_gop op, pvjp_dtype dtype, int64_t B, int64_t n) {
+    if (gop_components(op) == 0 || !valid_dtype(dtype) || n < 0 || B < 1 || B > kMaxSegments) return 0;
+    return gop_query_b<GsCkQ>(op, dtype, n, B);
+}
+
 extern "C" size_t pvjp_scan_generic_ws_bytes(pvjp_gop op, pvjp_dtype dtype, int64_t n) {
-    if (gop_components(op) == 0 || !valid_dtype(dtype) || n < 0) return 0;
-    return gop_query<GsWsQ>(op, dtype, n);
+    return scan_ws_bytes(op, dtype, 1, n);
 }
-
 extern "C" size_t pvjp_scan_generic_ckpt_bytes(pvjp_gop op, pvjp_dtype dtype, int64_t n) {
-    if (gop_components(op) == 0 || !valid_dtype(dtype) || n < 0) return 0;
-    return gop_query<GsCkQ>(op, dtype, n);
+    return scan_ckpt_bytes(op, dtype, 1, n);
+}
+extern "C" size_t pvjp_scan_generic_batched_ws_bytes(pvjp_gop op, pvjp_dtype dtype, int64_t B, int64_t L) {
+    return scan_ws_bytes(op, dtype, B, L);
+}
+extern "C" size_t pvjp_scan_generic_batched_ckpt_bytes(pvjp_gop op, pvjp_dtype dtype, int64_t B, int64_t L) {
+    return scan_ckpt_bytes(op, dtype, B, L);
 }
 
-static pvjp_status check_scan(const char* name, pvjp_gop op, pvjp_dtype dtype, const void* const* x, int64_t n,
-                              const void* ckpt, void* ws, size_t ws_bytes) {
+static pvjp_status check_scan(const char* name, pvjp_gop op, pvjp_dtype dtype, const void* const* x, int64_t B,
+                              int64_t n, const void* ckpt, void* ws, size_t ws_bytes) {
     const int K = gop_components(op);
     PVJP_REQUIRE(K > 0, "%s: unknown operator %d", name, (int)op);
     PVJP_REQUIRE(valid_dtype(dtype), "%s: unknown dtype %d", name, (int)dtype);
     PVJP_REQUIRE(n >= 0, "%s: negative n", name);
-    PVJP_REQUIRE(n < ((int64_t)1 << 40), "%s: n too large", name);
+    PVJP_REQUIRE(B >= 1 && B <= kMaxSegments, "%s: B = %lld segments out of range [1, %lld]", name, (long long)B,
+                 (long long)kMaxSegments);
+    PVJP_REQUIRE(n * B < ((int64_t)1 << 40), "%s: n too large", name);
     PVJP_REQUIRE(ws != nullptr && aligned(ws, 256), "%s: workspace must be non-NULL and 256-byte aligned", name);
     PVJP_REQUIRE(ckpt == nullptr || aligned(ckpt, 16), "%s: ckpt must be 16-byte aligned", name);
-    if (ws_bytes < pvjp_scan_generic_ws_bytes(op, dtype, n)) {
-        set_error("%s: workspace of %zu bytes, need %zu", name, ws_bytes, pvjp_scan_generic_ws_bytes(op, dtype, n));
+    const size_t need = scan_ws_bytes(op, dtype, B, n);
+    if (ws_bytes < need) {
+        set_error("%s: workspace of %zu bytes, need %zu", name, ws_bytes, need);
         return PVJP_ENOMEM;
     }
     if (n > 0) {
@@ -1336,65 +1423,86 @@ static pvjp_status check_scan(const char* name, pvjp_gop op, pvjp_dtype dtype, c
     return PVJP_OK;
 }
 
-extern "C" pvjp_status pvjp_scan_generic(pvjp_gop op, pvjp_dtype dtype, const void* const* x, int64_t n,
-                                         void* const* y, void* ckpt, void* ws, size_t ws_bytes, void* stream) {
+static pvjp_status scan_impl(const char* name, pvjp_gop op, pvjp_dtype dtype, const void* const* x, int64_t B,
+                             int64_t n, void* const* y, void* ckpt, void* ws, size_t ws_bytes, void* stream) {
     clear_error();
-    const pvjp_status s = check_scan("pvjp_scan_generic", op, dtype, x, n, ckpt, ws, ws_bytes);
+    const pvjp_status s = check_scan(name, op, dtype, x, B, n, ckpt, ws, ws_bytes);
     if (s != PVJP_OK) return s;
     if (n == 0) return PVJP_OK;
     const int K = gop_components(op);
-    PVJP_REQUIRE(y != nullptr, "pvjp_scan_generic: y is NULL");
+    PVJP_REQUIRE(y != nullptr, "%s: y is NULL", name);
     for (int c = 0; c < K; ++c) {
-        PVJP_REQUIRE(y[c] != nullptr, "pvjp_scan_generic: component %d of y is NULL", c);
-        PVJP_REQUIRE(aligned(y[c], dsize(dtype)), "pvjp_scan_generic: component %d of y is misaligned", c);
+        PVJP_REQUIRE(y[c] != nullptr, "%s: component %d of y is NULL", name, c);
+        PVJP_REQUIRE(aligned(y[c], dsize(dtype)), "%s: component %d of y is misaligned", name, c);
     }
     const hipStream_t st = as_stream(stream);
     if (dtype == PVJP_F64) {
-        if (op == PVJP_GOP_LOGADDEXP) dispatch_scan<GLogAddExp, double>(x, K, n, y, ckpt, ws, st);
-        else if (op == PVJP_GOP_LINREC) dispatch_scan<GLinRec, double>(x, K, n, y, ckpt, ws, st);
-        else dispatch_scan<GMat2, double>(x, K, n, y, ckpt, ws, st);
+        if (op == PVJP_GOP_LOGADDEXP) dispatch_scan<GLogAddExp, double>(x, K, n, y, ckpt, ws, st, B);
+        else if (op == PVJP_GOP_LINREC) dispatch_scan<GLinRec, double>(x, K, n, y, ckpt, ws, st, B);
+        else dispatch_scan<GMat2, double>(x, K, n, y, ckpt, ws, st, B);
     } else {
-        if (op == PVJP_GOP_LOGADDEXP) dispatch_scan<GLogAddExp, float>(x, K, n, y, ckpt, ws, st);
-        else if (op == PVJP_GOP_LINREC) dispatch_scan<GLinRec, float>(x, K, n, y, ckpt, ws, st);
-        else dispatch_scan<GMat2, float>(x, K, n, y, ckpt, ws, st);
+        if (op == PVJP_GOP_LOGADDEXP) dispatch_scan<GLogAddExp, float>(x, K, n, y, ckpt, ws, st, B);
+        else if (op == PVJP_GOP_LINREC) dispatch_scan<GLinRec, float>(x, K, n, y, ckpt, ws, st, B);
+        else dispatch_scan<GMat2, float>(x, K, n, y, ckpt, ws, st, B);
     }
-    PVJP_LAUNCHED("pvjp_scan_generic");
+    PVJP_LAUNCHED(name);
     return PVJP_OK;
+}
+
+static pvjp_status scan_vjp_impl(const char* name, pvjp_gop op, pvjp_dtype dtype, const void* const* x, int64_t B,
+                                 int64_t n, const void* ckpt, const void* const* y_bar, void* const* x_bar,
+                                 int accumulate, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    const pvjp_status s = check_scan(name, op, dtype, x, B, n, ckpt, ws, ws_bytes);
+    if (s != PVJP_OK) return s;
+    if (n == 0) return PVJP_OK;
+    const int K = gop_components(op);
+    PVJP_REQUIRE(y_bar != nullptr && x_bar != nullptr, "%s: y_bar and x_bar must be non-NULL", name);
+    for (int c = 0; c < K; ++c) {
+        PVJP_REQUIRE(y_bar[c] != nullptr, "%s: component %d of y_bar is NULL", name, c);
+        PVJP_REQUIRE(x_bar[c] != nullptr, "%s: component %d of x_bar is NULL", name, c);
+        PVJP_REQUIRE(aligned(y_bar[c], dsize(dtype)) && aligned(x_bar[c], dsize(dtype)),
+                     "%s: component %d of y_bar or x_bar is misaligned", name, c);
+    }
+    const hipStream_t st = as_stream(stream);
+    const int a = accumulate;
+    if (dtype == PVJP_F64) {
+        if (op == PVJP_GOP_LOGADDEXP) dispatch_scan_vjp<GLogAddExp, double>(x, K, n, ckpt, y_bar, x_bar, a, ws, st, B);
+        else if (op == PVJP_GOP_LINREC) dispatch_scan_vjp<GLinRec, double>(x, K, n, ckpt, y_bar, x_bar, a, ws, st, B);
+        else dispatch_scan_vjp<GMat2, double>(x, K, n, ckpt, y_bar, x_bar, a, ws, st, B);
+    } else {
+        if (op == PVJP_GOP_LOGADDEXP) dispatch_scan_vjp<GLogAddExp, float>(x, K, n, ckpt, y_bar, x_bar, a, ws, st, B);
+        else if (op == PVJP_GOP_LINREC) dispatch_scan_vjp<GLinRec, float>(x, K, n, ckpt, y_bar, x_bar, a, ws, st, B);
+        else dispatch_scan_vjp<GMat2, float>(x, K, n, ckpt, y_bar, x_bar, a, ws, st, B);
+    }
+    PVJP_LAUNCHED(name);
+    return PVJP_OK;
+}
+
+extern "C" pvjp_status pvjp_scan_generic(pvjp_gop op, pvjp_dtype dtype, const void* const* x, int64_t n,
+                                         void* const* y, void* ckpt, void* ws, size_t ws_bytes, void* stream) {
+    return scan_impl("pvjp_scan_generic", op, dtype, x, 1, n, y, ckpt, ws, ws_bytes, stream);
 }
 
 extern "C" pvjp_status pvjp_scan_generic_vjp(pvjp_gop op, pvjp_dtype dtype, const void* const* x, int64_t n,
                                              const void* ckpt, const void* const* y_bar, void* const* x_bar,
                                              int accumulate, void* ws, size_t ws_bytes, void* stream) {
-    clear_error();
-    const pvjp_status s = check_scan("pvjp_scan_generic_vjp", op, dtype, x, n, ckpt, ws, ws_bytes);
-    if (s != PVJP_OK) return s;
-    if (n == 0) return PVJP_OK;
-    const int K = gop_components(op);
-    PVJP_REQUIRE(y_bar != nullptr && x_bar != nullptr, "pvjp_scan_generic_vjp: y_bar and x_bar must be non-NULL");
-    for (int c = 0; c < K; ++c) {
-        PVJP_REQUIRE(y_bar[c] != nullptr, "pvjp_scan_generic_vjp: component %d of y_bar is NULL", c);
-        PVJP_REQUIRE(x_bar[c] != nullptr, "pvjp_scan_generic_vjp: component %d of x_bar is NULL", c);
-        PVJP_REQUIRE(aligned(y_bar[c], dsize(dtype)) && aligned(x_bar[c], dsize(dtype)),
-                     "pvjp_scan_generic_vjp: component %d of y_bar or x_bar is misaligned", c);
-    }
-    const hipStream_t st = as_stream(stream);
-    if (dtype == PVJP_F64) {
-        if (op == PVJP_GOP_LOGADDEXP)
-            dispatch_scan_vjp<GLogAddExp, double>(x, K, n, ckpt, y_bar, x_bar, accumulate, ws, st);
-        else if (op == PVJP_GOP_LINREC)
-            dispatch_scan_vjp<GLinRec, double>(x, K, n, ckpt, y_bar, x_bar, accumulate, ws, st);
-        else
-            dispatch_scan_vjp<GMat2, double>(x, K, n, ckpt, y_bar, x_bar, accumulate, ws, st);
-    } else {
-        if (op == PVJP_GOP_LOGADDEXP)
-            dispatch_scan_vjp<GLogAddExp, float>(x, K, n, ckpt, y_bar, x_bar, accumulate, ws, st);
-        else if (op == PVJP_GOP_LINREC)
-            dispatch_scan_vjp<GLinRec, float>(x, K, n, ckpt, y_bar, x_bar, accumulate, ws, st);
-        else
-            dispatch_scan_vjp<GMat2, float>(x, K, n, ckpt, y_bar, x_bar, accumulate, ws, st);
-    }
-    PVJP_LAUNCHED("pvjp_scan_generic_vjp");
-    return PVJP_OK;
+    return scan_vjp_impl("pvjp_scan_generic_vjp", op, dtype, x, 1, n, ckpt, y_bar, x_bar, accumulate, ws, ws_bytes,
+                         stream);
+}
+
+extern "C" pvjp_status pvjp_scan_generic_batched(pvjp_gop op, pvjp_dtype dtype, const void* const* x, int64_t B,
+                                                 int64_t L, void* const* y, void* ckpt, void* ws, size_t ws_bytes,
+                                                 void* stream) {
+    return scan_impl("pvjp_scan_generic_batched", op, dtype, x, B, L, y, ckpt, ws, ws_bytes, stream);
+}
+
+extern "C" pvjp_status pvjp_scan_generic_batched_vjp(pvjp_gop op, pvjp_dtype dtype, const void* const* x, int64_t B,
+                                                     int64_t L, const void* ckpt, const void* const* y_bar,
+                                                     void* const* x_bar, int accumulate, void* ws, size_t ws_bytes,
+                                                     void* stream) {
+    return scan_vjp_impl("pvjp_scan_generic_batched_vjp", op, dtype, x, B, L, ckpt, y_bar, x_bar, accumulate, ws,
+                         ws_bytes, stream);
 }
 
 // ------------------------------------------------------- forward mode entries

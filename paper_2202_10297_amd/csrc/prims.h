@@ -157,6 +157,8 @@ __device__ __forceinline__ typename Op::S wave_exclusive_scan(typename Op::S v) 
 // taken in groups of 64, one wave per group: group_fold_kernel folds each
 // group, agg_scan_kernel scans the group folds, group_prefix_kernel gives
 // every tile its group's prefix folded with the group's tiles before it.
+// blockIdx.y selects one of several independent scans laid out back to back
+// (segment y's tiles at y nt, its groups at y ng); a 1-D grid is segment 0.
 constexpr int kAggBlock = 1024;
 constexpr int kAggGroup = kWave;
 constexpr int kGroupBlock = 256;
@@ -169,6 +171,8 @@ __global__ __launch_bounds__(kAggBlock) void agg_scan_kernel(const typename Op::
                                                              typename Op::S* __restrict__ pre) {
     using S = typename Op::S;
     __shared__ S wtot[kAggBlock / kWave];
+    agg += (int64_t)blockIdx.y * cnt;
+    pre += (int64_t)blockIdx.y * cnt;
     const int64_t per = (cnt + kAggBlock - 1) / kAggBlock;
     const int64_t v0 = (int64_t)threadIdx.x * per;
     const int64_t v1 = (v0 + per < cnt) ? v0 + per : cnt;
@@ -187,6 +191,8 @@ template <class Op, bool REV>
 __global__ __launch_bounds__(kGroupBlock) void group_fold_kernel(const typename Op::S* __restrict__ agg, int64_t nt,
                                                                  int64_t ng, typename Op::S* __restrict__ gagg) {
     using S = typename Op::S;
+    agg += (int64_t)blockIdx.y * nt;
+    gagg += (int64_t)blockIdx.y * ng;
     const int64_t g = (int64_t)blockIdx.x * (kGroupBlock / kWave) + threadIdx.x / kWave;
     if (g >= ng) return;  // whole waves leave together
     const int lane = threadIdx.x & (kWave - 1);
@@ -201,6 +207,9 @@ __global__ __launch_bounds__(kGroupBlock) void group_prefix_kernel(const typenam
                                                                    int64_t ng, const typename Op::S* __restrict__ gpre,
                                                                    typename Op::S* __restrict__ pre) {
     using S = typename Op::S;
+    agg += (int64_t)blockIdx.y * nt;
+    gpre += (int64_t)blockIdx.y * ng;
+    pre += (int64_t)blockIdx.y * nt;
     const int64_t g = (int64_t)blockIdx.x * (kGroupBlock / kWave) + threadIdx.x / kWave;
     if (g >= ng) return;
     const int lane = threadIdx.x & (kWave - 1);

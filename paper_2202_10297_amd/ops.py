@@ -473,3 +473,47 @@ def gather_map_vjp(op, as_, is_, vs, ys_bar, as_bar=None, vs_bar=None, accumulat
     capi.call("pvjp_gather_map_vjp", o, _dt(as_), _ptr(as_), n, _ptr(is_), _ptr(vs), m, _ptr(ys_bar), _ptr(ab),
               _ptr(vb), int(accumulate), _ptr(ws), ws.numel(), _stream(dev))
     return ab, vb
+
+
+def _rows(op, xs):
+    xs, _, K = _components(op, xs)
+    if xs[0].dim() != 2:
+        raise ValueError("batched scans take [B, L] component tensors")
+    B, L = xs[0].shape
+    if any(tuple(x.shape) != (B, L) for x in xs):
+        raise ValueError("component tensors differ in shape")
+    return xs, B, L, K
+
+
+def scan_generic_batched(op, xs, ckpt: bool = True):
+    """Each row of the [B, L] component tensors scanned independently with a
+    general operator (the regular segmented scan that a vectorised operator
+    becomes).  Returns (ys, ckpt) like scan_generic."""
+    xs, B, L, K = _rows(op, xs)
+    dt, dev = _dt(xs[0]), xs[0].device
+    ys = [torch.empty_like(x) for x in xs]
+    ck = None
+    if ckpt:
+        ck = torch.empty(max(capi.lib().pvjp_scan_generic_batched_ckpt_bytes(_gop(op), dt, B, L), 16),
+                         dtype=torch.uint8, device=dev)
+    nb = capi.lib().pvjp_scan_generic_batched_ws_bytes(_gop(op), dt, B, L)
+    ws = WS.get("scan_generic", nb, dev)
+    capi.call("pvjp_scan_generic_batched", _gop(op), dt, capi.ptr_array([_ptr(x) for x in xs]), B, L,
+              capi.ptr_array([_ptr(y) for y in ys]), _ptr(ck), _ptr(ws), ws.numel(), _stream(dev))
+    return ys, ck
+
+
+def scan_generic_batched_vjp(op, xs, y_bar, x_bar=None, accumulate=False, ckpt=None):
+    """The VJP of scan_generic_batched, row by row (lists of K [B, L] tensors)."""
+    xs, B, L, K = _rows(op, xs)
+    dt, dev = _dt(xs[0]), xs[0].device
+    if x_bar is None:
+        x_bar = [torch.zeros_like(x) if accumulate else torch.empty_like(x) for x in xs]
+    if len(y_bar) != K or len(x_bar) != K:
+        raise ValueError(f"operator {op} takes {K} components")
+    nb = capi.lib().pvjp_scan_generic_batched_ws_bytes(_gop(op), dt, B, L)
+    ws = WS.get("scan_generic", nb, dev)
+    capi.call("pvjp_scan_generic_batched_vjp", _gop(op), dt, capi.ptr_array([_ptr(x) for x in xs]), B, L,
+              _ptr(ckpt), capi.ptr_array([_ptr(y) for y in y_bar]), capi.ptr_array([_ptr(x) for x in x_bar]),
+              int(accumulate), _ptr(ws), ws.numel(), _stream(dev))
+    return x_bar
