@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 23, help="elements per instance for the CPU oracle")
     ap.add_argument("--skip", default="", help="comma list of extra workloads to skip: reduce_map,reduce_generic,scan_generic,jvp,kmeans,"
-                         "gather_map,scan,gmm,batch,serve")
+                         "gather_map,scan_batched,scan,gmm,batch,serve")
     ap.add_argument("--only", default="",
                     help="run just this one extra workload (for profiling) and print its JSON instead of the "
                          "benchmark line")
@@ -222,7 +222,7 @@ def main():
     if args.only:
         fns = {"reduce_map": bench_reduce_map, "reduce_generic": bench_reduce_generic,
                "scan_generic": bench_scan_generic, "jvp": bench_jvp, "kmeans": bench_kmeans, "gather_map": bench_gather_map,
-               "scan": bench_scan,
+               "scan_batched": bench_scan_batched, "scan": bench_scan,
                "gmm": bench_gmm, "batch": bench_batch, "serve": bench_serve}
         print(json.dumps({args.only: fns[args.only](args)}))
         return
@@ -384,7 +384,7 @@ def main():
     extra = {}
     for name, fn in (("reduce_map", bench_reduce_map), ("reduce_generic", bench_reduce_generic),
                      ("scan_generic", bench_scan_generic), ("jvp", bench_jvp), ("kmeans", bench_kmeans),
-                     ("gather_map", bench_gather_map), ("scan", bench_scan), ("gmm", bench_gmm),
+                     ("gather_map", bench_gather_map), ("scan_batched", bench_scan_batched), ("scan", bench_scan), ("gmm", bench_gmm),
                      ("batch", bench_batch), ("serve", bench_serve)):
         if name in args.skip:
             continue
@@ -699,6 +699,37 @@ def bench_scan_generic(args):
                 "vjp_elems_per_s": round(n / (tv * 1e-3), 1)}
             del xs, xb, yb, ck
             torch.cuda.empty_cache()
+    return res
+
+
+def bench_scan_batched(args):
+    """The regular segmented scan (a vectorised operator's scan): B = 1024
+    rows of L = 65536 (2^26 elements, as the single scan above), with the
+    per-tile checkpoint; the same algorithmic and moved bytes per element."""
+    import torch
+
+    from paper_2202_10297_amd import ops
+
+    B, L = 1024, 1 << 16
+    n = B * L
+    res = {}
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    for op, K, dt, tname, es in (("logaddexp", 1, torch.float32, "f32", 4), ("linrec", 2, torch.float64, "f64", 8),
+                                 ("mat2", 4, torch.float32, "f32", 4)):
+        xs = [x.view(B, L) for x in _gop_inputs(op, n, dt, g)]
+        yb = [torch.randn(B, L, dtype=dt, device="cuda", generator=g) for _ in range(K)]
+        xb = [torch.empty_like(x) for x in xs]
+        _, ck = ops.scan_generic_batched(op, xs)
+        tp = _events_ms(lambda: ops.scan_generic_batched(op, xs), 5)
+        tv = _events_ms(lambda: ops.scan_generic_batched_vjp(op, xs, yb, x_bar=xb, ckpt=ck), 5)
+        comp = n * K * es
+        res[f"{op}_{tname}"] = {
+            "primal_ms": round(tp, 4), "vjp_ms": round(tv, 4), "grad_over_primal": round((tp + tv) / tp, 3),
+            "primal_hbm_frac": round(2 * comp / (tp * 1e-3) / 1e9 / HBM_PEAK_GBPS, 3),
+            "vjp_hbm_frac": round(3 * comp / (tv * 1e-3) / 1e9 / HBM_PEAK_GBPS, 3)}
+        del xs, xb, yb, ck
+        torch.cuda.empty_cache()
     return res
 
 
