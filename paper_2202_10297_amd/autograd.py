@@ -197,6 +197,64 @@ class GMMLogLik(torch.autograd.Function):
         return None, ab, mb, qb, lb
 
 
+class ScanGenericBatched(torch.autograd.Function):
+    """Regular segmented scan (Sec. 5.2's vectorised-operator rule): every row
+    of the K [B, L] component tensors scanned on its own.  Saved: the inputs
+    and the per-tile prefix checkpoint of every row."""
+
+    @staticmethod
+    def forward(ctx, op, *xs):
+        xs = [x.contiguous() for x in xs]
+        ys, ck = ops.scan_generic_batched(op, xs, ckpt=True)
+        ctx.op = op
+        ctx.save_for_backward(ck, *xs)
+        return tuple(ys)
+
+    @staticmethod
+    def backward(ctx, *gys):
+        ck, *xs = ctx.saved_tensors
+        yb = [torch.zeros_like(x) if g is None else g.contiguous() for g, x in zip(gys, xs)]
+        return (None, *ops.scan_generic_batched_vjp(ctx.op, xs, yb, ckpt=ck))
+
+
+class GatherMap(torch.autograd.Function):
+    """ys[i] = f(as_[is_[i]], vs[i]) (Sec. 5.4, a map reading a free array);
+    the backward accumulates the reads' adjoints into as_ (no grad for is_)."""
+
+    @staticmethod
+    def forward(ctx, as_, is_, vs, op):
+        as_, is_ = as_.contiguous(), is_.contiguous()
+        vs = vs.contiguous() if vs is not None else None
+        ctx.op = op
+        ctx.save_for_backward(as_, is_, vs)
+        return ops.gather_map(op, as_, is_, vs)
+
+    @staticmethod
+    def backward(ctx, gys):
+        as_, is_, vs = ctx.saved_tensors
+        ab, vb = ops.gather_map_vjp(ctx.op, as_, is_, vs, gys.contiguous())
+        return ab, None, vb, None
+
+
+class KMeansObjective(torch.autograd.Function):
+    """f(C) = sum_i min_k |x_i - c_k|^2 (Sec. 7.4) for fixed points X.  Saved:
+    the assignments (the search is not repeated in the backward).  The jvp of
+    the VJP (Hessian-vector product) is ops.kmeans_vjp with C_dot."""
+
+    @staticmethod
+    def forward(ctx, X, C):
+        X, C = X.contiguous(), C.contiguous()
+        f, assign = ops.kmeans_objective(X, C)
+        ctx.save_for_backward(X, C, assign)
+        return f[0]
+
+    @staticmethod
+    def backward(ctx, gf):
+        X, C, assign = ctx.saved_tensors
+        cb, _ = ops.kmeans_vjp(X, C, assign, f_bar=float(gf))
+        return None, cb
+
+
 def linrec_scan(a, b):
     return LinRecScan.apply(a, b)
 
@@ -227,3 +285,15 @@ def map(x, fn):  # noqa: A001 - the operator's name
 
 def gmm_loglik(X, alpha, mu, q, l):
     return GMMLogLik.apply(X, alpha, mu, q, l)
+
+
+def scan_generic_batched(op, *xs):
+    return ScanGenericBatched.apply(op, *xs)
+
+
+def gather_map(as_, is_, vs=None, op="mul"):
+    return GatherMap.apply(as_, is_, vs, op)
+
+
+def kmeans_objective(X, C):
+    return KMeansObjective.apply(X, C)

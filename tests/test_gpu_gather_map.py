@@ -138,3 +138,15 @@ def test_benchmark_size_sampled(ops, orc, n, dist):
     # any size: the accumulated total is the sum of every read's partial
     tot = np.dot(vs.astype(np.float64), yb.astype(np.float64))
     assert abs(ab.astype(np.float64).sum() - tot) <= 1e-5 * np.abs(vs * yb).sum()
+
+
+def test_autograd(orc):
+    from paper_2202_10297_amd import autograd
+
+    as_, is_, vs, yb = inputs(20001, 300, "zipf", "f64", seed=12)
+    a, v = dev(as_).requires_grad_(), dev(vs).requires_grad_()
+    ys = autograd.gather_map(a, dev(is_), v, op="sqdiff")
+    (ys * dev(yb)).sum().backward()
+    rab, rvb = orc.gather_map_vjp("sqdiff", as_, is_, vs, yb)
+    assert rel_l2(host(a.grad), rab) <= TOL_F64
+    assert rel_l2(host(v.grad), rvb) <= TOL_F64

@@ -87,3 +87,16 @@ def test_kmeans_empty_input_and_ties(ops, orc):
     assert host(f)[0] == 0.0
     cb, _ = ops.kmeans_vjp(dev(np.zeros((0, 2), dtype=np.float32)), dev(C), a)
     assert np.all(host(cb) == 0)
+
+
+def test_autograd(orc):
+    from paper_2202_10297_amd import autograd
+
+    X, C = workloads.kmeans(5000, 35, 5, "f32", seed=14)
+    c = dev(C).requires_grad_()
+    f = autograd.kmeans_objective(dev(X), c)
+    (0.5 * f).backward()
+    ref = orc.kmeans_vjp(X.astype(np.float64), C.astype(np.float64), 0.5)
+    assert rel_l2(host(c.grad), ref) <= TOL_F32
+    fv = float(f.detach())
+    assert abs(fv - orc.kmeans_objective(X, C)[0]) <= 1e-12 * fv

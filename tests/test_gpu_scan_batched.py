@@ -147,3 +147,13 @@ def test_benchmark_size_sampled_rows(ops, orc, op, dtype):
                      1e-12 if dtype == "f64" else 1e-5)
         assert rel_l2([host(g[b]) for g in xb], orc.scan_generic_vjp(op, [x[b] for x in xs], [y[b] for y in ybs])) \
             <= tol(dtype)
+
+
+def test_autograd(orc):
+    from paper_2202_10297_amd import autograd
+
+    xs, ybs = rows("mat2", 5, 3001, "f64", seed=13)
+    t = [dev(x).requires_grad_() for x in xs]
+    ys = autograd.scan_generic_batched("mat2", *t)
+    sum((y * dev(g)).sum() for y, g in zip(ys, ybs)).backward()
+    assert rel_l2([host(x.grad) for x in t], orc.scan_generic_rows_vjp("mat2", xs, ybs)) <= TOL_F64
