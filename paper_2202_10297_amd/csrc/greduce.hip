@@ -343,6 +343,119 @@ struct LinG {
     }
 };
 
+// lin_o states of the scan VJP per operator.  The general form keeps J_left^T
+// as a dense d x d matrix (LinG).  For the 2 x 2 matrix product J_left^T = I
+// (x) X_next (the same 2 x 2 block on the diagonal twice), and lin_o
+// compositions keep that form, (I (x) M2)(I (x) M1) = I (x) M2 M1, so the state
+// is (v[4], M[2][2]): a 2 x 2 product per composition instead of a 4 x 4 one,
+// with the same values (the dense form only adds exact zeros).
+template <class A>
+struct LinKron {
+    struct S {
+        A v[4];
+        A m[2][2];
+    };
+    __device__ static __forceinline__ S id() { return S{{A(0), A(0), A(0), A(0)}, {{A(1), A(0)}, {A(0), A(1)}}}; }
+    // x first, then y: (y.v + (I (x) y.m) x.v, y.m x.m)
+    __device__ static __forceinline__ S comb(const S& x, const S& y) {
+        S r;
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+                r.v[2 * b + a] = y.v[2 * b + a] + y.m[a][0] * x.v[2 * b] + y.m[a][1] * x.v[2 * b + 1];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) r.m[a][c] = y.m[a][0] * x.m[0][c] + y.m[a][1] * x.m[1][c];
+        return r;
+    }
+    template <class F>
+    __device__ static __forceinline__ S map(const S& v, F f) {
+        S r;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) r.v[i] = f(v.v[i]);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) r.m[a][c] = f(v.m[a][c]);
+        return r;
+    }
+    __device__ static __forceinline__ S up(S v, int d) {
+        return map(v, [d](A a) { return shfl_up1(a, d); });
+    }
+    __device__ static __forceinline__ S down(S v, int d) {
+        return map(v, [d](A a) { return shfl_down1(a, d); });
+    }
+    __device__ static __forceinline__ S idx(S v, int s) {
+        return map(v, [s](A a) { return shfl_idx1(a, s); });
+    }
+};
+
+// The lin_o element of position k, (y_bar_k, J_left(k)^T) with the next
+// element nx (a zero matrix where nothing follows), and one step of the
+// reversed recurrence r_k = y_bar_k + J_left(k)^T r_(k+1).
+template <class Op>
+struct LinOf {
+    using A = typename Op::Acc;
+    static constexpr int K = Op::K;
+    using L = LinG<A, K>;
+    __device__ static __forceinline__ typename L::S elem(const typename Op::S& y, const A (&nx)[K], bool has_next,
+                                                         const A (&yb)[K]) {
+        typename L::S e;
+        if (has_next) {
+            Op::jlT(y, nx, e.c);
+        } else {
+#pragma unroll
+            for (int i = 0; i < K; ++i)
+#pragma unroll
+                for (int j = 0; j < K; ++j) e.c[i][j] = A(0);
+        }
+#pragma unroll
+        for (int c = 0; c < K; ++c) e.v[c] = yb[c];
+        return e;
+    }
+    __device__ static __forceinline__ void step(const typename Op::S& y, const A (&nx)[K], bool has_next,
+                                                const A (&yb)[K], const A (&r)[K], A (&rn)[K]) {
+        const typename L::S e = elem(y, nx, has_next, yb);
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            A v = e.v[i];
+#pragma unroll
+            for (int j = 0; j < K; ++j) v += e.c[i][j] * r[j];
+            rn[i] = v;
+        }
+    }
+};
+
+template <class A0>
+struct LinOf<GMat2<A0>> {
+    using A = A0;
+    static constexpr int K = 4;
+    using L = LinKron<A>;
+    __device__ static __forceinline__ typename L::S elem(const typename GMat2<A>::S&, const A (&nx)[4], bool has_next,
+                                                         const A (&yb)[4]) {
+        typename L::S e;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) e.v[c] = yb[c];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) e.m[a][c] = has_next ? nx[2 * a + c] : A(0);
+        return e;
+    }
+    __device__ static __forceinline__ void step(const typename GMat2<A>::S&, const A (&nx)[4], bool has_next,
+                                                const A (&yb)[4], const A (&r)[4], A (&rn)[4]) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+                rn[2 * b + a] = has_next ? yb[2 * b + a] + nx[2 * a] * r[2 * b] + nx[2 * a + 1] * r[2 * b + 1]
+                                         : yb[2 * b + a];
+    }
+};
+
+
 template <class T>
 struct GPtrs {
     const T* p[8];
@@ -659,43 +772,30 @@ __device__ __forceinline__ void gs_run_states(const GPtrs<T>& x, int64_t n, int6
     }
 }
 
-// The lin_o element of position k of a run: (y_bar_k, J_left(k)^T), with a
-// zero matrix at the last index of the array (nothing follows it).
+// The element after position k of a run (the run's next element past its end).
 template <class Op, int IPT>
-__device__ __forceinline__ void gs_jl(const typename Op::S (&ys)[IPT], const typename Op::Acc (&xa)[Op::K][IPT],
-                                      const typename Op::Acc (&xn)[Op::K], int k, bool has_next,
-                                      typename Op::Acc (&cT)[Op::K][Op::K]) {
-    using A = typename Op::Acc;
-    constexpr int K = Op::K;
-    if (!has_next) {
+__device__ __forceinline__ void gs_next(const typename Op::Acc (&xa)[Op::K][IPT], const typename Op::Acc (&xn)[Op::K],
+                                        int k, typename Op::Acc (&nx)[Op::K]) {
 #pragma unroll
-        for (int i = 0; i < K; ++i)
-#pragma unroll
-            for (int j = 0; j < K; ++j) cT[i][j] = A(0);
-        return;
-    }
-    A nx[K];
-#pragma unroll
-    for (int c = 0; c < K; ++c) nx[c] = k + 1 < IPT ? xa[c][k + 1 < IPT ? k + 1 : 0] : xn[c];
-    Op::jlT(ys[k], nx, cT);
+    for (int c = 0; c < Op::K; ++c) nx[c] = k + 1 < IPT ? xa[c][k + 1 < IPT ? k + 1 : 0] : xn[c];
 }
 
 // Fold of a run's lin_o elements in reversed index order.
 template <class Op, class T, int IPT>
-__device__ __forceinline__ typename LinG<typename Op::Acc, Op::K>::S gs_run_lin(
+__device__ __forceinline__ typename LinOf<Op>::L::S gs_run_lin(
     const typename Op::S (&ys)[IPT], const typename Op::Acc (&xa)[Op::K][IPT], const typename Op::Acc (&xn)[Op::K],
     const T (&yb)[Op::K][IPT], int64_t n, int64_t base, int cnt) {
     using A = typename Op::Acc;
-    using LG = LinG<A, Op::K>;
+    using LG = typename LinOf<Op>::L;
     typename LG::S run = LG::id();
 #pragma unroll
     for (int k = IPT - 1; k >= 0; --k) {
         if (k < cnt) {
-            typename LG::S e;
-            gs_jl<Op, IPT>(ys, xa, xn, k, base + k + 1 < n, e.c);
+            A nx[Op::K], ybk[Op::K];
+            gs_next<Op, IPT>(xa, xn, k, nx);
 #pragma unroll
-            for (int c = 0; c < Op::K; ++c) e.v[c] = (A)yb[c][k];
-            run = LG::comb(run, e);
+            for (int c = 0; c < Op::K; ++c) ybk[c] = (A)yb[c][k];
+            run = LG::comb(run, LinOf<Op>::elem(ys[k], nx, base + k + 1 < n, ybk));
         }
     }
     return run;
@@ -732,10 +832,10 @@ __global__ __launch_bounds__(kGrBlock) void gscan_fwd_kernel(GPtrs<T> x, int64_t
 template <class Op, class T, int IPT, bool VEC>
 __global__ __launch_bounds__(kGrBlock) void gscan_vjp_agg_kernel(
     GPtrs<T> x, int64_t n, const typename Op::S* __restrict__ pre, GPtrs<T> ybar,
-    typename LinG<typename Op::Acc, Op::K>::S* __restrict__ lagg) {
+    typename LinOf<Op>::L::S* __restrict__ lagg) {
     using S = typename Op::S;
     using A = typename Op::Acc;
-    using LG = LinG<A, Op::K>;
+    using LG = typename LinOf<Op>::L;
     constexpr int K = Op::K;
     __shared__ S wtot[kGrBlock / kWave];
     __shared__ typename LG::S ltot[kGrBlock / kWave];
@@ -762,10 +862,10 @@ __global__ __launch_bounds__(kGrBlock) void gscan_vjp_agg_kernel(
 template <class Op, class T, int IPT, bool VEC, bool ACC>
 __global__ __launch_bounds__(kGrBlock) void gscan_vjp_kernel(
     GPtrs<T> x, int64_t n, const typename Op::S* __restrict__ pre, GPtrs<T> ybar,
-    const typename LinG<typename Op::Acc, Op::K>::S* __restrict__ lsuf, GOut<T> xbar) {
+    const typename LinOf<Op>::L::S* __restrict__ lsuf, GOut<T> xbar) {
     using S = typename Op::S;
     using A = typename Op::Acc;
-    using LG = LinG<A, Op::K>;
+    using LG = typename LinOf<Op>::L;
     constexpr int K = Op::K;
     __shared__ S wtot[kGrBlock / kWave];
     __shared__ typename LG::S ltot[kGrBlock / kWave];
@@ -790,16 +890,11 @@ __global__ __launch_bounds__(kGrBlock) void gscan_vjp_kernel(
     T out[K][IPT];
 #pragma unroll
     for (int k = IPT - 1; k >= 0; --k) {
-        A cT[K][K];
-        gs_jl<Op, IPT>(ys, xa, xn, k, base + k + 1 < n, cT);
-        A rn[K];
+        A nx[K], ybk[K], rn[K];
+        gs_next<Op, IPT>(xa, xn, k, nx);
 #pragma unroll
-        for (int i = 0; i < K; ++i) {
-            A v = (A)yb[i][k];
-#pragma unroll
-            for (int j = 0; j < K; ++j) v += cT[i][j] * r[j];
-            rn[i] = v;
-        }
+        for (int c = 0; c < K; ++c) ybk[c] = (A)yb[c][k];
+        LinOf<Op>::step(ys[k], nx, base + k + 1 < n, ybk, r, rn);
         A xk[K], o[K];
 #pragma unroll
         for (int c = 0; c < K; ++c) {
@@ -1086,7 +1181,7 @@ template <class Op, class T>
 static void launch_scan_vjp(const GPtrs<T>& x, int64_t n, const void* ckpt, const GPtrs<T>& yb, const GOut<T>& xb,
                             int acc, void* ws, bool vec, hipStream_t st, int64_t B = 1) {
     using S = typename Op::S;
-    using LG = LinG<typename Op::Acc, Op::K>;
+    using LG = typename LinOf<Op>::L;
     using LS = typename LG::S;
     static_assert(sizeof(LS) <= kLinSlot, "lin_o slot too small");
     constexpr int IPT = gs_ipt<Op, T>();
