@@ -716,12 +716,17 @@ __global__ __launch_bounds__(kGrBlock) void gred_vjp_kernel(GPtrs<T> x, int64_t 
 //
 // Items per thread: at most 32 bytes of each input component and 64 bytes
 // of inputs in the arithmetic type (the per-element states and Jacobians
-// live in registers).
+// live in registers); 128 bytes for the 2 x 2 matrix product, whose lin_o
+// state is small in its Kronecker form.
+template <class Op>
+constexpr int gs_arith_budget() {
+    return Op::K == 4 ? 128 : 64;
+}
 template <class Op, class T>
 constexpr int gs_ipt() {
-    return (32 / (int)sizeof(T)) < (64 / (Op::K * (int)sizeof(typename Op::Acc)))
+    return (32 / (int)sizeof(T)) < (gs_arith_budget<Op>() / (Op::K * (int)sizeof(typename Op::Acc)))
                ? 32 / (int)sizeof(T)
-               : 64 / (Op::K * (int)sizeof(typename Op::Acc));
+               : gs_arith_budget<Op>() / (Op::K * (int)sizeof(typename Op::Acc));
 }
 template <class Op, class T>
 constexpr int gs_tile() {

@@ -26,7 +26,7 @@ OPS = ["logaddexp", "linrec", "mat2"]
 def tile(op, dtype):
     if op == "logaddexp":
         return 2048 if dtype == "f32" else 1024
-    return 1024 if op == "linrec" else 512
+    return 1024  # linear recurrence and 2x2 product: 256 threads x 4 items
 
 
 def dev(x):
