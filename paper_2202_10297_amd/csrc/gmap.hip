@@ -69,21 +69,6 @@ __global__ __launch_bounds__(256) void gm_fwd_kernel(const T* __restrict__ as, i
     }
 }
 
-// vs_bar for element i and the element's partial for as_bar (ok: in range).
-template <int OP, class T>
-__device__ inline bool gm_elem(const T* __restrict__ as, int64_t n, const int32_t* __restrict__ is,
-                               const T* __restrict__ vs, const T* __restrict__ yb, int64_t i, T* __restrict__ vbar,
-                               int accumulate, int64_t& k, double& pa) {
-    k = is[i];
-    const bool ok = k >= 0 && k < n;
-    const double a = ok ? (double)as[k] : 0.0;
-    const double v = OP ? (double)vs[i] : 0.0;
-    double pv;
-    gm_partials<OP>(a, v, (double)yb[i], pa, pv);
-    if (OP) vbar[i] = accumulate ? vbar[i] + (T)pv : (T)pv;
-    return ok;
-}
-
 // LDS plan: block b takes elements [b chunk, (b+1) chunk), adds each read's
 // partial into its LDS bin, then writes its n bins to part[b][.].
 template <int OP, class T>
@@ -154,11 +139,30 @@ __global__ __launch_bounds__(256) void gm_contrib_kernel(const T* __restrict__ a
                                                          const int32_t* __restrict__ is, const T* __restrict__ vs,
                                                          const T* __restrict__ yb, int64_t m, T* __restrict__ vbar,
                                                          int accumulate, T* __restrict__ c) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
-        int64_t k;
-        double pa;
-        const bool ok = gm_elem<OP, T>(as, n, is, vs, yb, i, vbar, accumulate, k, pa);
-        c[i] = ok ? (T)pa : T(0);
+    const int64_t step = (int64_t)gridDim.x * blockDim.x * kGmU;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x * kGmU + threadIdx.x; base < m; base += step) {
+        int32_t k[kGmU];
+        T v[kGmU], y[kGmU], a[kGmU];
+#pragma unroll
+        for (int u = 0; u < kGmU; ++u) {
+            const int64_t i = base + (int64_t)u * blockDim.x;
+            const bool in = i < m;
+            k[u] = in ? is[i] : -1;
+            v[u] = (OP && in) ? vs[i] : T(0);
+            y[u] = in ? yb[i] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kGmU; ++u) a[u] = (OP && k[u] >= 0 && k[u] < n) ? as[k[u]] : T(0);
+#pragma unroll
+        for (int u = 0; u < kGmU; ++u) {
+            const int64_t i = base + (int64_t)u * blockDim.x;
+            if (i < m) {
+                double pa, pv;
+                gm_partials<OP>((double)a[u], (double)v[u], (double)y[u], pa, pv);
+                if (OP) vbar[i] = accumulate ? vbar[i] + (T)pv : (T)pv;
+                c[i] = (k[u] >= 0 && k[u] < n) ? (T)pa : T(0);
+            }
+        }
     }
 }
 
