@@ -66,6 +66,9 @@ _SIGS = {
     "orc_kmeans_vjp": [_L, _I, _I, _P, _P, _D, _P],
     "orc_kmeans_hvp": [_L, _I, _I, _P, _P, _D, _P, _P],
     "orc_gather_map": [_I, _L, _P, _L, _P, _P, _P],
+    "orc_skm_objective": [_L, _L, _I, _P, _P, _P, _P, _P, _P],
+    "orc_skm_vjp": [_L, _L, _I, _P, _P, _P, _P, _D, _P],
+    "orc_skm_hvp": [_L, _L, _I, _P, _P, _P, _P, _D, _P, _P],
     "orc_gather_map_vjp": [_I, _L, _P, _L, _P, _P, _P, _P, _P],
 }
 
@@ -452,4 +455,36 @@ def scan_generic_rows_vjp(op, xs, ys_bar):
         g = scan_generic_vjp(op, [x[b] for x in xs], [y[b] for y in yb])
         for o, v in zip(out, g):
             o[b] = v
+    return out
+
+
+# ---------------------------------------------------------- sparse k-means
+def _i64(x):
+    return np.ascontiguousarray(np.asarray(x, dtype=np.int64))
+
+
+def sparse_kmeans_objective(rowptr, col, val, D, C):
+    """(f, assign) for CSR points and dense centres C [K, D] (Sec. 7.5)."""
+    rp, cl, v, C = _i64(rowptr), _i32(col), _f64(val), _f64(C)
+    N = rp.size - 1
+    a = np.empty(N, dtype=np.int32)
+    f = np.zeros(1)
+    _check(lib().orc_skm_objective(N, D, C.shape[0], _p(rp), _p(cl), _p(v), _p(C), _p(a), _p(f)),
+           "sparse_kmeans_objective")
+    return float(f[0]), a
+
+
+def sparse_kmeans_vjp(rowptr, col, val, D, C, f_bar=1.0):
+    rp, cl, v, C = _i64(rowptr), _i32(col), _f64(val), _f64(C)
+    out = np.empty_like(C)
+    _check(lib().orc_skm_vjp(rp.size - 1, D, C.shape[0], _p(rp), _p(cl), _p(v), _p(C), float(f_bar), _p(out)),
+           "sparse_kmeans_vjp")
+    return out
+
+
+def sparse_kmeans_hvp(rowptr, col, val, D, C, C_dot, f_bar=1.0):
+    rp, cl, v, C, Cd = _i64(rowptr), _i32(col), _f64(val), _f64(C), _f64(C_dot)
+    out = np.empty_like(C)
+    _check(lib().orc_skm_hvp(rp.size - 1, D, C.shape[0], _p(rp), _p(cl), _p(v), _p(C), float(f_bar), _p(Cd),
+                             _p(out)), "sparse_kmeans_hvp")
     return out

@@ -1422,3 +1422,115 @@ int orc_gather_map_vjp(int op, int64_t n, const double* as, int64_t m, const int
     tape_free(t);
     return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Sparse k-means (Sec. 7.5): points in CSR (rowptr [N+1], col [nnz], val    */
+/* [nnz]), dense centres C [K x D].  The cost is the dense one with the      */
+/* squared distance.  The distance of row i to centre k is one FP64 chain:  */
+/* acc = |c_k|^2, then for every stored (j, x) of the row in CSR order       */
+/* acc = fma(x, x - 2 c_kj, acc) (|x - c|^2 = |c|^2 + sum over stored x of   */
+/* x (x - 2 c)).  |c_k|^2 is fixed too: blocks of 1024 dimensions, each an   */
+/* fma chain in d order, the block sums added in block order.  Ties go to    */
+/* the lowest k.  The gradient at fixed assignments is the plain closed form */
+/* 2 f_bar (n_k c_k - S_k), S_k the sum of the rows assigned to k, and the   */
+/* jvp of the VJP is 2 f_bar n_k C_dot_k.                                    */
+static double skm_cnorm(int64_t D, const double* c) {
+    double tot = 0.0;
+    for (int64_t b0 = 0; b0 < D; b0 += 1024) {
+        const int64_t b1 = b0 + 1024 < D ? b0 + 1024 : D;
+        double s = 0.0;
+        for (int64_t d = b0; d < b1; ++d) s = fma(c[d], c[d], s);
+        tot += s;
+    }
+    return tot;
+}
+
+static int skm_check(int64_t N, int64_t D, int K, const int64_t* rowptr, const int32_t* col, const double* val,
+                     const double* C) {
+    if (N < 0 || D < 1 || K < 1 || !rowptr || !C) return -1;
+    if (rowptr[0] != 0) return -1;
+    for (int64_t i = 0; i < N; ++i)
+        if (rowptr[i + 1] < rowptr[i]) return -1;
+    const int64_t nnz = rowptr[N];
+    if (nnz > 0 && (!col || !val)) return -1;
+    for (int64_t e = 0; e < nnz; ++e)
+        if (col[e] < 0 || col[e] >= D) return -1;
+    return 0;
+}
+
+static int skm_assign(int64_t N, int64_t D, int K, const int64_t* rowptr, const int32_t* col, const double* val,
+                      const double* C, int32_t* a, double* dmin) {
+    double* cn = (double*)malloc((size_t)K * sizeof(double));
+    if (!cn) return -2;
+    for (int k = 0; k < K; ++k) cn[k] = skm_cnorm(D, C + (int64_t)k * D);
+    for (int64_t i = 0; i < N; ++i) {
+        int best = 0;
+        double bd = 0.0;
+        for (int k = 0; k < K; ++k) {
+            const double* c = C + (int64_t)k * D;
+            double acc = cn[k];
+            for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+                const double x = val[e];
+                acc = fma(x, x - 2.0 * c[col[e]], acc);
+            }
+            if (k == 0 || acc < bd) bd = acc, best = k;
+        }
+        a[i] = best;
+        if (dmin) dmin[i] = bd;
+    }
+    free(cn);
+    return 0;
+}
+
+int orc_skm_objective(int64_t N, int64_t D, int K, const int64_t* rowptr, const int32_t* col, const double* val,
+                      const double* C, int32_t* assign, double* f) {
+    if (skm_check(N, D, K, rowptr, col, val, C) || !f) return -1;
+    int32_t* a = assign ? assign : (int32_t*)malloc((size_t)(N > 0 ? N : 1) * sizeof(int32_t));
+    double* dm = (double*)malloc((size_t)(N > 0 ? N : 1) * sizeof(double));
+    int rc = (a && dm) ? skm_assign(N, D, K, rowptr, col, val, C, a, dm) : -2;
+    if (!rc) {
+        double s = 0.0;
+        for (int64_t i = 0; i < N; ++i) s += dm[i];
+        *f = s;
+    }
+    if (!assign) free(a);
+    free(dm);
+    return rc;
+}
+
+static int skm_grad(int64_t N, int64_t D, int K, const int64_t* rowptr, const int32_t* col, const double* val,
+                    const double* C, double f_bar, const double* C_dot, double* out) {
+    if (skm_check(N, D, K, rowptr, col, val, C) || !out) return -1;
+    int32_t* a = (int32_t*)malloc((size_t)(N > 0 ? N : 1) * sizeof(int32_t));
+    int64_t* n = (int64_t*)calloc((size_t)K, sizeof(int64_t));
+    if (!a || !n) {
+        free(a), free(n);
+        return -2;
+    }
+    int rc = skm_assign(N, D, K, rowptr, col, val, C, a, NULL);
+    if (!rc) {
+        for (int64_t i = 0; i < N; ++i) ++n[a[i]];
+        for (int k = 0; k < K; ++k)
+            for (int64_t d = 0; d < D; ++d) {
+                const int64_t e = (int64_t)k * D + d;
+                out[e] = C_dot ? 2.0 * f_bar * (double)n[k] * C_dot[e] : 2.0 * f_bar * (double)n[k] * C[e];
+            }
+        if (!C_dot)
+            for (int64_t i = 0; i < N; ++i)
+                for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
+                    out[(int64_t)a[i] * D + col[e]] -= 2.0 * f_bar * val[e];
+    }
+    free(a), free(n);
+    return rc;
+}
+
+int orc_skm_vjp(int64_t N, int64_t D, int K, const int64_t* rowptr, const int32_t* col, const double* val,
+                const double* C, double f_bar, double* C_bar) {
+    return skm_grad(N, D, K, rowptr, col, val, C, f_bar, NULL, C_bar);
+}
+
+int orc_skm_hvp(int64_t N, int64_t D, int K, const int64_t* rowptr, const int32_t* col, const double* val,
+                const double* C, double f_bar, const double* C_dot, double* out) {
+    if (!C_dot) return -1;
+    return skm_grad(N, D, K, rowptr, col, val, C, f_bar, C_dot, out);
+}
