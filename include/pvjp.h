@@ -516,6 +516,34 @@ pvjp_status pvjp_gather_map_vjp(int op, pvjp_dtype dtype, const void* as, int64_
                                 const void* vs, int64_t m, const void* ys_bar, void* as_bar, void* vs_bar,
                                 int accumulate, void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* sparse k-means (Sec. 7.5)                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* f = sum_i min_k |x_i - c_k|^2 for points in CSR (rowptr [N+1] int64 from 0
+ * to nnz, non-decreasing; col [nnz] int32 in [0, D); val [nnz] FP32) and
+ * dense centres C [K x D] FP32 row-major, 1 <= K <= 64, K D <= 2^30.
+ * Distances are the FP64 chain acc = |c_k|^2 (1024-dimension fma-chain
+ * blocks added in order), then acc = fma(x, x - 2 c_kj, acc) over the row's
+ * stored entries in order; ties go to the lowest k, so the assignments match
+ * any implementation of that chain bit for bit.  assign [N] int32 (output);
+ * f: one double.  Entries outside [0, nnz) and columns outside [0, D) are
+ * skipped rather than read.  ws: 256-byte aligned, ws_bytes >=
+ * pvjp_sparse_kmeans_ws_bytes(N, D, K, nnz), else PVJP_ENOMEM. */
+size_t pvjp_sparse_kmeans_ws_bytes(int64_t N, int64_t D, int K, int64_t nnz);
+pvjp_status pvjp_sparse_kmeans_objective(const int64_t* rowptr, const int32_t* col, const float* val, int64_t N,
+                                         int64_t D, int64_t nnz, const float* C, int K, int32_t* assign, double* f,
+                                         void* ws, size_t ws_bytes, void* stream);
+/* VJP at the objective's assignments: C_bar (+)= 2 f_bar (n_k c_k - S_k),
+ * S_k the sum of the rows assigned to k (every stored entry accumulated into
+ * bin (a_i, j) on the reduce_by_index(+) path, FP64 sums); with C_dot, also
+ * the jvp of the VJP hvp (+)= 2 f_bar n_k C_dot_k (C_dot = 1: the Hessian
+ * diagonal).  C_dot and hvp are both NULL or both set. */
+pvjp_status pvjp_sparse_kmeans_vjp(const int64_t* rowptr, const int32_t* col, const float* val, int64_t N,
+                                   int64_t D, int64_t nnz, const float* C, int K, const int32_t* assign,
+                                   double f_bar, float* C_bar, const float* C_dot, float* hvp, int accumulate,
+                                   void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -517,3 +517,30 @@ def scan_generic_batched_vjp(op, xs, y_bar, x_bar=None, accumulate=False, ckpt=N
               _ptr(ckpt), capi.ptr_array([_ptr(y) for y in y_bar]), capi.ptr_array([_ptr(x) for x in x_bar]),
               int(accumulate), _ptr(ws), ws.numel(), _stream(dev))
     return x_bar
+
+
+def sparse_kmeans_objective(rowptr, col, val, D, C):
+    """(f [1] float64, assign [N] int32) for CSR points (rowptr int64, col
+    int32, val float32) and dense centres C [K, D] float32."""
+    N, K, nnz = rowptr.numel() - 1, C.shape[0], col.numel()
+    dev = C.device
+    f = torch.empty(1, dtype=torch.float64, device=dev)
+    a = torch.empty(N, dtype=torch.int32, device=dev)
+    nb = capi.lib().pvjp_sparse_kmeans_ws_bytes(N, D, K, nnz)
+    ws = WS.get("sparse_kmeans", nb, dev)
+    capi.call("pvjp_sparse_kmeans_objective", _ptr(rowptr), _ptr(col), _ptr(val), N, D, nnz, _ptr(C), K, _ptr(a),
+              _ptr(f), _ptr(ws), ws.numel(), _stream(dev))
+    return f, a
+
+
+def sparse_kmeans_vjp(rowptr, col, val, D, C, assign, f_bar=1.0, C_dot=None, out=None, accumulate=False):
+    """(C_bar, hvp or None) at the objective's assignments."""
+    N, K, nnz = rowptr.numel() - 1, C.shape[0], col.numel()
+    dev = C.device
+    mk = torch.zeros_like if accumulate else torch.empty_like
+    cb, hv = out if out is not None else (mk(C), mk(C) if C_dot is not None else None)
+    nb = capi.lib().pvjp_sparse_kmeans_ws_bytes(N, D, K, nnz)
+    ws = WS.get("sparse_kmeans", nb, dev)
+    capi.call("pvjp_sparse_kmeans_vjp", _ptr(rowptr), _ptr(col), _ptr(val), N, D, nnz, _ptr(C), K, _ptr(assign),
+              float(f_bar), _ptr(cb), _ptr(C_dot), _ptr(hv), int(accumulate), _ptr(ws), ws.numel(), _stream(dev))
+    return cb, hv
