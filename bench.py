@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 23, help="elements per instance for the CPU oracle")
     ap.add_argument("--skip", default="", help="comma list of extra workloads to skip: reduce_map,reduce_generic,scan_generic,jvp,kmeans,"
-                         "gather_map,scan_batched,scan,gmm,batch,serve")
+                         "gather_map,scan_batched,sparse_kmeans,scan,gmm,batch,serve")
     ap.add_argument("--only", default="",
                     help="run just this one extra workload (for profiling) and print its JSON instead of the "
                          "benchmark line")
@@ -222,7 +222,8 @@ def main():
     if args.only:
         fns = {"reduce_map": bench_reduce_map, "reduce_generic": bench_reduce_generic,
                "scan_generic": bench_scan_generic, "jvp": bench_jvp, "kmeans": bench_kmeans, "gather_map": bench_gather_map,
-               "scan_batched": bench_scan_batched, "scan": bench_scan,
+               "scan_batched": bench_scan_batched, "sparse_kmeans": bench_sparse_kmeans,
+               "scan": bench_scan,
                "gmm": bench_gmm, "batch": bench_batch, "serve": bench_serve}
         print(json.dumps({args.only: fns[args.only](args)}))
         return
@@ -384,7 +385,8 @@ def main():
     extra = {}
     for name, fn in (("reduce_map", bench_reduce_map), ("reduce_generic", bench_reduce_generic),
                      ("scan_generic", bench_scan_generic), ("jvp", bench_jvp), ("kmeans", bench_kmeans),
-                     ("gather_map", bench_gather_map), ("scan_batched", bench_scan_batched), ("scan", bench_scan), ("gmm", bench_gmm),
+                     ("gather_map", bench_gather_map), ("scan_batched", bench_scan_batched),
+                     ("sparse_kmeans", bench_sparse_kmeans), ("scan", bench_scan), ("gmm", bench_gmm),
                      ("batch", bench_batch), ("serve", bench_serve)):
         if name in args.skip:
             continue
@@ -731,6 +733,30 @@ def bench_scan_batched(args):
         del xs, xb, yb, ck
         torch.cuda.empty_cache()
     return res
+
+
+def bench_sparse_kmeans(args):
+    """Sparse k-means (k = 10) on bag-of-words-like CSR points shaped like the
+    paper's largest text workload's vocabulary: 100000 rows x 102660
+    columns, about 230 distinct entries per row (Zipf(1.1) columns).  The
+    objective, the gradient, and the gradient with the Hessian diagonal."""
+    import torch
+
+    from paper_2202_10297_amd import ops, workloads
+
+    N, D, K = 100000, 102660, 10
+    rp, cl, v, C = workloads.sparse_kmeans(N, D, K, 330.0, "f32", seed=0)
+    drp, dcl, dv, dC = (torch.from_numpy(a).cuda() for a in (rp, cl, v, C))
+    _, a = ops.sparse_kmeans_objective(drp, dcl, dv, D, dC)
+    ones = torch.ones_like(dC)
+    out = (torch.empty_like(dC), torch.empty_like(dC))
+    tf = _events_ms(lambda: ops.sparse_kmeans_objective(drp, dcl, dv, D, dC), 10)
+    tg = _events_ms(lambda: ops.sparse_kmeans_vjp(drp, dcl, dv, D, dC, a, out=(out[0], None)), 10)
+    th = _events_ms(lambda: ops.sparse_kmeans_vjp(drp, dcl, dv, D, dC, a, C_dot=ones, out=out), 10)
+    nnz = int(rp[-1])
+    return {"rows": N, "cols": D, "k": K, "nnz": nnz, "objective_ms": round(tf, 4), "gradient_ms": round(tg, 4),
+            "gradient_and_hessian_diag_ms": round(th, 4), "newton_step_ms": round(tf + th, 4),
+            "objective_nnz_per_s": round(nnz / (tf * 1e-3), 1)}
 
 
 def bench_jvp(args):

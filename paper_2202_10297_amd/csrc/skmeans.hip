@@ -61,25 +61,33 @@ __global__ __launch_bounds__(64) void skm_cnorm_kernel(const double* __restrict_
     cn[k] = tot;
 }
 
-// One wave per row (rows strided over the grid's waves), lane k < K: the
-// chain of centre k over the row's stored entries; then the nearest centre
-// by a butterfly over the lanes that keeps the lower k on ties.  Entries
-// outside [0, nnz) or columns outside [0, D) are skipped (malformed input
-// does not leave the arrays).
+// Rows are packed R = 64 / Kp to a wave (Kp: K rounded up to a power of two),
+// lane group g of Kp lanes takes its own row, lane k < K of the group the
+// chain of centre k over the row's stored entries (groups advance together,
+// so R rows' gathers are in flight); then the nearest centre by a butterfly
+// inside the group (offsets below Kp) that keeps the lower k on ties.
+// Entries outside [0, nnz) or columns outside [0, D) are skipped (malformed
+// input does not leave the arrays).
 __global__ __launch_bounds__(256) void skm_dist_kernel(const int64_t* __restrict__ rowptr,
                                                        const int32_t* __restrict__ col, const float* __restrict__ val,
-                                                       int64_t N, int64_t D, int64_t nnz, int K,
+                                                       int64_t N, int64_t D, int64_t nnz, int K, int Kp,
                                                        const double* __restrict__ Cw, const double* __restrict__ cn,
                                                        int32_t* __restrict__ assign, double* __restrict__ dmin) {
     const int lane = threadIdx.x & (kWave - 1);
+    const int R = kWave / Kp;
+    const int grp = lane / Kp, k = lane - grp * Kp;
     const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
-    const bool on = lane < K;
-    const double base = on ? cn[lane] : 0.0;
-    for (int64_t i = w0; i < N; i += nw) {
-        int64_t e0 = rowptr[i], e1 = rowptr[i + 1];
-        e0 = e0 < 0 ? 0 : (e0 > nnz ? nnz : e0);
-        e1 = e1 < e0 ? e0 : (e1 > nnz ? nnz : e1);
+    const bool on = k < K;
+    const double base = on ? cn[k] : 0.0;
+    for (int64_t r0 = w0 * R; r0 < N; r0 += nw * R) {
+        const int64_t i = r0 + grp;
+        int64_t e0 = 0, e1 = 0;
+        if (i < N) {
+            e0 = rowptr[i], e1 = rowptr[i + 1];
+            e0 = e0 < 0 ? 0 : (e0 > nnz ? nnz : e0);
+            e1 = e1 < e0 ? e0 : (e1 > nnz ? nnz : e1);
+        }
         double acc = base;
         int64_t e = e0;
         for (; e + kSkU <= e1; e += kSkU) {
@@ -90,7 +98,7 @@ __global__ __launch_bounds__(256) void skm_dist_kernel(const int64_t* __restrict
 #pragma unroll
             for (int u = 0; u < kSkU; ++u) {
                 const bool ok = on && j[u] >= 0 && j[u] < D;
-                c[u] = ok ? Cw[(int64_t)j[u] * K + lane] : 0.0;
+                c[u] = ok ? Cw[(int64_t)j[u] * K + k] : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < kSkU; ++u)
@@ -100,19 +108,18 @@ __global__ __launch_bounds__(256) void skm_dist_kernel(const int64_t* __restrict
             const int32_t j = col[e];
             if (j >= 0 && j < D) {
                 const double x = (double)val[e];
-                const double c = on ? Cw[(int64_t)j * K + lane] : 0.0;
+                const double c = on ? Cw[(int64_t)j * K + k] : 0.0;
                 acc = fma(x, x - 2.0 * c, acc);
             }
         }
         double bd = on ? acc : (double)INFINITY;
-        int bk = on ? lane : kWave;
-#pragma unroll
-        for (int off = kWave / 2; off >= 1; off >>= 1) {
+        int bk = on ? k : kWave;
+        for (int off = Kp / 2; off >= 1; off >>= 1) {
             const double od = __shfl_xor(bd, off, kWave);
-            const int ok = __shfl_xor(bk, off, kWave);
-            if (od < bd || (od == bd && ok < bk)) bd = od, bk = ok;
+            const int okk = __shfl_xor(bk, off, kWave);
+            if (od < bd || (od == bd && okk < bk)) bd = od, bk = okk;
         }
-        if (lane == 0) {
+        if (k == 0 && i < N) {
             assign[i] = bk;
             dmin[i] = bd;
         }
@@ -290,9 +297,12 @@ extern "C" pvjp_status pvjp_sparse_kmeans_objective(const int64_t* rowptr, const
                            C, K, D, p.nblk, (double*)(w + p.cpart));
         hipLaunchKernelGGL(skm_cnorm_kernel, dim3(1), dim3(64), 0, st, (const double*)(w + p.cpart), K, p.nblk,
                            (double*)(w + p.cn));
-        const int64_t waves = N < 65536 ? N : 65536;
+        int Kp = 1;
+        while (Kp < K) Kp <<= 1;
+        const int64_t rw = ceil_div(N, (int64_t)(kWave / Kp));  // waves that cover every row once
+        const int64_t waves = rw < 65536 ? rw : 65536;
         hipLaunchKernelGGL(skm_dist_kernel, dim3((unsigned)ceil_div(waves, 4)), dim3(256), 0, st, rowptr, col, val, N,
-                           D, nnz, K, (const double*)(w + p.cw), (const double*)(w + p.cn), assign,
+                           D, nnz, K, Kp, (const double*)(w + p.cw), (const double*)(w + p.cn), assign,
                            (double*)(w + p.dmin));
         hipLaunchKernelGGL(skm_part_kernel, dim3((unsigned)p.G), dim3(256), 0, st, (const double*)(w + p.dmin), N,
                            (double*)(w + p.part));

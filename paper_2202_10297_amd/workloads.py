@@ -94,30 +94,19 @@ def gather_map(m: int, n: int, dist: str = "uniform", dtype="f32", seed: int = 0
 
 def sparse_kmeans(N: int, D: int, K: int, nnz_mean: float = 50.0, dtype="f32", seed: int = 0):
     """(rowptr [N+1] int64, col [nnz] int32, val [nnz], C [K, D]) for sparse
-    k-means: bag-of-words-like rows, lengths log-normal around nnz_mean
-    (capped at D), columns Zipf(1.1) over D without repeats in a row (sorted),
-    counts 1..4 as values; initial centres = K distinct rows, densified."""
+    k-means: bag-of-words-like rows whose lengths are drawn log-normal around
+    nnz_mean (capped at D), columns Zipf(1.1) over D with repeats in a row
+    dropped (so a row keeps its distinct draws, sorted), counts 1..4 as
+    values; initial centres = K distinct rows, densified."""
     g = rng(seed)
     dt = _dt(dtype)
     lens = np.minimum(np.maximum(np.round(g.lognormal(np.log(nnz_mean), 0.6, N)), 0), D).astype(np.int64)
-    rows, cols = [], []
-    draw = zipf_indices(int(lens.sum() * 2 + 16), D, 1.1, g)
-    at = 0
-    for i in range(N):
-        need = int(lens[i])
-        got = np.empty(0, dtype=np.int64)
-        while got.size < need:
-            take = draw[at:at + 2 * need + 8].astype(np.int64)
-            at += take.size
-            if at >= draw.size:
-                draw, at = zipf_indices(draw.size, D, 1.1, g), 0
-            got = np.unique(np.concatenate([got, take]))
-            if got.size > need:
-                got = np.sort(g.choice(got, size=need, replace=False))
-        cols.append(got)
+    rows = np.repeat(np.arange(N, dtype=np.int64), lens)
+    cols = zipf_indices(int(lens.sum()), D, 1.1, g).astype(np.int64)
+    keys = np.unique(rows * D + cols)
     rowptr = np.zeros(N + 1, dtype=np.int64)
-    rowptr[1:] = np.cumsum([c.size for c in cols])
-    col = (np.concatenate(cols) if cols else np.zeros(0)).astype(np.int32)
+    rowptr[1:] = np.cumsum(np.bincount(keys // D, minlength=N))
+    col = (keys % D).astype(np.int32)
     val = g.integers(1, 5, col.size).astype(dt)
     pick = g.choice(N, size=min(K, N), replace=False) if N else np.zeros(0, dtype=np.int64)
     C = np.zeros((K, D), dtype=dt)
