@@ -255,6 +255,25 @@ class KMeansObjective(torch.autograd.Function):
         return None, cb
 
 
+class SparseKMeansObjective(torch.autograd.Function):
+    """f(C) = sum_i min_k |x_i - c_k|^2 (Sec. 7.5) for fixed CSR points.
+    Saved: the assignments (the search is not repeated in the backward)."""
+
+    @staticmethod
+    def forward(ctx, rowptr, col, val, D, C):
+        C = C.contiguous()
+        f, assign = ops.sparse_kmeans_objective(rowptr, col, val, D, C)
+        ctx.D = D
+        ctx.save_for_backward(rowptr, col, val, C, assign)
+        return f[0]
+
+    @staticmethod
+    def backward(ctx, gf):
+        rowptr, col, val, C, assign = ctx.saved_tensors
+        cb, _ = ops.sparse_kmeans_vjp(rowptr, col, val, ctx.D, C, assign, f_bar=float(gf))
+        return None, None, None, None, cb
+
+
 def linrec_scan(a, b):
     return LinRecScan.apply(a, b)
 
@@ -297,3 +316,7 @@ def gather_map(as_, is_, vs=None, op="mul"):
 
 def kmeans_objective(X, C):
     return KMeansObjective.apply(X, C)
+
+
+def sparse_kmeans_objective(rowptr, col, val, D, C):
+    return SparseKMeansObjective.apply(rowptr, col, val, D, C)

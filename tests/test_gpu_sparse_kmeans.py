@@ -74,3 +74,15 @@ def test_refusals(ops):
     v = dev(np.array([1.0], dtype=np.float32))
     with pytest.raises(capi.PvjpError):
         ops.sparse_kmeans_objective(rp, cl, v, 4, dev(np.zeros((65, 4), dtype=np.float32)))  # K > 64
+
+
+def test_autograd(orc):
+    from paper_2202_10297_amd import autograd
+
+    D = 2000
+    rp, cl, v, C = workloads.sparse_kmeans(1500, D, 6, 40, "f32", seed=21)
+    C = (C + 0.05).astype(np.float32)
+    c = dev(C).requires_grad_()
+    f = autograd.sparse_kmeans_objective(dev(rp), dev(cl), dev(v), D, c)
+    (2.0 * f).backward()
+    assert rel_l2(host(c.grad), orc.sparse_kmeans_vjp(rp, cl, v, D, C, 2.0)) <= TOL_F32
