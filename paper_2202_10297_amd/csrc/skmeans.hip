@@ -23,15 +23,16 @@ constexpr int kSkNormBlock = 1024;   // dimensions per |c|^2 chain
 constexpr int kSkSumBlocks = 1024;   // fixed partition of the objective's sum
 constexpr int kSkU = 4;              // stored entries whose loads are in flight together
 
-// Cw[d K + k] = c_k[d] in FP64: a row's entry j reads centre values j K ..
-// j K + K - 1, contiguous across the lanes.
+// Cw[d K + k] = c_k[d] (FP32; widened exactly to FP64 where used): a row's
+// entry j reads centre values j K .. j K + K - 1, contiguous across the lanes,
+// and the table is half the size of an FP64 one, so more of it stays in L2.
 __global__ __launch_bounds__(256) void skm_widen_kernel(const float* __restrict__ C, int K, int64_t D,
-                                                        double* __restrict__ Cw) {
+                                                        float* __restrict__ Cw) {
     const int64_t n = (int64_t)K * D;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t d = e / K;
         const int k = (int)(e - d * K);
-        Cw[e] = (double)C[(int64_t)k * D + d];
+        Cw[e] = C[(int64_t)k * D + d];
     }
 }
 
@@ -45,7 +46,15 @@ __global__ __launch_bounds__(256) void skm_cnorm_part_kernel(const float* __rest
     const int64_t d1 = (d0 + kSkNormBlock < D) ? d0 + kSkNormBlock : D;
     const float* c = C + (int64_t)k * D;
     double s = 0.0;
-    for (int64_t d = d0; d < d1; ++d) {
+    int64_t d = d0;
+    for (; d + 32 <= d1; d += 32) {  // 32 loads in flight ahead of the chain
+        float v[32];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) v[u] = c[d + u];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) s = fma((double)v[u], (double)v[u], s);
+    }
+    for (; d < d1; ++d) {
         const double v = (double)c[d];
         s = fma(v, v, s);
     }
@@ -71,7 +80,7 @@ __global__ __launch_bounds__(64) void skm_cnorm_kernel(const double* __restrict_
 __global__ __launch_bounds__(256) void skm_dist_kernel(const int64_t* __restrict__ rowptr,
                                                        const int32_t* __restrict__ col, const float* __restrict__ val,
                                                        int64_t N, int64_t D, int64_t nnz, int K, int Kp,
-                                                       const double* __restrict__ Cw, const double* __restrict__ cn,
+                                                       const float* __restrict__ Cw, const double* __restrict__ cn,
                                                        int32_t* __restrict__ assign, double* __restrict__ dmin) {
     const int lane = threadIdx.x & (kWave - 1);
     const int R = kWave / Kp;
@@ -98,7 +107,7 @@ __global__ __launch_bounds__(256) void skm_dist_kernel(const int64_t* __restrict
 #pragma unroll
             for (int u = 0; u < kSkU; ++u) {
                 const bool ok = on && j[u] >= 0 && j[u] < D;
-                c[u] = ok ? Cw[(int64_t)j[u] * K + k] : 0.0;
+                c[u] = ok ? (double)Cw[(int64_t)j[u] * K + k] : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < kSkU; ++u)
@@ -108,7 +117,7 @@ __global__ __launch_bounds__(256) void skm_dist_kernel(const int64_t* __restrict
             const int32_t j = col[e];
             if (j >= 0 && j < D) {
                 const double x = (double)val[e];
-                const double c = on ? Cw[(int64_t)j * K + k] : 0.0;
+                const double c = on ? (double)Cw[(int64_t)j * K + k] : 0.0;
                 acc = fma(x, x - 2.0 * c, acc);
             }
         }
@@ -235,7 +244,7 @@ static SkPlan skm_plan(int64_t N, int64_t D, int K, int64_t nnz) {
         o += align_up(b > 0 ? b : 1, 256);
         return at;
     };
-    p.cw = take((size_t)K * D * 8);
+    p.cw = take((size_t)K * D * 4);
     p.cpart = take((size_t)K * p.nblk * 8);
     p.cn = take((size_t)K * 8);
     p.dmin = take((size_t)(N > 0 ? N : 1) * 8);
@@ -292,7 +301,7 @@ extern "C" pvjp_status pvjp_sparse_kmeans_objective(const int64_t* rowptr, const
     if (N > 0) {
         const int64_t KD = (int64_t)K * D;
         hipLaunchKernelGGL(skm_widen_kernel, dim3(flat_grid(KD, 256, 4)), dim3(256), 0, st, C, K, D,
-                           (double*)(w + p.cw));
+                           (float*)(w + p.cw));
         hipLaunchKernelGGL(skm_cnorm_part_kernel, dim3((unsigned)ceil_div((int64_t)K * p.nblk, 256)), dim3(256), 0, st,
                            C, K, D, p.nblk, (double*)(w + p.cpart));
         hipLaunchKernelGGL(skm_cnorm_kernel, dim3(1), dim3(64), 0, st, (const double*)(w + p.cpart), K, p.nblk,
@@ -302,7 +311,7 @@ extern "C" pvjp_status pvjp_sparse_kmeans_objective(const int64_t* rowptr, const
         const int64_t rw = ceil_div(N, (int64_t)(kWave / Kp));  // waves that cover every row once
         const int64_t waves = rw < 65536 ? rw : 65536;
         hipLaunchKernelGGL(skm_dist_kernel, dim3((unsigned)ceil_div(waves, 4)), dim3(256), 0, st, rowptr, col, val, N,
-                           D, nnz, K, Kp, (const double*)(w + p.cw), (const double*)(w + p.cn), assign,
+                           D, nnz, K, Kp, (const float*)(w + p.cw), (const double*)(w + p.cn), assign,
                            (double*)(w + p.dmin));
         hipLaunchKernelGGL(skm_part_kernel, dim3((unsigned)p.G), dim3(256), 0, st, (const double*)(w + p.dmin), N,
                            (double*)(w + p.part));
