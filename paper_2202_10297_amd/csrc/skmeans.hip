@@ -21,7 +21,7 @@ namespace pvjp {
 constexpr int kSkMaxK = 64;          // one lane per centre
 constexpr int kSkNormBlock = 1024;   // dimensions per |c|^2 chain
 constexpr int kSkSumBlocks = 1024;   // fixed partition of the objective's sum
-constexpr int kSkU = 4;              // stored entries whose loads are in flight together
+constexpr int kSkU = 8;              // stored entries whose loads are in flight together
 
 // Cw[d K + k] = c_k[d] (FP32; widened exactly to FP64 where used): a row's
 // entry j reads centre values j K .. j K + K - 1, contiguous across the lanes,
