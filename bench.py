@@ -206,8 +206,8 @@ def main():
         ingest_pmc(*args.ingest_pmc)
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              "(multi-GPU sharding is design-only)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (sharding across GPUs is "
+              "designed, not implemented)", file=sys.stderr)
         sys.exit(2)
     import torch
 
