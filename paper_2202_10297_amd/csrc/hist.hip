@@ -353,6 +353,20 @@ __global__ __launch_bounds__(256) void hist_vjp_add_kernel(const int32_t* __rest
     }
 }
 
+// Streaming accesses of the adjoint gathers (the indices read once, vs_bar
+// written once) go non-temporal, so they do not push the gathered hs_bar
+// lines out of L2.
+typedef int pvjp_v4i __attribute__((ext_vector_type(4)));
+typedef float pvjp_v4f __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ int4 nt_load_i4(const int4* p) {
+    const pvjp_v4i v = __builtin_nontemporal_load(reinterpret_cast<const pvjp_v4i*>(p));
+    return make_int4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void nt_store_f4(float4* p, float4 o) {
+    const pvjp_v4f v = {o.x, o.y, o.z, o.w};
+    __builtin_nontemporal_store(v, reinterpret_cast<pvjp_v4f*>(p));
+}
+
 // 16-byte vector form of the gather: four indices per load, four adjoints
 // per store (pointers 16-byte aligned; the last n % 4 elements are done by
 // the first threads of block 0).
@@ -362,7 +376,7 @@ __global__ __launch_bounds__(256) void hist_vjp_add_vec_kernel(const int32_t* __
                                                                T* __restrict__ vsbar) {
     const int64_t nq = n >> 2;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += (int64_t)gridDim.x * blockDim.x) {
-        const int4 k = reinterpret_cast<const int4*>(inds)[q];
+        const int4 k = nt_load_i4(reinterpret_cast<const int4*>(inds) + q);
         T g[4];
         g[0] = ((uint32_t)k.x < (uint32_t)m) ? hsbar[k.x] : T(0);
         g[1] = ((uint32_t)k.y < (uint32_t)m) ? hsbar[k.y] : T(0);
@@ -374,8 +388,10 @@ __global__ __launch_bounds__(256) void hist_vjp_add_vec_kernel(const int32_t* __
             if (ACC) {
                 const float4 c = *dst;
                 o.x += c.x, o.y += c.y, o.z += c.z, o.w += c.w;
+                *dst = o;
+            } else {
+                nt_store_f4(dst, o);
             }
-            *dst = o;
         } else {
             double2* dst = reinterpret_cast<double2*>(vsbar) + 2 * q;
             double2 o0 = make_double2((double)g[0], (double)g[1]), o1 = make_double2((double)g[2], (double)g[3]);
@@ -429,7 +445,7 @@ __global__ __launch_bounds__(kGatherBlock) void hist_vjp_add_lds_kernel(const in
 #pragma unroll
         for (int u = 0; u < kGatherU; ++u) {
             const int64_t q = q0 + u * step;
-            k[u] = q < nq ? reinterpret_cast<const int4*>(inds)[q] : make_int4(-1, -1, -1, -1);
+            k[u] = q < nq ? nt_load_i4(reinterpret_cast<const int4*>(inds) + q) : make_int4(-1, -1, -1, -1);
         }
 #pragma unroll
         for (int u = 0; u < kGatherU; ++u) {
@@ -446,8 +462,10 @@ __global__ __launch_bounds__(kGatherBlock) void hist_vjp_add_lds_kernel(const in
                 if (ACC) {
                     const float4 c = *dst;
                     o.x += c.x, o.y += c.y, o.z += c.z, o.w += c.w;
+                    *dst = o;
+                } else {
+                    nt_store_f4(dst, o);
                 }
-                *dst = o;
             } else {
                 double2* dst = reinterpret_cast<double2*>(vsbar) + 2 * q;
                 double2 o0 = make_double2((double)g[0], (double)g[1]), o1 = make_double2((double)g[2], (double)g[3]);
