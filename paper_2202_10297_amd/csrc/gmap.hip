@@ -43,6 +43,17 @@ __device__ inline void gm_partials(double a, double v, double yb, double& pa, do
 
 constexpr int kGmU = 4;  // elements per thread per step, their loads in flight together
 
+// The per-element arrays are streamed once: their loads and stores go
+// non-temporal, so they do not push the gathered lines of as out of L2.
+template <class T>
+__device__ __forceinline__ T nt_ld(const T* p) {
+    return __builtin_nontemporal_load(p);
+}
+template <class T>
+__device__ __forceinline__ void nt_st(T* p, T v) {
+    __builtin_nontemporal_store(v, p);
+}
+
 // Each step of a thread takes elements base + u 256 + t, u < kGmU (coalesced
 // for every u): all index and value loads, then all gathers, then the stores.
 template <int OP, class T>
@@ -56,15 +67,15 @@ __global__ __launch_bounds__(256) void gm_fwd_kernel(const T* __restrict__ as, i
 #pragma unroll
         for (int u = 0; u < kGmU; ++u) {
             const int64_t i = base + (int64_t)u * blockDim.x;
-            k[u] = i < m ? is[i] : -1;
-            v[u] = (OP && i < m) ? vs[i] : T(0);
+            k[u] = i < m ? nt_ld(is + i) : -1;
+            v[u] = (OP && i < m) ? nt_ld(vs + i) : T(0);
         }
 #pragma unroll
         for (int u = 0; u < kGmU; ++u) a[u] = (k[u] >= 0 && k[u] < n) ? as[k[u]] : T(0);
 #pragma unroll
         for (int u = 0; u < kGmU; ++u) {
             const int64_t i = base + (int64_t)u * blockDim.x;
-            if (i < m) ys[i] = gm_f<OP, T>(a[u], v[u]);
+            if (i < m) nt_st(ys + i, gm_f<OP, T>(a[u], v[u]));
         }
     }
 }
@@ -147,9 +158,9 @@ __global__ __launch_bounds__(256) void gm_contrib_kernel(const T* __restrict__ a
         for (int u = 0; u < kGmU; ++u) {
             const int64_t i = base + (int64_t)u * blockDim.x;
             const bool in = i < m;
-            k[u] = in ? is[i] : -1;
-            v[u] = (OP && in) ? vs[i] : T(0);
-            y[u] = in ? yb[i] : T(0);
+            k[u] = in ? nt_ld(is + i) : -1;
+            v[u] = (OP && in) ? nt_ld(vs + i) : T(0);
+            y[u] = in ? nt_ld(yb + i) : T(0);
         }
 #pragma unroll
         for (int u = 0; u < kGmU; ++u) a[u] = (OP && k[u] >= 0 && k[u] < n) ? as[k[u]] : T(0);
@@ -159,8 +170,11 @@ __global__ __launch_bounds__(256) void gm_contrib_kernel(const T* __restrict__ a
             if (i < m) {
                 double pa, pv;
                 gm_partials<OP>((double)a[u], (double)v[u], (double)y[u], pa, pv);
-                if (OP) vbar[i] = accumulate ? vbar[i] + (T)pv : (T)pv;
-                c[i] = (k[u] >= 0 && k[u] < n) ? (T)pa : T(0);
+                if (OP) {
+                    if (accumulate) vbar[i] = vbar[i] + (T)pv;
+                    else nt_st(vbar + i, (T)pv);
+                }
+                nt_st(c + i, (k[u] >= 0 && k[u] < n) ? (T)pa : T(0));
             }
         }
     }
