@@ -67,6 +67,8 @@ _SIGS = {
     "orc_kmeans_hvp": [_L, _I, _I, _P, _P, _D, _P, _P],
     "orc_gather_map": [_I, _L, _P, _L, _P, _P, _P],
     "orc_skm_objective": [_L, _L, _I, _P, _P, _P, _P, _P, _P],
+    "orc_hist_generic": [_I, _L, _L, _P, _P, _P],
+    "orc_hist_generic_vjp": [_I, _L, _L, _P, _P, _P, _P],
     "orc_skm_vjp": [_L, _L, _I, _P, _P, _P, _P, _D, _P],
     "orc_skm_hvp": [_L, _L, _I, _P, _P, _P, _P, _D, _P, _P],
     "orc_gather_map_vjp": [_I, _L, _P, _L, _P, _P, _P, _P, _P],
@@ -487,4 +489,28 @@ def sparse_kmeans_hvp(rowptr, col, val, D, C, C_dot, f_bar=1.0):
     out = np.empty_like(C)
     _check(lib().orc_skm_hvp(rp.size - 1, D, C.shape[0], _p(rp), _p(cl), _p(v), _p(C), float(f_bar), _p(Cd),
                              _p(out)), "sparse_kmeans_hvp")
+    return out
+
+
+# ------------------------------------------- reduce_by_index, general operator
+def hist_generic(op, inds, xs, m):
+    """hs: K arrays [m], the index-order fold of each bin (Sec. 5.1.2)."""
+    xs, ptrs, n, K = _components(op, xs)
+    inds = _i32(inds)
+    hs = [np.empty(m) for _ in range(K)]
+    hp = (ctypes.c_void_p * K)(*[h.ctypes.data for h in hs])
+    _check(lib().orc_hist_generic(_gop(op), n, m, _p(inds), ptrs, hp), "hist_generic")
+    return hs
+
+
+def hist_generic_vjp(op, inds, xs, hs_bar):
+    """x_bar: K arrays [n], the general rule applied within each bin."""
+    xs, ptrs, n, K = _components(op, xs)
+    inds = _i32(inds)
+    hb = [_f64(h) for h in hs_bar]
+    m = hb[0].size
+    hbp = (ctypes.c_void_p * K)(*[h.ctypes.data for h in hb])
+    out = [np.empty(n) for _ in range(K)]
+    op_ = (ctypes.c_void_p * K)(*[o.ctypes.data for o in out])
+    _check(lib().orc_hist_generic_vjp(_gop(op), n, m, _p(inds), ptrs, hbp, op_), "hist_generic_vjp")
     return out

@@ -1534,3 +1534,84 @@ int orc_skm_hvp(int64_t N, int64_t D, int K, const int64_t* rowptr, const int32_
     if (!C_dot) return -1;
     return skm_grad(N, D, K, rowptr, col, val, C, f_bar, C_dot, out);
 }
+
+/* ------------------------------------------------------------------------ */
+/* reduce_by_index with a general operator (Sec. 5.1.2, with the general     */
+/* rule of Sec. 5.1.1 inside each bin): hs[b] = the fold, in index order, of */
+/* the elements i with inds[i] = b (the neutral element for an empty bin;    */
+/* indices outside [0, m) are skipped).  Each bin's elements are gathered in */
+/* index order and handed to the generic reduce and its VJP; elements out of */
+/* range get adjoint 0.  x, hs, hs_bar, x_bar: K component arrays.           */
+static int hg_order(int64_t n, int64_t m, const int32_t* inds, int64_t** off_out, int64_t** perm_out) {
+    int64_t* off = (int64_t*)calloc((size_t)(m + 1), sizeof(int64_t));
+    int64_t* perm = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    int64_t* cur = (int64_t*)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+    if (!off || !perm || !cur) {
+        free(off), free(perm), free(cur);
+        return -2;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        if (inds[i] >= 0 && inds[i] < m) ++off[inds[i] + 1];
+    for (int64_t b = 0; b < m; ++b) off[b + 1] += off[b];
+    for (int64_t b = 0; b < m; ++b) cur[b] = off[b];
+    for (int64_t i = 0; i < n; ++i)  /* in index order: stable */
+        if (inds[i] >= 0 && inds[i] < m) perm[cur[inds[i]]++] = i;
+    free(cur);
+    *off_out = off, *perm_out = perm;
+    return 0;
+}
+
+int orc_hist_generic(int op, int64_t n, int64_t m, const int32_t* inds, const double* const* x,
+                     double* const* hs) {
+    const int K = orc_gop_components(op);
+    if (K == 0 || n < 0 || m < 1 || (n > 0 && (!inds || !x)) || !hs) return -1;
+    int64_t *off, *perm;
+    if (hg_order(n, m, inds, &off, &perm)) return -2;
+    double* sub[4] = {0, 0, 0, 0};
+    int rc = 0;
+    for (int c = 0; c < K && !rc; ++c)
+        if (!(sub[c] = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double)))) rc = -2;
+    for (int64_t b = 0; b < m && !rc; ++b) {
+        const int64_t cnt = off[b + 1] - off[b];
+        for (int64_t r = 0; r < cnt; ++r)
+            for (int c = 0; c < K; ++c) sub[c][r] = x[c][perm[off[b] + r]];
+        double y[4];
+        rc = orc_reduce_generic(op, cnt, (const double* const*)sub, y);
+        for (int c = 0; c < K; ++c) hs[c][b] = y[c];
+    }
+    for (int c = 0; c < K; ++c) free(sub[c]);
+    free(off), free(perm);
+    return rc;
+}
+
+int orc_hist_generic_vjp(int op, int64_t n, int64_t m, const int32_t* inds, const double* const* x,
+                         const double* const* hs_bar, double* const* x_bar) {
+    const int K = orc_gop_components(op);
+    if (K == 0 || n < 0 || m < 1 || (n > 0 && (!inds || !x || !x_bar)) || !hs_bar) return -1;
+    int64_t *off, *perm;
+    if (hg_order(n, m, inds, &off, &perm)) return -2;
+    double* sub[4] = {0, 0, 0, 0};
+    double* gs[4] = {0, 0, 0, 0};
+    int rc = 0;
+    for (int c = 0; c < K && !rc; ++c) {
+        sub[c] = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+        gs[c] = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+        if (!sub[c] || !gs[c]) rc = -2;
+    }
+    for (int c = 0; c < K && !rc; ++c)
+        for (int64_t i = 0; i < n; ++i) x_bar[c][i] = 0.0;
+    for (int64_t b = 0; b < m && !rc; ++b) {
+        const int64_t cnt = off[b + 1] - off[b];
+        if (cnt == 0) continue;
+        for (int64_t r = 0; r < cnt; ++r)
+            for (int c = 0; c < K; ++c) sub[c][r] = x[c][perm[off[b] + r]];
+        double yb[4];
+        for (int c = 0; c < K; ++c) yb[c] = hs_bar[c][b];
+        rc = orc_reduce_generic_vjp(op, cnt, (const double* const*)sub, yb, gs);
+        for (int64_t r = 0; r < cnt && !rc; ++r)
+            for (int c = 0; c < K; ++c) x_bar[c][perm[off[b] + r]] = gs[c][r];
+    }
+    for (int c = 0; c < K; ++c) free(sub[c]), free(gs[c]);
+    free(off), free(perm);
+    return rc;
+}

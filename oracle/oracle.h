@@ -183,6 +183,15 @@ int orc_skm_vjp(int64_t N, int64_t D, int K, const int64_t* rowptr, const int32_
 int orc_skm_hvp(int64_t N, int64_t D, int K, const int64_t* rowptr, const int32_t* col, const double* val,
                 const double* C, double f_bar, const double* C_dot, double* out);
 
+/* reduce_by_index with a general operator (Sec. 5.1.2 with the general rule
+ * of Sec. 5.1.1 per bin): hs[c][b] = the index-order fold of the elements of
+ * bin b (the neutral element if none); inds outside [0, m) skipped (their
+ * adjoint 0).  K component arrays for x, hs, hs_bar, x_bar. */
+int orc_hist_generic(int op, int64_t n, int64_t m, const int32_t* inds, const double* const* x,
+                     double* const* hs);
+int orc_hist_generic_vjp(int op, int64_t n, int64_t m, const int32_t* inds, const double* const* x,
+                         const double* const* hs_bar, double* const* x_bar);
+
 #ifdef __cplusplus
 }
 #endif
