@@ -544,6 +544,25 @@ pvjp_status pvjp_sparse_kmeans_vjp(const int64_t* rowptr, const int32_t* col, co
                                    double f_bar, float* C_bar, const float* C_dot, float* hvp, int accumulate,
                                    void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* reduce_by_index with the log-add-exp operator (Sec. 5.1.2 with the general  */
+/* rule of Sec. 5.1.1 inside each bin)                                        */
+/* ------------------------------------------------------------------------ */
+
+/* hs[b] = log sum over i with inds[i] = b of e^(x[i]); -inf for an empty bin
+ * or one of -inf elements only; inds outside [0, m) skipped.  x, hs: dtype;
+ * inds [n] int32; 1 <= m <= 2^30.  Runs the reduce_by_index max and +
+ * paths (FP64 sums of the shifted exponentials).  ws: 256-byte aligned,
+ * ws_bytes >= pvjp_hist_lae_ws_bytes(dtype, n, m), else PVJP_ENOMEM. */
+size_t pvjp_hist_lae_ws_bytes(pvjp_dtype dtype, int64_t n, int64_t m);
+pvjp_status pvjp_hist_lae(pvjp_dtype dtype, const int32_t* inds, const void* x, int64_t n, int64_t m, void* hs,
+                          void* ws, size_t ws_bytes, void* stream);
+/* x_bar[i] (+)= hs_bar[b] e^(x[i] - hs[b]) for b = inds[i] (the operator
+ * commutes, so the general rule's ls (.) x (.) rs is the bin's total); 0 for
+ * a -inf element or an index out of range.  hs: the primal's output. */
+pvjp_status pvjp_hist_lae_vjp(pvjp_dtype dtype, const int32_t* inds, const void* x, int64_t n, int64_t m,
+                              const void* hs, const void* hs_bar, void* x_bar, int accumulate, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

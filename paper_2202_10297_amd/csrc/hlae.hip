@@ -1,0 +1,161 @@
+// reduce_by_index with the log-add-exp operator (Sec. 5.1.2, with the general
+// rule of Sec. 5.1.1 inside each bin): hs[b] = log sum over the elements of
+// bin b of e^(x_i).  The operator commutes, so ls_i (.) x_i (.) rs_i is the
+// bin's total whatever the order of the bin's elements, and the general rule
+// gives element i the adjoint hs_bar[b] e^(x_i - hs[b]): one pass, no sort.
+// The primal runs on this library's reduce_by_index paths: the bin maxima
+// (max), then the shifted exponentials summed per bin (+, FP64 sums), then
+// hs = max + log(sum).  An empty bin, or one of -inf elements only, gets -inf;
+// a -inf element gets adjoint 0; indices outside [0, m) are skipped.
+#include "common.h"
+
+namespace pvjp {
+
+__device__ __forceinline__ float hl_exp(float x) { return expf(x); }
+__device__ __forceinline__ double hl_exp(double x) { return exp(x); }
+__device__ __forceinline__ float hl_log(float x) { return logf(x); }
+__device__ __forceinline__ double hl_log(double x) { return log(x); }
+
+template <class T>
+__global__ __launch_bounds__(256) void hl_shift_kernel(const int32_t* __restrict__ inds, const T* __restrict__ x,
+                                                       int64_t n, int64_t m, const T* __restrict__ hmax,
+                                                       T* __restrict__ e) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = inds[i];
+        T v = T(0);
+        if (k >= 0 && k < m) {
+            const T mx = hmax[k], xi = x[i];
+            if (xi != -(T)INFINITY && mx != -(T)INFINITY) v = hl_exp(xi - mx);
+        }
+        e[i] = v;
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void hl_final_kernel(const T* __restrict__ hmax, const T* __restrict__ hsum,
+                                                       int64_t m, T* __restrict__ hs) {
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < m; b += (int64_t)gridDim.x * blockDim.x)
+        hs[b] = hsum[b] > T(0) ? hmax[b] + hl_log(hsum[b]) : -(T)INFINITY;
+}
+
+template <class T, bool ACC>
+__global__ __launch_bounds__(256) void hl_vjp_kernel(const int32_t* __restrict__ inds, const T* __restrict__ x,
+                                                     int64_t n, int64_t m, const T* __restrict__ hs,
+                                                     const T* __restrict__ hb, T* __restrict__ xb) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = inds[i];
+        T g = T(0);
+        if (k >= 0 && k < m) {
+            const T xi = x[i], h = hs[k];
+            if (xi != -(T)INFINITY && h != -(T)INFINITY) g = hb[k] * hl_exp(xi - h);
+        }
+        xb[i] = ACC ? xb[i] + g : g;
+    }
+}
+
+struct HlPlan {
+    size_t winner, hmax, e, hsum, hist, hist_bytes, total;
+};
+
+static HlPlan hl_plan(pvjp_dtype dtype, int64_t n, int64_t m) {
+    HlPlan p{};
+    const size_t es = dsize(dtype);
+    size_t o = 0;
+    auto take = [&](size_t b) {
+        const size_t at = o;
+        o += align_up(b > 0 ? b : 1, 256);
+        return at;
+    };
+    p.winner = take((size_t)m * 4);
+    p.hmax = take((size_t)m * es);
+    p.e = take((size_t)(n > 0 ? n : 1) * es);
+    p.hsum = take((size_t)m * es);
+    const size_t a = pvjp_hist_ws_bytes(PVJP_MAX, dtype, n, m), b = pvjp_hist_ws_bytes(PVJP_ADD, dtype, n, m);
+    p.hist_bytes = align_up(a > b ? a : b, 256);
+    p.hist = take(p.hist_bytes);
+    p.total = o;
+    return p;
+}
+
+template <class T>
+static pvjp_status hl_primal(pvjp_dtype dtype, const int32_t* inds, const T* x, int64_t n, int64_t m, T* hs,
+                             char* w, const HlPlan& p, hipStream_t st) {
+    T* hmax = (T*)(w + p.hmax);
+    T* e = (T*)(w + p.e);
+    T* hsum = (T*)(w + p.hsum);
+    if (pvjp_status s = pvjp_hist(PVJP_MAX, dtype, inds, x, n, m, hmax, (int32_t*)(w + p.winner), nullptr, nullptr,
+                                  nullptr, w + p.hist, p.hist_bytes, st))
+        return s;
+    if (n > 0)
+        hipLaunchKernelGGL(hl_shift_kernel<T>, dim3(flat_grid(n, 256, 4)), dim3(256), 0, st, inds, x, n, m,
+                           (const T*)hmax, e);
+    if (pvjp_status s = pvjp_hist(PVJP_ADD, dtype, inds, e, n, m, hsum, nullptr, nullptr, nullptr, nullptr,
+                                  w + p.hist, p.hist_bytes, st))
+        return s;
+    hipLaunchKernelGGL(hl_final_kernel<T>, dim3(flat_grid(m, 256, 4)), dim3(256), 0, st, (const T*)hmax,
+                       (const T*)hsum, m, hs);
+    return PVJP_OK;
+}
+
+}  // namespace pvjp
+
+using namespace pvjp;
+
+extern "C" size_t pvjp_hist_lae_ws_bytes(pvjp_dtype dtype, int64_t n, int64_t m) {
+    if (!valid_dtype(dtype) || n < 0 || m < 1) return 0;
+    return hl_plan(dtype, n, m).total;
+}
+
+extern "C" pvjp_status pvjp_hist_lae(pvjp_dtype dtype, const int32_t* inds, const void* x, int64_t n, int64_t m,
+                                     void* hs, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    PVJP_REQUIRE(valid_dtype(dtype), "pvjp_hist_lae: unknown dtype %d", (int)dtype);
+    PVJP_REQUIRE(n >= 0 && n < INT32_MAX && m >= 1 && m <= ((int64_t)1 << 30),
+                 "pvjp_hist_lae: n = %lld, m = %lld out of range", (long long)n, (long long)m);
+    PVJP_REQUIRE(hs != nullptr && (n == 0 || (inds != nullptr && x != nullptr)),
+                 "pvjp_hist_lae: hs, inds and x must be non-NULL");
+    PVJP_REQUIRE(ws != nullptr && aligned(ws, 256), "pvjp_hist_lae: ws must be non-NULL and 256-byte aligned");
+    const HlPlan p = hl_plan(dtype, n, m);
+    if (ws_bytes < p.total) {
+        set_error("pvjp_hist_lae: workspace has %zu bytes, needs %zu", ws_bytes, p.total);
+        return PVJP_ENOMEM;
+    }
+    char* w = reinterpret_cast<char*>(ws);
+    hipStream_t st = as_stream(stream);
+    const pvjp_status s = dtype == PVJP_F64
+                              ? hl_primal<double>(dtype, inds, (const double*)x, n, m, (double*)hs, w, p, st)
+                              : hl_primal<float>(dtype, inds, (const float*)x, n, m, (float*)hs, w, p, st);
+    if (s != PVJP_OK) return s;
+    PVJP_LAUNCHED("pvjp_hist_lae");
+    return PVJP_OK;
+}
+
+extern "C" pvjp_status pvjp_hist_lae_vjp(pvjp_dtype dtype, const int32_t* inds, const void* x, int64_t n, int64_t m,
+                                         const void* hs, const void* hs_bar, void* x_bar, int accumulate,
+                                         void* stream) {
+    clear_error();
+    PVJP_REQUIRE(valid_dtype(dtype), "pvjp_hist_lae_vjp: unknown dtype %d", (int)dtype);
+    PVJP_REQUIRE(n >= 0 && m >= 1, "pvjp_hist_lae_vjp: n = %lld, m = %lld out of range", (long long)n, (long long)m);
+    if (n == 0) return PVJP_OK;
+    PVJP_REQUIRE(inds != nullptr && x != nullptr && hs != nullptr && hs_bar != nullptr && x_bar != nullptr,
+                 "pvjp_hist_lae_vjp: inds, x, hs, hs_bar and x_bar must be non-NULL");
+    hipStream_t st = as_stream(stream);
+    const dim3 g(flat_grid(n, 256, 4)), b(256);
+    if (dtype == PVJP_F64) {
+        if (accumulate)
+            hipLaunchKernelGGL((hl_vjp_kernel<double, true>), g, b, 0, st, inds, (const double*)x, n, m,
+                               (const double*)hs, (const double*)hs_bar, (double*)x_bar);
+        else
+            hipLaunchKernelGGL((hl_vjp_kernel<double, false>), g, b, 0, st, inds, (const double*)x, n, m,
+                               (const double*)hs, (const double*)hs_bar, (double*)x_bar);
+    } else {
+        if (accumulate)
+            hipLaunchKernelGGL((hl_vjp_kernel<float, true>), g, b, 0, st, inds, (const float*)x, n, m,
+                               (const float*)hs, (const float*)hs_bar, (float*)x_bar);
+        else
+            hipLaunchKernelGGL((hl_vjp_kernel<float, false>), g, b, 0, st, inds, (const float*)x, n, m,
+                               (const float*)hs, (const float*)hs_bar, (float*)x_bar);
+    }
+    PVJP_LAUNCHED("pvjp_hist_lae_vjp");
+    return PVJP_OK;
+}

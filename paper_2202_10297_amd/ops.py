@@ -544,3 +544,25 @@ def sparse_kmeans_vjp(rowptr, col, val, D, C, assign, f_bar=1.0, C_dot=None, out
     capi.call("pvjp_sparse_kmeans_vjp", _ptr(rowptr), _ptr(col), _ptr(val), N, D, nnz, _ptr(C), K, _ptr(assign),
               float(f_bar), _ptr(cb), _ptr(C_dot), _ptr(hv), int(accumulate), _ptr(ws), ws.numel(), _stream(dev))
     return cb, hv
+
+
+def hist_lae(inds, x, m):
+    """hs [m]: log sum exp of each bin's elements (reduce_by_index with the
+    log-add-exp operator)."""
+    if inds.dtype != torch.int32:
+        raise TypeError("inds must be int32")
+    dt, dev, n = _dt(x), x.device, x.numel()
+    hs = torch.empty(m, dtype=x.dtype, device=dev)
+    nb = capi.lib().pvjp_hist_lae_ws_bytes(dt, n, m)
+    ws = WS.get("hist_lae", nb, dev)
+    capi.call("pvjp_hist_lae", dt, _ptr(inds), _ptr(x), n, m, _ptr(hs), _ptr(ws), ws.numel(), _stream(dev))
+    return hs
+
+
+def hist_lae_vjp(inds, x, hs, hs_bar, x_bar=None, accumulate=False):
+    """x_bar (+)= hs_bar[b] e^(x - hs[b]) per element of bin b."""
+    if x_bar is None:
+        x_bar = (torch.zeros_like if accumulate else torch.empty_like)(x)
+    capi.call("pvjp_hist_lae_vjp", _dt(x), _ptr(inds), _ptr(x), x.numel(), hs.numel(), _ptr(hs), _ptr(hs_bar),
+              _ptr(x_bar), int(accumulate), _stream(x.device))
+    return x_bar
