@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 23, help="elements per instance for the CPU oracle")
     ap.add_argument("--skip", default="", help="comma list of extra workloads to skip: reduce_map,reduce_generic,scan_generic,jvp,kmeans,"
-                         "gather_map,scan_batched,sparse_kmeans,scan,gmm,batch,serve")
+                         "gather_map,scan_batched,sparse_kmeans,hist_lae,scan,gmm,batch,serve")
     ap.add_argument("--only", default="",
                     help="run just this one extra workload (for profiling) and print its JSON instead of the "
                          "benchmark line")
@@ -222,7 +222,7 @@ def main():
     if args.only:
         fns = {"reduce_map": bench_reduce_map, "reduce_generic": bench_reduce_generic,
                "scan_generic": bench_scan_generic, "jvp": bench_jvp, "kmeans": bench_kmeans, "gather_map": bench_gather_map,
-               "scan_batched": bench_scan_batched, "sparse_kmeans": bench_sparse_kmeans,
+               "scan_batched": bench_scan_batched, "sparse_kmeans": bench_sparse_kmeans, "hist_lae": bench_hist_lae,
                "scan": bench_scan,
                "gmm": bench_gmm, "batch": bench_batch, "serve": bench_serve}
         print(json.dumps({args.only: fns[args.only](args)}))
@@ -386,7 +386,7 @@ def main():
     for name, fn in (("reduce_map", bench_reduce_map), ("reduce_generic", bench_reduce_generic),
                      ("scan_generic", bench_scan_generic), ("jvp", bench_jvp), ("kmeans", bench_kmeans),
                      ("gather_map", bench_gather_map), ("scan_batched", bench_scan_batched),
-                     ("sparse_kmeans", bench_sparse_kmeans), ("scan", bench_scan), ("gmm", bench_gmm),
+                     ("sparse_kmeans", bench_sparse_kmeans), ("hist_lae", bench_hist_lae), ("scan", bench_scan), ("gmm", bench_gmm),
                      ("batch", bench_batch), ("serve", bench_serve)):
         if name in args.skip:
             continue
@@ -757,6 +757,31 @@ def bench_sparse_kmeans(args):
     return {"rows": N, "cols": D, "k": K, "nnz": nnz, "objective_ms": round(tf, 4), "gradient_ms": round(tg, 4),
             "gradient_and_hessian_diag_ms": round(th, 4), "newton_step_ms": round(tf + th, 4),
             "objective_nnz_per_s": round(nnz / (tf * 1e-3), 1)}
+
+
+def bench_hist_lae(args):
+    """reduce_by_index with the log-add-exp operator at n = 2^26 FP32, m =
+    2^16 and 2^20 bins, Zipf(1.1) indices.  Algorithmic bytes: primal 8 per
+    element (indices, values) + 4 per bin; VJP 12 per element (indices,
+    values read, adjoints written) + 8 per bin (hs, hs_bar)."""
+    import torch
+
+    from paper_2202_10297_amd import ops, workloads
+
+    n = 1 << 26
+    res = {}
+    for m in (1 << 16, 1 << 20):
+        inds, x, hb = (torch.from_numpy(a).cuda() for a in workloads.hist(n, m, "zipf", "f32", seed=0))
+        hs = ops.hist_lae(inds, x, m)
+        xb = torch.empty_like(x)
+        tp = _events_ms(lambda: ops.hist_lae(inds, x, m), 10)
+        tv = _events_ms(lambda: ops.hist_lae_vjp(inds, x, hs, hb, x_bar=xb), 10)
+        res[f"m2^{m.bit_length() - 1}_zipf"] = {
+            "primal_ms": round(tp, 4), "vjp_ms": round(tv, 4), "grad_over_primal": round((tp + tv) / tp, 3),
+            "primal_hbm_frac": round((8 * n + 4 * m) / (tp * 1e-3) / 8e12, 3),
+            "vjp_hbm_frac": round((12 * n + 8 * m) / (tv * 1e-3) / 8e12, 3)}
+        del inds, x, hb, hs, xb
+    return res
 
 
 def bench_jvp(args):
