@@ -274,6 +274,23 @@ class SparseKMeansObjective(torch.autograd.Function):
         return None, None, None, None, cb
 
 
+class ReduceByIndexLogAddExp(torch.autograd.Function):
+    """hs[b] = log sum over bin b of e^(x_i) (reduce_by_index with the
+    log-add-exp operator).  Saved: x, the indices and hs."""
+
+    @staticmethod
+    def forward(ctx, x, inds, m):
+        x, inds = x.contiguous(), inds.contiguous()
+        hs = ops.hist_lae(inds, x, m)
+        ctx.save_for_backward(x, inds, hs)
+        return hs
+
+    @staticmethod
+    def backward(ctx, ghs):
+        x, inds, hs = ctx.saved_tensors
+        return ops.hist_lae_vjp(inds, x, hs, ghs.contiguous()), None, None
+
+
 def linrec_scan(a, b):
     return LinRecScan.apply(a, b)
 
@@ -320,3 +337,7 @@ def kmeans_objective(X, C):
 
 def sparse_kmeans_objective(rowptr, col, val, D, C):
     return SparseKMeansObjective.apply(rowptr, col, val, D, C)
+
+
+def reduce_by_index_logaddexp(x, inds, m):
+    return ReduceByIndexLogAddExp.apply(x, inds, m)

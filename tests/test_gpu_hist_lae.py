@@ -67,3 +67,13 @@ def test_hist_lae_accumulate_and_one_bin_is_the_generic_reduce(ops, orc):
     base = np.full(n, 0.5)
     xb = host(ops.hist_lae_vjp(dev(inds), dev(x), hs, dev(np.array([2.0])), x_bar=dev(base), accumulate=True))
     assert rel_l2(xb - 0.5, orc.reduce_generic_vjp("logaddexp", [x], [2.0])[0]) <= TOL_F64
+
+
+def test_autograd(orc):
+    from paper_2202_10297_amd import autograd
+
+    inds, x, hb = workloads.hist(20001, 300, "zipf", "f64", seed=31)
+    t = dev(x).requires_grad_()
+    hs = autograd.reduce_by_index_logaddexp(t, dev(inds), 300)
+    (hs * dev(hb)).sum().backward()
+    assert rel_l2(host(t.grad), orc.hist_generic_vjp("logaddexp", inds, [x], [hb])[0]) <= TOL_F64
