@@ -16,18 +16,35 @@ __device__ __forceinline__ double hl_exp(double x) { return exp(x); }
 __device__ __forceinline__ float hl_log(float x) { return logf(x); }
 __device__ __forceinline__ double hl_log(double x) { return log(x); }
 
+// Elements per thread per step (their loads and bin gathers in flight
+// together); the per-element streams go non-temporal so that they do not
+// push the gathered bin lines out of L2.
+constexpr int kHlU = 4;
+
 template <class T>
 __global__ __launch_bounds__(256) void hl_shift_kernel(const int32_t* __restrict__ inds, const T* __restrict__ x,
                                                        int64_t n, int64_t m, const T* __restrict__ hmax,
                                                        T* __restrict__ e) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t k = inds[i];
-        T v = T(0);
-        if (k >= 0 && k < m) {
-            const T mx = hmax[k], xi = x[i];
-            if (xi != -(T)INFINITY && mx != -(T)INFINITY) v = hl_exp(xi - mx);
+    const int64_t step = (int64_t)gridDim.x * blockDim.x * kHlU;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x * kHlU + threadIdx.x; base < n; base += step) {
+        int32_t k[kHlU];
+        T xi[kHlU], mx[kHlU];
+#pragma unroll
+        for (int u = 0; u < kHlU; ++u) {
+            const int64_t i = base + (int64_t)u * blockDim.x;
+            k[u] = i < n ? __builtin_nontemporal_load(inds + i) : -1;
+            xi[u] = i < n ? __builtin_nontemporal_load(x + i) : T(0);
         }
-        e[i] = v;
+#pragma unroll
+        for (int u = 0; u < kHlU; ++u) mx[u] = (k[u] >= 0 && k[u] < m) ? hmax[k[u]] : -(T)INFINITY;
+#pragma unroll
+        for (int u = 0; u < kHlU; ++u) {
+            const int64_t i = base + (int64_t)u * blockDim.x;
+            if (i < n) {
+                const bool live = xi[u] != -(T)INFINITY && mx[u] != -(T)INFINITY;
+                __builtin_nontemporal_store(live ? hl_exp(xi[u] - mx[u]) : T(0), e + i);
+            }
+        }
     }
 }
 
@@ -42,14 +59,32 @@ template <class T, bool ACC>
 __global__ __launch_bounds__(256) void hl_vjp_kernel(const int32_t* __restrict__ inds, const T* __restrict__ x,
                                                      int64_t n, int64_t m, const T* __restrict__ hs,
                                                      const T* __restrict__ hb, T* __restrict__ xb) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t k = inds[i];
-        T g = T(0);
-        if (k >= 0 && k < m) {
-            const T xi = x[i], h = hs[k];
-            if (xi != -(T)INFINITY && h != -(T)INFINITY) g = hb[k] * hl_exp(xi - h);
+    const int64_t step = (int64_t)gridDim.x * blockDim.x * kHlU;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x * kHlU + threadIdx.x; base < n; base += step) {
+        int32_t k[kHlU];
+        T xi[kHlU], h[kHlU], g[kHlU];
+#pragma unroll
+        for (int u = 0; u < kHlU; ++u) {
+            const int64_t i = base + (int64_t)u * blockDim.x;
+            k[u] = i < n ? __builtin_nontemporal_load(inds + i) : -1;
+            xi[u] = i < n ? __builtin_nontemporal_load(x + i) : T(0);
         }
-        xb[i] = ACC ? xb[i] + g : g;
+#pragma unroll
+        for (int u = 0; u < kHlU; ++u) {
+            const bool in = k[u] >= 0 && k[u] < m;
+            h[u] = in ? hs[k[u]] : -(T)INFINITY;
+            g[u] = in ? hb[k[u]] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kHlU; ++u) {
+            const int64_t i = base + (int64_t)u * blockDim.x;
+            if (i < n) {
+                const bool live = xi[u] != -(T)INFINITY && h[u] != -(T)INFINITY;
+                const T v = live ? g[u] * hl_exp(xi[u] - h[u]) : T(0);
+                if (ACC) xb[i] = xb[i] + v;
+                else __builtin_nontemporal_store(v, xb + i);
+            }
+        }
     }
 }
 
