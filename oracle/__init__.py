@@ -67,6 +67,7 @@ _SIGS = {
     "orc_kmeans_hvp": [_L, _I, _I, _P, _P, _D, _P, _P],
     "orc_gather_map": [_I, _L, _P, _L, _P, _P, _P],
     "orc_skm_objective": [_L, _L, _I, _P, _P, _P, _P, _P, _P],
+    "orc_skm_dist": [_L, _L, _I, _P, _P, _P, _P, _P],
     "orc_hist_generic": [_I, _L, _L, _P, _P, _P],
     "orc_hist_generic_vjp": [_I, _L, _L, _P, _P, _P, _P],
     "orc_skm_vjp": [_L, _L, _I, _P, _P, _P, _P, _D, _P],
@@ -474,6 +475,15 @@ def sparse_kmeans_objective(rowptr, col, val, D, C):
     _check(lib().orc_skm_objective(N, D, C.shape[0], _p(rp), _p(cl), _p(v), _p(C), _p(a), _p(f)),
            "sparse_kmeans_objective")
     return float(f[0]), a
+
+
+def sparse_kmeans_distances(rowptr, col, val, D, C):
+    """[N, K]: every row's squared distance to every centre."""
+    rp, cl, v, C = _i64(rowptr), _i32(col), _f64(val), _f64(C)
+    N = rp.size - 1
+    out = np.empty((N, C.shape[0]))
+    _check(lib().orc_skm_dist(N, D, C.shape[0], _p(rp), _p(cl), _p(v), _p(C), _p(out)), "sparse_kmeans_distances")
+    return out
 
 
 def sparse_kmeans_vjp(rowptr, col, val, D, C, f_bar=1.0):

@@ -1426,25 +1426,12 @@ int orc_gather_map_vjp(int op, int64_t n, const double* as, int64_t m, const int
 /* ------------------------------------------------------------------------ */
 /* Sparse k-means (Sec. 7.5): points in CSR (rowptr [N+1], col [nnz], val    */
 /* [nnz]), dense centres C [K x D].  The cost is the dense one with the      */
-/* squared distance.  The distance of row i to centre k is one FP64 chain:  */
-/* acc = |c_k|^2, then for every stored (j, x) of the row in CSR order       */
-/* acc = fma(x, x - 2 c_kj, acc) (|x - c|^2 = |c|^2 + sum over stored x of   */
-/* x (x - 2 c)).  |c_k|^2 is fixed too: blocks of 1024 dimensions, each an   */
-/* fma chain in d order, the block sums added in block order.  Ties go to    */
-/* the lowest k.  The gradient at fixed assignments is the plain closed form */
+/* squared distance, taken by its definition: row i is densified (zero       */
+/* where nothing is stored) and its distance to centre k is the plain sum    */
+/* over d = 0..D-1 of (x_d - c_kd)^2, in d order.  Ties go to the lowest k.  */
+/* The gradient at fixed assignments is the closed form                      */
 /* 2 f_bar (n_k c_k - S_k), S_k the sum of the rows assigned to k, and the   */
 /* jvp of the VJP is 2 f_bar n_k C_dot_k.                                    */
-static double skm_cnorm(int64_t D, const double* c) {
-    double tot = 0.0;
-    for (int64_t b0 = 0; b0 < D; b0 += 1024) {
-        const int64_t b1 = b0 + 1024 < D ? b0 + 1024 : D;
-        double s = 0.0;
-        for (int64_t d = b0; d < b1; ++d) s = fma(c[d], c[d], s);
-        tot += s;
-    }
-    return tot;
-}
-
 static int skm_check(int64_t N, int64_t D, int K, const int64_t* rowptr, const int32_t* col, const double* val,
                      const double* C) {
     if (N < 0 || D < 1 || K < 1 || !rowptr || !C) return -1;
@@ -1458,28 +1445,37 @@ static int skm_check(int64_t N, int64_t D, int K, const int64_t* rowptr, const i
     return 0;
 }
 
+/* dist [N x K] (nullable): every row's distance to every centre. */
 static int skm_assign(int64_t N, int64_t D, int K, const int64_t* rowptr, const int32_t* col, const double* val,
-                      const double* C, int32_t* a, double* dmin) {
-    double* cn = (double*)malloc((size_t)K * sizeof(double));
-    if (!cn) return -2;
-    for (int k = 0; k < K; ++k) cn[k] = skm_cnorm(D, C + (int64_t)k * D);
+                      const double* C, int32_t* a, double* dmin, double* dist) {
+    double* x = (double*)calloc((size_t)D, sizeof(double));
+    if (!x) return -2;
     for (int64_t i = 0; i < N; ++i) {
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) x[col[e]] = val[e];
         int best = 0;
         double bd = 0.0;
         for (int k = 0; k < K; ++k) {
             const double* c = C + (int64_t)k * D;
-            double acc = cn[k];
-            for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
-                const double x = val[e];
-                acc = fma(x, x - 2.0 * c[col[e]], acc);
+            double acc = 0.0;
+            for (int64_t d = 0; d < D; ++d) {
+                const double t = x[d] - c[d];
+                acc += t * t;
             }
+            if (dist) dist[i * K + k] = acc;
             if (k == 0 || acc < bd) bd = acc, best = k;
         }
-        a[i] = best;
+        if (a) a[i] = best;
         if (dmin) dmin[i] = bd;
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) x[col[e]] = 0.0;
     }
-    free(cn);
+    free(x);
     return 0;
+}
+
+int orc_skm_dist(int64_t N, int64_t D, int K, const int64_t* rowptr, const int32_t* col, const double* val,
+                 const double* C, double* dist) {
+    if (skm_check(N, D, K, rowptr, col, val, C) || !dist) return -1;
+    return skm_assign(N, D, K, rowptr, col, val, C, NULL, NULL, dist);
 }
 
 int orc_skm_objective(int64_t N, int64_t D, int K, const int64_t* rowptr, const int32_t* col, const double* val,
@@ -1487,7 +1483,7 @@ int orc_skm_objective(int64_t N, int64_t D, int K, const int64_t* rowptr, const 
     if (skm_check(N, D, K, rowptr, col, val, C) || !f) return -1;
     int32_t* a = assign ? assign : (int32_t*)malloc((size_t)(N > 0 ? N : 1) * sizeof(int32_t));
     double* dm = (double*)malloc((size_t)(N > 0 ? N : 1) * sizeof(double));
-    int rc = (a && dm) ? skm_assign(N, D, K, rowptr, col, val, C, a, dm) : -2;
+    int rc = (a && dm) ? skm_assign(N, D, K, rowptr, col, val, C, a, dm, NULL) : -2;
     if (!rc) {
         double s = 0.0;
         for (int64_t i = 0; i < N; ++i) s += dm[i];
@@ -1507,7 +1503,7 @@ static int skm_grad(int64_t N, int64_t D, int K, const int64_t* rowptr, const in
         free(a), free(n);
         return -2;
     }
-    int rc = skm_assign(N, D, K, rowptr, col, val, C, a, NULL);
+    int rc = skm_assign(N, D, K, rowptr, col, val, C, a, NULL, NULL);
     if (!rc) {
         for (int64_t i = 0; i < N; ++i) ++n[a[i]];
         for (int k = 0; k < K; ++k)

@@ -171,11 +171,13 @@ int orc_gather_map_vjp(int op, int64_t n, const double* as, int64_t m, const int
                        const double* ys_bar, double* as_bar, double* vs_bar);
 
 /* Sparse k-means (Sec. 7.5): CSR points (rowptr [N+1] int64, col [nnz] int32,
- * val [nnz]), dense centres C [K x D].  Distances on the FP64 chain
- * acc = |c_k|^2 (1024-dimension fma-chain blocks summed in order), then
- * acc = fma(x, x - 2 c_kj, acc) over the row's stored entries in order; ties
- * to the lowest k.  The VJP is 2 f_bar (n_k c_k - S_k) at fixed assignments,
- * the jvp of the VJP 2 f_bar n_k C_dot_k. */
+ * val [nnz]), dense centres C [K x D].  The distance of a row to a centre is
+ * the plain squared distance of the densified row, summed over d = 0..D-1 in
+ * order; ties to the lowest k.  The VJP is 2 f_bar (n_k c_k - S_k) at fixed
+ * assignments, the jvp of the VJP 2 f_bar n_k C_dot_k.  orc_skm_dist gives
+ * every distance, dist [N x K]. */
+int orc_skm_dist(int64_t N, int64_t D, int K, const int64_t* rowptr, const int32_t* col, const double* val,
+                 const double* C, double* dist);
 int orc_skm_objective(int64_t N, int64_t D, int K, const int64_t* rowptr, const int32_t* col, const double* val,
                       const double* C, int32_t* assign, double* f);
 int orc_skm_vjp(int64_t N, int64_t D, int K, const int64_t* rowptr, const int32_t* col, const double* val,

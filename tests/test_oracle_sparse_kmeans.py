@@ -1,5 +1,5 @@
 """Pins for the oracle's sparse k-means (Sec. 7.5): CSR points, dense centres,
-squared distance.  Checked against numpy on the densified points (all-pairs
+squared distance of the densified row.  Checked against numpy on the densified points (all-pairs
 distances, argmin, the closed-form gradient), against the separately pinned
 dense-k-means oracle (a taped gradient) on the same densified points, against
 central differences of the numpy objective, and the Hessian-vector product
@@ -33,6 +33,12 @@ def test_objective_matches_dense_numpy(orc, N, D, K, L):
     X = dense(rp, cl, v, D)
     rf, ra, dist = np_objective(X, C)
     assert abs(f - rf) <= 1e-12 * max(1.0, rf)
+    # every distance, against numpy's (pairwise-summed) squared distances,
+    # and the objective is the sum of each row's smallest one
+    od = orc.sparse_kmeans_distances(rp, cl, v, D, C)
+    assert np.allclose(od, dist, rtol=1e-13, atol=0)
+    assert f == od.min(axis=1).sum() or abs(f - od.min(axis=1).sum()) <= 1e-13 * f
+    assert np.array_equal(a, od.argmin(axis=1))
     # the same nearest centre wherever the two best distances are not within rounding
     srt = np.sort(dist, axis=1)
     clear = (srt[:, 1] - srt[:, 0]) > 1e-9 * np.maximum(1.0, srt[:, 0]) if K > 1 else np.ones(N, bool)
