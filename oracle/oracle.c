@@ -762,8 +762,12 @@ static void gop_comb(int op, const double* l, const double* r, double* out) {
     double o[4];
     switch (op) {
         case ORC_GOP_LOGADDEXP:
+            /* over the extended reals: -inf is the neutral element, NaN
+             * propagates, and e^(+inf) = +inf absorbs the other term */
             if (r[0] == -INFINITY) o[0] = l[0];
             else if (l[0] == -INFINITY) o[0] = r[0];
+            else if (isnan(l[0]) || isnan(r[0])) o[0] = l[0] + r[0];
+            else if (l[0] == INFINITY || r[0] == INFINITY) o[0] = INFINITY;
             else {
                 double m = l[0] > r[0] ? l[0] : r[0];
                 o[0] = m + log(exp(l[0] - m) + exp(r[0] - m));
@@ -789,6 +793,8 @@ static void gop_step(tape_t* t, int op, const int64_t* l, const int64_t* r, int6
         case ORC_GOP_LOGADDEXP:
             if (V(r[0]) == -INFINITY) o[0] = l[0]; /* r contributes nothing */
             else if (V(l[0]) == -INFINITY) o[0] = r[0];
+            else if (!isnan(V(l[0])) && !isnan(V(r[0])) && (V(l[0]) == INFINITY || V(r[0]) == INFINITY))
+                o[0] = t_pick(t, l[0], r[0], V(l[0]) != INFINITY); /* the +inf operand absorbs the other */
             else {
                 /* the shift m is a constant: d/da log(e^(a-m) + e^(b-m)) + m
                  * does not depend on it */

@@ -92,3 +92,16 @@ def test_adjoint_finite_differences(orc, op):
             q[c][i] -= h
             fd[i] = (f(p) - f(q)) / (2 * h)
         assert rel_l2(xb[c], fd) <= 1e-7
+
+
+def test_logaddexp_non_finite_bins(orc):
+    # over the extended reals: -inf is neutral, NaN propagates, +inf absorbs;
+    # numpy's logaddexp is an independent implementation of the same operator
+    x = np.array([0.5, np.inf, -1.0, np.nan, 2.0, -np.inf, np.inf, np.inf, -np.inf, 3.0])
+    inds = np.array([0, 0, 0, 1, 1, 2, 3, 3, 4, 5], dtype=np.int32)
+    got = orc.hist_generic("logaddexp", inds, [x], 7)[0]
+    for b in range(7):
+        sel = x[inds == b]
+        ref = np.logaddexp.reduce(sel) if sel.size else -np.inf
+        assert (np.isnan(got[b]) and np.isnan(ref)) or got[b] == ref, (b, got[b], ref)
+    assert np.isposinf(got[0]) and np.isnan(got[1]) and np.isneginf(got[2]) and np.isposinf(got[3])
