@@ -377,6 +377,10 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.cpu_sample, vs_np, inst, xs_np, is_np, sv_np, yb_np)
+        try:
+            cpu["by_config"] = oracle_by_config()
+        except Exception as e:  # report, keep the main line
+            cpu["by_config"] = {"error": f"{type(e).__name__}: {e}"}
 
     # Free the histogram/scatter inputs before the other workloads.
     del inst, vs, xs, is_, sv, ysb, calls
@@ -1013,6 +1017,154 @@ def bench_serve(args):
     return out
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
+
+
+def _host_threads():
+    """Threads for the oracle's P-thread baselines: the host's cores, capped at
+    16 (one GPU's share of a box's CPUs)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _threaded(jobs, threads, prepare=None):
+    """Runs the callables in `jobs` on `threads` host threads (the oracle's C
+    calls release the GIL) and returns the wall time.  With `prepare`, job i
+    is called with prepare[i]()'s result, and the preparation (input
+    generation) runs on the same threads before the timed region."""
+    import concurrent.futures as cf
+
+    with cf.ThreadPoolExecutor(threads) as ex:
+        args = [f.result() for f in [ex.submit(pr) for pr in prepare]] if prepare else [None] * len(jobs)
+        t0 = time.perf_counter()
+        for f in [ex.submit(j, *(() if a is None else (a,))) for j, a in zip(jobs, args)]:
+            f.result()
+        return time.perf_counter() - t0
+
+
+def oracle_by_config(serve_pool_seed=0):
+    """The oracle timed on this host for the other configurations, on bounded
+    samples (each a few seconds of CPU work), as SURVEY-style baselines:
+      C1  the n = 65,536 FP64 scan, primal + taped VJP, one thread, full size;
+      C3  GMM (D = 64, K = 200) objective + taped gradient on a sample of
+          points, P threads over point chunks and one thread;
+      C4  scan VJPs + sum VJPs over the first segments of the batch's length
+          table, P threads over segments;
+      C5  the first requests of the serving trace, offline, P threads.
+    Rates are measured on the sample, never extrapolated."""
+    sys.path.insert(0, ROOT)
+    import oracle
+    from paper_2202_10297_amd import workloads
+
+    if not os.path.exists(oracle.LIB_PATH):
+        oracle.build()
+    P = _host_threads()
+    res = {"threads": P, "host_cores": os.cpu_count(), "cpu_model": _cpu_model()}
+    # C1
+    a, b, ya, yb = workloads.linrec(65536, "f64", seed=0)
+    reps, t0 = 0, time.perf_counter()
+    while reps < 3 or time.perf_counter() - t0 < 1.0:
+        oracle.linrec_scan(a, b)
+        oracle.linrec_scan_vjp(a, b, ya, yb)
+        reps += 1
+    dt = (time.perf_counter() - t0) / reps
+    res["C1"] = {"value": round(65536 / dt, 1), "unit": "VJP elems/s (primal + taped VJP)", "cores": 1,
+                 "ms_per_instance": round(dt * 1e3, 3), "sample": "the full n = 65,536 FP64 instance", "reps": reps}
+    # C3
+    per = 40
+    X, al, mu, q, l = workloads.gmm(P * per, 64, 200, seed=0)
+
+    def gmm_job(lo, hi):
+        return lambda: (oracle.gmm_objective(X[lo:hi], al, mu, q, l), oracle.gmm_vjp(X[lo:hi], al, mu, q, l, 1.0))
+
+    wall = _threaded([gmm_job(i * per, (i + 1) * per) for i in range(P)], P)
+    t1 = time.perf_counter()
+    gmm_job(0, 100)()
+    one = time.perf_counter() - t1
+    res["C3"] = {"value": round(P * per / wall, 2), "unit": "points/s (objective + taped gradient)", "cores": P,
+                 "sample": f"{P * per} points of N = 10^6 (D = 64, K = 200), {per} per thread",
+                 "one_thread": {"value": round(100 / one, 2), "cores": 1, "sample": "100 points"}}
+    # C4
+    lengths = workloads.segment_lengths(4096, 64, 1 << 20, seed=0)
+    cut = int(np.searchsorted(np.cumsum(lengths), 1 << 24)) + 1
+    segs = [int(L) for L in lengths[:cut]]
+
+    def seg_inputs(L, s):
+        def prep():
+            gg = workloads.rng(100 + s)
+            return (gg.uniform(0.5, 1.0, L), gg.standard_normal(L), gg.standard_normal(L), gg.standard_normal(L))
+        return prep
+
+    def seg_run(x):
+        oracle.linrec_scan_vjp(*x)
+        oracle.reduce_vjp("add", x[1], 1.0)
+
+    wall = _threaded([seg_run] * len(segs), P, prepare=[seg_inputs(L, s) for s, L in enumerate(segs)])
+    tot = sum(segs)
+    res["C4"] = {"value": round(2 * tot / wall, 1), "unit": "VJP elems/s (scan + sum)", "cores": P,
+                 "sample": f"the first {len(segs)} of 4,096 segments ({tot} elements per set)"}
+    # C5
+    try:
+        res["C5"] = _oracle_serve_offline(oracle, workloads, P, nreq=8)
+    except Exception as e:  # report, keep the rest
+        res["C5"] = {"error": f"{type(e).__name__}: {e}"}
+    return res
+
+
+def _oracle_serve_offline(oracle, workloads, P, nreq):
+    """The first `nreq` requests of the serving trace (same pool seeds and
+    sizes as the served run), evaluated by the oracle on P threads."""
+    g = workloads.rng(0)
+    logu = lambda lo, hi: int(np.exp(g.uniform(np.log(lo), np.log(hi))))
+    per_kind = 24
+    spec = {"scan": [logu(1e3, 1e7) for _ in range(per_kind)]}
+    spec["hist"] = []
+    for _ in range(per_kind):
+        n = logu(1e4, 1e7)
+        spec["hist"].append((n, 1 << int(g.integers(12, 19))))
+    spec["gmm"] = [logu(1e3, 1e5) for _ in range(per_kind)]
+    gt = workloads.rng(12345)
+    n_arr = int(2000.0 * 5.0 * 1.2) + 16
+    t = np.cumsum(gt.exponential(1.0 / 2000.0, n_arr))
+    kinds = gt.choice(3, size=t.size, p=np.full(3, 1 / 3))
+    prep, jobs, elems, names = [], [], 0, []
+    for k in kinds[:nreq]:
+        kind = ("scan", "hist", "gmm")[int(k)]
+        i = int(gt.integers(0, per_kind))
+        v = int(gt.integers(0, 2))
+        names.append(kind)
+        if kind == "scan":
+            n = spec["scan"][i]
+            elems += n
+            prep.append(lambda n=n, i=i, v=v: (*workloads.linrec(n, "f32", seed=i)[:2],
+                                               *workloads.linrec(n, "f32", seed=i + 7919 * (v + 1))[2:]))
+            jobs.append(lambda x: oracle.linrec_scan_vjp(*x))
+        elif kind == "hist":
+            n, m = spec["hist"][i]
+            elems += n
+            prep.append(lambda n=n, m=m, i=i, v=v: (workloads.hist(n, m, "zipf", "f32", seed=i)[0], np.zeros(n),
+                                                    workloads.rng(i + 31 * (v + 1)).standard_normal(m)))
+            jobs.append(lambda x: oracle.hist_vjp("add", *x))
+        else:
+            N = spec["gmm"][i]
+            elems += N
+            prep.append(lambda N=N, i=i, v=v: (workloads.gmm(N, 32, 50, seed=3000 * 0 + i), 1.0 + 0.5 * v))
+            jobs.append(lambda x: oracle.gmm_vjp(*x[0], x[1]))
+    wall = _threaded(jobs, P, prepare=prep)
+    return {"value": round(nreq / wall, 3), "unit": "requests/s (offline)", "cores": min(P, nreq),
+            "sample": f"the first {nreq} requests of the 2,000 req/s trace ({', '.join(names)})", "elements": elems}
+
+
 def cpu_baseline(ns, vs_np, inst, xs_np, is_np, sv_np, yb_np):
     """The oracle (single-threaded, FP64 tape) on the first `ns` elements of
     every histogram instance and on the scatter restricted to targets below
@@ -1035,14 +1187,7 @@ def cpu_baseline(ns, vs_np, inst, xs_np, is_np, sv_np, yb_np):
     oracle.scatter_vjp(sel, yb_np[:ns])
     elems += sel.size
     dt = time.perf_counter() - t0
-    model = ""
-    try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                model = line.split(":", 1)[1].strip()
-                break
-    except OSError:
-        pass
+    model = _cpu_model()
     return {
         "value": round(elems / dt, 1),
         "unit": "elems/s",

@@ -100,6 +100,38 @@ pvjp_status pvjp_ws_clear(void* ws, size_t ws_bytes, void* stream);
 pvjp_status pvjp_ws_check(void* ws, int clear, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* Checked mode: device-side counts of inputs the method leaves undefined    */
+/* ------------------------------------------------------------------------ */
+
+/* Slots of the caller's counter block: int64 [PVJP_DIAG_N] in device memory,
+ * 8-byte aligned, zeroed by the caller.  Each call ADDS its counts to the
+ * block (one atomic add per launched block), so the block collects the
+ * counts of many calls until the caller reads and clears it.  None of these
+ * calls traps, changes its inputs or is needed by the operators: they are the
+ * checks a caller runs beside the operators when it wants them. */
+#define PVJP_DIAG_OOB 0 /* index outside [0, m) (reduce_by_index, Sec. 5.1.2; scatter targets outside [0, n)) */
+#define PVJP_DIAG_DUP 1 /* scatter target that repeats (Sec. 5.3 assumes unique targets); each extra occurrence once */
+#define PVJP_DIAG_NAN 2 /* NaN values */
+#define PVJP_DIAG_INF 3 /* +-inf values */
+#define PVJP_DIAG_N 4
+
+/* counters[PVJP_DIAG_OOB] += #{i < n : inds[i] < 0 or inds[i] >= m}.
+ * inds [n] int32 device. */
+pvjp_status pvjp_diag_indices(const int32_t* inds, int64_t n, int64_t m, int64_t* counters, void* stream);
+/* Bytes of the bitmap workspace of pvjp_diag_scatter: one bit per target. */
+size_t pvjp_diag_scatter_ws_bytes(int64_t n);
+/* For the m targets is [m] int32 into an array of n elements (n < 2^31):
+ * counters[PVJP_DIAG_OOB] += targets outside [0, n);
+ * counters[PVJP_DIAG_DUP] += occurrences of a target after its first.
+ * ws: device scratch of pvjp_diag_scatter_ws_bytes(n) bytes, 4-byte aligned;
+ * the call clears it itself (with a kernel, so it may be graph-captured). */
+pvjp_status pvjp_diag_scatter(const int32_t* is, int64_t m, int64_t n, int64_t* counters, void* ws,
+                              size_t ws_bytes, void* stream);
+/* counters[PVJP_DIAG_NAN] += NaN elements of x [n] dtype;
+ * counters[PVJP_DIAG_INF] += infinite elements. */
+pvjp_status pvjp_diag_nonfinite(pvjp_dtype dtype, const void* x, int64_t n, int64_t* counters, void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* Inclusive scan of the first-order linear recurrence (Sec. 5.2)             */
 /*                                                                            */
 /* Operator (a1,b1) (+) (a2,b2) = (a2*a1, a2*b1 + b2), neutral (1, 0):        */
@@ -176,6 +208,15 @@ pvjp_status pvjp_reduce_vjp(pvjp_op op, pvjp_dtype dtype, const void* x, int64_t
  * 2^22 bins: the bucket-partitioned path, which stores a packed 8-byte record
  * and a 2-byte bin per element (about 10n bytes plus per-bucket partials). */
 size_t pvjp_hist_ws_bytes(pvjp_op op, pvjp_dtype dtype, int64_t n, int64_t m);
+/* Which path pvjp_hist takes for (op, dtype, n, m, counts != 0), for tests
+ * and tuning: info[0] = PVJP_HIST_PATH_*; for the partitioned path info[1] =
+ * bins per bucket, info[2] = most records one work item of a bucket takes
+ * (larger buckets are split into several items, merged afterwards), info[3]
+ * = number of buckets; 0 otherwise.  info: int64 [4] host memory. */
+#define PVJP_HIST_PATH_LDS 0       /* every bin in each block's LDS, per-block partials merged */
+#define PVJP_HIST_PATH_CACHE 1     /* LDS cache of bins in front of device-memory atomics */
+#define PVJP_HIST_PATH_PARTITION 2 /* records sorted into buckets of bins, each bucket accumulated in LDS */
+pvjp_status pvjp_hist_plan_info(pvjp_op op, pvjp_dtype dtype, int64_t n, int64_t m, int counts, int64_t* info);
 /* inds [n] int32, vs [n] dtype, 1 <= m <= 2^30, n < 2^31.
  * hs [m] dtype (required).
  * winner [m] int32 (MIN/MAX, required): lowest i with inds[i] == k and

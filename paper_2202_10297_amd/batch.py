@@ -16,7 +16,7 @@ import numpy as np
 import torch
 
 from . import capi
-from .ops import _dt, _ptr, _stream
+from .ops import _after_lookback, _check_values, _dt, _ptr, _stream
 
 TILES = (1024, 2048, 4096)
 DEFAULT_TILE = 4096
@@ -81,8 +81,10 @@ class SegPlan:
         A = torch.empty_like(a) if outputs else None
         B = torch.empty_like(b) if outputs else None
         ck = torch.empty(self.ckpt_len(), dtype=a.dtype, device=a.device)
+        _check_values(a, b)
         capi.call("pvjp_seg_linrec_scan", _dt(a), _ptr(a), _ptr(b), self.total, self.nseg, self.tile, _ptr(A),
                   _ptr(B), _ptr(ck), _ptr(self.ws), self.ws.numel(), _stream(a.device))
+        _after_lookback(self.ws)
         return A, B, ck
 
     def vjp(self, a=None, b=None, yA_bar=None, yB_bar=None, ckpt=None, a_bar=None, b_bar=None, sum_ybar=None,
@@ -101,6 +103,7 @@ class SegPlan:
         capi.call("pvjp_seg_batch_vjp", _dt(ref), _ptr(a), _ptr(b), _ptr(yA_bar), _ptr(yB_bar), self.total,
                   self.nseg, self.tile, _ptr(ckpt), _ptr(a_bar), _ptr(b_bar), _ptr(sum_ybar), _ptr(sum_xbar),
                   int(accumulate), self.grid, _ptr(self.ws), self.ws.numel(), _stream(ref.device))
+        _after_lookback(self.ws)
         return a_bar, b_bar, sum_xbar
 
     # -------------------------------------------------------------- graphs

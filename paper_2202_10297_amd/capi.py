@@ -19,6 +19,8 @@ FN_SQUARE, FN_EXP, FN_LOG, FN_SIN, FN_TANH = 0, 1, 2, 3, 4
 GOP_LOGADDEXP, GOP_LINREC, GOP_MAT2 = 0, 1, 2
 GMAP = {"gather": 0, "mul": 1, "sqdiff": 2}
 LINREC_CKPT_INTERVAL = 1024
+HIST_PATH_LDS, HIST_PATH_CACHE, HIST_PATH_PARTITION = 0, 1, 2
+DIAG_OOB, DIAG_DUP, DIAG_NAN, DIAG_INF, DIAG_N = 0, 1, 2, 3, 4
 
 _P = ctypes.c_void_p
 _I = ctypes.c_int
@@ -32,6 +34,10 @@ SIGNATURES = {
     "pvjp_version": (_S, []),
     "pvjp_ws_clear": (_I, [_P, _Z, _P]),
     "pvjp_ws_check": (_I, [_P, _I, _P]),
+    "pvjp_diag_indices": (_I, [_P, _L, _L, _P, _P]),
+    "pvjp_diag_scatter_ws_bytes": (_Z, [_L]),
+    "pvjp_diag_scatter": (_I, [_P, _L, _L, _P, _P, _Z, _P]),
+    "pvjp_diag_nonfinite": (_I, [_I, _P, _L, _P, _P]),
     "pvjp_linrec_ckpt_len": (_L, [_L]),
     "pvjp_linrec_scan_ws_bytes": (_Z, [_I, _L]),
     "pvjp_linrec_scan": (_I, [_I, _P, _P, _L, _P, _P, _P, _P, _Z, _P]),
@@ -41,6 +47,7 @@ SIGNATURES = {
     "pvjp_reduce": (_I, [_I, _I, _P, _L, _P, _P, _P, _P, _P, _Z, _P]),
     "pvjp_reduce_vjp": (_I, [_I, _I, _P, _L, _P, _P, _P, _P, _P, _I, _P]),
     "pvjp_hist_ws_bytes": (_Z, [_I, _I, _L, _L]),
+    "pvjp_hist_plan_info": (_I, [_I, _I, _L, _L, _I, _P]),
     "pvjp_hist": (_I, [_I, _I, _P, _P, _L, _L, _P, _P, _P, _P, _P, _P, _Z, _P]),
     "pvjp_hist_vjp": (_I, [_I, _I, _P, _P, _L, _L, _P, _P, _P, _P, _P, _I, _P]),
     "pvjp_scatter": (_I, [_I, _P, _L, _P, _P, _L, _P, _P]),

@@ -1153,6 +1153,24 @@ extern "C" size_t pvjp_hist_ws_bytes(pvjp_op op, pvjp_dtype dtype, int64_t n, in
     return hist_ws(op, n, m, dtype == PVJP_F32);
 }
 
+extern "C" pvjp_status pvjp_hist_plan_info(pvjp_op op, pvjp_dtype dtype, int64_t n, int64_t m, int counts,
+                                           int64_t* info) {
+    clear_error();
+    PVJP_REQUIRE(valid_op(op) && valid_dtype(dtype), "pvjp_hist_plan_info: unknown op or dtype");
+    PVJP_REQUIRE(n >= 0 && n <= INT32_MAX && m >= 1 && m <= kMaxBins, "pvjp_hist_plan_info: n or m out of range");
+    PVJP_REQUIRE(info != nullptr, "pvjp_hist_plan_info: info is NULL");
+    info[1] = info[2] = info[3] = 0;
+    if (use_partition(op, dtype == PVJP_F32, m, counts != 0)) {
+        info[0] = PVJP_HIST_PATH_PARTITION;
+        info[1] = kPartBins;
+        info[2] = kPartSeg;
+        info[3] = ceil_div(m, kPartBins);
+    } else {
+        info[0] = hist_plan(op, n, m, counts != 0).cache ? PVJP_HIST_PATH_CACHE : PVJP_HIST_PATH_LDS;
+    }
+    return PVJP_OK;
+}
+
 extern "C" pvjp_status pvjp_hist(pvjp_op op, pvjp_dtype dtype, const int32_t* inds, const void* vs, int64_t n,
                                  int64_t m, void* hs, int32_t* winner, void* p, int32_t* z, int32_t* count,
                                  void* ws, size_t ws_bytes, void* stream) {
@@ -1227,7 +1245,11 @@ extern "C" pvjp_status pvjp_hist_jvp(pvjp_op op, pvjp_dtype dtype, const int32_t
     if (op == PVJP_ADD) {
         const pvjp_status s = pvjp_hist(op, dtype, inds, vs_dot, n, m, hs_dot, nullptr, nullptr, nullptr, nullptr, ws,
                                         ws_bytes, stream);
-        if (s != PVJP_OK) set_error("pvjp_hist_jvp: %s", pvjp_last_error());
+        if (s != PVJP_OK) {
+            char inner[256];
+            snprintf(inner, sizeof(inner), "%s", pvjp_last_error());
+            set_error("pvjp_hist_jvp: %s", inner);
+        }
         return s;
     }
     PVJP_REQUIRE(winner != nullptr, "pvjp_hist_jvp: MIN/MAX need the winners of pvjp_hist");

@@ -5,8 +5,13 @@
 // gives element i the adjoint hs_bar[b] e^(x_i - hs[b]): one pass, no sort.
 // The primal runs on this library's reduce_by_index paths: the bin maxima
 // (max), then the shifted exponentials summed per bin (+, FP64 sums), then
-// hs = max + log(sum).  An empty bin, or one of -inf elements only, gets -inf;
-// a -inf element gets adjoint 0; indices outside [0, m) are skipped.
+// hs = max + log(sum).  Over the extended reals -inf is the neutral element:
+// an empty bin, or one of -inf elements only, gets -inf and a -inf element
+// gets adjoint 0.  An element equal to its bin's maximum contributes e^0 = 1
+// (also when both are +inf), so a bin holding +inf gets +inf and a NaN
+// element makes its bin NaN.  An element equal to a +inf total gets the whole
+// hs_bar (the limit of the softmax weight of a unique +inf); several +inf
+// elements of one bin each get it.  Indices outside [0, m) are skipped.
 #include "common.h"
 
 namespace pvjp {
@@ -42,7 +47,8 @@ __global__ __launch_bounds__(256) void hl_shift_kernel(const int32_t* __restrict
             const int64_t i = base + (int64_t)u * blockDim.x;
             if (i < n) {
                 const bool live = xi[u] != -(T)INFINITY && mx[u] != -(T)INFINITY;
-                __builtin_nontemporal_store(live ? hl_exp(xi[u] - mx[u]) : T(0), e + i);
+                const T v = xi[u] == mx[u] ? T(1) : hl_exp(xi[u] - mx[u]);
+                __builtin_nontemporal_store(live ? v : T(0), e + i);
             }
         }
     }
@@ -52,7 +58,7 @@ template <class T>
 __global__ __launch_bounds__(256) void hl_final_kernel(const T* __restrict__ hmax, const T* __restrict__ hsum,
                                                        int64_t m, T* __restrict__ hs) {
     for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < m; b += (int64_t)gridDim.x * blockDim.x)
-        hs[b] = hsum[b] > T(0) ? hmax[b] + hl_log(hsum[b]) : -(T)INFINITY;
+        hs[b] = hsum[b] == T(0) ? -(T)INFINITY : hmax[b] + hl_log(hsum[b]);  // NaN sums stay NaN
 }
 
 template <class T, bool ACC>
@@ -80,7 +86,7 @@ __global__ __launch_bounds__(256) void hl_vjp_kernel(const int32_t* __restrict__
             const int64_t i = base + (int64_t)u * blockDim.x;
             if (i < n) {
                 const bool live = xi[u] != -(T)INFINITY && h[u] != -(T)INFINITY;
-                const T v = live ? g[u] * hl_exp(xi[u] - h[u]) : T(0);
+                const T v = live ? g[u] * (xi[u] == h[u] ? T(1) : hl_exp(xi[u] - h[u])) : T(0);
                 if (ACC) xb[i] = xb[i] + v;
                 else __builtin_nontemporal_store(v, xb + i);
             }
@@ -170,7 +176,8 @@ extern "C" pvjp_status pvjp_hist_lae_vjp(pvjp_dtype dtype, const int32_t* inds, 
                                          void* stream) {
     clear_error();
     PVJP_REQUIRE(valid_dtype(dtype), "pvjp_hist_lae_vjp: unknown dtype %d", (int)dtype);
-    PVJP_REQUIRE(n >= 0 && m >= 1, "pvjp_hist_lae_vjp: n = %lld, m = %lld out of range", (long long)n, (long long)m);
+    PVJP_REQUIRE(n >= 0 && n < INT32_MAX && m >= 1 && m <= ((int64_t)1 << 30),
+                 "pvjp_hist_lae_vjp: n = %lld, m = %lld out of range", (long long)n, (long long)m);
     if (n == 0) return PVJP_OK;
     PVJP_REQUIRE(inds != nullptr && x != nullptr && hs != nullptr && hs_bar != nullptr && x_bar != nullptr,
                  "pvjp_hist_lae_vjp: inds, x, hs, hs_bar and x_bar must be non-NULL");

@@ -109,6 +109,10 @@ extern "C" pvjp_status pvjp_scatter_jvp(pvjp_dtype dtype, void* ys_dot, int64_t 
                                         const void* vs_dot, int64_t m, void* stream) {
     clear_error();
     const pvjp_status s = pvjp_scatter(dtype, ys_dot, n, is, vs_dot, m, nullptr, stream);
-    if (s != PVJP_OK) set_error("pvjp_scatter_jvp: %s", pvjp_last_error());
+    if (s != PVJP_OK) {
+        char inner[256];
+        snprintf(inner, sizeof(inner), "%s", pvjp_last_error());
+        set_error("pvjp_scatter_jvp: %s", inner);
+    }
     return s;
 }

@@ -2,12 +2,14 @@
 // points stored in CSR (rowptr [N+1] int64, col [nnz] int32, val [nnz] FP32)
 // and dense centres C [K x D] FP32.
 //
-// The distance of row i to centre k is one FP64 chain, the same in every
-// implementation of it: acc = |c_k|^2, then for each stored (j, x) of the row
-// in CSR order acc = fma(x, x - 2 c_kj, acc), since |x - c|^2 = |c|^2 + sum
-// over stored x of x (x - 2 c).  |c_k|^2 is fixed as well: blocks of 1024
-// dimensions, each an fma chain in d order, the block sums added in block
-// order.  Ties go to the lowest k.
+// The distance of row i to centre k is one FP64 chain over the row's stored
+// entries only: acc = |c_k|^2, then for each stored (j, x) of the row in CSR
+// order acc = fma(x, x - 2 c_kj, acc), since |x - c|^2 = |c|^2 + sum over
+// stored x of x (x - 2 c).  |c_k|^2 is summed in blocks of 1024 dimensions,
+// each an fma chain in d order, the block sums added in block order.  This
+// equals the plain sum of (x_d - c_d)^2 over every dimension up to FP64
+// rounding, so the nearest centre agrees with it wherever the two best
+// distances are further apart than that rounding.  Ties go to the lowest k.
 //
 // At fixed assignments the gradient is 2 f_bar (n_k c_k - S_k), S_k the sum
 // of the rows assigned to k: a histogram-like accumulator of every stored

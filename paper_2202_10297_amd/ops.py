@@ -73,6 +73,81 @@ class Workspaces:
 WS = Workspaces()
 
 
+# ------------------------------------------------------------ checked mode
+class _Checked:
+    """Checked mode.  When on, the operators below first run the library's
+    diagnostic kernels on their inputs: indices outside the bin or target
+    range, repeated scatter targets, NaN and infinite values are added to a
+    per-device int64 counter block (read with ``diag``).  After a lookback
+    scan, the workspace's error word is read back (a stream synchronisation)
+    and a recorded error raises ``capi.PvjpError``.  Off by default: the
+    checks cost a pass over the inputs and, for the scans, a host wait."""
+
+    def __init__(self):
+        self.on = False
+        self.counters = {}
+
+    def block(self, device) -> torch.Tensor:
+        dev = torch.device(device)
+        c = self.counters.get(dev.index)
+        if c is None:
+            c = self.counters[dev.index] = torch.zeros(capi.DIAG_N, dtype=torch.int64, device=dev)
+        return c
+
+
+CHECKED = _Checked()
+
+
+def set_checked(on: bool = True) -> None:
+    CHECKED.on = bool(on)
+
+
+def diag(device=None, reset: bool = False) -> dict:
+    """Counts collected in checked mode on `device` (default: the current
+    one): {"oob", "dup", "nan", "inf"}; reset=True clears them."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    c = CHECKED.block(dev)
+    v = c.cpu().tolist()
+    if reset:
+        c.zero_()
+    return {"oob": v[capi.DIAG_OOB], "dup": v[capi.DIAG_DUP], "nan": v[capi.DIAG_NAN], "inf": v[capi.DIAG_INF]}
+
+
+def _check_indices(inds, m):
+    if CHECKED.on and inds.numel():
+        capi.call("pvjp_diag_indices", _ptr(inds), inds.numel(), int(m), _ptr(CHECKED.block(inds.device)),
+                  _stream(inds.device))
+
+
+def _check_values(*xs):
+    if not CHECKED.on:
+        return
+    for x in xs:
+        if x is not None and x.numel() and x.dtype in _DT:
+            capi.call("pvjp_diag_nonfinite", _dt(x), _ptr(x), x.numel(), _ptr(CHECKED.block(x.device)),
+                      _stream(x.device))
+
+
+def _check_targets(is_, n):
+    if CHECKED.on and is_.numel():
+        nb = capi.lib().pvjp_diag_scatter_ws_bytes(int(n))
+        ws = WS.get("diag_scatter", nb, is_.device)
+        capi.call("pvjp_diag_scatter", _ptr(is_), is_.numel(), int(n), _ptr(CHECKED.block(is_.device)), _ptr(ws),
+                  ws.numel(), _stream(is_.device))
+
+
+def check_workspace(ws) -> None:
+    """Raises capi.PvjpError if a lookback launch recorded an error in `ws`
+    (and clears it); synchronises the stream."""
+    capi.call("pvjp_ws_check", _ptr(ws), 1, _stream(ws.device))
+
+
+def _after_lookback(ws):
+    # not while a graph is being captured: the check waits on the stream
+    if CHECKED.on and not torch.cuda.is_current_stream_capturing():
+        check_workspace(ws)
+
+
 # ------------------------------------------------------------ linrec scan
 def linrec_scan(a: torch.Tensor, b: torch.Tensor, ckpt: bool = True):
     """Inclusive scan of (a, b) under (a1,b1)(+)(a2,b2) = (a2 a1, a2 b1 + b2).
@@ -83,8 +158,10 @@ def linrec_scan(a: torch.Tensor, b: torch.Tensor, ckpt: bool = True):
     ck = torch.empty(2 * capi.lib().pvjp_linrec_ckpt_len(n), dtype=a.dtype, device=a.device) if ckpt else None
     nb = capi.lib().pvjp_linrec_scan_ws_bytes(dt, n)
     ws = WS.get("linrec_fwd", nb, a.device)
+    _check_values(a, b)
     capi.call("pvjp_linrec_scan", dt, _ptr(a), _ptr(b), n, _ptr(A), _ptr(B), _ptr(ck), _ptr(ws), ws.numel(),
               _stream(a.device))
+    _after_lookback(ws)
     return A, B, ck
 
 
@@ -97,8 +174,10 @@ def linrec_scan_vjp(a, b, yA_bar, yB_bar, ckpt=None, a_bar=None, b_bar=None, acc
         b_bar = torch.zeros_like(b) if accumulate else torch.empty_like(b)
     nb = capi.lib().pvjp_linrec_scan_vjp_ws_bytes(dt, n)
     ws = WS.get("linrec_vjp", nb, a.device)
+    _check_values(a, b, yA_bar, yB_bar)
     capi.call("pvjp_linrec_scan_vjp", dt, _ptr(a), _ptr(b), _ptr(yA_bar), _ptr(yB_bar), n, _ptr(ckpt),
               _ptr(a_bar), _ptr(b_bar), int(accumulate), _ptr(ws), ws.numel(), _stream(a.device))
+    _after_lookback(ws)
     return a_bar, b_bar
 
 
@@ -238,6 +317,8 @@ def hist(op, inds: torch.Tensor, vs: torch.Tensor, m: int, counts: bool = False)
         z = aux["z"] = torch.empty(m, dtype=torch.int32, device=dev)
     if counts:
         count = aux["count"] = torch.empty(m, dtype=torch.int32, device=dev)
+    _check_indices(inds, m)
+    _check_values(vs)
     nb = capi.lib().pvjp_hist_ws_bytes(o, dt, n, m)
     ws = WS.get("hist", nb, dev)
     capi.call("pvjp_hist", o, dt, _ptr(inds), _ptr(vs), n, m, _ptr(hs), _ptr(winner), _ptr(p), _ptr(z),
@@ -252,6 +333,9 @@ def hist_vjp(op, inds, vs, m, aux, hs_bar, vs_bar=None, accumulate=False, n=None
     if vs_bar is None:
         shape = (n,)
         vs_bar = (torch.zeros if accumulate else torch.empty)(shape, dtype=hs_bar.dtype, device=hs_bar.device)
+    if o == capi.ADD or o == capi.MUL:
+        _check_indices(inds, m)
+    _check_values(hs_bar)
     capi.call("pvjp_hist_vjp", o, dt, _ptr(inds), _ptr(vs), n, m, _ptr(aux.get("winner")), _ptr(aux.get("p")),
               _ptr(aux.get("z")), _ptr(hs_bar), _ptr(vs_bar), int(accumulate), _stream(hs_bar.device))
     return vs_bar
@@ -262,6 +346,8 @@ def scatter_(xs: torch.Tensor, is_: torch.Tensor, vs: torch.Tensor, save: bool =
     """In place on xs; returns xs_saved (or None)."""
     dt = _dt(xs)
     saved = torch.empty(is_.numel(), dtype=xs.dtype, device=xs.device) if save else None
+    _check_targets(is_, xs.numel())
+    _check_values(vs)
     capi.call("pvjp_scatter", dt, _ptr(xs), xs.numel(), _ptr(is_), _ptr(vs), is_.numel(), _ptr(saved),
               _stream(xs.device))
     return saved
@@ -272,6 +358,8 @@ def scatter_vjp_(ys_bar, is_, vs_bar=None, accumulate=False, ys=None, xs_saved=N
     dt = _dt(ys_bar)
     if vs_bar is None:
         vs_bar = (torch.zeros if accumulate else torch.empty)(is_.numel(), dtype=ys_bar.dtype, device=ys_bar.device)
+    _check_targets(is_, ys_bar.numel())
+    _check_values(ys_bar)
     capi.call("pvjp_scatter_vjp", dt, _ptr(ys_bar), ys_bar.numel(), _ptr(is_), is_.numel(), _ptr(vs_bar),
               int(accumulate), _ptr(ys), _ptr(xs_saved), _stream(ys_bar.device))
     return vs_bar
@@ -455,6 +543,8 @@ def gather_map(op, as_, is_, vs=None, out=None):
         raise TypeError("is_ must be int32")
     m = is_.numel()
     ys = out if out is not None else torch.empty(m, dtype=as_.dtype, device=as_.device)
+    _check_indices(is_, as_.numel())
+    _check_values(as_, vs)
     capi.call("pvjp_gather_map", o, _dt(as_), _ptr(as_), as_.numel(), _ptr(is_), _ptr(vs), m, _ptr(ys),
               _stream(as_.device))
     return ys
@@ -468,6 +558,8 @@ def gather_map_vjp(op, as_, is_, vs, ys_bar, as_bar=None, vs_bar=None, accumulat
     mk = torch.zeros if accumulate else torch.empty
     ab = as_bar if as_bar is not None else mk(n, dtype=as_.dtype, device=dev)
     vb = vs_bar if (vs_bar is not None or o == 0) else mk(m, dtype=as_.dtype, device=dev)
+    _check_indices(is_, n)
+    _check_values(ys_bar)
     nb = capi.lib().pvjp_gather_map_ws_bytes(_dt(as_), n, m)
     ws = WS.get("gather_map", nb, dev)
     capi.call("pvjp_gather_map_vjp", o, _dt(as_), _ptr(as_), n, _ptr(is_), _ptr(vs), m, _ptr(ys_bar), _ptr(ab),
@@ -553,6 +645,8 @@ def hist_lae(inds, x, m):
         raise TypeError("inds must be int32")
     dt, dev, n = _dt(x), x.device, x.numel()
     hs = torch.empty(m, dtype=x.dtype, device=dev)
+    _check_indices(inds, m)
+    _check_values(x)
     nb = capi.lib().pvjp_hist_lae_ws_bytes(dt, n, m)
     ws = WS.get("hist_lae", nb, dev)
     capi.call("pvjp_hist_lae", dt, _ptr(inds), _ptr(x), n, m, _ptr(hs), _ptr(ws), ws.numel(), _stream(dev))
@@ -561,6 +655,16 @@ def hist_lae(inds, x, m):
 
 def hist_lae_vjp(inds, x, hs, hs_bar, x_bar=None, accumulate=False):
     """x_bar (+)= hs_bar[b] e^(x - hs[b]) per element of bin b."""
+    if inds.dtype != torch.int32:
+        raise TypeError("inds must be int32")
+    if inds.numel() != x.numel():
+        raise ValueError("inds and x must have the same number of elements")
+    if hs.dtype != x.dtype or hs_bar.dtype != x.dtype:
+        raise TypeError("hs and hs_bar must have the dtype of x")
+    if hs_bar.numel() != hs.numel():
+        raise ValueError("hs_bar must have one element per bin")
+    if x_bar is not None and (x_bar.dtype != x.dtype or x_bar.numel() != x.numel()):
+        raise ValueError("x_bar must have the dtype and size of x")
     if x_bar is None:
         x_bar = (torch.zeros_like if accumulate else torch.empty_like)(x)
     capi.call("pvjp_hist_lae_vjp", _dt(x), _ptr(inds), _ptr(x), x.numel(), hs.numel(), _ptr(hs), _ptr(hs_bar),

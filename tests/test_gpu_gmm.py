@@ -70,6 +70,27 @@ def test_gmm_gradient_from_s_checkpoint(ops, orc, N, D, K):
         assert rel_l2(host(g) - b, r) <= 2 * TOL_F32
 
 
+def test_gmm_several_point_chunks(ops, orc):
+    # 40000 points span three point chunks of the objective and the gradient,
+    # so the FP64 merge across chunks is checked element by element
+    N, D, K = 40000, 32, 5
+    X, alpha, mu, q, l = workloads.gmm(N, D, K, seed=11)
+    ll, lse = ops.gmm_objective(dev(X), dev(alpha), dev(mu), dev(q), dev(l))
+    rll, rlse = orc.gmm_objective(X, alpha, mu, q, l)
+    assert abs(host(ll)[0] - rll) <= TOL_F32 * abs(rll)
+    assert rel_l2(host(lse), rlse) <= TOL_F32
+    ref = orc.gmm_vjp(X, alpha, mu, q, l, 1.0)
+    for s in (None, "ckpt"):
+        if s is None:
+            got = ops.gmm_vjp(dev(X), dev(alpha), dev(mu), dev(q), dev(l), lse=lse, ell_bar=1.0)
+        else:
+            _, lse2, sck = ops.gmm_objective_ckpt(dev(X), dev(alpha), dev(mu), dev(q), dev(l))
+            got = ops.gmm_vjp(dev(X), dev(alpha), dev(mu), dev(q), dev(l), lse=lse2, s=sck, ell_bar=1.0)
+        for name, g, r in zip(["alpha", "mu", "q", "l"], got, ref):
+            err = rel_l2(host(g), r)
+            assert err <= TOL_F32, (s, name, err)
+
+
 def test_gmm_vjp_without_checkpoint_and_accumulate(ops, orc):
     N, D, K = 500, 64, 6
     X, alpha, mu, q, l = workloads.gmm(N, D, K, seed=3)

@@ -1,9 +1,16 @@
 """GPU parity of sparse k-means (Sec. 7.5: CSR points, dense centres) through
-the C ABI against the oracle: assignments bit-exact (both sides decide on the
-same FP64 distance chain), objective within 1e-12, gradient and Hessian-vector
-product within the FP32 bar.  Sizes from one row to bag-of-words shapes,
-K = 1 to 64, empty rows, and K D beyond the partitioned accumulator's 2^22
-bins.
+the C ABI against the oracle: objective within 1e-12, gradient and
+Hessian-vector product within the FP32 bar.  Sizes from one row to
+bag-of-words shapes, K = 1 to 64, empty rows, and K D beyond the partitioned
+accumulator's 2^22 bins.
+
+The oracle takes the squared distance of the densified row term by term; the
+kernel sums the same quantity as |c|^2 + sum over stored x of x (x - 2c).
+Both are FP64 sums of FP32 data, so they differ by rounding only.  The nearest
+centre must be the same wherever the oracle's two best distances are further
+apart than twice the rounding bound of either sum; on the remaining rows
+(reported, normally none) the kernel's choice must be one whose oracle
+distance is within that bound of the minimum.
 """
 import numpy as np
 import pytest
@@ -14,6 +21,33 @@ from paper_2202_10297_amd import workloads
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
+
+
+EPS64 = 2.0 ** -53
+
+
+def check_assign(got, rp, cl, v, D, C, orc):
+    """Assignments against the oracle's distances; returns the rows where the
+    two best differ by no more than the rounding bound."""
+    dist = orc.sparse_kmeans_distances(rp, cl, v, D, C)
+    N, K = dist.shape
+    row = np.repeat(np.arange(N), np.diff(rp))
+    x2 = np.bincount(row, weights=v.astype(np.float64) ** 2, minlength=N)
+    c2 = (C.astype(np.float64) ** 2).sum(axis=1).max()
+    L = D + np.diff(rp) + 2
+    # |sum error| <= L eps * sum of |terms|, and every term of either chain is
+    # bounded by 2 (x^2 + c^2) summed over the row
+    bound = 2.0 * L * EPS64 * 2.0 * (x2 + c2)
+    ref = dist.argmin(axis=1)
+    if K == 1:
+        assert np.array_equal(got, ref)
+        return 0
+    srt = np.sort(dist, axis=1)
+    clear = (srt[:, 1] - srt[:, 0]) > 2.0 * bound
+    assert np.array_equal(got[clear], ref[clear])
+    rows = np.nonzero(~clear)[0]
+    assert np.all(dist[rows, got[rows]] - srt[rows, 0] <= 2.0 * bound[rows])
+    return rows.size
 
 
 def dev(x):
@@ -33,7 +67,7 @@ def ops():
     return o
 
 
-CASES = [(1, 3, 1, 2), (50, 40, 3, 6), (2000, 3000, 10, 60), (3001, 500, 64, 20), (20000, 102660, 10, 120),
+CASES = [(1, 3, 1, 2), (50, 40, 3, 6), (2000, 3000, 10, 60), (3001, 500, 64, 20), (4000, 102660, 10, 120),
          (700, 600000, 8, 30)]
 
 
@@ -44,7 +78,8 @@ def test_sparse_kmeans(ops, orc, N, D, K, L):
     drp, dcl, dv, dC = dev(rp), dev(cl), dev(v), dev(C)
     f, a = ops.sparse_kmeans_objective(drp, dcl, dv, D, dC)
     rf, ra = orc.sparse_kmeans_objective(rp, cl, v, D, C)
-    assert np.array_equal(host(a), ra)
+    near = check_assign(host(a), rp, cl, v, D, C, orc)
+    print(f"N={N} D={D} K={K}: {near} rows with a near-tie excluded from the bitwise check")
     assert abs(host(f)[0] - rf) <= 1e-12 * max(1.0, rf)
     Cd = workloads.rng(6).standard_normal(C.shape).astype(np.float32)
     cb, hv = ops.sparse_kmeans_vjp(drp, dcl, dv, D, dC, a, 0.5, C_dot=dev(Cd))
@@ -59,8 +94,7 @@ def test_empty_rows_and_accumulate(ops, orc):
     C = (C + 0.05).astype(np.float32)
     drp, dcl, dv, dC = dev(rp), dev(cl), dev(v), dev(C)
     f, a = ops.sparse_kmeans_objective(drp, dcl, dv, D, dC)
-    rf, ra = orc.sparse_kmeans_objective(rp, cl, v, D, C)
-    assert np.array_equal(host(a), ra)
+    assert check_assign(host(a), rp, cl, v, D, C, orc) == 0
     base = np.full(C.shape, 0.25, dtype=np.float32)
     cb, _ = ops.sparse_kmeans_vjp(drp, dcl, dv, D, dC, a, out=(dev(base), None), accumulate=True)
     assert rel_l2(host(cb) - 0.25, orc.sparse_kmeans_vjp(rp, cl, v, D, C)) <= 2 * TOL_F32
