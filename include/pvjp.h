@@ -169,6 +169,22 @@ pvjp_status pvjp_linrec_scan_vjp(pvjp_dtype dtype, const void* a, const void* b,
                                  const void* ckpt, void* a_bar, void* b_bar, int accumulate,
                                  void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * return sweep as pvjp_linrec_scan_vjp, with the same arguments except the
+ * workspace, which is a fixed array inside the library (one per GPU, held
+ * until the process ends, at most pvjp_linrec_scan_vjp_noalloc_max_bytes():
+ * 8 MiB, enough for n up to 2^26 in FP64 and 2^27 in FP32).  Larger n
+ * returns PVJP_ENOMEM before any launch.  No call allocates or frees memory.
+ * Every call on one GPU shares that GPU's array: calls that may overlap on
+ * one GPU (two streams, two threads) race and must be serialised by the
+ * caller.  The stream's device is the one whose array is used. */
+size_t pvjp_linrec_scan_vjp_noalloc_max_bytes(void);
+pvjp_status pvjp_linrec_scan_vjp_noalloc(pvjp_dtype dtype, const void* a, const void* b,
+                                         const void* yA_bar, const void* yB_bar, int64_t n,
+                                         const void* ckpt, void* a_bar, void* b_bar, int accumulate,
+                                         void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* reduce (Sec. 5.1, special operators Sec. 5.1.1)                            */
 /* ------------------------------------------------------------------------ */

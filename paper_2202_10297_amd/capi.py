@@ -43,6 +43,8 @@ SIGNATURES = {
     "pvjp_linrec_scan": (_I, [_I, _P, _P, _L, _P, _P, _P, _P, _Z, _P]),
     "pvjp_linrec_scan_vjp_ws_bytes": (_Z, [_I, _L]),
     "pvjp_linrec_scan_vjp": (_I, [_I, _P, _P, _P, _P, _L, _P, _P, _P, _I, _P, _Z, _P]),
+    "pvjp_linrec_scan_vjp_noalloc_max_bytes": (_Z, []),
+    "pvjp_linrec_scan_vjp_noalloc": (_I, [_I, _P, _P, _P, _P, _L, _P, _P, _P, _I, _P]),
     "pvjp_reduce_ws_bytes": (_Z, [_I, _I, _L]),
     "pvjp_reduce": (_I, [_I, _I, _P, _L, _P, _P, _P, _P, _P, _Z, _P]),
     "pvjp_reduce_vjp": (_I, [_I, _I, _P, _L, _P, _P, _P, _P, _P, _I, _P]),

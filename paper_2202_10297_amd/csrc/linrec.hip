@@ -17,6 +17,8 @@
 //      r_bar_i = y_bar_i + a_{i+1} r_bar_{i+1};
 //   4. map a_bar_i = A_{i-1} rA_bar_i + B_{i-1} rB_bar_i, b_bar_i = rB_bar_i
 //      (the transposed right Jacobian [[A_{i-1}, 0], [B_{i-1}, 1]]).
+#include <mutex>
+
 #include "common.h"
 #include "prims.h"
 
@@ -474,6 +476,60 @@ static pvjp_status launch_vjp(const void* a, const void* b, const void* ya, cons
     return PVJP_OK;
 }
 
+// ------------------------------------------------- fixed-scratch variant
+// The VJP entry point for callers that cannot allocate takes its workspace
+// from this array instead of an argument.  Each GPU the library runs on
+// holds its own copy until the process ends.  It starts zero-filled (as a
+// workspace must), and every lookback launch leaves it ready for the next
+// one, so it is never cleared again.  In host code `scratch` names a
+// host-side stand-in, not device memory: the device address is looked up
+// once per device with hipGetSymbolAddress and only that address is used.
+constexpr size_t kNoAllocScratchBytes = (size_t)8 << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch[kMaxDevices];
+
+// Device address of `scratch` on the device that runs `st`.
+static pvjp_status scratch_for(hipStream_t st, void** out) {
+    int dev = 0;
+    if (st != nullptr) {
+        hipDevice_t d;
+        if (hipStreamGetDevice(st, &d) != hipSuccess) {
+            set_error("pvjp_linrec_scan_vjp_noalloc: cannot tell the stream's device");
+            return PVJP_EDEVICE;
+        }
+        dev = (int)d;
+    } else if (hipGetDevice(&dev) != hipSuccess) {
+        set_error("pvjp_linrec_scan_vjp_noalloc: no current device");
+        return PVJP_EDEVICE;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("pvjp_linrec_scan_vjp_noalloc: device %d beyond the %d this library tracks", dev, kMaxDevices);
+        return PVJP_EUNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[dev] == nullptr) {
+        int cur = 0;
+        if (hipGetDevice(&cur) != hipSuccess || (cur != dev && hipSetDevice(dev) != hipSuccess)) {
+            set_error("pvjp_linrec_scan_vjp_noalloc: cannot make device %d current", dev);
+            return PVJP_EDEVICE;
+        }
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess || p == nullptr) {
+            set_error("pvjp_linrec_scan_vjp_noalloc: hipGetSymbolAddress failed on device %d: %s", dev,
+                      hipGetErrorString(e));
+            return PVJP_EDEVICE;
+        }
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return PVJP_OK;
+}
+
 }  // namespace pvjp
 
 using namespace pvjp;
@@ -537,4 +593,31 @@ extern "C" pvjp_status pvjp_linrec_scan_vjp(pvjp_dtype dtype, const void* a, con
                                     as_stream(stream))
                : launch_vjp<float>(a, b, yA_bar, yB_bar, n, ckpt, a_bar, b_bar, accumulate, ws,
                                    as_stream(stream));
+}
+
+extern "C" size_t pvjp_linrec_scan_vjp_noalloc_max_bytes(void) { return kNoAllocScratchBytes; }
+
+extern "C" pvjp_status pvjp_linrec_scan_vjp_noalloc(pvjp_dtype dtype, const void* a, const void* b,
+                                                    const void* yA_bar, const void* yB_bar, int64_t n,
+                                                    const void* ckpt, void* a_bar, void* b_bar, int accumulate,
+                                                    void* stream) {
+    clear_error();
+    PVJP_REQUIRE(valid_dtype(dtype), "pvjp_linrec_scan_vjp_noalloc: unknown dtype %d", (int)dtype);
+    PVJP_REQUIRE(n >= 0 && n <= kMaxScanN, "pvjp_linrec_scan_vjp_noalloc: n = %lld out of range", (long long)n);
+    if (n == 0) return PVJP_OK;
+    PVJP_REQUIRE(a && b && yA_bar && yB_bar && a_bar && b_bar,
+                 "pvjp_linrec_scan_vjp_noalloc: a, b, yA_bar, yB_bar, a_bar, b_bar must be non-NULL");
+    const size_t need = pvjp_linrec_scan_vjp_ws_bytes(dtype, n);
+    if (need > kNoAllocScratchBytes) {
+        set_error("pvjp_linrec_scan_vjp_noalloc: n = %lld needs %zu bytes of scratch, beyond the fixed %zu",
+                  (long long)n, need, kNoAllocScratchBytes);
+        return PVJP_ENOMEM;
+    }
+    hipStream_t st = as_stream(stream);
+    void* ws = nullptr;
+    if (pvjp_status s = scratch_for(st, &ws)) return s;
+    const pvjp_status s =
+        dtype == PVJP_F64 ? launch_vjp<double>(a, b, yA_bar, yB_bar, n, ckpt, a_bar, b_bar, accumulate, ws, st)
+                          : launch_vjp<float>(a, b, yA_bar, yB_bar, n, ckpt, a_bar, b_bar, accumulate, ws, st);
+    return s;
 }
