@@ -270,8 +270,9 @@ def main():
         nb = L.pvjp_hist_ws_bytes(o, capi.F32, N_HIST, m)
         it["ws"] = torch.zeros(nb, dtype=torch.uint8, device=dev)
         it["vsb"] = torch.empty(N_HIST, dtype=torch.float32, device=dev)
-    saved = torch.empty(M_SCAT, dtype=torch.float32, device=dev)
     vsb_s = torch.empty(M_SCAT, dtype=torch.float32, device=dev)
+    plan_nb = L.pvjp_scatter_plan_bytes(capi.F32, N_SCAT, M_SCAT)
+    plan = torch.empty(plan_nb, dtype=torch.uint8, device=dev)
 
     def p(t):
         return None if t is None else t.data_ptr()
@@ -292,11 +293,14 @@ def main():
         calls.append((key, "primal", prim, hist_bytes(it["op"], N_HIST, m), N_HIST))
         calls.append((key, "vjp", vjp, hist_vjp_bytes(it["op"], N_HIST, m), 0))
 
+    # the scatter's forward sweep returns its updates grouped by target window
+    # (the plan, rebuilt every step from `is`), which the return sweep reads
     def sprim():
-        capi.call("pvjp_scatter", capi.F32, p(xs), N_SCAT, p(is_), p(sv), M_SCAT, p(saved), sp)
+        capi.call("pvjp_scatter_planned", capi.F32, p(xs), N_SCAT, p(is_), p(sv), M_SCAT, p(plan), plan_nb, sp)
 
     def svjp():
-        capi.call("pvjp_scatter_vjp", capi.F32, p(ysb), N_SCAT, p(is_), M_SCAT, p(vsb_s), 0, p(xs), p(saved), sp)
+        capi.call("pvjp_scatter_planned_vjp", capi.F32, p(ysb), N_SCAT, M_SCAT, p(vsb_s), 0, p(xs), p(plan),
+                  plan_nb, sp)
 
     calls.append(("scatter_m2^24_n2^26", "primal", sprim, scatter_bytes(M_SCAT), M_SCAT))
     calls.append(("scatter_m2^24_n2^26", "vjp", svjp, scatter_vjp_bytes(M_SCAT), 0))
@@ -354,8 +358,8 @@ def main():
     dom = int(np.argmax(avg))
     dkey, dkind, _, dbytes, _ = calls[dom]
     achieved = dbytes / (avg[dom] * 1e-3) / 1e9
-    kernel_name = {"primal": "hist_acc_kernel" if dkey.startswith("hist") else "scatter_kernel",
-                   "vjp": "hist_vjp" if dkey.startswith("hist") else "scatter_vjp_kernel"}[dkind]
+    kernel_name = {"primal": "pvjp_hist" if dkey.startswith("hist") else "pvjp_scatter_planned",
+                   "vjp": "pvjp_hist_vjp" if dkey.startswith("hist") else "pvjp_scatter_planned_vjp"}[dkind]
     roof = {
         "bound": "hbm",
         "kernel": f"{dkey}:{dkind} ({kernel_name})",
@@ -381,6 +385,16 @@ def main():
             cpu["by_config"] = oracle_by_config()
         except Exception as e:  # report, keep the main line
             cpu["by_config"] = {"error": f"{type(e).__name__}: {e}"}
+
+    # The unplanned scatter pair (one random access per update and array) on
+    # the same inputs, for comparison.
+    saved = torch.empty(M_SCAT, dtype=torch.float32, device=dev)
+    t_up = _events_ms(lambda: capi.call("pvjp_scatter", capi.F32, p(xs), N_SCAT, p(is_), p(sv), M_SCAT, p(saved),
+                                        sp), 10)
+    t_uv = _events_ms(lambda: capi.call("pvjp_scatter_vjp", capi.F32, p(ysb), N_SCAT, p(is_), M_SCAT, p(vsb_s), 0,
+                                        p(xs), p(saved), sp), 10)
+    detail["scatter_m2^24_n2^26"]["unplanned"] = {"primal_ms": round(t_up, 4), "vjp_ms": round(t_uv, 4)}
+    del saved, plan
 
     # Free the histogram/scatter inputs before the other workloads.
     del inst, vs, xs, is_, sv, ysb, calls

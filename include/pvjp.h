@@ -275,6 +275,36 @@ pvjp_status pvjp_scatter_vjp(pvjp_dtype dtype, void* ys_bar, int64_t n, const in
                              int64_t m, void* vs_bar, int accumulate, void* ys,
                              const void* xs_saved, void* stream);
 
+/* Scatter over a target-ordered plan (Sec. 5.3; the forward sweep returns an
+ * auxiliary result besides the scattered array).  Same semantics as
+ * pvjp_scatter / pvjp_scatter_vjp, different memory behaviour: the forward
+ * sweep groups the m updates by window of 32 KiB of the target array (a
+ * two-pass bucket sort) and writes that grouping, together with the
+ * overwritten values, into `plan`; both sweeps then move the target arrays
+ * only as whole windows staged in LDS instead of one random access per
+ * update.  The return sweep reads the plan instead of `is`.
+ *
+ * plan: caller-owned device memory of pvjp_scatter_plan_bytes(dtype, n, m)
+ *   bytes, 256-byte aligned; written by pvjp_scatter_planned, read by
+ *   pvjp_scatter_planned_vjp for the same (dtype, n, m) and unchanged `is`.
+ *   It needs no clearing.  Sizes: n, m < 2^31; n <= 2^31 - 1 for FP32 and
+ *   n <= 2^30 for FP64 (pvjp_scatter_plan_bytes returns 0 outside).
+ * Targets must be unique (repeats race, as for pvjp_scatter); targets
+ * outside [0, n) are dropped: they change nothing and their adjoint is 0. */
+size_t pvjp_scatter_plan_bytes(pvjp_dtype dtype, int64_t n, int64_t m);
+/* In place on xs [n]: xs[is[j]] = vs[j] for j < m; the overwritten values
+ * are kept in the plan. */
+pvjp_status pvjp_scatter_planned(pvjp_dtype dtype, void* xs, int64_t n, const int32_t* is,
+                                 const void* vs, int64_t m, void* plan, size_t plan_bytes,
+                                 void* stream);
+/* Return sweep, in place on ys_bar [n]:
+ *  vs_bar[j] (+)= ys_bar[is[j]], then ys_bar[is[j]] = 0 (ys_bar becomes
+ *  xs_bar); if ys != NULL also ys[is[j]] = the value the forward sweep
+ *  overwrote (restores xs in place).  vs_bar [m]. */
+pvjp_status pvjp_scatter_planned_vjp(pvjp_dtype dtype, void* ys_bar, int64_t n, int64_t m,
+                                     void* vs_bar, int accumulate, void* ys, const void* plan,
+                                     size_t plan_bytes, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* map (Sec. 5.4): y_i = f(x_i); the VJP recomputes f's intermediates inside  */
 /* the lambda instead of reading them from memory (Sec. 4.1).                  */

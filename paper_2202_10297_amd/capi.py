@@ -54,6 +54,9 @@ SIGNATURES = {
     "pvjp_hist_vjp": (_I, [_I, _I, _P, _P, _L, _L, _P, _P, _P, _P, _P, _I, _P]),
     "pvjp_scatter": (_I, [_I, _P, _L, _P, _P, _L, _P, _P]),
     "pvjp_scatter_vjp": (_I, [_I, _P, _L, _P, _L, _P, _I, _P, _P, _P]),
+    "pvjp_scatter_plan_bytes": (_Z, [_I, _L, _L]),
+    "pvjp_scatter_planned": (_I, [_I, _P, _L, _P, _P, _L, _P, _Z, _P]),
+    "pvjp_scatter_planned_vjp": (_I, [_I, _P, _L, _L, _P, _I, _P, _P, _Z, _P]),
     "pvjp_map": (_I, [_I, _I, _P, _L, _P, _P]),
     "pvjp_map_vjp": (_I, [_I, _I, _P, _P, _L, _P, _I, _P]),
     "pvjp_fig1": (_I, [_I, _P, _P, _L, _P, _P, _P]),

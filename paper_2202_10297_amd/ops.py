@@ -365,6 +365,45 @@ def scatter_vjp_(ys_bar, is_, vs_bar=None, accumulate=False, ys=None, xs_saved=N
     return vs_bar
 
 
+def scatter_plan_bytes(dtype, n: int, m: int) -> int:
+    return capi.lib().pvjp_scatter_plan_bytes(_DT[dtype], int(n), int(m))
+
+
+def scatter_planned_(xs: torch.Tensor, is_: torch.Tensor, vs: torch.Tensor, plan=None):
+    """In place on xs; returns the plan (the forward sweep's target-ordered
+    auxiliary result, holding the overwritten values) for
+    scatter_planned_vjp_."""
+    if is_.dtype != torch.int32:
+        raise TypeError("is_ must be int32")
+    if vs.dtype != xs.dtype or vs.numel() != is_.numel():
+        raise ValueError("vs must have the dtype of xs and one value per target")
+    n, m = xs.numel(), is_.numel()
+    nb = scatter_plan_bytes(xs.dtype, n, m)
+    if nb == 0:
+        raise ValueError(f"scatter plan: n = {n}, m = {m} out of range")
+    if plan is None or plan.numel() < nb:
+        buf = torch.empty(nb + 256, dtype=torch.uint8, device=xs.device)
+        off = (-buf.data_ptr()) % 256
+        plan = buf[off:off + nb]
+    _check_targets(is_, n)
+    _check_values(vs)
+    capi.call("pvjp_scatter_planned", _dt(xs), _ptr(xs), n, _ptr(is_), _ptr(vs), m, _ptr(plan), plan.numel(),
+              _stream(xs.device))
+    return plan
+
+
+def scatter_planned_vjp_(ys_bar, m: int, plan, vs_bar=None, accumulate=False, ys=None):
+    """In place on ys_bar (which becomes xs_bar); restores ys if given."""
+    n = ys_bar.numel()
+    if vs_bar is None:
+        vs_bar = (torch.zeros if accumulate else torch.empty)(m, dtype=ys_bar.dtype, device=ys_bar.device)
+    if ys is not None and (ys.dtype != ys_bar.dtype or ys.numel() != n):
+        raise ValueError("ys must have the dtype and size of ys_bar")
+    capi.call("pvjp_scatter_planned_vjp", _dt(ys_bar), _ptr(ys_bar), n, int(m), _ptr(vs_bar), int(accumulate),
+              _ptr(ys), _ptr(plan), plan.numel(), _stream(ys_bar.device))
+    return vs_bar
+
+
 # --------------------------------------------------------------------- map
 def map_(fn, x):
     y = torch.empty_like(x)
