@@ -390,12 +390,22 @@ __global__ __launch_bounds__(512) void sp_apply_fwd_kernel(T* __restrict__ xs, i
     for (int i = threadIdx.x; i < len; i += blockDim.x) xs[x0 + i] = lx[i];
 }
 
+// The random writes of vs_bar are issued after the block's last barrier, so
+// that they drain while the next window's loads run instead of holding the
+// barrier: each thread keeps the (j, g) of its first kSpHeld rounds of
+// records in registers (a window holds at most 2^s0 unique targets; rounds
+// beyond kSpHeld, possible only with more than kSpHeld * 512 records, write
+// at once).
+constexpr int kSpVjpBlock = 512;
+constexpr int kSpHeld = 8;
+
 template <class T, bool ACC, bool RESTORE>
-__global__ __launch_bounds__(512) void sp_apply_vjp_kernel(T* __restrict__ ybar, T* __restrict__ ys, int64_t n,
-                                                           int s0, const int32_t* __restrict__ wstart,
-                                                           const int32_t* __restrict__ rk,
-                                                           const int32_t* __restrict__ rj,
-                                                           const T* __restrict__ saved, T* __restrict__ vbar) {
+__global__ __launch_bounds__(kSpVjpBlock) void sp_apply_vjp_kernel(T* __restrict__ ybar, T* __restrict__ ys, int64_t n,
+                                                                   int s0, const int32_t* __restrict__ wstart,
+                                                                   const int32_t* __restrict__ rk,
+                                                                   const int32_t* __restrict__ rj,
+                                                                   const T* __restrict__ saved,
+                                                                   T* __restrict__ vbar) {
     __shared__ T ly[kSpWindowBytes / sizeof(T)];
     __shared__ T lys[RESTORE ? kSpWindowBytes / sizeof(T) : 1];
     const int w = blockIdx.x;
@@ -403,12 +413,27 @@ __global__ __launch_bounds__(512) void sp_apply_vjp_kernel(T* __restrict__ ybar,
     if (r0 >= r1) return;
     const int64_t x0 = (int64_t)w << s0;
     const int len = (int)((n - x0) < ((int64_t)1 << s0) ? (n - x0) : ((int64_t)1 << s0));
-    for (int i = threadIdx.x; i < len; i += blockDim.x) {
+    for (int i = threadIdx.x; i < len; i += kSpVjpBlock) {
         ly[i] = ybar[x0 + i];
         if (RESTORE) lys[i] = ys[x0 + i];
     }
     __syncthreads();
-    for (int r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+    int32_t hj[kSpHeld];
+    T hg[kSpHeld];
+#pragma unroll
+    for (int t = 0; t < kSpHeld; ++t) {
+        const int r = r0 + t * kSpVjpBlock + (int)threadIdx.x;
+        hj[t] = -1;
+        hg[t] = T(0);
+        if (r < r1) {
+            const int kl = (int)(rk[r] - x0);
+            hj[t] = rj[r];
+            hg[t] = ly[kl];
+            ly[kl] = T(0);
+            if (RESTORE) lys[kl] = saved[r];
+        }
+    }
+    for (int r = r0 + kSpHeld * kSpVjpBlock + (int)threadIdx.x; r < r1; r += kSpVjpBlock) {
         const int kl = (int)(rk[r] - x0);
         const int32_t j = rj[r];
         const T g = ly[kl];
@@ -417,10 +442,13 @@ __global__ __launch_bounds__(512) void sp_apply_vjp_kernel(T* __restrict__ ybar,
         vbar[j] = ACC ? vbar[j] + g : g;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < len; i += blockDim.x) {
+    for (int i = threadIdx.x; i < len; i += kSpVjpBlock) {
         ybar[x0 + i] = ly[i];
         if (RESTORE) ys[x0 + i] = lys[i];
     }
+#pragma unroll
+    for (int t = 0; t < kSpHeld; ++t)
+        if (hj[t] >= 0) vbar[hj[t]] = ACC ? vbar[hj[t]] + hg[t] : hg[t];
 }
 
 // Without accumulate, updates whose target was out of range get adjoint 0;
@@ -554,7 +582,7 @@ static void sp_vjp(T* ybar, int64_t n, int64_t m, T* vbar, int acc, T* ys, const
     const int32_t* rj = (const int32_t*)(p + L.rj);
     const T* saved = (const T*)(p + L.saved);
     if (!acc) hipLaunchKernelGGL(sp_clear_kernel<T>, dim3(flat_grid(m, 256, 8)), dim3(256), 0, st, vbar, m, total);
-    const dim3 g((unsigned)L.nw), b(512);
+    const dim3 g((unsigned)L.nw), b(kSpVjpBlock);
     if (acc) {
         if (ys)
             hipLaunchKernelGGL((sp_apply_vjp_kernel<T, true, true>), g, b, 0, st, ybar, ys, n, L.s0, wstart, rk, rj, saved, vbar);
