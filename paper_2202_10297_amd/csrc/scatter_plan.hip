@@ -23,6 +23,8 @@
 // Targets must be unique (the paper's assumption); repeated targets race.
 // Targets outside [0, n) are dropped from the plan: they change nothing and
 // their adjoint is 0.
+#include <type_traits>
+
 #include "common.h"
 #include "prims.h"
 
@@ -368,18 +370,47 @@ __global__ __launch_bounds__(256) void sp_wstart_kernel(int nc, const int32_t* _
 }
 
 // ------------------------------------------------------- window sweeps
+// Copies of a window between device memory and LDS: 16-byte vectors when the
+// window is whole and the array 16-byte aligned (vec != 0), else elements.
 template <class T>
-__global__ __launch_bounds__(512) void sp_apply_fwd_kernel(T* __restrict__ xs, int64_t n, int s0,
+using Vec16 = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+
+template <class T, int B>
+__device__ __forceinline__ void sp_win_load(T* __restrict__ l, const T* __restrict__ g, int len, bool whole) {
+    if (whole) {
+        constexpr int E = 16 / sizeof(T);
+        const Vec16<T>* gv = reinterpret_cast<const Vec16<T>*>(g);
+        Vec16<T>* lv = reinterpret_cast<Vec16<T>*>(l);
+        for (int i = threadIdx.x; i < len / E; i += B) lv[i] = gv[i];
+    } else {
+        for (int i = threadIdx.x; i < len; i += B) l[i] = g[i];
+    }
+}
+
+template <class T, int B>
+__device__ __forceinline__ void sp_win_store(T* __restrict__ g, const T* __restrict__ l, int len, bool whole) {
+    if (whole) {
+        constexpr int E = 16 / sizeof(T);
+        Vec16<T>* gv = reinterpret_cast<Vec16<T>*>(g);
+        const Vec16<T>* lv = reinterpret_cast<const Vec16<T>*>(l);
+        for (int i = threadIdx.x; i < len / E; i += B) gv[i] = lv[i];
+    } else {
+        for (int i = threadIdx.x; i < len; i += B) g[i] = l[i];
+    }
+}
+template <class T>
+__global__ __launch_bounds__(512) void sp_apply_fwd_kernel(T* __restrict__ xs, int64_t n, int s0, int vec,
                                                            const int32_t* __restrict__ wstart,
                                                            const int32_t* __restrict__ rk, const T* __restrict__ rv,
                                                            T* __restrict__ saved) {
-    __shared__ T lx[kSpWindowBytes / sizeof(T)];
+    __shared__ __align__(16) T lx[kSpWindowBytes / sizeof(T)];
     const int w = blockIdx.x;
     const int r0 = wstart[w], r1 = wstart[w + 1];
     if (r0 >= r1) return;
     const int64_t x0 = (int64_t)w << s0;
     const int len = (int)((n - x0) < ((int64_t)1 << s0) ? (n - x0) : ((int64_t)1 << s0));
-    for (int i = threadIdx.x; i < len; i += blockDim.x) lx[i] = xs[x0 + i];
+    const bool whole = vec && len == (1 << s0);
+    sp_win_load<T, 512>(lx, xs + x0, len, whole);
     __syncthreads();
     for (int r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
         const int kl = (int)(rk[r] - x0);
@@ -387,7 +418,7 @@ __global__ __launch_bounds__(512) void sp_apply_fwd_kernel(T* __restrict__ xs, i
         lx[kl] = rv[r];
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < len; i += blockDim.x) xs[x0 + i] = lx[i];
+    sp_win_store<T, 512>(xs + x0, lx, len, whole);
 }
 
 // The random writes of vs_bar are issued after the block's last barrier, so
@@ -401,22 +432,21 @@ constexpr int kSpHeld = 8;
 
 template <class T, bool ACC, bool RESTORE>
 __global__ __launch_bounds__(kSpVjpBlock) void sp_apply_vjp_kernel(T* __restrict__ ybar, T* __restrict__ ys, int64_t n,
-                                                                   int s0, const int32_t* __restrict__ wstart,
+                                                                   int s0, int vec, const int32_t* __restrict__ wstart,
                                                                    const int32_t* __restrict__ rk,
                                                                    const int32_t* __restrict__ rj,
                                                                    const T* __restrict__ saved,
                                                                    T* __restrict__ vbar) {
-    __shared__ T ly[kSpWindowBytes / sizeof(T)];
-    __shared__ T lys[RESTORE ? kSpWindowBytes / sizeof(T) : 1];
+    __shared__ __align__(16) T ly[kSpWindowBytes / sizeof(T)];
+    __shared__ __align__(16) T lys[RESTORE ? kSpWindowBytes / sizeof(T) : 2];
     const int w = blockIdx.x;
     const int r0 = wstart[w], r1 = wstart[w + 1];
     if (r0 >= r1) return;
     const int64_t x0 = (int64_t)w << s0;
     const int len = (int)((n - x0) < ((int64_t)1 << s0) ? (n - x0) : ((int64_t)1 << s0));
-    for (int i = threadIdx.x; i < len; i += kSpVjpBlock) {
-        ly[i] = ybar[x0 + i];
-        if (RESTORE) lys[i] = ys[x0 + i];
-    }
+    const bool whole = vec && len == (1 << s0);
+    sp_win_load<T, kSpVjpBlock>(ly, ybar + x0, len, whole);
+    if (RESTORE) sp_win_load<T, kSpVjpBlock>(lys, ys + x0, len, whole);
     __syncthreads();
     int32_t hj[kSpHeld];
     T hg[kSpHeld];
@@ -442,10 +472,8 @@ __global__ __launch_bounds__(kSpVjpBlock) void sp_apply_vjp_kernel(T* __restrict
         vbar[j] = ACC ? vbar[j] + g : g;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < len; i += kSpVjpBlock) {
-        ybar[x0 + i] = ly[i];
-        if (RESTORE) ys[x0 + i] = lys[i];
-    }
+    sp_win_store<T, kSpVjpBlock>(ybar + x0, ly, len, whole);
+    if (RESTORE) sp_win_store<T, kSpVjpBlock>(ys + x0, lys, len, whole);
 #pragma unroll
     for (int t = 0; t < kSpHeld; ++t)
         if (hj[t] >= 0) vbar[hj[t]] = ACC ? vbar[hj[t]] + hg[t] : hg[t];
@@ -568,7 +596,8 @@ static pvjp_status sp_forward(T* xs, int64_t n, const int32_t* is, const T* vs, 
     hipLaunchKernelGGL(sp_wstart_kernel, dim3(flat_grid(L.nw + 1, 256, 1)), dim3(256), 0, st, L.nc,
                        (const int32_t*)cstart, (const int32_t*)nch2, (const int32_t*)chb2, (const int32_t*)cnt2, wstart);
     // the window sweep
-    hipLaunchKernelGGL(sp_apply_fwd_kernel<T>, dim3((unsigned)L.nw), dim3(512), 0, st, xs, n, L.s0,
+    const int vec = aligned(xs, 16) ? 1 : 0;
+    hipLaunchKernelGGL(sp_apply_fwd_kernel<T>, dim3((unsigned)L.nw), dim3(512), 0, st, xs, n, L.s0, vec,
                        (const int32_t*)wstart, (const int32_t*)rk, (const T*)rv, saved);
     return PVJP_OK;
 }
@@ -583,16 +612,17 @@ static void sp_vjp(T* ybar, int64_t n, int64_t m, T* vbar, int acc, T* ys, const
     const T* saved = (const T*)(p + L.saved);
     if (!acc) hipLaunchKernelGGL(sp_clear_kernel<T>, dim3(flat_grid(m, 256, 8)), dim3(256), 0, st, vbar, m, total);
     const dim3 g((unsigned)L.nw), b(kSpVjpBlock);
+    const int vec = aligned(ybar, 16) && (ys == nullptr || aligned(ys, 16)) ? 1 : 0;
     if (acc) {
         if (ys)
-            hipLaunchKernelGGL((sp_apply_vjp_kernel<T, true, true>), g, b, 0, st, ybar, ys, n, L.s0, wstart, rk, rj, saved, vbar);
+            hipLaunchKernelGGL((sp_apply_vjp_kernel<T, true, true>), g, b, 0, st, ybar, ys, n, L.s0, vec, wstart, rk, rj, saved, vbar);
         else
-            hipLaunchKernelGGL((sp_apply_vjp_kernel<T, true, false>), g, b, 0, st, ybar, ys, n, L.s0, wstart, rk, rj, saved, vbar);
+            hipLaunchKernelGGL((sp_apply_vjp_kernel<T, true, false>), g, b, 0, st, ybar, ys, n, L.s0, vec, wstart, rk, rj, saved, vbar);
     } else {
         if (ys)
-            hipLaunchKernelGGL((sp_apply_vjp_kernel<T, false, true>), g, b, 0, st, ybar, ys, n, L.s0, wstart, rk, rj, saved, vbar);
+            hipLaunchKernelGGL((sp_apply_vjp_kernel<T, false, true>), g, b, 0, st, ybar, ys, n, L.s0, vec, wstart, rk, rj, saved, vbar);
         else
-            hipLaunchKernelGGL((sp_apply_vjp_kernel<T, false, false>), g, b, 0, st, ybar, ys, n, L.s0, wstart, rk, rj, saved, vbar);
+            hipLaunchKernelGGL((sp_apply_vjp_kernel<T, false, false>), g, b, 0, st, ybar, ys, n, L.s0, vec, wstart, rk, rj, saved, vbar);
     }
 }
 
