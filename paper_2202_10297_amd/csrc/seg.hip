@@ -7,17 +7,27 @@
 //    concatenation with the segmented operator (a flag restarts the
 //    recurrence at each segment head), writing per-segment results and
 //    checkpoints every PVJP_LINREC_CKPT_INTERVAL global elements.
-//  - Return sweep (seg_batch_vjp): one persistent launch.  Blocks take
-//    tickets from a queue holding first every scan tile in reverse order,
-//    then every sum-reduce tile.  For a scan tile the lin_o reversed scan
-//    needs no flag at all: the last element of each segment has no successor
-//    in its segment, so its c_i is 0, which cuts the carry exactly as the
-//    end of the array does.  The primal prefixes are recomputed from the
-//    checkpoint with the segmented operator.  A sum-reduce tile writes
-//    x_bar_i = y_bar[segment of i] (reduce(+)'s adjoint, Sec. 5.1.1).
+//  - Return sweep (seg_batch_vjp): one persistent launch over a queue of
+//    work items: first the scan's tile chains, longest first, then every
+//    sum-reduce tile.  The lin_o reversed scan needs no flag: the last
+//    element of each segment has no successor in its segment, so its c_i is
+//    0, which cuts the carry exactly as the end of the array does.  So a
+//    tile holding a segment end (a "cut tile") passes to its left a carry
+//    that is its own aggregate, whatever lies to its right.  The tiles split
+//    into chains: from just left of one cut tile down to the previous cut
+//    tile included (the segment table fixes them when the batch is
+//    prepared).  A chain's block first folds the cut tile at its right end
+//    into its carry (one read of that tile's a and y_bar), then walks the
+//    chain right to left, handing the carry from tile to tile in registers:
+//    no tile ever waits on another block.  The
+//    primal prefixes are recomputed from the checkpoint with the segmented
+//    operator.  A sum-reduce tile writes x_bar_i = y_bar[segment of i]
+//    (reduce(+)'s adjoint, Sec. 5.1.1).
 //
 // Segment heads of a tile come from an LDS bitmap built from the tile's first
 // segment (a table written once by pvjp_seg_prepare) and the segment offsets.
+#include <algorithm>
+#include <utility>
 #include <vector>
 
 #include "common.h"
@@ -34,9 +44,12 @@ static_assert(sizeof(TileState<SegLinRec<double>::S>) == kSegState && sizeof(Til
               "tile states of both sweeps share one slot per tile");
 
 // Workspace: [LookbackHdr | tile and group states (128 B each) |
-//             tile_seg0 int32[ntiles+1] | offsets int64[nseg+1]]
+//             tile_seg0 int32[ntiles+1] | offsets int64[nseg+1] |
+//             chain count int32 | chains int32[3 * (ntiles + 1)] (right-end
+//             tile, number of tiles, cut tile folded into the initial carry
+//             or -1; longest first)]
 struct SegLayout {
-    size_t states, seg0, offs, total;
+    size_t states, seg0, offs, nchain, chains, total;
     int64_t ntiles;
 };
 
@@ -46,7 +59,9 @@ static SegLayout seg_layout(int64_t total, int64_t nseg, int ts) {
     L.states = sizeof(LookbackHdr);
     L.seg0 = L.states + align_up((size_t)(L.ntiles + lookback_groups(L.ntiles)) * kSegState, 256);
     L.offs = L.seg0 + align_up((size_t)(L.ntiles + 1) * 4, 256);
-    L.total = L.offs + align_up((size_t)(nseg + 1) * 8, 256);
+    L.nchain = L.offs + align_up((size_t)(nseg + 1) * 8, 256);
+    L.chains = L.nchain + 256;
+    L.total = L.chains + align_up((size_t)(L.ntiles + 1) * 12, 256);
     return L;
 }
 
@@ -118,14 +133,17 @@ __global__ __launch_bounds__(kSegBlock) void seg_linrec_fwd_kernel(
     for (int j = 1; j < IPT; ++j) agg = Op::comb(agg, e[j]);
     S tot;
     S excl = block_exclusive_scan<Op, kSegBlock, false>(agg, tot, wtot);
+    // A tile holding a segment head restarts the recurrence: its inclusive
+    // state is its aggregate, published at once, and only the elements before
+    // its first head take the prefix of the tiles to the left (none when the
+    // tile starts with a head).
     if (threadIdx.x < kWave) {
         S prefix = Op::id();
-        if (tile == 0) {
-            if (threadIdx.x == 0) publish(&states[tile], tot, kInc, tag);
-        } else {
-            if (threadIdx.x == 0) publish(&states[tile], tot, kAgg, tag);
+        const bool early_inc = tile == 0 || tot.f != 0u;
+        if (threadIdx.x == 0) publish(&states[tile], tot, early_inc ? kInc : kAgg, tag);
+        if (tile > 0 && !bit_at(bits, 0)) {
             prefix = lookback<Op>(states, states + ntiles, tile, tot, tag, hdr);
-            if (threadIdx.x == 0) publish(&states[tile], Op::comb(prefix, tot), kInc, tag);
+            if (!early_inc && threadIdx.x == 0) publish(&states[tile], Op::comb(prefix, tot), kInc, tag);
         }
         if (threadIdx.x == 0) s_prefix = prefix;
     }
@@ -149,21 +167,23 @@ __global__ __launch_bounds__(kSegBlock) void seg_linrec_fwd_kernel(
 }
 
 // ----------------------------------------------------------- return sweep
+// One scan tile of a chain: `carry` is the inclusive lin_o state of the tile
+// to its right (the neutral element at the chain's right end); returns this
+// tile's inclusive state (valid in every thread), the next tile's carry.
 template <class T, int IPT, bool ACC>
-__device__ __forceinline__ void seg_scan_vjp_tile(const T* __restrict__ a, const T* __restrict__ b,
-                                                  const T* __restrict__ ya, const T* __restrict__ yb,
-                                                  int64_t total, const T* __restrict__ ckpt, T* __restrict__ abar,
-                                                  T* __restrict__ bbar, LookbackHdr* hdr,
-                                                  TileState<typename LinO<T>::S>* states, int64_t ntiles,
-                                                  int64_t v, uint32_t tag, T* lds, const uint32_t* bits,
-                                                  typename SegLinRec<T>::S* wtot_p, typename LinO<T>::S* wtot_l,
-                                                  typename LinO<T>::S* s_suffix) {
+__device__ __forceinline__ typename LinO<T>::S seg_scan_vjp_tile(const T* __restrict__ a, const T* __restrict__ b,
+                                                                 const T* __restrict__ ya, const T* __restrict__ yb,
+                                                                 int64_t total, const T* __restrict__ ckpt,
+                                                                 T* __restrict__ abar, T* __restrict__ bbar,
+                                                                 int64_t tile, typename LinO<T>::S carry, T* lds,
+                                                                 const uint32_t* bits,
+                                                                 typename SegLinRec<T>::S* wtot_p,
+                                                                 typename LinO<T>::S* wtot_l) {
     using P = SegLinRec<T>;
     using L = LinO<T>;
     using PS = typename P::S;
     using LS = typename L::S;
     constexpr int TS = kSegBlock * IPT;
-    const int64_t tile = ntiles - 1 - v;  // virtual order runs right to left
     const int64_t base = tile * TS;
     const int cnt = (int)((total - base) < TS ? (total - base) : TS);
     const int first = (int)threadIdx.x * IPT;
@@ -193,22 +213,22 @@ __device__ __forceinline__ void seg_scan_vjp_tile(const T* __restrict__ a, const
     // 1. primal prefixes (A_{i-1}, B_{i-1}) within each segment
     T pA[IPT], pB[IPT];
     {
-        PS e[IPT];
+        PS pe[IPT];
 #pragma unroll
-        for (int j = 0; j < IPT; ++j) e[j] = PS{ra[j], rb[j], (uint32_t)bit_at(bits, first + j), 0u};
-        PS agg = e[0];
+        for (int j = 0; j < IPT; ++j) pe[j] = PS{ra[j], rb[j], (uint32_t)bit_at(bits, first + j), 0u};
+        PS pagg = pe[0];
 #pragma unroll
-        for (int j = 1; j < IPT; ++j) agg = P::comb(agg, e[j]);
-        PS tot;
-        PS excl = block_exclusive_scan<P, kSegBlock, false>(agg, tot, wtot_p);
+        for (int j = 1; j < IPT; ++j) pagg = P::comb(pagg, pe[j]);
+        PS ptot;
+        PS pexcl = block_exclusive_scan<P, kSegBlock, false>(pagg, ptot, wtot_p);
         const int64_t c = base / kSegCk;
-        PS run = P::comb(PS{ckpt[2 * c], ckpt[2 * c + 1], 0u, 0u}, excl);
+        PS run = P::comb(PS{ckpt[2 * c], ckpt[2 * c + 1], 0u, 0u}, pexcl);
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
-            const bool head = e[j].f != 0u;
+            const bool head = pe[j].f != 0u;
             pA[j] = head ? T(1) : run.a;
             pB[j] = head ? T(0) : run.b;
-            run = P::comb(run, e[j]);
+            run = P::comb(run, pe[j]);
         }
     }
     // 2. lin_o elements: c_i = a_{i+1}, or 0 when i ends its segment
@@ -218,26 +238,14 @@ __device__ __forceinline__ void seg_scan_vjp_tile(const T* __restrict__ a, const
         const bool last = bit_at(bits, first + j + 1);
         e[j] = LS{last ? T(0) : rc[j], rya[j], ryb[j]};
     }
-    // 3. reversed scan with lookback over the tiles to the right
+    // 3. reversed scan inside the tile, after the carry from the right
     LS agg = L::id();
 #pragma unroll
     for (int j = IPT - 1; j >= 0; --j) agg = L::comb(agg, e[j]);
     LS tot;
     LS excl = block_exclusive_scan<L, kSegBlock, true>(agg, tot, wtot_l);
-    if (threadIdx.x < kWave) {
-        LS suffix = L::id();
-        if (v == 0) {
-            if (threadIdx.x == 0) publish(&states[v], tot, kInc, tag);
-        } else {
-            if (threadIdx.x == 0) publish(&states[v], tot, kAgg, tag);
-            suffix = lookback<L>(states, states + ntiles, v, tot, tag, hdr);
-            if (threadIdx.x == 0) publish(&states[v], L::comb(suffix, tot), kInc, tag);
-        }
-        if (threadIdx.x == 0) *s_suffix = suffix;
-    }
-    __syncthreads();
     // 4. input adjoints
-    LS run = L::comb(*s_suffix, excl);
+    LS run = L::comb(carry, excl);
 #pragma unroll
     for (int j = IPT - 1; j >= 0; --j) {
         run = L::comb(run, e[j]);
@@ -246,6 +254,7 @@ __device__ __forceinline__ void seg_scan_vjp_tile(const T* __restrict__ a, const
     }
     store_blocked<T, kSegBlock, IPT, ACC>(abar + base, cnt, ra, lds);
     store_blocked<T, kSegBlock, IPT, ACC>(bbar + base, cnt, rb, lds);
+    return L::comb(carry, tot);
 }
 
 template <class T, int IPT, bool ACC>
@@ -273,43 +282,90 @@ __device__ __forceinline__ void seg_sum_vjp_tile(int64_t total, const int32_t* _
     store_blocked<T, kSegBlock, IPT, ACC>(xbar + base, cnt, out, lds);
 }
 
+// The lin_o aggregate of one tile (c_i = a_{i+1}, 0 at segment ends; d_i =
+// y_bar_i), folded right to left; valid in every thread.
+template <class T, int IPT>
+__device__ __forceinline__ typename LinO<T>::S seg_tile_linagg(const T* __restrict__ a, const T* __restrict__ ya,
+                                                               const T* __restrict__ yb, int64_t total, int64_t tile,
+                                                               T* lds, const uint32_t* bits,
+                                                               typename LinO<T>::S* wtot_l) {
+    using L = LinO<T>;
+    using LS = typename L::S;
+    constexpr int TS = kSegBlock * IPT;
+    const int64_t base = tile * TS;
+    const int cnt = (int)((total - base) < TS ? (total - base) : TS);
+    const int first = (int)threadIdx.x * IPT;
+    T ra[IPT], rc[IPT], rya[IPT], ryb[IPT];
+    {
+        T sa[IPT], sya[IPT], syb[IPT];
+        load_striped<T, kSegBlock, IPT>(a + base, cnt, sa, T(1));
+        load_striped<T, kSegBlock, IPT>(ya + base, cnt, sya, T(0));
+        load_striped<T, kSegBlock, IPT>(yb + base, cnt, syb, T(0));
+        const T after = ((int)threadIdx.x == kSegBlock - 1 && base + TS < total) ? a[base + TS] : T(1);
+        striped_to_blocked<T, kSegBlock, IPT>(sa, ra, lds);
+        const T nxt = ((int)threadIdx.x < kSegBlock - 1) ? lds[lds_pad<T>(first + IPT)] : after;
+#pragma unroll
+        for (int j = 0; j < IPT - 1; ++j) rc[j] = ra[j + 1];
+        rc[IPT - 1] = nxt;
+        __syncthreads();
+        striped_to_blocked<T, kSegBlock, IPT>(sya, rya, lds);
+        __syncthreads();
+        striped_to_blocked<T, kSegBlock, IPT>(syb, ryb, lds);
+    }
+    LS agg = L::id();
+#pragma unroll
+    for (int j = IPT - 1; j >= 0; --j) {
+        const bool last = bit_at(bits, first + j + 1);
+        agg = L::comb(agg, LS{last ? T(0) : rc[j], rya[j], ryb[j]});
+    }
+    LS tot;
+    (void)block_exclusive_scan<L, kSegBlock, true>(agg, tot, wtot_l);
+    return tot;
+}
+
 template <class T, int IPT, bool ACC>
 __global__ __launch_bounds__(kSegBlock) void seg_batch_vjp_kernel(
     const T* __restrict__ a, const T* __restrict__ b, const T* __restrict__ ya, const T* __restrict__ yb,
     int64_t total, int64_t nseg, const int64_t* __restrict__ offs, const int32_t* __restrict__ seg0,
     const T* __restrict__ ckpt, T* __restrict__ abar, T* __restrict__ bbar, const T* __restrict__ sum_ybar,
-    T* __restrict__ sum_xbar, LookbackHdr* hdr, TileState<typename LinO<T>::S>* states, int64_t ntiles,
-    int64_t nscan, int64_t nsum) {
+    T* __restrict__ sum_xbar, LookbackHdr* hdr, const int32_t* __restrict__ nchain_p,
+    const int32_t* __restrict__ chains, int64_t ntiles, int scan, int64_t nsum) {
     constexpr int TS = kSegBlock * IPT;
     __shared__ T lds[lds_elems<T, TS>()];
     __shared__ typename SegLinRec<T>::S wtot_p[kSegBlock / kWave];
     __shared__ typename LinO<T>::S wtot_l[kSegBlock / kWave];
     __shared__ IntSum::S wtot_i[kSegBlock / kWave];
-    __shared__ typename LinO<T>::S s_suffix;
     __shared__ uint32_t bits[(TS + 1 + 31) / 32];
-    __shared__ uint32_t s_tag, s_ticket;
+    __shared__ uint32_t s_ticket;
 
+    const int64_t nscan = scan ? (int64_t)*nchain_p : 0;
     // every block makes one final, empty draw: the launch's last ticket
     const uint32_t last = (uint32_t)(nscan + nsum + gridDim.x - 1);
     if (threadIdx.x == 0) {
-        s_ticket = lookback_draw(hdr, last, &s_tag);
+        s_ticket = lookback_draw(hdr, last, nullptr);
         if (s_ticket > last) lookback_error(hdr, kErrTicket);
     }
     __syncthreads();
-    const uint32_t tag = s_tag;
     if (s_ticket > last) return;  // the workspace was not in its rest state: do nothing
-    // Queue: items [0, nscan) are the scan tiles in reverse order, items
-    // [nscan, nscan + nsum) the sum tiles.  A block only waits (in the
-    // lookback) on scan items dequeued before its own, which running blocks
-    // hold, so the loop always drains.
+    // Queue: items [0, nscan) are the scan's tile chains (longest first),
+    // items [nscan, nscan + nsum) the sum tiles.  No item waits on another.
     while (true) {
         const int64_t item = s_ticket;
         if (item >= nscan + nsum) break;
         if (item < nscan) {
-            const int64_t tile = ntiles - 1 - item;  // reverse order inside the scan part
-            build_heads<TS>(bits, seg0, offs, nseg, tile, tile * TS);
-            seg_scan_vjp_tile<T, IPT, ACC>(a, b, ya, yb, total, ckpt, abar, bbar, hdr, states, ntiles, item, tag, lds,
-                                           bits, wtot_p, wtot_l, &s_suffix);
+            const int64_t t1 = chains[3 * item], len = chains[3 * item + 1], cut = chains[3 * item + 2];
+            typename LinO<T>::S carry = LinO<T>::id();
+            if (cut >= 0) {  // the cut tile right of the chain: its aggregate is the carry
+                build_heads<TS>(bits, seg0, offs, nseg, cut, cut * TS);
+                carry = seg_tile_linagg<T, IPT>(a, ya, yb, total, cut, lds, bits, wtot_l);
+                __syncthreads();
+            }
+            for (int64_t t = t1; t > t1 - len; --t) {
+                build_heads<TS>(bits, seg0, offs, nseg, t, t * TS);
+                carry = seg_scan_vjp_tile<T, IPT, ACC>(a, b, ya, yb, total, ckpt, abar, bbar, t, carry, lds, bits,
+                                                       wtot_p, wtot_l);
+                __syncthreads();
+            }
         } else {
             const int64_t tile = item - nscan;
             build_heads<TS>(bits, seg0, offs, nseg, tile, tile * TS);
@@ -340,8 +396,8 @@ static void launch_batch(const void* a, const void* b, const void* ya, const voi
     hipLaunchKernelGGL((seg_batch_vjp_kernel<T, IPT, ACC>), dim3((unsigned)grid), dim3(kSegBlock), 0, st, (const T*)a,
                        (const T*)b, (const T*)ya, (const T*)yb, total, nseg, (const int64_t*)(ws + L.offs),
                        (const int32_t*)(ws + L.seg0), (const T*)ckpt, (T*)abar, (T*)bbar, (const T*)sy, (T*)sx,
-                       (LookbackHdr*)ws, (TileState<typename LinO<T>::S>*)(ws + L.states), L.ntiles,
-                       a ? L.ntiles : 0, sy ? L.ntiles : 0);
+                       (LookbackHdr*)ws, (const int32_t*)(ws + L.nchain), (const int32_t*)(ws + L.chains), L.ntiles,
+                       a ? 1 : 0, sy ? L.ntiles : 0);
 }
 
 template <class T, bool ACC>
@@ -390,10 +446,39 @@ extern "C" pvjp_status pvjp_seg_prepare(const int64_t* host_offsets, int64_t nse
         seg0[(size_t)t] = (int32_t)s;
     }
     seg0[(size_t)L.ntiles] = (int32_t)nseg;
+    // Tile chains of the return sweep.  A cut tile holds a segment end (the
+    // last tile holds the end of the data); with the cut tiles c_0 < ... <
+    // c_K, chain k covers tiles c_{k-1} .. c_k - 1 (0 .. c_0 - 1 for k = 0)
+    // and starts from the carry of c_k's aggregate; a last chain holds c_K
+    // alone with the neutral carry.  Longest first, so the queue's tail
+    // holds short work.
+    std::vector<char> cutv((size_t)L.ntiles, 0);
+    for (int64_t s2 = 1; s2 <= nseg; ++s2) cutv[(size_t)((host_offsets[s2] - 1) / tile_elems)] = 1;
+    struct Chain {
+        int32_t len, right, cut;
+    };
+    std::vector<Chain> ch;
+    {
+        int64_t prev = -1;  // previous cut tile (-1: none)
+        for (int64_t t = 0; t < L.ntiles; ++t) {
+            if (!cutv[(size_t)t]) continue;
+            const int64_t left = prev < 0 ? 0 : prev;
+            if (t - 1 >= left) ch.push_back(Chain{(int32_t)(t - left), (int32_t)(t - 1), (int32_t)t});
+            prev = t;
+        }
+        ch.push_back(Chain{1, (int32_t)(L.ntiles - 1), -1});  // the last tile is a cut tile
+    }
+    std::stable_sort(ch.begin(), ch.end(), [](const Chain& x, const Chain& y) { return x.len > y.len; });
+    std::vector<int32_t> chains(3 * ch.size());
+    for (size_t i = 0; i < ch.size(); ++i)
+        chains[3 * i] = ch[i].right, chains[3 * i + 1] = ch[i].len, chains[3 * i + 2] = ch[i].cut;
+    const int32_t nchain = (int32_t)ch.size();
     char* w = reinterpret_cast<char*>(ws);
     hipStream_t st = as_stream(stream);
     if (hipMemcpyAsync(w + L.seg0, seg0.data(), seg0.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemcpyAsync(w + L.offs, host_offsets, (size_t)(nseg + 1) * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(w + L.nchain, &nchain, 4, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(w + L.chains, chains.data(), chains.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess) {
         set_error("pvjp_seg_prepare: uploading the segment tables failed");
         return PVJP_EDEVICE;
