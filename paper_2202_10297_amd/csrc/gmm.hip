@@ -129,50 +129,30 @@ __device__ __forceinline__ void stage_x(const float* __restrict__ X, int64_t N, 
     }
 }
 
-// z = Q_k x - c_k for the wave's 32 points (column j = lane % 32), as MFMA
-// accumulators; returns sum_r z_r^2 in FP64 for the lane's point.
+// z = Q_k x - c_k for the wave's 32 points (column j = lane % 32) as MFMA
+// accumulators, with Q_k's fragments (qs[f * 64 + lane]), c_k (cs[r]) and
+// the X tile (xs, the wave's 32 points) read from LDS; the row tiles' MFMA
+// chains are interleaved.  Each accumulator sees the operands in step order
+// s = 0, 1, ..., the same as the forward sweep's chains, so z and |z|^2 are
+// bit-identical to the forward's.  Returns sum_r z_r^2 in FP64 for the
+// lane's point.
 template <int D>
-__device__ __forceinline__ double tile_znorm(const float (&qa)[Gm<D>::NF], const float (&bx)[Gm<D>::S],
-                                             const float (&cl)[Gm<D>::RT][16], f32x16 (&acc)[Gm<D>::RT]) {
-    using C = Gm<D>;
-#pragma unroll
-    for (int rt = 0; rt < C::RT; ++rt) {
-        f32x16 a = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int s = 0; s < 16 * (rt + 1); ++s) a = mfma32(qa[fidx(rt, s)], bx[s], a);
-        acc[rt] = a;
-    }
-    double nrm = 0.0;
-#pragma unroll
-    for (int rt = 0; rt < C::RT; ++rt) {
-#pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            const float z = acc[rt][t] - cl[rt][t];
-            acc[rt][t] = z;
-            nrm = fma((double)z, (double)z, nrm);
-        }
-    }
-    return nrm + __shfl_xor(nrm, 32, kWave);
-}
-
-// tile_znorm with Q_k's fragments (qs[f * 64 + lane]) and c_k (cs[r]) read
-// from LDS instead of registers; the row tiles' MFMA chains are interleaved.
-// Each accumulator sees the same operands in the same order as in
-// tile_znorm, so z and |z|^2 are bit-identical to the forward sweep's.
-template <int D>
-__device__ __forceinline__ double tile_znorm_lds(const float* qs, const float* cs, const float (&bx)[Gm<D>::S],
+__device__ __forceinline__ double tile_znorm_lds(const float* qs, const float* cs, const float* xs,
                                                  f32x16 (&acc)[Gm<D>::RT]) {
     using C = Gm<D>;
     const int lane = threadIdx.x & 63;
+    const int j = lane & 31, h = lane >> 5;
 #pragma unroll
     for (int rt = 0; rt < C::RT; ++rt)
 #pragma unroll
         for (int t = 0; t < 16; ++t) acc[rt][t] = 0.f;
 #pragma unroll 8
-    for (int s = 0; s < C::S; ++s)
+    for (int s = 0; s < C::S; ++s) {
+        const float bx = xs[xs_at<D>(j, 2 * s + h)];
 #pragma unroll
         for (int rt = 0; rt < C::RT; ++rt)
-            if (s < 16 * (rt + 1)) acc[rt] = mfma32(qs[fidx(rt, s) * 64 + lane], bx[s], acc[rt]);
+            if (s < 16 * (rt + 1)) acc[rt] = mfma32(qs[fidx(rt, s) * 64 + lane], bx, acc[rt]);
+    }
     double nrm = 0.0;
 #pragma unroll
     for (int rt = 0; rt < C::RT; ++rt) {
@@ -213,40 +193,114 @@ struct GmmHdr {
 };
 
 // ------------------------------------------------------------------ forward
+// The block's four waves share each batch of CPB components: Q_k's fragments
+// and c_k are staged in LDS once per block, and each wave interleaves the
+// independent MFMA chains of the batch (CPB components x the row tiles of
+// each), so the matrix unit has several chains to alternate between.  Every
+// chain sees the same operands in the same order as tile_znorm_lds, so z, |z|^2
+// and s_ik are bit-identical to the per-component form, and the online LSE
+// takes the components in index order.
 template <int D>
-__global__ __launch_bounds__(256) void gmm_fwd_kernel(const float* __restrict__ X, int64_t N, int K,
+struct GmFwd {
+    static constexpr int CPB = D == 64 ? 2 : 4;                // components per batch
+    static constexpr int QF = Gm<D>::NF * 64;                  // fragment floats per component
+    static constexpr int STAGE = CPB * (QF + D);               // floats staged per batch
+    static constexpr int PER = (STAGE + 255) / 256;            // per thread (the last round partly empty)
+    static constexpr int XS = 4 * 32 * D;                      // the X tiles, staged first
+    static constexpr int LDS = XS > PER * 256 ? XS : PER * 256;
+};
+
+template <int D>
+__device__ __forceinline__ void fwd_fetch(const float* __restrict__ Qf, const float* __restrict__ cvec, int k0, int K,
+                                          float (&r)[GmFwd<D>::PER]) {
+    using F = GmFwd<D>;
+#pragma unroll
+    for (int u = 0; u < F::PER; ++u) {
+        const int e = u * 256 + (int)threadIdx.x;  // staged float index
+        const int c = e < F::CPB * F::QF ? e / F::QF : (e - F::CPB * F::QF) / D;
+        const int k = k0 + c;
+        float v = 0.f;
+        if (e < F::STAGE && k < K) {
+            if (e < F::CPB * F::QF)
+                v = Qf[(int64_t)k * F::QF + (e - c * F::QF)];
+            else
+                v = cvec[(int64_t)k * D + (e - F::CPB * F::QF - c * D)];
+        }
+        r[u] = v;
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void gmm_fwd_kernel(const float* __restrict__ X, int64_t N, int K,
                                                       const float* __restrict__ Qf, const float* __restrict__ cvec,
                                                       const double* __restrict__ bias,
                                                       const double* __restrict__ lse_alpha, double* __restrict__ lse,
                                                       double* __restrict__ sck, double* parts, GmmHdr* hdr,
                                                       double* loglik) {
     using C = Gm<D>;
-    __shared__ float Xs[4][32 * D];
+    using F = GmFwd<D>;
+    __shared__ float sm[F::LDS];
     __shared__ double red[4];
     __shared__ int s_last;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t p0 = ((int64_t)blockIdx.x * 4 + w) * 32;
-    stage_x<D>(X, N, p0, Xs[w]);
+    float* Xs = sm + w * 32 * D;
+    stage_x<D>(X, N, p0, Xs);
     __syncthreads();
     float bx[C::S];
 #pragma unroll
-    for (int s = 0; s < C::S; ++s) bx[s] = Xs[w][xs_at<D>(lane & 31, 2 * s + (lane >> 5))];
+    for (int s = 0; s < C::S; ++s) bx[s] = Xs[xs_at<D>(lane & 31, 2 * s + (lane >> 5))];
     const int64_t p = p0 + (lane & 31);
+    const float* qs = sm;                       // [CPB][QF] during the batches
+    const float* cs = sm + F::CPB * F::QF;      // [CPB][D]
 
     double m = -INFINITY, ssum = 0.0;
-    float qa[C::NF], cl[C::RT][16];
     const bool own = (lane < 32) && (p < N);
-    for (int k = 0; k < K; ++k) {
-        load_component<D>(Qf, cvec, k, qa, cl);
-        f32x16 acc[C::RT];
-        const double nrm = tile_znorm<D>(qa, bx, cl, acc);
-        const double s = bias[k] - 0.5 * nrm;
-        if (sck && own) sck[(int64_t)k * N + p] = s;  // component-major: 32 points per wave in a row
-        if (s > m) {
-            ssum = ssum * exp(m - s) + 1.0;
-            m = s;
-        } else {
-            ssum += exp(s - m);
+    for (int k0 = 0; k0 < K; k0 += F::CPB) {
+        {
+            float nxt[F::PER];
+            fwd_fetch<D>(Qf, cvec, k0, K, nxt);
+            __syncthreads();  // every wave is done with the previous batch (or with X)
+#pragma unroll
+            for (int u = 0; u < F::PER; ++u) sm[u * 256 + threadIdx.x] = nxt[u];
+            __syncthreads();
+        }
+        f32x16 acc[F::CPB][C::RT];
+#pragma unroll
+        for (int c = 0; c < F::CPB; ++c)
+#pragma unroll
+            for (int rt = 0; rt < C::RT; ++rt)
+#pragma unroll
+                for (int t = 0; t < 16; ++t) acc[c][rt][t] = 0.f;
+#pragma unroll 4
+        for (int s = 0; s < C::S; ++s)
+#pragma unroll
+            for (int rt = 0; rt < C::RT; ++rt)
+#pragma unroll
+                for (int c = 0; c < F::CPB; ++c)
+                    if (s < 16 * (rt + 1)) acc[c][rt] = mfma32(qs[c * F::QF + fidx(rt, s) * 64 + lane], bx[s], acc[c][rt]);
+#pragma unroll
+        for (int c = 0; c < F::CPB; ++c) {
+            const int k = k0 + c;
+            if (k >= K) break;
+            double nrm = 0.0;
+#pragma unroll
+            for (int rt = 0; rt < C::RT; ++rt) {
+#pragma unroll
+                for (int t = 0; t < 16; ++t) {
+                    const float z = acc[c][rt][t] - cs[c * D + 32 * rt + drow(t, lane)];
+                    nrm = fma((double)z, (double)z, nrm);
+                }
+            }
+            nrm += __shfl_xor(nrm, 32, kWave);
+            const double sv = bias[k] - 0.5 * nrm;
+            if (sck && own) sck[(int64_t)k * N + p] = sv;  // component-major: 32 points per wave in a row
+            if (sv > m) {
+                ssum = ssum * exp(m - sv) + 1.0;
+                m = sv;
+            } else {
+                ssum += exp(sv - m);
+            }
         }
     }
     const double l_i = m + log(ssum);
@@ -351,14 +405,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
             for (int r = h * (D / 2); r < (h + 1) * (D / 2); ++r)
                 Zw[zs_at(r, j)] = wf * (Xw[xs_at<D>(j, r)] - cs[r]);
         } else {
-            float bx[C::S];
-#pragma unroll
-            for (int s = 0; s < C::S; ++s) bx[s] = Xw[xs_at<D>(j, 2 * s + h)];
             f32x16 z[C::RT];
             // The MFMA phases run at raised wave priority, so that the other
             // wave on the SIMD issues its loads and FP64 work in their gaps.
             __builtin_amdgcn_s_setprio(1);
-            const double nrm = tile_znorm_lds<D>(qs, cs, bx, z);
+            const double nrm = tile_znorm_lds<D>(qs, cs, Xw, z);
             __builtin_amdgcn_s_setprio(0);
             double wd = 0.0;
             if (p < N) wd = ell_bar * exp((bk - 0.5 * nrm) - lse[p]);
