@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--only", default="",
                     help="run just this one extra workload (for profiling) and print its JSON instead of the "
                          "benchmark line")
-    ap.add_argument("--serve-seconds", type=float, default=4.0, help="measured seconds of the serving trace")
+    ap.add_argument("--serve-seconds", type=float, default=30.0, help="measured seconds of the serving trace")
     ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn the counter_collection.csv files of a FETCH_SIZE and a WRITE_SIZE run into "
                          "profiles/traffic.json (no GPU needed), then exit")
@@ -355,6 +355,11 @@ def main():
     for d in detail.values():
         d["grad_over_primal"] = round((d["primal_ms"] + d["vjp_ms"]) / d["primal_ms"], 3)
 
+    # The whole step against the roofline: every call's algorithmic bytes
+    # over the step's time.
+    step_bytes = sum(c[3] for c in calls)
+    step_roof = {"alg_bytes": step_bytes, "achieved_GBps": round(step_bytes / (ms_per_step * 1e-3) / 1e9, 1),
+                 "frac": round(step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
     dom = int(np.argmax(avg))
     dkey, dkind, _, dbytes, _ = calls[dom]
     achieved = dbytes / (avg[dom] * 1e-3) / 1e9
@@ -444,6 +449,7 @@ def main():
         "grad_over_primal_max": max(d["grad_over_primal"] for d in detail.values()),
         "served_latency": None,
         "roofline": roof,
+        "step_roofline": step_roof,
         "copy_GBps_achievable": achievable,
         "cpu_baseline": cpu,
         "detail": detail,
@@ -1009,25 +1015,41 @@ def bench_batch(args):
 
 
 def bench_serve(args):
-    """Poisson arrivals at 2,000 requests/s mixing scan VJPs (n in [1e3, 1e7]),
-    + histogram VJPs (n in [1e4, 1e7], 2^12..2^18 bins, Zipf) and GMM gradients
-    (N in [1e3, 1e5], D = 32, K = 50) under a 64 GB budget; the same trace
-    served serially (one slot) for comparison."""
+    """Poisson arrivals at 2,000 requests/s for 30 s after a 5 s warm-up,
+    mixing scan VJPs (n in [1e3, 1e7]), + histogram VJPs (n in [1e4, 1e7],
+    2^12..2^18 bins, Zipf) and GMM gradients (N in [1e3, 1e5], D = 32,
+    K = 50) over 256 resident instances per kind under a 64 GB budget; the
+    same trace served serially (one slot) for comparison; then a saturating
+    burst (every request arriving at once) served both ways, whose throughput
+    shows what overlapping requests on the device buys."""
     from paper_2202_10297_amd import serve
 
-    pool = serve.Pool(per_kind=24, seed=0)
-    warm = 1.0
-    trace = serve.make_trace(pool, rate=2000.0, duration=warm + args.serve_seconds, seed=0)
-    srv = serve.Server(pool, slots=8, budget_bytes=64 << 30)
-    stats, _ = srv.run(trace, warmup=warm)
-    serial = serve.Server(pool, slots=1, budget_bytes=64 << 30)
-    trace1 = serve.make_trace(pool, rate=2000.0, duration=warm + args.serve_seconds, seed=0)
-    s1, _ = serial.run(trace1, warmup=warm)
+    t0 = time.time()
+    pool = serve.Pool(per_kind=256, seed=0, device_gen=True)
+    build_s = time.time() - t0
+    warm = 5.0
     keep = lambda d: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
-    out = keep(stats)
-    out["serial_one_slot"] = keep({k: s1[k] for k in ("p50_ms", "p99_ms", "throughput_rps", "max_inflight")})
+    out = {}
+    for slots, name in ((8, None), (1, "serial_one_slot")):
+        trace = serve.make_trace(pool, rate=2000.0, duration=warm + args.serve_seconds, seed=0)
+        log(f"serve: {slots} slot(s), {len(trace)} requests")
+        st, _ = serve.Server(pool, slots=slots, budget_bytes=64 << 30).run(trace, warmup=warm)
+        if name is None:
+            out = keep(st)
+        else:
+            out[name] = keep({k: st[k] for k in ("p50_ms", "p99_ms", "throughput_rps", "max_inflight")})
+    sat = {}
+    for slots in (8, 1):
+        burst = serve.make_burst(pool, 1500, seed=1)
+        st, _ = serve.Server(pool, slots=slots, budget_bytes=64 << 30).run(burst)
+        sat[f"slots{slots}"] = keep({k: st[k] for k in ("throughput_rps", "elems_per_s", "p50_ms", "p99_ms",
+                                                         "max_inflight", "wall_s")})
+    out["saturation_burst_1500"] = sat
     out["rate_rps"] = 2000.0
+    out["warmup_s"] = warm
     out["measured_s"] = args.serve_seconds
+    out["resident_per_kind"] = 256
+    out["pool_build_s"] = round(build_s, 1)
     return out
 
 

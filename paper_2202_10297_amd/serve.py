@@ -47,12 +47,16 @@ class Pool:
     """Resident primal inputs (and checkpoints) for each request kind."""
 
     def __init__(self, per_kind=16, seed=0, device="cuda", scan_range=(10 ** 3, 10 ** 7),
-                 hist_range=(10 ** 4, 10 ** 7), hist_bins=(12, 18), gmm_range=(10 ** 3, 10 ** 5), ybar_variants=2):
+                 hist_range=(10 ** 4, 10 ** 7), hist_bins=(12, 18), gmm_range=(10 ** 3, 10 ** 5), ybar_variants=2,
+                 device_gen=False):
         self.device = torch.device(device)
         self.inst = {k: [] for k in KINDS}
         g = workloads.rng(seed)
         logu = lambda lo, hi: int(np.exp(g.uniform(np.log(lo), np.log(hi))))
         t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(self.device)
+        if device_gen:
+            self._device_pool(per_kind, seed, logu, g, scan_range, hist_range, hist_bins, gmm_range, ybar_variants)
+            return
         for i in range(per_kind):
             n = logu(*scan_range)
             a, b, _, _ = workloads.linrec(n, "f32", seed=seed * 1000 + i)
@@ -80,6 +84,45 @@ class Pool:
                                                                      lse=lse, ybar=yb)))
         torch.cuda.synchronize(self.device)
 
+    def _device_pool(self, per_kind, seed, logu, g, scan_range, hist_range, hist_bins, gmm_range, ybar_variants):
+        """The same instance sizes and input distributions as the host-drawn
+        pool, drawn on the device with torch's generator (a large pool's
+        Zipf indices would take minutes on the host)."""
+        dev = self.device
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(seed + 77)
+        f32 = torch.float32
+        randn = lambda *sh: torch.randn(*sh, dtype=f32, device=dev, generator=gen)
+        for _ in range(per_kind):
+            n = logu(*scan_range)
+            a = torch.rand(n, dtype=f32, device=dev, generator=gen) * 0.5 + 0.5
+            b = randn(n)
+            _, _, ck = ops.linrec_scan(a, b)
+            yb = [(randn(n), randn(n)) for _ in range(ybar_variants)]
+            self.inst["scan"].append(Instance("scan", n, tensors=dict(a=a, b=b, ckpt=ck, ybar=yb)))
+        for _ in range(per_kind):
+            n = logu(*hist_range)
+            m = 1 << int(g.integers(hist_bins[0], hist_bins[1] + 1))
+            k = torch.arange(1, m + 1, dtype=torch.float64, device=dev)
+            cdf = torch.cumsum(k ** -1.1, 0)
+            cdf /= cdf[-1].clone()
+            u = torch.rand(n, dtype=torch.float64, device=dev, generator=gen)
+            r = torch.searchsorted(cdf, u, right=True).clamp_(max=m - 1)
+            perm = torch.randperm(m, device=dev, generator=gen)
+            inds = perm[r].to(torch.int32)
+            yb = [randn(m) for _ in range(ybar_variants)]
+            self.inst["hist"].append(Instance("hist", n, m, tensors=dict(inds=inds, ybar=yb)))
+        tri = GMM_D * (GMM_D - 1) // 2
+        for _ in range(per_kind):
+            N = logu(*gmm_range)
+            X, al, mu = randn(N, GMM_D), randn(GMM_K), randn(GMM_K, GMM_D)
+            q, l = randn(GMM_K, GMM_D) * 0.1, randn(GMM_K, tri) * 0.1
+            _, lse = ops.gmm_objective(X, al, mu, q, l)
+            yb = [1.0 + 0.5 * v for v in range(ybar_variants)]
+            self.inst["gmm"].append(Instance("gmm", N, tensors=dict(X=X, alpha=al, mu=mu, q=q, l=l, lse=lse,
+                                                                     ybar=yb)))
+        torch.cuda.synchronize(dev)
+
     def max_n(self, kind):
         return max(i.n for i in self.inst[kind])
 
@@ -98,6 +141,17 @@ class Request:
     event: object = None
     slot: int = -1
     footprint: int = 0
+
+
+def make_burst(pool: Pool, count: int, seed=0, mix=(1 / 3, 1 / 3, 1 / 3)):
+    """`count` requests that all arrive at time 0 (a saturating load)."""
+    g = workloads.rng(seed + 54321)
+    kinds = g.choice(len(KINDS), size=count, p=np.asarray(mix) / np.sum(mix))
+    reqs = []
+    for i, k in enumerate(kinds):
+        kind = KINDS[int(k)]
+        reqs.append(Request(i, 0.0, kind, int(g.integers(0, len(pool.inst[kind]))), int(g.integers(0, 2))))
+    return reqs
 
 
 def make_trace(pool: Pool, rate=2000.0, duration=30.0, seed=0, mix=(1 / 3, 1 / 3, 1 / 3)):
