@@ -59,7 +59,9 @@ def parse():
                          "profiles/traffic.json (no GPU needed), then exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain streaming kernel over 2^28 FP32 (1 GiB read, 1 GiB written), whose "
-                         "FETCH_SIZE/WRITE_SIZE counters scale the counters of the other kernels")
+                         "FETCH_SIZE/WRITE_SIZE counters scale the counters of the other kernels, then a gather of "
+                         "2^21 whole 128-byte rows in random order (256 MiB read at random, 16 MiB of indices, "
+                         "256 MiB written in order), whose counters calibrate random-order reads")
     return ap.parse_args()
 
 
@@ -99,10 +101,11 @@ def call_order():
 
 # First kernel of each kind of library call: a new call starts at each one.
 CALL_START_KERNELS = ("hist_acc_kernel", "hist_init_kernel", "hpart_count_kernel", "hist_vjp_add_vec_kernel",
-                      "hist_vjp_add_lds_kernel", "hist_vjp_add_kernel", "fill_zero_vec_kernel", "scatter_kernel",
-                      "scatter_vjp_kernel")
-MAIN_LINE_PREFIXES = ("hist_", "hpart_", "fill_zero", "scatter_")
-CALL_SOURCE = {"hist": "paper_2202_10297_amd/csrc/hist.hip", "scatter": "paper_2202_10297_amd/csrc/scatter.hip"}
+                      "hist_vjp_add_lds_kernel", "hist_vjp_add_kernel", "fill_zero_vec_kernel", "sp_count1_kernel",
+                      "sp_clear_kernel")
+MAIN_LINE_PREFIXES = ("hist_", "hpart_", "fill_zero", "sp_")
+CALL_SOURCE = {"hist": "paper_2202_10297_amd/csrc/hist.hip", "scatter": "paper_2202_10297_amd/csrc/scatter_plan.hip"}
+GATHER_ROWS = 1 << 21  # 128-byte rows of the random-order gather calibration (256 MiB)
 
 
 def _short_kernel(name):
@@ -136,6 +139,10 @@ def ingest_pmc(fetch_csv, write_csv):
         if not cal:
             raise SystemExit(f"{path}: no calibration kernel (run bench.py with --copy-calibration)")
         scale[what] = (4.0 * COPY_N) / (sum(cal) / len(cal))
+        gat = [v for name, v in d if "vectorized_gather_kernel" in name]
+        if gat:  # random-order whole rows: reads 256 MiB + 8-byte indices, writes 256 MiB
+            known = 128.0 * GATHER_ROWS + (8.0 * GATHER_ROWS if what == "fetch" else 0.0)
+            scale["gather_" + what] = known / (sum(gat) / len(gat))
         groups = []
         for name, v in d:
             if "pvjp::" not in name:
@@ -163,8 +170,17 @@ def ingest_pmc(fetch_csv, write_csv):
             "write_bytes": round(wb),
             "bytes_per_launch": round(fb + wb),
         }
+        if "gather_fetch" in scale:  # the same counters read with the random-order calibration
+            fg = sum(v for _, v in groups_by["fetch"][i]) * scale["gather_fetch"]
+            out[f"{key}:{kind}"]["fetch_bytes_gather_scale"] = round(fg)
+            out[f"{key}:{kind}"]["bytes_per_launch_gather_scale"] = round(fg + wb)
     out["_calibration"] = {"kernel": f"torch neg over 2^{COPY_N.bit_length() - 1} FP32 (1 GiB read, 1 GiB written)",
                            "fetch_scale": round(scale["fetch"], 4), "write_scale": round(scale["write"], 4)}
+    if "gather_fetch" in scale:
+        out["_calibration"]["gather_kernel"] = ("torch index_select of 2^21 128-byte rows in random order "
+                                                "(256 MiB read at random + 16 MiB indices, 256 MiB written)")
+        out["_calibration"]["gather_fetch_scale"] = round(scale["gather_fetch"], 4)
+        out["_calibration"]["gather_write_scale"] = round(scale.get("gather_write", float("nan")), 4)
     path = os.path.join(ROOT, "profiles", "traffic.json")
     os.makedirs(os.path.dirname(path), exist_ok=True)
     with open(path, "w") as f:
@@ -235,6 +251,13 @@ def main():
             torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
+        rows = torch.ones((GATHER_ROWS, 32), dtype=torch.float32, device=dev)
+        perm = torch.randperm(GATHER_ROWS, device=dev)
+        out = torch.empty_like(rows)
+        for _ in range(3):
+            torch.index_select(rows, 0, perm, out=out)
+        torch.cuda.synchronize()
+        del rows, perm, out
         torch.cuda.empty_cache()
 
     t0 = time.time()
@@ -620,6 +643,30 @@ def bench_reduce_map(args):
                 "vjp_hbm_frac": round(3 * es * n / (tv * 1e-3) / 1e9 / HBM_PEAK_GBPS, 3)}
         del x, xb, sign, ybar, xa
         torch.cuda.empty_cache()
+    # The write-only adjoints again at 2^28 FP32 (1 GiB written, four times
+    # the 256 MiB last-level cache, which a 2^26 stream could partly live in).
+    from paper_2202_10297_amd import capi
+
+    n2 = 1 << 28
+    x = torch.rand(n2, dtype=torch.float32, device="cuda", generator=g)
+    xb = torch.empty_like(x)
+    wo = {}
+    for op in ("add", "max"):
+        y, aux = ops.reduce(op, x)
+        yb = torch.ones_like(y)
+        tv = _events_ms(lambda: ops.reduce_vjp(op, x, aux, yb, x_bar=xb), 10)
+        wo[f"reduce_{op}_vjp"] = {"ms": round(tv, 4), "hbm_frac": round(4 * n2 / (tv * 1e-3) / 1e9 / HBM_PEAK_GBPS, 3)}
+    m = 1 << 16
+    winner = (torch.arange(m, device="cuda", dtype=torch.int32) * (n2 // m)).contiguous()
+    hb = torch.ones(m, dtype=torch.float32, device="cuda")
+    sp = torch.cuda.current_stream().cuda_stream
+    tv = _events_ms(lambda: capi.call("pvjp_hist_vjp", capi.MAX, capi.F32, None, None, n2, m, winner.data_ptr(), None,
+                                      None, hb.data_ptr(), xb.data_ptr(), 0, sp), 10)
+    wo["hist_max_vjp_m65536"] = {"ms": round(tv, 4),
+                                 "hbm_frac": round((4 * n2 + 12 * m) / (tv * 1e-3) / 1e9 / HBM_PEAK_GBPS, 3)}
+    res["write_only_fp32_2^28"] = wo
+    del x, xb, winner, hb
+    torch.cuda.empty_cache()
     return res
 
 
