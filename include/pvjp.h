@@ -221,8 +221,9 @@ pvjp_status pvjp_reduce_vjp(pvjp_op op, pvjp_dtype dtype, const void* x, int64_t
  * caller, owned by the caller, reusable across calls on one stream).  Small
  * m (the bins fit one block's LDS): per-block partial histograms, O(m) with
  * a few hundred rows.  FP32 + / min / max with m beyond that and at most
- * 2^22 bins: the bucket-partitioned path, which stores a packed 8-byte record
- * and a 2-byte bin per element (about 10n bytes plus per-bucket partials). */
+ * 2^22 bins: the bucket-partitioned path, which stores per element a 2-byte
+ * bin and the value (+, 4 bytes) or an ordered 8-byte key (min/max): about
+ * 10n bytes plus per-bucket partials. */
 size_t pvjp_hist_ws_bytes(pvjp_op op, pvjp_dtype dtype, int64_t n, int64_t m);
 /* Which path pvjp_hist takes for (op, dtype, n, m, counts != 0), for tests
  * and tuning: info[0] = PVJP_HIST_PATH_*; for the partitioned path info[1] =

@@ -723,10 +723,10 @@ __global__ __launch_bounds__(kHistBlock) void hpart_scatter_kernel(const int32_t
             const uint32_t j = (uint32_t)k & (kPartBins - 1);
             if (KEYS) {
                 rec[pos] = w;
-                rbin[pos] = (uint16_t)j;
-            } else {
-                rec[pos] = ((uint64_t)j << 32) | (w & 0xffffffffull);
+            } else {  // + : the value alone, 4 bytes (the first half of the record array)
+                reinterpret_cast<uint32_t*>(rec)[pos] = (uint32_t)(w & 0xffffffffull);
             }
+            rbin[pos] = (uint16_t)j;
         }
         __syncthreads();
         // advance the cursors by the batch counts (run lengths) and reset
@@ -790,8 +790,8 @@ __global__ __launch_bounds__(kAccBlock) void hpart_acc_kernel(const uint64_t* __
     for (int t = 0; t < U; ++t) {
         const int64_t r = r0 + (int64_t)t * kAccBlock + threadIdx.x;
         const int64_t rr = r < r1 ? r : last;
-        u[t] = rec[rr];
-        jb[t] = OP == PVJP_ADD ? 0u : (uint32_t)rbin[rr];
+        u[t] = OP == PVJP_ADD ? (uint64_t)reinterpret_cast<const uint32_t*>(rec)[rr] : rec[rr];
+        jb[t] = (uint32_t)rbin[rr];
     }
     for (int64_t base = r0; base < r1; base += kRound) {
         const int64_t nbase = base + kRound;
@@ -800,8 +800,8 @@ __global__ __launch_bounds__(kAccBlock) void hpart_acc_kernel(const uint64_t* __
             for (int t = 0; t < U; ++t) {
                 const int64_t r = nbase + (int64_t)t * kAccBlock + threadIdx.x;
                 const int64_t rr = r < r1 ? r : last;
-                un[t] = rec[rr];
-                jn[t] = OP == PVJP_ADD ? 0u : (uint32_t)rbin[rr];
+                un[t] = OP == PVJP_ADD ? (uint64_t)reinterpret_cast<const uint32_t*>(rec)[rr] : rec[rr];
+                jn[t] = (uint32_t)rbin[rr];
             }
         }
 #pragma unroll
@@ -809,7 +809,7 @@ __global__ __launch_bounds__(kAccBlock) void hpart_acc_kernel(const uint64_t* __
             const int64_t r = base + (int64_t)t * kAccBlock + threadIdx.x;
             if (r >= r1) continue;
             if (OP == PVJP_ADD) {
-                const uint32_t j = (uint32_t)(u[t] >> 32);
+                const uint32_t j = jb[t];
                 atomicAdd(reinterpret_cast<double*>(&acc[j * kAccCopies + copy]),
                           (double)__uint_as_float((uint32_t)u[t]));
                 if (COUNTS) atomicAdd(&cnt[j], 1);
@@ -846,11 +846,26 @@ __global__ __launch_bounds__(256) void hpart_merge_kernel(const uint64_t* __rest
                                                           const int32_t* __restrict__ pcnt,
                                                           const int32_t* __restrict__ istart, int32_t m,
                                                           uint64_t* __restrict__ gacc, int32_t* __restrict__ gcount) {
+    // A thread per bin; eight work items' partials in flight, folded in order.
+    constexpr int U = 8;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x) {
         const int b = (int)(k >> kPartShift), j = (int)(k & (kPartBins - 1));
         uint64_t acc = acc_identity<OP>();
         int32_t zz = 0, cc = 0;
-        for (int it = istart[b]; it < istart[b + 1]; ++it)
+        const int i1 = istart[b + 1];
+        int it = istart[b];
+        for (; it + U <= i1; it += U) {
+            uint64_t v[U];
+            int32_t c[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                v[u] = pacc[(int64_t)(it + u) * kPartBins + j];
+                c[u] = pcnt ? pcnt[(int64_t)(it + u) * kPartBins + j] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) merge_fold<OP>(acc, zz, cc, v[u], 0, c[u]);
+        }
+        for (; it < i1; ++it)
             merge_fold<OP>(acc, zz, cc, pacc[(int64_t)it * kPartBins + j], 0, pcnt ? pcnt[(int64_t)it * kPartBins + j] : 0);
         gacc[k] = acc;
         if (gcount) gcount[k] = cc;
@@ -998,7 +1013,7 @@ static void run_partitioned(const int32_t* inds, const float* vs, int64_t n, int
     else
         hipLaunchKernelGGL((hpart_acc_kernel<OP, false>), dim3((unsigned)L.items_max), dim3(kAccBlock), 0, st, rec,
                            rbin, L.nb, bstart, istart, pacc, pcnt);
-    hipLaunchKernelGGL(hpart_merge_kernel<OP>, dim3(flat_grid(m, 256, 4)), dim3(256), 0, st, pacc,
+    hipLaunchKernelGGL(hpart_merge_kernel<OP>, dim3(flat_grid(m, 256, 1)), dim3(256), 0, st, pacc,
                        count ? pcnt : nullptr, istart, m, gacc, count);
 }
 
