@@ -557,7 +557,7 @@ constexpr int kPartBins = 1 << kPartShift;
 constexpr int kPartMaxBuckets = 1024;
 constexpr int64_t kPartSeg = (int64_t)1 << 17;
 constexpr int kPartScanThreads = 1024;
-constexpr int kPartGrid = 1024;
+constexpr int kPartGrid = 512;
 
 template <bool VEC>
 __device__ __forceinline__ int4 load_k4(const int32_t* __restrict__ inds, int64_t e, int64_t hi) {
