@@ -37,6 +37,7 @@ namespace pvjp {
 
 constexpr int kSegBlock = 256;
 constexpr int kSegCk = PVJP_LINREC_CKPT_INTERVAL;
+constexpr int64_t kSumGroup = 16;  // sum tiles per work item of the return sweep
 
 constexpr size_t kSegState = 128;
 static_assert(sizeof(TileState<SegLinRec<double>::S>) == kSegState && sizeof(TileState<LinO<double>::S>) == kSegState &&
@@ -348,7 +349,8 @@ __global__ __launch_bounds__(kSegBlock) void seg_batch_vjp_kernel(
     __syncthreads();
     if (s_ticket > last) return;  // the workspace was not in its rest state: do nothing
     // Queue: items [0, nscan) are the scan's tile chains (longest first),
-    // items [nscan, nscan + nsum) the sum tiles.  No item waits on another.
+    // items [nscan, nscan + nsum) runs of kSumGroup sum tiles.  No item waits
+    // on another.
     while (true) {
         const int64_t item = s_ticket;
         if (item >= nscan + nsum) break;
@@ -367,9 +369,16 @@ __global__ __launch_bounds__(kSegBlock) void seg_batch_vjp_kernel(
                 __syncthreads();
             }
         } else {
-            const int64_t tile = item - nscan;
-            build_heads<TS>(bits, seg0, offs, nseg, tile, tile * TS);
-            seg_sum_vjp_tile<T, IPT, ACC>(total, seg0, sum_ybar, sum_xbar, tile, bits, lds, wtot_i);
+            // a sum item is a run of kSumGroup tiles: one ticket per run keeps
+            // the queue's counter (one device-scope atomic per draw, serialised
+            // on one address) off the critical path
+            const int64_t t0 = (item - nscan) * kSumGroup;
+            const int64_t t1 = (t0 + kSumGroup < ntiles) ? t0 + kSumGroup : ntiles;
+            for (int64_t tile = t0; tile < t1; ++tile) {
+                build_heads<TS>(bits, seg0, offs, nseg, tile, tile * TS);
+                seg_sum_vjp_tile<T, IPT, ACC>(total, seg0, sum_ybar, sum_xbar, tile, bits, lds, wtot_i);
+                __syncthreads();
+            }
         }
         __syncthreads();
         if (threadIdx.x == 0) s_ticket = lookback_draw(hdr, last, nullptr);
@@ -397,7 +406,7 @@ static void launch_batch(const void* a, const void* b, const void* ya, const voi
                        (const T*)b, (const T*)ya, (const T*)yb, total, nseg, (const int64_t*)(ws + L.offs),
                        (const int32_t*)(ws + L.seg0), (const T*)ckpt, (T*)abar, (T*)bbar, (const T*)sy, (T*)sx,
                        (LookbackHdr*)ws, (const int32_t*)(ws + L.nchain), (const int32_t*)(ws + L.chains), L.ntiles,
-                       a ? 1 : 0, sy ? L.ntiles : 0);
+                       a ? 1 : 0, sy ? ceil_div(L.ntiles, kSumGroup) : 0);
 }
 
 template <class T, bool ACC>
