@@ -100,7 +100,7 @@ def call_order():
 
 
 # First kernel of each kind of library call: a new call starts at each one.
-CALL_START_KERNELS = ("hist_acc_kernel", "hist_init_kernel", "hpart_count_kernel", "hist_vjp_add_vec_kernel",
+CALL_START_KERNELS = ("hist_acc_kernel", "hist_init_kernel", "hpart_tile_kernel", "hist_vjp_add_vec_kernel",
                       "hist_vjp_add_lds_kernel", "hist_vjp_add_kernel", "fill_zero_vec_kernel", "sp_count1_kernel",
                       "sp_clear_kernel")
 MAIN_LINE_PREFIXES = ("hist_", "hpart_", "fill_zero", "sp_")

@@ -221,14 +221,15 @@ pvjp_status pvjp_reduce_vjp(pvjp_op op, pvjp_dtype dtype, const void* x, int64_t
  * caller, owned by the caller, reusable across calls on one stream).  Small
  * m (the bins fit one block's LDS): per-block partial histograms, O(m) with
  * a few hundred rows.  FP32 + / min / max with m beyond that and at most
- * 2^22 bins: the bucket-partitioned path, which stores per element a 2-byte
- * bin and the value (+, 4 bytes) or an ordered 8-byte key (min/max): about
- * 10n bytes plus per-bucket partials. */
+ * 2^22 bins: the bucket-partitioned path, which sorts every tile of 8192
+ * elements by bucket and stores per element the value (4 bytes) and its bin
+ * in the bucket (+: 2 bytes; min/max: 4 bytes with the position in the
+ * tile): about 8n bytes plus per-tile bucket offsets and per-item partials. */
 size_t pvjp_hist_ws_bytes(pvjp_op op, pvjp_dtype dtype, int64_t n, int64_t m);
 /* Which path pvjp_hist takes for (op, dtype, n, m, counts != 0), for tests
  * and tuning: info[0] = PVJP_HIST_PATH_*; for the partitioned path info[1] =
  * bins per bucket, info[2] = most records one work item of a bucket takes
- * (larger buckets are split into several items, merged afterwards), info[3]
+ * (a bucket with more is split into several items, merged afterwards), info[3]
  * = number of buckets; 0 otherwise.  info: int64 [4] host memory. */
 #define PVJP_HIST_PATH_LDS 0       /* every bin in each block's LDS, per-block partials merged */
 #define PVJP_HIST_PATH_CACHE 1     /* LDS cache of bins in front of device-memory atomics */

@@ -336,7 +336,18 @@ __global__ void hist_final_kernel(const T* __restrict__ vs, const uint64_t* __re
             else
                 w = (winner[k] == 0x7fffffff) ? -1 : winner[k];
             winner[k] = w;
-            hs[k] = (w >= 0) ? vs[w] : (OP == PVJP_MAX ? -(T)__builtin_huge_val() : (T)__builtin_huge_val());
+            if (w < 0) {
+                hs[k] = OP == PVJP_MAX ? -(T)__builtin_huge_val() : (T)__builtin_huge_val();
+            } else if (sizeof(T) == 4) {
+                // the key's upper half is the order-preserving code of the
+                // winner's value; it reads back exactly except for a zero,
+                // whose sign the code drops: that one is read from vs
+                const uint32_t o = OP == PVJP_MAX ? (uint32_t)(a >> 32) : ~(uint32_t)(a >> 32);
+                const uint32_t bits = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
+                hs[k] = bits == 0u ? vs[w] : (T)__uint_as_float(bits);
+            } else {
+                hs[k] = vs[w];
+            }
         }
     }
 }
@@ -544,205 +555,260 @@ __global__ __launch_bounds__(256) void hist_vjp_winner_kernel(const int32_t* __r
 
 // ------------------------------------------------- bucket-partitioned path
 // For FP32 values with + / min / max when the m bins do not fit one block's
-// LDS (m up to 2^22): instead of one global atomic per element,
-//   1. count the elements of every 4096-bin bucket per block (LDS counters),
-//   2. one block scans the (bucket, block) counts into write offsets and
-//      splits every bucket into work items of at most kPartSeg records,
-//   3. scatter each element as a packed record into its bucket,
-//   4. one block per work item accumulates its bucket's 4096 bins in LDS and
-//      writes them out as a partial,
-//   5. merge the partials of each bin in work-item order.
+// LDS (m up to 2^22), instead of one global atomic per element:
+//   1. tile sort: one block per tile of kTile consecutive elements ranks
+//      them by 4096-bin bucket in LDS, writes them back into the tile's own
+//      slice of the record arrays in bucket order (fully contiguous,
+//      coalesced stores whatever the bucket count) and records the tile's
+//      bucket offsets;
+//   2. per bucket, an exclusive scan of its run lengths over the tiles;
+//      each bucket is split into work items of about kPartSeg records made
+//      of whole runs;
+//   3. one block per work item walks its runs and accumulates the bucket's
+//      4096 bins in LDS, then writes them out as a partial;
+//   4. merge the partials of each bin in work-item order.
+// No pass over the input only to count it, and no record store depends on
+// a global cursor.
 constexpr int kPartShift = 12;
 constexpr int kPartBins = 1 << kPartShift;
 constexpr int kPartMaxBuckets = 1024;
 constexpr int64_t kPartSeg = (int64_t)1 << 17;
 constexpr int kPartScanThreads = 1024;
-constexpr int kPartGrid = 512;
+constexpr int kTileThreads = 512;
+constexpr int kTileQuads = 4;                              // quads of elements per thread
+constexpr int kTile = 4 * kTileThreads * kTileQuads;       // 8192 elements
+constexpr int kTileBucketsPerThread = kPartMaxBuckets / kTileThreads;
+static_assert(kTile <= 65536, "an element's position in its tile must fit 16 bits");
+static_assert(kPartMaxBuckets % kTileThreads == 0, "tile threads own whole groups of buckets in the scan");
+static_assert(kTile < kPartSeg, "a work item must hold any single run");
 
-template <bool VEC>
-__device__ __forceinline__ int4 load_k4(const int32_t* __restrict__ inds, int64_t e, int64_t hi) {
-    if (VEC && e + 3 < hi) return *reinterpret_cast<const int4*>(inds + e);
-    return make_int4(e < hi ? inds[e] : -1, e + 1 < hi ? inds[e + 1] : -1, e + 2 < hi ? inds[e + 2] : -1,
-                     e + 3 < hi ? inds[e + 3] : -1);
+// Stores of the first cnt staged words of a tile, 16 bytes per lane.
+__device__ __forceinline__ void tile_store_u32(uint32_t* __restrict__ dst, const uint32_t* stage, int cnt) {
+    for (int i = 4 * (int)threadIdx.x; i < cnt; i += 4 * kTileThreads) {
+        if (i + 3 < cnt)
+            *reinterpret_cast<uint4*>(dst + i) = *reinterpret_cast<const uint4*>(stage + i);
+        else
+            for (int k = i; k < cnt; ++k) dst[k] = stage[k];
+    }
+}
+__device__ __forceinline__ void tile_store_u16(uint16_t* __restrict__ dst, const uint16_t* stage, int cnt) {
+    for (int i = 8 * (int)threadIdx.x; i < cnt; i += 8 * kTileThreads) {
+        if (i + 7 < cnt)
+            *reinterpret_cast<uint4*>(dst + i) = *reinterpret_cast<const uint4*>(stage + i);
+        else
+            for (int k = i; k < cnt; ++k) dst[k] = stage[k];
+    }
 }
 
-template <bool VEC>
-__global__ __launch_bounds__(kHistBlock) void hpart_count_kernel(const int32_t* __restrict__ inds, int64_t n,
-                                                                 int32_t m, int64_t chunk, int nb,
-                                                                 int32_t* __restrict__ bcount) {
-    __shared__ int32_t cnt[kPartMaxBuckets];
-    for (int b = threadIdx.x; b < nb; b += kHistBlock) cnt[b] = 0;
+// Tile sort.  Tile t owns records [t * kTile, t * kTile + valid) of every
+// record array; toff[t][b] is the start of bucket b's run in the tile and
+// toff[t][nb] the number of in-range elements.  Record of element e with bin
+// k = b * 4096 + j: rval = the value's bits; for + rbin = j (2 bytes), for
+// min/max rbin = j | (e - t * kTile) << 16 (4 bytes: the position in the
+// tile gives back the element index for the lowest-index rule).
+template <int OP, bool VEC>
+__global__ __launch_bounds__(kTileThreads) void hpart_tile_kernel(const int32_t* __restrict__ inds,
+                                                                const float* __restrict__ vs, int64_t n, int32_t m,
+                                                                int nb, uint32_t* __restrict__ rval,
+                                                                void* __restrict__ rbin, int32_t* __restrict__ toff) {
+    constexpr bool KEYS = OP != PVJP_ADD;
+    __shared__ int32_t bcnt[kPartMaxBuckets];  // counts, then run starts
+    __shared__ __align__(16) uint32_t sval[kTile];
+    __shared__ __align__(16) uint32_t sbin[KEYS ? kTile : kTile / 2];
+    __shared__ IntSum::S wtot[kTileThreads / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    const int64_t hi = (base + kTile < n) ? base + kTile : n;
+    for (int b = threadIdx.x; b < nb; b += kTileThreads) bcnt[b] = 0;
+    Quad<float> q[kTileQuads];
+#pragma unroll
+    for (int u = 0; u < kTileQuads; ++u)
+        q[u] = load_quad<float, VEC>(inds, vs, base + 4 * ((int64_t)u * kTileThreads + threadIdx.x), hi);
     __syncthreads();
-    const int64_t lo = (int64_t)blockIdx.x * chunk;
-    const int64_t hi = (lo + chunk < n) ? lo + chunk : n;
-    constexpr int64_t kStride = 4 * kHistBlock * kHistBatch;
-    // the next batch's indices are in flight while this batch is counted
-    int4 k[kHistBatch], kn[kHistBatch];
+    int rank[4 * kTileQuads];
 #pragma unroll
-    for (int u = 0; u < kHistBatch; ++u) k[u] = load_k4<VEC>(inds, lo + 4 * ((int64_t)u * kHistBlock + threadIdx.x), hi);
-    for (int64_t base = lo; base < hi; base += kStride) {
-        const int64_t nbase = base + kStride;
-        if (nbase < hi) {
+    for (int u = 0; u < kTileQuads; ++u) {
+        const int32_t kk[4] = {q[u].k.x, q[u].k.y, q[u].k.z, q[u].k.w};
 #pragma unroll
-            for (int u = 0; u < kHistBatch; ++u)
-                kn[u] = load_k4<VEC>(inds, nbase + 4 * ((int64_t)u * kHistBlock + threadIdx.x), hi);
-        }
-#pragma unroll
-        for (int u = 0; u < kHistBatch; ++u) {
-            if ((uint32_t)k[u].x < (uint32_t)m) atomicAdd(&cnt[k[u].x >> kPartShift], 1);
-            if ((uint32_t)k[u].y < (uint32_t)m) atomicAdd(&cnt[k[u].y >> kPartShift], 1);
-            if ((uint32_t)k[u].z < (uint32_t)m) atomicAdd(&cnt[k[u].z >> kPartShift], 1);
-            if ((uint32_t)k[u].w < (uint32_t)m) atomicAdd(&cnt[k[u].w >> kPartShift], 1);
-        }
-#pragma unroll
-        for (int u = 0; u < kHistBatch; ++u) k[u] = kn[u];
+        for (int t = 0; t < 4; ++t)
+            rank[4 * u + t] = ((uint32_t)kk[t] < (uint32_t)m) ? atomicAdd(&bcnt[kk[t] >> kPartShift], 1) : -1;
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < nb; b += kHistBlock) bcount[(int64_t)b * gridDim.x + blockIdx.x] = cnt[b];
-}
-
-// Exclusive offsets of the (bucket, block) counts: one block per bucket scans
-// its kPartGrid block counts in place (coalesced) and writes the bucket total.
-__global__ __launch_bounds__(kPartGrid) void hpart_scan_local_kernel(int32_t* __restrict__ bcount,
-                                                                     int32_t* __restrict__ btotal) {
-    __shared__ IntSum::S wtot[kPartGrid / kWave];
-    const int64_t e = (int64_t)blockIdx.x * kPartGrid + threadIdx.x;
-    const int c = bcount[e];
+    // exclusive scan of the tile's bucket counts: each thread owns a few buckets
+    int c[kTileBucketsPerThread], sum = 0;
+#pragma unroll
+    for (int i = 0; i < kTileBucketsPerThread; ++i) {
+        const int b = kTileBucketsPerThread * (int)threadIdx.x + i;
+        c[i] = b < nb ? bcnt[b] : 0;
+        sum += c[i];
+    }
     IntSum::S tot;
-    bcount[e] = block_exclusive_scan<IntSum, kPartGrid, false>(IntSum::S{c}, tot, wtot).v;
-    if (threadIdx.x == 0) btotal[blockIdx.x] = tot.v;
+    int ex = block_exclusive_scan<IntSum, kTileThreads, false>(IntSum::S{sum}, tot, wtot).v;
+    int32_t* to = toff + (int64_t)blockIdx.x * (nb + 1);
+#pragma unroll
+    for (int i = 0; i < kTileBucketsPerThread; ++i) {
+        const int b = kTileBucketsPerThread * (int)threadIdx.x + i;
+        if (b < nb) {
+            bcnt[b] = ex;
+            to[b] = ex;
+        }
+        ex += c[i];
+    }
+    if (threadIdx.x == 0) to[nb] = tot.v;
+    __syncthreads();
+    uint16_t* sbin16 = reinterpret_cast<uint16_t*>(sbin);
+#pragma unroll
+    for (int u = 0; u < kTileQuads; ++u) {
+        const int32_t kk[4] = {q[u].k.x, q[u].k.y, q[u].k.z, q[u].k.w};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (rank[4 * u + t] < 0) continue;
+            const int slot = bcnt[kk[t] >> kPartShift] + rank[4 * u + t];
+            const uint32_t j = (uint32_t)kk[t] & (kPartBins - 1);
+            sval[slot] = __float_as_uint(q[u].v[t]);
+            if (KEYS)
+                sbin[slot] = j | ((uint32_t)(4 * (u * kTileThreads + (int)threadIdx.x) + t) << 16);
+            else
+                sbin16[slot] = (uint16_t)j;
+        }
+    }
+    __syncthreads();
+    tile_store_u32(rval + base, sval, tot.v);
+    if (KEYS)
+        tile_store_u32(reinterpret_cast<uint32_t*>(rbin) + base, sbin, tot.v);
+    else
+        tile_store_u16(reinterpret_cast<uint16_t*>(rbin) + base, sbin16, tot.v);
 }
 
-// One block: bucket starts from the bucket totals, and work-item starts.
-__global__ __launch_bounds__(kPartScanThreads) void hpart_scan_kernel(const int32_t* __restrict__ btotal, int nb,
-                                                                      int32_t* __restrict__ bstart,
+// Per chunk c of kColChunk tiles (grid y) and group of kColThreads buckets
+// (grid x), a thread per bucket b walks the chunk's tiles: the bucket-major
+// run descriptor D[b][t] = start of b's run in tile t | its length << 16,
+// the run's start within the chunk's part of the bucket (Ploc), the chunk
+// total ctot[b][c] and the chunk-local start of its last non-empty run
+// clast[b][c] (-1: none).  Reads of a tile's offsets are coalesced across
+// the threads; each thread writes its rows 16 bytes at a time.
+constexpr int kColChunk = 32;
+constexpr int kColThreads = 256;
+__global__ __launch_bounds__(kColThreads) void hpart_colscan_kernel(const int32_t* __restrict__ toff, int ntiles,
+                                                                    int nb, int nchunks, uint32_t* __restrict__ D,
+                                                                    int32_t* __restrict__ Ploc,
+                                                                    int32_t* __restrict__ ctot,
+                                                                    int32_t* __restrict__ clast) {
+    const int b = blockIdx.x * kColThreads + (int)threadIdx.x;
+    const int c = blockIdx.y;
+    if (b >= nb) return;
+    const int t0 = c * kColChunk;
+    const int nt = (ntiles - t0 < kColChunk) ? ntiles - t0 : kColChunk;
+    uint32_t* Db = D + (int64_t)b * ntiles + t0;
+    int32_t* Pb = Ploc + (int64_t)b * ntiles + t0;
+    // rows of D and Ploc are 16-byte aligned when ntiles is a multiple of 4
+    const bool vec = (ntiles & 3) == 0;
+    // every offset of the chunk is loaded before any is used
+    int s0[kColChunk], s1[kColChunk];
+#pragma unroll
+    for (int u = 0; u < kColChunk; ++u) {
+        const int32_t* o = toff + (int64_t)(t0 + (u < nt ? u : 0)) * (nb + 1) + b;
+        s0[u] = o[0];
+        s1[u] = o[1];
+    }
+    int run = 0, last = -1;
+#pragma unroll
+    for (int q = 0; q < kColChunk; q += 4) {
+        uint32_t d[4];
+        int p[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int len = q + u < nt ? s1[q + u] - s0[q + u] : 0;
+            d[u] = (uint32_t)s0[q + u] | ((uint32_t)len << 16);
+            p[u] = run;
+            if (len > 0) last = run;
+            run += len;
+        }
+        if (q >= nt) continue;
+        if (vec && q + 4 <= nt) {
+            *reinterpret_cast<uint4*>(Db + q) = make_uint4(d[0], d[1], d[2], d[3]);
+            *reinterpret_cast<int4*>(Pb + q) = make_int4(p[0], p[1], p[2], p[3]);
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (q + u < nt) {
+                    Db[q + u] = d[u];
+                    Pb[q + u] = p[u];
+                }
+            }
+        }
+    }
+    ctot[(int64_t)b * nchunks + c] = run;
+    clast[(int64_t)b * nchunks + c] = last;
+}
+
+// Per bucket (one block each): chunk prefixes (ctot is overwritten with the
+// exclusive prefix) and the bucket's work-item count -- item i takes the
+// runs that start in [i * kPartSeg, (i + 1) * kPartSeg), so the count is one
+// more than the last non-empty run's start over kPartSeg, none for an empty
+// bucket.
+constexpr int kBscanThreads = 256;
+__global__ __launch_bounds__(kBscanThreads) void hpart_bscan_kernel(int32_t* __restrict__ ctot,
+                                                                    const int32_t* __restrict__ clast,
+                                                                    int nchunks, int32_t* __restrict__ bitems) {
+    __shared__ IntSum::S wtot[kBscanThreads / kWave];
+    __shared__ int lastp;
+    const int b = blockIdx.x;
+    int32_t* cb = ctot + (int64_t)b * nchunks;
+    const int32_t* lb = clast + (int64_t)b * nchunks;
+    if (threadIdx.x == 0) lastp = -1;
+    int carry = 0;
+    for (int c0 = 0; c0 < nchunks; c0 += kBscanThreads) {
+        const int c = c0 + (int)threadIdx.x;
+        const int tc = c < nchunks ? cb[c] : 0;
+        const int lc = c < nchunks ? lb[c] : -1;
+        IntSum::S tot;
+        const int ex = block_exclusive_scan<IntSum, kBscanThreads, false>(IntSum::S{tc}, tot, wtot).v;
+        if (c < nchunks) cb[c] = carry + ex;
+        if (lc >= 0) atomicMax(&lastp, carry + ex + lc);
+        carry += tot.v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) bitems[b] = lastp >= 0 ? (int)(lastp / kPartSeg) + 1 : 0;
+}
+
+// One block: work-item starts per bucket.
+__global__ __launch_bounds__(kPartScanThreads) void hpart_scan_kernel(const int32_t* __restrict__ bitems, int nb,
                                                                       int32_t* __restrict__ istart) {
     __shared__ IntSum::S wtot[kPartScanThreads / kWave];
     const int b = threadIdx.x;
-    const int c = b < nb ? btotal[b] : 0;
-    IntSum::S tot;
-    const int ex = block_exclusive_scan<IntSum, kPartScanThreads, false>(IntSum::S{c}, tot, wtot).v;
-    if (b < nb) bstart[b] = ex;
-    if (b == 0) bstart[nb] = tot.v;
-    const int items = (int)((c + kPartSeg - 1) / kPartSeg);
+    const int items = b < nb ? bitems[b] : 0;
     IntSum::S itot;
     const int iex = block_exclusive_scan<IntSum, kPartScanThreads, false>(IntSum::S{items}, itot, wtot).v;
     if (b < nb) istart[b] = iex;
     if (b == 0) istart[nb] = itot.v;
 }
 
-// Scatter of packed records into their buckets.  Each batch of 4096
-// elements is first counting-sorted by bucket in LDS, so that every bucket's
-// run of the batch leaves as one contiguous, coalesced write.  The next
-// batch's loads are issued before the current batch is ranked, staged and
-// written, so HBM reads overlap the LDS work.  For + the staged word carries
-// the full bin (its bucket is recomputed from it); for min/max the staged
-// word is the packed key and the bin is staged beside it.
-constexpr int kPartBatch = 4 * kHistBlock * kHistBatch;  // 4096 elements
-
-template <int OP, bool VEC>
-__global__ __launch_bounds__(kHistBlock) void hpart_scatter_kernel(const int32_t* __restrict__ inds,
-                                                                   const float* __restrict__ vs, int64_t n,
-                                                                   int32_t m, int64_t chunk, int nb,
-                                                                   const int32_t* __restrict__ local,
-                                                                   const int32_t* __restrict__ bstart,
-                                                                   uint64_t* __restrict__ rec,
-                                                                   uint16_t* __restrict__ rbin) {
-    constexpr bool KEYS = OP != PVJP_ADD;
-    __shared__ int32_t cur[kPartMaxBuckets];   // next global position of each bucket
-    __shared__ int32_t bcnt[kPartMaxBuckets];  // batch count, then batch run start
-    __shared__ uint64_t stage[kPartBatch];
-    __shared__ int32_t sbin[KEYS ? kPartBatch : 1];
-    __shared__ IntSum::S wtot[kHistBlock / kWave];
-    for (int b = threadIdx.x; b < nb; b += kHistBlock) {
-        cur[b] = bstart[b] + local[(int64_t)b * gridDim.x + blockIdx.x];
-        bcnt[b] = 0;
+// First tile of every work item: item i of bucket b takes the tiles whose run
+// of b starts in [i * kPartSeg, (i + 1) * kPartSeg), i.e. from the first tile
+// t with P[b][t] >= i * kPartSeg, where P[b][t] = Ploc + the chunk prefix is
+// the start of b's run in tile t within the bucket.  Non-empty runs start at
+// 0 and are shorter than kPartSeg, so up to the last non-empty run every
+// such interval holds a run start, and exactly one thread finds the first
+// tile of each item.
+__global__ __launch_bounds__(256) void hpart_items_kernel(const int32_t* __restrict__ Ploc,
+                                                          const int32_t* __restrict__ cpre, int ntiles, int nb,
+                                                          int nchunks, const int32_t* __restrict__ istart,
+                                                          int32_t* __restrict__ itile) {
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= (int64_t)nb * ntiles) return;
+    const int b = (int)(g / ntiles), t = (int)(g % ntiles);
+    auto P = [&](int tt) {
+        return (int64_t)Ploc[(int64_t)b * ntiles + tt] + cpre[(int64_t)b * nchunks + tt / kColChunk];
+    };
+    const int items = istart[b + 1] - istart[b];
+    int64_t i;
+    if (t == 0) {
+        i = 0;
+    } else {
+        i = P(t) / kPartSeg;
+        if (i == 0 || i * kPartSeg <= P(t - 1)) return;
     }
-    __syncthreads();
-    const int64_t lo = (int64_t)blockIdx.x * chunk;
-    const int64_t hi = (lo + chunk < n) ? lo + chunk : n;
-    Quad<float> q[kHistBatch], qn[kHistBatch];
-#pragma unroll
-    for (int u = 0; u < kHistBatch; ++u)
-        q[u] = load_quad<float, VEC>(inds, vs, lo + 4 * ((int64_t)u * kHistBlock + threadIdx.x), hi);
-    for (int64_t base = lo; base < hi; base += kPartBatch) {
-        const int64_t nbase = base + kPartBatch;
-        if (nbase < hi) {
-#pragma unroll
-            for (int u = 0; u < kHistBatch; ++u)
-                qn[u] = load_quad<float, VEC>(inds, vs, nbase + 4 * ((int64_t)u * kHistBlock + threadIdx.x), hi);
-        }
-        int rank[4 * kHistBatch];
-#pragma unroll
-        for (int u = 0; u < kHistBatch; ++u) {
-            const int32_t kk[4] = {q[u].k.x, q[u].k.y, q[u].k.z, q[u].k.w};
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-                rank[4 * u + t] = ((uint32_t)kk[t] < (uint32_t)m) ? atomicAdd(&bcnt[kk[t] >> kPartShift], 1) : -1;
-        }
-        __syncthreads();
-        // exclusive scan of the batch counts: each thread owns 4 buckets
-        int c4[4], sum = 0;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int b = 4 * (int)threadIdx.x + t;
-            c4[t] = b < nb ? bcnt[b] : 0;
-            sum += c4[t];
-        }
-        IntSum::S tot;
-        int ex = block_exclusive_scan<IntSum, kHistBlock, false>(IntSum::S{sum}, tot, wtot).v;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int b = 4 * (int)threadIdx.x + t;
-            if (b < nb) bcnt[b] = ex;  // run start of bucket b in the staging area
-            ex += c4[t];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < kHistBatch; ++u) {
-            const int32_t kk[4] = {q[u].k.x, q[u].k.y, q[u].k.z, q[u].k.w};
-            const int64_t e = base + 4 * ((int64_t)u * kHistBlock + threadIdx.x);
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                if (rank[4 * u + t] < 0) continue;
-                const int slot = bcnt[kk[t] >> kPartShift] + rank[4 * u + t];
-                if (KEYS) {
-                    stage[slot] = elem_key<OP>(q[u].v[t], e + t);
-                    sbin[slot] = kk[t];
-                } else {
-                    stage[slot] = ((uint64_t)(uint32_t)kk[t] << 32) | (uint64_t)__float_as_uint(q[u].v[t]);
-                }
-            }
-        }
-        __syncthreads();
-        for (int sl = threadIdx.x; sl < tot.v; sl += kHistBlock) {
-            const uint64_t w = stage[sl];
-            const int32_t k = KEYS ? sbin[sl] : (int32_t)(w >> 32);
-            const int b = k >> kPartShift;
-            const int pos = cur[b] + (sl - bcnt[b]);
-            const uint32_t j = (uint32_t)k & (kPartBins - 1);
-            if (KEYS) {
-                rec[pos] = w;
-            } else {  // + : the value alone, 4 bytes (the first half of the record array)
-                reinterpret_cast<uint32_t*>(rec)[pos] = (uint32_t)(w & 0xffffffffull);
-            }
-            rbin[pos] = (uint16_t)j;
-        }
-        __syncthreads();
-        // advance the cursors by the batch counts (run lengths) and reset
-        for (int t = 0; t < 4; ++t) {
-            const int b = 4 * (int)threadIdx.x + t;
-            if (b < nb) {
-                const int next = (b + 1 < nb) ? bcnt[b + 1] : tot.v;
-                cur[b] += next - bcnt[b];
-            }
-        }
-        __syncthreads();
-        for (int b = threadIdx.x; b < nb; b += kHistBlock) bcnt[b] = 0;
-#pragma unroll
-        for (int u = 0; u < kHistBatch; ++u) q[u] = qn[u];
-        __syncthreads();
-    }
+    if (i < items) itile[istart[b] + i] = t;
 }
 
 // One block per work item accumulates its bucket's 4096 bins in LDS.  The
@@ -752,77 +818,161 @@ __global__ __launch_bounds__(kHistBlock) void hpart_scatter_kernel(const int32_t
 // of the records on a few bins -- update different words in different
 // banks instead of serialising on one address.  The copies are folded in a
 // fixed order at the end.
+// Each wave takes a contiguous share of the item's tiles.  It loads the run
+// descriptors of 64 tiles at a time (a lane each, one coalesced load) and
+// reads kAccPar groups of up to kAccGroup consecutive runs side by side
+// (when the share is short, its runs are split evenly between the groups,
+// which keeps long runs of a hot bucket spread over all of a lane's
+// loads).  Within such a group the runs form one flat
+// sequence (lane l takes records l, l + 64, ...; a record finds its run by
+// comparing its rank with the group's run prefix), so lanes stay full
+// whatever the run lengths, and each lane has kAccPar * kAccSlots records
+// in flight.
 constexpr int kAccBlock = 1024;
 constexpr int kAccCopies = 4;
+constexpr int kXcds = 8;  // accelerator dies of an MI355X, each with its own L2
+constexpr int kXcdMapBuckets = 128;
+constexpr int kAccGroup = 8;
+constexpr int kAccSlots = 4;  // records per lane and group in flight
+constexpr int kAccPar = 2;    // groups read side by side
+
+// Uniform run table of one group: run u holds records [pre[u], pre[u + 1])
+// of the group's flat sequence, at record slot off[u] + r.
+struct AccGroup {
+    int pre[kAccGroup + 1];
+    uint32_t off[kAccGroup];
+};
+
+// Runs first .. first + count - 1 of the lanes' descriptors (count <=
+// kAccGroup); slots are counted from the start of the chunk's first tile.
+__device__ __forceinline__ AccGroup acc_group(uint32_t dl, int first, int count) {
+    AccGroup G;
+    G.pre[0] = 0;
+#pragma unroll
+    for (int u = 0; u < kAccGroup; ++u) {
+        uint32_t d = 0u;
+        if (u < count) d = (uint32_t)__builtin_amdgcn_readlane((int)dl, first + u);
+        const int len = (int)(d >> 16);
+        G.off[u] = (uint32_t)(first + u) * (uint32_t)kTile + (d & 0xffffu) - (uint32_t)G.pre[u];
+        G.pre[u + 1] = G.pre[u] + len;
+    }
+    return G;
+}
+
+// The empty asm keeps the chain as conditional moves from scalar registers
+// (left alone, the compiler turns it into an indexed load from a private
+// array in scratch memory).
+__device__ __forceinline__ uint32_t acc_slot(const AccGroup& G, int r) {
+    uint32_t o = G.off[0];
+#pragma unroll
+    for (int u = 1; u < kAccGroup; ++u) {
+        o = (r >= G.pre[u]) ? G.off[u] : o;
+        __asm__ volatile("" : "+v"(o));
+    }
+    return o + (uint32_t)r;
+}
 
 template <int OP, bool COUNTS>
-__global__ __launch_bounds__(kAccBlock) void hpart_acc_kernel(const uint64_t* __restrict__ rec,
-                                                              const uint16_t* __restrict__ rbin, int nb,
-                                                              const int32_t* __restrict__ bstart,
+__device__ __forceinline__ void acc_record(uint64_t* acc, int32_t* cnt, uint32_t copy, int64_t tile_base,
+                                           uint32_t at, uint32_t v, uint32_t bn) {
+    const uint32_t j = bn & (kPartBins - 1);
+    if (OP != PVJP_ADD) {
+        // the tile start plus the position in the tile: the element index
+        const int64_t e = tile_base + (int64_t)(at & ~(uint32_t)(kTile - 1)) + (int64_t)(bn >> 16);
+        atomicMax(reinterpret_cast<unsigned long long*>(&acc[j * kAccCopies + copy]),
+                  (unsigned long long)elem_key<OP>(__uint_as_float(v), e));
+    } else {
+        atomicAdd(reinterpret_cast<double*>(&acc[j * kAccCopies + copy]), (double)__uint_as_float(v));
+    }
+    if (COUNTS) atomicAdd(&cnt[j], 1);
+}
+
+template <int OP, bool COUNTS>
+__global__ __launch_bounds__(kAccBlock) void hpart_acc_kernel(const uint32_t* __restrict__ rval,
+                                                              const void* __restrict__ rbin, int nb, int ntiles,
+                                                              const uint32_t* __restrict__ D,
                                                               const int32_t* __restrict__ istart,
+                                                              const int32_t* __restrict__ itile,
                                                               uint64_t* __restrict__ pacc,
                                                               int32_t* __restrict__ pcnt) {
+    constexpr bool KEYS = OP != PVJP_ADD;
+    constexpr int NW = kAccBlock / kWave;
     __shared__ uint64_t acc[kPartBins * kAccCopies];
     __shared__ int32_t cnt[COUNTS ? kPartBins : 1];
-    const int item = blockIdx.x;
-    if (item >= istart[nb]) return;
+    // With many buckets (short runs): blocks go to the XCDs round-robin, so
+    // each XCD takes an equal contiguous range of the items (the grid is a
+    // multiple of kXcds and covers them) and items of adjacent buckets,
+    // whose runs share cache lines in every tile, meet in one L2.  With few
+    // buckets the runs span whole lines and items go in grid order.
+    const int nitems = istart[nb];
+    int item = (int)blockIdx.x;
+    if (nb >= kXcdMapBuckets) {
+        const int per = (nitems + kXcds - 1) / kXcds;
+        if ((int)(blockIdx.x / kXcds) >= per) return;
+        item = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+    }
+    if (item >= nitems) return;
     int lo = 0, hi = nb;  // last bucket b with istart[b] <= item
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         if (istart[mid] <= item) lo = mid; else hi = mid;
     }
     const int b = lo;
-    const int64_t r0 = (int64_t)bstart[b] + (int64_t)(item - istart[b]) * kPartSeg;
-    const int64_t r1 = (r0 + kPartSeg < (int64_t)bstart[b + 1]) ? r0 + kPartSeg : (int64_t)bstart[b + 1];
+    const int ta = itile[item];
+    const int tb = (item + 1 < istart[b + 1]) ? itile[item + 1] : ntiles;
     for (int j = threadIdx.x; j < kPartBins * kAccCopies; j += kAccBlock) acc[j] = acc_identity<OP>();
     if (COUNTS)
         for (int j = threadIdx.x; j < kPartBins; j += kAccBlock) cnt[j] = 0;
     __syncthreads();
     const uint32_t copy = threadIdx.x & (kAccCopies - 1);
-    // Loads are clamped to the item's last record (never out of range) and
-    // the next round's loads are issued before this round's LDS atomics.
-    constexpr int U = 8;
-    constexpr int64_t kRound = (int64_t)U * kAccBlock;
-    const int64_t last = r1 - 1;
-    uint64_t u[U], un[U];
-    uint32_t jb[U], jn[U];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kWave);
+    const int span = (tb - ta + NW - 1) / NW;
+    const int w0 = ta + wave * span;
+    const int w1 = (w0 + span < tb) ? w0 + span : tb;
+    const uint32_t* Db = D + (int64_t)b * ntiles;
+    for (int c0 = w0; c0 < w1; c0 += kWave) {
+        // lane l: the descriptor of tile c0 + l (an empty run past the share)
+        const uint32_t dl = (c0 + lane < w1) ? Db[c0 + lane] : 0u;
+        const int nc = (w1 - c0 < kWave) ? w1 - c0 : kWave;
+        const int64_t tbase = (int64_t)c0 * kTile;
+        const char* cv = reinterpret_cast<const char*>(rval + tbase);
+        const char* cb = reinterpret_cast<const char*>(rbin) + tbase * (KEYS ? 4 : 2);
+        // a pass reads kAccPar groups of kAccGroup consecutive runs side by
+        // side; fewer runs than one pass takes are split evenly between them
+        const bool split = nc < kAccPar * kAccGroup;
+        const int ps = split ? (nc + kAccPar - 1) / kAccPar : kAccGroup;
+        for (int g = 0; g < nc; g += kAccPar * ps) {
+            AccGroup G[kAccPar];
+            int R = 0;
 #pragma unroll
-    for (int t = 0; t < U; ++t) {
-        const int64_t r = r0 + (int64_t)t * kAccBlock + threadIdx.x;
-        const int64_t rr = r < r1 ? r : last;
-        u[t] = OP == PVJP_ADD ? (uint64_t)reinterpret_cast<const uint32_t*>(rec)[rr] : rec[rr];
-        jb[t] = (uint32_t)rbin[rr];
-    }
-    for (int64_t base = r0; base < r1; base += kRound) {
-        const int64_t nbase = base + kRound;
-        if (nbase < r1) {
-#pragma unroll
-            for (int t = 0; t < U; ++t) {
-                const int64_t r = nbase + (int64_t)t * kAccBlock + threadIdx.x;
-                const int64_t rr = r < r1 ? r : last;
-                un[t] = OP == PVJP_ADD ? (uint64_t)reinterpret_cast<const uint32_t*>(rec)[rr] : rec[rr];
-                jn[t] = (uint32_t)rbin[rr];
+            for (int p = 0; p < kAccPar; ++p) {
+                const int first = g + p * ps;
+                const int count = nc - first < ps ? nc - first : ps;
+                G[p] = acc_group(dl, first, count);
+                R = G[p].pre[kAccGroup] > R ? G[p].pre[kAccGroup] : R;
             }
-        }
+            for (int r0 = 0; r0 < R; r0 += kAccSlots * kWave) {
+                uint32_t at[kAccPar * kAccSlots], vv[kAccPar * kAccSlots], bb[kAccPar * kAccSlots];
+                bool ok[kAccPar * kAccSlots];
 #pragma unroll
-        for (int t = 0; t < U; ++t) {
-            const int64_t r = base + (int64_t)t * kAccBlock + threadIdx.x;
-            if (r >= r1) continue;
-            if (OP == PVJP_ADD) {
-                const uint32_t j = jb[t];
-                atomicAdd(reinterpret_cast<double*>(&acc[j * kAccCopies + copy]),
-                          (double)__uint_as_float((uint32_t)u[t]));
-                if (COUNTS) atomicAdd(&cnt[j], 1);
-            } else {
-                atomicMax(reinterpret_cast<unsigned long long*>(&acc[jb[t] * kAccCopies + copy]),
-                          (unsigned long long)u[t]);
-                if (COUNTS) atomicAdd(&cnt[jb[t]], 1);
+                for (int s = 0; s < kAccPar * kAccSlots; ++s) {
+                    const int p = s / kAccSlots;
+                    const int r = r0 + (s % kAccSlots) * kWave + lane;
+                    ok[s] = r < G[p].pre[kAccGroup];
+                    // past the group's end a lane reads the chunk's first
+                    // slot (always allocated) and drops it: the loads stay
+                    // outside branches, so all of them are in flight at once
+                    at[s] = ok[s] ? acc_slot(G[p], r) : 0u;
+                    // a uniform base and a 32-bit byte offset per lane
+                    vv[s] = *reinterpret_cast<const uint32_t*>(cv + (at[s] << 2));
+                    bb[s] = KEYS ? *reinterpret_cast<const uint32_t*>(cb + (at[s] << 2))
+                                 : (uint32_t)*reinterpret_cast<const uint16_t*>(cb + (at[s] << 1));
+                }
+#pragma unroll
+                for (int s = 0; s < kAccPar * kAccSlots; ++s)
+                    if (ok[s]) acc_record<OP, COUNTS>(acc, cnt, copy, tbase, at[s], vv[s], bb[s]);
             }
-        }
-#pragma unroll
-        for (int t = 0; t < U; ++t) {
-            u[t] = un[t];
-            jb[t] = jn[t];
         }
     }
     __syncthreads();
@@ -840,7 +990,6 @@ __global__ __launch_bounds__(kAccBlock) void hpart_acc_kernel(const uint64_t* __
         if (COUNTS) pcnt[(int64_t)item * kPartBins + j] = cnt[j];
     }
 }
-
 template <int OP>
 __global__ __launch_bounds__(256) void hpart_merge_kernel(const uint64_t* __restrict__ pacc,
                                                           const int32_t* __restrict__ pcnt,
@@ -926,29 +1075,34 @@ static bool use_partition(int op, bool f32, int64_t m, bool counts) {
 }
 
 struct PartLayout {
-    int nb;
-    int64_t chunk, items_max;
-    size_t bcount, btotal, bstart, istart, rec, rbin, pacc, pcnt, total;
+    int nb, ntiles, nchunks;
+    int64_t items_max;
+    size_t toff, D, Ploc, ctot, clast, bitems, istart, itile, rval, rbin, pacc, pcnt, total;
 };
 
 static PartLayout part_layout(int64_t n, int64_t m) {
     PartLayout L{};
     L.nb = (int)ceil_div(m, kPartBins);
-    const int64_t quantum = 4 * kHistBlock;
-    L.chunk = ceil_div(ceil_div(n > 0 ? n : 1, kPartGrid), quantum) * quantum;
+    L.ntiles = (int)ceil_div(n > 0 ? n : 1, kTile);
+    L.nchunks = (int)ceil_div(L.ntiles, kColChunk);
     L.items_max = ceil_div(n > 0 ? n : 1, kPartSeg) + L.nb;
+    const size_t slots = (size_t)L.ntiles * kTile;
     size_t o = 0;
     auto take = [&](size_t bytes) {
         const size_t at = o;
         o += align_up(bytes, 256);
         return at;
     };
-    L.bcount = take((size_t)L.nb * kPartGrid * 4);
-    L.btotal = take((size_t)L.nb * 4);
-    L.bstart = take((size_t)(L.nb + 1) * 4);
+    L.toff = take((size_t)L.ntiles * (L.nb + 1) * 4);
+    L.D = take((size_t)L.nb * L.ntiles * 4);
+    L.Ploc = take((size_t)L.nb * L.ntiles * 4);
+    L.ctot = take((size_t)L.nb * L.nchunks * 4);
+    L.clast = take((size_t)L.nb * L.nchunks * 4);
+    L.bitems = take((size_t)L.nb * 4);
     L.istart = take((size_t)(L.nb + 1) * 4);
-    L.rec = take((size_t)(n > 0 ? n : 1) * 8);
-    L.rbin = take((size_t)(n > 0 ? n : 1) * 2);
+    L.itile = take((size_t)L.items_max * 4);
+    L.rval = take(slots * 4);
+    L.rbin = take(slots * 4);  // 2 bytes per record for +, 4 for min/max
     L.pacc = take((size_t)L.items_max * kPartBins * 8);
     L.pcnt = take((size_t)L.items_max * kPartBins * 4);
     L.total = o;
@@ -985,34 +1139,39 @@ static void run_partitioned(const int32_t* inds, const float* vs, int64_t n, int
                             size_t off, uint64_t* gacc, hipStream_t st) {
     const PartLayout L = part_layout(n, m);
     char* base = w + off;
-    int32_t* bcount = reinterpret_cast<int32_t*>(base + L.bcount);
-    int32_t* btotal = reinterpret_cast<int32_t*>(base + L.btotal);
-    int32_t* bstart = reinterpret_cast<int32_t*>(base + L.bstart);
+    int32_t* toff = reinterpret_cast<int32_t*>(base + L.toff);
+    uint32_t* D = reinterpret_cast<uint32_t*>(base + L.D);
+    int32_t* Ploc = reinterpret_cast<int32_t*>(base + L.Ploc);
+    int32_t* ctot = reinterpret_cast<int32_t*>(base + L.ctot);
+    int32_t* clast = reinterpret_cast<int32_t*>(base + L.clast);
+    int32_t* bitems = reinterpret_cast<int32_t*>(base + L.bitems);
     int32_t* istart = reinterpret_cast<int32_t*>(base + L.istart);
-    uint64_t* rec = reinterpret_cast<uint64_t*>(base + L.rec);
-    uint16_t* rbin = reinterpret_cast<uint16_t*>(base + L.rbin);
+    int32_t* itile = reinterpret_cast<int32_t*>(base + L.itile);
+    uint32_t* rval = reinterpret_cast<uint32_t*>(base + L.rval);
+    void* rbin = base + L.rbin;
     uint64_t* pacc = reinterpret_cast<uint64_t*>(base + L.pacc);
     int32_t* pcnt = reinterpret_cast<int32_t*>(base + L.pcnt);
-    const int G = kPartGrid;
     const bool vec = aligned(inds, 16) && aligned(vs, 16);
+    // n == 0 still runs one (empty) tile, so every table is written
     if (vec)
-        hipLaunchKernelGGL(hpart_count_kernel<true>, dim3(G), dim3(kHistBlock), 0, st, inds, n, m, L.chunk, L.nb, bcount);
+        hipLaunchKernelGGL((hpart_tile_kernel<OP, true>), dim3(L.ntiles), dim3(kTileThreads), 0, st, inds, vs, n, m,
+                           L.nb, rval, rbin, toff);
     else
-        hipLaunchKernelGGL(hpart_count_kernel<false>, dim3(G), dim3(kHistBlock), 0, st, inds, n, m, L.chunk, L.nb, bcount);
-    hipLaunchKernelGGL(hpart_scan_local_kernel, dim3(L.nb), dim3(kPartGrid), 0, st, bcount, btotal);
-    hipLaunchKernelGGL(hpart_scan_kernel, dim3(1), dim3(kPartScanThreads), 0, st, btotal, L.nb, bstart, istart);
-    if (vec)
-        hipLaunchKernelGGL((hpart_scatter_kernel<OP, true>), dim3(G), dim3(kHistBlock), 0, st, inds, vs, n, m, L.chunk,
-                           L.nb, bcount, bstart, rec, rbin);
-    else
-        hipLaunchKernelGGL((hpart_scatter_kernel<OP, false>), dim3(G), dim3(kHistBlock), 0, st, inds, vs, n, m, L.chunk,
-                           L.nb, bcount, bstart, rec, rbin);
+        hipLaunchKernelGGL((hpart_tile_kernel<OP, false>), dim3(L.ntiles), dim3(kTileThreads), 0, st, inds, vs, n, m,
+                           L.nb, rval, rbin, toff);
+    hipLaunchKernelGGL(hpart_colscan_kernel, dim3((unsigned)ceil_div(L.nb, kColThreads), L.nchunks),
+                       dim3(kColThreads), 0, st, toff, L.ntiles, L.nb, L.nchunks, D, Ploc, ctot, clast);
+    hipLaunchKernelGGL(hpart_bscan_kernel, dim3(L.nb), dim3(kBscanThreads), 0, st, ctot, clast, L.nchunks, bitems);
+    hipLaunchKernelGGL(hpart_scan_kernel, dim3(1), dim3(kPartScanThreads), 0, st, bitems, L.nb, istart);
+    hipLaunchKernelGGL(hpart_items_kernel, dim3((unsigned)ceil_div((int64_t)L.nb * L.ntiles, 256)), dim3(256), 0, st,
+                       Ploc, ctot, L.ntiles, L.nb, L.nchunks, istart, itile);
+    const unsigned agrid = (unsigned)(ceil_div(L.items_max, (int64_t)kXcds) * kXcds);
     if (count)
-        hipLaunchKernelGGL((hpart_acc_kernel<OP, true>), dim3((unsigned)L.items_max), dim3(kAccBlock), 0, st, rec, rbin,
-                           L.nb, bstart, istart, pacc, pcnt);
+        hipLaunchKernelGGL((hpart_acc_kernel<OP, true>), dim3(agrid), dim3(kAccBlock), 0, st, rval, rbin, L.nb,
+                           L.ntiles, D, istart, itile, pacc, pcnt);
     else
-        hipLaunchKernelGGL((hpart_acc_kernel<OP, false>), dim3((unsigned)L.items_max), dim3(kAccBlock), 0, st, rec,
-                           rbin, L.nb, bstart, istart, pacc, pcnt);
+        hipLaunchKernelGGL((hpart_acc_kernel<OP, false>), dim3(agrid), dim3(kAccBlock), 0, st, rval, rbin, L.nb,
+                           L.ntiles, D, istart, itile, pacc, pcnt);
     hipLaunchKernelGGL(hpart_merge_kernel<OP>, dim3(flat_grid(m, 256, 1)), dim3(256), 0, st, pacc,
                        count ? pcnt : nullptr, istart, m, gacc, count);
 }
@@ -1178,7 +1337,7 @@ extern "C" pvjp_status pvjp_hist_plan_info(pvjp_op op, pvjp_dtype dtype, int64_t
     if (use_partition(op, dtype == PVJP_F32, m, counts != 0)) {
         info[0] = PVJP_HIST_PATH_PARTITION;
         info[1] = kPartBins;
-        info[2] = kPartSeg;
+        info[2] = kPartSeg + kTile;  // runs start within kPartSeg records; a run is below kTile
         info[3] = ceil_div(m, kPartBins);
     } else {
         info[0] = hist_plan(op, n, m, counts != 0).cache ? PVJP_HIST_PATH_CACHE : PVJP_HIST_PATH_LDS;
