@@ -829,7 +829,7 @@ __global__ __launch_bounds__(256) void hpart_items_kernel(const int32_t* __restr
 // whatever the run lengths, and each lane has kAccPar * kAccSlots records
 // in flight.
 constexpr int kAccBlock = 1024;
-constexpr int kAccCopies = 4;
+constexpr int kAccCopies = 2;
 constexpr int kXcds = 8;  // accelerator dies of an MI355X, each with its own L2
 constexpr int kXcdMapBuckets = 128;
 constexpr int kAccGroup = 8;
