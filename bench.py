@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 23, help="elements per instance for the CPU oracle")
     ap.add_argument("--skip", default="", help="comma list of extra workloads to skip: reduce_map,reduce_generic,scan_generic,jvp,kmeans,"
-                         "gather_map,scan_batched,sparse_kmeans,hist_lae,scan,gmm,batch,serve")
+                         "gather_map,scan_batched,sparse_kmeans,hist_lae,hist_generic,scan,gmm,batch,serve")
     ap.add_argument("--only", default="",
                     help="run just this one extra workload (for profiling) and print its JSON instead of the "
                          "benchmark line")
@@ -239,7 +239,7 @@ def main():
         fns = {"reduce_map": bench_reduce_map, "reduce_generic": bench_reduce_generic,
                "scan_generic": bench_scan_generic, "jvp": bench_jvp, "kmeans": bench_kmeans, "gather_map": bench_gather_map,
                "scan_batched": bench_scan_batched, "sparse_kmeans": bench_sparse_kmeans, "hist_lae": bench_hist_lae,
-               "scan": bench_scan,
+               "hist_generic": bench_hist_generic, "scan": bench_scan,
                "gmm": bench_gmm, "batch": bench_batch, "serve": bench_serve}
         print(json.dumps({args.only: fns[args.only](args)}))
         return
@@ -432,7 +432,8 @@ def main():
     for name, fn in (("reduce_map", bench_reduce_map), ("reduce_generic", bench_reduce_generic),
                      ("scan_generic", bench_scan_generic), ("jvp", bench_jvp), ("kmeans", bench_kmeans),
                      ("gather_map", bench_gather_map), ("scan_batched", bench_scan_batched),
-                     ("sparse_kmeans", bench_sparse_kmeans), ("hist_lae", bench_hist_lae), ("scan", bench_scan), ("gmm", bench_gmm),
+                     ("sparse_kmeans", bench_sparse_kmeans), ("hist_lae", bench_hist_lae),
+                     ("hist_generic", bench_hist_generic), ("scan", bench_scan), ("gmm", bench_gmm),
                      ("batch", bench_batch), ("serve", bench_serve)):
         if name in args.skip:
             continue
@@ -852,6 +853,39 @@ def bench_hist_lae(args):
             "primal_hbm_frac": round((8 * n + 4 * m) / (tp * 1e-3) / 8e12, 3),
             "vjp_hbm_frac": round((12 * n + 8 * m) / (tv * 1e-3) / 8e12, 3)}
         del inds, x, hb, hs, xb
+    return res
+
+
+def bench_hist_generic(args):
+    """reduce_by_index with a general, non-commuting operator (the linear
+    recurrence, K = 2, and the 2x2 matrix product, K = 4) at n = 2^26 FP32,
+    m = 2^16 bins, uniform indices: stable sort by bin, segmented scans.
+    Algorithmic bytes: primal 4 + 4 K per element + 4 K per bin; VJP 4 + 8 K
+    per element (indices and x read, x_bar written) + 4 K per bin."""
+    import torch
+
+    from paper_2202_10297_amd import ops, workloads
+
+    n, m = 1 << 26, 1 << 16
+    res = {}
+    for op in ("linrec", "mat2"):
+        inds, xs, hb = workloads.hist_generic(op, n, m, "uniform", "f32", seed=0)
+        di = torch.from_numpy(inds).cuda()
+        dx = [torch.from_numpy(x).cuda() for x in xs]
+        dh = [torch.from_numpy(h).cuda() for h in hb]
+        del inds, xs, hb
+        K = len(dx)
+        ops.hist_generic(op, di, dx, m)
+        xb = [torch.empty_like(x) for x in dx]
+        tp = _events_ms(lambda: ops.hist_generic(op, di, dx, m), 5)
+        tv = _events_ms(lambda: ops.hist_generic_vjp(op, di, dx, dh, x_bar=xb), 5)
+        res[f"{op}_m2^16_uniform"] = {
+            "primal_ms": round(tp, 3), "vjp_ms": round(tv, 3), "grad_over_primal": round((tp + tv) / tp, 3),
+            "primal_elems_per_s": round(n / (tp * 1e-3), 1), "vjp_elems_per_s": round(n / (tv * 1e-3), 1),
+            "primal_hbm_frac": round(((4 + 4 * K) * n + 4 * K * m) / (tp * 1e-3) / 8e12, 4),
+            "vjp_hbm_frac": round(((4 + 8 * K) * n + 4 * K * m) / (tv * 1e-3) / 8e12, 4)}
+        del di, dx, dh, xb
+        torch.cuda.empty_cache()
     return res
 
 

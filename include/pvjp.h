@@ -652,6 +652,33 @@ pvjp_status pvjp_hist_lae(pvjp_dtype dtype, const int32_t* inds, const void* x, 
 pvjp_status pvjp_hist_lae_vjp(pvjp_dtype dtype, const int32_t* inds, const void* x, int64_t n, int64_t m,
                               const void* hs, const void* hs_bar, void* x_bar, int accumulate, void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* reduce_by_index with a general associative operator (Sec. 5.1.2 with the   */
+/* general rule of Sec. 5.1.1 inside each bin); the operator need not commute */
+/* ------------------------------------------------------------------------ */
+
+/* hs[b] = x_{i_1} (.) x_{i_2} (.) ... over the elements with inds[i] = b in
+ * increasing index order i_1 < i_2 < ...; the neutral element for an empty
+ * bin; indices outside [0, m) are skipped.  Operators and the component
+ * layout are those of pvjp_reduce_generic (x, hs: host arrays of K device
+ * pointers, to n and m elements of dtype); inds [n] int32; 1 <= m <= 2^24,
+ * n < 2^31.  The elements are stably sorted by bin, each bin is folded by a
+ * segmented scan; folds in FP64 for both dtypes.  ws: device memory owned by
+ * the caller, 256-byte aligned, no initialisation needed, at least
+ * pvjp_hist_generic_ws_bytes bytes (else PVJP_ENOMEM): about 16n bytes plus
+ * per-chunk digit counts and per-tile states.  Deterministic. */
+size_t pvjp_hist_generic_ws_bytes(pvjp_gop op, pvjp_dtype dtype, int64_t n, int64_t m);
+pvjp_status pvjp_hist_generic(pvjp_gop op, pvjp_dtype dtype, const int32_t* inds, const void* const* x, int64_t n,
+                              int64_t m, void* const* hs, void* ws, size_t ws_bytes, void* stream);
+/* x_bar_i (+)= (d(ls_i (.) x_i (.) rs_i)/dx_i)^T hs_bar[b] for b = inds[i],
+ * with ls_i and rs_i the folds of the bin's elements before and after i (the
+ * reduce rule inside each bin, y_bar = the bin's hs_bar); 0 for an index out
+ * of range.  hs_bar: K device pointers to m elements; x_bar: K device
+ * pointers to n elements, overwritten (accumulate = 0) or added to. */
+pvjp_status pvjp_hist_generic_vjp(pvjp_gop op, pvjp_dtype dtype, const int32_t* inds, const void* const* x,
+                                  int64_t n, int64_t m, const void* const* hs_bar, void* const* x_bar,
+                                  int accumulate, void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

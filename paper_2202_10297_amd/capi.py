@@ -95,6 +95,9 @@ SIGNATURES = {
     "pvjp_hist_lae_ws_bytes": (_Z, [_I, _L, _L]),
     "pvjp_hist_lae": (_I, [_I, _P, _P, _L, _L, _P, _P, _Z, _P]),
     "pvjp_hist_lae_vjp": (_I, [_I, _P, _P, _L, _L, _P, _P, _P, _I, _P]),
+    "pvjp_hist_generic_ws_bytes": (_Z, [_I, _I, _L, _L]),
+    "pvjp_hist_generic": (_I, [_I, _I, _P, _P, _L, _L, _P, _P, _Z, _P]),
+    "pvjp_hist_generic_vjp": (_I, [_I, _I, _P, _P, _L, _L, _P, _P, _I, _P, _Z, _P]),
     "pvjp_sparse_kmeans_objective": (_I, [_P, _P, _P, _L, _L, _L, _P, _I, _P, _P, _P, _Z, _P]),
     "pvjp_sparse_kmeans_vjp": (_I, [_P, _P, _P, _L, _L, _L, _P, _I, _P, ctypes.c_double, _P, _P, _P, _I, _P, _Z,
                                     _P]),

@@ -1,0 +1,622 @@
+// reduce_by_index with a general associative operator (Sec. 5.1.2, with the
+// general rule of Sec. 5.1.1 inside every bin) and its VJP.
+//
+// hs[b] = the fold, in index order, of the elements i with inds[i] = b (the
+// neutral element for an empty bin; indices outside [0, m) are skipped).
+// The operator need not commute, so each bin's elements must meet in index
+// order:
+//   1. a stable sort of the in-range elements by bin: one or two passes of a
+//      12-bit digit, low digit first, each a per-chunk digit count, a
+//      digit-major scan of the counts and a stable scatter in which one wave
+//      walks its chunk in index order (ranks among equal digits from wave
+//      ballots, so equal bins keep their order);
+//   2. bin starts, by binary search of the sorted bins;
+//   3. over the sorted elements, segmented exclusive scans: forward (the
+//      fold of the bin's earlier elements, ls) and reversed (of its later
+//      ones, rs), with the usual lifted operator that restarts at a flagged
+//      element (a bin's first element forward, its last one reversed), over
+//      fixed tiles in three passes: tile folds, one block scanning the tile
+//      folds, then per tile the in-tile scans with the tile's carry;
+//   4. the primal writes each bin's fold at its last element; the VJP maps
+//      f(ls, x, rs, hs_bar[bin]) (the reduce rule, y_bar = the bin's hs_bar)
+//      over the sorted elements and writes it at the element's own index.
+// Folds are formed in FP64 for FP32 and FP64 data alike.
+#include <algorithm>
+
+#include "common.h"
+#include "gops.h"
+#include "prims.h"
+
+namespace pvjp {
+
+constexpr int kHgDigitBits = 12;
+constexpr int kHgDigits = 1 << kHgDigitBits;
+constexpr int64_t kHgChunk = 32768;  // elements per sort chunk (one block)
+constexpr int kHgCountBlock = 256;
+constexpr int kHgColChunk = 64;      // sort chunks per column-scan chunk
+constexpr int kHgScanThreads = 1024;
+constexpr int kHgBlock = 256;
+constexpr int kHgIpt = 4;
+constexpr int kHgTile = kHgBlock * kHgIpt;
+constexpr size_t kHgSlot = 64;       // bytes per tile for a lifted state
+constexpr int64_t kHgMaxBins = (int64_t)1 << (2 * kHgDigitBits);
+
+// ------------------------------------------------------------------ sort
+// Digit counts of one chunk (any order: counting needs no stability).  The
+// first pass reads the indices (out-of-range ones skipped), the second the
+// first pass's output, whose length is on the device.
+__global__ __launch_bounds__(kHgCountBlock) void hg_count_kernel(const int32_t* __restrict__ keys, int64_t n,
+                                                                 const int32_t* __restrict__ nvalid, int32_t m,
+                                                                 int shift, int ndig, int32_t* __restrict__ cntb) {
+    __shared__ int32_t cnt[kHgDigits];
+    for (int d = threadIdx.x; d < ndig; d += kHgCountBlock) cnt[d] = 0;
+    __syncthreads();
+    const int64_t ne = nvalid ? (int64_t)*nvalid : n;
+    const int64_t lo = (int64_t)blockIdx.x * kHgChunk;
+    const int64_t hi = (lo + kHgChunk < ne) ? lo + kHgChunk : ne;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kHgCountBlock) {
+        const int32_t k = keys[i];
+        if ((uint32_t)k < (uint32_t)m) atomicAdd(&cnt[(k >> shift) & (kHgDigits - 1)], 1);
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < ndig; d += kHgCountBlock) cntb[(int64_t)blockIdx.x * kHgDigits + d] = cnt[d];
+}
+
+// Per digit (a thread) and column chunk of kHgColChunk sort chunks (grid y):
+// the count of each chunk is replaced by the sum of the earlier chunks'
+// counts in the column chunk, whose total goes to ctot[c][d].
+__global__ __launch_bounds__(kHgCountBlock) void hg_colscan_kernel(int32_t* __restrict__ cntb, int nblk, int ndig,
+                                                                   int32_t* __restrict__ ctot) {
+    const int d = blockIdx.x * kHgCountBlock + (int)threadIdx.x;
+    const int c = blockIdx.y;
+    if (d >= ndig) return;
+    int v[kHgColChunk];
+#pragma unroll
+    for (int j = 0; j < kHgColChunk; ++j) {
+        const int b = c * kHgColChunk + j;
+        v[j] = b < nblk ? cntb[(int64_t)b * kHgDigits + d] : 0;
+    }
+    int run = 0;
+#pragma unroll
+    for (int j = 0; j < kHgColChunk; ++j) {
+        const int b = c * kHgColChunk + j;
+        if (b < nblk) cntb[(int64_t)b * kHgDigits + d] = run;
+        run += v[j];
+    }
+    ctot[(int64_t)c * kHgDigits + d] = run;
+}
+
+// One block: ctot[c][d] becomes the start of (column chunk c, digit d) in the
+// sorted output (the digit's start plus its earlier column chunks), and the
+// number of sorted elements is written once.
+__global__ __launch_bounds__(kHgScanThreads) void hg_digitscan_kernel(int32_t* __restrict__ ctot, int nchunks,
+                                                                      int ndig, int32_t* __restrict__ nvalid) {
+    __shared__ IntSum::S wtot[kHgScanThreads / kWave];
+    constexpr int DPT = kHgDigits / kHgScanThreads;
+    int tot[DPT], sum = 0;
+#pragma unroll
+    for (int u = 0; u < DPT; ++u) {
+        const int d = DPT * (int)threadIdx.x + u;
+        int run = 0;
+        if (d < ndig) {
+            for (int c = 0; c < nchunks; ++c) {
+                int32_t* p = ctot + (int64_t)c * kHgDigits + d;
+                const int v = *p;
+                *p = run;
+                run += v;
+            }
+        }
+        tot[u] = run;
+        sum += run;
+    }
+    IntSum::S all;
+    int start = block_exclusive_scan<IntSum, kHgScanThreads, false>(IntSum::S{sum}, all, wtot).v;
+#pragma unroll
+    for (int u = 0; u < DPT; ++u) {
+        const int d = DPT * (int)threadIdx.x + u;
+        if (d < ndig)
+            for (int c = 0; c < nchunks; ++c) ctot[(int64_t)c * kHgDigits + d] += start;
+        start += tot[u];
+    }
+    if (threadIdx.x == 0 && nvalid) *nvalid = all.v;
+}
+
+// Stable scatter of one chunk by one wave, 64 elements at a time in index
+// order.  Lanes with equal digits find each other with one ballot per digit
+// bit; a lane's rank among them and the digit's running position (LDS) give
+// its place, and the group's last such lane advances the position.
+__global__ __launch_bounds__(kWave) void hg_scatter_kernel(const int32_t* __restrict__ keys_in,
+                                                           const int32_t* __restrict__ perm_in, int64_t n,
+                                                           const int32_t* __restrict__ nvalid, int32_t m, int shift,
+                                                           int ndig, int nbits, const int32_t* __restrict__ cntb,
+                                                           const int32_t* __restrict__ ctot,
+                                                           int32_t* __restrict__ keys_out,
+                                                           int32_t* __restrict__ perm_out) {
+    __shared__ int32_t pos[kHgDigits];
+    const int lane = threadIdx.x;
+    const int blk = blockIdx.x;
+    const int c = blk / kHgColChunk;
+    for (int d = lane; d < ndig; d += kWave)
+        pos[d] = ctot[(int64_t)c * kHgDigits + d] + cntb[(int64_t)blk * kHgDigits + d];
+    __syncthreads();
+    const int64_t ne = nvalid ? (int64_t)*nvalid : n;
+    const int64_t lo = (int64_t)blk * kHgChunk;
+    const int64_t hi = (lo + kHgChunk < ne) ? lo + kHgChunk : ne;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    constexpr int U = 4;  // groups whose loads are in flight together
+    for (int64_t g0 = lo; g0 < hi; g0 += (int64_t)U * kWave) {
+        int32_t k[U], src[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = g0 + (int64_t)u * kWave + lane;
+            k[u] = i < hi ? keys_in[i] : -1;
+            src[u] = i < hi ? (perm_in ? perm_in[i] : (int32_t)i) : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool valid = (uint32_t)k[u] < (uint32_t)m;
+            const int d = valid ? (k[u] >> shift) & (kHgDigits - 1) : 0;
+            uint64_t peers = __ballot(valid);
+            for (int bit = 0; bit < nbits; ++bit) {
+                const bool one = (d >> bit) & 1;
+                const uint64_t b = __ballot(valid && one);
+                peers &= one ? b : ~b;
+            }
+            const int base = valid ? pos[d] : 0;
+            const int rank = __popcll(peers & below);
+            if (valid) {
+                const int at = base + rank;
+                keys_out[at] = k[u];
+                perm_out[at] = src[u];
+                // the highest lane of the group moves the digit's position on
+                if ((peers >> lane) == 1ull) pos[d] = base + __popcll(peers);
+            }
+        }
+    }
+}
+
+// off[b] = the first sorted position whose bin is b or later (b in [0, m]).
+__global__ __launch_bounds__(256) void hg_off_kernel(const int32_t* __restrict__ keys,
+                                                     const int32_t* __restrict__ nvalid, int32_t m,
+                                                     int32_t* __restrict__ off) {
+    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (b > m) return;
+    int64_t lo = 0, hi = *nvalid;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)keys[mid] < b) lo = mid + 1; else hi = mid;
+    }
+    off[b] = (int32_t)lo;
+}
+
+// --------------------------------------------------- segmented fold scans
+// The lifted operator: a state remembers whether it holds a flagged element,
+// and a later flagged state discards everything before it.
+template <class Q>
+struct SegOf {
+    using QS = typename Q::S;
+    struct S {
+        QS v;
+        uint32_t f, pad;
+    };
+    __device__ static __forceinline__ S id() { return S{Q::id(), 0u, 0u}; }
+    __device__ static __forceinline__ S comb(S x, S y) { return y.f ? y : S{Q::comb(x.v, y.v), x.f, 0u}; }
+    __device__ static __forceinline__ S up(S v, int d) {
+        return S{Q::up(v.v, d), (uint32_t)shfl_up1((int)v.f, d), 0u};
+    }
+    __device__ static __forceinline__ S down(S v, int d) {
+        return S{Q::down(v.v, d), (uint32_t)shfl_down1((int)v.f, d), 0u};
+    }
+};
+
+template <class T>
+struct HgIn {
+    const T* p[4];
+};
+template <class T>
+struct HgOut {
+    T* p[4];
+};
+
+// Sorted element p: its bin and its components (as FP64), plus whether it
+// opens (first) and closes (last) its bin.
+template <class Op, class T>
+struct HgElem {
+    int32_t key, src;
+    bool first, last;
+    typename Op::S a;
+};
+
+template <class Op, class T>
+__device__ __forceinline__ HgElem<Op, T> hg_elem(const int32_t* __restrict__ keys, const int32_t* __restrict__ perm,
+                                                 const HgIn<T>& x, int64_t nv, int64_t p) {
+    HgElem<Op, T> e;
+    e.key = keys[p];
+    e.src = perm[p];
+    e.first = p == 0 || keys[p - 1] != e.key;
+    e.last = p + 1 == nv || keys[p + 1] != e.key;
+    double c[Op::K];
+#pragma unroll
+    for (int k = 0; k < Op::K; ++k) c[k] = (double)x.p[k][e.src];
+    e.a = Op::elem(c);
+    return e;
+}
+
+// Tile folds, forward (flag: the bin's first element) and reversed (flag:
+// its last element, scanned with the operands exchanged).
+template <class Op, class T>
+__global__ __launch_bounds__(kHgBlock) void hg_tile_fold_kernel(const int32_t* __restrict__ keys,
+                                                                const int32_t* __restrict__ perm, HgIn<T> x,
+                                                                const int32_t* __restrict__ nvalid, char* __restrict__ aggF,
+                                                                char* __restrict__ aggR) {
+    using F = SegOf<Op>;
+    using R = SegOf<Flip<Op>>;
+    __shared__ typename F::S wf[kHgBlock / kWave];
+    __shared__ typename R::S wr[kHgBlock / kWave];
+    const int64_t nv = *nvalid;
+    const int64_t p0 = (int64_t)blockIdx.x * kHgTile + (int64_t)threadIdx.x * kHgIpt;
+    typename F::S sf = F::id();
+    typename R::S sr = R::id();
+    typename R::S re[kHgIpt];
+#pragma unroll
+    for (int j = 0; j < kHgIpt; ++j) {
+        re[j] = R::id();
+        if (p0 + j < nv) {
+            const HgElem<Op, T> e = hg_elem<Op, T>(keys, perm, x, nv, p0 + j);
+            sf = F::comb(sf, typename F::S{e.a, e.first ? 1u : 0u, 0u});
+            re[j] = typename R::S{e.a, e.last ? 1u : 0u, 0u};
+        }
+    }
+#pragma unroll
+    for (int j = kHgIpt - 1; j >= 0; --j) sr = R::comb(sr, re[j]);
+    typename F::S tf;
+    typename R::S tr;
+    block_exclusive_scan<F, kHgBlock, false>(sf, tf, wf);
+    block_exclusive_scan<R, kHgBlock, true>(sr, tr, wr);
+    if (threadIdx.x == 0) {
+        *reinterpret_cast<typename F::S*>(aggF + (size_t)blockIdx.x * kHgSlot) = tf;
+        *reinterpret_cast<typename R::S*>(aggR + (size_t)blockIdx.x * kHgSlot) = tr;
+    }
+}
+
+// One block: each tile's carry, the lifted fold of all tiles before it
+// (forward) and after it (reversed).  Thread t owns a contiguous run of tiles.
+template <class Op>
+__global__ __launch_bounds__(kHgScanThreads) void hg_tile_scan_kernel(const char* __restrict__ aggF,
+                                                                      const char* __restrict__ aggR, int64_t ntiles,
+                                                                      char* __restrict__ carF, char* __restrict__ carR) {
+    using F = SegOf<Op>;
+    using R = SegOf<Flip<Op>>;
+    __shared__ typename F::S wf[kHgScanThreads / kWave];
+    __shared__ typename R::S wr[kHgScanThreads / kWave];
+    const int64_t per = (ntiles + kHgScanThreads - 1) / kHgScanThreads;
+    const int64_t t0 = (int64_t)threadIdx.x * per;
+    const int64_t t1 = (t0 + per < ntiles) ? t0 + per : ntiles;
+    auto getF = [&](int64_t t) { return *reinterpret_cast<const typename F::S*>(aggF + (size_t)t * kHgSlot); };
+    auto getR = [&](int64_t t) { return *reinterpret_cast<const typename R::S*>(aggR + (size_t)t * kHgSlot); };
+    typename F::S sf = F::id();
+    typename R::S sr = R::id();
+    for (int64_t t = t0; t < t1; ++t) sf = F::comb(sf, getF(t));
+    for (int64_t t = t1 - 1; t >= t0; --t) sr = R::comb(sr, getR(t));
+    typename F::S tf;
+    typename R::S tr;
+    sf = block_exclusive_scan<F, kHgScanThreads, false>(sf, tf, wf);
+    sr = block_exclusive_scan<R, kHgScanThreads, true>(sr, tr, wr);
+    for (int64_t t = t0; t < t1; ++t) {
+        *reinterpret_cast<typename F::S*>(carF + (size_t)t * kHgSlot) = sf;
+        sf = F::comb(sf, getF(t));
+    }
+    for (int64_t t = t1 - 1; t >= t0; --t) {
+        *reinterpret_cast<typename R::S*>(carR + (size_t)t * kHgSlot) = sr;
+        sr = R::comb(sr, getR(t));
+    }
+}
+
+// Per tile: the forward scan with the tile's carry; the primal writes each
+// bin's fold at its last element.  The VJP also runs the reversed scan and
+// maps f over (ls, x, rs) with y_bar = hs_bar of the element's bin.
+template <class Op, class T, bool VJP, bool ACC>
+__global__ __launch_bounds__(kHgBlock) void hg_apply_kernel(const int32_t* __restrict__ keys,
+                                                            const int32_t* __restrict__ perm, HgIn<T> x,
+                                                            const int32_t* __restrict__ nvalid,
+                                                            const char* __restrict__ carF,
+                                                            const char* __restrict__ carR, HgOut<T> hs,
+                                                            HgIn<T> hs_bar, HgOut<T> x_bar) {
+    using F = SegOf<Op>;
+    using R = SegOf<Flip<Op>>;
+    using QS = typename Op::S;
+    __shared__ typename F::S wf[kHgBlock / kWave];
+    __shared__ typename R::S wr[kHgBlock / kWave];
+    const int64_t nv = *nvalid;
+    const int64_t p0 = (int64_t)blockIdx.x * kHgTile + (int64_t)threadIdx.x * kHgIpt;
+    HgElem<Op, T> e[kHgIpt];
+    bool in[kHgIpt];
+    typename F::S sf = F::id();
+#pragma unroll
+    for (int j = 0; j < kHgIpt; ++j) {
+        in[j] = p0 + j < nv;
+        if (in[j]) {
+            e[j] = hg_elem<Op, T>(keys, perm, x, nv, p0 + j);
+            sf = F::comb(sf, typename F::S{e[j].a, e[j].first ? 1u : 0u, 0u});
+        }
+    }
+    typename F::S tf;
+    typename F::S xf = block_exclusive_scan<F, kHgBlock, false>(sf, tf, wf);
+    xf = F::comb(*reinterpret_cast<const typename F::S*>(carF + (size_t)blockIdx.x * kHgSlot), xf);
+    if (!VJP) {
+#pragma unroll
+        for (int j = 0; j < kHgIpt; ++j) {
+            if (!in[j]) continue;
+            xf = F::comb(xf, typename F::S{e[j].a, e[j].first ? 1u : 0u, 0u});
+            if (e[j].last) {
+                double out[Op::K];
+                Op::value(xf.v, out);
+#pragma unroll
+                for (int k = 0; k < Op::K; ++k) hs.p[k][e[j].key] = (T)out[k];
+            }
+        }
+        return;
+    }
+    QS ls[kHgIpt], la[kHgIpt];
+#pragma unroll
+    for (int j = 0; j < kHgIpt; ++j) {
+        if (!in[j]) continue;
+        ls[j] = e[j].first ? Op::id() : xf.v;
+        la[j] = Op::comb(ls[j], e[j].a);
+        xf = F::comb(xf, typename F::S{e[j].a, e[j].first ? 1u : 0u, 0u});
+    }
+    typename R::S sr = R::id();
+#pragma unroll
+    for (int j = kHgIpt - 1; j >= 0; --j)
+        if (in[j]) sr = R::comb(sr, typename R::S{e[j].a, e[j].last ? 1u : 0u, 0u});
+    typename R::S tr;
+    typename R::S xr = block_exclusive_scan<R, kHgBlock, true>(sr, tr, wr);
+    xr = R::comb(*reinterpret_cast<const typename R::S*>(carR + (size_t)blockIdx.x * kHgSlot), xr);
+#pragma unroll
+    for (int j = kHgIpt - 1; j >= 0; --j) {
+        if (!in[j]) continue;
+        const QS rs = e[j].last ? Op::id() : xr.v;
+        double yb[Op::K], out[Op::K];
+#pragma unroll
+        for (int k = 0; k < Op::K; ++k) yb[k] = (double)hs_bar.p[k][e[j].key];
+        Op::vjp(ls[j], e[j].a, rs, la[j], yb, out);
+#pragma unroll
+        for (int k = 0; k < Op::K; ++k) {
+            T* dst = x_bar.p[k] + e[j].src;
+            *dst = ACC ? (T)((double)*dst + out[k]) : (T)out[k];
+        }
+        xr = R::comb(xr, typename R::S{e[j].a, e[j].last ? 1u : 0u, 0u});
+    }
+}
+
+// Empty bins hold the neutral element.
+template <class Op, class T>
+__global__ __launch_bounds__(256) void hg_empty_kernel(const int32_t* __restrict__ off, int32_t m, HgOut<T> hs) {
+    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (b >= m || off[b] != off[b + 1]) return;
+    double out[Op::K];
+    Op::value(Op::id(), out);
+#pragma unroll
+    for (int k = 0; k < Op::K; ++k) hs.p[k][b] = (T)out[k];
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void hg_zero_kernel(HgOut<T> x, int K, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        for (int k = 0; k < K; ++k) x.p[k][i] = T(0);
+}
+
+// ------------------------------------------------------------------ host
+static int hg_components(pvjp_gop op) {
+    return op == PVJP_GOP_LOGADDEXP ? 1 : op == PVJP_GOP_LINREC ? 2 : op == PVJP_GOP_MAT2 ? 4 : 0;
+}
+
+struct HgLayout {
+    int64_t nblk, nchunks, ntiles;
+    size_t cntb, ctot, nvalid, keysA, permA, keysB, permB, off, aggF, aggR, carF, carR, total;
+};
+
+static HgLayout hg_layout(int64_t n, int64_t m) {
+    HgLayout L{};
+    const int64_t nn = n > 0 ? n : 1;
+    L.nblk = ceil_div(nn, kHgChunk);
+    L.nchunks = ceil_div(L.nblk, kHgColChunk);
+    L.ntiles = ceil_div(nn, kHgTile);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += align_up(bytes, 256);
+        return at;
+    };
+    L.cntb = take((size_t)L.nblk * kHgDigits * 4);
+    L.ctot = take((size_t)L.nchunks * kHgDigits * 4);
+    L.nvalid = take(4);
+    L.keysA = take((size_t)nn * 4);
+    L.permA = take((size_t)nn * 4);
+    L.keysB = take((size_t)nn * 4);
+    L.permB = take((size_t)nn * 4);
+    L.off = take((size_t)(m + 1) * 4);
+    L.aggF = take((size_t)L.ntiles * kHgSlot);
+    L.aggR = take((size_t)L.ntiles * kHgSlot);
+    L.carF = take((size_t)L.ntiles * kHgSlot);
+    L.carR = take((size_t)L.ntiles * kHgSlot);
+    L.total = o;
+    return L;
+}
+
+// The sort, the bin starts and the tile carries, shared by both entry points.
+// Returns the sorted bins and element indices.
+template <class Op, class T>
+static void hg_prepare(const int32_t* inds, int64_t n, int32_t m, const HgIn<T>& x, char* w, const HgLayout& L,
+                       const int32_t** keys, const int32_t** perm, hipStream_t st) {
+    int32_t* cntb = reinterpret_cast<int32_t*>(w + L.cntb);
+    int32_t* ctot = reinterpret_cast<int32_t*>(w + L.ctot);
+    int32_t* nvalid = reinterpret_cast<int32_t*>(w + L.nvalid);
+    int32_t* kA = reinterpret_cast<int32_t*>(w + L.keysA);
+    int32_t* pA = reinterpret_cast<int32_t*>(w + L.permA);
+    int32_t* kB = reinterpret_cast<int32_t*>(w + L.keysB);
+    int32_t* pB = reinterpret_cast<int32_t*>(w + L.permB);
+    const int passes = m > kHgDigits ? 2 : 1;
+    const int32_t* kin = inds;
+    const int32_t* pin = nullptr;
+    for (int pass = 0; pass < passes; ++pass) {
+        const int shift = pass * kHgDigitBits;
+        const int ndig = pass == 0 ? (int)std::min<int64_t>(m, kHgDigits) : (int)ceil_div(m, kHgDigits);
+        int nbits = 0;
+        while ((1 << nbits) < ndig) ++nbits;
+        int32_t* kout = pass == 0 ? kA : kB;
+        int32_t* pout = pass == 0 ? pA : pB;
+        const int32_t* nv = pass == 0 ? nullptr : nvalid;
+        hipLaunchKernelGGL(hg_count_kernel, dim3((unsigned)L.nblk), dim3(kHgCountBlock), 0, st, kin, n, nv, m, shift,
+                           ndig, cntb);
+        hipLaunchKernelGGL(hg_colscan_kernel, dim3((unsigned)ceil_div(ndig, kHgCountBlock), (unsigned)L.nchunks),
+                           dim3(kHgCountBlock), 0, st, cntb, (int)L.nblk, ndig, ctot);
+        hipLaunchKernelGGL(hg_digitscan_kernel, dim3(1), dim3(kHgScanThreads), 0, st, ctot, (int)L.nchunks, ndig,
+                           pass == 0 ? nvalid : nullptr);
+        hipLaunchKernelGGL(hg_scatter_kernel, dim3((unsigned)L.nblk), dim3(kWave), 0, st, kin, pin, n, nv, m, shift,
+                           ndig, nbits, cntb, ctot, kout, pout);
+        kin = kout;
+        pin = pout;
+    }
+    *keys = kin;
+    *perm = pin;
+    hipLaunchKernelGGL((hg_tile_fold_kernel<Op, T>), dim3((unsigned)L.ntiles), dim3(kHgBlock), 0, st, kin, pin, x,
+                       nvalid, w + L.aggF, w + L.aggR);
+    hipLaunchKernelGGL(hg_tile_scan_kernel<Op>, dim3(1), dim3(kHgScanThreads), 0, st, w + L.aggF, w + L.aggR,
+                       L.ntiles, w + L.carF, w + L.carR);
+}
+
+template <class Op, class T>
+static void hg_primal(const int32_t* inds, int64_t n, int32_t m, const void* const* x, void* const* hs, char* w,
+                      hipStream_t st) {
+    const HgLayout L = hg_layout(n, m);
+    HgIn<T> xi{};
+    HgOut<T> ho{};
+    for (int k = 0; k < Op::K; ++k) {
+        xi.p[k] = n > 0 ? (const T*)x[k] : nullptr;
+        ho.p[k] = (T*)hs[k];
+    }
+    const int32_t *keys, *perm;
+    hg_prepare<Op, T>(inds, n, m, xi, w, L, &keys, &perm, st);
+    int32_t* nvalid = reinterpret_cast<int32_t*>(w + L.nvalid);
+    int32_t* off = reinterpret_cast<int32_t*>(w + L.off);
+    hipLaunchKernelGGL(hg_off_kernel, dim3((unsigned)ceil_div((int64_t)m + 1, 256)), dim3(256), 0, st, keys, nvalid,
+                       m, off);
+    hipLaunchKernelGGL((hg_apply_kernel<Op, T, false, false>), dim3((unsigned)L.ntiles), dim3(kHgBlock), 0, st, keys,
+                       perm, xi, nvalid, w + L.carF, w + L.carR, ho, HgIn<T>{}, HgOut<T>{});
+    hipLaunchKernelGGL((hg_empty_kernel<Op, T>), dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, off, m, ho);
+}
+
+template <class Op, class T>
+static void hg_vjp(const int32_t* inds, int64_t n, int32_t m, const void* const* x, const void* const* hs_bar,
+                   void* const* x_bar, bool acc, char* w, hipStream_t st) {
+    const HgLayout L = hg_layout(n, m);
+    HgIn<T> xi{}, hb{};
+    HgOut<T> xb{};
+    for (int k = 0; k < Op::K; ++k) {
+        xi.p[k] = (const T*)x[k];
+        hb.p[k] = (const T*)hs_bar[k];
+        xb.p[k] = (T*)x_bar[k];
+    }
+    if (!acc)  // elements outside [0, m) get a zero adjoint
+        hipLaunchKernelGGL(hg_zero_kernel<T>, dim3(flat_grid(n, 256, 4)), dim3(256), 0, st, xb, Op::K, n);
+    const int32_t *keys, *perm;
+    hg_prepare<Op, T>(inds, n, m, xi, w, L, &keys, &perm, st);
+    int32_t* nvalid = reinterpret_cast<int32_t*>(w + L.nvalid);
+    if (acc)
+        hipLaunchKernelGGL((hg_apply_kernel<Op, T, true, true>), dim3((unsigned)L.ntiles), dim3(kHgBlock), 0, st,
+                           keys, perm, xi, nvalid, w + L.carF, w + L.carR, HgOut<T>{}, hb, xb);
+    else
+        hipLaunchKernelGGL((hg_apply_kernel<Op, T, true, false>), dim3((unsigned)L.ntiles), dim3(kHgBlock), 0, st,
+                           keys, perm, xi, nvalid, w + L.carF, w + L.carR, HgOut<T>{}, hb, xb);
+}
+
+static pvjp_status hg_check(const char* name, pvjp_gop op, pvjp_dtype dtype, const int32_t* inds,
+                            const void* const* x, int64_t n, int64_t m, void* ws, size_t ws_bytes) {
+    const int K = hg_components(op);
+    PVJP_REQUIRE(K > 0, "%s: unknown operator %d", name, (int)op);
+    PVJP_REQUIRE(valid_dtype(dtype), "%s: unknown dtype %d", name, (int)dtype);
+    PVJP_REQUIRE(n >= 0 && n <= INT32_MAX, "%s: n = %lld out of range [0, 2^31)", name, (long long)n);
+    PVJP_REQUIRE(m >= 1 && m <= kHgMaxBins, "%s: m = %lld out of range [1, 2^24]", name, (long long)m);
+    PVJP_REQUIRE(ws != nullptr && aligned(ws, 256), "%s: workspace must be non-NULL and 256-byte aligned", name);
+    const size_t need = pvjp_hist_generic_ws_bytes(op, dtype, n, m);
+    if (ws_bytes < need) {
+        set_error("%s: workspace of %zu bytes, need %zu", name, ws_bytes, need);
+        return PVJP_ENOMEM;
+    }
+    if (n > 0) {
+        PVJP_REQUIRE(inds != nullptr && x != nullptr, "%s: inds and x must be non-NULL", name);
+        for (int c = 0; c < K; ++c) {
+            PVJP_REQUIRE(x[c] != nullptr, "%s: component %d of x is NULL", name, c);
+            PVJP_REQUIRE(aligned(x[c], dsize(dtype)), "%s: component %d of x is misaligned", name, c);
+        }
+    }
+    return PVJP_OK;
+}
+
+}  // namespace pvjp
+
+using namespace pvjp;
+
+extern "C" size_t pvjp_hist_generic_ws_bytes(pvjp_gop op, pvjp_dtype dtype, int64_t n, int64_t m) {
+    if (hg_components(op) == 0 || !valid_dtype(dtype) || n < 0 || m < 1 || m > kHgMaxBins) return 0;
+    return hg_layout(n, m).total;
+}
+
+extern "C" pvjp_status pvjp_hist_generic(pvjp_gop op, pvjp_dtype dtype, const int32_t* inds, const void* const* x,
+                                         int64_t n, int64_t m, void* const* hs, void* ws, size_t ws_bytes,
+                                         void* stream) {
+    clear_error();
+    const pvjp_status s = hg_check("pvjp_hist_generic", op, dtype, inds, x, n, m, ws, ws_bytes);
+    if (s != PVJP_OK) return s;
+    const int K = hg_components(op);
+    PVJP_REQUIRE(hs != nullptr, "pvjp_hist_generic: hs is NULL");
+    for (int c = 0; c < K; ++c) PVJP_REQUIRE(hs[c] != nullptr, "pvjp_hist_generic: component %d of hs is NULL", c);
+    const hipStream_t st = as_stream(stream);
+    char* w = reinterpret_cast<char*>(ws);
+    const int32_t mm = (int32_t)m;
+    if (dtype == PVJP_F64) {
+        if (op == PVJP_GOP_LOGADDEXP) hg_primal<GLogAddExp<double>, double>(inds, n, mm, x, hs, w, st);
+        else if (op == PVJP_GOP_LINREC) hg_primal<GLinRec<double>, double>(inds, n, mm, x, hs, w, st);
+        else hg_primal<GMat2<double>, double>(inds, n, mm, x, hs, w, st);
+    } else {
+        if (op == PVJP_GOP_LOGADDEXP) hg_primal<GLogAddExp<double>, float>(inds, n, mm, x, hs, w, st);
+        else if (op == PVJP_GOP_LINREC) hg_primal<GLinRec<double>, float>(inds, n, mm, x, hs, w, st);
+        else hg_primal<GMat2<double>, float>(inds, n, mm, x, hs, w, st);
+    }
+    PVJP_LAUNCHED("pvjp_hist_generic");
+    return PVJP_OK;
+}
+
+extern "C" pvjp_status pvjp_hist_generic_vjp(pvjp_gop op, pvjp_dtype dtype, const int32_t* inds,
+                                             const void* const* x, int64_t n, int64_t m, const void* const* hs_bar,
+                                             void* const* x_bar, int accumulate, void* ws, size_t ws_bytes,
+                                             void* stream) {
+    clear_error();
+    const pvjp_status s = hg_check("pvjp_hist_generic_vjp", op, dtype, inds, x, n, m, ws, ws_bytes);
+    if (s != PVJP_OK) return s;
+    if (n == 0) return PVJP_OK;
+    const int K = hg_components(op);
+    PVJP_REQUIRE(hs_bar != nullptr && x_bar != nullptr, "pvjp_hist_generic_vjp: hs_bar and x_bar must be non-NULL");
+    for (int c = 0; c < K; ++c) {
+        PVJP_REQUIRE(hs_bar[c] != nullptr, "pvjp_hist_generic_vjp: component %d of hs_bar is NULL", c);
+        PVJP_REQUIRE(x_bar[c] != nullptr, "pvjp_hist_generic_vjp: component %d of x_bar is NULL", c);
+        PVJP_REQUIRE(aligned(x_bar[c], dsize(dtype)), "pvjp_hist_generic_vjp: component %d of x_bar is misaligned",
+                     c);
+    }
+    const hipStream_t st = as_stream(stream);
+    char* w = reinterpret_cast<char*>(ws);
+    const int32_t mm = (int32_t)m;
+    const bool acc = accumulate != 0;
+    if (dtype == PVJP_F64) {
+        if (op == PVJP_GOP_LOGADDEXP) hg_vjp<GLogAddExp<double>, double>(inds, n, mm, x, hs_bar, x_bar, acc, w, st);
+        else if (op == PVJP_GOP_LINREC) hg_vjp<GLinRec<double>, double>(inds, n, mm, x, hs_bar, x_bar, acc, w, st);
+        else hg_vjp<GMat2<double>, double>(inds, n, mm, x, hs_bar, x_bar, acc, w, st);
+    } else {
+        if (op == PVJP_GOP_LOGADDEXP) hg_vjp<GLogAddExp<double>, float>(inds, n, mm, x, hs_bar, x_bar, acc, w, st);
+        else if (op == PVJP_GOP_LINREC) hg_vjp<GLinRec<double>, float>(inds, n, mm, x, hs_bar, x_bar, acc, w, st);
+        else hg_vjp<GMat2<double>, float>(inds, n, mm, x, hs_bar, x_bar, acc, w, st);
+    }
+    PVJP_LAUNCHED("pvjp_hist_generic_vjp");
+    return PVJP_OK;
+}

@@ -709,3 +709,51 @@ def hist_lae_vjp(inds, x, hs, hs_bar, x_bar=None, accumulate=False):
     capi.call("pvjp_hist_lae_vjp", _dt(x), _ptr(inds), _ptr(x), x.numel(), hs.numel(), _ptr(hs), _ptr(hs_bar),
               _ptr(x_bar), int(accumulate), _stream(x.device))
     return x_bar
+
+
+# ------------------------------------------- reduce_by_index, general operator
+def hist_generic(op, inds, xs, m):
+    """hs: K tensors [m], each bin's fold in index order with an operator of
+    Sec. 5.1.1's general rule (it need not commute); the neutral element for
+    an empty bin."""
+    if inds.dtype != torch.int32:
+        raise TypeError("inds must be int32")
+    xs, n, K = _components(op, xs)
+    if inds.numel() != n:
+        raise ValueError("inds and the components must have the same number of elements")
+    dt, dev = _dt(xs[0]), xs[0].device
+    _check_indices(inds, m)
+    _check_values(*xs)
+    hs = [torch.empty(m, dtype=xs[0].dtype, device=dev) for _ in range(K)]
+    nb = capi.lib().pvjp_hist_generic_ws_bytes(_gop(op), dt, n, m)
+    ws = WS.get("hist_generic", nb, dev)
+    capi.call("pvjp_hist_generic", _gop(op), dt, _ptr(inds), capi.ptr_array([_ptr(x) for x in xs]), n, m,
+              capi.ptr_array([_ptr(h) for h in hs]), _ptr(ws), ws.numel(), _stream(dev))
+    return hs
+
+
+def hist_generic_vjp(op, inds, xs, hs_bar, x_bar=None, accumulate=False):
+    """x_bar (+)= the general rule inside each bin with y_bar = the bin's
+    hs_bar (K tensors [m]); 0 for an element whose index is out of range."""
+    if inds.dtype != torch.int32:
+        raise TypeError("inds must be int32")
+    xs, n, K = _components(op, xs)
+    if inds.numel() != n:
+        raise ValueError("inds and the components must have the same number of elements")
+    hs_bar = list(hs_bar)
+    if len(hs_bar) != K:
+        raise ValueError(f"operator {op} takes {K} components")
+    m = hs_bar[0].numel()
+    if any(h.numel() != m or h.dtype != xs[0].dtype for h in hs_bar):
+        raise ValueError("hs_bar components must have m elements of the dtype of x")
+    if x_bar is None:
+        x_bar = [(torch.zeros_like if accumulate else torch.empty_like)(x) for x in xs]
+    if len(x_bar) != K or any(b.numel() != n or b.dtype != xs[0].dtype for b in x_bar):
+        raise ValueError("x_bar must hold K tensors of the size and dtype of x")
+    dt, dev = _dt(xs[0]), xs[0].device
+    nb = capi.lib().pvjp_hist_generic_ws_bytes(_gop(op), dt, n, m)
+    ws = WS.get("hist_generic", nb, dev)
+    capi.call("pvjp_hist_generic_vjp", _gop(op), dt, _ptr(inds), capi.ptr_array([_ptr(x) for x in xs]), n, m,
+              capi.ptr_array([_ptr(h) for h in hs_bar]), capi.ptr_array([_ptr(b) for b in x_bar]), int(accumulate),
+              _ptr(ws), ws.numel(), _stream(dev))
+    return x_bar

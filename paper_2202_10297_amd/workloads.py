@@ -214,3 +214,14 @@ def kmeans(N: int, D: int, K: int, dtype="f32", seed: int = 0):
     pick = g.choice(N, size=K, replace=False) if N >= K else np.arange(N)
     C = X[pick].copy()
     return X, C
+
+
+def hist_generic(op: str, n: int, m: int, dist: str = "uniform", dtype="f64", seed: int = 0):
+    """(inds, components, hs_bar) for reduce_by_index with a general operator:
+    indices as for hist() (uniform or Zipf(1.1) over m), components as for
+    gop(), hs_bar a list of K arrays [m] ~ N(0, 1)."""
+    inds, _, _ = hist(n, m, dist, "f32", seed=seed)
+    xs, _ = gop(op, n, dtype, seed=seed + 1)
+    g = rng(seed + 2)
+    dt = _dt(dtype)
+    return inds, xs, [g.standard_normal(m).astype(dt) for _ in xs]
