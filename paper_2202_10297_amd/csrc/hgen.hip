@@ -15,8 +15,9 @@
 //      fold of the bin's earlier elements, ls) and reversed (of its later
 //      ones, rs), with the usual lifted operator that restarts at a flagged
 //      element (a bin's first element forward, its last one reversed), over
-//      fixed tiles in three passes: tile folds, one block scanning the tile
-//      folds, then per tile the in-tile scans with the tile's carry;
+//      fixed tiles: tile folds, the tiles' carries (a wave per 64 tiles, one
+//      block over the groups, a wave per group again), then per tile the
+//      in-tile scans with the tile's carry;
 //   4. the primal writes each bin's fold at its last element; the VJP maps
 //      f(ls, x, rs, hs_bar[bin]) (the reduce rule, y_bar = the bin's hs_bar)
 //      over the sorted elements and writes it at the element's own index.
@@ -45,7 +46,8 @@ constexpr int64_t kHgMaxBins = (int64_t)1 << (2 * kHgDigitBits);
 // Digit counts of one chunk (any order: counting needs no stability).  The
 // first pass reads the indices (out-of-range ones skipped), the second the
 // first pass's output, whose length is on the device.
-__global__ __launch_bounds__(kHgCountBlock) void hg_count_kernel(const int32_t* __restrict__ keys, int64_t n,
+__global__ __launch_bounds__(kHgCountBlock) void hg_count_kernel(const int32_t* __restrict__ keys,
+                                                                 const int2* __restrict__ pairs, int64_t n,
                                                                  const int32_t* __restrict__ nvalid, int32_t m,
                                                                  int shift, int ndig, int32_t* __restrict__ cntb) {
     __shared__ int32_t cnt[kHgDigits];
@@ -55,7 +57,7 @@ __global__ __launch_bounds__(kHgCountBlock) void hg_count_kernel(const int32_t* 
     const int64_t lo = (int64_t)blockIdx.x * kHgChunk;
     const int64_t hi = (lo + kHgChunk < ne) ? lo + kHgChunk : ne;
     for (int64_t i = lo + threadIdx.x; i < hi; i += kHgCountBlock) {
-        const int32_t k = keys[i];
+        const int32_t k = keys ? keys[i] : pairs[i].x;
         if ((uint32_t)k < (uint32_t)m) atomicAdd(&cnt[(k >> shift) & (kHgDigits - 1)], 1);
     }
     __syncthreads();
@@ -126,12 +128,11 @@ __global__ __launch_bounds__(kHgScanThreads) void hg_digitscan_kernel(int32_t* _
 // bit; a lane's rank among them and the digit's running position (LDS) give
 // its place, and the group's last such lane advances the position.
 __global__ __launch_bounds__(kWave) void hg_scatter_kernel(const int32_t* __restrict__ keys_in,
-                                                           const int32_t* __restrict__ perm_in, int64_t n,
+                                                           const int2* __restrict__ pairs_in, int64_t n,
                                                            const int32_t* __restrict__ nvalid, int32_t m, int shift,
                                                            int ndig, int nbits, const int32_t* __restrict__ cntb,
                                                            const int32_t* __restrict__ ctot,
-                                                           int32_t* __restrict__ keys_out,
-                                                           int32_t* __restrict__ perm_out) {
+                                                           int2* __restrict__ pairs_out) {
     __shared__ int32_t pos[kHgDigits];
     const int lane = threadIdx.x;
     const int blk = blockIdx.x;
@@ -149,8 +150,17 @@ __global__ __launch_bounds__(kWave) void hg_scatter_kernel(const int32_t* __rest
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t i = g0 + (int64_t)u * kWave + lane;
-            k[u] = i < hi ? keys_in[i] : -1;
-            src[u] = i < hi ? (perm_in ? perm_in[i] : (int32_t)i) : 0;
+            if (i < hi && keys_in) {
+                k[u] = keys_in[i];
+                src[u] = (int32_t)i;
+            } else if (i < hi) {
+                const int2 q = pairs_in[i];
+                k[u] = q.x;
+                src[u] = q.y;
+            } else {
+                k[u] = -1;
+                src[u] = 0;
+            }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -165,9 +175,8 @@ __global__ __launch_bounds__(kWave) void hg_scatter_kernel(const int32_t* __rest
             const int base = valid ? pos[d] : 0;
             const int rank = __popcll(peers & below);
             if (valid) {
-                const int at = base + rank;
-                keys_out[at] = k[u];
-                perm_out[at] = src[u];
+                // the bin and the element index in one 8-byte store
+                pairs_out[base + rank] = make_int2(k[u], src[u]);
                 // the highest lane of the group moves the digit's position on
                 if ((peers >> lane) == 1ull) pos[d] = base + __popcll(peers);
             }
@@ -176,7 +185,7 @@ __global__ __launch_bounds__(kWave) void hg_scatter_kernel(const int32_t* __rest
 }
 
 // off[b] = the first sorted position whose bin is b or later (b in [0, m]).
-__global__ __launch_bounds__(256) void hg_off_kernel(const int32_t* __restrict__ keys,
+__global__ __launch_bounds__(256) void hg_off_kernel(const int2* __restrict__ pairs,
                                                      const int32_t* __restrict__ nvalid, int32_t m,
                                                      int32_t* __restrict__ off) {
     const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -184,7 +193,7 @@ __global__ __launch_bounds__(256) void hg_off_kernel(const int32_t* __restrict__
     int64_t lo = 0, hi = *nvalid;
     while (lo < hi) {
         const int64_t mid = (lo + hi) >> 1;
-        if ((int64_t)keys[mid] < b) lo = mid + 1; else hi = mid;
+        if ((int64_t)pairs[mid].x < b) lo = mid + 1; else hi = mid;
     }
     off[b] = (int32_t)lo;
 }
@@ -218,8 +227,9 @@ struct HgOut {
     T* p[4];
 };
 
-// Sorted element p: its bin and its components (as FP64), plus whether it
-// opens (first) and closes (last) its bin.
+// Sorted element p: its bin, its own index and its components (as FP64, from
+// the sorted copy of x), plus whether it opens (first) and closes (last) its
+// bin.
 template <class Op, class T>
 struct HgElem {
     int32_t key, src;
@@ -228,25 +238,38 @@ struct HgElem {
 };
 
 template <class Op, class T>
-__device__ __forceinline__ HgElem<Op, T> hg_elem(const int32_t* __restrict__ keys, const int32_t* __restrict__ perm,
-                                                 const HgIn<T>& x, int64_t nv, int64_t p) {
+__device__ __forceinline__ HgElem<Op, T> hg_elem(const int2* __restrict__ pairs, const HgIn<T>& xs, int64_t nv,
+                                                 int64_t p) {
     HgElem<Op, T> e;
-    e.key = keys[p];
-    e.src = perm[p];
-    e.first = p == 0 || keys[p - 1] != e.key;
-    e.last = p + 1 == nv || keys[p + 1] != e.key;
+    const int2 q = pairs[p];
+    e.key = q.x;
+    e.src = q.y;
+    e.first = p == 0 || pairs[p - 1].x != e.key;
+    e.last = p + 1 == nv || pairs[p + 1].x != e.key;
     double c[Op::K];
 #pragma unroll
-    for (int k = 0; k < Op::K; ++k) c[k] = (double)x.p[k][e.src];
+    for (int k = 0; k < Op::K; ++k) c[k] = (double)xs.p[k][p];
     e.a = Op::elem(c);
     return e;
+}
+
+// The components in sorted order: one gather of x per element and
+// component, after which every pass reads them in order.
+template <class T>
+__global__ __launch_bounds__(256) void hg_gather_kernel(const int2* __restrict__ pairs,
+                                                        const int32_t* __restrict__ nvalid, HgIn<T> x, int K,
+                                                        HgOut<T> xs) {
+    const int64_t nv = *nvalid;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < nv; p += (int64_t)gridDim.x * 256) {
+        const int32_t src = pairs[p].y;
+        for (int k = 0; k < K; ++k) xs.p[k][p] = x.p[k][src];
+    }
 }
 
 // Tile folds, forward (flag: the bin's first element) and reversed (flag:
 // its last element, scanned with the operands exchanged).
 template <class Op, class T>
-__global__ __launch_bounds__(kHgBlock) void hg_tile_fold_kernel(const int32_t* __restrict__ keys,
-                                                                const int32_t* __restrict__ perm, HgIn<T> x,
+__global__ __launch_bounds__(kHgBlock) void hg_tile_fold_kernel(const int2* __restrict__ pairs, HgIn<T> xs,
                                                                 const int32_t* __restrict__ nvalid, char* __restrict__ aggF,
                                                                 char* __restrict__ aggR) {
     using F = SegOf<Op>;
@@ -262,7 +285,7 @@ __global__ __launch_bounds__(kHgBlock) void hg_tile_fold_kernel(const int32_t* _
     for (int j = 0; j < kHgIpt; ++j) {
         re[j] = R::id();
         if (p0 + j < nv) {
-            const HgElem<Op, T> e = hg_elem<Op, T>(keys, perm, x, nv, p0 + j);
+            const HgElem<Op, T> e = hg_elem<Op, T>(pairs, xs, nv, p0 + j);
             sf = F::comb(sf, typename F::S{e.a, e.first ? 1u : 0u, 0u});
             re[j] = typename R::S{e.a, e.last ? 1u : 0u, 0u};
         }
@@ -279,8 +302,9 @@ __global__ __launch_bounds__(kHgBlock) void hg_tile_fold_kernel(const int32_t* _
     }
 }
 
-// One block: each tile's carry, the lifted fold of all tiles before it
-// (forward) and after it (reversed).  Thread t owns a contiguous run of tiles.
+// One block: each item's carry, the lifted fold of all items before it
+// (forward) and after it (reversed), for an array of tile or group folds.
+// Thread t owns a contiguous run of items.
 template <class Op>
 __global__ __launch_bounds__(kHgScanThreads) void hg_tile_scan_kernel(const char* __restrict__ aggF,
                                                                       const char* __restrict__ aggR, int64_t ntiles,
@@ -312,12 +336,62 @@ __global__ __launch_bounds__(kHgScanThreads) void hg_tile_scan_kernel(const char
     }
 }
 
+// Tile carries in three steps: a wave folds each group of 64 tiles, one
+// block scans the group folds (hg_tile_scan_kernel over the groups), and a
+// wave per group turns the group's carry into its tiles' carries.
+constexpr int kHgGroup = kWave;
+
+template <class Op>
+__global__ __launch_bounds__(kHgGroup) void hg_group_fold_kernel(const char* __restrict__ aggF,
+                                                                 const char* __restrict__ aggR, int64_t ntiles,
+                                                                 char* __restrict__ gF, char* __restrict__ gR) {
+    using F = SegOf<Op>;
+    using R = SegOf<Flip<Op>>;
+    __shared__ typename F::S wf[1];
+    __shared__ typename R::S wr[1];
+    const int64_t t = (int64_t)blockIdx.x * kHgGroup + threadIdx.x;
+    const typename F::S af = t < ntiles ? *reinterpret_cast<const typename F::S*>(aggF + (size_t)t * kHgSlot) : F::id();
+    const typename R::S ar = t < ntiles ? *reinterpret_cast<const typename R::S*>(aggR + (size_t)t * kHgSlot) : R::id();
+    typename F::S tf;
+    typename R::S tr;
+    block_exclusive_scan<F, kHgGroup, false>(af, tf, wf);
+    block_exclusive_scan<R, kHgGroup, true>(ar, tr, wr);
+    if (threadIdx.x == 0) {
+        *reinterpret_cast<typename F::S*>(gF + (size_t)blockIdx.x * kHgSlot) = tf;
+        *reinterpret_cast<typename R::S*>(gR + (size_t)blockIdx.x * kHgSlot) = tr;
+    }
+}
+
+template <class Op>
+__global__ __launch_bounds__(kHgGroup) void hg_group_carry_kernel(const char* __restrict__ aggF,
+                                                                  const char* __restrict__ aggR, int64_t ntiles,
+                                                                  const char* __restrict__ gcF,
+                                                                  const char* __restrict__ gcR,
+                                                                  char* __restrict__ carF, char* __restrict__ carR) {
+    using F = SegOf<Op>;
+    using R = SegOf<Flip<Op>>;
+    __shared__ typename F::S wf[1];
+    __shared__ typename R::S wr[1];
+    const int64_t t = (int64_t)blockIdx.x * kHgGroup + threadIdx.x;
+    const typename F::S af = t < ntiles ? *reinterpret_cast<const typename F::S*>(aggF + (size_t)t * kHgSlot) : F::id();
+    const typename R::S ar = t < ntiles ? *reinterpret_cast<const typename R::S*>(aggR + (size_t)t * kHgSlot) : R::id();
+    typename F::S tf;
+    typename R::S tr;
+    const typename F::S xf = block_exclusive_scan<F, kHgGroup, false>(af, tf, wf);
+    const typename R::S xr = block_exclusive_scan<R, kHgGroup, true>(ar, tr, wr);
+    if (t < ntiles) {
+        *reinterpret_cast<typename F::S*>(carF + (size_t)t * kHgSlot) =
+            F::comb(*reinterpret_cast<const typename F::S*>(gcF + (size_t)blockIdx.x * kHgSlot), xf);
+        *reinterpret_cast<typename R::S*>(carR + (size_t)t * kHgSlot) =
+            R::comb(*reinterpret_cast<const typename R::S*>(gcR + (size_t)blockIdx.x * kHgSlot), xr);
+    }
+}
+
 // Per tile: the forward scan with the tile's carry; the primal writes each
 // bin's fold at its last element.  The VJP also runs the reversed scan and
 // maps f over (ls, x, rs) with y_bar = hs_bar of the element's bin.
 template <class Op, class T, bool VJP, bool ACC>
-__global__ __launch_bounds__(kHgBlock) void hg_apply_kernel(const int32_t* __restrict__ keys,
-                                                            const int32_t* __restrict__ perm, HgIn<T> x,
+__global__ __launch_bounds__(kHgBlock) void hg_apply_kernel(const int2* __restrict__ pairs, HgIn<T> xs,
                                                             const int32_t* __restrict__ nvalid,
                                                             const char* __restrict__ carF,
                                                             const char* __restrict__ carR, HgOut<T> hs,
@@ -336,7 +410,7 @@ __global__ __launch_bounds__(kHgBlock) void hg_apply_kernel(const int32_t* __res
     for (int j = 0; j < kHgIpt; ++j) {
         in[j] = p0 + j < nv;
         if (in[j]) {
-            e[j] = hg_elem<Op, T>(keys, perm, x, nv, p0 + j);
+            e[j] = hg_elem<Op, T>(pairs, xs, nv, p0 + j);
             sf = F::comb(sf, typename F::S{e[j].a, e[j].first ? 1u : 0u, 0u});
         }
     }
@@ -413,10 +487,11 @@ static int hg_components(pvjp_gop op) {
 
 struct HgLayout {
     int64_t nblk, nchunks, ntiles;
-    size_t cntb, ctot, nvalid, keysA, permA, keysB, permB, off, aggF, aggR, carF, carR, total;
+    int64_t ngroups;
+    size_t cntb, ctot, nvalid, pairsA, pairsB, xs[4], off, aggF, aggR, carF, carR, gF, gR, gcF, gcR, total;
 };
 
-static HgLayout hg_layout(int64_t n, int64_t m) {
+static HgLayout hg_layout(int64_t n, int64_t m, int K, size_t tsize) {
     HgLayout L{};
     const int64_t nn = n > 0 ? n : 1;
     L.nblk = ceil_div(nn, kHgChunk);
@@ -431,86 +506,99 @@ static HgLayout hg_layout(int64_t n, int64_t m) {
     L.cntb = take((size_t)L.nblk * kHgDigits * 4);
     L.ctot = take((size_t)L.nchunks * kHgDigits * 4);
     L.nvalid = take(4);
-    L.keysA = take((size_t)nn * 4);
-    L.permA = take((size_t)nn * 4);
-    L.keysB = take((size_t)nn * 4);
-    L.permB = take((size_t)nn * 4);
+    L.pairsA = take((size_t)nn * 8);
+    L.pairsB = take((size_t)nn * 8);
+    for (int k = 0; k < K; ++k) L.xs[k] = take((size_t)nn * tsize);
     L.off = take((size_t)(m + 1) * 4);
     L.aggF = take((size_t)L.ntiles * kHgSlot);
     L.aggR = take((size_t)L.ntiles * kHgSlot);
     L.carF = take((size_t)L.ntiles * kHgSlot);
     L.carR = take((size_t)L.ntiles * kHgSlot);
+    L.ngroups = ceil_div(L.ntiles, kHgGroup);
+    L.gF = take((size_t)L.ngroups * kHgSlot);
+    L.gR = take((size_t)L.ngroups * kHgSlot);
+    L.gcF = take((size_t)L.ngroups * kHgSlot);
+    L.gcR = take((size_t)L.ngroups * kHgSlot);
     L.total = o;
     return L;
 }
 
-// The sort, the bin starts and the tile carries, shared by both entry points.
-// Returns the sorted bins and element indices.
+// The sort, the sorted copy of x and the tile carries, shared by both entry
+// points.  Returns the sorted (bin, element index) pairs and the sorted x.
 template <class Op, class T>
-static void hg_prepare(const int32_t* inds, int64_t n, int32_t m, const HgIn<T>& x, char* w, const HgLayout& L,
-                       const int32_t** keys, const int32_t** perm, hipStream_t st) {
+static const int2* hg_prepare(const int32_t* inds, int64_t n, int32_t m, const HgIn<T>& x, char* w,
+                              const HgLayout& L, HgIn<T>* xs_out, hipStream_t st) {
     int32_t* cntb = reinterpret_cast<int32_t*>(w + L.cntb);
     int32_t* ctot = reinterpret_cast<int32_t*>(w + L.ctot);
     int32_t* nvalid = reinterpret_cast<int32_t*>(w + L.nvalid);
-    int32_t* kA = reinterpret_cast<int32_t*>(w + L.keysA);
-    int32_t* pA = reinterpret_cast<int32_t*>(w + L.permA);
-    int32_t* kB = reinterpret_cast<int32_t*>(w + L.keysB);
-    int32_t* pB = reinterpret_cast<int32_t*>(w + L.permB);
+    int2* pA = reinterpret_cast<int2*>(w + L.pairsA);
+    int2* pB = reinterpret_cast<int2*>(w + L.pairsB);
     const int passes = m > kHgDigits ? 2 : 1;
-    const int32_t* kin = inds;
-    const int32_t* pin = nullptr;
+    const int2* pin = nullptr;
     for (int pass = 0; pass < passes; ++pass) {
         const int shift = pass * kHgDigitBits;
         const int ndig = pass == 0 ? (int)std::min<int64_t>(m, kHgDigits) : (int)ceil_div(m, kHgDigits);
         int nbits = 0;
         while ((1 << nbits) < ndig) ++nbits;
-        int32_t* kout = pass == 0 ? kA : kB;
-        int32_t* pout = pass == 0 ? pA : pB;
+        int2* pout = pass == 0 ? pA : pB;
+        const int32_t* kin = pass == 0 ? inds : nullptr;
         const int32_t* nv = pass == 0 ? nullptr : nvalid;
-        hipLaunchKernelGGL(hg_count_kernel, dim3((unsigned)L.nblk), dim3(kHgCountBlock), 0, st, kin, n, nv, m, shift,
-                           ndig, cntb);
+        hipLaunchKernelGGL(hg_count_kernel, dim3((unsigned)L.nblk), dim3(kHgCountBlock), 0, st, kin, pin, n, nv, m,
+                           shift, ndig, cntb);
         hipLaunchKernelGGL(hg_colscan_kernel, dim3((unsigned)ceil_div(ndig, kHgCountBlock), (unsigned)L.nchunks),
                            dim3(kHgCountBlock), 0, st, cntb, (int)L.nblk, ndig, ctot);
         hipLaunchKernelGGL(hg_digitscan_kernel, dim3(1), dim3(kHgScanThreads), 0, st, ctot, (int)L.nchunks, ndig,
                            pass == 0 ? nvalid : nullptr);
         hipLaunchKernelGGL(hg_scatter_kernel, dim3((unsigned)L.nblk), dim3(kWave), 0, st, kin, pin, n, nv, m, shift,
-                           ndig, nbits, cntb, ctot, kout, pout);
-        kin = kout;
+                           ndig, nbits, cntb, ctot, pout);
         pin = pout;
     }
-    *keys = kin;
-    *perm = pin;
-    hipLaunchKernelGGL((hg_tile_fold_kernel<Op, T>), dim3((unsigned)L.ntiles), dim3(kHgBlock), 0, st, kin, pin, x,
+    HgIn<T> xs{};
+    HgOut<T> xo{};
+    for (int k = 0; k < Op::K; ++k) {
+        xo.p[k] = reinterpret_cast<T*>(w + L.xs[k]);
+        xs.p[k] = xo.p[k];
+    }
+    if (n > 0)
+        hipLaunchKernelGGL(hg_gather_kernel<T>, dim3(flat_grid(n, 256, 4)), dim3(256), 0, st, pin, nvalid, x, Op::K,
+                           xo);
+    hipLaunchKernelGGL((hg_tile_fold_kernel<Op, T>), dim3((unsigned)L.ntiles), dim3(kHgBlock), 0, st, pin, xs,
                        nvalid, w + L.aggF, w + L.aggR);
-    hipLaunchKernelGGL(hg_tile_scan_kernel<Op>, dim3(1), dim3(kHgScanThreads), 0, st, w + L.aggF, w + L.aggR,
-                       L.ntiles, w + L.carF, w + L.carR);
+    hipLaunchKernelGGL(hg_group_fold_kernel<Op>, dim3((unsigned)L.ngroups), dim3(kHgGroup), 0, st, w + L.aggF,
+                       w + L.aggR, L.ntiles, w + L.gF, w + L.gR);
+    hipLaunchKernelGGL(hg_tile_scan_kernel<Op>, dim3(1), dim3(kHgScanThreads), 0, st, w + L.gF, w + L.gR,
+                       L.ngroups, w + L.gcF, w + L.gcR);
+    hipLaunchKernelGGL(hg_group_carry_kernel<Op>, dim3((unsigned)L.ngroups), dim3(kHgGroup), 0, st, w + L.aggF,
+                       w + L.aggR, L.ntiles, w + L.gcF, w + L.gcR, w + L.carF, w + L.carR);
+    *xs_out = xs;
+    return pin;
 }
 
 template <class Op, class T>
 static void hg_primal(const int32_t* inds, int64_t n, int32_t m, const void* const* x, void* const* hs, char* w,
                       hipStream_t st) {
-    const HgLayout L = hg_layout(n, m);
+    const HgLayout L = hg_layout(n, m, Op::K, sizeof(T));
     HgIn<T> xi{};
     HgOut<T> ho{};
     for (int k = 0; k < Op::K; ++k) {
         xi.p[k] = n > 0 ? (const T*)x[k] : nullptr;
         ho.p[k] = (T*)hs[k];
     }
-    const int32_t *keys, *perm;
-    hg_prepare<Op, T>(inds, n, m, xi, w, L, &keys, &perm, st);
+    HgIn<T> xs;
+    const int2* pairs = hg_prepare<Op, T>(inds, n, m, xi, w, L, &xs, st);
     int32_t* nvalid = reinterpret_cast<int32_t*>(w + L.nvalid);
     int32_t* off = reinterpret_cast<int32_t*>(w + L.off);
-    hipLaunchKernelGGL(hg_off_kernel, dim3((unsigned)ceil_div((int64_t)m + 1, 256)), dim3(256), 0, st, keys, nvalid,
+    hipLaunchKernelGGL(hg_off_kernel, dim3((unsigned)ceil_div((int64_t)m + 1, 256)), dim3(256), 0, st, pairs, nvalid,
                        m, off);
-    hipLaunchKernelGGL((hg_apply_kernel<Op, T, false, false>), dim3((unsigned)L.ntiles), dim3(kHgBlock), 0, st, keys,
-                       perm, xi, nvalid, w + L.carF, w + L.carR, ho, HgIn<T>{}, HgOut<T>{});
+    hipLaunchKernelGGL((hg_apply_kernel<Op, T, false, false>), dim3((unsigned)L.ntiles), dim3(kHgBlock), 0, st, pairs,
+                       xs, nvalid, w + L.carF, w + L.carR, ho, HgIn<T>{}, HgOut<T>{});
     hipLaunchKernelGGL((hg_empty_kernel<Op, T>), dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, off, m, ho);
 }
 
 template <class Op, class T>
 static void hg_vjp(const int32_t* inds, int64_t n, int32_t m, const void* const* x, const void* const* hs_bar,
                    void* const* x_bar, bool acc, char* w, hipStream_t st) {
-    const HgLayout L = hg_layout(n, m);
+    const HgLayout L = hg_layout(n, m, Op::K, sizeof(T));
     HgIn<T> xi{}, hb{};
     HgOut<T> xb{};
     for (int k = 0; k < Op::K; ++k) {
@@ -520,15 +608,15 @@ static void hg_vjp(const int32_t* inds, int64_t n, int32_t m, const void* const*
     }
     if (!acc)  // elements outside [0, m) get a zero adjoint
         hipLaunchKernelGGL(hg_zero_kernel<T>, dim3(flat_grid(n, 256, 4)), dim3(256), 0, st, xb, Op::K, n);
-    const int32_t *keys, *perm;
-    hg_prepare<Op, T>(inds, n, m, xi, w, L, &keys, &perm, st);
+    HgIn<T> xs;
+    const int2* pairs = hg_prepare<Op, T>(inds, n, m, xi, w, L, &xs, st);
     int32_t* nvalid = reinterpret_cast<int32_t*>(w + L.nvalid);
     if (acc)
         hipLaunchKernelGGL((hg_apply_kernel<Op, T, true, true>), dim3((unsigned)L.ntiles), dim3(kHgBlock), 0, st,
-                           keys, perm, xi, nvalid, w + L.carF, w + L.carR, HgOut<T>{}, hb, xb);
+                           pairs, xs, nvalid, w + L.carF, w + L.carR, HgOut<T>{}, hb, xb);
     else
         hipLaunchKernelGGL((hg_apply_kernel<Op, T, true, false>), dim3((unsigned)L.ntiles), dim3(kHgBlock), 0, st,
-                           keys, perm, xi, nvalid, w + L.carF, w + L.carR, HgOut<T>{}, hb, xb);
+                           pairs, xs, nvalid, w + L.carF, w + L.carR, HgOut<T>{}, hb, xb);
 }
 
 static pvjp_status hg_check(const char* name, pvjp_gop op, pvjp_dtype dtype, const int32_t* inds,
@@ -560,7 +648,7 @@ using namespace pvjp;
 
 extern "C" size_t pvjp_hist_generic_ws_bytes(pvjp_gop op, pvjp_dtype dtype, int64_t n, int64_t m) {
     if (hg_components(op) == 0 || !valid_dtype(dtype) || n < 0 || m < 1 || m > kHgMaxBins) return 0;
-    return hg_layout(n, m).total;
+    return hg_layout(n, m, hg_components(op), dsize(dtype)).total;
 }
 
 extern "C" pvjp_status pvjp_hist_generic(pvjp_gop op, pvjp_dtype dtype, const int32_t* inds, const void* const* x,
