@@ -16,16 +16,18 @@
 //
 // Return sweep: with w_ik = ell_bar * exp(s_ik - LSE_i) (s_ik recomputed,
 // Sec. 4.1), the parameter adjoints are
-//   G_k = sum_i w_ik z_ik y_ik^T   (y = x - mu_k; an MFMA contraction over
-//                                   points of the weighted Z and Y tiles),
-//   v_k = sum_i w_ik z_ik, W_k = sum_i w_ik,
+//   G_k = sum_i w_ik z_ik y_ik^T = Q_k S_k with S_k = sum_i w_ik y_ik y_ik^T
+//         (y = x - mu_k; S_k is an MFMA contraction over points of the
+//         weighted and plain Y tiles, the product with Q_k is FP64),
+//   v_k = sum_i w_ik z_ik = Q_k sum_i w_ik y_ik, W_k = sum_i w_ik,
 //   alpha_bar_k = W_k - N ell_bar softmax(alpha)_k,
 //   mu_bar_k = Q_k^T v_k,
 //   q_bar_kd = W_k - exp(q_kd) G_k[d][d],
 //   l_bar_k[r,c] = -G_k[r][c]  (r > c).
-// Per (component, point chunk) blocks write FP32 partials (accumulated in the
-// MFMA registers over at most 4096 points per wave); a per-component kernel
-// sums them in FP64 in a fixed order and applies the parameter maps.
+// Per (component, point chunk) blocks write FP32 partials of S_k and u_k
+// (accumulated in the MFMA registers over at most 4096 points per wave); a
+// per-component kernel sums them in FP64 in a fixed order, forms G_k and v_k
+// and applies the parameter maps.
 #include <math.h>
 
 #include "common.h"
@@ -109,6 +111,39 @@ __global__ __launch_bounds__(256) void gmm_prep_kernel(const float* __restrict__
             for (int j = 0; j < K; ++j) s += exp((double)alpha[j] - mx);
             *lse_alpha = mx + log(s);
         }
+    }
+}
+
+// The wave's share of a 32-point X tile in registers (loaded ahead of use)
+// and its store into the LDS tile.
+template <int D>
+struct XRegs {
+    float4 v[(32 * D) / 256];
+};
+
+template <int D>
+__device__ __forceinline__ void load_x(const float* __restrict__ X, int64_t N, int64_t p0, XRegs<D>& r) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < (32 * D) / 256; ++q) {
+        const int e = 4 * (lane + 64 * q);  // 4 consecutive floats of one point
+        const int64_t p = p0 + e / D;
+        r.v[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (p < N) r.v[q] = *reinterpret_cast<const float4*>(X + p * D + e % D);
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void store_x(const XRegs<D>& r, float* xs) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < (32 * D) / 256; ++q) {
+        const int e = 4 * (lane + 64 * q);
+        const int pt = e / D, c = e % D;
+        xs[xs_at<D>(pt, c)] = r.v[q].x;
+        xs[xs_at<D>(pt, c + 1)] = r.v[q].y;
+        xs[xs_at<D>(pt, c + 2)] = r.v[q].z;
+        xs[xs_at<D>(pt, c + 3)] = r.v[q].w;
     }
 }
 
@@ -335,11 +370,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void g
 }
 
 // ----------------------------------------------------------------- backward
-// FROM_S: the forward's s_ik checkpoint (sck, K x N) gives w_ik directly, so
-// z is not recomputed: the tile of w (x - mu_k) is formed from X, and the
-// same contraction accumulates S_k = sum_i w_ik y_ik y_ik^T (and u_k =
-// sum_i w_ik y_ik) instead of G_k and v_k; gmm_param_kernel then forms
-// G_k = Q_k S_k and v_k = Q_k u_k.  Half the MFMA work of the recomputing form.
+// The contraction runs over y = x - mu_k on both sides: S_k = sum_i w_ik
+// y_ik y_ik^T and u_k = sum_i w_ik y_ik, from the X tile in LDS and each
+// point's weight (no weighted-z tile); gmm_param_kernel then forms
+// G_k = Q_k S_k and v_k = Q_k u_k in FP64 (z_ik = Q_k y_ik).  The weight
+// needs s_ik: recomputed from |z_ik|^2 (one MFMA pass over Q_k), or, with
+// FROM_S, read from the forward's s_ik checkpoint (sck, K x N), which halves
+// the MFMA work.
 template <int D, bool FROM_S>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gmm_bwd_kernel(const float* __restrict__ X, int64_t N, int K, int64_t chunk,
                                                       int nch, const float* __restrict__ Qf,
@@ -349,15 +386,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
                                                       double ell_bar, float* __restrict__ gpart,
                                                       float* __restrict__ vpart, double* __restrict__ wpart) {
     using C = Gm<D>;
-    // X tiles and weighted-Z tiles of the four waves; reused at the end as
-    // the scratch of the cross-wave reduction.  Q_k's MFMA fragments live in
-    // LDS too, read at each step: held in registers they would leave room
-    // for only one wave per SIMD.
+    // X tiles of the four waves, and room for the scratch of the cross-wave
+    // reduction at the end.  Q_k's MFMA fragments live in LDS too, read at
+    // each step: held in registers they would leave room for only one wave
+    // per SIMD.
     __shared__ __align__(16) float smem[2 * 4 * 32 * D];
     __shared__ float qs[C::NF * 64];
     __shared__ float cs[D];
     float* const Xw = smem + (threadIdx.x >> 6) * 32 * D;
-    float* const Zw = smem + 4 * 32 * D + (threadIdx.x >> 6) * 32 * D;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int k = blockIdx.x % K;
     const int ch = blockIdx.x / K;
@@ -377,76 +413,75 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
     for (int g = 0; g < C::NGT; ++g)
 #pragma unroll
         for (int t = 0; t < 16; ++t) gacc[g][t] = 0.f;
-    // v_k = sum_i w z_i: lane r % D sums row r of each staged w z tile (for
-    // D = 32 the two half-waves take 16 points each), one register instead
-    // of one per (row, point-lane) accumulator.
-    float vrow = 0.f;
+    float urow[C::RT];
+#pragma unroll
+    for (int t = 0; t < C::RT; ++t) urow[t] = 0.f;
     double wsum = 0.0;
 
     const int64_t cbeg = (int64_t)ch * chunk;
     const int iters = (int)(chunk / 128);
     __syncthreads();  // qs and cs
-    // Every tile below is private to its wave (Xw, Zw), so the waves only
+    // Every tile below is private to its wave (Xw), so the waves only
     // synchronise with themselves and drift apart freely: one wave's MFMA
     // phase overlaps another's loads and FP64 work.
+    // The next tile's X values (and its point's LSE and s_ik) are loaded
+    // while this tile computes.
+    XRegs<D> xr;
+    double lse_n = 0.0, s_n = 0.0;
+    {
+        const int64_t p0 = cbeg + (int64_t)w * 32;
+        load_x<D>(X, N, p0, xr);
+        if (p0 + j < N) {
+            lse_n = lse[p0 + j];
+            if (FROM_S) s_n = sck[(int64_t)k * N + p0 + j];
+        }
+    }
     for (int it = 0; it < iters; ++it) {
         const int64_t p0 = cbeg + (int64_t)(it * 4 + w) * 32;
         wave_lds_sync();
-        stage_x<D>(X, N, p0, Xw);
+        store_x<D>(xr, Xw);
         wave_lds_sync();
+        const double lse_p = lse_n, s_p = s_n;
+        if (it + 1 < iters) {
+            const int64_t pn = p0 + 4 * 32;
+            load_x<D>(X, N, pn, xr);
+            if (pn + j < N) {
+                lse_n = lse[pn + j];
+                if (FROM_S) s_n = sck[(int64_t)k * N + pn + j];
+            }
+        }
         const int64_t p = p0 + j;
+        double wd = 0.0;
         if (FROM_S) {
-            double wd = 0.0;
-            if (p < N) wd = ell_bar * exp(sck[(int64_t)k * N + p] - lse[p]);
-            const float wf = (float)wd;
-            if (h == 0) wsum += wd;
-            // w (x - mu_k): lane (j, h) fills rows [h D/2, (h+1) D/2) of point j
-#pragma unroll 8
-            for (int r = h * (D / 2); r < (h + 1) * (D / 2); ++r)
-                Zw[zs_at(r, j)] = wf * (Xw[xs_at<D>(j, r)] - cs[r]);
+            if (p < N) wd = ell_bar * exp(s_p - lse_p);
         } else {
+            // s_ik from |z|^2: z is recomputed for its norm only (the MFMA
+            // phases run at raised wave priority, so that the other wave on
+            // the SIMD issues its loads and FP64 work in their gaps)
             f32x16 z[C::RT];
-            // The MFMA phases run at raised wave priority, so that the other
-            // wave on the SIMD issues its loads and FP64 work in their gaps.
             __builtin_amdgcn_s_setprio(1);
             const double nrm = tile_znorm_lds<D>(qs, cs, Xw, z);
             __builtin_amdgcn_s_setprio(0);
-            double wd = 0.0;
-            if (p < N) wd = ell_bar * exp((bk - 0.5 * nrm) - lse[p]);
-            const float wf = (float)wd;
-            if (h == 0) wsum += wd;
-#pragma unroll
-            for (int rt = 0; rt < C::RT; ++rt)
-#pragma unroll
-                for (int t = 0; t < 16; ++t) Zw[zs_at(32 * rt + drow(t, lane), j)] = wf * z[rt][t];
+            if (p < N) wd = ell_bar * exp((bk - 0.5 * nrm) - lse_p);
         }
-        wave_lds_sync();
-        {
-            // The swizzle moves even-odd pairs of points together, so a row is
-            // read as float2 pairs.
-            const int r = lane % D;
-            const int pb = (D == 32) ? 16 * h : 0;
-            constexpr int np = (D == 32) ? 16 : 32;
-            float sr = 0.f;
-#pragma unroll
-            for (int pp = 0; pp < np; pp += 2) {
-                const float2 v2 = *reinterpret_cast<const float2*>(&Zw[zs_at(r, pb + pp)]);
-                sr += v2.x + v2.y;
-            }
-            vrow += sr;
-        }
-        // G_k += (w Z)^T Y over this tile's 32 points, lower-triangular
-        // blocks; each step loads one operand per row and column tile and
-        // feeds the blocks' independent accumulators in turn.
+        const float wf = (float)wd;  // lane (j, h): the weight of point j
+        if (h == 0) wsum += wd;
+        // S_k += (w Y)^T Y over this tile's 32 points, lower-triangular
+        // blocks: step s contracts point 2s + h, whose weight comes from lane
+        // 2s + h; u_k = sum w y accumulates from the same products.  Each step
+        // loads one operand per row tile and feeds the blocks' independent
+        // accumulators in turn.
         __builtin_amdgcn_s_setprio(1);
 #pragma unroll 8
         for (int s = 0; s < 16; ++s) {
             const int pt = 2 * s + h;
+            const float wp = __shfl(wf, pt, kWave);
             float za[C::RT], yb[C::RT];
 #pragma unroll
             for (int t = 0; t < C::RT; ++t) {
-                za[t] = Zw[zs_at(32 * t + j, pt)];
                 yb[t] = Xw[xs_at<D>(pt, 32 * t + j)] - mub[t];
+                za[t] = wp * yb[t];
+                urow[t] += za[t];
             }
             int g = 0;
 #pragma unroll
@@ -460,8 +495,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
         __builtin_amdgcn_s_setprio(0);
     }
 
-    // For D = 32 the two half-waves hold halves of each row sum.
-    if (D == 32) vrow += __shfl_xor(vrow, 32, kWave);
+    // u: the two half-waves hold the halves of each row sum; lane r < D takes
+    // row r's (rows 32 t + j live in lane j's urow[t]).
+#pragma unroll
+    for (int t = 0; t < C::RT; ++t) urow[t] += __shfl_xor(urow[t], 32, kWave);
+    const float uhi = __shfl(urow[C::RT - 1], lane & 31, kWave);
+    float vrow = lane < 32 ? urow[0] : uhi;
 #pragma unroll
     for (int d = 16; d >= 1; d >>= 1) wsum += __shfl_xor(wsum, d, kWave);
 
@@ -500,7 +539,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
 }
 
 // ------------------------------------------------------ reduce + parameters
-template <int D, bool FROM_S>
+template <int D>
 __global__ __launch_bounds__(256) void gmm_param_kernel(int64_t N, int K, int nch, const float* __restrict__ alpha,
                                                         const float* __restrict__ q, const float* __restrict__ l,
                                                         const double* __restrict__ lse_alpha, double ell_bar,
@@ -546,7 +585,7 @@ __global__ __launch_bounds__(256) void gmm_param_kernel(int64_t N, int K, int nc
         Q[r][c] = x;
     }
     __syncthreads();
-    if (FROM_S) {
+    {
         // The partials hold S_k (lower 32x32 blocks, symmetric) and u_k:
         // mirror S, then G_k = Q_k S_k row by row from the bottom (row r of G
         // needs rows <= r of S, which are still unchanged) and v_k = Q_k u_k.
@@ -658,7 +697,7 @@ static void launch_bwd_t(const float* X, int64_t N, int K, const float* alpha, c
                        (int)L.nch, (const float*)(ws + L.Qf), (const float*)(ws + L.cvec), mu,
                        (const double*)(ws + L.bias), lse, sck, ell_bar, (float*)(ws + L.gpart),
                        (float*)(ws + L.vpart), (double*)(ws + L.wpart));
-    hipLaunchKernelGGL((gmm_param_kernel<D, FROM_S>), dim3(K), dim3(256), 0, st, N, K, (int)L.nch, alpha, q, l,
+    hipLaunchKernelGGL((gmm_param_kernel<D>), dim3(K), dim3(256), 0, st, N, K, (int)L.nch, alpha, q, l,
                        (const double*)scal, ell_bar, (const float*)(ws + L.gpart), (const float*)(ws + L.vpart),
                        (const double*)(ws + L.wpart), ab, mb, qb, lb, acc);
 }
