@@ -887,50 +887,51 @@ __device__ __forceinline__ void acc_record(uint64_t* acc, int32_t* cnt, uint32_t
     if (COUNTS) atomicAdd(&cnt[j], 1);
 }
 
-template <int OP, bool COUNTS>
-__global__ __launch_bounds__(kAccBlock) void hpart_acc_kernel(const uint32_t* __restrict__ rval,
-                                                              const void* __restrict__ rbin, int nb, int ntiles,
-                                                              const uint32_t* __restrict__ D,
-                                                              const int32_t* __restrict__ istart,
-                                                              const int32_t* __restrict__ itile,
-                                                              uint64_t* __restrict__ pacc,
-                                                              int32_t* __restrict__ pcnt) {
-    constexpr bool KEYS = OP != PVJP_ADD;
-    constexpr int NW = kAccBlock / kWave;
-    __shared__ uint64_t acc[kPartBins * kAccCopies];
-    __shared__ int32_t cnt[COUNTS ? kPartBins : 1];
-    // With many buckets (short runs): blocks go to the XCDs round-robin, so
-    // each XCD takes an equal contiguous range of the items (the grid is a
-    // multiple of kXcds and covers them) and items of adjacent buckets,
-    // whose runs share cache lines in every tile, meet in one L2.  With few
-    // buckets the runs span whole lines and items go in grid order.
+// The work item of this block (-1: none) with its bucket and tiles.  With
+// many buckets (short runs): blocks go to the XCDs round-robin, so each XCD
+// takes an equal contiguous range of the items (the grid is a multiple of
+// kXcds and covers them) and items of adjacent buckets, whose runs share
+// cache lines in every tile, meet in one L2.  With few buckets the runs span
+// whole lines and items go in grid order.
+struct PartItem {
+    int item, b, ta, tb;
+};
+
+__device__ __forceinline__ PartItem part_item(int nb, int ntiles, const int32_t* __restrict__ istart,
+                                              const int32_t* __restrict__ itile) {
+    PartItem I{-1, 0, 0, 0};
     const int nitems = istart[nb];
     int item = (int)blockIdx.x;
     if (nb >= kXcdMapBuckets) {
         const int per = (nitems + kXcds - 1) / kXcds;
-        if ((int)(blockIdx.x / kXcds) >= per) return;
+        if ((int)(blockIdx.x / kXcds) >= per) return I;
         item = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
     }
-    if (item >= nitems) return;
+    if (item >= nitems) return I;
     int lo = 0, hi = nb;  // last bucket b with istart[b] <= item
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         if (istart[mid] <= item) lo = mid; else hi = mid;
     }
-    const int b = lo;
-    const int ta = itile[item];
-    const int tb = (item + 1 < istart[b + 1]) ? itile[item + 1] : ntiles;
-    for (int j = threadIdx.x; j < kPartBins * kAccCopies; j += kAccBlock) acc[j] = acc_identity<OP>();
-    if (COUNTS)
-        for (int j = threadIdx.x; j < kPartBins; j += kAccBlock) cnt[j] = 0;
-    __syncthreads();
-    const uint32_t copy = threadIdx.x & (kAccCopies - 1);
+    I.item = item;
+    I.b = lo;
+    I.ta = itile[item];
+    I.tb = (item + 1 < istart[lo + 1]) ? itile[item + 1] : ntiles;
+    return I;
+}
+
+// Walks the item's records (see above) and hands each lane's records to
+// fn(tile_base, ok, slot, value bits, bin word), the whole wave calling.
+template <bool KEYS, class Fn>
+__device__ __forceinline__ void part_walk(const uint32_t* __restrict__ rval, const void* __restrict__ rbin,
+                                          const uint32_t* __restrict__ D, int ntiles, const PartItem& I, Fn fn) {
+    constexpr int NW = kAccBlock / kWave;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kWave);
-    const int span = (tb - ta + NW - 1) / NW;
-    const int w0 = ta + wave * span;
-    const int w1 = (w0 + span < tb) ? w0 + span : tb;
-    const uint32_t* Db = D + (int64_t)b * ntiles;
+    const int span = (I.tb - I.ta + NW - 1) / NW;
+    const int w0 = I.ta + wave * span;
+    const int w1 = (w0 + span < I.tb) ? w0 + span : I.tb;
+    const uint32_t* Db = D + (int64_t)I.b * ntiles;
     for (int c0 = w0; c0 < w1; c0 += kWave) {
         // lane l: the descriptor of tile c0 + l (an empty run past the share)
         const uint32_t dl = (c0 + lane < w1) ? Db[c0 + lane] : 0u;
@@ -970,11 +971,34 @@ __global__ __launch_bounds__(kAccBlock) void hpart_acc_kernel(const uint32_t* __
                                  : (uint32_t)*reinterpret_cast<const uint16_t*>(cb + (at[s] << 1));
                 }
 #pragma unroll
-                for (int s = 0; s < kAccPar * kAccSlots; ++s)
-                    if (ok[s]) acc_record<OP, COUNTS>(acc, cnt, copy, tbase, at[s], vv[s], bb[s]);
+                for (int s = 0; s < kAccPar * kAccSlots; ++s) fn(tbase, ok[s], at[s], vv[s], bb[s]);
             }
         }
     }
+}
+
+template <int OP, bool COUNTS>
+__global__ __launch_bounds__(kAccBlock) void hpart_acc_kernel(const uint32_t* __restrict__ rval,
+                                                              const void* __restrict__ rbin, int nb, int ntiles,
+                                                              const uint32_t* __restrict__ D,
+                                                              const int32_t* __restrict__ istart,
+                                                              const int32_t* __restrict__ itile,
+                                                              uint64_t* __restrict__ pacc,
+                                                              int32_t* __restrict__ pcnt) {
+    constexpr bool KEYS = OP != PVJP_ADD;
+    __shared__ uint64_t acc[kPartBins * kAccCopies];
+    __shared__ int32_t cnt[COUNTS ? kPartBins : 1];
+    const PartItem I = part_item(nb, ntiles, istart, itile);
+    if (I.item < 0) return;
+    const int item = I.item;
+    for (int j = threadIdx.x; j < kPartBins * kAccCopies; j += kAccBlock) acc[j] = acc_identity<OP>();
+    if (COUNTS)
+        for (int j = threadIdx.x; j < kPartBins; j += kAccBlock) cnt[j] = 0;
+    __syncthreads();
+    const uint32_t copy = threadIdx.x & (kAccCopies - 1);
+    part_walk<KEYS>(rval, rbin, D, ntiles, I, [&](int64_t tbase, bool ok, uint32_t at, uint32_t v, uint32_t bn) {
+        if (ok) acc_record<OP, COUNTS>(acc, cnt, copy, tbase, at, v, bn);
+    });
     __syncthreads();
     for (int j = threadIdx.x; j < kPartBins; j += kAccBlock) {
         uint64_t v = acc[j * kAccCopies];
@@ -1018,6 +1042,90 @@ __global__ __launch_bounds__(256) void hpart_merge_kernel(const uint64_t* __rest
             merge_fold<OP>(acc, zz, cc, pacc[(int64_t)it * kPartBins + j], 0, pcnt ? pcnt[(int64_t)it * kPartBins + j] : 0);
         gacc[k] = acc;
         if (gcount) gcount[k] = cc;
+    }
+}
+
+// log-add-exp over the partition (the operator of the log-add-exp
+// reduce_by_index): per work item, each bin's largest element (ordered keys,
+// one sweep over the item's records), then the sum of e^(x - that maximum)
+// over the same records in FP64 (a second sweep); the partial of a bin is
+// its (maximum key, sum).  -inf elements add nothing; an element equal to
+// the maximum adds e^0 = 1, also when both are +inf.
+__device__ __forceinline__ float unord32(uint32_t o) {
+    return __uint_as_float((o & 0x80000000u) ? (o & 0x7fffffffu) : ~o);
+}
+
+__global__ __launch_bounds__(kAccBlock) void hpart_lae_acc_kernel(const uint32_t* __restrict__ rval,
+                                                                  const void* __restrict__ rbin, int nb, int ntiles,
+                                                                  const uint32_t* __restrict__ D,
+                                                                  const int32_t* __restrict__ istart,
+                                                                  const int32_t* __restrict__ itile,
+                                                                  double* __restrict__ psum,
+                                                                  uint32_t* __restrict__ pmax) {
+    __shared__ uint32_t mx[kPartBins];
+    __shared__ double sm[kPartBins * kAccCopies];
+    const PartItem I = part_item(nb, ntiles, istart, itile);
+    if (I.item < 0) return;
+    for (int j = threadIdx.x; j < kPartBins; j += kAccBlock) mx[j] = 0u;
+    for (int j = threadIdx.x; j < kPartBins * kAccCopies; j += kAccBlock) sm[j] = 0.0;
+    __syncthreads();
+    part_walk<false>(rval, rbin, D, ntiles, I, [&](int64_t, bool ok, uint32_t, uint32_t v, uint32_t bn) {
+        if (ok) atomicMax(&mx[bn & (kPartBins - 1)], ord32(__uint_as_float(v)));
+    });
+    __syncthreads();
+    const uint32_t copy = threadIdx.x & (kAccCopies - 1);
+    part_walk<false>(rval, rbin, D, ntiles, I, [&](int64_t, bool ok, uint32_t, uint32_t v, uint32_t bn) {
+        if (!ok) return;
+        const uint32_t j = bn & (kPartBins - 1);
+        const float x = __uint_as_float(v), m = unord32(mx[j]);
+        if (x != -INFINITY && m != -INFINITY)
+            atomicAdd(&sm[j * kAccCopies + copy], (double)(x == m ? 1.0f : expf(x - m)));
+    });
+    __syncthreads();
+    for (int j = threadIdx.x; j < kPartBins; j += kAccBlock) {
+        double v = sm[j * kAccCopies];
+#pragma unroll
+        for (int c = 1; c < kAccCopies; ++c) v += sm[j * kAccCopies + c];
+        psum[(int64_t)I.item * kPartBins + j] = v;
+        pmax[(int64_t)I.item * kPartBins + j] = mx[j];
+    }
+}
+
+// A thread per bin folds its items' (maximum, sum) partials in item order:
+// the largest maximum M over the items that hold a live element, then
+// sum_i s_i e^(m_i - M) (1 where m_i = M), and hs = M + log(sum); -inf for a
+// bin without live elements.  A NaN anywhere in the bin makes the sum NaN.
+__global__ __launch_bounds__(256) void hpart_lae_merge_kernel(const double* __restrict__ psum,
+                                                              const uint32_t* __restrict__ pmax,
+                                                              const int32_t* __restrict__ istart, int32_t m,
+                                                              float* __restrict__ hs) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x) {
+        const int b = (int)(k >> kPartShift), j = (int)(k & (kPartBins - 1));
+        const int i0 = istart[b], i1 = istart[b + 1];
+        uint32_t mk = 0u;
+        bool any = false;
+        for (int it = i0; it < i1; ++it) {
+            const double sv = psum[(int64_t)it * kPartBins + j];
+            if (sv != 0.0 || sv != sv) {
+                const uint32_t key = pmax[(int64_t)it * kPartBins + j];
+                mk = key > mk ? key : mk;
+                any = true;
+            }
+        }
+        if (!any) {
+            hs[k] = -INFINITY;
+            continue;
+        }
+        const double M = (double)unord32(mk);
+        double S = 0.0;
+        for (int it = i0; it < i1; ++it) {
+            const double sv = psum[(int64_t)it * kPartBins + j];
+            if (sv != 0.0 || sv != sv) {
+                const uint32_t key = pmax[(int64_t)it * kPartBins + j];
+                S += key == mk ? sv : sv * exp((double)unord32(key) - M);
+            }
+        }
+        hs[k] = (float)(M + log(S));
     }
 }
 
@@ -1134,11 +1242,11 @@ static size_t hist_ws(int op, int64_t n, int64_t m, bool f32) {
     return align_up((size_t)m * 8, 256) + (op == PVJP_MUL ? align_up((size_t)m * 4, 256) : 0) + part;
 }
 
+// The partition shared by the accumulators: the tile sort, the run
+// descriptors and the work items.
 template <int OP>
-static void run_partitioned(const int32_t* inds, const float* vs, int64_t n, int32_t m, int32_t* count, char* w,
-                            size_t off, uint64_t* gacc, hipStream_t st) {
-    const PartLayout L = part_layout(n, m);
-    char* base = w + off;
+static void part_sort(const int32_t* inds, const float* vs, int64_t n, int32_t m, const PartLayout& L, char* base,
+                      hipStream_t st) {
     int32_t* toff = reinterpret_cast<int32_t*>(base + L.toff);
     uint32_t* D = reinterpret_cast<uint32_t*>(base + L.D);
     int32_t* Ploc = reinterpret_cast<int32_t*>(base + L.Ploc);
@@ -1149,8 +1257,6 @@ static void run_partitioned(const int32_t* inds, const float* vs, int64_t n, int
     int32_t* itile = reinterpret_cast<int32_t*>(base + L.itile);
     uint32_t* rval = reinterpret_cast<uint32_t*>(base + L.rval);
     void* rbin = base + L.rbin;
-    uint64_t* pacc = reinterpret_cast<uint64_t*>(base + L.pacc);
-    int32_t* pcnt = reinterpret_cast<int32_t*>(base + L.pcnt);
     const bool vec = aligned(inds, 16) && aligned(vs, 16);
     // n == 0 still runs one (empty) tile, so every table is written
     if (vec)
@@ -1165,6 +1271,21 @@ static void run_partitioned(const int32_t* inds, const float* vs, int64_t n, int
     hipLaunchKernelGGL(hpart_scan_kernel, dim3(1), dim3(kPartScanThreads), 0, st, bitems, L.nb, istart);
     hipLaunchKernelGGL(hpart_items_kernel, dim3((unsigned)ceil_div((int64_t)L.nb * L.ntiles, 256)), dim3(256), 0, st,
                        Ploc, ctot, L.ntiles, L.nb, L.nchunks, istart, itile);
+}
+
+template <int OP>
+static void run_partitioned(const int32_t* inds, const float* vs, int64_t n, int32_t m, int32_t* count, char* w,
+                            size_t off, uint64_t* gacc, hipStream_t st) {
+    const PartLayout L = part_layout(n, m);
+    char* base = w + off;
+    part_sort<OP>(inds, vs, n, m, L, base, st);
+    const uint32_t* D = reinterpret_cast<const uint32_t*>(base + L.D);
+    const int32_t* istart = reinterpret_cast<const int32_t*>(base + L.istart);
+    const int32_t* itile = reinterpret_cast<const int32_t*>(base + L.itile);
+    const uint32_t* rval = reinterpret_cast<const uint32_t*>(base + L.rval);
+    const void* rbin = base + L.rbin;
+    uint64_t* pacc = reinterpret_cast<uint64_t*>(base + L.pacc);
+    int32_t* pcnt = reinterpret_cast<int32_t*>(base + L.pcnt);
     const unsigned agrid = (unsigned)(ceil_div(L.items_max, (int64_t)kXcds) * kXcds);
     if (count)
         hipLaunchKernelGGL((hpart_acc_kernel<OP, true>), dim3(agrid), dim3(kAccBlock), 0, st, rval, rbin, L.nb,
@@ -1174,6 +1295,27 @@ static void run_partitioned(const int32_t* inds, const float* vs, int64_t n, int
                            L.ntiles, D, istart, itile, pacc, pcnt);
     hipLaunchKernelGGL(hpart_merge_kernel<OP>, dim3(flat_grid(m, 256, 1)), dim3(256), 0, st, pacc,
                        count ? pcnt : nullptr, istart, m, gacc, count);
+}
+
+// The log-add-exp reduce_by_index on the partition (FP32, the bins beyond
+// one block's LDS): one tile sort, two sweeps per work item, one merge.
+bool hist_lae_partition_ok(pvjp_dtype dtype, int64_t m) {
+    return dtype == PVJP_F32 && use_partition(PVJP_ADD, true, m, false);
+}
+
+void hist_lae_partitioned(const int32_t* inds, const float* x, int64_t n, int32_t m, float* hs, char* ws,
+                          hipStream_t st) {
+    const PartLayout L = part_layout(n, m);
+    part_sort<PVJP_ADD>(inds, x, n, m, L, ws, st);
+    double* psum = reinterpret_cast<double*>(ws + L.pacc);
+    uint32_t* pmax = reinterpret_cast<uint32_t*>(ws + L.pcnt);
+    const unsigned agrid = (unsigned)(ceil_div(L.items_max, (int64_t)kXcds) * kXcds);
+    hipLaunchKernelGGL(hpart_lae_acc_kernel, dim3(agrid), dim3(kAccBlock), 0, st,
+                       reinterpret_cast<const uint32_t*>(ws + L.rval), (const void*)(ws + L.rbin), L.nb, L.ntiles,
+                       reinterpret_cast<const uint32_t*>(ws + L.D), reinterpret_cast<const int32_t*>(ws + L.istart),
+                       reinterpret_cast<const int32_t*>(ws + L.itile), psum, pmax);
+    hipLaunchKernelGGL(hpart_lae_merge_kernel, dim3(flat_grid(m, 256, 1)), dim3(256), 0, st, psum, pmax,
+                       reinterpret_cast<const int32_t*>(ws + L.istart), m, hs);
 }
 
 template <class T, int OP, bool CACHE, bool COUNTS>

@@ -3,8 +3,11 @@
 // bin b of e^(x_i).  The operator commutes, so ls_i (.) x_i (.) rs_i is the
 // bin's total whatever the order of the bin's elements, and the general rule
 // gives element i the adjoint hs_bar[b] e^(x_i - hs[b]): one pass, no sort.
-// The primal runs on this library's reduce_by_index paths: the bin maxima
-// (max), then the shifted exponentials summed per bin (+, FP64 sums), then
+// The primal: for FP32 with bins beyond one block's LDS, one pass of the
+// bucket partition whose work items take each bin's maximum and then the
+// sum of e^(x - maximum) over the same records (FP64), merged per bin by
+// rescaling; otherwise this library's reduce_by_index paths in turn: the bin
+// maxima (max), the shifted exponentials summed per bin (+, FP64 sums), and
 // hs = max + log(sum).  Over the extended reals -inf is the neutral element:
 // an empty bin, or one of -inf elements only, gets -inf and a -inf element
 // gets adjoint 0.  An element equal to its bin's maximum contributes e^0 = 1
@@ -13,6 +16,7 @@
 // hs_bar (the limit of the softmax weight of a unique +inf); several +inf
 // elements of one bin each get it.  Indices outside [0, m) are skipped.
 #include "common.h"
+#include "hpart.h"
 
 namespace pvjp {
 
@@ -121,6 +125,13 @@ static HlPlan hl_plan(pvjp_dtype dtype, int64_t n, int64_t m) {
 template <class T>
 static pvjp_status hl_primal(pvjp_dtype dtype, const int32_t* inds, const T* x, int64_t n, int64_t m, T* hs,
                              char* w, const HlPlan& p, hipStream_t st) {
+    if constexpr (sizeof(T) == 4) {
+        if (hist_lae_partition_ok(dtype, m)) {
+            // one partition, the maximum and the scaled sum per work item
+            hist_lae_partitioned(inds, (const float*)x, n, (int32_t)m, (float*)hs, w + p.hist, st);
+            return PVJP_OK;
+        }
+    }
     T* hmax = (T*)(w + p.hmax);
     T* e = (T*)(w + p.e);
     T* hsum = (T*)(w + p.hsum);
