@@ -879,8 +879,16 @@ __device__ __forceinline__ void acc_record(uint64_t* acc, int32_t* cnt, uint32_t
     if (OP != PVJP_ADD) {
         // the tile start plus the position in the tile: the element index
         const int64_t e = tile_base + (int64_t)(at & ~(uint32_t)(kTile - 1)) + (int64_t)(bn >> 16);
-        atomicMax(reinterpret_cast<unsigned long long*>(&acc[j * kAccCopies + copy]),
-                  (unsigned long long)elem_key<OP>(__uint_as_float(v), e));
+        // A key only ever grows, so a record whose key does not exceed the
+        // word read now cannot win and skips the atomic.  A read of one word
+        // by many lanes is a broadcast, while atomics on one word serialise:
+        // on a hot bin almost every record stops here, and on a uniform one
+        // the expected number of winners among k records is the k-th
+        // harmonic number.
+        const uint64_t key = elem_key<OP>(__uint_as_float(v), e);
+        uint64_t* w = &acc[j * kAccCopies + copy];
+        if (key > __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+            atomicMax(reinterpret_cast<unsigned long long*>(w), (unsigned long long)key);
     } else {
         atomicAdd(reinterpret_cast<double*>(&acc[j * kAccCopies + copy]), (double)__uint_as_float(v));
     }

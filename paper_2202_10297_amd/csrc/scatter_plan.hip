@@ -30,7 +30,7 @@
 
 namespace pvjp {
 
-constexpr int kSpBlock = 256;
+constexpr int kSpBlock = 512;
 constexpr int kSpChunk = 4096;          // updates per chunk of a bucketing pass
 constexpr int kSpPer = kSpChunk / kSpBlock;
 constexpr int kSpFineBits = 6;          // fine digits per coarse bucket: 64
@@ -42,21 +42,44 @@ constexpr int kSpScanTile = 4096;       // entries per tile of the count scans (
 template <class T>
 constexpr int sp_s0() { return sizeof(T) == 4 ? 13 : 12; }  // log2 of window elements
 
+// Blocks are dealt to the 8 accelerator dies in turn (block b to die b % 8),
+// and each die has its own L2.  The bucketing passes give each die a
+// contiguous range of chunks instead: the count or run that chunk c writes
+// for a digit sits right before chunk c + 1's, so the lines the two share
+// are completed in one L2 and leave it whole instead of as two partial
+// writes from two dies.  Returns -1 for the few blocks past the last chunk.
+constexpr int kSpXcds = 8;
+__device__ __forceinline__ int sp_xcd_chunk(int nchunks) {
+    const int per = (nchunks + kSpXcds - 1) / kSpXcds;
+    const int slot = (int)(blockIdx.x / kSpXcds);
+    const int c = (int)(blockIdx.x % kSpXcds) * per + slot;
+    return (slot < per && c < nchunks) ? c : -1;
+}
+static unsigned sp_xcd_grid(int64_t nchunks) { return (unsigned)(ceil_div(nchunks, (int64_t)kSpXcds) * kSpXcds); }
+
 // --------------------------------------------------------- bucketing pass 1
 // cnt[d * nch + c] = number of valid updates of chunk c whose coarse digit is d.
 __global__ __launch_bounds__(kSpBlock) void sp_count1_kernel(const int32_t* __restrict__ is, int64_t m, int64_t n,
                                                              int s1, int nc, int nch, int32_t* __restrict__ cnt) {
     extern __shared__ int32_t lc[];  // [nc]
+    const int c = sp_xcd_chunk(nch);
+    if (c < 0) return;
     for (int d = threadIdx.x; d < nc; d += kSpBlock) lc[d] = 0;
     __syncthreads();
-    const int c = blockIdx.x;
     const int64_t j0 = (int64_t)c * kSpChunk;
+    if (m > 0) {
+        // all of the thread's loads first (clamped, not predicated, so that
+        // they are in flight together), then the counts
+        int32_t k[kSpPer];
 #pragma unroll
-    for (int u = 0; u < kSpPer; ++u) {
-        const int64_t j = j0 + (int64_t)u * kSpBlock + threadIdx.x;
-        if (j < m) {
-            const int32_t k = is[j];
-            if (k >= 0 && (int64_t)k < n) atomicAdd(&lc[k >> s1], 1);
+        for (int u = 0; u < kSpPer; ++u) {
+            const int64_t j = j0 + (int64_t)u * kSpBlock + threadIdx.x;
+            k[u] = is[j < m ? j : m - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < kSpPer; ++u) {
+            const int64_t j = j0 + (int64_t)u * kSpBlock + threadIdx.x;
+            if (j < m && k[u] >= 0 && (int64_t)k[u] < n) atomicAdd(&lc[k[u] >> s1], 1);
         }
     }
     __syncthreads();
@@ -247,7 +270,8 @@ __global__ __launch_bounds__(kSpBlock) void sp_scatter1_kernel(const int32_t* __
     extern __shared__ __align__(16) char smem[];
     __shared__ IntSum::S wtot[kSpBlock / kWave];
     const SpStage<T> L = sp_stage_layout<T>(smem, nc);
-    const int c = blockIdx.x;
+    const int c = sp_xcd_chunk(nch);
+    if (c < 0 || m <= 0) return;  // with no updates there is nothing to place
     for (int d = threadIdx.x; d < nc; d += kSpBlock) {
         L.cnt[d] = 0;
         L.base[d] = off1[(int64_t)d * nch + c];
@@ -256,19 +280,20 @@ __global__ __launch_bounds__(kSpBlock) void sp_scatter1_kernel(const int32_t* __
     const int64_t j0 = (int64_t)c * kSpChunk;
     int32_t k[kSpPer], jj[kSpPer];
     T v[kSpPer];
+    // loads clamped to the last update, then the ones past it or out of
+    // range are marked "no record"
 #pragma unroll
     for (int u = 0; u < kSpPer; ++u) {
         const int64_t j = j0 + (int64_t)u * kSpBlock + threadIdx.x;
-        k[u] = -1;
+        const int64_t jc = j < m ? j : m - 1;
+        k[u] = is[jc];
+        v[u] = vs[jc];
         jj[u] = (int32_t)j;
-        v[u] = T(0);
-        if (j < m) {
-            const int32_t kk = is[j];
-            if (kk >= 0 && (int64_t)kk < n) {
-                k[u] = kk;
-                v[u] = vs[j];
-            }
-        }
+    }
+#pragma unroll
+    for (int u = 0; u < kSpPer; ++u) {
+        const int64_t j = j0 + (int64_t)u * kSpBlock + threadIdx.x;
+        if (j >= m || k[u] < 0 || (int64_t)k[u] >= n) k[u] = -1;
     }
     sp_scatter_chunk<T>(L, nc, k, jj, v, CoarseDigit{s1}, rk, rj, rv, wtot);
 }
@@ -289,12 +314,14 @@ __device__ __forceinline__ int sp_owner(const int32_t* __restrict__ chb2, int nc
 // f * nch2[c] + i.  Blocks past the last chunk zero their 64 entries, so the
 // whole array scans to valid offsets.
 __global__ __launch_bounds__(kSpBlock) void sp_count2_kernel(const int32_t* __restrict__ rk, int s0, int nc,
+                                                             int nch2max,
                                                              const int32_t* __restrict__ cstart,
                                                              const int32_t* __restrict__ nch2,
                                                              const int32_t* __restrict__ chb2,
                                                              int32_t* __restrict__ cnt2) {
     __shared__ int32_t lc[kSpFine];
-    const int g = blockIdx.x;
+    const int g = sp_xcd_chunk(nch2max);
+    if (g < 0) return;
     const int nchunks = chb2[nc];
     if (g >= nchunks) {
         if (threadIdx.x < kSpFine) cnt2[(int64_t)g * kSpFine + threadIdx.x] = 0;
@@ -306,10 +333,17 @@ __global__ __launch_bounds__(kSpBlock) void sp_count2_kernel(const int32_t* __re
     const int i = g - chb2[c];
     const int64_t r0 = (int64_t)cstart[c] + (int64_t)i * kSpChunk;
     const int64_t r1 = (r0 + kSpChunk < (int64_t)cstart[c + 1]) ? r0 + kSpChunk : (int64_t)cstart[c + 1];
+    // a chunk holds at least one record: loads clamped to its last one
+    int32_t k[kSpPer];
 #pragma unroll
     for (int u = 0; u < kSpPer; ++u) {
         const int64_t r = r0 + (int64_t)u * kSpBlock + threadIdx.x;
-        if (r < r1) atomicAdd(&lc[(rk[r] >> s0) & (kSpFine - 1)], 1);
+        k[u] = rk[r < r1 ? r : r1 - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kSpPer; ++u) {
+        const int64_t r = r0 + (int64_t)u * kSpBlock + threadIdx.x;
+        if (r < r1) atomicAdd(&lc[(k[u] >> s0) & (kSpFine - 1)], 1);
     }
     __syncthreads();
     if (threadIdx.x < kSpFine)
@@ -320,7 +354,7 @@ template <class T>
 __global__ __launch_bounds__(kSpBlock) void sp_scatter2_kernel(const int32_t* __restrict__ rk1,
                                                                const int32_t* __restrict__ rj1,
                                                                const T* __restrict__ rv1, int s0, int nc,
-                                                               const int32_t* __restrict__ cstart,
+                                                               int nch2max, const int32_t* __restrict__ cstart,
                                                                const int32_t* __restrict__ nch2,
                                                                const int32_t* __restrict__ chb2,
                                                                const int32_t* __restrict__ off2,
@@ -328,8 +362,8 @@ __global__ __launch_bounds__(kSpBlock) void sp_scatter2_kernel(const int32_t* __
                                                                T* __restrict__ rv) {
     extern __shared__ __align__(16) char smem[];
     __shared__ IntSum::S wtot[kSpBlock / kWave];
-    const int g = blockIdx.x;
-    if (g >= chb2[nc]) return;
+    const int g = sp_xcd_chunk(nch2max);
+    if (g < 0 || g >= chb2[nc]) return;
     const int c = sp_owner(chb2, nc, g);
     const int i = g - chb2[c];
     const SpStage<T> L = sp_stage_layout<T>(smem, kSpFine);
@@ -345,11 +379,14 @@ __global__ __launch_bounds__(kSpBlock) void sp_scatter2_kernel(const int32_t* __
 #pragma unroll
     for (int u = 0; u < kSpPer; ++u) {
         const int64_t r = r0 + (int64_t)u * kSpBlock + threadIdx.x;
-        const bool in = r < r1;
-        k[u] = in ? rk1[r] : -1;
-        jj[u] = in ? rj1[r] : 0;
-        v[u] = in ? rv1[r] : T(0);
+        const int64_t rc = r < r1 ? r : r1 - 1;  // a chunk holds at least one record
+        k[u] = rk1[rc];
+        jj[u] = rj1[rc];
+        v[u] = rv1[rc];
     }
+#pragma unroll
+    for (int u = 0; u < kSpPer; ++u)
+        if (r0 + (int64_t)u * kSpBlock + threadIdx.x >= r1) k[u] = -1;
     sp_scatter_chunk<T>(L, kSpFine, k, jj, v, FineDigit{s0}, rk, rj, rv, wtot);
 }
 
@@ -398,11 +435,18 @@ __device__ __forceinline__ void sp_win_store(T* __restrict__ g, const T* __restr
         for (int i = threadIdx.x; i < len; i += B) g[i] = l[i];
     }
 }
+// The first kSpFwdHeld rounds of a window's records are loaded before the
+// window itself, so both are in flight together (a window of uniformly
+// spread targets holds about 2^s0 / 4 records: 4 rounds of 512).  The loads
+// are clamped to the window's last record rather than predicated.
+constexpr int kSpFwdBlock = 512;
+constexpr int kSpFwdHeld = 4;
+
 template <class T>
-__global__ __launch_bounds__(512) void sp_apply_fwd_kernel(T* __restrict__ xs, int64_t n, int s0, int vec,
-                                                           const int32_t* __restrict__ wstart,
-                                                           const int32_t* __restrict__ rk, const T* __restrict__ rv,
-                                                           T* __restrict__ saved) {
+__global__ __launch_bounds__(kSpFwdBlock) void sp_apply_fwd_kernel(T* __restrict__ xs, int64_t n, int s0, int vec,
+                                                                   const int32_t* __restrict__ wstart,
+                                                                   const int32_t* __restrict__ rk,
+                                                                   const T* __restrict__ rv, T* __restrict__ saved) {
     __shared__ __align__(16) T lx[kSpWindowBytes / sizeof(T)];
     const int w = blockIdx.x;
     const int r0 = wstart[w], r1 = wstart[w + 1];
@@ -410,15 +454,33 @@ __global__ __launch_bounds__(512) void sp_apply_fwd_kernel(T* __restrict__ xs, i
     const int64_t x0 = (int64_t)w << s0;
     const int len = (int)((n - x0) < ((int64_t)1 << s0) ? (n - x0) : ((int64_t)1 << s0));
     const bool whole = vec && len == (1 << s0);
-    sp_win_load<T, 512>(lx, xs + x0, len, whole);
+    int32_t hk[kSpFwdHeld];
+    T hv[kSpFwdHeld];
+#pragma unroll
+    for (int t = 0; t < kSpFwdHeld; ++t) {
+        const int r = r0 + t * kSpFwdBlock + (int)threadIdx.x;
+        const int rc = r < r1 ? r : r1 - 1;
+        hk[t] = rk[rc];
+        hv[t] = rv[rc];
+    }
+    sp_win_load<T, kSpFwdBlock>(lx, xs + x0, len, whole);
     __syncthreads();
-    for (int r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+#pragma unroll
+    for (int t = 0; t < kSpFwdHeld; ++t) {
+        const int r = r0 + t * kSpFwdBlock + (int)threadIdx.x;
+        if (r < r1) {
+            const int kl = (int)(hk[t] - x0);
+            saved[r] = lx[kl];
+            lx[kl] = hv[t];
+        }
+    }
+    for (int r = r0 + kSpFwdHeld * kSpFwdBlock + (int)threadIdx.x; r < r1; r += kSpFwdBlock) {
         const int kl = (int)(rk[r] - x0);
         saved[r] = lx[kl];
         lx[kl] = rv[r];
     }
     __syncthreads();
-    sp_win_store<T, 512>(xs + x0, lx, len, whole);
+    sp_win_store<T, kSpFwdBlock>(xs + x0, lx, len, whole);
 }
 
 // The random writes of vs_bar are issued after the block's last barrier, so
@@ -445,22 +507,32 @@ __global__ __launch_bounds__(kSpVjpBlock) void sp_apply_vjp_kernel(T* __restrict
     const int64_t x0 = (int64_t)w << s0;
     const int len = (int)((n - x0) < ((int64_t)1 << s0) ? (n - x0) : ((int64_t)1 << s0));
     const bool whole = vec && len == (1 << s0);
-    sp_win_load<T, kSpVjpBlock>(ly, ybar + x0, len, whole);
-    if (RESTORE) sp_win_load<T, kSpVjpBlock>(lys, ys + x0, len, whole);
-    __syncthreads();
-    int32_t hj[kSpHeld];
-    T hg[kSpHeld];
+    // the held rounds' records are loaded (clamped to the last record)
+    // before the windows, so that all of them are in flight together
+    int32_t hk[kSpHeld], hj[kSpHeld];
+    T hs[kSpHeld], hg[kSpHeld];
 #pragma unroll
     for (int t = 0; t < kSpHeld; ++t) {
         const int r = r0 + t * kSpVjpBlock + (int)threadIdx.x;
-        hj[t] = -1;
+        const int rc = r < r1 ? r : r1 - 1;
+        hk[t] = rk[rc];
+        hj[t] = rj[rc];
+        hs[t] = RESTORE ? saved[rc] : T(0);
+    }
+    sp_win_load<T, kSpVjpBlock>(ly, ybar + x0, len, whole);
+    if (RESTORE) sp_win_load<T, kSpVjpBlock>(lys, ys + x0, len, whole);
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < kSpHeld; ++t) {
+        const int r = r0 + t * kSpVjpBlock + (int)threadIdx.x;
         hg[t] = T(0);
         if (r < r1) {
-            const int kl = (int)(rk[r] - x0);
-            hj[t] = rj[r];
+            const int kl = (int)(hk[t] - x0);
             hg[t] = ly[kl];
             ly[kl] = T(0);
-            if (RESTORE) lys[kl] = saved[r];
+            if (RESTORE) lys[kl] = hs[t];
+        } else {
+            hj[t] = -1;
         }
     }
     for (int r = r0 + kSpHeld * kSpVjpBlock + (int)threadIdx.x; r < r1; r += kSpVjpBlock) {
@@ -573,7 +645,7 @@ static pvjp_status sp_forward(T* xs, int64_t n, const int32_t* is, const T* vs, 
     T* saved = (T*)(p + L.saved);
     sp_allow_lds<T>();
     // pass 1: coarse buckets
-    hipLaunchKernelGGL(sp_count1_kernel, dim3(L.nch1), dim3(kSpBlock), (size_t)L.nc * 4, st, is, m, n, L.s1, L.nc,
+    hipLaunchKernelGGL(sp_count1_kernel, dim3(sp_xcd_grid(L.nch1)), dim3(kSpBlock), (size_t)L.nc * 4, st, is, m, n, L.s1, L.nc,
                        L.nch1, cnt1);
     hipLaunchKernelGGL(sp_tile_sum_kernel, dim3((unsigned)L.nt1), dim3(1024), 0, st, cnt1, L.n1, tsum1);
     hipLaunchKernelGGL(sp_tile_scan_kernel, dim3((unsigned)L.nt1), dim3(1024), 0, st, cnt1, L.n1, (const int32_t*)tsum1,
@@ -581,23 +653,25 @@ static pvjp_status sp_forward(T* xs, int64_t n, const int32_t* is, const T* vs, 
     hipLaunchKernelGGL(sp_seg_kernel, dim3(1), dim3(1024), 0, st, (const int32_t*)cnt1, L.nch1, L.nc,
                        (const int32_t*)total, cstart, nch2, chb2);
     const size_t lds1 = sp_stage_bytes(L.nc, sizeof(T));
-    hipLaunchKernelGGL(sp_scatter1_kernel<T>, dim3(L.nch1), dim3(kSpBlock), lds1, st, is, vs, m, n, L.s1, L.nc, L.nch1,
+    hipLaunchKernelGGL(sp_scatter1_kernel<T>, dim3(sp_xcd_grid(L.nch1)), dim3(kSpBlock), lds1, st, is, vs, m, n, L.s1, L.nc, L.nch1,
                        (const int32_t*)cnt1, rk1, rj1, rv1);
     // pass 2: fine buckets inside each coarse bucket
-    hipLaunchKernelGGL(sp_count2_kernel, dim3(L.nch2max), dim3(kSpBlock), 0, st, (const int32_t*)rk1, L.s0, L.nc,
+    hipLaunchKernelGGL(sp_count2_kernel, dim3(sp_xcd_grid(L.nch2max)), dim3(kSpBlock), 0, st, (const int32_t*)rk1,
+                       L.s0, L.nc, L.nch2max,
                        (const int32_t*)cstart, (const int32_t*)nch2, (const int32_t*)chb2, cnt2);
     hipLaunchKernelGGL(sp_tile_sum_kernel, dim3((unsigned)L.nt2), dim3(1024), 0, st, cnt2, L.n2, tsum2);
     hipLaunchKernelGGL(sp_tile_scan_kernel, dim3((unsigned)L.nt2), dim3(1024), 0, st, cnt2, L.n2, (const int32_t*)tsum2,
                        (int32_t*)nullptr);
     const size_t lds2 = sp_stage_bytes(kSpFine, sizeof(T));
-    hipLaunchKernelGGL(sp_scatter2_kernel<T>, dim3(L.nch2max), dim3(kSpBlock), lds2, st, (const int32_t*)rk1,
-                       (const int32_t*)rj1, (const T*)rv1, L.s0, L.nc, (const int32_t*)cstart, (const int32_t*)nch2,
+    hipLaunchKernelGGL(sp_scatter2_kernel<T>, dim3(sp_xcd_grid(L.nch2max)), dim3(kSpBlock), lds2, st,
+                       (const int32_t*)rk1, (const int32_t*)rj1, (const T*)rv1, L.s0, L.nc, L.nch2max,
+                       (const int32_t*)cstart, (const int32_t*)nch2,
                        (const int32_t*)chb2, (const int32_t*)cnt2, rk, rj, rv);
     hipLaunchKernelGGL(sp_wstart_kernel, dim3(flat_grid(L.nw + 1, 256, 1)), dim3(256), 0, st, L.nc,
                        (const int32_t*)cstart, (const int32_t*)nch2, (const int32_t*)chb2, (const int32_t*)cnt2, wstart);
     // the window sweep
     const int vec = aligned(xs, 16) ? 1 : 0;
-    hipLaunchKernelGGL(sp_apply_fwd_kernel<T>, dim3((unsigned)L.nw), dim3(512), 0, st, xs, n, L.s0, vec,
+    hipLaunchKernelGGL(sp_apply_fwd_kernel<T>, dim3((unsigned)L.nw), dim3(kSpFwdBlock), 0, st, xs, n, L.s0, vec,
                        (const int32_t*)wstart, (const int32_t*)rk, (const T*)rv, saved);
     return PVJP_OK;
 }
