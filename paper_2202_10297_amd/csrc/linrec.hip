@@ -64,7 +64,9 @@ __global__ __launch_bounds__(kScanBlock) void linrec_fwd_kernel(
     __shared__ S s_prefix;
 
     if (GIVEN) {
-        if (threadIdx.x == 0) s_ticket = blockIdx.x;
+        // right to left: the first tiles read are the last ones the
+        // aggregate pass read, which the last-level cache may still hold
+        if (threadIdx.x == 0) s_ticket = (uint32_t)(ntiles - 1 - blockIdx.x);
     } else if (threadIdx.x == 0) {
         s_ticket = lookback_draw(hdr, (uint32_t)(ntiles - 1), &s_tag);
         if (s_ticket >= ntiles) lookback_error(hdr, kErrTicket);
