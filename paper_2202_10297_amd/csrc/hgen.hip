@@ -49,7 +49,8 @@ constexpr int64_t kHgMaxBins = (int64_t)1 << (2 * kHgDigitBits);
 __global__ __launch_bounds__(kHgCountBlock) void hg_count_kernel(const int32_t* __restrict__ keys,
                                                                  const int2* __restrict__ pairs, int64_t n,
                                                                  const int32_t* __restrict__ nvalid, int32_t m,
-                                                                 int shift, int ndig, int32_t* __restrict__ cntb) {
+                                                                 int shift, int dmask, int ndig,
+                                                                 int32_t* __restrict__ cntb) {
     __shared__ int32_t cnt[kHgDigits];
     for (int d = threadIdx.x; d < ndig; d += kHgCountBlock) cnt[d] = 0;
     __syncthreads();
@@ -58,7 +59,7 @@ __global__ __launch_bounds__(kHgCountBlock) void hg_count_kernel(const int32_t* 
     const int64_t hi = (lo + kHgChunk < ne) ? lo + kHgChunk : ne;
     for (int64_t i = lo + threadIdx.x; i < hi; i += kHgCountBlock) {
         const int32_t k = keys ? keys[i] : pairs[i].x;
-        if ((uint32_t)k < (uint32_t)m) atomicAdd(&cnt[(k >> shift) & (kHgDigits - 1)], 1);
+        if ((uint32_t)k < (uint32_t)m) atomicAdd(&cnt[(k >> shift) & dmask], 1);
     }
     __syncthreads();
     for (int d = threadIdx.x; d < ndig; d += kHgCountBlock) cntb[(int64_t)blockIdx.x * kHgDigits + d] = cnt[d];
@@ -130,7 +131,8 @@ __global__ __launch_bounds__(kHgScanThreads) void hg_digitscan_kernel(int32_t* _
 __global__ __launch_bounds__(kWave) void hg_scatter_kernel(const int32_t* __restrict__ keys_in,
                                                            const int2* __restrict__ pairs_in, int64_t n,
                                                            const int32_t* __restrict__ nvalid, int32_t m, int shift,
-                                                           int ndig, int nbits, const int32_t* __restrict__ cntb,
+                                                           int dmask, int ndig, int nbits,
+                                                           const int32_t* __restrict__ cntb,
                                                            const int32_t* __restrict__ ctot,
                                                            int2* __restrict__ pairs_out) {
     __shared__ int32_t pos[kHgDigits];
@@ -165,7 +167,7 @@ __global__ __launch_bounds__(kWave) void hg_scatter_kernel(const int32_t* __rest
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const bool valid = (uint32_t)k[u] < (uint32_t)m;
-            const int d = valid ? (k[u] >> shift) & (kHgDigits - 1) : 0;
+            const int d = valid ? (k[u] >> shift) & dmask : 0;
             uint64_t peers = __ballot(valid);
             for (int bit = 0; bit < nbits; ++bit) {
                 const bool one = (d >> bit) & 1;
@@ -533,24 +535,32 @@ static const int2* hg_prepare(const int32_t* inds, int64_t n, int32_t m, const H
     int32_t* nvalid = reinterpret_cast<int32_t*>(w + L.nvalid);
     int2* pA = reinterpret_cast<int2*>(w + L.pairsA);
     int2* pB = reinterpret_cast<int2*>(w + L.pairsB);
-    const int passes = m > kHgDigits ? 2 : 1;
+    // bits of the largest bin, split evenly between the two passes when one
+    // pass cannot take them all (fewer digits per pass: longer runs of a
+    // digit within a chunk, whose stores then share lines)
+    int bbits = 0;
+    while (((int64_t)1 << bbits) < (int64_t)m) ++bbits;
+    const int passes = bbits > kHgDigitBits ? 2 : 1;
+    const int bits0 = passes == 2 ? (bbits + 1) / 2 : kHgDigitBits;
     const int2* pin = nullptr;
     for (int pass = 0; pass < passes; ++pass) {
-        const int shift = pass * kHgDigitBits;
-        const int ndig = pass == 0 ? (int)std::min<int64_t>(m, kHgDigits) : (int)ceil_div(m, kHgDigits);
+        const int shift = pass * bits0;
+        const int dmask = pass == 0 ? (1 << bits0) - 1 : kHgDigits - 1;
+        const int ndig = pass == 0 ? (int)std::min<int64_t>(m, (int64_t)1 << bits0)
+                                   : (int)ceil_div(m, (int64_t)1 << bits0);
         int nbits = 0;
         while ((1 << nbits) < ndig) ++nbits;
         int2* pout = pass == 0 ? pA : pB;
         const int32_t* kin = pass == 0 ? inds : nullptr;
         const int32_t* nv = pass == 0 ? nullptr : nvalid;
         hipLaunchKernelGGL(hg_count_kernel, dim3((unsigned)L.nblk), dim3(kHgCountBlock), 0, st, kin, pin, n, nv, m,
-                           shift, ndig, cntb);
+                           shift, dmask, ndig, cntb);
         hipLaunchKernelGGL(hg_colscan_kernel, dim3((unsigned)ceil_div(ndig, kHgCountBlock), (unsigned)L.nchunks),
                            dim3(kHgCountBlock), 0, st, cntb, (int)L.nblk, ndig, ctot);
         hipLaunchKernelGGL(hg_digitscan_kernel, dim3(1), dim3(kHgScanThreads), 0, st, ctot, (int)L.nchunks, ndig,
                            pass == 0 ? nvalid : nullptr);
         hipLaunchKernelGGL(hg_scatter_kernel, dim3((unsigned)L.nblk), dim3(kWave), 0, st, kin, pin, n, nv, m, shift,
-                           ndig, nbits, cntb, ctot, pout);
+                           dmask, ndig, nbits, cntb, ctot, pout);
         pin = pout;
     }
     HgIn<T> xs{};
