@@ -5,11 +5,14 @@
 // neutral element for an empty bin; indices outside [0, m) are skipped).
 // The operator need not commute, so each bin's elements must meet in index
 // order:
-//   1. a stable sort of the in-range elements by bin: one or two passes of a
-//      12-bit digit, low digit first, each a per-chunk digit count, a
-//      digit-major scan of the counts and a stable scatter in which one wave
-//      walks its chunk in index order (ranks among equal digits from wave
-//      ballots, so equal bins keep their order);
+//   1. a stable sort of the in-range elements by bin: one pass of up to 12
+//      bits, or two passes splitting the bin's bits evenly, low digit first,
+//      each a per-chunk digit count, a digit-major scan of the counts and a
+//      stable scatter in which one wave walks its chunk in index order (ranks
+//      among equal digits from wave ballots, so equal bins keep their order).
+//      The sort moves whole records -- bin, element index and the element's
+//      components -- so x is read once, in index order, instead of gathered
+//      at random into sorted order;
 //   2. bin starts, by binary search of the sorted bins;
 //   3. over the sorted elements, segmented exclusive scans: forward (the
 //      fold of the bin's earlier elements, ls) and reversed (of its later
@@ -42,12 +45,39 @@ constexpr int kHgTile = kHgBlock * kHgIpt;
 constexpr size_t kHgSlot = 64;       // bytes per tile for a lifted state
 constexpr int64_t kHgMaxBins = (int64_t)1 << (2 * kHgDigitBits);
 
+// A sort record: word 0 the bin, word 1 the element index, from word 2 the
+// element's K components (T each), padded to whole 16-byte vectors so that a
+// record moves with full-width loads and stores.
+template <int W>
+struct alignas(16) HgRec {
+    uint32_t w[W];
+};
+template <class T, int K>
+constexpr int hg_words() {
+    return (2 + K * (int)(sizeof(T) / 4) + 3) / 4 * 4;
+}
+template <class T, int W>
+__device__ __forceinline__ T hg_comp(const HgRec<W>& r, int k) {
+    return reinterpret_cast<const T*>(&r.w[2])[k];
+}
+
+// Up to four component arrays of one dtype.
+template <class T>
+struct HgIn {
+    const T* p[4];
+};
+template <class T>
+struct HgOut {
+    T* p[4];
+};
+
 // ------------------------------------------------------------------ sort
 // Digit counts of one chunk (any order: counting needs no stability).  The
 // first pass reads the indices (out-of-range ones skipped), the second the
 // first pass's output, whose length is on the device.
+template <int W>
 __global__ __launch_bounds__(kHgCountBlock) void hg_count_kernel(const int32_t* __restrict__ keys,
-                                                                 const int2* __restrict__ pairs, int64_t n,
+                                                                 const HgRec<W>* __restrict__ recs, int64_t n,
                                                                  const int32_t* __restrict__ nvalid, int32_t m,
                                                                  int shift, int dmask, int ndig,
                                                                  int32_t* __restrict__ cntb) {
@@ -58,7 +88,7 @@ __global__ __launch_bounds__(kHgCountBlock) void hg_count_kernel(const int32_t* 
     const int64_t lo = (int64_t)blockIdx.x * kHgChunk;
     const int64_t hi = (lo + kHgChunk < ne) ? lo + kHgChunk : ne;
     for (int64_t i = lo + threadIdx.x; i < hi; i += kHgCountBlock) {
-        const int32_t k = keys ? keys[i] : pairs[i].x;
+        const int32_t k = keys ? keys[i] : (int32_t)recs[i].w[0];
         if ((uint32_t)k < (uint32_t)m) atomicAdd(&cnt[(k >> shift) & dmask], 1);
     }
     __syncthreads();
@@ -127,14 +157,17 @@ __global__ __launch_bounds__(kHgScanThreads) void hg_digitscan_kernel(int32_t* _
 // Stable scatter of one chunk by one wave, 64 elements at a time in index
 // order.  Lanes with equal digits find each other with one ballot per digit
 // bit; a lane's rank among them and the digit's running position (LDS) give
-// its place, and the group's last such lane advances the position.
-__global__ __launch_bounds__(kWave) void hg_scatter_kernel(const int32_t* __restrict__ keys_in,
-                                                           const int2* __restrict__ pairs_in, int64_t n,
+// its place, and the group's last such lane advances the position.  The
+// first pass builds each record from the indices and x (read in order), the
+// second moves records.
+template <class T, int K, int W>
+__global__ __launch_bounds__(kWave) void hg_scatter_kernel(const int32_t* __restrict__ keys_in, HgIn<T> x,
+                                                           const HgRec<W>* __restrict__ recs_in, int64_t n,
                                                            const int32_t* __restrict__ nvalid, int32_t m, int shift,
                                                            int dmask, int ndig, int nbits,
                                                            const int32_t* __restrict__ cntb,
                                                            const int32_t* __restrict__ ctot,
-                                                           int2* __restrict__ pairs_out) {
+                                                           HgRec<W>* __restrict__ recs_out) {
     __shared__ int32_t pos[kHgDigits];
     const int lane = threadIdx.x;
     const int blk = blockIdx.x;
@@ -148,26 +181,28 @@ __global__ __launch_bounds__(kWave) void hg_scatter_kernel(const int32_t* __rest
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
     constexpr int U = 4;  // groups whose loads are in flight together
     for (int64_t g0 = lo; g0 < hi; g0 += (int64_t)U * kWave) {
-        int32_t k[U], src[U];
+        HgRec<W> r[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t i = g0 + (int64_t)u * kWave + lane;
             if (i < hi && keys_in) {
-                k[u] = keys_in[i];
-                src[u] = (int32_t)i;
+                r[u].w[0] = (uint32_t)keys_in[i];
+                r[u].w[1] = (uint32_t)i;
+#pragma unroll
+                for (int w = 2; w < W; ++w) r[u].w[w] = 0u;
+#pragma unroll
+                for (int k = 0; k < K; ++k) reinterpret_cast<T*>(&r[u].w[2])[k] = x.p[k][i];
             } else if (i < hi) {
-                const int2 q = pairs_in[i];
-                k[u] = q.x;
-                src[u] = q.y;
+                r[u] = recs_in[i];
             } else {
-                k[u] = -1;
-                src[u] = 0;
+                r[u].w[0] = 0xffffffffu;  // no element: outside every bin
             }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const bool valid = (uint32_t)k[u] < (uint32_t)m;
-            const int d = valid ? (k[u] >> shift) & dmask : 0;
+            const int32_t kk = (int32_t)r[u].w[0];
+            const bool valid = (uint32_t)kk < (uint32_t)m;
+            const int d = valid ? (kk >> shift) & dmask : 0;
             uint64_t peers = __ballot(valid);
             for (int bit = 0; bit < nbits; ++bit) {
                 const bool one = (d >> bit) & 1;
@@ -177,8 +212,7 @@ __global__ __launch_bounds__(kWave) void hg_scatter_kernel(const int32_t* __rest
             const int base = valid ? pos[d] : 0;
             const int rank = __popcll(peers & below);
             if (valid) {
-                // the bin and the element index in one 8-byte store
-                pairs_out[base + rank] = make_int2(k[u], src[u]);
+                recs_out[base + rank] = r[u];
                 // the highest lane of the group moves the digit's position on
                 if ((peers >> lane) == 1ull) pos[d] = base + __popcll(peers);
             }
@@ -187,7 +221,8 @@ __global__ __launch_bounds__(kWave) void hg_scatter_kernel(const int32_t* __rest
 }
 
 // off[b] = the first sorted position whose bin is b or later (b in [0, m]).
-__global__ __launch_bounds__(256) void hg_off_kernel(const int2* __restrict__ pairs,
+template <int W>
+__global__ __launch_bounds__(256) void hg_off_kernel(const HgRec<W>* __restrict__ recs,
                                                      const int32_t* __restrict__ nvalid, int32_t m,
                                                      int32_t* __restrict__ off) {
     const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -195,7 +230,7 @@ __global__ __launch_bounds__(256) void hg_off_kernel(const int2* __restrict__ pa
     int64_t lo = 0, hi = *nvalid;
     while (lo < hi) {
         const int64_t mid = (lo + hi) >> 1;
-        if ((int64_t)pairs[mid].x < b) lo = mid + 1; else hi = mid;
+        if ((int64_t)recs[mid].w[0] < b) lo = mid + 1; else hi = mid;
     }
     off[b] = (int32_t)lo;
 }
@@ -220,18 +255,9 @@ struct SegOf {
     }
 };
 
-template <class T>
-struct HgIn {
-    const T* p[4];
-};
-template <class T>
-struct HgOut {
-    T* p[4];
-};
 
 // Sorted element p: its bin, its own index and its components (as FP64, from
-// the sorted copy of x), plus whether it opens (first) and closes (last) its
-// bin.
+// its record), plus whether it opens (first) and closes (last) its bin.
 template <class Op, class T>
 struct HgElem {
     int32_t key, src;
@@ -239,39 +265,25 @@ struct HgElem {
     typename Op::S a;
 };
 
-template <class Op, class T>
-__device__ __forceinline__ HgElem<Op, T> hg_elem(const int2* __restrict__ pairs, const HgIn<T>& xs, int64_t nv,
-                                                 int64_t p) {
+template <class Op, class T, int W>
+__device__ __forceinline__ HgElem<Op, T> hg_elem(const HgRec<W>* __restrict__ recs, int64_t nv, int64_t p) {
     HgElem<Op, T> e;
-    const int2 q = pairs[p];
-    e.key = q.x;
-    e.src = q.y;
-    e.first = p == 0 || pairs[p - 1].x != e.key;
-    e.last = p + 1 == nv || pairs[p + 1].x != e.key;
+    const HgRec<W> r = recs[p];
+    e.key = (int32_t)r.w[0];
+    e.src = (int32_t)r.w[1];
+    e.first = p == 0 || (int32_t)recs[p - 1].w[0] != e.key;
+    e.last = p + 1 == nv || (int32_t)recs[p + 1].w[0] != e.key;
     double c[Op::K];
 #pragma unroll
-    for (int k = 0; k < Op::K; ++k) c[k] = (double)xs.p[k][p];
+    for (int k = 0; k < Op::K; ++k) c[k] = (double)hg_comp<T, W>(r, k);
     e.a = Op::elem(c);
     return e;
 }
 
-// The components in sorted order: one gather of x per element and
-// component, after which every pass reads them in order.
-template <class T>
-__global__ __launch_bounds__(256) void hg_gather_kernel(const int2* __restrict__ pairs,
-                                                        const int32_t* __restrict__ nvalid, HgIn<T> x, int K,
-                                                        HgOut<T> xs) {
-    const int64_t nv = *nvalid;
-    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < nv; p += (int64_t)gridDim.x * 256) {
-        const int32_t src = pairs[p].y;
-        for (int k = 0; k < K; ++k) xs.p[k][p] = x.p[k][src];
-    }
-}
-
 // Tile folds, forward (flag: the bin's first element) and reversed (flag:
 // its last element, scanned with the operands exchanged).
-template <class Op, class T>
-__global__ __launch_bounds__(kHgBlock) void hg_tile_fold_kernel(const int2* __restrict__ pairs, HgIn<T> xs,
+template <class Op, class T, int W>
+__global__ __launch_bounds__(kHgBlock) void hg_tile_fold_kernel(const HgRec<W>* __restrict__ recs,
                                                                 const int32_t* __restrict__ nvalid, char* __restrict__ aggF,
                                                                 char* __restrict__ aggR) {
     using F = SegOf<Op>;
@@ -287,7 +299,7 @@ __global__ __launch_bounds__(kHgBlock) void hg_tile_fold_kernel(const int2* __re
     for (int j = 0; j < kHgIpt; ++j) {
         re[j] = R::id();
         if (p0 + j < nv) {
-            const HgElem<Op, T> e = hg_elem<Op, T>(pairs, xs, nv, p0 + j);
+            const HgElem<Op, T> e = hg_elem<Op, T, W>(recs, nv, p0 + j);
             sf = F::comb(sf, typename F::S{e.a, e.first ? 1u : 0u, 0u});
             re[j] = typename R::S{e.a, e.last ? 1u : 0u, 0u};
         }
@@ -392,8 +404,8 @@ __global__ __launch_bounds__(kHgGroup) void hg_group_carry_kernel(const char* __
 // Per tile: the forward scan with the tile's carry; the primal writes each
 // bin's fold at its last element.  The VJP also runs the reversed scan and
 // maps f over (ls, x, rs) with y_bar = hs_bar of the element's bin.
-template <class Op, class T, bool VJP, bool ACC>
-__global__ __launch_bounds__(kHgBlock) void hg_apply_kernel(const int2* __restrict__ pairs, HgIn<T> xs,
+template <class Op, class T, int W, bool VJP, bool ACC>
+__global__ __launch_bounds__(kHgBlock) void hg_apply_kernel(const HgRec<W>* __restrict__ recs,
                                                             const int32_t* __restrict__ nvalid,
                                                             const char* __restrict__ carF,
                                                             const char* __restrict__ carR, HgOut<T> hs,
@@ -412,7 +424,7 @@ __global__ __launch_bounds__(kHgBlock) void hg_apply_kernel(const int2* __restri
     for (int j = 0; j < kHgIpt; ++j) {
         in[j] = p0 + j < nv;
         if (in[j]) {
-            e[j] = hg_elem<Op, T>(pairs, xs, nv, p0 + j);
+            e[j] = hg_elem<Op, T, W>(recs, nv, p0 + j);
             sf = F::comb(sf, typename F::S{e[j].a, e[j].first ? 1u : 0u, 0u});
         }
     }
@@ -490,10 +502,15 @@ static int hg_components(pvjp_gop op) {
 struct HgLayout {
     int64_t nblk, nchunks, ntiles;
     int64_t ngroups;
-    size_t cntb, ctot, nvalid, pairsA, pairsB, xs[4], off, aggF, aggR, carF, carR, gF, gR, gcF, gcR, total;
+    size_t cntb, ctot, nvalid, recA, recB, off, aggF, aggR, carF, carR, gF, gR, gcF, gcR, total;
 };
 
-static HgLayout hg_layout(int64_t n, int64_t m, int K, size_t tsize) {
+static size_t hg_rec_bytes(int K, size_t tsize) {
+    return (size_t)((2 + K * (int)(tsize / 4) + 3) / 4 * 4) * 4;
+}
+
+// rec_bytes: the size of one sort record (hg_rec_bytes).
+static HgLayout hg_layout(int64_t n, int64_t m, size_t rec_bytes) {
     HgLayout L{};
     const int64_t nn = n > 0 ? n : 1;
     L.nblk = ceil_div(nn, kHgChunk);
@@ -508,9 +525,8 @@ static HgLayout hg_layout(int64_t n, int64_t m, int K, size_t tsize) {
     L.cntb = take((size_t)L.nblk * kHgDigits * 4);
     L.ctot = take((size_t)L.nchunks * kHgDigits * 4);
     L.nvalid = take(4);
-    L.pairsA = take((size_t)nn * 8);
-    L.pairsB = take((size_t)nn * 8);
-    for (int k = 0; k < K; ++k) L.xs[k] = take((size_t)nn * tsize);
+    L.recA = take((size_t)nn * rec_bytes);
+    L.recB = take((size_t)nn * rec_bytes);
     L.off = take((size_t)(m + 1) * 4);
     L.aggF = take((size_t)L.ntiles * kHgSlot);
     L.aggR = take((size_t)L.ntiles * kHgSlot);
@@ -525,16 +541,18 @@ static HgLayout hg_layout(int64_t n, int64_t m, int K, size_t tsize) {
     return L;
 }
 
-// The sort, the sorted copy of x and the tile carries, shared by both entry
-// points.  Returns the sorted (bin, element index) pairs and the sorted x.
+// The sort and the tile carries, shared by both entry points.  Returns the
+// sorted records.
 template <class Op, class T>
-static const int2* hg_prepare(const int32_t* inds, int64_t n, int32_t m, const HgIn<T>& x, char* w,
-                              const HgLayout& L, HgIn<T>* xs_out, hipStream_t st) {
+static const HgRec<hg_words<T, Op::K>()>* hg_prepare(const int32_t* inds, int64_t n, int32_t m, const HgIn<T>& x,
+                                                     char* w, const HgLayout& L, hipStream_t st) {
+    constexpr int W = hg_words<T, Op::K>();
+    using Rec = HgRec<W>;
     int32_t* cntb = reinterpret_cast<int32_t*>(w + L.cntb);
     int32_t* ctot = reinterpret_cast<int32_t*>(w + L.ctot);
     int32_t* nvalid = reinterpret_cast<int32_t*>(w + L.nvalid);
-    int2* pA = reinterpret_cast<int2*>(w + L.pairsA);
-    int2* pB = reinterpret_cast<int2*>(w + L.pairsB);
+    Rec* rA = reinterpret_cast<Rec*>(w + L.recA);
+    Rec* rB = reinterpret_cast<Rec*>(w + L.recB);
     // bits of the largest bin, split evenly between the two passes when one
     // pass cannot take them all (fewer digits per pass: longer runs of a
     // digit within a chunk, whose stores then share lines)
@@ -542,7 +560,7 @@ static const int2* hg_prepare(const int32_t* inds, int64_t n, int32_t m, const H
     while (((int64_t)1 << bbits) < (int64_t)m) ++bbits;
     const int passes = bbits > kHgDigitBits ? 2 : 1;
     const int bits0 = passes == 2 ? (bbits + 1) / 2 : kHgDigitBits;
-    const int2* pin = nullptr;
+    const Rec* rin = nullptr;
     for (int pass = 0; pass < passes; ++pass) {
         const int shift = pass * bits0;
         const int dmask = pass == 0 ? (1 << bits0) - 1 : kHgDigits - 1;
@@ -550,29 +568,20 @@ static const int2* hg_prepare(const int32_t* inds, int64_t n, int32_t m, const H
                                    : (int)ceil_div(m, (int64_t)1 << bits0);
         int nbits = 0;
         while ((1 << nbits) < ndig) ++nbits;
-        int2* pout = pass == 0 ? pA : pB;
+        Rec* rout = pass == 0 ? rA : rB;
         const int32_t* kin = pass == 0 ? inds : nullptr;
         const int32_t* nv = pass == 0 ? nullptr : nvalid;
-        hipLaunchKernelGGL(hg_count_kernel, dim3((unsigned)L.nblk), dim3(kHgCountBlock), 0, st, kin, pin, n, nv, m,
-                           shift, dmask, ndig, cntb);
+        hipLaunchKernelGGL(hg_count_kernel<W>, dim3((unsigned)L.nblk), dim3(kHgCountBlock), 0, st, kin, rin, n, nv,
+                           m, shift, dmask, ndig, cntb);
         hipLaunchKernelGGL(hg_colscan_kernel, dim3((unsigned)ceil_div(ndig, kHgCountBlock), (unsigned)L.nchunks),
                            dim3(kHgCountBlock), 0, st, cntb, (int)L.nblk, ndig, ctot);
         hipLaunchKernelGGL(hg_digitscan_kernel, dim3(1), dim3(kHgScanThreads), 0, st, ctot, (int)L.nchunks, ndig,
                            pass == 0 ? nvalid : nullptr);
-        hipLaunchKernelGGL(hg_scatter_kernel, dim3((unsigned)L.nblk), dim3(kWave), 0, st, kin, pin, n, nv, m, shift,
-                           dmask, ndig, nbits, cntb, ctot, pout);
-        pin = pout;
+        hipLaunchKernelGGL((hg_scatter_kernel<T, Op::K, W>), dim3((unsigned)L.nblk), dim3(kWave), 0, st, kin, x, rin,
+                           n, nv, m, shift, dmask, ndig, nbits, cntb, ctot, rout);
+        rin = rout;
     }
-    HgIn<T> xs{};
-    HgOut<T> xo{};
-    for (int k = 0; k < Op::K; ++k) {
-        xo.p[k] = reinterpret_cast<T*>(w + L.xs[k]);
-        xs.p[k] = xo.p[k];
-    }
-    if (n > 0)
-        hipLaunchKernelGGL(hg_gather_kernel<T>, dim3(flat_grid(n, 256, 4)), dim3(256), 0, st, pin, nvalid, x, Op::K,
-                           xo);
-    hipLaunchKernelGGL((hg_tile_fold_kernel<Op, T>), dim3((unsigned)L.ntiles), dim3(kHgBlock), 0, st, pin, xs,
+    hipLaunchKernelGGL((hg_tile_fold_kernel<Op, T, W>), dim3((unsigned)L.ntiles), dim3(kHgBlock), 0, st, rin,
                        nvalid, w + L.aggF, w + L.aggR);
     hipLaunchKernelGGL(hg_group_fold_kernel<Op>, dim3((unsigned)L.ngroups), dim3(kHgGroup), 0, st, w + L.aggF,
                        w + L.aggR, L.ntiles, w + L.gF, w + L.gR);
@@ -580,35 +589,35 @@ static const int2* hg_prepare(const int32_t* inds, int64_t n, int32_t m, const H
                        L.ngroups, w + L.gcF, w + L.gcR);
     hipLaunchKernelGGL(hg_group_carry_kernel<Op>, dim3((unsigned)L.ngroups), dim3(kHgGroup), 0, st, w + L.aggF,
                        w + L.aggR, L.ntiles, w + L.gcF, w + L.gcR, w + L.carF, w + L.carR);
-    *xs_out = xs;
-    return pin;
+    return rin;
 }
 
 template <class Op, class T>
 static void hg_primal(const int32_t* inds, int64_t n, int32_t m, const void* const* x, void* const* hs, char* w,
                       hipStream_t st) {
-    const HgLayout L = hg_layout(n, m, Op::K, sizeof(T));
+    constexpr int W = hg_words<T, Op::K>();
+    const HgLayout L = hg_layout(n, m, hg_rec_bytes(Op::K, sizeof(T)));
     HgIn<T> xi{};
     HgOut<T> ho{};
     for (int k = 0; k < Op::K; ++k) {
         xi.p[k] = n > 0 ? (const T*)x[k] : nullptr;
         ho.p[k] = (T*)hs[k];
     }
-    HgIn<T> xs;
-    const int2* pairs = hg_prepare<Op, T>(inds, n, m, xi, w, L, &xs, st);
+    const HgRec<W>* recs = hg_prepare<Op, T>(inds, n, m, xi, w, L, st);
     int32_t* nvalid = reinterpret_cast<int32_t*>(w + L.nvalid);
     int32_t* off = reinterpret_cast<int32_t*>(w + L.off);
-    hipLaunchKernelGGL(hg_off_kernel, dim3((unsigned)ceil_div((int64_t)m + 1, 256)), dim3(256), 0, st, pairs, nvalid,
-                       m, off);
-    hipLaunchKernelGGL((hg_apply_kernel<Op, T, false, false>), dim3((unsigned)L.ntiles), dim3(kHgBlock), 0, st, pairs,
-                       xs, nvalid, w + L.carF, w + L.carR, ho, HgIn<T>{}, HgOut<T>{});
+    hipLaunchKernelGGL(hg_off_kernel<W>, dim3((unsigned)ceil_div((int64_t)m + 1, 256)), dim3(256), 0, st, recs,
+                       nvalid, m, off);
+    hipLaunchKernelGGL((hg_apply_kernel<Op, T, W, false, false>), dim3((unsigned)L.ntiles), dim3(kHgBlock), 0, st,
+                       recs, nvalid, w + L.carF, w + L.carR, ho, HgIn<T>{}, HgOut<T>{});
     hipLaunchKernelGGL((hg_empty_kernel<Op, T>), dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, off, m, ho);
 }
 
 template <class Op, class T>
 static void hg_vjp(const int32_t* inds, int64_t n, int32_t m, const void* const* x, const void* const* hs_bar,
                    void* const* x_bar, bool acc, char* w, hipStream_t st) {
-    const HgLayout L = hg_layout(n, m, Op::K, sizeof(T));
+    constexpr int W = hg_words<T, Op::K>();
+    const HgLayout L = hg_layout(n, m, hg_rec_bytes(Op::K, sizeof(T)));
     HgIn<T> xi{}, hb{};
     HgOut<T> xb{};
     for (int k = 0; k < Op::K; ++k) {
@@ -618,15 +627,14 @@ static void hg_vjp(const int32_t* inds, int64_t n, int32_t m, const void* const*
     }
     if (!acc)  // elements outside [0, m) get a zero adjoint
         hipLaunchKernelGGL(hg_zero_kernel<T>, dim3(flat_grid(n, 256, 4)), dim3(256), 0, st, xb, Op::K, n);
-    HgIn<T> xs;
-    const int2* pairs = hg_prepare<Op, T>(inds, n, m, xi, w, L, &xs, st);
+    const HgRec<W>* recs = hg_prepare<Op, T>(inds, n, m, xi, w, L, st);
     int32_t* nvalid = reinterpret_cast<int32_t*>(w + L.nvalid);
     if (acc)
-        hipLaunchKernelGGL((hg_apply_kernel<Op, T, true, true>), dim3((unsigned)L.ntiles), dim3(kHgBlock), 0, st,
-                           pairs, xs, nvalid, w + L.carF, w + L.carR, HgOut<T>{}, hb, xb);
+        hipLaunchKernelGGL((hg_apply_kernel<Op, T, W, true, true>), dim3((unsigned)L.ntiles), dim3(kHgBlock), 0, st,
+                           recs, nvalid, w + L.carF, w + L.carR, HgOut<T>{}, hb, xb);
     else
-        hipLaunchKernelGGL((hg_apply_kernel<Op, T, true, false>), dim3((unsigned)L.ntiles), dim3(kHgBlock), 0, st,
-                           pairs, xs, nvalid, w + L.carF, w + L.carR, HgOut<T>{}, hb, xb);
+        hipLaunchKernelGGL((hg_apply_kernel<Op, T, W, true, false>), dim3((unsigned)L.ntiles), dim3(kHgBlock), 0, st,
+                           recs, nvalid, w + L.carF, w + L.carR, HgOut<T>{}, hb, xb);
 }
 
 static pvjp_status hg_check(const char* name, pvjp_gop op, pvjp_dtype dtype, const int32_t* inds,
@@ -658,7 +666,7 @@ using namespace pvjp;
 
 extern "C" size_t pvjp_hist_generic_ws_bytes(pvjp_gop op, pvjp_dtype dtype, int64_t n, int64_t m) {
     if (hg_components(op) == 0 || !valid_dtype(dtype) || n < 0 || m < 1 || m > kHgMaxBins) return 0;
-    return hg_layout(n, m, hg_components(op), dsize(dtype)).total;
+    return hg_layout(n, m, hg_rec_bytes(hg_components(op), dsize(dtype))).total;
 }
 
 extern "C" pvjp_status pvjp_hist_generic(pvjp_gop op, pvjp_dtype dtype, const int32_t* inds, const void* const* x,
