@@ -5,12 +5,12 @@
 // neutral element for an empty bin; indices outside [0, m) are skipped).
 // The operator need not commute, so each bin's elements must meet in index
 // order:
-//   1. a stable sort of the in-range elements by bin: one pass of up to 12
-//      bits, or two passes splitting the bin's bits evenly, low digit first,
-//      each a per-chunk digit count, a digit-major scan of the counts and a
-//      stable scatter in which one wave walks its chunk in index order (ranks
-//      among equal digits from wave ballots, so equal bins keep their order).
-//      The sort moves whole records -- bin, element index and the element's
+//   1. a stable sort of the in-range elements by bin: passes of up to 8 bits
+//      (the bin's bits split evenly), low digit first, each a per-chunk digit
+//      count, a digit-major scan of the counts and a stable scatter staged in
+//      LDS (ranks among equal digits from wave ballots, so equal bins keep
+//      their order; each digit's records leave as contiguous runs).  The sort
+//      moves whole records -- bin, element index and the element's
 //      components -- so x is read once, in index order, instead of gathered
 //      at random into sorted order;
 //   2. bin starts, by binary search of the sorted bins;
@@ -154,69 +154,117 @@ __global__ __launch_bounds__(kHgScanThreads) void hg_digitscan_kernel(int32_t* _
     if (threadIdx.x == 0 && nvalid) *nvalid = all.v;
 }
 
-// Stable scatter of one chunk by one wave, 64 elements at a time in index
-// order.  Lanes with equal digits find each other with one ballot per digit
-// bit; a lane's rank among them and the digit's running position (LDS) give
-// its place, and the group's last such lane advances the position.  The
-// first pass builds each record from the indices and x (read in order), the
-// second moves records.
+// Stable scatter of one chunk, staged in LDS so that each digit's records
+// leave as contiguous runs instead of one scattered store per record.  The
+// chunk is taken in sub-chunks of kHgSub records in index order (long
+// enough that a digit's run in it averages a whole line); wave w of the
+// block owns records [w * 64 G, (w + 1) * 64 G) of a sub-chunk, as G =
+// kHgSortGroups groups of 64 taken in order.  Ranks: within a group, the lanes of equal
+// digit find each other with one ballot per digit bit (rank = earlier such
+// lanes); a wave's running count per digit orders its groups; the counts
+// of earlier waves order the waves; earlier sub-chunks and chunks come
+// before through the digit's running position.  So equal digits keep their
+// index order.  Records are placed in LDS at (the digit's start in the
+// sub-chunk + rank), then thread t writes slots t, t + 256, ... to the
+// digit's running position in the output.  The first pass builds each
+// record from the indices and x (read in order), later passes move records.
+constexpr int kHgSortThreads = 256;
+constexpr int kHgSortWaves = kHgSortThreads / kWave;
+constexpr int kHgSortGroups = 8;                               // groups of 64 per wave and sub-chunk
+constexpr int kHgSub = kHgSortThreads * kHgSortGroups;         // 2048 records
+constexpr int kHgPassBits = 8;                                 // digits per pass: at most 256
+constexpr int kHgPassDigits = 1 << kHgPassBits;
+static_assert(kHgPassDigits == kHgSortThreads, "a thread per digit in the sub-chunk scans");
+static_assert(kHgChunk % kHgSub == 0, "chunks are whole sub-chunks");
+
 template <class T, int K, int W>
-__global__ __launch_bounds__(kWave) void hg_scatter_kernel(const int32_t* __restrict__ keys_in, HgIn<T> x,
-                                                           const HgRec<W>* __restrict__ recs_in, int64_t n,
-                                                           const int32_t* __restrict__ nvalid, int32_t m, int shift,
-                                                           int dmask, int ndig, int nbits,
-                                                           const int32_t* __restrict__ cntb,
-                                                           const int32_t* __restrict__ ctot,
-                                                           HgRec<W>* __restrict__ recs_out) {
-    __shared__ int32_t pos[kHgDigits];
-    const int lane = threadIdx.x;
+__global__ __launch_bounds__(kHgSortThreads) void hg_scatter_kernel(const int32_t* __restrict__ keys_in, HgIn<T> x,
+                                                                    const HgRec<W>* __restrict__ recs_in, int64_t n,
+                                                                    const int32_t* __restrict__ nvalid, int32_t m,
+                                                                    int shift, int dmask, int ndig, int nbits,
+                                                                    const int32_t* __restrict__ cntb,
+                                                                    const int32_t* __restrict__ ctot,
+                                                                    HgRec<W>* __restrict__ recs_out) {
+    __shared__ HgRec<W> stage[kHgSub];
+    __shared__ int32_t wcnt[kHgSortWaves][kHgPassDigits];  // per wave: running count, then its offset
+    __shared__ int32_t lstart[kHgPassDigits];              // the digit's first slot in the sub-chunk
+    __shared__ int32_t gpos[kHgPassDigits];                // the digit's running output position
+    __shared__ IntSum::S wtot[kHgSortWaves];
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = tid / kWave;
     const int blk = blockIdx.x;
     const int c = blk / kHgColChunk;
-    for (int d = lane; d < ndig; d += kWave)
-        pos[d] = ctot[(int64_t)c * kHgDigits + d] + cntb[(int64_t)blk * kHgDigits + d];
-    __syncthreads();
+    if (tid < ndig) gpos[tid] = ctot[(int64_t)c * kHgDigits + tid] + cntb[(int64_t)blk * kHgDigits + tid];
     const int64_t ne = nvalid ? (int64_t)*nvalid : n;
     const int64_t lo = (int64_t)blk * kHgChunk;
     const int64_t hi = (lo + kHgChunk < ne) ? lo + kHgChunk : ne;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
-    constexpr int U = 4;  // groups whose loads are in flight together
-    for (int64_t g0 = lo; g0 < hi; g0 += (int64_t)U * kWave) {
-        HgRec<W> r[U];
+    for (int64_t s0 = lo; s0 < hi; s0 += kHgSub) {
+        for (int w = 0; w < kHgSortWaves; ++w) wcnt[w][tid] = 0;
+        HgRec<W> r[kHgSortGroups];
+        bool valid[kHgSortGroups];
+        int dg[kHgSortGroups];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t i = g0 + (int64_t)u * kWave + lane;
+        for (int g = 0; g < kHgSortGroups; ++g) {
+            const int64_t i = s0 + wave * (kHgSortGroups * kWave) + g * kWave + lane;
             if (i < hi && keys_in) {
-                r[u].w[0] = (uint32_t)keys_in[i];
-                r[u].w[1] = (uint32_t)i;
+                r[g].w[0] = (uint32_t)keys_in[i];
+                r[g].w[1] = (uint32_t)i;
 #pragma unroll
-                for (int w = 2; w < W; ++w) r[u].w[w] = 0u;
+                for (int w = 2; w < W; ++w) r[g].w[w] = 0u;
 #pragma unroll
-                for (int k = 0; k < K; ++k) reinterpret_cast<T*>(&r[u].w[2])[k] = x.p[k][i];
+                for (int k = 0; k < K; ++k) reinterpret_cast<T*>(&r[g].w[2])[k] = x.p[k][i];
             } else if (i < hi) {
-                r[u] = recs_in[i];
+                r[g] = recs_in[i];
             } else {
-                r[u].w[0] = 0xffffffffu;  // no element: outside every bin
+                r[g].w[0] = 0xffffffffu;  // no element: outside every bin
             }
+            valid[g] = (uint32_t)r[g].w[0] < (uint32_t)m;
+            dg[g] = valid[g] ? ((int32_t)r[g].w[0] >> shift) & dmask : 0;
         }
+        __syncthreads();  // counters cleared; the previous sub-chunk's slots read out
+        // ranks within the wave, groups in order
+        int rank[kHgSortGroups];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int32_t kk = (int32_t)r[u].w[0];
-            const bool valid = (uint32_t)kk < (uint32_t)m;
-            const int d = valid ? (kk >> shift) & dmask : 0;
-            uint64_t peers = __ballot(valid);
+        for (int g = 0; g < kHgSortGroups; ++g) {
+            const int d = dg[g];
+            uint64_t peers = __ballot(valid[g]);
             for (int bit = 0; bit < nbits; ++bit) {
                 const bool one = (d >> bit) & 1;
-                const uint64_t b = __ballot(valid && one);
+                const uint64_t b = __ballot(valid[g] && one);
                 peers &= one ? b : ~b;
             }
-            const int base = valid ? pos[d] : 0;
-            const int rank = __popcll(peers & below);
-            if (valid) {
-                recs_out[base + rank] = r[u];
-                // the highest lane of the group moves the digit's position on
-                if ((peers >> lane) == 1ull) pos[d] = base + __popcll(peers);
-            }
+            const int before = valid[g] ? wcnt[wave][d] : 0;
+            rank[g] = before + __popcll(peers & below);
+            // the highest lane of the group moves the wave's count on (lanes
+            // of a wave run together: every lane has read it first)
+            if (valid[g] && (peers >> lane) == 1ull) wcnt[wave][d] = before + __popcll(peers);
         }
+        __syncthreads();
+        // per digit (a thread each): the waves' offsets and the digit's total,
+        // then the digits' starts in the sub-chunk
+        int tot = 0;
+        for (int w = 0; w < kHgSortWaves; ++w) {
+            const int cw = wcnt[w][tid];
+            wcnt[w][tid] = tot;
+            tot += cw;
+        }
+        IntSum::S all;
+        const int st = block_exclusive_scan<IntSum, kHgSortThreads, false>(IntSum::S{tot}, all, wtot).v;
+        lstart[tid] = st;
+        __syncthreads();
+#pragma unroll
+        for (int g = 0; g < kHgSortGroups; ++g)
+            if (valid[g]) stage[lstart[dg[g]] + wcnt[wave][dg[g]] + rank[g]] = r[g];
+        __syncthreads();
+        for (int sl = tid; sl < all.v; sl += kHgSortThreads) {
+            const HgRec<W> q = stage[sl];
+            const int d = ((int32_t)q.w[0] >> shift) & dmask;
+            recs_out[gpos[d] + (sl - lstart[d])] = q;
+        }
+        __syncthreads();  // every slot placed before the positions move on
+        gpos[tid] += tot;
     }
 }
 
@@ -553,22 +601,20 @@ static const HgRec<hg_words<T, Op::K>()>* hg_prepare(const int32_t* inds, int64_
     int32_t* nvalid = reinterpret_cast<int32_t*>(w + L.nvalid);
     Rec* rA = reinterpret_cast<Rec*>(w + L.recA);
     Rec* rB = reinterpret_cast<Rec*>(w + L.recB);
-    // bits of the largest bin, split evenly between the two passes when one
-    // pass cannot take them all (fewer digits per pass: longer runs of a
-    // digit within a chunk, whose stores then share lines)
+    // bits of the largest bin, split evenly over passes of at most 8 bits
+    // (at least one pass, which also drops the indices outside [0, m))
     int bbits = 0;
     while (((int64_t)1 << bbits) < (int64_t)m) ++bbits;
-    const int passes = bbits > kHgDigitBits ? 2 : 1;
-    const int bits0 = passes == 2 ? (bbits + 1) / 2 : kHgDigitBits;
+    const int passes = std::max(1, (bbits + kHgPassBits - 1) / kHgPassBits);
+    const int bpp = std::max(1, (bbits + passes - 1) / passes);
     const Rec* rin = nullptr;
     for (int pass = 0; pass < passes; ++pass) {
-        const int shift = pass * bits0;
-        const int dmask = pass == 0 ? (1 << bits0) - 1 : kHgDigits - 1;
-        const int ndig = pass == 0 ? (int)std::min<int64_t>(m, (int64_t)1 << bits0)
-                                   : (int)ceil_div(m, (int64_t)1 << bits0);
+        const int shift = pass * bpp;
+        const int dmask = (1 << bpp) - 1;
+        const int ndig = (int)std::min<int64_t>((int64_t)1 << bpp, ceil_div((int64_t)m, (int64_t)1 << shift));
         int nbits = 0;
         while ((1 << nbits) < ndig) ++nbits;
-        Rec* rout = pass == 0 ? rA : rB;
+        Rec* rout = (pass & 1) ? rB : rA;
         const int32_t* kin = pass == 0 ? inds : nullptr;
         const int32_t* nv = pass == 0 ? nullptr : nvalid;
         hipLaunchKernelGGL(hg_count_kernel<W>, dim3((unsigned)L.nblk), dim3(kHgCountBlock), 0, st, kin, rin, n, nv,
@@ -577,8 +623,8 @@ static const HgRec<hg_words<T, Op::K>()>* hg_prepare(const int32_t* inds, int64_
                            dim3(kHgCountBlock), 0, st, cntb, (int)L.nblk, ndig, ctot);
         hipLaunchKernelGGL(hg_digitscan_kernel, dim3(1), dim3(kHgScanThreads), 0, st, ctot, (int)L.nchunks, ndig,
                            pass == 0 ? nvalid : nullptr);
-        hipLaunchKernelGGL((hg_scatter_kernel<T, Op::K, W>), dim3((unsigned)L.nblk), dim3(kWave), 0, st, kin, x, rin,
-                           n, nv, m, shift, dmask, ndig, nbits, cntb, ctot, rout);
+        hipLaunchKernelGGL((hg_scatter_kernel<T, Op::K, W>), dim3((unsigned)L.nblk), dim3(kHgSortThreads), 0, st, kin,
+                           x, rin, n, nv, m, shift, dmask, ndig, nbits, cntb, ctot, rout);
         rin = rout;
     }
     hipLaunchKernelGGL((hg_tile_fold_kernel<Op, T, W>), dim3((unsigned)L.ntiles), dim3(kHgBlock), 0, st, rin,
