@@ -6,8 +6,9 @@ seeded inputs.
 Bars: FP64 relative L2 1e-12 per component; FP32 inputs 2e-5 against the
 FP64 oracle on the same FP32 values, rounded to FP32; empty log-add-exp bins -inf exactly;
 adjoints of out-of-range indices exactly 0.  Cases: one bin (every element
-in it, across every tile), few bins, m = 2^10 (one sort pass), m = 2^16 and
-2^20 (two passes), Zipf(1.1) indices, indices out of range on both sides,
+in it, across every tile), few bins (one sort pass of at most 8 bits),
+m = 257, 2^10 and 2^16 (two passes), 2^17 + 3 and 2^20 (three), the largest
+m = 2^24 (three full passes), Zipf(1.1) indices, indices out of range on both sides,
 n = 0 and 1, more sort chunks than a column-scan chunk holds (n = 2.5M),
 accumulation, and bitwise repeatability.
 """
@@ -78,7 +79,8 @@ def run_case(ops, orc, op, n, m, dtype, dist="uniform", seed=0, oob=True):
     return di, dx, hb, hs, xb
 
 
-CASES = [(0, 5), (1, 1), (1000, 1), (5003, 7), (300007, 1 << 10), (300007, 1 << 16), (200003, 1 << 20)]
+CASES = [(0, 5), (1, 1), (1000, 1), (5003, 7), (20011, 257), (300007, 1 << 10), (300007, 1 << 16),
+         (100003, (1 << 17) + 3), (200003, 1 << 20)]
 
 
 @pytest.mark.parametrize("op", OPS)
@@ -91,6 +93,12 @@ def test_parity(ops, orc, op, dtype, n, m):
 @pytest.mark.parametrize("op", OPS)
 def test_zipf(ops, orc, op):
     run_case(ops, orc, op, 300007, 4096 + 3, "f64", dist="zipf", seed=11)
+
+
+@pytest.mark.parametrize("op", ["linrec", "mat2"])
+def test_largest_bin_count(ops, orc, op):
+    # m = 2^24: three sort passes of 8 bits each
+    run_case(ops, orc, op, 60013, 1 << 24, "f32", seed=24)
 
 
 def test_many_sort_chunks(ops, orc):
