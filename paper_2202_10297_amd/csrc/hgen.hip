@@ -454,6 +454,7 @@ __global__ __launch_bounds__(kHgGroup) void hg_group_carry_kernel(const char* __
 // maps f over (ls, x, rs) with y_bar = hs_bar of the element's bin.
 template <class Op, class T, int W, bool VJP, bool ACC>
 __global__ __launch_bounds__(kHgBlock) void hg_apply_kernel(const HgRec<W>* __restrict__ recs,
+                                                            HgRec<W>* __restrict__ urecs,
                                                             const int32_t* __restrict__ nvalid,
                                                             const char* __restrict__ carF,
                                                             const char* __restrict__ carR, HgOut<T> hs,
@@ -516,10 +517,21 @@ __global__ __launch_bounds__(kHgBlock) void hg_apply_kernel(const HgRec<W>* __re
 #pragma unroll
         for (int k = 0; k < Op::K; ++k) yb[k] = (double)hs_bar.p[k][e[j].key];
         Op::vjp(ls[j], e[j].a, rs, la[j], yb, out);
+        if (urecs) {
+            // (index, x_bar) records in sorted order, for the unsort
+            HgRec<W> q;
+            q.w[0] = (uint32_t)e[j].src;
 #pragma unroll
-        for (int k = 0; k < Op::K; ++k) {
-            T* dst = x_bar.p[k] + e[j].src;
-            *dst = ACC ? (T)((double)*dst + out[k]) : (T)out[k];
+            for (int w = 1; w < W; ++w) q.w[w] = 0u;
+#pragma unroll
+            for (int k = 0; k < Op::K; ++k) reinterpret_cast<T*>(&q.w[2])[k] = (T)out[k];
+            urecs[p0 + j] = q;
+        } else {
+#pragma unroll
+            for (int k = 0; k < Op::K; ++k) {
+                T* dst = x_bar.p[k] + e[j].src;
+                *dst = ACC ? (T)((double)*dst + out[k]) : (T)out[k];
+            }
         }
         xr = R::comb(xr, typename R::S{e[j].a, e[j].last ? 1u : 0u, 0u});
     }
@@ -540,6 +552,24 @@ template <class T>
 __global__ __launch_bounds__(256) void hg_zero_kernel(HgOut<T> x, int K, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
         for (int k = 0; k < K; ++k) x.p[k][i] = T(0);
+}
+
+// The unsort's last step: records in increasing element index (in-range
+// elements only), each component written at the element's index -- in
+// order, with gaps where indices were out of range.
+template <class T, int K, int W, bool ACC>
+__global__ __launch_bounds__(256) void hg_unsort_write_kernel(const HgRec<W>* __restrict__ recs,
+                                                              const int32_t* __restrict__ nvalid, HgOut<T> x_bar) {
+    const int64_t nv = *nvalid;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < nv; p += (int64_t)gridDim.x * 256) {
+        const HgRec<W> q = recs[p];
+        const int64_t i = (int64_t)q.w[0];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const T v = hg_comp<T, W>(q, k);
+            x_bar.p[k][i] = ACC ? (T)((double)x_bar.p[k][i] + (double)v) : v;
+        }
+    }
 }
 
 // ------------------------------------------------------------------ host
@@ -589,6 +619,42 @@ static HgLayout hg_layout(int64_t n, int64_t m, size_t rec_bytes) {
     return L;
 }
 
+// Stable LSD passes of at most 8 bits (the key's bits split evenly; at least
+// one pass) over keys below m: from the indices and x (keys != NULL; the
+// first pass also counts the in-range elements into *nvalid) or from the
+// records rin (nv on the device).  Ping-pongs between bufA and bufB and
+// returns the sorted records.
+template <class T, int K, int W>
+static const HgRec<W>* hg_sort_passes(const int32_t* keys, const HgIn<T>& x, const HgRec<W>* rin, int64_t n,
+                                      const int32_t* nv_in, int64_t m, HgRec<W>* bufA, HgRec<W>* bufB,
+                                      int32_t* cntb, int32_t* ctot, int32_t* nvalid, const HgLayout& L,
+                                      hipStream_t st) {
+    int bbits = 0;
+    while (((int64_t)1 << bbits) < m) ++bbits;
+    const int passes = std::max(1, (bbits + kHgPassBits - 1) / kHgPassBits);
+    const int bpp = std::max(1, (bbits + passes - 1) / passes);
+    for (int pass = 0; pass < passes; ++pass) {
+        const int shift = pass * bpp;
+        const int dmask = (1 << bpp) - 1;
+        const int ndig = (int)std::min<int64_t>((int64_t)1 << bpp, ceil_div(m, (int64_t)1 << shift));
+        int nbits = 0;
+        while ((1 << nbits) < ndig) ++nbits;
+        HgRec<W>* rout = (pass & 1) ? bufB : bufA;
+        const int32_t* kin = pass == 0 ? keys : nullptr;
+        const int32_t* nv = (pass == 0 && keys) ? nullptr : (keys ? nvalid : nv_in);
+        hipLaunchKernelGGL(hg_count_kernel<W>, dim3((unsigned)L.nblk), dim3(kHgCountBlock), 0, st, kin, rin, n, nv,
+                           (int32_t)m, shift, dmask, ndig, cntb);
+        hipLaunchKernelGGL(hg_colscan_kernel, dim3((unsigned)ceil_div(ndig, kHgCountBlock), (unsigned)L.nchunks),
+                           dim3(kHgCountBlock), 0, st, cntb, (int)L.nblk, ndig, ctot);
+        hipLaunchKernelGGL(hg_digitscan_kernel, dim3(1), dim3(kHgScanThreads), 0, st, ctot, (int)L.nchunks, ndig,
+                           (pass == 0 && keys) ? nvalid : nullptr);
+        hipLaunchKernelGGL((hg_scatter_kernel<T, K, W>), dim3((unsigned)L.nblk), dim3(kHgSortThreads), 0, st, kin, x,
+                           rin, n, nv, (int32_t)m, shift, dmask, ndig, nbits, cntb, ctot, rout);
+        rin = rout;
+    }
+    return rin;
+}
+
 // The sort and the tile carries, shared by both entry points.  Returns the
 // sorted records.
 template <class Op, class T>
@@ -601,32 +667,7 @@ static const HgRec<hg_words<T, Op::K>()>* hg_prepare(const int32_t* inds, int64_
     int32_t* nvalid = reinterpret_cast<int32_t*>(w + L.nvalid);
     Rec* rA = reinterpret_cast<Rec*>(w + L.recA);
     Rec* rB = reinterpret_cast<Rec*>(w + L.recB);
-    // bits of the largest bin, split evenly over passes of at most 8 bits
-    // (at least one pass, which also drops the indices outside [0, m))
-    int bbits = 0;
-    while (((int64_t)1 << bbits) < (int64_t)m) ++bbits;
-    const int passes = std::max(1, (bbits + kHgPassBits - 1) / kHgPassBits);
-    const int bpp = std::max(1, (bbits + passes - 1) / passes);
-    const Rec* rin = nullptr;
-    for (int pass = 0; pass < passes; ++pass) {
-        const int shift = pass * bpp;
-        const int dmask = (1 << bpp) - 1;
-        const int ndig = (int)std::min<int64_t>((int64_t)1 << bpp, ceil_div((int64_t)m, (int64_t)1 << shift));
-        int nbits = 0;
-        while ((1 << nbits) < ndig) ++nbits;
-        Rec* rout = (pass & 1) ? rB : rA;
-        const int32_t* kin = pass == 0 ? inds : nullptr;
-        const int32_t* nv = pass == 0 ? nullptr : nvalid;
-        hipLaunchKernelGGL(hg_count_kernel<W>, dim3((unsigned)L.nblk), dim3(kHgCountBlock), 0, st, kin, rin, n, nv,
-                           m, shift, dmask, ndig, cntb);
-        hipLaunchKernelGGL(hg_colscan_kernel, dim3((unsigned)ceil_div(ndig, kHgCountBlock), (unsigned)L.nchunks),
-                           dim3(kHgCountBlock), 0, st, cntb, (int)L.nblk, ndig, ctot);
-        hipLaunchKernelGGL(hg_digitscan_kernel, dim3(1), dim3(kHgScanThreads), 0, st, ctot, (int)L.nchunks, ndig,
-                           pass == 0 ? nvalid : nullptr);
-        hipLaunchKernelGGL((hg_scatter_kernel<T, Op::K, W>), dim3((unsigned)L.nblk), dim3(kHgSortThreads), 0, st, kin,
-                           x, rin, n, nv, m, shift, dmask, ndig, nbits, cntb, ctot, rout);
-        rin = rout;
-    }
+    const Rec* rin = hg_sort_passes<T, Op::K, W>(inds, x, nullptr, n, nullptr, m, rA, rB, cntb, ctot, nvalid, L, st);
     hipLaunchKernelGGL((hg_tile_fold_kernel<Op, T, W>), dim3((unsigned)L.ntiles), dim3(kHgBlock), 0, st, rin,
                        nvalid, w + L.aggF, w + L.aggR);
     hipLaunchKernelGGL(hg_group_fold_kernel<Op>, dim3((unsigned)L.ngroups), dim3(kHgGroup), 0, st, w + L.aggF,
@@ -655,7 +696,7 @@ static void hg_primal(const int32_t* inds, int64_t n, int32_t m, const void* con
     hipLaunchKernelGGL(hg_off_kernel<W>, dim3((unsigned)ceil_div((int64_t)m + 1, 256)), dim3(256), 0, st, recs,
                        nvalid, m, off);
     hipLaunchKernelGGL((hg_apply_kernel<Op, T, W, false, false>), dim3((unsigned)L.ntiles), dim3(kHgBlock), 0, st,
-                       recs, nvalid, w + L.carF, w + L.carR, ho, HgIn<T>{}, HgOut<T>{});
+                       recs, (HgRec<W>*)nullptr, nvalid, w + L.carF, w + L.carR, ho, HgIn<T>{}, HgOut<T>{});
     hipLaunchKernelGGL((hg_empty_kernel<Op, T>), dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, off, m, ho);
 }
 
@@ -675,12 +716,34 @@ static void hg_vjp(const int32_t* inds, int64_t n, int32_t m, const void* const*
         hipLaunchKernelGGL(hg_zero_kernel<T>, dim3(flat_grid(n, 256, 4)), dim3(256), 0, st, xb, Op::K, n);
     const HgRec<W>* recs = hg_prepare<Op, T>(inds, n, m, xi, w, L, st);
     int32_t* nvalid = reinterpret_cast<int32_t*>(w + L.nvalid);
+    // With four components, K scattered stores per element cost more than
+    // writing (index, x_bar) records in sorted order and sorting them back by
+    // index with the same staged passes; with fewer, the stores are cheaper.
+    HgRec<W>* urecs = nullptr;
+    HgRec<W>* rA = reinterpret_cast<HgRec<W>*>(w + L.recA);
+    HgRec<W>* rB = reinterpret_cast<HgRec<W>*>(w + L.recB);
+    if (Op::K >= 4) urecs = (recs == rA) ? rB : rA;
     if (acc)
         hipLaunchKernelGGL((hg_apply_kernel<Op, T, W, true, true>), dim3((unsigned)L.ntiles), dim3(kHgBlock), 0, st,
-                           recs, nvalid, w + L.carF, w + L.carR, HgOut<T>{}, hb, xb);
+                           recs, urecs, nvalid, w + L.carF, w + L.carR, HgOut<T>{}, hb, xb);
     else
         hipLaunchKernelGGL((hg_apply_kernel<Op, T, W, true, false>), dim3((unsigned)L.ntiles), dim3(kHgBlock), 0, st,
-                           recs, nvalid, w + L.carF, w + L.carR, HgOut<T>{}, hb, xb);
+                           recs, urecs, nvalid, w + L.carF, w + L.carR, HgOut<T>{}, hb, xb);
+    if (urecs) {
+        // the sorted records' buffer is free now: the passes start there, so
+        // that no pass reads and writes one buffer
+        HgRec<W>* other = (urecs == rA) ? rB : rA;
+        int32_t* cntb = reinterpret_cast<int32_t*>(w + L.cntb);
+        int32_t* ctot = reinterpret_cast<int32_t*>(w + L.ctot);
+        const HgRec<W>* out = hg_sort_passes<T, Op::K, W>(nullptr, HgIn<T>{}, urecs, n, nvalid, n, other, urecs, cntb,
+                                                          ctot, nvalid, L, st);
+        if (acc)
+            hipLaunchKernelGGL((hg_unsort_write_kernel<T, Op::K, W, true>), dim3(flat_grid(n, 256, 4)), dim3(256), 0,
+                               st, out, nvalid, xb);
+        else
+            hipLaunchKernelGGL((hg_unsort_write_kernel<T, Op::K, W, false>), dim3(flat_grid(n, 256, 4)), dim3(256), 0,
+                               st, out, nvalid, xb);
+    }
 }
 
 static pvjp_status hg_check(const char* name, pvjp_gop op, pvjp_dtype dtype, const int32_t* inds,
