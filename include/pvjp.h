@@ -665,10 +665,11 @@ pvjp_status pvjp_hist_lae_vjp(pvjp_dtype dtype, const int32_t* inds, const void*
  * n < 2^31.  The elements are stably sorted by bin, each bin is folded by a
  * segmented scan; folds in FP64 for both dtypes.  ws: device memory owned by
  * the caller, 256-byte aligned, no initialisation needed, at least
- * pvjp_hist_generic_ws_bytes bytes (else PVJP_ENOMEM): about 2 r n bytes,
- * r = 8 + K s rounded up to a multiple of 16 for elements of s bytes (two
- * buffers of sort records: bin, element index and the element's components),
- * plus per-chunk digit counts and per-tile states.  Deterministic. */
+ * pvjp_hist_generic_ws_bytes bytes (else PVJP_ENOMEM): about 2 (r + 4) n
+ * bytes, r = 8 + K s rounded up to a multiple of 16 for elements of s bytes
+ * (two buffers of sort records -- bin, element index and the element's
+ * components -- and two of their keys alone), plus per-chunk digit counts
+ * and per-tile states.  Deterministic. */
 size_t pvjp_hist_generic_ws_bytes(pvjp_gop op, pvjp_dtype dtype, int64_t n, int64_t m);
 pvjp_status pvjp_hist_generic(pvjp_gop op, pvjp_dtype dtype, const int32_t* inds, const void* const* x, int64_t n,
                               int64_t m, void* const* hs, void* ws, size_t ws_bytes, void* stream);

@@ -184,7 +184,8 @@ __global__ __launch_bounds__(kHgSortThreads) void hg_scatter_kernel(const int32_
                                                                     int shift, int dmask, int ndig, int nbits,
                                                                     const int32_t* __restrict__ cntb,
                                                                     const int32_t* __restrict__ ctot,
-                                                                    HgRec<W>* __restrict__ recs_out) {
+                                                                    HgRec<W>* __restrict__ recs_out,
+                                                                    int32_t* __restrict__ keys_out) {
     __shared__ HgRec<W> stage[kHgSub];
     __shared__ int32_t wcnt[kHgSortWaves][kHgPassDigits];  // per wave: running count, then its offset
     __shared__ int32_t lstart[kHgPassDigits];              // the digit's first slot in the sub-chunk
@@ -261,7 +262,9 @@ __global__ __launch_bounds__(kHgSortThreads) void hg_scatter_kernel(const int32_
         for (int sl = tid; sl < all.v; sl += kHgSortThreads) {
             const HgRec<W> q = stage[sl];
             const int d = ((int32_t)q.w[0] >> shift) & dmask;
-            recs_out[gpos[d] + (sl - lstart[d])] = q;
+            const int64_t o = gpos[d] + (sl - lstart[d]);
+            recs_out[o] = q;
+            if (keys_out) keys_out[o] = (int32_t)q.w[0];  // what the next pass counts
         }
         __syncthreads();  // every slot placed before the positions move on
         gpos[tid] += tot;
@@ -455,6 +458,7 @@ __global__ __launch_bounds__(kHgGroup) void hg_group_carry_kernel(const char* __
 template <class Op, class T, int W, bool VJP, bool ACC>
 __global__ __launch_bounds__(kHgBlock) void hg_apply_kernel(const HgRec<W>* __restrict__ recs,
                                                             HgRec<W>* __restrict__ urecs,
+                                                            int32_t* __restrict__ ukeys,
                                                             const int32_t* __restrict__ nvalid,
                                                             const char* __restrict__ carF,
                                                             const char* __restrict__ carR, HgOut<T> hs,
@@ -526,6 +530,7 @@ __global__ __launch_bounds__(kHgBlock) void hg_apply_kernel(const HgRec<W>* __re
 #pragma unroll
             for (int k = 0; k < Op::K; ++k) reinterpret_cast<T*>(&q.w[2])[k] = (T)out[k];
             urecs[p0 + j] = q;
+            ukeys[p0 + j] = e[j].src;
         } else {
 #pragma unroll
             for (int k = 0; k < Op::K; ++k) {
@@ -580,7 +585,7 @@ static int hg_components(pvjp_gop op) {
 struct HgLayout {
     int64_t nblk, nchunks, ntiles;
     int64_t ngroups;
-    size_t cntb, ctot, nvalid, recA, recB, off, aggF, aggR, carF, carR, gF, gR, gcF, gcR, total;
+    size_t cntb, ctot, nvalid, recA, recB, keyA, keyB, off, aggF, aggR, carF, carR, gF, gR, gcF, gcR, total;
 };
 
 static size_t hg_rec_bytes(int K, size_t tsize) {
@@ -605,6 +610,8 @@ static HgLayout hg_layout(int64_t n, int64_t m, size_t rec_bytes) {
     L.nvalid = take(4);
     L.recA = take((size_t)nn * rec_bytes);
     L.recB = take((size_t)nn * rec_bytes);
+    L.keyA = take((size_t)nn * 4);
+    L.keyB = take((size_t)nn * 4);
     L.off = take((size_t)(m + 1) * 4);
     L.aggF = take((size_t)L.ntiles * kHgSlot);
     L.aggR = take((size_t)L.ntiles * kHgSlot);
@@ -622,17 +629,21 @@ static HgLayout hg_layout(int64_t n, int64_t m, size_t rec_bytes) {
 // Stable LSD passes of at most 8 bits (the key's bits split evenly; at least
 // one pass) over keys below m: from the indices and x (keys != NULL; the
 // first pass also counts the in-range elements into *nvalid) or from the
-// records rin (nv on the device).  Ping-pongs between bufA and bufB and
-// returns the sorted records.
+// records rin, whose keys ckeys may hold compactly (nv on the device).
+// Records ping-pong between bufA and bufB; for records of 32 bytes or more,
+// each pass but the last also writes its output's keys compactly (keyA /
+// keyB), which the next pass counts instead of reading whole records.
+// Returns the sorted records.
 template <class T, int K, int W>
-static const HgRec<W>* hg_sort_passes(const int32_t* keys, const HgIn<T>& x, const HgRec<W>* rin, int64_t n,
-                                      const int32_t* nv_in, int64_t m, HgRec<W>* bufA, HgRec<W>* bufB,
-                                      int32_t* cntb, int32_t* ctot, int32_t* nvalid, const HgLayout& L,
-                                      hipStream_t st) {
+static const HgRec<W>* hg_sort_passes(const int32_t* keys, const HgIn<T>& x, const HgRec<W>* rin,
+                                      const int32_t* ckeys, int64_t n, const int32_t* nv_in, int64_t m,
+                                      HgRec<W>* bufA, HgRec<W>* bufB, int32_t* keyA, int32_t* keyB, int32_t* cntb,
+                                      int32_t* ctot, int32_t* nvalid, const HgLayout& L, hipStream_t st) {
     int bbits = 0;
     while (((int64_t)1 << bbits) < m) ++bbits;
     const int passes = std::max(1, (bbits + kHgPassBits - 1) / kHgPassBits);
     const int bpp = std::max(1, (bbits + passes - 1) / passes);
+    const int32_t* kcount = keys ? keys : ckeys;
     for (int pass = 0; pass < passes; ++pass) {
         const int shift = pass * bpp;
         const int dmask = (1 << bpp) - 1;
@@ -640,17 +651,21 @@ static const HgRec<W>* hg_sort_passes(const int32_t* keys, const HgIn<T>& x, con
         int nbits = 0;
         while ((1 << nbits) < ndig) ++nbits;
         HgRec<W>* rout = (pass & 1) ? bufB : bufA;
+        // compact keys pay for their extra stores only when a record is at
+        // least 32 bytes (a 16-byte one costs the count about as much to read)
+        int32_t* kout = (W >= 8 && pass + 1 < passes) ? ((pass & 1) ? keyB : keyA) : nullptr;
         const int32_t* kin = pass == 0 ? keys : nullptr;
         const int32_t* nv = (pass == 0 && keys) ? nullptr : (keys ? nvalid : nv_in);
-        hipLaunchKernelGGL(hg_count_kernel<W>, dim3((unsigned)L.nblk), dim3(kHgCountBlock), 0, st, kin, rin, n, nv,
-                           (int32_t)m, shift, dmask, ndig, cntb);
+        hipLaunchKernelGGL(hg_count_kernel<W>, dim3((unsigned)L.nblk), dim3(kHgCountBlock), 0, st, kcount, rin, n,
+                           nv, (int32_t)m, shift, dmask, ndig, cntb);
         hipLaunchKernelGGL(hg_colscan_kernel, dim3((unsigned)ceil_div(ndig, kHgCountBlock), (unsigned)L.nchunks),
                            dim3(kHgCountBlock), 0, st, cntb, (int)L.nblk, ndig, ctot);
         hipLaunchKernelGGL(hg_digitscan_kernel, dim3(1), dim3(kHgScanThreads), 0, st, ctot, (int)L.nchunks, ndig,
                            (pass == 0 && keys) ? nvalid : nullptr);
         hipLaunchKernelGGL((hg_scatter_kernel<T, K, W>), dim3((unsigned)L.nblk), dim3(kHgSortThreads), 0, st, kin, x,
-                           rin, n, nv, (int32_t)m, shift, dmask, ndig, nbits, cntb, ctot, rout);
+                           rin, n, nv, (int32_t)m, shift, dmask, ndig, nbits, cntb, ctot, rout, kout);
         rin = rout;
+        kcount = kout;
     }
     return rin;
 }
@@ -667,7 +682,9 @@ static const HgRec<hg_words<T, Op::K>()>* hg_prepare(const int32_t* inds, int64_
     int32_t* nvalid = reinterpret_cast<int32_t*>(w + L.nvalid);
     Rec* rA = reinterpret_cast<Rec*>(w + L.recA);
     Rec* rB = reinterpret_cast<Rec*>(w + L.recB);
-    const Rec* rin = hg_sort_passes<T, Op::K, W>(inds, x, nullptr, n, nullptr, m, rA, rB, cntb, ctot, nvalid, L, st);
+    const Rec* rin = hg_sort_passes<T, Op::K, W>(inds, x, nullptr, nullptr, n, nullptr, m, rA, rB,
+                                                 reinterpret_cast<int32_t*>(w + L.keyA),
+                                                 reinterpret_cast<int32_t*>(w + L.keyB), cntb, ctot, nvalid, L, st);
     hipLaunchKernelGGL((hg_tile_fold_kernel<Op, T, W>), dim3((unsigned)L.ntiles), dim3(kHgBlock), 0, st, rin,
                        nvalid, w + L.aggF, w + L.aggR);
     hipLaunchKernelGGL(hg_group_fold_kernel<Op>, dim3((unsigned)L.ngroups), dim3(kHgGroup), 0, st, w + L.aggF,
@@ -696,7 +713,8 @@ static void hg_primal(const int32_t* inds, int64_t n, int32_t m, const void* con
     hipLaunchKernelGGL(hg_off_kernel<W>, dim3((unsigned)ceil_div((int64_t)m + 1, 256)), dim3(256), 0, st, recs,
                        nvalid, m, off);
     hipLaunchKernelGGL((hg_apply_kernel<Op, T, W, false, false>), dim3((unsigned)L.ntiles), dim3(kHgBlock), 0, st,
-                       recs, (HgRec<W>*)nullptr, nvalid, w + L.carF, w + L.carR, ho, HgIn<T>{}, HgOut<T>{});
+                       recs, (HgRec<W>*)nullptr, (int32_t*)nullptr, nvalid, w + L.carF, w + L.carR, ho, HgIn<T>{},
+                       HgOut<T>{});
     hipLaunchKernelGGL((hg_empty_kernel<Op, T>), dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, off, m, ho);
 }
 
@@ -723,20 +741,23 @@ static void hg_vjp(const int32_t* inds, int64_t n, int32_t m, const void* const*
     HgRec<W>* rA = reinterpret_cast<HgRec<W>*>(w + L.recA);
     HgRec<W>* rB = reinterpret_cast<HgRec<W>*>(w + L.recB);
     if (Op::K >= 4) urecs = (recs == rA) ? rB : rA;
+    int32_t* kA = reinterpret_cast<int32_t*>(w + L.keyA);
+    int32_t* kB = reinterpret_cast<int32_t*>(w + L.keyB);
+    int32_t* ukeys = urecs ? kB : nullptr;  // the unsort's first pass writes kA
     if (acc)
         hipLaunchKernelGGL((hg_apply_kernel<Op, T, W, true, true>), dim3((unsigned)L.ntiles), dim3(kHgBlock), 0, st,
-                           recs, urecs, nvalid, w + L.carF, w + L.carR, HgOut<T>{}, hb, xb);
+                           recs, urecs, ukeys, nvalid, w + L.carF, w + L.carR, HgOut<T>{}, hb, xb);
     else
         hipLaunchKernelGGL((hg_apply_kernel<Op, T, W, true, false>), dim3((unsigned)L.ntiles), dim3(kHgBlock), 0, st,
-                           recs, urecs, nvalid, w + L.carF, w + L.carR, HgOut<T>{}, hb, xb);
+                           recs, urecs, ukeys, nvalid, w + L.carF, w + L.carR, HgOut<T>{}, hb, xb);
     if (urecs) {
         // the sorted records' buffer is free now: the passes start there, so
         // that no pass reads and writes one buffer
         HgRec<W>* other = (urecs == rA) ? rB : rA;
         int32_t* cntb = reinterpret_cast<int32_t*>(w + L.cntb);
         int32_t* ctot = reinterpret_cast<int32_t*>(w + L.ctot);
-        const HgRec<W>* out = hg_sort_passes<T, Op::K, W>(nullptr, HgIn<T>{}, urecs, n, nvalid, n, other, urecs, cntb,
-                                                          ctot, nvalid, L, st);
+        const HgRec<W>* out = hg_sort_passes<T, Op::K, W>(nullptr, HgIn<T>{}, urecs, ukeys, n, nvalid, n, other,
+                                                          urecs, kA, kB, cntb, ctot, nvalid, L, st);
         if (acc)
             hipLaunchKernelGGL((hg_unsort_write_kernel<T, Op::K, W, true>), dim3(flat_grid(n, 256, 4)), dim3(256), 0,
                                st, out, nvalid, xb);
