@@ -33,6 +33,8 @@
 
 namespace pvjp {
 
+// Row length of the per-chunk digit counts (a pass uses at most
+// kHgPassDigits of a row's entries).
 constexpr int kHgDigitBits = 12;
 constexpr int kHgDigits = 1 << kHgDigitBits;
 constexpr int64_t kHgChunk = 32768;  // elements per sort chunk (one block)
@@ -43,7 +45,7 @@ constexpr int kHgBlock = 256;
 constexpr int kHgIpt = 4;
 constexpr int kHgTile = kHgBlock * kHgIpt;
 constexpr size_t kHgSlot = 64;       // bytes per tile for a lifted state
-constexpr int64_t kHgMaxBins = (int64_t)1 << (2 * kHgDigitBits);
+constexpr int64_t kHgMaxBins = (int64_t)1 << 24;  // three sort passes of 8 bits
 
 // A sort record: word 0 the bin, word 1 the element index, from word 2 the
 // element's K components (T each), padded to whole 16-byte vectors so that a
