@@ -2,8 +2,8 @@
 returning its updates grouped by target window) against the oracle, bit for
 bit: the scattered array, the return sweep's vs_bar and xs_bar, and the
 restored array.  Sizes from one update to the full 2^24 targets into 2^26,
-windows cut by the array's end, out-of-range targets, accumulate, FP32 and
-FP64; at full size against the oracle on sampled targets and against the
+windows cut by the array's end, windows full of updates, out-of-range
+targets, accumulate, FP32 and FP64; at full size against the oracle on sampled targets and against the
 unplanned kernels everywhere.
 """
 import numpy as np
@@ -49,6 +49,29 @@ def test_scatter_planned(ops, orc, dtype, n, m):
     rxb, rvb = orc.scatter_vjp(is_, yb)
     assert np.array_equal(host(ybar), rxb) and np.array_equal(host(vbar), rvb)
     assert np.array_equal(host(x), xs)  # restored
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_scatter_planned_dense_windows(ops, orc, dtype):
+    # Every target of [0, 2^18) and of the array's last 40000 elements, in
+    # random order: whole windows full of updates (more records per window
+    # than either sweep holds in registers), one coarse bucket split into
+    # many chunks of the second bucketing pass, most buckets empty.
+    n = 1 << 20
+    xs, _, _, yb = workloads.scatter(n, 1, dtype, seed=21)
+    g = workloads.rng(22)
+    is_ = g.permutation(np.concatenate([np.arange(1 << 18), np.arange(n - 40000, n)])).astype(np.int32)
+    m = is_.size
+    vs = g.standard_normal(m).astype(xs.dtype)
+    x = dev(xs)
+    plan = ops.scatter_planned_(x, dev(is_), dev(vs))
+    rys, _ = orc.scatter(xs, is_, vs)
+    assert np.array_equal(host(x), rys)
+    ybar = dev(yb)
+    vbar = ops.scatter_planned_vjp_(ybar, m, plan, ys=x)
+    rxb, rvb = orc.scatter_vjp(is_, yb)
+    assert np.array_equal(host(ybar), rxb) and np.array_equal(host(vbar), rvb)
+    assert np.array_equal(host(x), xs)
 
 
 def test_scatter_planned_out_of_range_and_accumulate(ops, orc):
