@@ -6,7 +6,7 @@
 // The operator need not commute, so each bin's elements must meet in index
 // order:
 //   1. a stable sort of the in-range elements by bin: passes of up to 8 bits
-//      (the bin's bits split evenly), low digit first, each a per-chunk digit
+//      (9 for large records when that saves a pass; the bin's bits split evenly), low digit first, each a per-chunk digit
 //      count, a digit-major scan of the counts and a stable scatter staged in
 //      LDS (ranks among equal digits from wave ballots, so equal bins keep
 //      their order; each digit's records leave as contiguous runs).  The sort
@@ -174,12 +174,14 @@ constexpr int kHgSortThreads = 256;
 constexpr int kHgSortWaves = kHgSortThreads / kWave;
 constexpr int kHgSortGroups = 8;                               // groups of 64 per wave and sub-chunk
 constexpr int kHgSub = kHgSortThreads * kHgSortGroups;         // 2048 records
-constexpr int kHgPassBits = 8;                                 // digits per pass: at most 256
+constexpr int kHgPassBits = 8;                                 // bits per pass, one digit per thread
 constexpr int kHgPassDigits = 1 << kHgPassBits;
 static_assert(kHgPassDigits == kHgSortThreads, "a thread per digit in the sub-chunk scans");
 static_assert(kHgChunk % kHgSub == 0, "chunks are whole sub-chunks");
 
-template <class T, int K, int W>
+// DPT: digits per thread in the per-digit steps (1: up to 256 digits, 2: up
+// to 512); thread t owns digits [DPT t, DPT t + DPT).
+template <class T, int K, int W, int DPT>
 __global__ __launch_bounds__(kHgSortThreads) void hg_scatter_kernel(const int32_t* __restrict__ keys_in, HgIn<T> x,
                                                                     const HgRec<W>* __restrict__ recs_in, int64_t n,
                                                                     const int32_t* __restrict__ nvalid, int32_t m,
@@ -188,23 +190,30 @@ __global__ __launch_bounds__(kHgSortThreads) void hg_scatter_kernel(const int32_
                                                                     const int32_t* __restrict__ ctot,
                                                                     HgRec<W>* __restrict__ recs_out,
                                                                     int32_t* __restrict__ keys_out) {
+    constexpr int ND = kHgPassDigits * DPT;
     __shared__ HgRec<W> stage[kHgSub];
-    __shared__ int32_t wcnt[kHgSortWaves][kHgPassDigits];  // per wave: running count, then its offset
-    __shared__ int32_t lstart[kHgPassDigits];              // the digit's first slot in the sub-chunk
-    __shared__ int32_t gpos[kHgPassDigits];                // the digit's running output position
+    __shared__ int32_t wcnt[kHgSortWaves][ND];  // per wave: running count, then its offset
+    __shared__ int32_t lstart[ND];              // the digit's first slot in the sub-chunk
+    __shared__ int32_t gpos[ND];                // the digit's running output position
     __shared__ IntSum::S wtot[kHgSortWaves];
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid / kWave;
     const int blk = blockIdx.x;
     const int c = blk / kHgColChunk;
-    if (tid < ndig) gpos[tid] = ctot[(int64_t)c * kHgDigits + tid] + cntb[(int64_t)blk * kHgDigits + tid];
+#pragma unroll
+    for (int u = 0; u < DPT; ++u) {
+        const int d = DPT * tid + u;
+        if (d < ndig) gpos[d] = ctot[(int64_t)c * kHgDigits + d] + cntb[(int64_t)blk * kHgDigits + d];
+    }
     const int64_t ne = nvalid ? (int64_t)*nvalid : n;
     const int64_t lo = (int64_t)blk * kHgChunk;
     const int64_t hi = (lo + kHgChunk < ne) ? lo + kHgChunk : ne;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
     for (int64_t s0 = lo; s0 < hi; s0 += kHgSub) {
-        for (int w = 0; w < kHgSortWaves; ++w) wcnt[w][tid] = 0;
+        for (int w = 0; w < kHgSortWaves; ++w)
+#pragma unroll
+            for (int u = 0; u < DPT; ++u) wcnt[w][DPT * tid + u] = 0;
         HgRec<W> r[kHgSortGroups];
         bool valid[kHgSortGroups];
         int dg[kHgSortGroups];
@@ -245,17 +254,27 @@ __global__ __launch_bounds__(kHgSortThreads) void hg_scatter_kernel(const int32_
             if (valid[g] && (peers >> lane) == 1ull) wcnt[wave][d] = before + __popcll(peers);
         }
         __syncthreads();
-        // per digit (a thread each): the waves' offsets and the digit's total,
+        // per digit (DPT a thread): the waves' offsets and the digit's total,
         // then the digits' starts in the sub-chunk
-        int tot = 0;
-        for (int w = 0; w < kHgSortWaves; ++w) {
-            const int cw = wcnt[w][tid];
-            wcnt[w][tid] = tot;
-            tot += cw;
+        int tot[DPT], sum = 0;
+#pragma unroll
+        for (int u = 0; u < DPT; ++u) {
+            const int d = DPT * tid + u;
+            tot[u] = 0;
+            for (int w = 0; w < kHgSortWaves; ++w) {
+                const int cw = wcnt[w][d];
+                wcnt[w][d] = tot[u];
+                tot[u] += cw;
+            }
+            sum += tot[u];
         }
         IntSum::S all;
-        const int st = block_exclusive_scan<IntSum, kHgSortThreads, false>(IntSum::S{tot}, all, wtot).v;
-        lstart[tid] = st;
+        int st = block_exclusive_scan<IntSum, kHgSortThreads, false>(IntSum::S{sum}, all, wtot).v;
+#pragma unroll
+        for (int u = 0; u < DPT; ++u) {
+            lstart[DPT * tid + u] = st;
+            st += tot[u];
+        }
         __syncthreads();
 #pragma unroll
         for (int g = 0; g < kHgSortGroups; ++g)
@@ -269,7 +288,8 @@ __global__ __launch_bounds__(kHgSortThreads) void hg_scatter_kernel(const int32_
             if (keys_out) keys_out[o] = (int32_t)q.w[0];  // what the next pass counts
         }
         __syncthreads();  // every slot placed before the positions move on
-        gpos[tid] += tot;
+#pragma unroll
+        for (int u = 0; u < DPT; ++u) gpos[DPT * tid + u] += tot[u];
     }
 }
 
@@ -628,8 +648,8 @@ static HgLayout hg_layout(int64_t n, int64_t m, size_t rec_bytes) {
     return L;
 }
 
-// Stable LSD passes of at most 8 bits (the key's bits split evenly; at least
-// one pass) over keys below m: from the indices and x (keys != NULL; the
+// Stable LSD passes of at most 8 bits, or 9 for records of 32 bytes or more
+// when that saves a pass (the key's bits split evenly; at least one pass) over keys below m: from the indices and x (keys != NULL; the
 // first pass also counts the in-range elements into *nvalid) or from the
 // records rin, whose keys ckeys may hold compactly (nv on the device).
 // Records ping-pong between bufA and bufB; for records of 32 bytes or more,
@@ -643,7 +663,11 @@ static const HgRec<W>* hg_sort_passes(const int32_t* keys, const HgIn<T>& x, con
                                       int32_t* ctot, int32_t* nvalid, const HgLayout& L, hipStream_t st) {
     int bbits = 0;
     while (((int64_t)1 << bbits) < m) ++bbits;
-    const int passes = std::max(1, (bbits + kHgPassBits - 1) / kHgPassBits);
+    int passes = std::max(1, (bbits + kHgPassBits - 1) / kHgPassBits);
+    // records of 32 bytes or more run whole lines with 512 digits too: take
+    // 9-bit passes when that saves one (an unsort of 2^26 indices: 3, not 4)
+    const int passes9 = std::max(1, (bbits + kHgPassBits) / (kHgPassBits + 1));
+    if (W >= 8 && passes9 < passes) passes = passes9;
     const int bpp = std::max(1, (bbits + passes - 1) / passes);
     const int32_t* kcount = keys ? keys : ckeys;
     for (int pass = 0; pass < passes; ++pass) {
@@ -664,8 +688,12 @@ static const HgRec<W>* hg_sort_passes(const int32_t* keys, const HgIn<T>& x, con
                            dim3(kHgCountBlock), 0, st, cntb, (int)L.nblk, ndig, ctot);
         hipLaunchKernelGGL(hg_digitscan_kernel, dim3(1), dim3(kHgScanThreads), 0, st, ctot, (int)L.nchunks, ndig,
                            (pass == 0 && keys) ? nvalid : nullptr);
-        hipLaunchKernelGGL((hg_scatter_kernel<T, K, W>), dim3((unsigned)L.nblk), dim3(kHgSortThreads), 0, st, kin, x,
-                           rin, n, nv, (int32_t)m, shift, dmask, ndig, nbits, cntb, ctot, rout, kout);
+        if (ndig > kHgPassDigits)
+            hipLaunchKernelGGL((hg_scatter_kernel<T, K, W, 2>), dim3((unsigned)L.nblk), dim3(kHgSortThreads), 0, st,
+                               kin, x, rin, n, nv, (int32_t)m, shift, dmask, ndig, nbits, cntb, ctot, rout, kout);
+        else
+            hipLaunchKernelGGL((hg_scatter_kernel<T, K, W, 1>), dim3((unsigned)L.nblk), dim3(kHgSortThreads), 0, st,
+                               kin, x, rin, n, nv, (int32_t)m, shift, dmask, ndig, nbits, cntb, ctot, rout, kout);
         rin = rout;
         kcount = kout;
     }
