@@ -42,7 +42,7 @@ constexpr int kHgCountBlock = 256;
 constexpr int kHgColChunk = 64;      // sort chunks per column-scan chunk
 constexpr int kHgScanThreads = 1024;
 constexpr int kHgBlock = 256;
-constexpr int kHgIpt = 4;
+constexpr int kHgIpt = 2;  // of 1, 2, 4, 8: 2 the fastest (adjacent lanes 32 bytes apart)
 constexpr int kHgTile = kHgBlock * kHgIpt;
 constexpr size_t kHgSlot = 64;       // bytes per tile for a lifted state
 constexpr int64_t kHgMaxBins = (int64_t)1 << 24;  // three sort passes of 8 bits
