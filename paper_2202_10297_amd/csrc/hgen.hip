@@ -575,10 +575,15 @@ __global__ __launch_bounds__(256) void hg_empty_kernel(const int32_t* __restrict
     for (int k = 0; k < Op::K; ++k) hs.p[k][b] = (T)out[k];
 }
 
+// Without accumulation, every in-range element's x_bar is written by the
+// apply (or the unsort); the elements whose index is outside [0, m) get 0
+// here, read from the indices, instead of clearing whole arrays first.
 template <class T>
-__global__ __launch_bounds__(256) void hg_zero_kernel(HgOut<T> x, int K, int64_t n) {
+__global__ __launch_bounds__(256) void hg_zero_oob_kernel(const int32_t* __restrict__ inds, int64_t n, int32_t m,
+                                                          HgOut<T> x, int K) {
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-        for (int k = 0; k < K; ++k) x.p[k][i] = T(0);
+        if ((uint32_t)inds[i] >= (uint32_t)m)
+            for (int k = 0; k < K; ++k) x.p[k][i] = T(0);
 }
 
 // The unsort's last step: records in increasing element index (in-range
@@ -761,7 +766,8 @@ static void hg_vjp(const int32_t* inds, int64_t n, int32_t m, const void* const*
         xb.p[k] = (T*)x_bar[k];
     }
     if (!acc)  // elements outside [0, m) get a zero adjoint
-        hipLaunchKernelGGL(hg_zero_kernel<T>, dim3(flat_grid(n, 256, 4)), dim3(256), 0, st, xb, Op::K, n);
+        hipLaunchKernelGGL(hg_zero_oob_kernel<T>, dim3(flat_grid(n, 256, 4)), dim3(256), 0, st, inds, n, m, xb,
+                           Op::K);
     const HgRec<W>* recs = hg_prepare<Op, T>(inds, n, m, xi, w, L, st);
     int32_t* nvalid = reinterpret_cast<int32_t*>(w + L.nvalid);
     // With four components, K scattered stores per element cost more than
